@@ -1,0 +1,220 @@
+/*
+ * mpmc.h -- C ABI of libmpmc.so: massively parallel Metropolis Monte Carlo of
+ * hard disks on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Anderson, Jankowski, Grubb, Engel, Glotzer, "Massively parallel
+ * Monte Carlo for many-particle simulations on GPUs" (arXiv:1211.1646).
+ * A sweep (Alg. 1) shuffles the four checkerboard sets of cells (Eq. 1),
+ * updates every cell of one set concurrently -- shuffle the cell's particles,
+ * then n_M trial moves on particle list[s mod n], rejecting moves that leave
+ * the cell or overlap a disk of the 3x3 neighbourhood (Alg. 2) -- and ends
+ * with a random shift of the cell grid (Alg. 4).
+ *
+ * Conventions for every call:
+ *  - Device memory is owned by the caller.  mpmc_required_bytes() reports the
+ *    size of each buffer; the caller allocates them (e.g. as torch tensors)
+ *    and passes device pointers in mpmc_buffers.  The library keeps non-owning
+ *    pointers that must stay valid until mpmc_destroy().  The library itself
+ *    allocates only its small host-side handle and, for mpmc_sweep, the
+ *    hipGraph objects it captures.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls marked "async" only enqueue work on it; calls marked "sync" wait
+ *    for it and copy results to host memory.
+ *  - Positions are FP32 cell-local coordinates in (0, w] per axis, stored in
+ *    compressed-row form: cells in row-major order c = cy*cells_x + cx, the
+ *    particles of cell c at xy[2*k], xy[2*k+1] for start[c] <= k < start[c+1],
+ *    start[cells] = N.
+ *  - Every call returns MPMC_OK (0) or a negative status; mpmc_last_error()
+ *    gives a message for the calling thread's last failure.  Argument and
+ *    geometry errors are detected on the host before anything is enqueued.
+ *    Invariant violations found by a kernel (a cell above capacity) set a
+ *    device error word that the next sync call reports as MPMC_EDEVICE.
+ *  - The random streams are Philox4x32-10 with key (seed, replica) and
+ *    counter (cell or 0xFFFFFFFF, sweep low word, sweep high word, tag); the
+ *    sweep counter lives in device memory, so results depend only on the
+ *    state, the sweep index and the key -- not on launch shapes.
+ */
+#ifndef MPMC_H
+#define MPMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mpmc_status;
+#define MPMC_OK 0
+#define MPMC_EINVAL (-1)   /* bad argument */
+#define MPMC_EGEOM (-2)    /* grid odd or < 4 cells, w < sigma, w too wide for capacity 7 */
+#define MPMC_EOVERLAP (-3) /* state handed in contains overlapping disks */
+#define MPMC_EHIP (-4)     /* HIP runtime error */
+#define MPMC_EDEVICE (-5)  /* a kernel found an invariant violation */
+#define MPMC_ESTATE (-6)   /* state handed in is malformed (offsets, ranges, capacity) */
+
+#define MPMC_FLAG_ACC 1u   /* keep per-disk displacement accumulators (MSD) */
+#define MPMC_FLAG_TAG 2u   /* keep per-disk identity tags */
+
+#define MPMC_HIST_BINS 200 /* contact histogram: 200 bins of 1e-4 sigma */
+
+typedef struct mpmc_system *mpmc_handle;
+
+/* System description (Sec. 3.1 and 3.3 free parameters: cell width via the
+ * grid, maximum move delta, moves per cell n_M, seed).  sigma = 1. */
+typedef struct mpmc_params {
+    int32_t lattice_nx;  /* > 0: start from an nx x ny triangular lattice      */
+    int32_t lattice_ny;  /*      (ny even) at packing fraction phi            */
+    double phi;
+    int32_t cells_x;     /* > 0: explicit grid; 0: chosen from w_min / w_max  */
+    int32_t cells_y;
+    double w_min;        /* largest even grid with width >= w_min (default 1) */
+    double w_max;        /* > 0: smallest even grid with width < w_max         */
+    float cell_w_x;      /* lattice_nx == 0: explicit cell widths; the state  */
+    float cell_w_y;      /*   is then loaded with mpmc_set_state              */
+    int64_t n_particles; /* lattice_nx == 0: particle count to size buffers   */
+    float delta;         /* trial displacement uniform in (-delta, delta)^2;  */
+                         /*   0 < delta <= min(w)/2                           */
+    int32_t n_moves;     /* n_M: trial moves per active cell per sub-sweep    */
+    uint32_t seed;       /* Philox key word 0                                 */
+    uint32_t replica;    /* Philox key word 1                                 */
+    uint32_t flags;      /* MPMC_FLAG_*                                       */
+} mpmc_params;
+
+/* Derived geometry (Sec. 3.1; capacity from Fig. 3). */
+typedef struct mpmc_geometry {
+    int64_t n_particles;
+    int32_t cells_x, cells_y;
+    float w_x, w_y;        /* FP32 cell widths: the dynamics' box is cells*w   */
+    int32_t capacity;      /* most disks one cell can hold (4..7)             */
+    double box_x, box_y;   /* cells_x * w_x, cells_y * w_y (FP64)              */
+    double density;        /* n_particles / (box_x * box_y)                    */
+} mpmc_geometry;
+
+/* Bytes the caller must provide for each buffer.  pos/start/acc/tag are
+ * ping-pong pairs: each of the two halves needs the reported size.  acc and
+ * tag are 0 unless the corresponding flag is set. */
+typedef struct mpmc_buffer_sizes {
+    size_t pos;   /* float2 per particle                                       */
+    size_t start; /* uint32 per cell + 1                                       */
+    size_t acc;   /* float2 per particle (MPMC_FLAG_ACC)                        */
+    size_t tag;   /* uint32 per particle (MPMC_FLAG_TAG)                        */
+    size_t work;  /* scratch: scan partials and reductions                     */
+    size_t ctl;   /* control block: sweep counter, key, delta, counters,
+                     error word, contact histogram                             */
+} mpmc_buffer_sizes;
+
+/* Device pointers, each 256-byte aligned, sizes as reported above. */
+typedef struct mpmc_buffers {
+    void *pos[2];
+    void *start[2];
+    void *acc[2];   /* NULL unless MPMC_FLAG_ACC */
+    void *tag[2];   /* NULL unless MPMC_FLAG_TAG */
+    void *work;
+    void *ctl;
+} mpmc_buffers;
+
+/* Geometry of a parameter set (Sec. 3.1, Fig. 3).  Host only, no GPU use.
+ * Errors: MPMC_EINVAL for bad lattice/phi, MPMC_EGEOM for an unusable grid. */
+mpmc_status mpmc_geometry_of(const mpmc_params *p, mpmc_geometry *out);
+
+/* Buffer sizes for a parameter set.  Host only, no GPU use. */
+mpmc_status mpmc_required_bytes(const mpmc_params *p, mpmc_buffer_sizes *out);
+
+/* init_system: build the system (Sec. 4: N disks at packing fraction phi)
+ * and upload it on `stream` (sync).  With lattice_nx > 0 the state is the
+ * triangular lattice; otherwise the grid is explicit and empty until
+ * mpmc_set_state.  Sets sweep = 0, counters = 0, delta and key from p.
+ * *out receives a handle to destroy with mpmc_destroy. */
+mpmc_status mpmc_init_system(const mpmc_params *p, const mpmc_buffers *b, void *stream,
+                             mpmc_handle *out);
+
+/* sweep(n_sweeps, seed): n_sweeps full sweeps of Alg. 1 (async): the sweep's
+ * set order, four sub-sweeps (Alg. 2), shift and rebin (Alg. 4), sweep += 1.
+ * `seed` replaces key word 0 for these and later sweeps.  Long runs are
+ * launched as captured hipGraphs of a fixed block of sweeps. */
+mpmc_status mpmc_sweep(mpmc_handle h, int64_t n_sweeps, uint32_t seed);
+
+/* One sub-sweep of checkerboard set `set` (0..3 = a..d of Eq. 1) with the
+ * current sweep's cell streams (Alg. 1 lines 4-13, Alg. 2).  async. */
+mpmc_status mpmc_subsweep(mpmc_handle h, int32_t set);
+
+/* shift_and_rebin (Alg. 4).  f in 0..3 (+x, -x, +y, -y) with 0 <= d <= w_f/2
+ * shifts by the given amount and leaves the sweep counter alone; f = -1 takes
+ * f and d from the current sweep's draws and then advances the sweep counter
+ * (the last step of a sweep).  The cell lists are rebuilt by counting sort
+ * and prefix scan into the other ping-pong half.  async. */
+mpmc_status mpmc_shift_and_rebin(mpmc_handle h, int32_t f, float d);
+
+/* Accumulate the ordered-pair contact histogram of the current configuration
+ * into the control block (Sec. 4: 200 bins of width 1e-4 on [1, 1.02),
+ * binned on r^2 edges).  reset != 0 clears the accumulated histogram first.
+ * async.  Errors: MPMC_EGEOM if the grid is too small for the histogram's
+ * reach (two cells per axis when w < 1.02). */
+mpmc_status mpmc_pair_histogram(mpmc_handle h, int32_t reset);
+
+/* pressure_from_contact: P* = rho (1 + pi/2 rho g(sigma+)) (Eq. P), with
+ * g(sigma+) from a degree-5 least-squares fit of g(R_i) (Eqs. gR, R) over
+ * (1, 1.02], computed on the device in FP64 from the accumulated histogram;
+ * if none has been accumulated, the current configuration's.  sync.
+ * Any output pointer may be NULL; hist receives MPMC_HIST_BINS counts. */
+mpmc_status mpmc_pressure_from_contact(mpmc_handle h, double *p_star, double *g_contact,
+                                       uint64_t *hist, uint64_t *n_samples);
+
+/* Copy the state to host memory (sync): xy[2N] local coordinates,
+ * start[cells+1], sweep counter.  Any pointer may be NULL. */
+mpmc_status mpmc_get_state(mpmc_handle h, float *xy, uint32_t *start, uint64_t *sweep);
+
+/* Load a state from host memory (sync).  Validates offsets, per-cell
+ * capacity and coordinate ranges on the host (MPMC_ESTATE) and overlaps on
+ * the device (MPMC_EOVERLAP); tags may be NULL (then 0..N-1 in list order);
+ * accumulators are cleared.  N must equal the n_particles the buffers were
+ * sized for. */
+mpmc_status mpmc_set_state(mpmc_handle h, const float *xy, const uint32_t *start,
+                           uint64_t sweep, const uint32_t *tags);
+
+/* Copy accumulators acc[2N] and tags[N] to host memory (sync), list order. */
+mpmc_status mpmc_get_aux(mpmc_handle h, float *acc, uint32_t *tags);
+
+/* Clear the displacement accumulators (async). */
+mpmc_status mpmc_reset_acc(mpmc_handle h);
+
+/* Mean squared displacement mean(|acc|^2) over all disks, FP64, fixed
+ * reduction order (sync). */
+mpmc_status mpmc_msd(mpmc_handle h, double *msd);
+
+/* Number of ordered overlapping pairs in the kernels' metric (sync). */
+mpmc_status mpmc_count_overlaps(mpmc_handle h, int64_t *pairs);
+
+/* Trial moves and accepted moves since init or the last set_state (sync). */
+mpmc_status mpmc_get_counters(mpmc_handle h, uint64_t *trials, uint64_t *accepts);
+
+/* Maximum trial displacement delta (async set / sync get). */
+mpmc_status mpmc_set_delta(mpmc_handle h, float delta);
+mpmc_status mpmc_get_delta(mpmc_handle h, float *delta);
+
+/* Plain acceptance-ratio tuner for equilibration (async): n_windows times,
+ * run window_sweeps sweeps, then with a = accepts/trials of that window
+ * set delta <- delta * clamp(a/0.3, 0.5, 2), clamped to [1e-3, min(w)/2],
+ * on the device. */
+mpmc_status mpmc_tune(mpmc_handle h, int32_t window_sweeps, int32_t n_windows);
+
+/* Launch shape: lanes cooperating on one cell (1, 2, 4, 8, 16) and
+ * workgroup size (64..1024, a multiple of 64).  Results do not depend on it. */
+mpmc_status mpmc_set_launch(mpmc_handle h, int32_t lanes_per_cell, int32_t block_size);
+
+/* Wait for all work enqueued by this handle; reports MPMC_EDEVICE if a kernel
+ * set the error word. */
+mpmc_status mpmc_synchronize(mpmc_handle h);
+
+/* Free the handle and its graphs (not the caller's buffers). */
+void mpmc_destroy(mpmc_handle h);
+
+/* Message describing the calling thread's last failure ("" if none). */
+const char *mpmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPMC_H */

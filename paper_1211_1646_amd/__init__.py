@@ -1,0 +1,14 @@
+"""MPMC hard-disk Monte Carlo on MI355X (HIP, gfx950).
+
+Massively parallel Metropolis Monte Carlo of hard disks after Anderson,
+Jankowski, Grubb, Engel and Glotzer (arXiv:1211.1646): checkerboard
+sub-sweeps with in-cell trial moves (Alg. 1, 2), random cell shift and
+rebuild of the cell lists (Alg. 4), pressure from the contact value of g(r)
+(Sec. 4).  The work runs in libmpmc.so (include/mpmc.h); this package only
+marshals arguments.
+"""
+from ._lib import FLAG_ACC, FLAG_TAG, HIST_BINS, MPMCError, load  # noqa: F401
+from .system import HardDiskSystem, SystemConfig, geometry, required_bytes  # noqa: F401
+
+__all__ = ["HardDiskSystem", "SystemConfig", "geometry", "required_bytes", "MPMCError",
+           "FLAG_ACC", "FLAG_TAG", "HIST_BINS", "load"]

@@ -1,0 +1,865 @@
+// HIP kernels of the MPMC hard-disk sweep for gfx950 (CDNA4, wave64).
+//
+// Method: Anderson et al., "Massively parallel Monte Carlo for many-particle
+// simulations on GPUs" -- Alg. 1 (sweep), Alg. 2 (sub-sweep), Alg. 4 (cell
+// shift), Sec. 4 (contact-value pressure, Eqs. gR, R, P).
+//
+// Data layout in device memory (compressed rows, struct-of-arrays):
+//   pos[N]     float2 cell-local coordinates in (0, w], cells in row-major
+//              order, each cell's particles contiguous;
+//   start[C+1] uint32 offsets, start[C] = N;
+//   acc[N]     float2 displacement accumulators (optional), tag[N] (optional).
+// A sub-sweep writes only the active cells' own ranges and reads the eight
+// inactive neighbours, so it updates in place; the rebin writes the other
+// ping-pong half.
+//
+// Every floating-point expression is written so that each operation rounds
+// once (no contraction); the library is built with -ffp-contract=off and the
+// pragma below repeats it for these kernels.
+#include "mpmc_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace mpmc {
+namespace {
+
+constexpr uint32_t kTagShuffle = 0x40000000u;
+constexpr uint32_t kTagSweep = 0x80000000u;
+constexpr uint32_t kCellGlobal = 0xFFFFFFFFu;
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): per round two 32x32
+// products of words 0 and 2 with the round multipliers, XOR with words 1, 3
+// and the round key; the key advances by the Weyl constants.
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint32_t word_of(const uint4 &v, int i)
+{
+    return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+
+// Uniform integer in [0, k): high word of the 64-bit product v * k.
+__device__ __forceinline__ uint32_t bounded(uint32_t v, uint32_t k) { return __umulhi(v, k); }
+
+// Trial displacement from one word: high half -> x, low half -> y, each the
+// midpoint (2h + 1 - 65536) / 65536 of a sub-interval of (-1, 1), times delta.
+__device__ __forceinline__ void displacement(uint32_t u, float delta, float &dx, float &dy)
+{
+    const int hx = (int)(u >> 16);
+    const int hy = (int)(u & 0xFFFFu);
+    const float ux = (float)(2 * hx + 1 - 65536) * 0x1p-16f;
+    const float uy = (float)(2 * hy + 1 - 65536) * 0x1p-16f;
+    dx = ux * delta;
+    dy = uy * delta;
+}
+
+struct Draws {
+    uint32_t order;   // byte q = set processed in slot q
+    int f;
+    float d;
+};
+
+// The sweep-global block (Alg. 1 lines 2 and 15-16): Fisher-Yates order of
+// the four sets from words 0..2; f from the top two bits of word 3 and
+// d = u (w_f / 2) from its low 24 bits.  The order is kept as four bytes of
+// one register so that no array is indexed at run time.
+__device__ __forceinline__ Draws sweep_draws(unsigned long long s, uint32_t k0, uint32_t k1,
+                                             float wx, float wy)
+{
+    const uint4 G = philox(kCellGlobal, (uint32_t)s, (uint32_t)(s >> 32), kTagSweep, k0, k1);
+    Draws D;
+    uint32_t ord = 0x03020100u;
+#pragma unroll
+    for (int i = 3; i >= 1; --i) {
+        const uint32_t j = bounded(word_of(G, 3 - i), (uint32_t)(i + 1));
+        const uint32_t oi = (ord >> (8 * i)) & 0xFFu;
+        const uint32_t oj = (ord >> (8 * j)) & 0xFFu;
+        ord = (ord & ~(0xFFu << (8 * i))) | (oj << (8 * i));
+        ord = (ord & ~(0xFFu << (8 * j))) | (oi << (8 * j));
+    }
+    D.order = ord;
+    D.f = (int)(G.w >> 30);
+    const float w = D.f < 2 ? wx : wy;
+    const float u = (float)(G.w & 0xFFFFFFu) * 0x1p-24f;
+    D.d = u * (0.5f * w);
+    return D;
+}
+
+// Register arrays indexed by a run-time slot: unrolled selects, no scratch.
+template <int CAP>
+__device__ __forceinline__ float rsel(const float (&a)[CAP], int i)
+{
+    float r = a[0];
+#pragma unroll
+    for (int q = 1; q < CAP; ++q) r = (i == q) ? a[q] : r;
+    return r;
+}
+
+template <int CAP>
+__device__ __forceinline__ void rput(float (&a)[CAP], int i, float v)
+{
+#pragma unroll
+    for (int q = 0; q < CAP; ++q)
+        if (i == q) a[q] = v;
+}
+
+template <int CAP>
+__device__ __forceinline__ void rswap(float (&a)[CAP], int i, int j)
+{
+    const float vi = rsel(a, i), vj = rsel(a, j);
+    rput(a, i, vj);
+    rput(a, j, vi);
+}
+
+// Workgroup id -> logical tile, so that consecutive tiles (neighbouring
+// cells) run on the same XCD: workgroups are dispatched round-robin over the
+// eight XCDs, each with its own L2.  The grid is launched as 8 * per groups;
+// tiles >= the logical count do no work.
+__device__ __forceinline__ int xcd_tile(int per)
+{
+    return (int)(blockIdx.x % 8u) * per + (int)(blockIdx.x / 8u);
+}
+
+__device__ __forceinline__ unsigned wave_sum_u32(unsigned v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum of one value per thread over the workgroup (blockDim <= 1024).
+__device__ __forceinline__ unsigned block_sum_u32(unsigned v, unsigned *scratch16)
+{
+    v = wave_sum_u32(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) scratch16[wave] = v;
+    __syncthreads();
+    unsigned total = 0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int q = 0; q < nw; ++q) total += scratch16[q];
+    __syncthreads();
+    return total;
+}
+
+// Exclusive prefix over the workgroup in thread order; *total gets the sum.
+__device__ __forceinline__ unsigned block_exclusive_scan_u32(unsigned v, unsigned *scratch16,
+                                                             unsigned *total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned n = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += n;
+    }
+    if (lane == 63) scratch16[wave] = incl;
+    __syncthreads();
+    unsigned before = 0, all = 0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int q = 0; q < nw; ++q) {
+        const unsigned t = scratch16[q];
+        if (q < wave) before += t;
+        all += t;
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - v;
+}
+
+// ------------------------------------------------------------ sub-sweep
+// One lane per active cell of set Q (Alg. 2).  The cell's particles and
+// accumulators sit in registers; the eight inactive neighbour cells are read
+// from memory (they are not written during this sub-sweep).
+template <int CAP>
+__global__ void __launch_bounds__(1024)
+k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
+           float2 *__restrict__ acc, Ctl *__restrict__ ctl, int n_moves, int set, int ntile,
+           int per)
+{
+    __shared__ unsigned red[2][16];
+    const int tile = xcd_tile(per);
+    const unsigned long long s = ctl->sweep;
+    const uint32_t k0 = ctl->key0, k1 = ctl->key1;
+    const float delta = ctl->delta;
+    const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
+
+    int Q = set;
+    if (Q < 0) {
+        const Draws D = sweep_draws(s, k0, k1, g.wx, g.wy);
+        Q = (int)((D.order >> (8 * (-1 - set))) & 0xFFu);
+    }
+    const int qx = Q & 1, qy = Q >> 1;
+    const int hx = g.mx >> 1, hy = g.my >> 1;
+    const int gid = tile * (int)blockDim.x + (int)threadIdx.x;
+
+    unsigned n_trials = 0, n_acc = 0;
+    if (tile < ntile && gid < hx * hy) {
+        const int iy = gid / hx, ix = gid - iy * hx;
+        const int cx = 2 * ix + qx, cy = 2 * iy + qy;
+        const int c = cy * g.mx + cx;
+        const uint32_t b0 = start[c];
+        int n = (int)(start[c + 1] - b0);
+        if (n > CAP) {
+            atomicOr(&ctl->errword, kErrCapacity);
+            n = 0;
+        }
+        if (n > 0) {
+            const bool has_acc = acc != nullptr;
+            float px[CAP], py[CAP], ax[CAP], ay[CAP];
+#pragma unroll
+            for (int q = 0; q < CAP; ++q) {
+                px[q] = py[q] = ax[q] = ay[q] = 0.0f;
+                if (q < n) {
+                    const float2 v = pos[b0 + q];
+                    px[q] = v.x;
+                    py[q] = v.y;
+                    if (has_acc) {
+                        const float2 a = acc[b0 + q];
+                        ax[q] = a.x;
+                        ay[q] = a.y;
+                    }
+                }
+            }
+            // rng.shuffle(c.particles): Fisher-Yates over the stored list.
+            uint4 W = make_uint4(0, 0, 0, 0);
+            for (int k = 0; k < n - 1; ++k) {
+                if ((k & 3) == 0)
+                    W = philox((uint32_t)c, s_lo, s_hi, kTagShuffle + (uint32_t)(k >> 2), k0, k1);
+                const int i = n - 1 - k;
+                const int j = (int)bounded(word_of(W, k & 3), (uint32_t)(i + 1));
+                rswap(px, i, j);
+                rswap(py, i, j);
+                if (has_acc) {
+                    rswap(ax, i, j);
+                    rswap(ay, i, j);
+                }
+            }
+            // The eight neighbour cells: index ranges and translations
+            // (exactly -w, 0 or +w, Sec. 3.1).
+            const int xl = cx == 0 ? g.mx - 1 : cx - 1;
+            const int xr = cx == g.mx - 1 ? 0 : cx + 1;
+            const int yd = cy == 0 ? g.my - 1 : cy - 1;
+            const int yu = cy == g.my - 1 ? 0 : cy + 1;
+            uint32_t nb[8], ne[8];
+            float tx[8], ty[8];
+            {
+                const int cols[3] = {xl, cx, xr};
+                const int rows[3] = {yd, cy, yu};
+                const float txs[3] = {-g.wx, 0.0f, g.wx};
+                const float tys[3] = {-g.wy, 0.0f, g.wy};
+                int q = 0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        if (a == 1 && b == 1) continue;
+                        const int nc = rows[a] * g.mx + cols[b];
+                        nb[q] = start[nc];
+                        ne[q] = start[nc + 1];
+                        tx[q] = txs[b];
+                        ty[q] = tys[a];
+                        ++q;
+                    }
+            }
+            int p = 0;
+            for (int t = 0; t < n_moves; ++t) {
+                if ((t & 3) == 0) W = philox((uint32_t)c, s_lo, s_hi, (uint32_t)(t >> 2), k0, k1);
+                float dx, dy;
+                displacement(word_of(W, t & 3), delta, dx, dy);
+                const float xm = rsel(px, p) + dx;
+                const float ym = rsel(py, p) + dy;
+                bool ok = xm > 0.0f && xm <= g.wx && ym > 0.0f && ym <= g.wy;
+                if (ok) {
+#pragma unroll
+                    for (int q = 0; q < CAP; ++q) {
+                        if (q < n && q != p) {
+                            const float ddx = xm - px[q];
+                            const float ddy = ym - py[q];
+                            const float r2 = ddx * ddx + ddy * ddy;
+                            ok = ok && !(r2 < 1.0f);
+                        }
+                    }
+                }
+                if (ok) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        for (uint32_t j = nb[q]; j < ne[q]; ++j) {
+                            const float2 v = pos[j];
+                            const float ox = v.x + tx[q];
+                            const float oy = v.y + ty[q];
+                            const float ddx = xm - ox;
+                            const float ddy = ym - oy;
+                            const float r2 = ddx * ddx + ddy * ddy;
+                            if (r2 < 1.0f) ok = false;
+                        }
+                    }
+                }
+                if (ok) {
+                    rput(px, p, xm);
+                    rput(py, p, ym);
+                    if (has_acc) {
+                        rput(ax, p, rsel(ax, p) + dx);
+                        rput(ay, p, rsel(ay, p) + dy);
+                    }
+                    ++n_acc;
+                }
+                if (++p == n) p = 0;
+            }
+            n_trials = (unsigned)n_moves;
+#pragma unroll
+            for (int q = 0; q < CAP; ++q) {
+                if (q < n) {
+                    pos[b0 + q] = make_float2(px[q], py[q]);
+                    if (has_acc) acc[b0 + q] = make_float2(ax[q], ay[q]);
+                }
+            }
+        }
+    }
+    const unsigned bt = block_sum_u32(n_trials, red[0]);
+    const unsigned ba = block_sum_u32(n_acc, red[1]);
+    if (threadIdx.x == 0 && bt) {
+        atomicAdd(&ctl->trials, (unsigned long long)bt);
+        atomicAdd(&ctl->accepts, (unsigned long long)ba);
+    }
+}
+
+// ----------------------------------------------------------------- rebin
+// Alg. 4 as a counting sort: new cell c holds the stayers of old c followed
+// by the leavers of the old cell in direction f, both in old list order.
+// Phase 1 counts per workgroup tile, phase 2 scans the tile totals, phase 3
+// recounts (same operations, same result), scans inside the tile and
+// scatters.  Each disk's decision is one rounded shifted coordinate tested
+// against (0, w].
+struct RebinArgs {
+    Geom g;
+    const float2 *pos;
+    const uint32_t *start;
+    const float2 *acc;
+    const uint32_t *tag;
+    float2 *pos_out;
+    uint32_t *start_out;
+    float2 *acc_out;
+    uint32_t *tag_out;
+    uint32_t *part;  // per-tile totals, then exclusive offsets
+    Ctl *ctl;
+    int f;
+    float d;
+    int advance;
+    int ntile;
+    int per;
+};
+
+__device__ __forceinline__ float shifted(float v, bool minus, float d)
+{
+    return minus ? v - d : v + d;
+}
+
+template <bool SCATTER>
+__global__ void __launch_bounds__(1024) k_rebin(RebinArgs a)
+{
+    __shared__ unsigned red[16];
+    const Geom &g = a.g;
+    const int tile = xcd_tile(a.per);
+    int f = a.f;
+    float d = a.d;
+    if (f < 0) {
+        const Draws D = sweep_draws(a.ctl->sweep, a.ctl->key0, a.ctl->key1, g.wx, g.wy);
+        f = D.f;
+        d = D.d;
+    }
+    const bool along_x = f < 2;
+    const bool minus = (f == 0 || f == 2);   // +x / +y: t = v - d
+    const float w = along_x ? g.wx : g.wy;
+    const float sw = minus ? w : -w;         // translation into the receiving cell
+
+    const int c = tile * (int)blockDim.x + (int)threadIdx.x;
+    const bool valid = tile < a.ntile && c < g.C;
+    uint32_t ob = 0, oe = 0, nbb = 0, nbe = 0;
+    unsigned cnt = 0;
+    if (valid) {
+        const int cy = c / g.mx, cx = c - cy * g.mx;
+        int ncx = cx, ncy = cy;
+        if (along_x) ncx = minus ? (cx == g.mx - 1 ? 0 : cx + 1) : (cx == 0 ? g.mx - 1 : cx - 1);
+        else ncy = minus ? (cy == g.my - 1 ? 0 : cy + 1) : (cy == 0 ? g.my - 1 : cy - 1);
+        const int nc = ncy * g.mx + ncx;
+        ob = a.start[c];
+        oe = a.start[c + 1];
+        nbb = a.start[nc];
+        nbe = a.start[nc + 1];
+        for (uint32_t k = ob; k < oe; ++k) {
+            const float2 v = a.pos[k];
+            const float t = shifted(along_x ? v.x : v.y, minus, d);
+            cnt += (t > 0.0f && t <= w) ? 1u : 0u;
+        }
+        for (uint32_t k = nbb; k < nbe; ++k) {
+            const float2 v = a.pos[k];
+            const float t = shifted(along_x ? v.x : v.y, minus, d);
+            cnt += (t > 0.0f && t <= w) ? 0u : 1u;
+        }
+    }
+    if (!SCATTER) {
+        const unsigned tot = block_sum_u32(cnt, red);
+        if (threadIdx.x == 0 && tile < a.ntile) a.part[tile] = tot;
+        return;
+    }
+    unsigned tot;
+    const unsigned off = block_exclusive_scan_u32(cnt, red, &tot);
+    if (valid) {
+        uint32_t o = a.part[tile] + off;
+        a.start_out[c] = o;
+        if (c == g.C - 1) a.start_out[g.C] = o + cnt;
+        if (cnt > (unsigned)g.cap) atomicOr(&a.ctl->errword, kErrCapacity);
+        const bool has_acc = a.acc != nullptr, has_tag = a.tag != nullptr;
+        for (uint32_t k = ob; k < oe; ++k) {
+            const float2 v = a.pos[k];
+            const float t = shifted(along_x ? v.x : v.y, minus, d);
+            if (t > 0.0f && t <= w) {
+                a.pos_out[o] = along_x ? make_float2(t, v.y) : make_float2(v.x, t);
+                if (has_acc) a.acc_out[o] = a.acc[k];
+                if (has_tag) a.tag_out[o] = a.tag[k];
+                ++o;
+            }
+        }
+        for (uint32_t k = nbb; k < nbe; ++k) {
+            const float2 v = a.pos[k];
+            const float t = shifted(along_x ? v.x : v.y, minus, d);
+            if (!(t > 0.0f && t <= w)) {
+                const float tt = t + sw;
+                a.pos_out[o] = along_x ? make_float2(tt, v.y) : make_float2(v.x, tt);
+                if (has_acc) a.acc_out[o] = a.acc[k];
+                if (has_tag) a.tag_out[o] = a.tag[k];
+                ++o;
+            }
+        }
+    }
+    // The last workgroup to finish advances the sweep counter.  Every
+    // workgroup read the counter before arriving here.
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(&a.ctl->done, 1u);
+        if (prev == gridDim.x - 1) {
+            atomicExch(&a.ctl->done, 0u);
+            if (a.advance) atomicAdd(&a.ctl->sweep, 1ull);
+        }
+    }
+}
+
+// Exclusive scan of the per-tile totals in place (one workgroup).
+__global__ void __launch_bounds__(1024) k_scan_tiles(uint32_t *part, int ntile, Ctl *ctl,
+                                                     long long N)
+{
+    __shared__ unsigned red[16];
+    const int T = (int)blockDim.x;
+    const int chunk = (ntile + T - 1) / T;
+    const int b = (int)threadIdx.x * chunk;
+    const int e = min(ntile, b + chunk);
+    unsigned local = 0;
+    for (int i = b; i < e; ++i) local += part[i];
+    unsigned total;
+    unsigned run = block_exclusive_scan_u32(local, red, &total);
+    for (int i = b; i < e; ++i) {
+        const unsigned v = part[i];
+        part[i] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0 && (long long)total != N) atomicOr(&ctl->errword, kErrCount);
+}
+
+// ------------------------------------------------------ pair histogram
+// Ordered pairs (k, j != k) within reach, r^2 in k's frame as in the trial
+// moves, binned on E_b = (float)((1 + b 1e-4)^2) (Sec. 4).
+__global__ void __launch_bounds__(256)
+k_pair_hist(Geom g, const float2 *__restrict__ pos, const uint32_t *__restrict__ start,
+            Ctl *__restrict__ ctl, int Rx, int Ry, int ntile, int per)
+{
+    __shared__ float E[kHistBins + 1];
+    __shared__ unsigned H[kHistBins];
+    for (int i = threadIdx.x; i <= kHistBins; i += blockDim.x) {
+        const double r = 1.0 + (double)i * 1e-4;
+        E[i] = (float)(r * r);
+        if (i < kHistBins) H[i] = 0;
+    }
+    __syncthreads();
+    const int tile = xcd_tile(per);
+    const int c = tile * (int)blockDim.x + (int)threadIdx.x;
+    if (tile < ntile && c < g.C) {
+        const int cy = c / g.mx, cx = c - cy * g.mx;
+        const float e0 = E[0], eN = E[kHistBins];
+        for (uint32_t k = start[c]; k < start[c + 1]; ++k) {
+            const float2 pk = pos[k];
+            for (int oy = -Ry; oy <= Ry; ++oy) {
+                const int ncy = (cy + oy + 2 * g.my) % g.my;
+                const float ty = (float)oy * g.wy;
+                for (int ox = -Rx; ox <= Rx; ++ox) {
+                    const int ncx = (cx + ox + 2 * g.mx) % g.mx;
+                    const float tx = (float)ox * g.wx;
+                    const int nc = ncy * g.mx + ncx;
+                    for (uint32_t j = start[nc]; j < start[nc + 1]; ++j) {
+                        if (j == k) continue;
+                        const float2 v = pos[j];
+                        const float qx = v.x + tx;
+                        const float qy = v.y + ty;
+                        const float ddx = pk.x - qx;
+                        const float ddy = pk.y - qy;
+                        const float r2 = ddx * ddx + ddy * ddy;
+                        if (r2 < e0 || r2 >= eN) continue;
+                        int lo = 0, hi = kHistBins;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (r2 >= E[mid]) lo = mid;
+                            else hi = mid;
+                        }
+                        atomicAdd(&H[lo], 1u);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHistBins; i += blockDim.x)
+        if (H[i]) atomicAdd(&ctl->hist[i], (unsigned long long)H[i]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctl->hist_samples, 1ull);
+}
+
+__global__ void k_hist_reset(Ctl *ctl)
+{
+    for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) ctl->hist[i] = 0ull;
+    if (threadIdx.x == 0) ctl->hist_samples = 0ull;
+}
+
+// ------------------------------------------------------ contact fit (FP64)
+// g(R_i) from Eq. gR at the Eq. R points, unweighted least squares of a
+// degree-5 polynomial in (R - 1)/0.02 by Householder QR, P* from Eq. P.
+__global__ void __launch_bounds__(256) k_pressure_fit(Geom g, Ctl *ctl)
+{
+    constexpr int NB = kHistBins, NC = 6;
+    __shared__ double A[NB][NC];
+    __shared__ double y[NB];
+    __shared__ double v[NB];
+    const unsigned long long S = ctl->hist_samples;
+    const double box_x = (double)g.mx * (double)g.wx;
+    const double box_y = (double)g.my * (double)g.wy;
+    const double rho = (double)g.N / (box_x * box_y);
+    const double dr = 1e-4, cfit = 0.02, pi = 3.14159265358979323846;
+    for (int i = threadIdx.x; i < NB; i += blockDim.x) {
+        const double r0 = 1.0 + (double)i * dr;
+        const double r1 = 1.0 + (double)(i + 1) * dr;
+        const double R = (2.0 / 3.0) * (r1 * r1 * r1 - r0 * r0 * r0) / (r1 * r1 - r0 * r0);
+        const double n = (double)ctl->hist[i] / (double)(S ? S : 1ull);
+        y[i] = n / ((double)g.N * rho * 2.0 * pi * R * dr);
+        const double x = (R - 1.0) / cfit;
+        double xp = 1.0;
+        for (int k = 0; k < NC; ++k) {
+            A[i][k] = xp;
+            xp *= x;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    if (S == 0) {
+        ctl->fit[3] = -1.0;
+        return;
+    }
+    for (int k = 0; k < NC; ++k) {
+        double norm2 = 0.0;
+        for (int i = k; i < NB; ++i) norm2 += A[i][k] * A[i][k];
+        const double norm = sqrt(norm2);
+        const double alpha = A[k][k] > 0.0 ? -norm : norm;
+        double vn2 = 0.0;
+        for (int i = k; i < NB; ++i) {
+            v[i] = A[i][k] - (i == k ? alpha : 0.0);
+            vn2 += v[i] * v[i];
+        }
+        if (vn2 == 0.0) continue;
+        for (int j = k; j < NC; ++j) {
+            double dot = 0.0;
+            for (int i = k; i < NB; ++i) dot += v[i] * A[i][j];
+            const double sc = 2.0 * dot / vn2;
+            for (int i = k; i < NB; ++i) A[i][j] -= sc * v[i];
+        }
+        double dot = 0.0;
+        for (int i = k; i < NB; ++i) dot += v[i] * y[i];
+        const double sc = 2.0 * dot / vn2;
+        for (int i = k; i < NB; ++i) y[i] -= sc * v[i];
+    }
+    double coef[NC];
+    for (int k = NC - 1; k >= 0; --k) {
+        double acc = y[k];
+        for (int j = k + 1; j < NC; ++j) acc -= A[k][j] * coef[j];
+        coef[k] = acc / A[k][k];
+    }
+    ctl->fit[0] = rho * (1.0 + 0.5 * pi * rho * coef[0]);
+    ctl->fit[1] = coef[0];
+    ctl->fit[2] = rho;
+    ctl->fit[3] = 1.0;
+}
+
+// ------------------------------------------------------ overlap count
+__global__ void __launch_bounds__(256)
+k_count_overlaps(Geom g, const float2 *__restrict__ pos, const uint32_t *__restrict__ start,
+                 Ctl *__restrict__ ctl, int ntile, int per)
+{
+    __shared__ unsigned red[16];
+    const int tile = xcd_tile(per);
+    const int c = tile * (int)blockDim.x + (int)threadIdx.x;
+    unsigned bad = 0;
+    if (tile < ntile && c < g.C) {
+        const int cy = c / g.mx, cx = c - cy * g.mx;
+        for (uint32_t k = start[c]; k < start[c + 1]; ++k) {
+            const float2 pk = pos[k];
+            for (int oy = -1; oy <= 1; ++oy) {
+                const int ncy = (cy + oy + g.my) % g.my;
+                const float ty = oy < 0 ? -g.wy : (oy > 0 ? g.wy : 0.0f);
+                for (int ox = -1; ox <= 1; ++ox) {
+                    const int ncx = (cx + ox + g.mx) % g.mx;
+                    const float tx = ox < 0 ? -g.wx : (ox > 0 ? g.wx : 0.0f);
+                    const int nc = ncy * g.mx + ncx;
+                    for (uint32_t j = start[nc]; j < start[nc + 1]; ++j) {
+                        if (j == k) continue;
+                        const float2 v = pos[j];
+                        const float ddx = pk.x - (v.x + tx);
+                        const float ddy = pk.y - (v.y + ty);
+                        bad += (ddx * ddx + ddy * ddy < 1.0f) ? 1u : 0u;
+                    }
+                }
+            }
+        }
+    }
+    const unsigned tot = block_sum_u32(bad, red);
+    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&ctl->overlaps, (unsigned long long)tot);
+}
+
+__global__ void k_overlaps_reset(Ctl *ctl) { ctl->overlaps = 0; }
+
+// ------------------------------------------------------------- MSD
+// Deterministic FP64 reduction: fixed chunks per workgroup, fixed tree.
+constexpr int kMsdBlocks = 512;
+constexpr int kMsdThreads = 256;
+
+__global__ void __launch_bounds__(kMsdThreads)
+k_msd_partial(const float2 *__restrict__ acc, long long N, double *__restrict__ part)
+{
+    __shared__ double sh[kMsdThreads];
+    const long long chunk = (N + gridDim.x - 1) / gridDim.x;
+    const long long b = (long long)blockIdx.x * chunk;
+    const long long e = b + chunk < N ? b + chunk : N;
+    double s = 0.0;
+    for (long long i = b + threadIdx.x; i < e; i += blockDim.x) {
+        const float2 a = acc[i];
+        s += (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(kMsdThreads)
+k_msd_final(const double *__restrict__ part, int nb, long long N, Ctl *ctl)
+{
+    __shared__ double sh[kMsdThreads];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ctl->msd = N > 0 ? sh[0] / (double)N : 0.0;
+}
+
+// ------------------------------------------------------------- tuner
+// delta <- delta * clamp(a / 0.3, 0.5, 2), clamped to [1e-3, min(w)/2],
+// with a the acceptance of the window since the last update (FP64).
+__global__ void k_tune(Geom g, Ctl *ctl, int apply)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const unsigned long long t = ctl->trials - ctl->win_trials;
+    const unsigned long long a = ctl->accepts - ctl->win_accepts;
+    if (apply && t > 0) {
+        const double ratio = (double)a / (double)t;
+        double r = ratio / 0.3;
+        if (r < 0.5) r = 0.5;
+        if (r > 2.0) r = 2.0;
+        double nd = (double)ctl->delta * r;
+        const double hi = 0.5 * (double)(g.wx < g.wy ? g.wx : g.wy);
+        if (nd < 1e-3) nd = 1e-3;
+        if (nd > hi) nd = hi;
+        ctl->delta = (float)nd;
+    }
+    ctl->win_trials = ctl->trials;
+    ctl->win_accepts = ctl->accepts;
+}
+
+// ------------------------------------------------------------- utility
+__global__ void k_fill_u32(uint32_t *p, uint32_t value, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
+__global__ void k_ctl_reset(Ctl *ctl, unsigned long long sweep, unsigned int key0,
+                            unsigned int key1, float delta)
+{
+    if (threadIdx.x == 0) {
+        ctl->sweep = sweep;
+        ctl->trials = ctl->accepts = 0ull;
+        ctl->win_trials = ctl->win_accepts = 0ull;
+        ctl->key0 = key0;
+        ctl->key1 = key1;
+        ctl->delta = delta;
+        ctl->errword = 0u;
+        ctl->done = 0u;
+        ctl->hist_samples = 0ull;
+        ctl->overlaps = 0;
+        ctl->msd = 0.0;
+        for (int i = 0; i < 4; ++i) ctl->fit[i] = 0.0;
+    }
+    for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) ctl->hist[i] = 0ull;
+}
+
+__global__ void k_ctl_set_key0(Ctl *ctl, unsigned int key0) { ctl->key0 = key0; }
+__global__ void k_ctl_set_delta(Ctl *ctl, float delta) { ctl->delta = delta; }
+
+inline int tiles_for(long long items, int block) { return (int)((items + block - 1) / block); }
+inline int per_xcd(int ntile) { return (ntile + 7) / 8; }
+
+}  // namespace
+
+// ================================================================ launches
+hipError_t launch_subsweep(const Geom &g, float2 *pos, const uint32_t *start, float2 *acc,
+                           Ctl *ctl, int n_moves, int set, int lanes_per_cell, int block,
+                           hipStream_t st)
+{
+    if (lanes_per_cell != 1) return hipErrorInvalidValue;
+    const long long cells = (long long)(g.mx / 2) * (g.my / 2);
+    const int ntile = tiles_for(cells, block);
+    const int per = per_xcd(ntile);
+    const dim3 grid(8 * per), blk(block);
+    switch (g.cap) {
+    case 4: hipLaunchKernelGGL(k_subsweep<4>, grid, blk, 0, st, g, pos, start, acc, ctl, n_moves, set, ntile, per); break;
+    case 5: hipLaunchKernelGGL(k_subsweep<5>, grid, blk, 0, st, g, pos, start, acc, ctl, n_moves, set, ntile, per); break;
+    case 6: hipLaunchKernelGGL(k_subsweep<6>, grid, blk, 0, st, g, pos, start, acc, ctl, n_moves, set, ntile, per); break;
+    case 7: hipLaunchKernelGGL(k_subsweep<7>, grid, blk, 0, st, g, pos, start, acc, ctl, n_moves, set, ntile, per); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rebin(const Geom &g, const float2 *pos, const uint32_t *start,
+                        const float2 *acc, const uint32_t *tag, float2 *pos_out,
+                        uint32_t *start_out, float2 *acc_out, uint32_t *tag_out,
+                        uint32_t *work, Ctl *ctl, int f, float d, int advance, int block,
+                        hipStream_t st)
+{
+    RebinArgs a;
+    a.g = g;
+    a.pos = pos; a.start = start; a.acc = acc; a.tag = tag;
+    a.pos_out = pos_out; a.start_out = start_out; a.acc_out = acc_out; a.tag_out = tag_out;
+    a.part = work;
+    a.ctl = ctl;
+    a.f = f; a.d = d; a.advance = advance;
+    a.ntile = tiles_for(g.C, block);
+    a.per = per_xcd(a.ntile);
+    const dim3 grid(8 * a.per), blk(block);
+    hipLaunchKernelGGL(k_rebin<false>, grid, blk, 0, st, a);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, work, a.ntile, ctl, g.N);
+    hipLaunchKernelGGL(k_rebin<true>, grid, blk, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_histogram(const Geom &g, const float2 *pos, const uint32_t *start,
+                                 Ctl *ctl, int reset, int block, hipStream_t st)
+{
+    (void)block;
+    if (reset) hipLaunchKernelGGL(k_hist_reset, dim3(1), dim3(256), 0, st, ctl);
+    const double rmax = 1.0 + kHistBins * 1e-4;
+    const int Rx = (double)g.wx >= rmax ? 1 : 2;
+    const int Ry = (double)g.wy >= rmax ? 1 : 2;
+    const int ntile = tiles_for(g.C, 256);
+    const int per = per_xcd(ntile);
+    hipLaunchKernelGGL(k_pair_hist, dim3(8 * per), dim3(256), 0, st, g, pos, start, ctl, Rx, Ry,
+                       ntile, per);
+    return hipGetLastError();
+}
+
+hipError_t launch_pressure_fit(const Geom &g, Ctl *ctl, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pressure_fit, dim3(1), dim3(256), 0, st, g, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_overlaps(const Geom &g, const float2 *pos, const uint32_t *start,
+                                 Ctl *ctl, int block, hipStream_t st)
+{
+    (void)block;
+    hipLaunchKernelGGL(k_overlaps_reset, dim3(1), dim3(1), 0, st, ctl);
+    const int ntile = tiles_for(g.C, 256);
+    const int per = per_xcd(ntile);
+    hipLaunchKernelGGL(k_count_overlaps, dim3(8 * per), dim3(256), 0, st, g, pos, start, ctl,
+                       ntile, per);
+    return hipGetLastError();
+}
+
+hipError_t launch_msd(const Geom &g, const float2 *acc, double *work, Ctl *ctl, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_msd_partial, dim3(kMsdBlocks), dim3(kMsdThreads), 0, st, acc, g.N, work);
+    hipLaunchKernelGGL(k_msd_final, dim3(1), dim3(kMsdThreads), 0, st, work, kMsdBlocks, g.N, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_tune(const Geom &g, Ctl *ctl, int apply, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tune, dim3(1), dim3(64), 0, st, g, ctl, apply);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, long long n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, value, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_reset(Ctl *ctl, unsigned long long sweep, unsigned int key0,
+                            unsigned int key1, float delta, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(256), 0, st, ctl, sweep, key0, key1, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_set_key0(Ctl *ctl, unsigned int key0, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ctl_set_key0, dim3(1), dim3(1), 0, st, ctl, key0);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_set_delta(Ctl *ctl, float delta, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ctl_set_delta, dim3(1), dim3(1), 0, st, ctl, delta);
+    return hipGetLastError();
+}
+
+}  // namespace mpmc

@@ -1,0 +1,198 @@
+"""Python face of libmpmc.so: a hard-disk system on one GPU.
+
+Torch provides the device buffers (sized by mpmc_required_bytes) and a
+dedicated stream; every step of the simulation runs in the library's HIP
+kernels.  Method: Anderson et al., arXiv:1211.1646 (Alg. 1, 2, 4; Sec. 4).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+
+
+@dataclass
+class SystemConfig:
+    """Parameters of mpmc_params (sigma = 1)."""
+    lattice_nx: int = 0
+    lattice_ny: int = 0
+    phi: float = 0.0
+    cells_x: int = 0
+    cells_y: int = 0
+    w_min: float = 1.0
+    w_max: float = 0.0
+    cell_w_x: float = 0.0
+    cell_w_y: float = 0.0
+    n_particles: int = 0
+    delta: float = 0.1
+    n_moves: int = 4
+    seed: int = 1
+    replica: int = 0
+    flags: int = 0
+
+    def to_c(self) -> L.Params:
+        p = L.Params()
+        for name, _ in L.Params._fields_:
+            setattr(p, name, getattr(self, name))
+        return p
+
+
+def geometry(cfg: SystemConfig) -> dict:
+    """Derived geometry (host only, no GPU needed)."""
+    g = L.Geometry()
+    L.check(L.load().mpmc_geometry_of(C.byref(cfg.to_c()), C.byref(g)))
+    return {name: getattr(g, name) for name, _ in L.Geometry._fields_}
+
+
+def required_bytes(cfg: SystemConfig) -> dict:
+    s = L.BufferSizes()
+    L.check(L.load().mpmc_required_bytes(C.byref(cfg.to_c()), C.byref(s)))
+    return {name: getattr(s, name) for name, _ in L.BufferSizes._fields_}
+
+
+class HardDiskSystem:
+    """One system of hard disks resident on a GPU."""
+
+    def __init__(self, cfg: SystemConfig, device: str = "cuda:0"):
+        import torch
+        self.cfg = cfg
+        self.lib = L.load()
+        self.device = torch.device(device)
+        sizes = required_bytes(cfg)
+        self.geometry = geometry(cfg)
+        self.N = int(self.geometry["n_particles"])
+        self.mx, self.my = self.geometry["cells_x"], self.geometry["cells_y"]
+        self.C = self.mx * self.my
+        self.wx = np.float32(self.geometry["w_x"])
+        self.wy = np.float32(self.geometry["w_y"])
+        self.cap = self.geometry["capacity"]
+
+        def buf(n):
+            return torch.empty(max(int(n), 256), dtype=torch.uint8, device=self.device)
+
+        self._bufs = {k: [buf(sizes[k]), buf(sizes[k])] for k in ("pos", "start")}
+        self._bufs["acc"] = [buf(sizes["acc"]), buf(sizes["acc"])] if sizes["acc"] else None
+        self._bufs["tag"] = [buf(sizes["tag"]), buf(sizes["tag"])] if sizes["tag"] else None
+        self._work = buf(sizes["work"])
+        self._ctl = buf(sizes["ctl"])
+        b = L.Buffers()
+        for i in range(2):
+            b.pos[i] = self._bufs["pos"][i].data_ptr()
+            b.start[i] = self._bufs["start"][i].data_ptr()
+            b.acc[i] = self._bufs["acc"][i].data_ptr() if self._bufs["acc"] else None
+            b.tag[i] = self._bufs["tag"][i].data_ptr() if self._bufs["tag"] else None
+        b.work = self._work.data_ptr()
+        b.ctl = self._ctl.data_ptr()
+        self.stream = torch.cuda.Stream(device=self.device)
+        torch.cuda.synchronize(self.device)
+        h = C.c_void_p()
+        L.check(self.lib.mpmc_init_system(C.byref(cfg.to_c()), C.byref(b),
+                                          C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    # ----------------------------------------------------------- lifecycle
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.mpmc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ dynamics
+    def sweep(self, n: int = 1, seed: int | None = None):
+        L.check(self.lib.mpmc_sweep(self._h, int(n), self.cfg.seed if seed is None else int(seed)))
+        if seed is not None:
+            self.cfg.seed = int(seed)
+
+    def subsweep(self, set_index: int):
+        L.check(self.lib.mpmc_subsweep(self._h, int(set_index)))
+
+    def shift_and_rebin(self, f: int = -1, d: float = 0.0):
+        L.check(self.lib.mpmc_shift_and_rebin(self._h, int(f), float(np.float32(d))))
+
+    def tune(self, window_sweeps: int, n_windows: int):
+        L.check(self.lib.mpmc_tune(self._h, int(window_sweeps), int(n_windows)))
+
+    def set_launch(self, lanes_per_cell: int = 1, block_size: int = 256):
+        L.check(self.lib.mpmc_set_launch(self._h, int(lanes_per_cell), int(block_size)))
+
+    def synchronize(self):
+        L.check(self.lib.mpmc_synchronize(self._h))
+
+    # ---------------------------------------------------------- parameters
+    @property
+    def delta(self) -> np.float32:
+        d = C.c_float()
+        L.check(self.lib.mpmc_get_delta(self._h, C.byref(d)))
+        return np.float32(d.value)
+
+    def set_delta(self, delta: float):
+        L.check(self.lib.mpmc_set_delta(self._h, float(np.float32(delta))))
+
+    # --------------------------------------------------------------- state
+    def get_state(self):
+        xy = np.empty((self.N, 2), np.float32)
+        start = np.empty(self.C + 1, np.uint32)
+        sw = C.c_uint64()
+        L.check(self.lib.mpmc_get_state(self._h, xy.ctypes.data, start.ctypes.data, C.byref(sw)))
+        return xy, start, int(sw.value)
+
+    def set_state(self, xy, start, sweep: int = 0, tags=None):
+        xy = np.ascontiguousarray(xy, np.float32)
+        start = np.ascontiguousarray(start, np.uint32)
+        tp = None
+        if tags is not None:
+            tags = np.ascontiguousarray(tags, np.uint32)
+            tp = tags.ctypes.data
+        L.check(self.lib.mpmc_set_state(self._h, xy.ctypes.data if xy.size else None,
+                                        start.ctypes.data, int(sweep), tp))
+
+    def aux(self):
+        acc = np.zeros((self.N, 2), np.float32) if self._bufs["acc"] else None
+        tag = np.zeros(self.N, np.uint32) if self._bufs["tag"] else None
+        L.check(self.lib.mpmc_get_aux(self._h, acc.ctypes.data if acc is not None else None,
+                                      tag.ctypes.data if tag is not None else None))
+        return acc, tag
+
+    def reset_acc(self):
+        L.check(self.lib.mpmc_reset_acc(self._h))
+
+    def msd(self) -> float:
+        v = C.c_double()
+        L.check(self.lib.mpmc_msd(self._h, C.byref(v)))
+        return v.value
+
+    def count_overlaps(self) -> int:
+        v = C.c_int64()
+        L.check(self.lib.mpmc_count_overlaps(self._h, C.byref(v)))
+        return int(v.value)
+
+    def counters(self):
+        t, a = C.c_uint64(), C.c_uint64()
+        L.check(self.lib.mpmc_get_counters(self._h, C.byref(t), C.byref(a)))
+        return int(t.value), int(a.value)
+
+    # ------------------------------------------------------------ pressure
+    def pair_histogram(self, reset: bool = False):
+        L.check(self.lib.mpmc_pair_histogram(self._h, 1 if reset else 0))
+
+    def pressure_from_contact(self):
+        """(P*, g(sigma+), histogram, number of configurations)."""
+        p, g0 = C.c_double(), C.c_double()
+        hist = np.zeros(L.HIST_BINS, np.uint64)
+        ns = C.c_uint64()
+        L.check(self.lib.mpmc_pressure_from_contact(
+            self._h, C.byref(p), C.byref(g0), hist.ctypes.data_as(C.POINTER(C.c_uint64)),
+            C.byref(ns)))
+        return p.value, g0.value, hist, int(ns.value)
+
+    @property
+    def box(self):
+        return self.mx * np.float64(self.wx), self.my * np.float64(self.wy)

@@ -1,0 +1,106 @@
+"""The C-ABI library: it loads, exports every declared symbol, and its host-side
+logic (geometry, buffer sizes, argument checks) agrees with the oracle.
+No GPU calls."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1211_1646_amd as pkg
+from paper_1211_1646_amd import _lib as L
+from paper_1211_1646_amd.system import SystemConfig, geometry, required_bytes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "mpmc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpmc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = _declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L._SIGNATURES), set(names) ^ set(L._SIGNATURES)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes field sits at the offset the C compiler gives it."""
+    import ctypes as C
+    import subprocess
+    structs = {"mpmc_params": L.Params, "mpmc_geometry": L.Geometry,
+               "mpmc_buffer_sizes": L.BufferSizes, "mpmc_buffers": L.Buffers}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpmc.h"', "int main(void){"]
+    for cname, cls in structs.items():
+        lines.append('printf("%%s %%zu\\n", "%s", sizeof(%s));' % (cname, cname))
+        for fname, _ in cls._fields_:
+            lines.append('printf("%%s.%%s %%zu\\n", "%s", "%s", offsetof(%s, %s));'
+                         % (cname, fname, cname, fname))
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = dict(line.rsplit(" ", 1) for line in
+               subprocess.run([str(exe)], capture_output=True, text=True).stdout.split("\n") if line)
+    for cname, cls in structs.items():
+        assert int(out[cname]) == C.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(out["%s.%s" % (cname, fname)]) == getattr(cls, fname).offset, (cname, fname)
+
+
+@pytest.mark.parametrize("nx,phi,w_min,w_max", [
+    (64, 0.60, 1.0, 0.0), (256, 0.70, 1.0, 0.0), (1024, 0.70, 1.0, math.sqrt(2.0)),
+    (1024, 0.716, 1.0, math.sqrt(2.0)), (1024, 0.72, 1.0, math.sqrt(2.0)),
+    (1024, 0.70, 1.0, 1.932), (96, 0.65, 1.0, 0.0), (500, 0.73, 1.0, 0.0), (20, 0.45, 1.2, 0.0)])
+def test_geometry_agrees_with_oracle(nx, phi, w_min, w_max):
+    g = geometry(SystemConfig(lattice_nx=nx, lattice_ny=nx, phi=phi, w_min=w_min, w_max=w_max))
+    o = oracle.geometry(nx, nx, phi, w_min=w_min, w_max=w_max)
+    assert (g["cells_x"], g["cells_y"], g["capacity"]) == (o["mx"], o["my"], o["cap"])
+    assert np.float32(g["w_x"]) == o["wx"] and np.float32(g["w_y"]) == o["wy"]
+    assert g["n_particles"] == nx * nx
+    assert g["box_x"] == g["cells_x"] * np.float64(o["wx"])
+    assert abs(g["density"] * np.pi / 4 - phi) < 1e-6
+
+
+def test_required_bytes():
+    cfg = SystemConfig(lattice_nx=64, lattice_ny=64, phi=0.6, flags=pkg.FLAG_ACC | pkg.FLAG_TAG)
+    s = required_bytes(cfg)
+    g = geometry(cfg)
+    N, C = g["n_particles"], g["cells_x"] * g["cells_y"]
+    assert s["pos"] >= 8 * N and s["acc"] >= 8 * N and s["tag"] >= 4 * N
+    assert s["start"] >= 4 * (C + 1)
+    assert all(v % 256 == 0 for v in s.values())
+    assert required_bytes(SystemConfig(lattice_nx=64, lattice_ny=64, phi=0.6))["acc"] == 0
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(lattice_nx=8, lattice_ny=7, phi=0.5), L.MPMC_EINVAL),          # odd rows
+    (dict(lattice_nx=8, lattice_ny=8, phi=0.95), L.MPMC_EINVAL),         # phi too large
+    (dict(lattice_nx=4, lattice_ny=4, phi=0.7), L.MPMC_EGEOM),           # grid < 4
+    (dict(lattice_nx=64, lattice_ny=64, phi=0.6, cells_x=77), L.MPMC_EGEOM),   # odd grid
+    (dict(lattice_nx=64, lattice_ny=64, phi=0.6, cells_x=80), L.MPMC_EGEOM),   # w < 1
+    (dict(lattice_nx=64, lattice_ny=64, phi=0.6, w_min=2.0), L.MPMC_EGEOM),    # w > 1.932
+    (dict(cells_x=6, cells_y=6, cell_w_x=1.2, cell_w_y=0.9, n_particles=4), L.MPMC_EGEOM),
+    (dict(cells_x=4, cells_y=4, cell_w_x=1.2, cell_w_y=1.2, n_particles=65), L.MPMC_EGEOM),
+])
+def test_geometry_errors(kw, status):
+    with pytest.raises(L.MPMCError) as e:
+        geometry(SystemConfig(**kw))
+    assert e.value.status == status
+    assert L.load().mpmc_last_error()
+
+
+def test_package_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        L.load()

@@ -1,0 +1,309 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle: bit-exact
+cell lists, positions, accumulators, tags and counters; the contact fit
+within FP64 rounding.  Needs an MI355X."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import OracleSystem
+from oracle import estimator as E
+
+pytestmark = pytest.mark.gpu
+
+FLAGS = 3  # accumulators + tags on both sides
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1211_1646_amd as pkg
+    pkg.load()
+    return pkg
+
+
+def lattice_pair(pkg, nx, ny, phi, w_max=0.0, delta=0.1, n_moves=4, seed=1, replica=0,
+                 flags=FLAGS, w_min=1.0):
+    log("  lattice pair nx=%d ny=%d phi=%.3f w_max=%.4f n_moves=%d" % (nx, ny, phi, w_max, n_moves))
+    cfg = pkg.SystemConfig(lattice_nx=nx, lattice_ny=ny, phi=phi, w_min=w_min, w_max=w_max,
+                           delta=delta, n_moves=n_moves, seed=seed, replica=replica, flags=flags)
+    G = pkg.HardDiskSystem(cfg)
+    O = OracleSystem.lattice(nx, ny, phi, w_min=w_min, w_max=w_max, delta=delta, n_moves=n_moves,
+                             seed=seed, replica=replica, flags=flags)
+    return G, O
+
+
+def grid_pair(pkg, O, n_moves=None, seed=1, replica=0, flags=FLAGS, delta=None):
+    """A GPU system holding the oracle's current state."""
+    xy, start, sweep = O.get_state()
+    _, tag = O.aux()
+    cfg = pkg.SystemConfig(cells_x=O.mx, cells_y=O.my, cell_w_x=float(O.wx), cell_w_y=float(O.wy),
+                           n_particles=len(xy), delta=float(O.delta if delta is None else delta),
+                           n_moves=n_moves if n_moves is not None else 4, seed=seed,
+                           replica=replica, flags=flags)
+    G = pkg.HardDiskSystem(cfg)
+    G.set_state(xy, start, sweep, tag)
+    return G
+
+
+def assert_same(G, O, what=""):
+    gx, gs, gsw = G.get_state()
+    ox, os_, osw = O.get_state()
+    assert gsw == osw, (what, gsw, osw)
+    assert np.array_equal(gs, os_), (what, "cell lists differ", int(np.argmax(gs != os_)))
+    bad = np.nonzero(np.any(gx.view(np.uint32) != ox.view(np.uint32), axis=1))[0]
+    assert bad.size == 0, (what, "positions differ", bad[:5], gx[bad[:3]], ox[bad[:3]])
+    ga, gt = G.aux()
+    oa, ot = O.aux()
+    if gt is not None:
+        assert np.array_equal(gt, ot), (what, "tags differ")
+    if ga is not None:
+        assert np.array_equal(ga.view(np.uint32), oa.view(np.uint32)), (what, "accumulators differ")
+    assert G.counters() == O.counters(), (what, G.counters(), O.counters())
+
+
+CONFIGS = [
+    (64, 64, 0.60, 0.0),             # small workload, w >= 1
+    (24, 24, 0.70, math.sqrt(2.0)),  # w < sqrt(2), capacity 4
+    (20, 20, 0.72, 1.932),           # capacity 7
+    (16, 18, 0.45, 1.664),           # rectangular lattice, capacity 5
+    (30, 30, 0.50, 1.8),             # capacity 6
+]
+
+
+@pytest.mark.parametrize("nx,ny,phi,w_max", CONFIGS)
+def test_initial_state_matches(gpu, nx, ny, phi, w_max):
+    G, O = lattice_pair(gpu, nx, ny, phi, w_max)
+    assert_same(G, O, "init")
+    assert G.count_overlaps() == 0
+
+
+@pytest.mark.parametrize("nx,ny,phi,w_max", CONFIGS)
+def test_single_subsweeps_match(gpu, nx, ny, phi, w_max):
+    G, O = lattice_pair(gpu, nx, ny, phi, w_max, delta=0.2)
+    O.sweep(7)
+    G = grid_pair(gpu, O, delta=0.2)
+    for Q in (2, 0, 3, 1, 1):
+        log("  subsweep Q=%d" % Q)
+        G.subsweep(Q)
+        O.subsweep(Q)
+        assert_same(G, O, "subsweep %d" % Q)
+
+
+@pytest.mark.parametrize("nx,ny,phi,w_max", CONFIGS)
+def test_explicit_shifts_match(gpu, nx, ny, phi, w_max):
+    G, O = lattice_pair(gpu, nx, ny, phi, w_max, delta=0.2)
+    O.sweep(5)
+    G = grid_pair(gpu, O, delta=0.2)
+    rng = np.random.default_rng(nx)
+    for f in (0, 1, 2, 3, 2, 0, 3, 1):
+        w = O.wx if f < 2 else O.wy
+        for d in (np.float32(0.0), np.float32(rng.uniform(0, 0.5)) * np.float32(0.5) * w,
+                  np.float32(0.5) * w):
+            log("  shift f=%d d=%r" % (f, float(d)))
+            G.shift_and_rebin(f, d)
+            O.shift(f, d)
+            assert_same(G, O, "shift %d %r" % (f, d))
+
+
+@pytest.mark.parametrize("n_moves", [0, 1, 3, 4, 6, 9])
+def test_sweeps_match_for_any_n_moves(gpu, n_moves):
+    G, O = lattice_pair(gpu, 20, 20, 0.70, math.sqrt(2.0), delta=0.15, n_moves=n_moves, seed=5)
+    for k in range(12):
+        G.sweep(1)
+        O.sweep(1)
+        assert_same(G, O, "sweep %d" % k)
+
+
+def test_small_workload_1000_sweeps(gpu):
+    """N = 4096 at phi = 0.60, w >= 1, delta = 0.1, n_M = 4, seed 1:
+    counters after every sweep of the first hundred, the whole state every
+    hundred sweeps, including accept counts."""
+    G, O = lattice_pair(gpu, 64, 64, 0.60, 0.0, delta=0.1, n_moves=4, seed=1)
+    for k in range(100):
+        G.sweep(1)
+        O.sweep(1)
+        assert G.counters() == O.counters(), k
+    assert_same(G, O, "sweep 100")
+    for block in range(9):
+        G.sweep(100)
+        O.sweep(100)
+        log("  sweeps %d" % (200 + 100 * block))
+        assert_same(G, O, "sweep %d" % (200 + 100 * block))
+    assert G.count_overlaps() == 0
+
+
+def test_graph_path_matches_eager_path(gpu):
+    G1, O = lattice_pair(gpu, 32, 32, 0.70, math.sqrt(2.0), delta=0.12, seed=3)
+    G2, _ = lattice_pair(gpu, 32, 32, 0.70, math.sqrt(2.0), delta=0.12, seed=3)
+    G1.sweep(48)            # three captured graphs of 16 sweeps
+    for _ in range(48):
+        G2.sweep(1)        # one sweep at a time, no graph
+    O.sweep(48)
+    assert_same(G1, O, "graph")
+    assert_same(G2, O, "eager")
+    G1.sweep(17)           # graph + one eager sweep, then graphs on the other half
+    G1.sweep(16)
+    O.sweep(33)
+    assert_same(G1, O, "graph odd")
+
+
+@pytest.mark.parametrize("block", [64, 128, 512, 1024])
+def test_launch_shape_does_not_change_results(gpu, block):
+    G, O = lattice_pair(gpu, 40, 40, 0.70, math.sqrt(2.0), delta=0.15, seed=9)
+    G.set_launch(1, block)
+    G.sweep(20)
+    O.sweep(20)
+    assert_same(G, O, "block %d" % block)
+
+
+def test_seed_change_and_delta_change(gpu):
+    G, O = lattice_pair(gpu, 24, 24, 0.65, 0.0, delta=0.1, seed=1)
+    G.sweep(5)
+    O.sweep(5)
+    G.sweep(5, seed=77)
+    O.set_seed(77)
+    O.sweep(5)
+    assert_same(G, O, "seed")
+    G.set_delta(0.25)
+    O.set_delta(np.float32(0.25))
+    G.sweep(5, seed=77)
+    O.sweep(5)
+    assert_same(G, O, "delta")
+    assert G.delta == np.float32(0.25)
+
+
+def test_tuner_matches_oracle(gpu):
+    G, O = lattice_pair(gpu, 48, 48, 0.70, 0.0, delta=0.02, seed=4)
+    window, n = 10, 8
+    G.tune(window, n)
+    for _ in range(n):
+        t0, a0 = O.counters()
+        O.sweep(window)
+        t1, a1 = O.counters()
+        O.set_delta(oracle.tuned_delta(O.delta, t1 - t0, a1 - a0, O.wx, O.wy))
+    assert G.delta == O.delta
+    assert_same(G, O, "tuned")
+    log("  tuned delta %r" % float(G.delta))
+
+
+@pytest.mark.parametrize("nx,ny,phi,w_max", [(40, 40, 0.70, 0.0), (40, 40, 0.70, math.sqrt(2.0)),
+                                             (30, 30, 0.60, 1.932)])
+def test_pair_histogram_and_pressure(gpu, nx, ny, phi, w_max):
+    G, O = lattice_pair(gpu, nx, ny, phi, w_max, delta=0.15, seed=8)
+    hist_o = np.zeros(200, np.uint64)
+    G.pair_histogram(reset=True)
+    for k in range(6):
+        G.sweep(3)
+        O.sweep(3)
+        G.pair_histogram()
+        hist_o += O.pair_histogram()
+    # the first GPU sample was the lattice; add it on the oracle side too
+    O0 = OracleSystem.lattice(nx, ny, phi, w_max=w_max, delta=0.15, seed=8, flags=FLAGS)
+    hist_o += O0.pair_histogram()
+    p, g0, hist_g, ns = G.pressure_from_contact()
+    assert ns == 7
+    assert np.array_equal(hist_g, hist_o)
+    Lx, Ly = O.box
+    rho = O.N / (Lx * Ly)
+    p_ref, g_ref = E.pressure_from_histogram(hist_o, 7, O.N, rho)
+    assert abs(g0 - g_ref) <= 1e-9 * abs(g_ref) + 1e-12, (g0, g_ref)
+    assert abs(p - p_ref) <= 1e-9 * abs(p_ref), (p, p_ref)
+    # single configuration when nothing is accumulated
+    G2, O2 = lattice_pair(gpu, nx, ny, phi, w_max, delta=0.15, seed=8)
+    G2.sweep(4)
+    O2.sweep(4)
+    p2, _, h2, n2 = G2.pressure_from_contact()
+    assert n2 == 1 and np.array_equal(h2, O2.pair_histogram())
+
+
+def test_msd_matches(gpu):
+    G, O = lattice_pair(gpu, 32, 32, 0.68, 0.0, delta=0.2, seed=12)
+    G.sweep(30)
+    O.sweep(30)
+    acc, _ = O.aux()
+    ref = float(np.mean((acc.astype(np.float64) ** 2).sum(axis=1)))
+    assert abs(G.msd() - ref) <= 1e-12 * ref
+    G.reset_acc()
+    O.reset_acc()
+    G.sweep(3)
+    O.sweep(3)
+    assert_same(G, O, "after reset")
+
+
+def test_tiny_systems(gpu):
+    """One and two disks, an empty cell grid apart from them."""
+    w = np.float32(1.25)
+    for pts in ([[0.6, 0.7]], [[0.3, 0.3], [1.2, 1.1]]):
+        xy = np.array(pts, np.float32)
+        start = np.zeros(37, np.uint32)
+        start[1:] = len(pts)
+        O = OracleSystem.grid(6, 6, w, w, delta=np.float32(0.6), n_moves=4, seed=29, flags=FLAGS)
+        O.set_state(xy, start)
+        G = grid_pair(gpu, O, n_moves=4, seed=29, delta=np.float32(0.6))
+        G.sweep(40)
+        O.sweep(40)
+        assert_same(G, O, "tiny %d" % len(pts))
+
+
+def test_state_errors(gpu):
+    from paper_1211_1646_amd import _lib as L
+    O = OracleSystem.grid(4, 4, np.float32(1.2), np.float32(1.2), flags=FLAGS)
+    cfg = gpu.SystemConfig(cells_x=4, cells_y=4, cell_w_x=1.2, cell_w_y=1.2, n_particles=2,
+                           delta=0.1, flags=FLAGS)
+    G = gpu.HardDiskSystem(cfg)
+    start = np.zeros(17, np.uint32)
+    start[1:] = 2
+    with pytest.raises(L.MPMCError) as e:      # overlapping pair
+        G.set_state(np.array([[0.5, 0.5], [0.9, 0.5]], np.float32), start)
+    assert e.value.status == L.MPMC_EOVERLAP
+    with pytest.raises(L.MPMCError) as e:      # outside (0, w]
+        G.set_state(np.array([[0.0, 0.5], [1.1, 1.1]], np.float32), start)
+    assert e.value.status == L.MPMC_ESTATE
+    with pytest.raises(L.MPMCError) as e:
+        G.subsweep(4)
+    assert e.value.status == L.MPMC_EINVAL
+    with pytest.raises(L.MPMCError) as e:
+        G.shift_and_rebin(0, 0.7)              # d > w/2
+    assert e.value.status == L.MPMC_EINVAL
+    with pytest.raises(L.MPMCError) as e:
+        G.set_delta(0.61)
+    assert e.value.status == L.MPMC_EINVAL
+    G.set_state(np.array([[0.5, 0.5], [0.5, 1.2]], np.float32), start)   # touching allowed
+    assert G.count_overlaps() == 0
+
+
+def test_medium_workload(gpu):
+    """N = 65,536 at phi = 0.70, w in [1, 1.2): 300 sweeps, whole state every
+    hundred sweeps, counters every ten."""
+    G, O = lattice_pair(gpu, 256, 256, 0.70, 0.0, delta=0.1, seed=1)
+    for k in range(30):
+        G.sweep(10)
+        O.sweep(10)
+        assert G.counters() == O.counters(), k
+        if (k + 1) % 10 == 0:
+            log("  medium sweep %d" % (10 * (k + 1)))
+            assert_same(G, O, "medium %d" % (10 * (k + 1)))
+    assert G.count_overlaps() == 0
+
+
+@pytest.mark.parametrize("phi", [0.70, 0.716, 0.720])
+def test_large_workload_full_size(gpu, phi):
+    """N = 1,048,576 at the benchmark's geometry (w < sqrt(2), capacity 4),
+    launched as the benchmark launches it (captured graphs of 16 sweeps):
+    the whole state after 16 sweeps equals the oracle's."""
+    G, O = lattice_pair(gpu, 1024, 1024, phi, math.sqrt(2.0), delta=0.1, seed=1, flags=0)
+    assert_same(G, O, "init")
+    G.sweep(16)
+    O.sweep(16)
+    assert_same(G, O, "16 sweeps")
+    assert G.count_overlaps() == 0
