@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--cpu-sweeps", type=int, default=0,
                     help="oracle sweeps for the CPU baseline (0 = sized to ~15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (a known byte count "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -80,6 +83,14 @@ def main():
                            w_max=math.sqrt(2.0), delta=0.1, n_moves=args.n_moves, seed=1, flags=0)
     print("[bench] building system N=%d phi=%.3f" % (args.lattice ** 2, args.phi), file=sys.stderr,
           flush=True)
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     S = pkg.HardDiskSystem(cfg)
     S.set_launch(1, args.block)
     geo = S.geometry

@@ -199,8 +199,9 @@ mpmc_status mpmc_get_delta(mpmc_handle h, float *delta);
  * on the device. */
 mpmc_status mpmc_tune(mpmc_handle h, int32_t window_sweeps, int32_t n_windows);
 
-/* Launch shape: lanes cooperating on one cell (1, 2, 4, 8, 16) and
- * workgroup size (64..1024, a multiple of 64).  Results do not depend on it. */
+/* Launch shape: lanes cooperating on one cell (1) and workgroup size (64,
+ * 128, 192 or 256; reduced where a wider cell's neighbour table would exceed
+ * 64 KB of LDS).  Results do not depend on it. */
 mpmc_status mpmc_set_launch(mpmc_handle h, int32_t lanes_per_cell, int32_t block_size);
 
 /* Wait for all work enqueued by this handle; reports MPMC_EDEVICE if a kernel

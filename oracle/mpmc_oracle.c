@@ -638,20 +638,40 @@ int oracle_set_state(oracle_sys *S, const float *xy, const uint32_t *start,
     }
     S->N = start[S->C];
     S->sweep = sweep;
+    S->trials = S->accepts = 0; /* counters run from the loaded state */
     return ORC_OK;
 }
 
-/* Any overlapping pair, in the same metric as the trial moves?  Returns the
- * number of ordered overlapping pairs. */
+/* Invariant check: ordered pairs (k, j) with r^2 < 1 - 2^-16 evaluated in
+ * k's frame as in the trial moves.  A move is tested in the mover's frame
+ * (r^2 < 1); seen from the partner's frame the same pair may round to
+ * 1 - a few ulp, so the invariant allows that much slack. */
 int64_t oracle_count_overlaps(const oracle_sys *S)
 {
+    const float r2min = 1.0f - 0x1p-16f;
     int64_t bad = 0;
     for (int cy = 0; cy < S->my; ++cy)
         for (int cx = 0; cx < S->mx; ++cx) {
             int c = cy * S->mx + cx;
             for (int i = 0; i < S->n[c]; ++i) {
-                int slot = c * S->cap + i;
-                bad += overlaps(S, cx, cy, slot, S->disk_x[slot], S->disk_y[slot]);
+                int self = c * S->cap + i;
+                float xk = S->disk_x[self], yk = S->disk_y[self];
+                for (int oy = -1; oy <= 1; ++oy) {
+                    int ncy = wrap(cy + oy, S->my);
+                    float ty = oy < 0 ? -S->wy : (oy > 0 ? S->wy : 0.0f);
+                    for (int ox = -1; ox <= 1; ++ox) {
+                        int ncx = wrap(cx + ox, S->mx);
+                        float tx = ox < 0 ? -S->wx : (ox > 0 ? S->wx : 0.0f);
+                        int nc = ncy * S->mx + ncx;
+                        for (int j = 0; j < S->n[nc]; ++j) {
+                            int slot = nc * S->cap + j;
+                            if (slot == self) continue;
+                            float ddx = xk - (S->disk_x[slot] + tx);
+                            float ddy = yk - (S->disk_y[slot] + ty);
+                            bad += (ddx * ddx + ddy * ddy < r2min);
+                        }
+                    }
+                }
             }
         }
     return bad;

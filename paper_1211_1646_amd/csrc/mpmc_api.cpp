@@ -147,7 +147,9 @@ mpmc_status check_params(const mpmc_params *p, const mpmc_geometry &g)
 
 size_t work_bytes(long long C)
 {
-    return align256((size_t)mpmc::scan_partials(C) * 4) + 512 * sizeof(double) + 256;
+    return align256((size_t)mpmc::scan_partials(C) * 4) +
+           align256((size_t)mpmc::count_stride(C) * 10 * 4) +
+           (size_t)mpmc::kMsdBlocksMax * sizeof(double) + 256;
 }
 
 }  // namespace
@@ -161,14 +163,14 @@ struct mpmc_system {
     uint32_t *start[2];
     float2 *acc[2];
     uint32_t *tag[2];
-    uint32_t *work_u32;
-    double *work_f64;
+    mpmc::Work work;
     Ctl *ctl;
     int cur;
     int lanes;
     int block;
     uint32_t key0;
-    bool ready;   // a valid, overlap-free state is on the device
+    bool ready;        // a valid, overlap-free state is on the device
+    bool lone_pending; // lone sub-sweep counts not yet folded into ctl
     hipGraphExec_t graph[2];
 };
 
@@ -185,6 +187,10 @@ void drop_graphs(mpmc_system *h)
 
 mpmc_status read_ctl(mpmc_system *h, Ctl *out)
 {
+    if (h->lone_pending) {
+        MPMC_HIP(mpmc::launch_fold_lone(h->work, h->ctl, h->st));
+        h->lone_pending = false;
+    }
     MPMC_HIP(hipMemcpyAsync(out, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->st));
     MPMC_HIP(hipStreamSynchronize(h->st));
     if (out->errword) {
@@ -198,17 +204,21 @@ mpmc_status read_ctl(mpmc_system *h, Ctl *out)
 
 mpmc_status enqueue_subsweep(mpmc_system *h, int set)
 {
-    MPMC_HIP(mpmc::launch_subsweep(h->g, h->pos[h->cur], h->start[h->cur], h->acc[h->cur], h->ctl,
-                                   h->p.n_moves, set, h->lanes, h->block, h->st));
+    if (set >= 0) h->lone_pending = true;
+    MPMC_HIP(mpmc::launch_subsweep(h->g, h->pos[h->cur], h->start[h->cur], h->acc[h->cur],
+                                   h->tag[h->cur], h->ctl, h->work, h->p.n_moves, set, h->lanes,
+                                   h->block, h->st));
     return MPMC_OK;
 }
 
-mpmc_status enqueue_rebin(mpmc_system *h, int f, float d, int advance)
+// fold_block > 0: the four sub-sweeps of this sweep ran with that workgroup
+// size and their counters are folded by the rebin's scan.
+mpmc_status enqueue_rebin(mpmc_system *h, int f, float d, int advance, int fold_block)
 {
     const int o = h->cur ^ 1;
     MPMC_HIP(mpmc::launch_rebin(h->g, h->pos[h->cur], h->start[h->cur], h->acc[h->cur],
                                 h->tag[h->cur], h->pos[o], h->start[o], h->acc[o], h->tag[o],
-                                h->work_u32, h->ctl, f, d, advance, h->block, h->st));
+                                h->work, h->ctl, f, d, advance, h->block, fold_block, h->st));
     h->cur = o;
     return MPMC_OK;
 }
@@ -219,7 +229,7 @@ mpmc_status enqueue_sweep(mpmc_system *h)
         const mpmc_status s = enqueue_subsweep(h, -1 - slot);
         if (s) return s;
     }
-    return enqueue_rebin(h, -1, 0.0f, 1);
+    return enqueue_rebin(h, -1, 0.0f, 1, h->block);
 }
 
 mpmc_status run_sweeps(mpmc_system *h, int64_t n)
@@ -293,6 +303,8 @@ mpmc_status upload_state(mpmc_system *h, const float *xy, const uint32_t *start,
     }
     if (h->acc[0]) MPMC_HIP(mpmc::launch_fill_u32((uint32_t *)h->acc[0], 0u, 2 * N, h->st));
     MPMC_HIP(mpmc::launch_ctl_reset(h->ctl, sweep, h->key0, h->p.replica, h->p.delta, h->st));
+    MPMC_HIP(mpmc::launch_fill_u32(h->work.cnt, 0u, 10LL * h->work.cnt_stride, h->st));
+    h->lone_pending = false;
     MPMC_HIP(hipStreamSynchronize(h->st));
     // overlap check in the kernels' metric
     MPMC_HIP(mpmc::launch_count_overlaps(h->g, h->pos[0], h->start[0], h->ctl, h->block, h->st));
@@ -371,14 +383,22 @@ mpmc_status mpmc_init_system(const mpmc_params *p, const mpmc_buffers *b, void *
         h->acc[i] = (p->flags & MPMC_FLAG_ACC) ? (float2 *)b->acc[i] : nullptr;
         h->tag[i] = (p->flags & MPMC_FLAG_TAG) ? (uint32_t *)b->tag[i] : nullptr;
     }
-    h->work_u32 = (uint32_t *)b->work;
-    h->work_f64 = (double *)((char *)b->work + align256((size_t)mpmc::scan_partials(h->g.C) * 4));
+    {
+        char *w = (char *)b->work;
+        h->work.scan = (uint32_t *)w;
+        w += align256((size_t)mpmc::scan_partials(h->g.C) * 4);
+        h->work.cnt = (uint32_t *)w;
+        h->work.cnt_stride = (int)mpmc::count_stride(h->g.C);
+        w += align256((size_t)mpmc::count_stride(h->g.C) * 10 * 4);
+        h->work.f64 = (double *)w;
+    }
     h->ctl = (Ctl *)b->ctl;
     h->cur = 0;
     h->lanes = 1;
     h->block = 256;
     h->key0 = p->seed;
     h->ready = false;
+    h->lone_pending = false;
     h->graph[0] = h->graph[1] = nullptr;
 
     const int C = h->g.C;
@@ -445,8 +465,8 @@ mpmc_status mpmc_init_system(const mpmc_params *p, const mpmc_buffers *b, void *
 
 mpmc_status mpmc_sweep(mpmc_handle h, int64_t n_sweeps, uint32_t seed)
 {
-    MPMC_NEED_STATE(h);
     if (!h || n_sweeps < 0) return fail(MPMC_EINVAL, "bad handle or sweep count");
+    MPMC_NEED_STATE(h);
     if (seed != h->key0) {
         MPMC_HIP(mpmc::launch_ctl_set_key0(h->ctl, seed, h->st));
         h->key0 = seed;
@@ -456,21 +476,21 @@ mpmc_status mpmc_sweep(mpmc_handle h, int64_t n_sweeps, uint32_t seed)
 
 mpmc_status mpmc_subsweep(mpmc_handle h, int32_t set)
 {
-    MPMC_NEED_STATE(h);
     if (!h || set < 0 || set > 3) return fail(MPMC_EINVAL, "set must be 0..3");
+    MPMC_NEED_STATE(h);
     return enqueue_subsweep(h, set);
 }
 
 mpmc_status mpmc_shift_and_rebin(mpmc_handle h, int32_t f, float d)
 {
-    MPMC_NEED_STATE(h);
     if (!h || f < -1 || f > 3) return fail(MPMC_EINVAL, "f must be -1..3");
     if (f >= 0) {
         const float w = f < 2 ? h->g.wx : h->g.wy;
         if (!(d >= 0.0f && d <= 0.5f * w)) return fail(MPMC_EINVAL, "d must lie in [0, w/2]");
-        return enqueue_rebin(h, f, d, 0);
     }
-    return enqueue_rebin(h, -1, 0.0f, 1);
+    MPMC_NEED_STATE(h);
+    if (f >= 0) return enqueue_rebin(h, f, d, 0, 0);
+    return enqueue_rebin(h, -1, 0.0f, 1, 0);
 }
 
 mpmc_status mpmc_pair_histogram(mpmc_handle h, int32_t reset)
@@ -561,7 +581,7 @@ mpmc_status mpmc_msd(mpmc_handle h, double *msd)
     MPMC_NEED_STATE(h);
     if (!h || !msd) return fail(MPMC_EINVAL, "null argument");
     if (!h->acc[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_ACC");
-    MPMC_HIP(mpmc::launch_msd(h->g, h->acc[h->cur], h->work_f64, h->ctl, h->st));
+    MPMC_HIP(mpmc::launch_msd(h->g, h->acc[h->cur], h->work, h->ctl, h->st));
     Ctl c;
     const mpmc_status s = read_ctl(h, &c);
     if (s) return s;
@@ -614,8 +634,8 @@ mpmc_status mpmc_get_delta(mpmc_handle h, float *delta)
 
 mpmc_status mpmc_tune(mpmc_handle h, int32_t window_sweeps, int32_t n_windows)
 {
-    MPMC_NEED_STATE(h);
     if (!h || window_sweeps < 1 || n_windows < 0) return fail(MPMC_EINVAL, "bad tuner arguments");
+    MPMC_NEED_STATE(h);
     MPMC_HIP(mpmc::launch_tune(h->g, h->ctl, 0, h->st));   // open the first window
     for (int w = 0; w < n_windows; ++w) {
         const mpmc_status s = run_sweeps(h, window_sweeps);
@@ -630,8 +650,8 @@ mpmc_status mpmc_set_launch(mpmc_handle h, int32_t lanes_per_cell, int32_t block
     if (!h) return fail(MPMC_EINVAL, "null handle");
     if (lanes_per_cell != 1)
         return fail(MPMC_EINVAL, "lanes_per_cell must be 1");
-    if (block_size < 64 || block_size > 1024 || block_size % 64)
-        return fail(MPMC_EINVAL, "block size must be a multiple of 64 in [64, 1024]");
+    if (block_size < 64 || block_size > 256 || block_size % 64)
+        return fail(MPMC_EINVAL, "block size must be a multiple of 64 in [64, 256]");
     drop_graphs(h);
     h->lanes = lanes_per_cell;
     h->block = block_size;

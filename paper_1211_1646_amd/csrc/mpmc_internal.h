@@ -22,8 +22,8 @@ struct alignas(256) Ctl {
     unsigned int key0, key1;         // Philox key (seed, replica)
     float delta;                     // maximum trial displacement
     unsigned int errword;            // kErr* bits set by kernels
-    unsigned int done;               // finished-workgroup counter of the rebin
-    unsigned int pad0;
+    int shift_f;                     // the sweep's shift, recorded by the scan
+    float shift_d;                   //   kernel before it advances the sweep
     unsigned long long hist_samples; // configurations in hist[]
     double fit[4];                   // P*, g(sigma+), rho, status
     long long overlaps;              // ordered overlapping pairs (count kernel)
@@ -45,27 +45,44 @@ struct SweepBuffers {
     const uint32_t *tag;
 };
 
+// Scratch layout (caller's work buffer): u32 scan partials of the rebin,
+// then per-workgroup trial/accept partials (slot-major [slot][trials|accepts]
+// [tile]: slots 0-3 are the four sub-sweeps of a sweep, slot 4 accumulates
+// lone sub-sweeps), then FP64 reduction partials.
+struct Work {
+    uint32_t *scan;    // scan_partials(C) entries
+    uint32_t *cnt;     // 10 * count_stride(C) entries
+    double *f64;       // kMsdBlocksMax entries
+    int cnt_stride;
+};
+
 // ---- launch wrappers (defined in mpmc_kernels.hip) ----
-// Sub-sweep of one checkerboard set; set >= 0 explicit, set < 0 means the
-// sweep's slot (-1 - set) of the shuffled set order.
+// Sub-sweep of one checkerboard set; set >= 0 explicit (its counters go to
+// the lone slot, folded by launch_fold_lone), set < 0 means the sweep's slot
+// (-1 - set) of the shuffled set order (counters folded by the rebin).  The
+// workgroup size is at most 256 (LDS: 8 * cap float2 per lane).
 hipError_t launch_subsweep(const Geom &g, float2 *pos, const uint32_t *start, float2 *acc,
-                           Ctl *ctl, int n_moves, int set, int lanes_per_cell, int block,
-                           hipStream_t st);
+                           uint32_t *tag, Ctl *ctl, const Work &w, int n_moves, int set,
+                           int lanes_per_cell, int block, hipStream_t st);
 
 // Shift (f, d) -- or the sweep's own draws when f < 0 -- and rebuild the
 // cell lists into the *_out buffers.  advance != 0 increments the sweep.
+hipError_t launch_fold_lone(const Work &w, Ctl *ctl, hipStream_t st);
+
+// With f < 0 it also folds the four sub-sweeps' counters (sub_block = their
+// workgroup size) into the control block.
 hipError_t launch_rebin(const Geom &g, const float2 *pos, const uint32_t *start,
                         const float2 *acc, const uint32_t *tag, float2 *pos_out,
                         uint32_t *start_out, float2 *acc_out, uint32_t *tag_out,
-                        uint32_t *work, Ctl *ctl, int f, float d, int advance, int block,
-                        hipStream_t st);
+                        const Work &w, Ctl *ctl, int f, float d, int advance, int block,
+                        int sub_block, hipStream_t st);
 
 hipError_t launch_pair_histogram(const Geom &g, const float2 *pos, const uint32_t *start,
                                  Ctl *ctl, int reset, int block, hipStream_t st);
 hipError_t launch_pressure_fit(const Geom &g, Ctl *ctl, hipStream_t st);
 hipError_t launch_count_overlaps(const Geom &g, const float2 *pos, const uint32_t *start,
                                  Ctl *ctl, int block, hipStream_t st);
-hipError_t launch_msd(const Geom &g, const float2 *acc, double *work, Ctl *ctl,
+hipError_t launch_msd(const Geom &g, const float2 *acc, const Work &w, Ctl *ctl,
                       hipStream_t st);
 // apply == 0 only opens a new tuner window (records the counters).
 hipError_t launch_tune(const Geom &g, Ctl *ctl, int apply, hipStream_t st);
@@ -75,9 +92,10 @@ hipError_t launch_ctl_reset(Ctl *ctl, unsigned long long sweep, unsigned int key
 hipError_t launch_ctl_set_key0(Ctl *ctl, unsigned int key0, hipStream_t st);
 hipError_t launch_ctl_set_delta(Ctl *ctl, float delta, hipStream_t st);
 
-// Work-buffer layout: u32 scan partials for rebin, then FP64 reduction
-// partials; sized by the host from the smallest workgroup allowed.
+// Work-buffer sizes, from the smallest workgroup allowed.
 constexpr int kMinBlock = 64;
+constexpr int kMsdBlocksMax = 512;
 inline long long scan_partials(long long C) { return (C + kMinBlock - 1) / kMinBlock + 8; }
+inline long long count_stride(long long C) { return (C / 4 + kMinBlock - 1) / kMinBlock + 8; }
 
 }  // namespace mpmc

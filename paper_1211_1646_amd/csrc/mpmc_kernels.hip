@@ -16,6 +16,8 @@
 // Every floating-point expression is written so that each operation rounds
 // once (no contraction); the library is built with -ffp-contract=off and the
 // pragma below repeats it for these kernels.
+#include <utility>
+
 #include "mpmc_internal.h"
 
 #pragma clang fp contract(off)
@@ -102,30 +104,56 @@ __device__ __forceinline__ Draws sweep_draws(unsigned long long s, uint32_t k0, 
     return D;
 }
 
-// Register arrays indexed by a run-time slot: unrolled selects, no scratch.
-template <int CAP>
-__device__ __forceinline__ float rsel(const float (&a)[CAP], int i)
+// Small per-lane register arrays.  Every element access below uses a
+// compile-time index (C++17 fold expressions over an index sequence), so the
+// arrays live in VGPRs from the first optimisation pass on; run-time slots
+// are handled by select networks, never by indexing.
+template <typename T, int N, int... I>
+__device__ __forceinline__ T rsel_(const T (&a)[N], int i, std::integer_sequence<int, I...>)
 {
-    float r = a[0];
-#pragma unroll
-    for (int q = 1; q < CAP; ++q) r = (i == q) ? a[q] : r;
+    T r = a[0];
+    ((r = (I == i) ? a[I] : r), ...);
     return r;
 }
-
-template <int CAP>
-__device__ __forceinline__ void rput(float (&a)[CAP], int i, float v)
+template <typename T, int N>
+__device__ __forceinline__ T rsel(const T (&a)[N], int i)
 {
-#pragma unroll
-    for (int q = 0; q < CAP; ++q)
-        if (i == q) a[q] = v;
+    return rsel_(a, i, std::make_integer_sequence<int, N>{});
 }
 
-template <int CAP>
-__device__ __forceinline__ void rswap(float (&a)[CAP], int i, int j)
+// Rotate the first n entries left by one: a[0..n) <- a[1], ..., a[n-1], a[0].
+template <typename T, int N, int... I>
+__device__ __forceinline__ void rrot_(T (&a)[N], int n, std::integer_sequence<int, I...>)
 {
-    const float vi = rsel(a, i), vj = rsel(a, j);
-    rput(a, i, vj);
-    rput(a, j, vi);
+    const T first = a[0];
+    ((a[I] = (I + 1 < n) ? a[(I + 1 < N) ? I + 1 : I] : ((I == n - 1) ? first : a[I])), ...);
+}
+template <typename T, int N>
+__device__ __forceinline__ void rrot(T (&a)[N], int n)
+{
+    rrot_(a, n, std::make_integer_sequence<int, N>{});
+}
+
+// a[q] <- a[perm nibble q] for every q: apply a permutation packed as 4-bit
+// source indices.
+template <typename T, int N, int... I>
+__device__ __forceinline__ void rperm_(T (&a)[N], uint32_t P, std::integer_sequence<int, I...>)
+{
+    const T old[N] = {a[I]...};
+    ((a[I] = rsel(old, (int)((P >> (4 * I)) & 0xFu))), ...);
+}
+template <typename T, int N>
+__device__ __forceinline__ void rperm(T (&a)[N], uint32_t P)
+{
+    rperm_(a, P, std::make_integer_sequence<int, N>{});
+}
+
+// Swap nibbles i and j of a packed permutation.
+__device__ __forceinline__ uint32_t nib_swap(uint32_t P, int i, int j)
+{
+    const uint32_t vi = (P >> (4 * i)) & 0xFu, vj = (P >> (4 * j)) & 0xFu;
+    P &= ~((0xFu << (4 * i)) | (0xFu << (4 * j)));
+    return P | (vj << (4 * i)) | (vi << (4 * j));
 }
 
 // Workgroup id -> logical tile, so that consecutive tiles (neighbouring
@@ -184,15 +212,30 @@ __device__ __forceinline__ unsigned block_exclusive_scan_u32(unsigned v, unsigne
 }
 
 // ------------------------------------------------------------ sub-sweep
-// One lane per active cell of set Q (Alg. 2).  The cell's particles and
-// accumulators sit in registers; the eight inactive neighbour cells are read
-// from memory (they are not written during this sub-sweep).
+// One lane per active cell of set Q (Alg. 2).  The kernel is organised to
+// expose memory-level parallelism rather than to chase pointers:
+//   1. all 18 offsets of the 3x3 block are loaded at once;
+//   2. every position of the block is loaded at once (predicated by count);
+//      the Philox blocks of the cell are computed while the loads fly;
+//   3. neighbour disks are translated into the cell's frame (exactly -w, 0
+//      or +w, Sec. 3.1) and those that can reach the cell at all -- closer
+//      than 1.0001 to the cell rectangle, a superset of every disk a trial
+//      position inside the cell can overlap -- are compacted into this
+//      lane's column of an LDS table (row-major by entry, one column per
+//      lane, so a wave reads 64 consecutive float2 per row);
+//   4. the n_M trials run from registers (own cell) and LDS (neighbours).
+// Dropping unreachable disks cannot change a decision: a trial outside the
+// cell is rejected before any overlap test, and one inside it is at distance
+// >= 1 from every dropped disk.
+constexpr float kReach2 = 1.0001f;
+
 template <int CAP>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(256)
 k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
-           float2 *__restrict__ acc, Ctl *__restrict__ ctl, int n_moves, int set, int ntile,
-           int per)
+           float2 *__restrict__ acc, uint32_t *__restrict__ tag, const Ctl *__restrict__ ctl,
+           uint32_t *__restrict__ cnt, int cnt_stride, int n_moves, int set, int ntile, int per)
 {
+    extern __shared__ float2 nbr[];   // [8 * CAP][blockDim.x]
     __shared__ unsigned red[2][16];
     const int tile = xcd_tile(per);
     const unsigned long long s = ctl->sweep;
@@ -208,24 +251,49 @@ k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
     const int qx = Q & 1, qy = Q >> 1;
     const int hx = g.mx >> 1, hy = g.my >> 1;
     const int gid = tile * (int)blockDim.x + (int)threadIdx.x;
+    const int L = (int)blockDim.x, lane = (int)threadIdx.x;
 
     unsigned n_trials = 0, n_acc = 0;
     if (tile < ntile && gid < hx * hy) {
         const int iy = gid / hx, ix = gid - iy * hx;
         const int cx = 2 * ix + qx, cy = 2 * iy + qy;
         const int c = cy * g.mx + cx;
-        const uint32_t b0 = start[c];
-        int n = (int)(start[c + 1] - b0);
-        if (n > CAP) {
-            atomicOr(&ctl->errword, kErrCapacity);
+        const int xl = cx == 0 ? g.mx - 1 : cx - 1;
+        const int xr = cx == g.mx - 1 ? 0 : cx + 1;
+        const int yd = cy == 0 ? g.my - 1 : cy - 1;
+        const int yu = cy == g.my - 1 ? 0 : cy + 1;
+        // 1. offsets of the nine cells q = 3*row + col, row/col 0,1,2 = -1,0,+1
+        uint32_t rb[9], rn[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const int row = q / 3 == 0 ? yd : (q / 3 == 1 ? cy : yu);
+            const int col = q % 3 == 0 ? xl : (q % 3 == 1 ? cx : xr);
+            const int cc = row * g.mx + col;
+            rb[q] = start[cc];
+            rn[q] = start[cc + 1];
+        }
+        bool bad = false;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            rn[q] -= rb[q];
+            bad |= rn[q] > (uint32_t)CAP;
+        }
+        int n = (int)rn[4];
+        if (bad) {
+            atomicOr((unsigned int *)&ctl->errword, kErrCapacity);
             n = 0;
         }
         if (n > 0) {
-            const bool has_acc = acc != nullptr;
+            const uint32_t b0 = rb[4];
+            const bool has_acc = acc != nullptr, has_tag = tag != nullptr;
+            // 2. all positions of the block in flight together
+            float2 nv[9][CAP];
             float px[CAP], py[CAP], ax[CAP], ay[CAP];
+            uint32_t tg[CAP];
 #pragma unroll
             for (int q = 0; q < CAP; ++q) {
                 px[q] = py[q] = ax[q] = ay[q] = 0.0f;
+                tg[q] = 0u;
                 if (q < n) {
                     const float2 v = pos[b0 + q];
                     px[q] = v.x;
@@ -235,61 +303,77 @@ k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
                         ax[q] = a.x;
                         ay[q] = a.y;
                     }
+                    if (has_tag) tg[q] = tag[b0 + q];
                 }
             }
-            // rng.shuffle(c.particles): Fisher-Yates over the stored list.
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+#pragma unroll
+                for (int i = 0; i < CAP; ++i) {
+                    nv[q][i] = make_float2(0.0f, 0.0f);
+                    if (q != 4 && i < (int)rn[q]) nv[q][i] = pos[rb[q] + i];
+                }
+            }
+            // Philox blocks of this cell: one shuffle block (n <= 5) and the
+            // first trial block, issued while the loads are outstanding.
+            uint4 Wsh = make_uint4(0, 0, 0, 0);
+            if (n > 1) Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle, k0, k1);
             uint4 W = make_uint4(0, 0, 0, 0);
-            for (int k = 0; k < n - 1; ++k) {
-                if ((k & 3) == 0)
-                    W = philox((uint32_t)c, s_lo, s_hi, kTagShuffle + (uint32_t)(k >> 2), k0, k1);
-                const int i = n - 1 - k;
-                const int j = (int)bounded(word_of(W, k & 3), (uint32_t)(i + 1));
-                rswap(px, i, j);
-                rswap(py, i, j);
-                if (has_acc) {
-                    rswap(ax, i, j);
-                    rswap(ay, i, j);
+            if (n_moves > 0) W = philox((uint32_t)c, s_lo, s_hi, 0u, k0, k1);
+            // 3. translate, keep the reachable ones, compact into LDS
+            int K = 0;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                if (q == 4) continue;
+                const float tx = q % 3 == 0 ? -g.wx : (q % 3 == 2 ? g.wx : 0.0f);
+                const float ty = q / 3 == 0 ? -g.wy : (q / 3 == 2 ? g.wy : 0.0f);
+#pragma unroll
+                for (int i = 0; i < CAP; ++i) {
+                    if (i < (int)rn[q]) {
+                        const float ox = nv[q][i].x + tx;
+                        const float oy = nv[q][i].y + ty;
+                        const float ex = ox < 0.0f ? -ox : (ox > g.wx ? ox - g.wx : 0.0f);
+                        const float ey = oy < 0.0f ? -oy : (oy > g.wy ? oy - g.wy : 0.0f);
+                        if (ex * ex + ey * ey < kReach2) {
+                            nbr[K * L + lane] = make_float2(ox, oy);
+                            ++K;
+                        }
+                    }
                 }
             }
-            // The eight neighbour cells: index ranges and translations
-            // (exactly -w, 0 or +w, Sec. 3.1).
-            const int xl = cx == 0 ? g.mx - 1 : cx - 1;
-            const int xr = cx == g.mx - 1 ? 0 : cx + 1;
-            const int yd = cy == 0 ? g.my - 1 : cy - 1;
-            const int yu = cy == g.my - 1 ? 0 : cy + 1;
-            uint32_t nb[8], ne[8];
-            float tx[8], ty[8];
-            {
-                const int cols[3] = {xl, cx, xr};
-                const int rows[3] = {yd, cy, yu};
-                const float txs[3] = {-g.wx, 0.0f, g.wx};
-                const float tys[3] = {-g.wy, 0.0f, g.wy};
-                int q = 0;
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        if (a == 1 && b == 1) continue;
-                        const int nc = rows[a] * g.mx + cols[b];
-                        nb[q] = start[nc];
-                        ne[q] = start[nc + 1];
-                        tx[q] = txs[b];
-                        ty[q] = tys[a];
-                        ++q;
-                    }
+            // rng.shuffle(c.particles): Fisher-Yates over the stored list,
+            // done on a packed permutation (nibble q = source slot of list
+            // position q) and applied to the registers once.
+            uint32_t P = 0x76543210u;
+            for (int k = 0; k < n - 1; ++k) {
+                if (k > 0 && (k & 3) == 0)
+                    Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle + (uint32_t)(k >> 2), k0, k1);
+                const int i = n - 1 - k;
+                const int j = (int)bounded(word_of(Wsh, k & 3), (uint32_t)(i + 1));
+                P = nib_swap(P, i, j);
             }
-            int p = 0;
+            if (n > 1) {
+                rperm(px, P);
+                rperm(py, P);
+                if (has_acc) {
+                    rperm(ax, P);
+                    rperm(ay, P);
+                }
+                if (has_tag) rperm(tg, P);
+            }
+            // 4. n_M trial moves on list[t mod n]: the registers are rotated
+            // after every trial so that the particle moved is always entry 0.
             for (int t = 0; t < n_moves; ++t) {
-                if ((t & 3) == 0) W = philox((uint32_t)c, s_lo, s_hi, (uint32_t)(t >> 2), k0, k1);
+                if (t > 0 && (t & 3) == 0) W = philox((uint32_t)c, s_lo, s_hi, (uint32_t)(t >> 2), k0, k1);
                 float dx, dy;
                 displacement(word_of(W, t & 3), delta, dx, dy);
-                const float xm = rsel(px, p) + dx;
-                const float ym = rsel(py, p) + dy;
+                const float xm = px[0] + dx;
+                const float ym = py[0] + dy;
                 bool ok = xm > 0.0f && xm <= g.wx && ym > 0.0f && ym <= g.wy;
                 if (ok) {
 #pragma unroll
-                    for (int q = 0; q < CAP; ++q) {
-                        if (q < n && q != p) {
+                    for (int q = 1; q < CAP; ++q) {
+                        if (q < n) {
                             const float ddx = xm - px[q];
                             const float ddy = ym - py[q];
                             const float r2 = ddx * ddx + ddy * ddy;
@@ -297,47 +381,109 @@ k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
                         }
                     }
                 }
-                if (ok) {
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        for (uint32_t j = nb[q]; j < ne[q]; ++j) {
-                            const float2 v = pos[j];
-                            const float ox = v.x + tx[q];
-                            const float oy = v.y + ty[q];
-                            const float ddx = xm - ox;
-                            const float ddy = ym - oy;
-                            const float r2 = ddx * ddx + ddy * ddy;
-                            if (r2 < 1.0f) ok = false;
-                        }
-                    }
+                for (int k = 0; ok && k < K; ++k) {
+                    const float2 e = nbr[k * L + lane];
+                    const float ddx = xm - e.x;
+                    const float ddy = ym - e.y;
+                    const float r2 = ddx * ddx + ddy * ddy;
+                    ok = !(r2 < 1.0f);
                 }
                 if (ok) {
-                    rput(px, p, xm);
-                    rput(py, p, ym);
+                    px[0] = xm;
+                    py[0] = ym;
                     if (has_acc) {
-                        rput(ax, p, rsel(ax, p) + dx);
-                        rput(ay, p, rsel(ay, p) + dy);
+                        ax[0] = ax[0] + dx;
+                        ay[0] = ay[0] + dy;
                     }
                     ++n_acc;
                 }
-                if (++p == n) p = 0;
+                if (n > 1) {
+                    rrot(px, n);
+                    rrot(py, n);
+                    if (has_acc) {
+                        rrot(ax, n);
+                        rrot(ay, n);
+                    }
+                    if (has_tag) rrot(tg, n);
+                }
             }
             n_trials = (unsigned)n_moves;
+            // register entry q now holds list position (q + n_M) mod n
+            const int r0 = n_moves % n;
 #pragma unroll
             for (int q = 0; q < CAP; ++q) {
                 if (q < n) {
-                    pos[b0 + q] = make_float2(px[q], py[q]);
-                    if (has_acc) acc[b0 + q] = make_float2(ax[q], ay[q]);
+                    int o = q + r0;
+                    o = o >= n ? o - n : o;
+                    pos[b0 + o] = make_float2(px[q], py[q]);
+                    if (has_acc) acc[b0 + o] = make_float2(ax[q], ay[q]);
+                    if (has_tag && n > 1) tag[b0 + o] = tg[q];
                 }
             }
         }
     }
+    // Per-workgroup counts: a sweep's sub-sweep writes its slot (summed by the
+    // rebin's scan); a lone sub-sweep adds into the lone slot, whose entries
+    // each belong to one workgroup, and which is folded before the next read
+    // of the counters -- no contended atomics either way.
     const unsigned bt = block_sum_u32(n_trials, red[0]);
     const unsigned ba = block_sum_u32(n_acc, red[1]);
-    if (threadIdx.x == 0 && bt) {
-        atomicAdd(&ctl->trials, (unsigned long long)bt);
-        atomicAdd(&ctl->accepts, (unsigned long long)ba);
+    if (threadIdx.x == 0 && tile < ntile) {
+        if (set < 0) {
+            const int slot = -1 - set;
+            cnt[(2 * slot) * cnt_stride + tile] = bt;
+            cnt[(2 * slot + 1) * cnt_stride + tile] = ba;
+        } else {
+            cnt[8 * cnt_stride + tile] += bt;
+            cnt[9 * cnt_stride + tile] += ba;
+        }
     }
+}
+
+// Sum the per-workgroup counts of `nslots` consecutive slots into the control
+// block (one workgroup of <= 1024 threads).  zero != 0 clears the slots read.
+__device__ __forceinline__ void fold_counters(uint32_t *cnt, int stride, int nslots, int ntile,
+                                              int zero, Ctl *ctl, unsigned long long *sh)
+{
+    unsigned long long t = 0, a = 0;
+    for (int s = 0; s < nslots; ++s)
+        for (int i = threadIdx.x; i < ntile; i += blockDim.x) {
+            t += cnt[(2 * s) * stride + i];
+            a += cnt[(2 * s + 1) * stride + i];
+            if (zero) {
+                cnt[(2 * s) * stride + i] = 0u;
+                cnt[(2 * s + 1) * stride + i] = 0u;
+            }
+        }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        t += __shfl_xor(t, o, 64);
+        a += __shfl_xor(a, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[wave] = t;
+        sh[16 + wave] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long T = 0, A = 0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int q = 0; q < nw; ++q) {
+            T += sh[q];
+            A += sh[16 + q];
+        }
+        ctl->trials += T;
+        ctl->accepts += A;
+    }
+    __syncthreads();
+}
+
+// Fold the lone sub-sweeps' slot (8, 9) into the control block and clear it.
+__global__ void __launch_bounds__(1024) k_fold_lone(uint32_t *cnt, int stride, Ctl *ctl)
+{
+    __shared__ unsigned long long sh[32];
+    fold_counters(cnt + 8 * stride, stride, 1, stride, 1, ctl, sh);
 }
 
 // ----------------------------------------------------------------- rebin
@@ -361,7 +507,6 @@ struct RebinArgs {
     Ctl *ctl;
     int f;
     float d;
-    int advance;
     int ntile;
     int per;
 };
@@ -380,9 +525,14 @@ __global__ void __launch_bounds__(1024) k_rebin(RebinArgs a)
     int f = a.f;
     float d = a.d;
     if (f < 0) {
-        const Draws D = sweep_draws(a.ctl->sweep, a.ctl->key0, a.ctl->key1, g.wx, g.wy);
-        f = D.f;
-        d = D.d;
+        if (!SCATTER) {   // the sweep's own draws; the scan records them
+            const Draws D = sweep_draws(a.ctl->sweep, a.ctl->key0, a.ctl->key1, g.wx, g.wy);
+            f = D.f;
+            d = D.d;
+        } else {          // the sweep counter has advanced: use the record
+            f = a.ctl->shift_f;
+            d = a.ctl->shift_d;
+        }
     }
     const bool along_x = f < 2;
     const bool minus = (f == 0 || f == 2);   // +x / +y: t = v - d
@@ -449,24 +599,18 @@ __global__ void __launch_bounds__(1024) k_rebin(RebinArgs a)
             }
         }
     }
-    // The last workgroup to finish advances the sweep counter.  Every
-    // workgroup read the counter before arriving here.
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(&a.ctl->done, 1u);
-        if (prev == gridDim.x - 1) {
-            atomicExch(&a.ctl->done, 0u);
-            if (a.advance) atomicAdd(&a.ctl->sweep, 1ull);
-        }
-    }
 }
 
-// Exclusive scan of the per-tile totals in place (one workgroup).
-__global__ void __launch_bounds__(1024) k_scan_tiles(uint32_t *part, int ntile, Ctl *ctl,
-                                                     long long N)
+// Exclusive scan of the per-tile totals in place (one workgroup).  It also
+// folds the sweep's sub-sweep counters and, when the shift is the sweep's own,
+// records (f, d) for the scatter and advances the sweep counter: one thread of
+// one workgroup writes them, so no atomics are needed.
+__global__ void __launch_bounds__(1024)
+k_scan_tiles(uint32_t *part, int ntile, Ctl *ctl, long long N, uint32_t *cnt, int stride,
+             int nslots, int sub_tiles, int advance, float wx, float wy)
 {
     __shared__ unsigned red[16];
+    __shared__ unsigned long long sh[32];
     const int T = (int)blockDim.x;
     const int chunk = (ntile + T - 1) / T;
     const int b = (int)threadIdx.x * chunk;
@@ -481,6 +625,14 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(uint32_t *part, int ntile, 
         run += v;
     }
     if (threadIdx.x == 0 && (long long)total != N) atomicOr(&ctl->errword, kErrCount);
+    if (nslots > 0) fold_counters(cnt, stride, nslots, sub_tiles, 0, ctl, sh);
+    if (advance && threadIdx.x == 0) {
+        const unsigned long long s = ctl->sweep;
+        const Draws D = sweep_draws(s, ctl->key0, ctl->key1, wx, wy);
+        ctl->shift_f = D.f;
+        ctl->shift_d = D.d;
+        ctl->sweep = s + 1ull;
+    }
 }
 
 // ------------------------------------------------------ pair histogram
@@ -613,6 +765,11 @@ __global__ void __launch_bounds__(256) k_pressure_fit(Geom g, Ctl *ctl)
 }
 
 // ------------------------------------------------------ overlap count
+// A pair overlaps when r^2 < 1 - 2^-16 in either disk's frame.  The trial
+// moves test r^2 < 1 in the mover's frame; seen from the partner's frame the
+// same pair can round to 1 - a few ulp, so the invariant allows that slack.
+constexpr float kOverlapR2 = 1.0f - 0x1p-16f;
+
 __global__ void __launch_bounds__(256)
 k_count_overlaps(Geom g, const float2 *__restrict__ pos, const uint32_t *__restrict__ start,
                  Ctl *__restrict__ ctl, int ntile, int per)
@@ -637,7 +794,7 @@ k_count_overlaps(Geom g, const float2 *__restrict__ pos, const uint32_t *__restr
                         const float2 v = pos[j];
                         const float ddx = pk.x - (v.x + tx);
                         const float ddy = pk.y - (v.y + ty);
-                        bad += (ddx * ddx + ddy * ddy < 1.0f) ? 1u : 0u;
+                        bad += (ddx * ddx + ddy * ddy < kOverlapR2) ? 1u : 0u;
                     }
                 }
             }
@@ -651,7 +808,7 @@ __global__ void k_overlaps_reset(Ctl *ctl) { ctl->overlaps = 0; }
 
 // ------------------------------------------------------------- MSD
 // Deterministic FP64 reduction: fixed chunks per workgroup, fixed tree.
-constexpr int kMsdBlocks = 512;
+constexpr int kMsdBlocks = kMsdBlocksMax;
 constexpr int kMsdThreads = 256;
 
 __global__ void __launch_bounds__(kMsdThreads)
@@ -731,7 +888,8 @@ __global__ void k_ctl_reset(Ctl *ctl, unsigned long long sweep, unsigned int key
         ctl->key1 = key1;
         ctl->delta = delta;
         ctl->errword = 0u;
-        ctl->done = 0u;
+        ctl->shift_f = 0;
+        ctl->shift_d = 0.0f;
         ctl->hist_samples = 0ull;
         ctl->overlaps = 0;
         ctl->msd = 0.0;
@@ -744,48 +902,72 @@ __global__ void k_ctl_set_key0(Ctl *ctl, unsigned int key0) { ctl->key0 = key0; 
 __global__ void k_ctl_set_delta(Ctl *ctl, float delta) { ctl->delta = delta; }
 
 inline int tiles_for(long long items, int block) { return (int)((items + block - 1) / block); }
+
+// Workgroup size of the sub-sweep: the requested one, reduced so that the
+// neighbour table (8 * cap float2 per lane) stays within 64 KB of LDS.
+inline int sub_block_for(const Geom &g, int block)
+{
+    const int fit = (65536 / (8 * g.cap * (int)sizeof(float2))) / 64 * 64;
+    return block < fit ? block : fit;
+}
 inline int per_xcd(int ntile) { return (ntile + 7) / 8; }
 
 }  // namespace
 
 // ================================================================ launches
 hipError_t launch_subsweep(const Geom &g, float2 *pos, const uint32_t *start, float2 *acc,
-                           Ctl *ctl, int n_moves, int set, int lanes_per_cell, int block,
-                           hipStream_t st)
+                           uint32_t *tag, Ctl *ctl, const Work &w, int n_moves, int set,
+                           int lanes_per_cell, int block, hipStream_t st)
 {
-    if (lanes_per_cell != 1) return hipErrorInvalidValue;
+    if (lanes_per_cell != 1 || block > 256) return hipErrorInvalidValue;
+    block = sub_block_for(g, block);
     const long long cells = (long long)(g.mx / 2) * (g.my / 2);
     const int ntile = tiles_for(cells, block);
     const int per = per_xcd(ntile);
     const dim3 grid(8 * per), blk(block);
+    const size_t lds = (size_t)8 * g.cap * block * sizeof(float2);
+#define MPMC_SUB(CAP)                                                                          \
+    hipLaunchKernelGGL(k_subsweep<CAP>, grid, blk, lds, st, g, pos, start, acc, tag, ctl, w.cnt, \
+                       w.cnt_stride, n_moves, set, ntile, per)
     switch (g.cap) {
-    case 4: hipLaunchKernelGGL(k_subsweep<4>, grid, blk, 0, st, g, pos, start, acc, ctl, n_moves, set, ntile, per); break;
-    case 5: hipLaunchKernelGGL(k_subsweep<5>, grid, blk, 0, st, g, pos, start, acc, ctl, n_moves, set, ntile, per); break;
-    case 6: hipLaunchKernelGGL(k_subsweep<6>, grid, blk, 0, st, g, pos, start, acc, ctl, n_moves, set, ntile, per); break;
-    case 7: hipLaunchKernelGGL(k_subsweep<7>, grid, blk, 0, st, g, pos, start, acc, ctl, n_moves, set, ntile, per); break;
+    case 4: MPMC_SUB(4); break;
+    case 5: MPMC_SUB(5); break;
+    case 6: MPMC_SUB(6); break;
+    case 7: MPMC_SUB(7); break;
     default: return hipErrorInvalidValue;
     }
+#undef MPMC_SUB
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_lone(const Work &w, Ctl *ctl, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fold_lone, dim3(1), dim3(1024), 0, st, w.cnt, w.cnt_stride, ctl);
     return hipGetLastError();
 }
 
 hipError_t launch_rebin(const Geom &g, const float2 *pos, const uint32_t *start,
                         const float2 *acc, const uint32_t *tag, float2 *pos_out,
                         uint32_t *start_out, float2 *acc_out, uint32_t *tag_out,
-                        uint32_t *work, Ctl *ctl, int f, float d, int advance, int block,
-                        hipStream_t st)
+                        const Work &w, Ctl *ctl, int f, float d, int advance, int block,
+                        int sub_block, hipStream_t st)
 {
     RebinArgs a;
     a.g = g;
     a.pos = pos; a.start = start; a.acc = acc; a.tag = tag;
     a.pos_out = pos_out; a.start_out = start_out; a.acc_out = acc_out; a.tag_out = tag_out;
-    a.part = work;
+    a.part = w.scan;
     a.ctl = ctl;
-    a.f = f; a.d = d; a.advance = advance;
+    a.f = f; a.d = d;
     a.ntile = tiles_for(g.C, block);
     a.per = per_xcd(a.ntile);
     const dim3 grid(8 * a.per), blk(block);
+    const int fold = (f < 0 && sub_block > 0) ? 4 : 0;
+    const int sub_tiles =
+        sub_block > 0 ? tiles_for((long long)(g.mx / 2) * (g.my / 2), sub_block_for(g, sub_block)) : 0;
     hipLaunchKernelGGL(k_rebin<false>, grid, blk, 0, st, a);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, work, a.ntile, ctl, g.N);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, w.scan, a.ntile, ctl, g.N, w.cnt,
+                       w.cnt_stride, fold, sub_tiles, (f < 0 && advance) ? 1 : 0, g.wx, g.wy);
     hipLaunchKernelGGL(k_rebin<true>, grid, blk, 0, st, a);
     return hipGetLastError();
 }
@@ -823,10 +1005,10 @@ hipError_t launch_count_overlaps(const Geom &g, const float2 *pos, const uint32_
     return hipGetLastError();
 }
 
-hipError_t launch_msd(const Geom &g, const float2 *acc, double *work, Ctl *ctl, hipStream_t st)
+hipError_t launch_msd(const Geom &g, const float2 *acc, const Work &w, Ctl *ctl, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_msd_partial, dim3(kMsdBlocks), dim3(kMsdThreads), 0, st, acc, g.N, work);
-    hipLaunchKernelGGL(k_msd_final, dim3(1), dim3(kMsdThreads), 0, st, work, kMsdBlocks, g.N, ctl);
+    hipLaunchKernelGGL(k_msd_partial, dim3(kMsdBlocks), dim3(kMsdThreads), 0, st, acc, g.N, w.f64);
+    hipLaunchKernelGGL(k_msd_final, dim3(1), dim3(kMsdThreads), 0, st, w.f64, kMsdBlocks, g.N, ctl);
     return hipGetLastError();
 }
 
