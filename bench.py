@@ -35,7 +35,8 @@ def parse():
     ap.add_argument("--phi", type=float, default=0.70)
     ap.add_argument("--lattice", type=int, default=1024)
     ap.add_argument("--n-moves", type=int, default=4)
-    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--block", type=int, default=0,
+                    help="sub-sweep workgroup size; 0 = pick with the autotuner during warm-up")
     ap.add_argument("--kernel-samples", type=int, default=200,
                     help="sub-sweep launches timed one by one with HIP events")
     ap.add_argument("--cpu-sweeps", type=int, default=0,
@@ -92,7 +93,6 @@ def main():
         torch.cuda.synchronize()
         del a, b
     S = pkg.HardDiskSystem(cfg)
-    S.set_launch(1, args.block)
     geo = S.geometry
     N, C = geo["n_particles"], geo["cells_x"] * geo["cells_y"]
 
@@ -102,7 +102,15 @@ def main():
     S.sweep(args.warmup - 10 * windows)
     S.synchronize()
     delta = float(S.delta)
-    print("[bench] warm-up done, delta=%.5f" % delta, file=sys.stderr, flush=True)
+    # launch shape: autotuned (shape never changes results), or as given
+    if args.block > 0:
+        S.set_launch(1, args.block)
+        tuned = None
+    else:
+        tuned = S.autotune(16)
+    print("[bench] warm-up done, delta=%.5f, sub-sweep block %d%s" % (
+        delta, S.block, " (autotuned, %.1f us/sweep)" % tuned[1] if tuned else ""),
+        file=sys.stderr, flush=True)
 
     # timed sweeps: one captured graph per 16 sweeps, events on the system's stream
     t0_trials, t0_acc = S.counters()
@@ -163,6 +171,7 @@ def main():
                    "sweeps_per_s": args.steps / secs,
                    "acceptance": (t1_acc - t0_acc) / max(trials, 1),
                    "trial_moves_per_sweep": trials / args.steps,
+                   "subsweep_block": S.block,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

@@ -204,6 +204,16 @@ mpmc_status mpmc_tune(mpmc_handle h, int32_t window_sweeps, int32_t n_windows);
  * 64 KB of LDS).  Results do not depend on it. */
 mpmc_status mpmc_set_launch(mpmc_handle h, int32_t lanes_per_cell, int32_t block_size);
 
+/* Autotuner for the launch shape.  Only shape knobs that leave results bit
+ * for bit unchanged are searched (the sub-sweep workgroup size: 64, 128, 192,
+ * 256), so the sweeps it times are ordinary sweeps of the chain: for each
+ * candidate it runs `sweeps` sweeps to capture and warm the graph, then
+ * times `sweeps` more with HIP events on the stream, and finally keeps the
+ * fastest shape.  `sweeps` >= 16; the chain advances by 2 * sweeps per
+ * candidate.  sync.  Either output may be NULL. */
+mpmc_status mpmc_autotune(mpmc_handle h, int32_t sweeps, int32_t *block_out,
+                          double *us_per_sweep_out);
+
 /* Wait for all work enqueued by this handle; reports MPMC_EDEVICE if a kernel
  * set the error word. */
 mpmc_status mpmc_synchronize(mpmc_handle h);

@@ -81,6 +81,7 @@ _SIGNATURES = {
     "mpmc_get_delta": (C.c_int32, [_H, C.POINTER(C.c_float)]),
     "mpmc_tune": (C.c_int32, [_H, C.c_int32, C.c_int32]),
     "mpmc_set_launch": (C.c_int32, [_H, C.c_int32, C.c_int32]),
+    "mpmc_autotune": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "mpmc_synchronize": (C.c_int32, [_H]),
     "mpmc_destroy": (None, [_H]),
     "mpmc_last_error": (C.c_char_p, []),

@@ -39,6 +39,7 @@ mpmc_status fail(mpmc_status st, const std::string &msg)
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kGraphSweeps = 16;   // sweeps per captured graph (even)
+constexpr int kRebinBlock = 256;   // workgroup size of the rebin kernels
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
@@ -218,7 +219,7 @@ mpmc_status enqueue_rebin(mpmc_system *h, int f, float d, int advance, int fold_
     const int o = h->cur ^ 1;
     MPMC_HIP(mpmc::launch_rebin(h->g, h->pos[h->cur], h->start[h->cur], h->acc[h->cur],
                                 h->tag[h->cur], h->pos[o], h->start[o], h->acc[o], h->tag[o],
-                                h->work, h->ctl, f, d, advance, h->block, fold_block, h->st));
+                                h->work, h->ctl, f, d, advance, kRebinBlock, fold_block, h->st));
     h->cur = o;
     return MPMC_OK;
 }
@@ -302,7 +303,7 @@ mpmc_status upload_state(mpmc_system *h, const float *xy, const uint32_t *start,
         MPMC_HIP(hipMemcpyAsync(h->tag[0], tags, sizeof(uint32_t) * (size_t)N, hipMemcpyHostToDevice, h->st));
     }
     if (h->acc[0]) MPMC_HIP(mpmc::launch_fill_u32((uint32_t *)h->acc[0], 0u, 2 * N, h->st));
-    MPMC_HIP(mpmc::launch_ctl_reset(h->ctl, sweep, h->key0, h->p.replica, h->p.delta, h->st));
+    MPMC_HIP(mpmc::launch_ctl_reset(h->g, h->ctl, sweep, h->key0, h->p.replica, h->p.delta, h->st));
     MPMC_HIP(mpmc::launch_fill_u32(h->work.cnt, 0u, 10LL * h->work.cnt_stride, h->st));
     h->lone_pending = false;
     MPMC_HIP(hipStreamSynchronize(h->st));
@@ -448,7 +449,7 @@ mpmc_status mpmc_init_system(const mpmc_params *p, const mpmc_buffers *b, void *
         if (N != 0) {
             // empty until mpmc_set_state; start all zero is not a valid N > 0
             // state, so only the control block is initialised here
-            MPMC_HIP(mpmc::launch_ctl_reset(h->ctl, 0, h->key0, p->replica, p->delta, h->st));
+            MPMC_HIP(mpmc::launch_ctl_reset(h->g, h->ctl, 0, h->key0, p->replica, p->delta, h->st));
             MPMC_HIP(hipStreamSynchronize(h->st));
             s = MPMC_OK;
         } else {
@@ -468,7 +469,7 @@ mpmc_status mpmc_sweep(mpmc_handle h, int64_t n_sweeps, uint32_t seed)
     if (!h || n_sweeps < 0) return fail(MPMC_EINVAL, "bad handle or sweep count");
     MPMC_NEED_STATE(h);
     if (seed != h->key0) {
-        MPMC_HIP(mpmc::launch_ctl_set_key0(h->ctl, seed, h->st));
+        MPMC_HIP(mpmc::launch_ctl_set_key0(h->g, h->ctl, seed, h->st));
         h->key0 = seed;
     }
     return run_sweeps(h, n_sweeps);
@@ -656,6 +657,47 @@ mpmc_status mpmc_set_launch(mpmc_handle h, int32_t lanes_per_cell, int32_t block
     h->lanes = lanes_per_cell;
     h->block = block_size;
     return MPMC_OK;
+}
+
+mpmc_status mpmc_autotune(mpmc_handle h, int32_t sweeps, int32_t *block_out,
+                          double *us_per_sweep_out)
+{
+    if (!h || sweeps < 16) return fail(MPMC_EINVAL, "autotune needs at least 16 sweeps per candidate");
+    MPMC_NEED_STATE(h);
+    if (!h->st) return fail(MPMC_EINVAL, "autotune needs a non-default stream");
+    const int candidates[] = {64, 128, 192, 256};
+    hipEvent_t e0, e1;
+    MPMC_HIP(hipEventCreate(&e0));
+    MPMC_HIP(hipEventCreate(&e1));
+    int best = h->block;
+    float best_ms = -1.0f;
+    mpmc_status s = MPMC_OK;
+    for (int b : candidates) {
+        s = mpmc_set_launch(h, h->lanes, b);
+        if (s) break;
+        s = run_sweeps(h, sweeps);   // capture and warm
+        if (s) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e0, h->st) != hipSuccess || (s = run_sweeps(h, sweeps)) != MPMC_OK ||
+            hipEventRecord(e1, h->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            if (!s) s = fail(MPMC_EHIP, "autotune timing failed");
+            break;
+        }
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = b;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s) return s;
+    s = mpmc_set_launch(h, h->lanes, best);
+    if (s) return s;
+    if (block_out) *block_out = best;
+    if (us_per_sweep_out) *us_per_sweep_out = 1e3 * (double)best_ms / (double)sweeps;
+    Ctl c;
+    return read_ctl(h, &c);
 }
 
 mpmc_status mpmc_synchronize(mpmc_handle h)

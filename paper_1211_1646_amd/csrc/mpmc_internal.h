@@ -22,8 +22,16 @@ struct alignas(256) Ctl {
     unsigned int key0, key1;         // Philox key (seed, replica)
     float delta;                     // maximum trial displacement
     unsigned int errword;            // kErr* bits set by kernels
-    int shift_f;                     // the sweep's shift, recorded by the scan
-    float shift_d;                   //   kernel before it advances the sweep
+    unsigned int pad0[2];
+    // Sweep-global draws of sweep s in draw[s & 1]: set order (byte q = set
+    // of slot q), shift direction f and distance d.  Written when the sweep
+    // counter or the key changes, read by every launch of the sweep.
+    struct Draw {
+        unsigned int order;
+        int f;
+        float d;
+        unsigned int pad;
+    } draw[2];
     unsigned long long hist_samples; // configurations in hist[]
     double fit[4];                   // P*, g(sigma+), rho, status
     long long overlaps;              // ordered overlapping pairs (count kernel)
@@ -87,9 +95,9 @@ hipError_t launch_msd(const Geom &g, const float2 *acc, const Work &w, Ctl *ctl,
 // apply == 0 only opens a new tuner window (records the counters).
 hipError_t launch_tune(const Geom &g, Ctl *ctl, int apply, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, long long n, hipStream_t st);
-hipError_t launch_ctl_reset(Ctl *ctl, unsigned long long sweep, unsigned int key0,
+hipError_t launch_ctl_reset(const Geom &g, Ctl *ctl, unsigned long long sweep, unsigned int key0,
                             unsigned int key1, float delta, hipStream_t st);
-hipError_t launch_ctl_set_key0(Ctl *ctl, unsigned int key0, hipStream_t st);
+hipError_t launch_ctl_set_key0(const Geom &g, Ctl *ctl, unsigned int key0, hipStream_t st);
 hipError_t launch_ctl_set_delta(Ctl *ctl, float delta, hipStream_t st);
 
 // Work-buffer sizes, from the smallest workgroup allowed.

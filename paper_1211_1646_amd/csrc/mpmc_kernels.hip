@@ -104,6 +104,16 @@ __device__ __forceinline__ Draws sweep_draws(unsigned long long s, uint32_t k0, 
     return D;
 }
 
+// Record the draws of sweep s in the control block (one thread).
+__device__ __forceinline__ void store_draws(Ctl *ctl, unsigned long long s, float wx, float wy)
+{
+    const Draws D = sweep_draws(s, ctl->key0, ctl->key1, wx, wy);
+    Ctl::Draw &r = ctl->draw[s & 1ull];
+    r.order = D.order;
+    r.f = D.f;
+    r.d = D.d;
+}
+
 // Small per-lane register arrays.  Every element access below uses a
 // compile-time index (C++17 fold expressions over an index sequence), so the
 // arrays live in VGPRs from the first optimisation pass on; run-time slots
@@ -228,6 +238,7 @@ __device__ __forceinline__ unsigned block_exclusive_scan_u32(unsigned v, unsigne
 // cell is rejected before any overlap test, and one inside it is at distance
 // >= 1 from every dropped disk.
 constexpr float kReach2 = 1.0001f;
+constexpr float kReachEdge = 1.0001f;
 
 template <int CAP>
 __global__ void __launch_bounds__(256)
@@ -235,8 +246,7 @@ k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
            float2 *__restrict__ acc, uint32_t *__restrict__ tag, const Ctl *__restrict__ ctl,
            uint32_t *__restrict__ cnt, int cnt_stride, int n_moves, int set, int ntile, int per)
 {
-    extern __shared__ float2 nbr[];   // [8 * CAP][blockDim.x]
-    __shared__ unsigned red[2][16];
+    extern __shared__ float2 nbr[];   // [8 * CAP][blockDim.x]; reused for the counts
     const int tile = xcd_tile(per);
     const unsigned long long s = ctl->sweep;
     const uint32_t k0 = ctl->key0, k1 = ctl->key1;
@@ -244,10 +254,7 @@ k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
     const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
 
     int Q = set;
-    if (Q < 0) {
-        const Draws D = sweep_draws(s, k0, k1, g.wx, g.wy);
-        Q = (int)((D.order >> (8 * (-1 - set))) & 0xFFu);
-    }
+    if (Q < 0) Q = (int)((ctl->draw[s & 1ull].order >> (8 * (-1 - set))) & 0xFFu);
     const int qx = Q & 1, qy = Q >> 1;
     const int hx = g.mx >> 1, hy = g.my >> 1;
     const int gid = tile * (int)blockDim.x + (int)threadIdx.x;
@@ -286,33 +293,34 @@ k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
         if (n > 0) {
             const uint32_t b0 = rb[4];
             const bool has_acc = acc != nullptr, has_tag = tag != nullptr;
-            // 2. all positions of the block in flight together
+            // 2. all positions of the block in flight together: unconditional
+            // loads at indices clamped into [0, N), selected afterwards
+            const uint32_t last = (uint32_t)(g.N - 1);
             float2 nv[9][CAP];
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+#pragma unroll
+                for (int i = 0; i < CAP; ++i) nv[q][i] = pos[min(rb[q] + (uint32_t)i, last)];
             float px[CAP], py[CAP], ax[CAP], ay[CAP];
             uint32_t tg[CAP];
 #pragma unroll
             for (int q = 0; q < CAP; ++q) {
-                px[q] = py[q] = ax[q] = ay[q] = 0.0f;
+                px[q] = nv[4][q].x;
+                py[q] = nv[4][q].y;
+                ax[q] = ay[q] = 0.0f;
                 tg[q] = 0u;
-                if (q < n) {
-                    const float2 v = pos[b0 + q];
-                    px[q] = v.x;
-                    py[q] = v.y;
-                    if (has_acc) {
-                        const float2 a = acc[b0 + q];
-                        ax[q] = a.x;
-                        ay[q] = a.y;
-                    }
-                    if (has_tag) tg[q] = tag[b0 + q];
+            }
+            if (has_acc) {
+#pragma unroll
+                for (int q = 0; q < CAP; ++q) {
+                    const float2 a = acc[min(b0 + (uint32_t)q, last)];
+                    ax[q] = a.x;
+                    ay[q] = a.y;
                 }
             }
+            if (has_tag) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) {
-#pragma unroll
-                for (int i = 0; i < CAP; ++i) {
-                    nv[q][i] = make_float2(0.0f, 0.0f);
-                    if (q != 4 && i < (int)rn[q]) nv[q][i] = pos[rb[q] + i];
-                }
+                for (int q = 0; q < CAP; ++q) tg[q] = tag[min(b0 + (uint32_t)q, last)];
             }
             // Philox blocks of this cell: one shuffle block (n <= 5) and the
             // first trial block, issued while the loads are outstanding.
@@ -320,25 +328,33 @@ k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
             if (n > 1) Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle, k0, k1);
             uint4 W = make_uint4(0, 0, 0, 0);
             if (n_moves > 0) W = philox((uint32_t)c, s_lo, s_hi, 0u, k0, k1);
-            // 3. translate, keep the reachable ones, compact into LDS
+            // 3. translate into the cell's frame (x - w, x or x + w: adding
+            // the exact translation 0 is skipped, x + 0 == x for x > 0), keep
+            // the disks that can reach the cell, compact them into LDS.  The
+            // reach test per neighbour: one comparison for the four edge
+            // cells, the distance to the shared corner for the four corners.
             int K = 0;
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
                 if (q == 4) continue;
-                const float tx = q % 3 == 0 ? -g.wx : (q % 3 == 2 ? g.wx : 0.0f);
-                const float ty = q / 3 == 0 ? -g.wy : (q / 3 == 2 ? g.wy : 0.0f);
+                const int ra = q / 3, cb = q % 3;
 #pragma unroll
                 for (int i = 0; i < CAP; ++i) {
-                    if (i < (int)rn[q]) {
-                        const float ox = nv[q][i].x + tx;
-                        const float oy = nv[q][i].y + ty;
-                        const float ex = ox < 0.0f ? -ox : (ox > g.wx ? ox - g.wx : 0.0f);
-                        const float ey = oy < 0.0f ? -oy : (oy > g.wy ? oy - g.wy : 0.0f);
-                        if (ex * ex + ey * ey < kReach2) {
-                            nbr[K * L + lane] = make_float2(ox, oy);
-                            ++K;
-                        }
+                    float ox = nv[q][i].x, oy = nv[q][i].y;
+                    if (cb == 0) ox = ox - g.wx;
+                    if (cb == 2) ox = ox + g.wx;
+                    if (ra == 0) oy = oy - g.wy;
+                    if (ra == 2) oy = oy + g.wy;
+                    bool reach;
+                    if (ra == 1) reach = cb == 0 ? ox > -kReachEdge : ox < g.wx + kReachEdge;
+                    else if (cb == 1) reach = ra == 0 ? oy > -kReachEdge : oy < g.wy + kReachEdge;
+                    else {
+                        const float ex = cb == 0 ? -ox : ox - g.wx;
+                        const float ey = ra == 0 ? -oy : oy - g.wy;
+                        reach = ex * ex + ey * ey < kReach2;
                     }
+                    nbr[K * L + lane] = make_float2(ox, oy);   // row K <= slots seen so far
+                    K += (i < (int)rn[q] && reach) ? 1 : 0;
                 }
             }
             // rng.shuffle(c.particles): Fisher-Yates over the stored list,
@@ -426,8 +442,10 @@ k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
     // rebin's scan); a lone sub-sweep adds into the lone slot, whose entries
     // each belong to one workgroup, and which is folded before the next read
     // of the counters -- no contended atomics either way.
-    const unsigned bt = block_sum_u32(n_trials, red[0]);
-    const unsigned ba = block_sum_u32(n_acc, red[1]);
+    __syncthreads();   // every lane is done with its neighbour table
+    unsigned *red = reinterpret_cast<unsigned *>(nbr);
+    const unsigned bt = block_sum_u32(n_trials, red);
+    const unsigned ba = block_sum_u32(n_acc, red + 16);
     if (threadIdx.x == 0 && tile < ntile) {
         if (set < 0) {
             const int slot = -1 - set;
@@ -507,6 +525,7 @@ struct RebinArgs {
     Ctl *ctl;
     int f;
     float d;
+    int advance;
     int ntile;
     int per;
 };
@@ -524,15 +543,10 @@ __global__ void __launch_bounds__(1024) k_rebin(RebinArgs a)
     const int tile = xcd_tile(a.per);
     int f = a.f;
     float d = a.d;
-    if (f < 0) {
-        if (!SCATTER) {   // the sweep's own draws; the scan records them
-            const Draws D = sweep_draws(a.ctl->sweep, a.ctl->key0, a.ctl->key1, g.wx, g.wy);
-            f = D.f;
-            d = D.d;
-        } else {          // the sweep counter has advanced: use the record
-            f = a.ctl->shift_f;
-            d = a.ctl->shift_d;
-        }
+    if (f < 0) {   // the sweep's own draws (after the scan advanced the counter, the previous)
+        const unsigned long long s = a.ctl->sweep - ((SCATTER && a.advance) ? 1ull : 0ull);
+        f = a.ctl->draw[s & 1ull].f;
+        d = a.ctl->draw[s & 1ull].d;
     }
     const bool along_x = f < 2;
     const bool minus = (f == 0 || f == 2);   // +x / +y: t = v - d
@@ -603,8 +617,9 @@ __global__ void __launch_bounds__(1024) k_rebin(RebinArgs a)
 
 // Exclusive scan of the per-tile totals in place (one workgroup).  It also
 // folds the sweep's sub-sweep counters and, when the shift is the sweep's own,
-// records (f, d) for the scatter and advances the sweep counter: one thread of
-// one workgroup writes them, so no atomics are needed.
+// advances the sweep counter and records the next sweep's draws (the scatter
+// still finds this sweep's in the other half of the record): one thread of one
+// workgroup writes them, so no atomics are needed.
 __global__ void __launch_bounds__(1024)
 k_scan_tiles(uint32_t *part, int ntile, Ctl *ctl, long long N, uint32_t *cnt, int stride,
              int nslots, int sub_tiles, int advance, float wx, float wy)
@@ -627,11 +642,9 @@ k_scan_tiles(uint32_t *part, int ntile, Ctl *ctl, long long N, uint32_t *cnt, in
     if (threadIdx.x == 0 && (long long)total != N) atomicOr(&ctl->errword, kErrCount);
     if (nslots > 0) fold_counters(cnt, stride, nslots, sub_tiles, 0, ctl, sh);
     if (advance && threadIdx.x == 0) {
-        const unsigned long long s = ctl->sweep;
-        const Draws D = sweep_draws(s, ctl->key0, ctl->key1, wx, wy);
-        ctl->shift_f = D.f;
-        ctl->shift_d = D.d;
-        ctl->sweep = s + 1ull;
+        const unsigned long long s = ctl->sweep + 1ull;
+        store_draws(ctl, s, wx, wy);
+        ctl->sweep = s;
     }
 }
 
@@ -878,7 +891,7 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t value, long long n)
 }
 
 __global__ void k_ctl_reset(Ctl *ctl, unsigned long long sweep, unsigned int key0,
-                            unsigned int key1, float delta)
+                            unsigned int key1, float delta, float wx, float wy)
 {
     if (threadIdx.x == 0) {
         ctl->sweep = sweep;
@@ -888,8 +901,7 @@ __global__ void k_ctl_reset(Ctl *ctl, unsigned long long sweep, unsigned int key
         ctl->key1 = key1;
         ctl->delta = delta;
         ctl->errword = 0u;
-        ctl->shift_f = 0;
-        ctl->shift_d = 0.0f;
+        store_draws(ctl, sweep, wx, wy);
         ctl->hist_samples = 0ull;
         ctl->overlaps = 0;
         ctl->msd = 0.0;
@@ -898,7 +910,11 @@ __global__ void k_ctl_reset(Ctl *ctl, unsigned long long sweep, unsigned int key
     for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) ctl->hist[i] = 0ull;
 }
 
-__global__ void k_ctl_set_key0(Ctl *ctl, unsigned int key0) { ctl->key0 = key0; }
+__global__ void k_ctl_set_key0(Ctl *ctl, unsigned int key0, float wx, float wy)
+{
+    ctl->key0 = key0;
+    store_draws(ctl, ctl->sweep, wx, wy);
+}
 __global__ void k_ctl_set_delta(Ctl *ctl, float delta) { ctl->delta = delta; }
 
 inline int tiles_for(long long items, int block) { return (int)((items + block - 1) / block); }
@@ -959,6 +975,7 @@ hipError_t launch_rebin(const Geom &g, const float2 *pos, const uint32_t *start,
     a.part = w.scan;
     a.ctl = ctl;
     a.f = f; a.d = d;
+    a.advance = (f < 0 && advance) ? 1 : 0;
     a.ntile = tiles_for(g.C, block);
     a.per = per_xcd(a.ntile);
     const dim3 grid(8 * a.per), blk(block);
@@ -1025,16 +1042,17 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, long long n, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_ctl_reset(Ctl *ctl, unsigned long long sweep, unsigned int key0,
+hipError_t launch_ctl_reset(const Geom &g, Ctl *ctl, unsigned long long sweep, unsigned int key0,
                             unsigned int key1, float delta, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(256), 0, st, ctl, sweep, key0, key1, delta);
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(256), 0, st, ctl, sweep, key0, key1, delta, g.wx,
+                       g.wy);
     return hipGetLastError();
 }
 
-hipError_t launch_ctl_set_key0(Ctl *ctl, unsigned int key0, hipStream_t st)
+hipError_t launch_ctl_set_key0(const Geom &g, Ctl *ctl, unsigned int key0, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ctl_set_key0, dim3(1), dim3(1), 0, st, ctl, key0);
+    hipLaunchKernelGGL(k_ctl_set_key0, dim3(1), dim3(1), 0, st, ctl, key0, g.wx, g.wy);
     return hipGetLastError();
 }
 

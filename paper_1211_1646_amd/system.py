@@ -92,6 +92,7 @@ class HardDiskSystem:
         L.check(self.lib.mpmc_init_system(C.byref(cfg.to_c()), C.byref(b),
                                           C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self._h = h
+        self.block = 256
 
     # ----------------------------------------------------------- lifecycle
     def close(self):
@@ -122,6 +123,15 @@ class HardDiskSystem:
 
     def set_launch(self, lanes_per_cell: int = 1, block_size: int = 256):
         L.check(self.lib.mpmc_set_launch(self._h, int(lanes_per_cell), int(block_size)))
+        self.block = int(block_size)
+
+    def autotune(self, sweeps: int = 32):
+        """Pick the fastest sub-sweep workgroup size (results are identical
+        for every shape); returns (block, microseconds per sweep)."""
+        b, us = C.c_int32(), C.c_double()
+        L.check(self.lib.mpmc_autotune(self._h, int(sweeps), C.byref(b), C.byref(us)))
+        self.block = int(b.value)
+        return self.block, us.value
 
     def synchronize(self):
         L.check(self.lib.mpmc_synchronize(self._h))

@@ -171,6 +171,17 @@ def test_launch_shape_does_not_change_results(gpu, block):
     assert_same(G, O, "block %d" % block)
 
 
+def test_autotune_leaves_the_chain_alone(gpu):
+    G, O = lattice_pair(gpu, 64, 64, 0.70, math.sqrt(2.0), delta=0.12, seed=6)
+    block, us = G.autotune(16)
+    assert block in (64, 128, 192, 256) and us > 0
+    O.sweep(4 * 2 * 16)
+    assert_same(G, O, "autotuned")
+    G.sweep(20)
+    O.sweep(20)
+    assert_same(G, O, "after autotune")
+
+
 def test_seed_change_and_delta_change(gpu):
     G, O = lattice_pair(gpu, 24, 24, 0.65, 0.0, delta=0.1, seed=1)
     G.sweep(5)
