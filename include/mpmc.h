@@ -33,6 +33,15 @@
  *    counter (cell or 0xFFFFFFFF, sweep low word, sweep high word, tag); the
  *    sweep counter lives in device memory, so results depend only on the
  *    state, the sweep index and the key -- not on launch shapes.
+ *  - A handle holds R >= 1 independent systems ("replicas"), each with its
+ *    own N, packing fraction, grid, delta, n_M, key and sweep counter.
+ *    mpmc_init_system builds R = 1; mpmc_batch_init builds R >= 1.  Calls
+ *    that advance the chain (sweep, subsweep, shift_and_rebin, tune,
+ *    pair_histogram, reset_acc, set_delta) act on every replica at once,
+ *    in the same kernel launches; replica r then evolves exactly as a single
+ *    system with the same parameters would.  The per-system getters without
+ *    a replica argument require R = 1 (MPMC_EINVAL otherwise); the
+ *    mpmc_replica_* forms take the replica index.
  */
 #ifndef MPMC_H
 #define MPMC_H
@@ -121,6 +130,15 @@ mpmc_status mpmc_geometry_of(const mpmc_params *p, mpmc_geometry *out);
 /* Buffer sizes for a parameter set.  Host only, no GPU use. */
 mpmc_status mpmc_required_bytes(const mpmc_params *p, mpmc_buffer_sizes *out);
 
+/* Buffer sizes for n_replicas systems, per_replica[0 .. n_replicas).  All
+ * replicas must share `flags`.  In the shared layout each replica's cells
+ * are padded to a multiple of 256 (at least one padding cell) and its active
+ * cells to a multiple of 768.  Host only.  Errors as mpmc_geometry_of, plus MPMC_EINVAL for
+ * n_replicas outside [1, 65535] or differing flags, and MPMC_EGEOM when the
+ * total exceeds 32-bit offsets. */
+mpmc_status mpmc_batch_required_bytes(const mpmc_params *per_replica, int32_t n_replicas,
+                                      mpmc_buffer_sizes *out);
+
 /* init_system: build the system (Sec. 4: N disks at packing fraction phi)
  * and upload it on `stream` (sync).  With lattice_nx > 0 the state is the
  * triangular lattice; otherwise the grid is explicit and empty until
@@ -129,11 +147,27 @@ mpmc_status mpmc_required_bytes(const mpmc_params *p, mpmc_buffer_sizes *out);
 mpmc_status mpmc_init_system(const mpmc_params *p, const mpmc_buffers *b, void *stream,
                              mpmc_handle *out);
 
+/* Batched form: n_replicas independent systems in one handle (sync).  Replica
+ * r is built from per_replica[r] exactly as mpmc_init_system would build it
+ * (lattice replicas start from their lattice; grid replicas stay empty until
+ * mpmc_replica_set_state) and is keyed (seed, replica) from its own params.
+ * Buffers are sized by mpmc_batch_required_bytes. */
+mpmc_status mpmc_batch_init(const mpmc_params *per_replica, int32_t n_replicas,
+                            const mpmc_buffers *b, void *stream, mpmc_handle *out);
+
+/* Number of replicas of a handle. */
+mpmc_status mpmc_num_replicas(mpmc_handle h, int32_t *n);
+
+/* Geometry of replica r (host only). */
+mpmc_status mpmc_replica_geometry(mpmc_handle h, int32_t r, mpmc_geometry *out);
+
 /* sweep(n_sweeps, seed): n_sweeps full sweeps of Alg. 1 (async): the sweep's
  * set order, four sub-sweeps (Alg. 2), shift and rebin (Alg. 4), sweep += 1.
  * `seed` replaces key word 0 for these and later sweeps.  Long runs are
  * launched as captured hipGraphs of a fixed block of sweeps. */
 mpmc_status mpmc_sweep(mpmc_handle h, int64_t n_sweeps, uint32_t seed);
+/* (In a batch, `seed` replaces key word 0 of every replica; key word 1 stays
+ * each replica's own.) */
 
 /* One sub-sweep of checkerboard set `set` (0..3 = a..d of Eq. 1) with the
  * current sweep's cell streams (Alg. 1 lines 4-13, Alg. 2).  async. */
@@ -160,10 +194,19 @@ mpmc_status mpmc_pair_histogram(mpmc_handle h, int32_t reset);
  * Any output pointer may be NULL; hist receives MPMC_HIST_BINS counts. */
 mpmc_status mpmc_pressure_from_contact(mpmc_handle h, double *p_star, double *g_contact,
                                        uint64_t *hist, uint64_t *n_samples);
+/* The same for replica r of a batch, from its own histogram; with R > 1 a
+ * replica without an accumulated histogram gives MPMC_ESTATE. */
+mpmc_status mpmc_replica_pressure_from_contact(mpmc_handle h, int32_t r, double *p_star,
+                                               double *g_contact, uint64_t *hist,
+                                               uint64_t *n_samples);
 
 /* Copy the state to host memory (sync): xy[2N] local coordinates,
  * start[cells+1], sweep counter.  Any pointer may be NULL. */
 mpmc_status mpmc_get_state(mpmc_handle h, float *xy, uint32_t *start, uint64_t *sweep);
+/* Replica r's state in its own numbering: xy[2 N_r], start[C_r + 1] with
+ * start[0] = 0, its sweep counter (sync). */
+mpmc_status mpmc_replica_get_state(mpmc_handle h, int32_t r, float *xy, uint32_t *start,
+                                   uint64_t *sweep);
 
 /* Load a state from host memory (sync).  Validates offsets, per-cell
  * capacity and coordinate ranges on the host (MPMC_ESTATE) and overlaps on
@@ -172,31 +215,45 @@ mpmc_status mpmc_get_state(mpmc_handle h, float *xy, uint32_t *start, uint64_t *
  * sized for. */
 mpmc_status mpmc_set_state(mpmc_handle h, const float *xy, const uint32_t *start,
                            uint64_t sweep, const uint32_t *tags);
+/* Load replica r's state (own numbering, N_r disks) and reset its sweep
+ * counter, counters, delta and key to its initial ones (sync).  The other
+ * replicas are untouched. */
+mpmc_status mpmc_replica_set_state(mpmc_handle h, int32_t r, const float *xy,
+                                   const uint32_t *start, uint64_t sweep, const uint32_t *tags);
 
 /* Copy accumulators acc[2N] and tags[N] to host memory (sync), list order. */
 mpmc_status mpmc_get_aux(mpmc_handle h, float *acc, uint32_t *tags);
+mpmc_status mpmc_replica_get_aux(mpmc_handle h, int32_t r, float *acc, uint32_t *tags);
 
-/* Clear the displacement accumulators (async). */
+/* Clear the displacement accumulators of every replica (async). */
 mpmc_status mpmc_reset_acc(mpmc_handle h);
 
 /* Mean squared displacement mean(|acc|^2) over all disks, FP64, fixed
  * reduction order (sync). */
 mpmc_status mpmc_msd(mpmc_handle h, double *msd);
+mpmc_status mpmc_replica_msd(mpmc_handle h, int32_t r, double *msd);
 
-/* Number of ordered overlapping pairs in the kernels' metric (sync). */
+/* Number of ordered overlapping pairs in the kernels' metric, summed over
+ * the replicas (sync). */
 mpmc_status mpmc_count_overlaps(mpmc_handle h, int64_t *pairs);
 
-/* Trial moves and accepted moves since init or the last set_state (sync). */
+/* Trial moves and accepted moves since init or the last set_state, summed
+ * over the replicas (sync); the replica form gives one replica's. */
 mpmc_status mpmc_get_counters(mpmc_handle h, uint64_t *trials, uint64_t *accepts);
+mpmc_status mpmc_replica_get_counters(mpmc_handle h, int32_t r, uint64_t *trials,
+                                      uint64_t *accepts);
 
-/* Maximum trial displacement delta (async set / sync get). */
+/* Maximum trial displacement delta (async set / sync get).  mpmc_set_delta
+ * sets every replica's; the replica forms one replica's. */
 mpmc_status mpmc_set_delta(mpmc_handle h, float delta);
 mpmc_status mpmc_get_delta(mpmc_handle h, float *delta);
+mpmc_status mpmc_replica_set_delta(mpmc_handle h, int32_t r, float delta);
+mpmc_status mpmc_replica_get_delta(mpmc_handle h, int32_t r, float *delta);
 
 /* Plain acceptance-ratio tuner for equilibration (async): n_windows times,
  * run window_sweeps sweeps, then with a = accepts/trials of that window
  * set delta <- delta * clamp(a/0.3, 0.5, 2), clamped to [1e-3, min(w)/2],
- * on the device. */
+ * on the device, for each replica from its own counts. */
 mpmc_status mpmc_tune(mpmc_handle h, int32_t window_sweeps, int32_t n_windows);
 
 /* Launch shape: lanes cooperating on one cell (1) and workgroup size (64,

@@ -83,6 +83,24 @@ _SIGNATURES = {
     "mpmc_set_launch": (C.c_int32, [_H, C.c_int32, C.c_int32]),
     "mpmc_autotune": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "mpmc_synchronize": (C.c_int32, [_H]),
+    "mpmc_batch_required_bytes": (C.c_int32, [C.POINTER(Params), C.c_int32, C.POINTER(BufferSizes)]),
+    "mpmc_batch_init": (C.c_int32, [C.POINTER(Params), C.c_int32, C.POINTER(Buffers), C.c_void_p,
+                                    C.POINTER(C.c_void_p)]),
+    "mpmc_num_replicas": (C.c_int32, [_H, C.POINTER(C.c_int32)]),
+    "mpmc_replica_geometry": (C.c_int32, [_H, C.c_int32, C.POINTER(Geometry)]),
+    "mpmc_replica_pressure_from_contact": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_double),
+                                                       C.POINTER(C.c_double), C.POINTER(C.c_uint64),
+                                                       C.POINTER(C.c_uint64)]),
+    "mpmc_replica_get_state": (C.c_int32, [_H, C.c_int32, C.c_void_p, C.c_void_p,
+                                           C.POINTER(C.c_uint64)]),
+    "mpmc_replica_set_state": (C.c_int32, [_H, C.c_int32, C.c_void_p, C.c_void_p, C.c_uint64,
+                                           C.c_void_p]),
+    "mpmc_replica_get_aux": (C.c_int32, [_H, C.c_int32, C.c_void_p, C.c_void_p]),
+    "mpmc_replica_msd": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_double)]),
+    "mpmc_replica_get_counters": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_uint64),
+                                              C.POINTER(C.c_uint64)]),
+    "mpmc_replica_set_delta": (C.c_int32, [_H, C.c_int32, C.c_float]),
+    "mpmc_replica_get_delta": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_float)]),
     "mpmc_destroy": (None, [_H]),
     "mpmc_last_error": (C.c_char_p, []),
 }

@@ -1,10 +1,12 @@
 // Host side of libmpmc.so: the C ABI declared in include/mpmc.h.
 //
-// Validates arguments and geometry, builds the initial lattice, owns no device
-// memory (the caller's buffers are used through non-owning pointers), and
-// enqueues the kernels of mpmc_kernels.hip on the caller's stream.  Long runs
-// of sweeps are captured once into hipGraphs of a fixed, even number of
-// sweeps (the ping-pong buffers return to the same half after each graph).
+// Validates arguments and geometry, builds the initial lattices, owns no
+// device memory (the caller's buffers are used through non-owning pointers),
+// and enqueues the kernels of mpmc_kernels.hip on the caller's stream.  A
+// handle holds R >= 1 replicas laid out back to back (a single system is
+// R = 1); every kernel launch covers all of them.  Long runs of sweeps are
+// captured once into hipGraphs of a fixed, even number of sweeps (the
+// ping-pong buffers return to the same half after each graph).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,6 +21,7 @@
 
 using mpmc::Ctl;
 using mpmc::Geom;
+using mpmc::Rep;
 
 namespace {
 
@@ -39,7 +42,7 @@ mpmc_status fail(mpmc_status st, const std::string &msg)
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kGraphSweeps = 16;   // sweeps per captured graph (even)
-constexpr int kRebinBlock = 256;   // workgroup size of the rebin kernels
+constexpr int kMaxReplicas = 65535;
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
@@ -146,33 +149,121 @@ mpmc_status check_params(const mpmc_params *p, const mpmc_geometry &g)
     return MPMC_OK;
 }
 
-size_t work_bytes(long long C)
+long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
+
+// Placement of the replicas: cells padded to whole rebin tiles, active slots
+// to whole active chunks, disks back to back.
+struct Layout {
+    std::vector<mpmc_geometry> geo;
+    std::vector<Rep> reps;
+    long long N = 0, cells = 0, active = 0;
+    int cap = 0;
+};
+
+mpmc_status plan(const mpmc_params *p, int n, Layout *L)
 {
-    return align256((size_t)mpmc::scan_partials(C) * 4) +
-           align256((size_t)mpmc::count_stride(C) * 10 * 4) +
+    if (!p || n < 1) return fail(MPMC_EINVAL, "need at least one replica");
+    if (n > kMaxReplicas) return fail(MPMC_EINVAL, "too many replicas");
+    L->geo.resize((size_t)n);
+    L->reps.resize((size_t)n);
+    L->N = L->cells = L->active = 0;
+    L->cap = 0;
+    for (int r = 0; r < n; ++r) {
+        mpmc_status s = derive_geometry(&p[r], &L->geo[(size_t)r]);
+        if (s) return s;
+        s = check_params(&p[r], L->geo[(size_t)r]);
+        if (s) return s;
+        if (p[r].flags != p[0].flags) return fail(MPMC_EINVAL, "replicas must share flags");
+        const mpmc_geometry &g = L->geo[(size_t)r];
+        Rep &R = L->reps[(size_t)r];
+        std::memset(&R, 0, sizeof R);
+        R.g.mx = g.cells_x;
+        R.g.my = g.cells_y;
+        R.g.C = g.cells_x * g.cells_y;
+        R.g.cap = g.capacity;
+        R.g.wx = g.w_x;
+        R.g.wy = g.w_y;
+        R.g.N = g.n_particles;
+        R.cb = L->cells;
+        // at least one padding cell: the end offset of the last real cell is
+        // then always the replica's own entry (see the placeholder below)
+        R.cpad = round_up((long long)R.g.C + 1, mpmc::kRebinTile);
+        R.pb = L->N;
+        R.ab = L->active;
+        R.apad = round_up((long long)(g.cells_x / 2) * (g.cells_y / 2), mpmc::kActiveChunk);
+        R.n_moves = p[r].n_moves;
+        R.key0 = p[r].seed;
+        R.key1 = p[r].replica;
+        R.delta0 = p[r].delta;
+        L->cells += R.cpad;
+        L->N += R.g.N;
+        L->active += R.apad;
+        L->cap = std::max(L->cap, R.g.cap);
+    }
+    if (L->N > 0xFFFFFF00LL) return fail(MPMC_EGEOM, "too many disks (32-bit offsets)");
+    if (L->cells > 0x7FFFFF00LL) return fail(MPMC_EGEOM, "too many cells");
+    return MPMC_OK;
+}
+
+size_t work_bytes(const Layout &L)
+{
+    return align256((size_t)mpmc::scan_entries(L.cells) * 4) +
+           align256((size_t)mpmc::count_stride(L.active) * 2 * 8) +
            (size_t)mpmc::kMsdBlocksMax * sizeof(double) + 256;
+}
+
+// Control buffer: Ctl[R], Rep[R], replica of each active chunk, replica of
+// each rebin tile.
+struct CtlLayout {
+    size_t reps, arep, crep, total;
+};
+
+CtlLayout ctl_layout(const Layout &L)
+{
+    const size_t R = L.reps.size();
+    CtlLayout c;
+    c.reps = align256(R * sizeof(Ctl));
+    c.arep = c.reps + align256(R * sizeof(Rep));
+    c.crep = c.arep + align256((size_t)(L.active / mpmc::kActiveChunk) * 2);
+    c.total = c.crep + align256((size_t)(L.cells / mpmc::kRebinTile) * 2);
+    return c;
+}
+
+mpmc_status sizes_of(const mpmc_params *p, int n, mpmc_buffer_sizes *out)
+{
+    if (!out) return fail(MPMC_EINVAL, "null argument");
+    Layout L;
+    const mpmc_status s = plan(p, n, &L);
+    if (s) return s;
+    out->pos = align256(std::max<size_t>(8 * (size_t)L.N, 8));
+    out->start = align256(4 * (size_t)(L.cells + 1));
+    out->acc = (p[0].flags & MPMC_FLAG_ACC) ? align256(std::max<size_t>(8 * (size_t)L.N, 8)) : 0;
+    out->tag = (p[0].flags & MPMC_FLAG_TAG) ? align256(std::max<size_t>(4 * (size_t)L.N, 4)) : 0;
+    out->work = work_bytes(L);
+    out->ctl = ctl_layout(L).total;
+    return MPMC_OK;
 }
 
 }  // namespace
 
 struct mpmc_system {
-    mpmc_params p;
-    mpmc_geometry geo;
-    Geom g;
+    std::vector<mpmc_params> p;
+    Layout L;
+    mpmc::Tables t;
     hipStream_t st;
     float2 *pos[2];
     uint32_t *start[2];
     float2 *acc[2];
     uint32_t *tag[2];
     mpmc::Work work;
-    Ctl *ctl;
     int cur;
-    int lanes;
     int block;
-    uint32_t key0;
-    bool ready;        // a valid, overlap-free state is on the device
-    bool lone_pending; // lone sub-sweep counts not yet folded into ctl
+    std::vector<uint32_t> key0;   // current key word 0 of each replica
+    std::vector<char> loaded;     // replica holds a valid, overlap-free state
+    bool ready;                   // every replica is loaded
     hipGraphExec_t graph[2];
+    std::vector<Ctl> ctl_host;
+    int R() const { return (int)p.size(); }
 };
 
 namespace {
@@ -186,40 +277,39 @@ void drop_graphs(mpmc_system *h)
         }
 }
 
-mpmc_status read_ctl(mpmc_system *h, Ctl *out)
+// Fold the counter partials, copy every control block to the host, wait,
+// and report a device error word.
+mpmc_status read_ctl(mpmc_system *h)
 {
-    if (h->lone_pending) {
-        MPMC_HIP(mpmc::launch_fold_lone(h->work, h->ctl, h->st));
-        h->lone_pending = false;
-    }
-    MPMC_HIP(hipMemcpyAsync(out, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->st));
+    MPMC_HIP(mpmc::launch_fold_counters(h->t, h->work, h->st));
+    MPMC_HIP(hipMemcpyAsync(h->ctl_host.data(), h->t.ctls, sizeof(Ctl) * (size_t)h->R(),
+                            hipMemcpyDeviceToHost, h->st));
     MPMC_HIP(hipStreamSynchronize(h->st));
-    if (out->errword) {
-        char buf[128];
-        std::snprintf(buf, sizeof buf, "device invariant violated (error word 0x%x)%s", out->errword,
-                      (out->errword & mpmc::kErrCapacity) ? ": cell above capacity" : "");
-        return fail(MPMC_EDEVICE, buf);
+    for (int r = 0; r < h->R(); ++r) {
+        const unsigned e = h->ctl_host[(size_t)r].errword;
+        if (e) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "device invariant violated in replica %d (error word 0x%x)%s",
+                          r, e, (e & mpmc::kErrCapacity) ? ": cell above capacity" : "");
+            return fail(MPMC_EDEVICE, buf);
+        }
     }
     return MPMC_OK;
 }
 
 mpmc_status enqueue_subsweep(mpmc_system *h, int set)
 {
-    if (set >= 0) h->lone_pending = true;
-    MPMC_HIP(mpmc::launch_subsweep(h->g, h->pos[h->cur], h->start[h->cur], h->acc[h->cur],
-                                   h->tag[h->cur], h->ctl, h->work, h->p.n_moves, set, h->lanes,
-                                   h->block, h->st));
+    MPMC_HIP(mpmc::launch_subsweep(h->t, h->pos[h->cur], h->start[h->cur], h->acc[h->cur],
+                                   h->tag[h->cur], h->work, set, h->block, h->st));
     return MPMC_OK;
 }
 
-// fold_block > 0: the four sub-sweeps of this sweep ran with that workgroup
-// size and their counters are folded by the rebin's scan.
-mpmc_status enqueue_rebin(mpmc_system *h, int f, float d, int advance, int fold_block)
+mpmc_status enqueue_rebin(mpmc_system *h, int f, float d, int advance)
 {
     const int o = h->cur ^ 1;
-    MPMC_HIP(mpmc::launch_rebin(h->g, h->pos[h->cur], h->start[h->cur], h->acc[h->cur],
+    MPMC_HIP(mpmc::launch_rebin(h->t, h->pos[h->cur], h->start[h->cur], h->acc[h->cur],
                                 h->tag[h->cur], h->pos[o], h->start[o], h->acc[o], h->tag[o],
-                                h->work, h->ctl, f, d, advance, kRebinBlock, fold_block, h->st));
+                                h->work, f, d, advance, h->st));
     h->cur = o;
     return MPMC_OK;
 }
@@ -230,7 +320,7 @@ mpmc_status enqueue_sweep(mpmc_system *h)
         const mpmc_status s = enqueue_subsweep(h, -1 - slot);
         if (s) return s;
     }
-    return enqueue_rebin(h, -1, 0.0f, 1, h->block);
+    return enqueue_rebin(h, -1, 0.0f, 1);
 }
 
 mpmc_status run_sweeps(mpmc_system *h, int64_t n)
@@ -266,54 +356,242 @@ mpmc_status run_sweeps(mpmc_system *h, int64_t n)
     return MPMC_OK;
 }
 
-mpmc_status validate_host_state(const mpmc_system *h, const float *xy, const uint32_t *start)
+// A replica's state in its own numbering: start[0] = 0, start[C] = N_r.
+mpmc_status validate_host_state(const Rep &R, const float *xy, const uint32_t *start)
 {
-    const int C = h->g.C;
+    const int C = R.g.C;
     if (start[0] != 0) return fail(MPMC_ESTATE, "start[0] != 0");
     for (int c = 0; c < C; ++c) {
         if (start[c + 1] < start[c]) return fail(MPMC_ESTATE, "offsets decrease");
-        if (start[c + 1] - start[c] > (uint32_t)h->g.cap) return fail(MPMC_ESTATE, "cell above capacity");
+        if (start[c + 1] - start[c] > (uint32_t)R.g.cap) return fail(MPMC_ESTATE, "cell above capacity");
     }
-    if ((long long)start[C] != h->g.N) return fail(MPMC_ESTATE, "particle count differs from the buffers' N");
-    for (long long k = 0; k < h->g.N; ++k) {
+    if ((long long)start[C] != R.g.N) return fail(MPMC_ESTATE, "particle count differs from the buffers' N");
+    for (long long k = 0; k < R.g.N; ++k) {
         const float x = xy[2 * k], y = xy[2 * k + 1];
-        if (!(x > 0.0f && x <= h->g.wx && y > 0.0f && y <= h->g.wy))
+        if (!(x > 0.0f && x <= R.g.wx && y > 0.0f && y <= R.g.wy))
             return fail(MPMC_ESTATE, "local coordinate outside (0, w]");
     }
     return MPMC_OK;
 }
 
-mpmc_status upload_state(mpmc_system *h, const float *xy, const uint32_t *start, uint64_t sweep,
-                         const uint32_t *tags)
+// Offsets of replica r in global numbering, padded cells included:
+// out[0 .. cpad) (the entry after them belongs to the next replica).  Entries
+// past C hold N_r, so the padding cells take up whatever start[C] leaves.
+void global_offsets(const Rep &R, const uint32_t *start, uint32_t *out)
 {
-    const long long N = h->g.N;
-    const int C = h->g.C;
-    drop_graphs(h);
-    h->cur = 0;
+    for (long long c = 0; c < R.cpad; ++c) {
+        const uint32_t v = c <= R.g.C ? start[c] : (uint32_t)R.g.N;
+        out[c] = (uint32_t)R.pb + v;
+    }
+}
+
+// Initial condition of a lattice replica (Sec. 4): site (i, j) at
+// x = (i + 1/4 + (j odd)/2) a, y = (j + 1/2) h in FP64; cell ceil(x/w) - 1;
+// local (float)(x - c w); cells list their disks in ascending lattice index.
+mpmc_status build_lattice(const mpmc_params &p, const Rep &R, std::vector<float> &xy,
+                          std::vector<uint32_t> &start, std::vector<uint32_t> &tags)
+{
+    const int nx = p.lattice_nx, ny = p.lattice_ny;
+    const long long N = R.g.N;
+    const int C = R.g.C;
+    const Lattice Lt = lattice_of(nx, ny, p.phi);
+    start.assign((size_t)C + 1, 0);
+    xy.assign(2 * (size_t)N, 0.0f);
+    tags.assign((size_t)N, 0);
+    std::vector<int> cell_of((size_t)N);
+    std::vector<float> lx((size_t)N), ly((size_t)N);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const size_t k = (size_t)j * nx + i;
+            const double x = ((double)i + 0.25 + 0.5 * (double)(j & 1)) * Lt.a;
+            const double y = ((double)j + 0.5) * Lt.h;
+            const int cx = (int)std::ceil(x / (double)R.g.wx) - 1;
+            const int cy = (int)std::ceil(y / (double)R.g.wy) - 1;
+            if (cx < 0 || cx >= R.g.mx || cy < 0 || cy >= R.g.my)
+                return fail(MPMC_EGEOM, "lattice site outside the cell grid");
+            lx[k] = (float)(x - (double)cx * (double)R.g.wx);
+            ly[k] = (float)(y - (double)cy * (double)R.g.wy);
+            cell_of[k] = cy * R.g.mx + cx;
+            start[(size_t)cell_of[k] + 1] += 1;
+        }
+    for (int c = 0; c < C; ++c) start[(size_t)c + 1] += start[(size_t)c];
+    std::vector<uint32_t> fill(start.begin(), start.end() - 1);
+    for (long long k = 0; k < N; ++k) {
+        const uint32_t o = fill[(size_t)cell_of[(size_t)k]]++;
+        xy[2 * (size_t)o] = lx[(size_t)k];
+        xy[2 * (size_t)o + 1] = ly[(size_t)k];
+        tags[o] = (uint32_t)k;
+    }
+    return validate_host_state(R, xy.data(), start.data());
+}
+
+// Overlap check of the loaded replicas in the kernels' metric; marks them
+// loaded when clean.
+mpmc_status check_loaded(mpmc_system *h, const std::vector<int> &which)
+{
+    MPMC_HIP(mpmc::launch_count_overlaps(h->t, h->pos[h->cur], h->start[h->cur], h->st));
+    mpmc_status s = read_ctl(h);
+    if (s) return s;
+    for (int r : which)
+        if (h->ctl_host[(size_t)r].overlaps != 0) {
+            char buf[96];
+            std::snprintf(buf, sizeof buf, "state of replica %d contains overlapping disks", r);
+            return fail(MPMC_EOVERLAP, buf);
+        }
+    for (int r : which) h->loaded[(size_t)r] = 1;
+    h->ready = std::all_of(h->loaded.begin(), h->loaded.end(), [](char c) { return c != 0; });
+    return MPMC_OK;
+}
+
+// Load replica r's state into the current half.  The padded tail of its
+// offsets and the next replica's first offset are unchanged because N_r is.
+mpmc_status upload_replica(mpmc_system *h, int r, const float *xy, const uint32_t *start,
+                           uint64_t sweep, const uint32_t *tags)
+{
+    const Rep &R = h->L.reps[(size_t)r];
+    const long long N = R.g.N;
+    h->loaded[(size_t)r] = 0;
     h->ready = false;
-    MPMC_HIP(hipMemcpyAsync(h->pos[0], xy, sizeof(float2) * (size_t)N, hipMemcpyHostToDevice, h->st));
-    MPMC_HIP(hipMemcpyAsync(h->start[0], start, sizeof(uint32_t) * (size_t)(C + 1), hipMemcpyHostToDevice, h->st));
+    std::vector<uint32_t> off((size_t)R.cpad);
+    global_offsets(R, start, off.data());
+    const int c = h->cur;
+    if (N > 0)
+        MPMC_HIP(hipMemcpyAsync(h->pos[c] + R.pb, xy, sizeof(float2) * (size_t)N, hipMemcpyHostToDevice, h->st));
+    MPMC_HIP(hipMemcpyAsync(h->start[c] + R.cb, off.data(), sizeof(uint32_t) * (size_t)R.cpad,
+                            hipMemcpyHostToDevice, h->st));
     std::vector<uint32_t> idx;
-    if (h->tag[0]) {
+    if (h->tag[c] && N > 0) {
         if (!tags) {
             idx.resize((size_t)N);
             for (long long k = 0; k < N; ++k) idx[(size_t)k] = (uint32_t)k;
             tags = idx.data();
         }
-        MPMC_HIP(hipMemcpyAsync(h->tag[0], tags, sizeof(uint32_t) * (size_t)N, hipMemcpyHostToDevice, h->st));
+        MPMC_HIP(hipMemcpyAsync(h->tag[c] + R.pb, tags, sizeof(uint32_t) * (size_t)N, hipMemcpyHostToDevice, h->st));
     }
-    if (h->acc[0]) MPMC_HIP(mpmc::launch_fill_u32((uint32_t *)h->acc[0], 0u, 2 * N, h->st));
-    MPMC_HIP(mpmc::launch_ctl_reset(h->g, h->ctl, sweep, h->key0, h->p.replica, h->p.delta, h->st));
-    MPMC_HIP(mpmc::launch_fill_u32(h->work.cnt, 0u, 10LL * h->work.cnt_stride, h->st));
-    h->lone_pending = false;
-    MPMC_HIP(hipStreamSynchronize(h->st));
-    // overlap check in the kernels' metric
-    MPMC_HIP(mpmc::launch_count_overlaps(h->g, h->pos[0], h->start[0], h->ctl, h->block, h->st));
-    Ctl c;
-    const mpmc_status s = read_ctl(h, &c);
+    if (h->acc[c]) MPMC_HIP(mpmc::launch_fill_u32((uint32_t *)(h->acc[c] + R.pb), 0u, 2 * N, h->st));
+    // counters of the other replicas are kept: fold them before the reset
+    MPMC_HIP(mpmc::launch_fold_counters(h->t, h->work, h->st));
+    MPMC_HIP(mpmc::launch_ctl_reset(h->t, r, sweep, h->st));
+    h->key0[(size_t)r] = R.key0;
+    MPMC_HIP(hipStreamSynchronize(h->st));   // host arrays go out of scope
+    return check_loaded(h, {r});
+}
+
+// Build a handle: copy the tables to the device, lay out the initial states
+// (lattices where given, empty placeholders for the rest) and check them.
+mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *stream,
+                   mpmc_handle *out)
+{
+    if (!b || !out) return fail(MPMC_EINVAL, "null argument");
+    *out = nullptr;
+    Layout L;
+    mpmc_status s = plan(p, n, &L);
     if (s) return s;
-    if (c.overlaps != 0) return fail(MPMC_EOVERLAP, "state contains overlapping disks");
-    h->ready = true;
+    const uint32_t flags = p[0].flags;
+    for (int i = 0; i < 2; ++i) {
+        if (!b->pos[i] || !b->start[i]) return fail(MPMC_EINVAL, "pos/start buffers missing");
+        if ((flags & MPMC_FLAG_ACC) && !b->acc[i]) return fail(MPMC_EINVAL, "acc buffers missing");
+        if ((flags & MPMC_FLAG_TAG) && !b->tag[i]) return fail(MPMC_EINVAL, "tag buffers missing");
+    }
+    if (!b->work || !b->ctl) return fail(MPMC_EINVAL, "work/ctl buffers missing");
+    // host-side states first, so that geometry errors allocate nothing
+    std::vector<uint32_t> start_g((size_t)L.cells + 1);
+    std::vector<float> xy_g(2 * (size_t)std::max(L.N, 1LL), 0.0f);
+    std::vector<uint32_t> tag_g((size_t)std::max(L.N, 1LL), 0);
+    std::vector<int> lattice;
+    for (int r = 0; r < n; ++r) {
+        const Rep &R = L.reps[(size_t)r];
+        std::vector<float> xy;
+        std::vector<uint32_t> st, tg;
+        if (p[r].lattice_nx > 0) {
+            s = build_lattice(p[r], R, xy, st, tg);
+            if (s) return s;
+            std::copy(xy.begin(), xy.end(), xy_g.begin() + 2 * R.pb);
+            std::copy(tg.begin(), tg.end(), tag_g.begin() + R.pb);
+            lattice.push_back(r);
+        } else {
+            // placeholder until set_state: every real cell empty; the
+            // replica's disks (zeros) sit in its first padding cell, which no
+            // kernel reads, so every offset stays inside the position buffer
+            st.assign((size_t)R.g.C + 1, 0);
+            if (R.g.N == 0) lattice.push_back(r);   // empty grid: already valid
+        }
+        global_offsets(R, st.data(), start_g.data() + R.cb);
+    }
+    start_g[(size_t)L.cells] = (uint32_t)L.N;
+
+    mpmc_system *h = new mpmc_system();
+    h->p.assign(p, p + n);
+    h->L = L;
+    h->st = (hipStream_t)stream;
+    for (int i = 0; i < 2; ++i) {
+        h->pos[i] = (float2 *)b->pos[i];
+        h->start[i] = (uint32_t *)b->start[i];
+        h->acc[i] = (flags & MPMC_FLAG_ACC) ? (float2 *)b->acc[i] : nullptr;
+        h->tag[i] = (flags & MPMC_FLAG_TAG) ? (uint32_t *)b->tag[i] : nullptr;
+    }
+    {
+        char *w = (char *)b->work;
+        h->work.scan = (uint32_t *)w;
+        w += align256((size_t)mpmc::scan_entries(L.cells) * 4);
+        h->work.cnt = (unsigned long long *)w;
+        h->work.cnt_stride = (int)mpmc::count_stride(L.active);
+        w += align256((size_t)mpmc::count_stride(L.active) * 2 * 8);
+        h->work.f64 = (double *)w;
+    }
+    const CtlLayout cl = ctl_layout(L);
+    char *cb = (char *)b->ctl;
+    h->t.ctls = (Ctl *)cb;
+    h->t.reps = (const Rep *)(cb + cl.reps);
+    h->t.arep = (const uint16_t *)(cb + cl.arep);
+    h->t.crep = (const uint16_t *)(cb + cl.crep);
+    h->t.R = n;
+    h->t.cap = L.cap;
+    h->t.cells = L.cells;
+    h->t.active = L.active;
+    h->t.N = L.N;
+    h->cur = 0;
+    h->block = 256;
+    h->key0.resize((size_t)n);
+    for (int r = 0; r < n; ++r) h->key0[(size_t)r] = p[r].seed;
+    h->loaded.assign((size_t)n, 0);
+    h->ready = false;
+    h->graph[0] = h->graph[1] = nullptr;
+    h->ctl_host.resize((size_t)n);
+
+    std::vector<uint16_t> arep((size_t)(L.active / mpmc::kActiveChunk));
+    std::vector<uint16_t> crep((size_t)(L.cells / mpmc::kRebinTile));
+    for (int r = 0; r < n; ++r) {
+        const Rep &R = L.reps[(size_t)r];
+        for (long long i = R.ab / mpmc::kActiveChunk; i < (R.ab + R.apad) / mpmc::kActiveChunk; ++i)
+            arep[(size_t)i] = (uint16_t)r;
+        for (long long i = R.cb / mpmc::kRebinTile; i < (R.cb + R.cpad) / mpmc::kRebinTile; ++i)
+            crep[(size_t)i] = (uint16_t)r;
+    }
+    auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->st) : hipSuccess;
+    };
+    hipError_t e = up(cb + cl.reps, L.reps.data(), sizeof(Rep) * (size_t)n);
+    if (e == hipSuccess) e = up(cb + cl.arep, arep.data(), arep.size() * 2);
+    if (e == hipSuccess) e = up(cb + cl.crep, crep.data(), crep.size() * 2);
+    if (e == hipSuccess) e = up(h->pos[0], xy_g.data(), sizeof(float2) * (size_t)L.N);
+    if (e == hipSuccess) e = up(h->start[0], start_g.data(), sizeof(uint32_t) * start_g.size());
+    if (e == hipSuccess && h->tag[0]) e = up(h->tag[0], tag_g.data(), sizeof(uint32_t) * (size_t)L.N);
+    if (e == hipSuccess && h->acc[0]) e = mpmc::launch_fill_u32((uint32_t *)h->acc[0], 0u, 2 * L.N, h->st);
+    if (e == hipSuccess)
+        e = mpmc::launch_fill_u32((uint32_t *)h->work.cnt, 0u, 4LL * h->work.cnt_stride, h->st);
+    if (e == hipSuccess) e = mpmc::launch_ctl_reset(h->t, -1, 0, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(MPMC_EHIP, std::string("init upload: ") + hipGetErrorString(e));
+    }
+    s = check_loaded(h, lattice);
+    if (s) {
+        delete h;
+        return s;
+    }
+    *out = h;
     return MPMC_OK;
 }
 
@@ -322,6 +600,33 @@ mpmc_status upload_state(mpmc_system *h, const float *xy, const uint32_t *start,
         if (!(h)) return fail(MPMC_EINVAL, "null handle");                                   \
         if (!(h)->ready) return fail(MPMC_ESTATE, "no valid state loaded (mpmc_set_state)"); \
     } while (0)
+
+#define MPMC_NEED_REPLICA(h, r)                                                              \
+    do {                                                                                     \
+        if (!(h)) return fail(MPMC_EINVAL, "null handle");                                   \
+        if ((r) < 0 || (r) >= (h)->R()) return fail(MPMC_EINVAL, "replica out of range");    \
+    } while (0)
+
+#define MPMC_NEED_LOADED(h, r)                                                               \
+    do {                                                                                     \
+        MPMC_NEED_REPLICA(h, r);                                                             \
+        if (!(h)->loaded[(size_t)(r)])                                                       \
+            return fail(MPMC_ESTATE, "no valid state loaded (mpmc_set_state)");              \
+    } while (0)
+
+#define MPMC_NEED_SINGLE(h)                                                                  \
+    do {                                                                                     \
+        if (!(h)) return fail(MPMC_EINVAL, "null handle");                                   \
+        if ((h)->R() != 1) return fail(MPMC_EINVAL, "batched handle: use mpmc_replica_*");   \
+    } while (0)
+
+mpmc_status check_delta(const mpmc_system *h, int r, float delta)
+{
+    const Geom &g = h->L.reps[(size_t)r].g;
+    if (!(delta > 0.0f) || delta > 0.5f * std::min(g.wx, g.wy))
+        return fail(MPMC_EINVAL, "delta must lie in (0, min(w)/2]");
+    return MPMC_OK;
+}
 
 }  // namespace
 
@@ -336,131 +641,41 @@ mpmc_status mpmc_geometry_of(const mpmc_params *p, mpmc_geometry *out)
 
 mpmc_status mpmc_required_bytes(const mpmc_params *p, mpmc_buffer_sizes *out)
 {
-    if (!out) return fail(MPMC_EINVAL, "null argument");
-    mpmc_geometry g;
-    const mpmc_status s = derive_geometry(p, &g);
-    if (s) return s;
-    const long long N = g.n_particles, C = (long long)g.cells_x * g.cells_y;
-    out->pos = align256(std::max<size_t>(8 * (size_t)N, 8));
-    out->start = align256(4 * (size_t)(C + 1));
-    out->acc = (p->flags & MPMC_FLAG_ACC) ? align256(std::max<size_t>(8 * (size_t)N, 8)) : 0;
-    out->tag = (p->flags & MPMC_FLAG_TAG) ? align256(std::max<size_t>(4 * (size_t)N, 4)) : 0;
-    out->work = work_bytes(C);
-    out->ctl = align256(sizeof(Ctl));
-    return MPMC_OK;
+    if (!p) return fail(MPMC_EINVAL, "null argument");
+    return sizes_of(p, 1, out);
+}
+
+mpmc_status mpmc_batch_required_bytes(const mpmc_params *per_replica, int32_t n_replicas,
+                                      mpmc_buffer_sizes *out)
+{
+    return sizes_of(per_replica, n_replicas, out);
 }
 
 mpmc_status mpmc_init_system(const mpmc_params *p, const mpmc_buffers *b, void *stream,
                              mpmc_handle *out)
 {
-    if (!p || !b || !out) return fail(MPMC_EINVAL, "null argument");
-    *out = nullptr;
-    mpmc_geometry geo;
-    mpmc_status s = derive_geometry(p, &geo);
-    if (s) return s;
-    s = check_params(p, geo);
-    if (s) return s;
-    for (int i = 0; i < 2; ++i) {
-        if (!b->pos[i] || !b->start[i]) return fail(MPMC_EINVAL, "pos/start buffers missing");
-        if ((p->flags & MPMC_FLAG_ACC) && !b->acc[i]) return fail(MPMC_EINVAL, "acc buffers missing");
-        if ((p->flags & MPMC_FLAG_TAG) && !b->tag[i]) return fail(MPMC_EINVAL, "tag buffers missing");
-    }
-    if (!b->work || !b->ctl) return fail(MPMC_EINVAL, "work/ctl buffers missing");
+    if (!p) return fail(MPMC_EINVAL, "null argument");
+    return create(p, 1, b, stream, out);
+}
 
-    mpmc_system *h = new mpmc_system();
-    h->p = *p;
-    h->geo = geo;
-    h->g.mx = geo.cells_x;
-    h->g.my = geo.cells_y;
-    h->g.C = geo.cells_x * geo.cells_y;
-    h->g.cap = geo.capacity;
-    h->g.wx = geo.w_x;
-    h->g.wy = geo.w_y;
-    h->g.N = geo.n_particles;
-    h->st = (hipStream_t)stream;
-    for (int i = 0; i < 2; ++i) {
-        h->pos[i] = (float2 *)b->pos[i];
-        h->start[i] = (uint32_t *)b->start[i];
-        h->acc[i] = (p->flags & MPMC_FLAG_ACC) ? (float2 *)b->acc[i] : nullptr;
-        h->tag[i] = (p->flags & MPMC_FLAG_TAG) ? (uint32_t *)b->tag[i] : nullptr;
-    }
-    {
-        char *w = (char *)b->work;
-        h->work.scan = (uint32_t *)w;
-        w += align256((size_t)mpmc::scan_partials(h->g.C) * 4);
-        h->work.cnt = (uint32_t *)w;
-        h->work.cnt_stride = (int)mpmc::count_stride(h->g.C);
-        w += align256((size_t)mpmc::count_stride(h->g.C) * 10 * 4);
-        h->work.f64 = (double *)w;
-    }
-    h->ctl = (Ctl *)b->ctl;
-    h->cur = 0;
-    h->lanes = 1;
-    h->block = 256;
-    h->key0 = p->seed;
-    h->ready = false;
-    h->lone_pending = false;
-    h->graph[0] = h->graph[1] = nullptr;
+mpmc_status mpmc_batch_init(const mpmc_params *per_replica, int32_t n_replicas,
+                            const mpmc_buffers *b, void *stream, mpmc_handle *out)
+{
+    return create(per_replica, n_replicas, b, stream, out);
+}
 
-    const int C = h->g.C;
-    const long long N = h->g.N;
-    std::vector<uint32_t> start((size_t)C + 1, 0);
-    std::vector<float> xy(2 * (size_t)std::max(N, 1LL));
-    std::vector<uint32_t> tags((size_t)std::max(N, 1LL));
-    if (p->lattice_nx > 0) {
-        // Initial condition: lattice site (i, j) at x = (i + 1/4 + (j odd)/2) a,
-        // y = (j + 1/2) h in FP64; cell ceil(x/w) - 1; local (float)(x - c w);
-        // cells list their disks in ascending lattice index.
-        const int nx = p->lattice_nx, ny = p->lattice_ny;
-        const Lattice L = lattice_of(nx, ny, p->phi);
-        std::vector<int> cell_of((size_t)N);
-        std::vector<float> lx((size_t)N), ly((size_t)N);
-        for (int j = 0; j < ny; ++j)
-            for (int i = 0; i < nx; ++i) {
-                const size_t k = (size_t)j * nx + i;
-                const double x = ((double)i + 0.25 + 0.5 * (double)(j & 1)) * L.a;
-                const double y = ((double)j + 0.5) * L.h;
-                const int cx = (int)std::ceil(x / (double)h->g.wx) - 1;
-                const int cy = (int)std::ceil(y / (double)h->g.wy) - 1;
-                if (cx < 0 || cx >= h->g.mx || cy < 0 || cy >= h->g.my) {
-                    delete h;
-                    return fail(MPMC_EGEOM, "lattice site outside the cell grid");
-                }
-                lx[k] = (float)(x - (double)cx * (double)h->g.wx);
-                ly[k] = (float)(y - (double)cy * (double)h->g.wy);
-                cell_of[k] = cy * h->g.mx + cx;
-                start[(size_t)cell_of[k] + 1] += 1;
-            }
-        for (int c = 0; c < C; ++c) start[(size_t)c + 1] += start[(size_t)c];
-        std::vector<uint32_t> fill(start.begin(), start.end() - 1);
-        for (long long k = 0; k < N; ++k) {
-            const uint32_t o = fill[(size_t)cell_of[(size_t)k]]++;
-            xy[2 * (size_t)o] = lx[(size_t)k];
-            xy[2 * (size_t)o + 1] = ly[(size_t)k];
-            tags[o] = (uint32_t)k;
-        }
-        s = validate_host_state(h, xy.data(), start.data());
-        if (s) {
-            delete h;
-            return s;
-        }
-        s = upload_state(h, xy.data(), start.data(), 0, tags.data());
-    } else {
-        if (N != 0) {
-            // empty until mpmc_set_state; start all zero is not a valid N > 0
-            // state, so only the control block is initialised here
-            MPMC_HIP(mpmc::launch_ctl_reset(h->g, h->ctl, 0, h->key0, p->replica, p->delta, h->st));
-            MPMC_HIP(hipStreamSynchronize(h->st));
-            s = MPMC_OK;
-        } else {
-            s = upload_state(h, xy.data(), start.data(), 0, nullptr);
-        }
-    }
-    if (s) {
-        delete h;
-        return s;
-    }
-    *out = h;
+mpmc_status mpmc_num_replicas(mpmc_handle h, int32_t *n)
+{
+    if (!h || !n) return fail(MPMC_EINVAL, "null argument");
+    *n = h->R();
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_replica_geometry(mpmc_handle h, int32_t r, mpmc_geometry *out)
+{
+    MPMC_NEED_REPLICA(h, r);
+    if (!out) return fail(MPMC_EINVAL, "null argument");
+    *out = h->L.geo[(size_t)r];
     return MPMC_OK;
 }
 
@@ -468,9 +683,9 @@ mpmc_status mpmc_sweep(mpmc_handle h, int64_t n_sweeps, uint32_t seed)
 {
     if (!h || n_sweeps < 0) return fail(MPMC_EINVAL, "bad handle or sweep count");
     MPMC_NEED_STATE(h);
-    if (seed != h->key0) {
-        MPMC_HIP(mpmc::launch_ctl_set_key0(h->g, h->ctl, seed, h->st));
-        h->key0 = seed;
+    if (std::any_of(h->key0.begin(), h->key0.end(), [&](uint32_t k) { return k != seed; })) {
+        MPMC_HIP(mpmc::launch_ctl_set_key0(h->t, seed, h->st));
+        std::fill(h->key0.begin(), h->key0.end(), seed);
     }
     return run_sweeps(h, n_sweeps);
 }
@@ -485,43 +700,45 @@ mpmc_status mpmc_subsweep(mpmc_handle h, int32_t set)
 mpmc_status mpmc_shift_and_rebin(mpmc_handle h, int32_t f, float d)
 {
     if (!h || f < -1 || f > 3) return fail(MPMC_EINVAL, "f must be -1..3");
-    if (f >= 0) {
-        const float w = f < 2 ? h->g.wx : h->g.wy;
-        if (!(d >= 0.0f && d <= 0.5f * w)) return fail(MPMC_EINVAL, "d must lie in [0, w/2]");
-    }
+    if (f >= 0)
+        for (const Rep &R : h->L.reps) {
+            const float w = f < 2 ? R.g.wx : R.g.wy;
+            if (!(d >= 0.0f && d <= 0.5f * w)) return fail(MPMC_EINVAL, "d must lie in [0, w/2]");
+        }
     MPMC_NEED_STATE(h);
-    if (f >= 0) return enqueue_rebin(h, f, d, 0, 0);
-    return enqueue_rebin(h, -1, 0.0f, 1, 0);
+    if (f >= 0) return enqueue_rebin(h, f, d, 0);
+    return enqueue_rebin(h, -1, 0.0f, 1);
 }
 
 mpmc_status mpmc_pair_histogram(mpmc_handle h, int32_t reset)
 {
     MPMC_NEED_STATE(h);
-    if (!h) return fail(MPMC_EINVAL, "null handle");
     const double rmax = 1.0 + MPMC_HIST_BINS * 1e-4;
-    const int Rx = (double)h->g.wx >= rmax ? 1 : 2, Ry = (double)h->g.wy >= rmax ? 1 : 2;
-    if (h->g.mx < 2 * Rx + 2 || h->g.my < 2 * Ry + 2)
-        return fail(MPMC_EGEOM, "grid too small for the histogram's reach");
-    MPMC_HIP(mpmc::launch_pair_histogram(h->g, h->pos[h->cur], h->start[h->cur], h->ctl, reset,
-                                         h->block, h->st));
+    for (const Rep &R : h->L.reps) {
+        const int Rx = (double)R.g.wx >= rmax ? 1 : 2, Ry = (double)R.g.wy >= rmax ? 1 : 2;
+        if (R.g.mx < 2 * Rx + 2 || R.g.my < 2 * Ry + 2)
+            return fail(MPMC_EGEOM, "grid too small for the histogram's reach");
+    }
+    MPMC_HIP(mpmc::launch_pair_histogram(h->t, h->pos[h->cur], h->start[h->cur], reset, h->st));
     return MPMC_OK;
 }
 
-mpmc_status mpmc_pressure_from_contact(mpmc_handle h, double *p_star, double *g_contact,
-                                       uint64_t *hist, uint64_t *n_samples)
+mpmc_status mpmc_replica_pressure_from_contact(mpmc_handle h, int32_t r, double *p_star,
+                                               double *g_contact, uint64_t *hist,
+                                               uint64_t *n_samples)
 {
-    MPMC_NEED_STATE(h);
-    if (!h) return fail(MPMC_EINVAL, "null handle");
-    Ctl c;
-    mpmc_status s = read_ctl(h, &c);
+    MPMC_NEED_LOADED(h, r);
+    mpmc_status s = read_ctl(h);
     if (s) return s;
-    if (c.hist_samples == 0) {
+    if (h->ctl_host[(size_t)r].hist_samples == 0) {
+        if (h->R() != 1) return fail(MPMC_ESTATE, "no histogram accumulated for this replica");
         s = mpmc_pair_histogram(h, 1);
         if (s) return s;
     }
-    MPMC_HIP(mpmc::launch_pressure_fit(h->g, h->ctl, h->st));
-    s = read_ctl(h, &c);
+    MPMC_HIP(mpmc::launch_pressure_fit(h->t, r, h->st));
+    s = read_ctl(h);
     if (s) return s;
+    const Ctl &c = h->ctl_host[(size_t)r];
     if (c.fit[3] != 1.0) return fail(MPMC_EDEVICE, "pressure fit failed");
     if (p_star) *p_star = c.fit[0];
     if (g_contact) *g_contact = c.fit[1];
@@ -530,118 +747,194 @@ mpmc_status mpmc_pressure_from_contact(mpmc_handle h, double *p_star, double *g_
     return MPMC_OK;
 }
 
+mpmc_status mpmc_pressure_from_contact(mpmc_handle h, double *p_star, double *g_contact,
+                                       uint64_t *hist, uint64_t *n_samples)
+{
+    MPMC_NEED_SINGLE(h);
+    return mpmc_replica_pressure_from_contact(h, 0, p_star, g_contact, hist, n_samples);
+}
+
+mpmc_status mpmc_replica_get_state(mpmc_handle h, int32_t r, float *xy, uint32_t *start,
+                                   uint64_t *sweep)
+{
+    MPMC_NEED_LOADED(h, r);
+    const Rep &R = h->L.reps[(size_t)r];
+    if (xy && R.g.N > 0)
+        MPMC_HIP(hipMemcpyAsync(xy, h->pos[h->cur] + R.pb, sizeof(float2) * (size_t)R.g.N,
+                                hipMemcpyDeviceToHost, h->st));
+    if (start)
+        MPMC_HIP(hipMemcpyAsync(start, h->start[h->cur] + R.cb, sizeof(uint32_t) * ((size_t)R.g.C + 1),
+                                hipMemcpyDeviceToHost, h->st));
+    const mpmc_status s = read_ctl(h);
+    if (s) return s;
+    if (start)
+        for (int c = 0; c <= R.g.C; ++c) start[c] -= (uint32_t)R.pb;
+    if (sweep) *sweep = h->ctl_host[(size_t)r].sweep;
+    return MPMC_OK;
+}
+
 mpmc_status mpmc_get_state(mpmc_handle h, float *xy, uint32_t *start, uint64_t *sweep)
 {
-    MPMC_NEED_STATE(h);
-    if (!h) return fail(MPMC_EINVAL, "null handle");
-    if (xy) MPMC_HIP(hipMemcpyAsync(xy, h->pos[h->cur], sizeof(float2) * (size_t)h->g.N, hipMemcpyDeviceToHost, h->st));
-    if (start) MPMC_HIP(hipMemcpyAsync(start, h->start[h->cur], sizeof(uint32_t) * ((size_t)h->g.C + 1), hipMemcpyDeviceToHost, h->st));
-    Ctl c;
-    const mpmc_status s = read_ctl(h, &c);
+    MPMC_NEED_SINGLE(h);
+    return mpmc_replica_get_state(h, 0, xy, start, sweep);
+}
+
+mpmc_status mpmc_replica_set_state(mpmc_handle h, int32_t r, const float *xy,
+                                   const uint32_t *start, uint64_t sweep, const uint32_t *tags)
+{
+    MPMC_NEED_REPLICA(h, r);
+    const Rep &R = h->L.reps[(size_t)r];
+    if (!start || (!xy && R.g.N > 0)) return fail(MPMC_EINVAL, "null argument");
+    const mpmc_status s = validate_host_state(R, xy, start);
     if (s) return s;
-    if (sweep) *sweep = c.sweep;
-    return MPMC_OK;
+    return upload_replica(h, r, xy, start, sweep, tags);
 }
 
 mpmc_status mpmc_set_state(mpmc_handle h, const float *xy, const uint32_t *start, uint64_t sweep,
                            const uint32_t *tags)
 {
-    if (!h || !start || (!xy && h->g.N > 0)) return fail(MPMC_EINVAL, "null argument");
-    mpmc_status s = validate_host_state(h, xy, start);
-    if (s) return s;
-    return upload_state(h, xy, start, sweep, tags);
+    MPMC_NEED_SINGLE(h);
+    return mpmc_replica_set_state(h, 0, xy, start, sweep, tags);
+}
+
+mpmc_status mpmc_replica_get_aux(mpmc_handle h, int32_t r, float *acc, uint32_t *tags)
+{
+    MPMC_NEED_LOADED(h, r);
+    const Rep &R = h->L.reps[(size_t)r];
+    if (acc) {
+        if (!h->acc[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_ACC");
+        if (R.g.N > 0)
+            MPMC_HIP(hipMemcpyAsync(acc, h->acc[h->cur] + R.pb, sizeof(float2) * (size_t)R.g.N,
+                                    hipMemcpyDeviceToHost, h->st));
+    }
+    if (tags) {
+        if (!h->tag[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_TAG");
+        if (R.g.N > 0)
+            MPMC_HIP(hipMemcpyAsync(tags, h->tag[h->cur] + R.pb, sizeof(uint32_t) * (size_t)R.g.N,
+                                    hipMemcpyDeviceToHost, h->st));
+    }
+    return read_ctl(h);
 }
 
 mpmc_status mpmc_get_aux(mpmc_handle h, float *acc, uint32_t *tags)
 {
-    MPMC_NEED_STATE(h);
-    if (!h) return fail(MPMC_EINVAL, "null handle");
-    if (acc) {
-        if (!h->acc[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_ACC");
-        MPMC_HIP(hipMemcpyAsync(acc, h->acc[h->cur], sizeof(float2) * (size_t)h->g.N, hipMemcpyDeviceToHost, h->st));
-    }
-    if (tags) {
-        if (!h->tag[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_TAG");
-        MPMC_HIP(hipMemcpyAsync(tags, h->tag[h->cur], sizeof(uint32_t) * (size_t)h->g.N, hipMemcpyDeviceToHost, h->st));
-    }
-    Ctl c;
-    return read_ctl(h, &c);
+    MPMC_NEED_SINGLE(h);
+    return mpmc_replica_get_aux(h, 0, acc, tags);
 }
 
 mpmc_status mpmc_reset_acc(mpmc_handle h)
 {
     MPMC_NEED_STATE(h);
-    if (!h) return fail(MPMC_EINVAL, "null handle");
     if (!h->acc[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_ACC");
-    MPMC_HIP(mpmc::launch_fill_u32((uint32_t *)h->acc[h->cur], 0u, 2 * h->g.N, h->st));
+    MPMC_HIP(mpmc::launch_fill_u32((uint32_t *)h->acc[h->cur], 0u, 2 * h->L.N, h->st));
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_replica_msd(mpmc_handle h, int32_t r, double *msd)
+{
+    MPMC_NEED_LOADED(h, r);
+    if (!msd) return fail(MPMC_EINVAL, "null argument");
+    if (!h->acc[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_ACC");
+    const Rep &R = h->L.reps[(size_t)r];
+    MPMC_HIP(mpmc::launch_msd(h->acc[h->cur] + R.pb, R.g.N, h->t.ctls + r, h->work, h->st));
+    const mpmc_status s = read_ctl(h);
+    if (s) return s;
+    *msd = h->ctl_host[(size_t)r].msd;
     return MPMC_OK;
 }
 
 mpmc_status mpmc_msd(mpmc_handle h, double *msd)
 {
-    MPMC_NEED_STATE(h);
-    if (!h || !msd) return fail(MPMC_EINVAL, "null argument");
-    if (!h->acc[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_ACC");
-    MPMC_HIP(mpmc::launch_msd(h->g, h->acc[h->cur], h->work, h->ctl, h->st));
-    Ctl c;
-    const mpmc_status s = read_ctl(h, &c);
-    if (s) return s;
-    *msd = c.msd;
-    return MPMC_OK;
+    MPMC_NEED_SINGLE(h);
+    return mpmc_replica_msd(h, 0, msd);
 }
 
 mpmc_status mpmc_count_overlaps(mpmc_handle h, int64_t *pairs)
 {
     MPMC_NEED_STATE(h);
-    if (!h || !pairs) return fail(MPMC_EINVAL, "null argument");
-    MPMC_HIP(mpmc::launch_count_overlaps(h->g, h->pos[h->cur], h->start[h->cur], h->ctl, h->block, h->st));
-    Ctl c;
-    const mpmc_status s = read_ctl(h, &c);
+    if (!pairs) return fail(MPMC_EINVAL, "null argument");
+    MPMC_HIP(mpmc::launch_count_overlaps(h->t, h->pos[h->cur], h->start[h->cur], h->st));
+    const mpmc_status s = read_ctl(h);
     if (s) return s;
-    *pairs = c.overlaps;
+    int64_t total = 0;
+    for (const Ctl &c : h->ctl_host) total += c.overlaps;
+    *pairs = total;
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_replica_get_counters(mpmc_handle h, int32_t r, uint64_t *trials,
+                                      uint64_t *accepts)
+{
+    MPMC_NEED_REPLICA(h, r);
+    const mpmc_status s = read_ctl(h);
+    if (s) return s;
+    if (trials) *trials = h->ctl_host[(size_t)r].trials;
+    if (accepts) *accepts = h->ctl_host[(size_t)r].accepts;
     return MPMC_OK;
 }
 
 mpmc_status mpmc_get_counters(mpmc_handle h, uint64_t *trials, uint64_t *accepts)
 {
     if (!h) return fail(MPMC_EINVAL, "null handle");
-    Ctl c;
-    const mpmc_status s = read_ctl(h, &c);
+    const mpmc_status s = read_ctl(h);
     if (s) return s;
-    if (trials) *trials = c.trials;
-    if (accepts) *accepts = c.accepts;
+    uint64_t t = 0, a = 0;
+    for (const Ctl &c : h->ctl_host) {
+        t += c.trials;
+        a += c.accepts;
+    }
+    if (trials) *trials = t;
+    if (accepts) *accepts = a;
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_replica_set_delta(mpmc_handle h, int32_t r, float delta)
+{
+    MPMC_NEED_REPLICA(h, r);
+    const mpmc_status s = check_delta(h, r, delta);
+    if (s) return s;
+    MPMC_HIP(mpmc::launch_ctl_set_delta(h->t, r, delta, h->st));
     return MPMC_OK;
 }
 
 mpmc_status mpmc_set_delta(mpmc_handle h, float delta)
 {
     if (!h) return fail(MPMC_EINVAL, "null handle");
-    if (!(delta > 0.0f) || delta > 0.5f * std::min(h->g.wx, h->g.wy))
-        return fail(MPMC_EINVAL, "delta must lie in (0, min(w)/2]");
-    MPMC_HIP(mpmc::launch_ctl_set_delta(h->ctl, delta, h->st));
-    h->p.delta = delta;
+    for (int r = 0; r < h->R(); ++r) {
+        const mpmc_status s = check_delta(h, r, delta);
+        if (s) return s;
+    }
+    MPMC_HIP(mpmc::launch_ctl_set_delta(h->t, -1, delta, h->st));
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_replica_get_delta(mpmc_handle h, int32_t r, float *delta)
+{
+    MPMC_NEED_REPLICA(h, r);
+    if (!delta) return fail(MPMC_EINVAL, "null argument");
+    const mpmc_status s = read_ctl(h);
+    if (s) return s;
+    *delta = h->ctl_host[(size_t)r].delta;
     return MPMC_OK;
 }
 
 mpmc_status mpmc_get_delta(mpmc_handle h, float *delta)
 {
-    if (!h || !delta) return fail(MPMC_EINVAL, "null argument");
-    Ctl c;
-    const mpmc_status s = read_ctl(h, &c);
-    if (s) return s;
-    *delta = c.delta;
-    return MPMC_OK;
+    MPMC_NEED_SINGLE(h);
+    return mpmc_replica_get_delta(h, 0, delta);
 }
 
 mpmc_status mpmc_tune(mpmc_handle h, int32_t window_sweeps, int32_t n_windows)
 {
     if (!h || window_sweeps < 1 || n_windows < 0) return fail(MPMC_EINVAL, "bad tuner arguments");
     MPMC_NEED_STATE(h);
-    MPMC_HIP(mpmc::launch_tune(h->g, h->ctl, 0, h->st));   // open the first window
+    MPMC_HIP(mpmc::launch_fold_counters(h->t, h->work, h->st));
+    MPMC_HIP(mpmc::launch_tune(h->t, 0, h->st));   // open the first window
     for (int w = 0; w < n_windows; ++w) {
         const mpmc_status s = run_sweeps(h, window_sweeps);
         if (s) return s;
-        MPMC_HIP(mpmc::launch_tune(h->g, h->ctl, 1, h->st));
+        MPMC_HIP(mpmc::launch_fold_counters(h->t, h->work, h->st));
+        MPMC_HIP(mpmc::launch_tune(h->t, 1, h->st));
     }
     return MPMC_OK;
 }
@@ -653,8 +946,7 @@ mpmc_status mpmc_set_launch(mpmc_handle h, int32_t lanes_per_cell, int32_t block
         return fail(MPMC_EINVAL, "lanes_per_cell must be 1");
     if (block_size < 64 || block_size > 256 || block_size % 64)
         return fail(MPMC_EINVAL, "block size must be a multiple of 64 in [64, 256]");
-    drop_graphs(h);
-    h->lanes = lanes_per_cell;
+    if (block_size != h->block) drop_graphs(h);
     h->block = block_size;
     return MPMC_OK;
 }
@@ -673,7 +965,7 @@ mpmc_status mpmc_autotune(mpmc_handle h, int32_t sweeps, int32_t *block_out,
     float best_ms = -1.0f;
     mpmc_status s = MPMC_OK;
     for (int b : candidates) {
-        s = mpmc_set_launch(h, h->lanes, b);
+        s = mpmc_set_launch(h, 1, b);
         if (s) break;
         s = run_sweeps(h, sweeps);   // capture and warm
         if (s) break;
@@ -692,19 +984,17 @@ mpmc_status mpmc_autotune(mpmc_handle h, int32_t sweeps, int32_t *block_out,
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (s) return s;
-    s = mpmc_set_launch(h, h->lanes, best);
+    s = mpmc_set_launch(h, 1, best);
     if (s) return s;
     if (block_out) *block_out = best;
     if (us_per_sweep_out) *us_per_sweep_out = 1e3 * (double)best_ms / (double)sweeps;
-    Ctl c;
-    return read_ctl(h, &c);
+    return read_ctl(h);
 }
 
 mpmc_status mpmc_synchronize(mpmc_handle h)
 {
     if (!h) return fail(MPMC_EINVAL, "null handle");
-    Ctl c;
-    return read_ctl(h, &c);
+    return read_ctl(h);
 }
 
 void mpmc_destroy(mpmc_handle h)

@@ -1,5 +1,12 @@
 // Internal declarations shared by the host API (mpmc_api.cpp) and the
 // kernels (mpmc_kernels.hip).  Not part of the public ABI.
+//
+// Every handle holds R >= 1 independent systems ("replicas").  Their cells and
+// disks are concatenated in one compressed-row layout; each replica's cell
+// range is padded to whole rebin tiles and its active-cell range to whole
+// active chunks, so that every workgroup of every kernel belongs to exactly
+// one replica and finds it with one table load.  A single system is the
+// batch with R = 1.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,18 +18,24 @@ constexpr int kHistBins = 200;
 constexpr uint32_t kErrCapacity = 1u;     // a cell holds more disks than its capacity
 constexpr uint32_t kErrCount = 2u;        // rebuilt cell list does not hold N disks
 
-// Device control block: everything a captured sweep graph reads or writes
-// that changes between launches lives here, not in kernel arguments.
+constexpr int kRebinTile = 256;           // cells per rebin workgroup (one per thread)
+constexpr int kActiveChunk = 768;         // active-slot granularity (lcm of 64, 128, 192, 256)
+constexpr int kGranule = 64;              // counter partials: one per 64 active slots
+constexpr int kMsdBlocksMax = 512;
+
+// Per-replica control block: everything a captured sweep graph reads or
+// writes that changes between launches lives here, not in kernel arguments.
 struct alignas(256) Ctl {
     unsigned long long sweep;        // current sweep index s
-    unsigned long long trials;       // trial moves since init / set_state
-    unsigned long long accepts;      // accepted moves
+    unsigned long long trials;       // trial moves since init / set_state (folded)
+    unsigned long long accepts;      // accepted moves (folded)
     unsigned long long win_trials;   // counters at the start of the tuner window
     unsigned long long win_accepts;
     unsigned int key0, key1;         // Philox key (seed, replica)
     float delta;                     // maximum trial displacement
     unsigned int errword;            // kErr* bits set by kernels
-    unsigned int pad0[2];
+    int shift_f;                     // the running sweep's shift, recorded by the
+    float shift_d;                   //   rebin's count kernel for its scatter
     // Sweep-global draws of sweep s in draw[s & 1]: set order (byte q = set
     // of slot q), shift direction f and distance d.  Written when the sweep
     // counter or the key changes, read by every launch of the sweep.
@@ -45,65 +58,80 @@ struct Geom {
     long long N;
 };
 
-// Per-sweep draws shared by the sub-sweep and rebin launches.
-struct SweepBuffers {
-    const float2 *pos;
-    const uint32_t *start;
-    const float2 *acc;
-    const uint32_t *tag;
+// Placement and initial parameters of one replica.
+struct Rep {
+    Geom g;
+    long long cb;        // first global cell; multiple of kRebinTile
+    long long cpad;      // padded cell count; multiple of kRebinTile
+    long long pb;        // first global disk
+    long long ab;        // first global active slot; multiple of kActiveChunk
+    long long apad;      // padded active-slot count; multiple of kActiveChunk
+    int n_moves;
+    unsigned int key0, key1;
+    float delta0;
+    int pad[2];
 };
 
-// Scratch layout (caller's work buffer): u32 scan partials of the rebin,
-// then per-workgroup trial/accept partials (slot-major [slot][trials|accepts]
-// [tile]: slots 0-3 are the four sub-sweeps of a sweep, slot 4 accumulates
-// lone sub-sweeps), then FP64 reduction partials.
+// Device tables of a handle (in the caller's control buffer), passed to the
+// kernels by value.
+struct Tables {
+    const Rep *reps;        // [R]
+    Ctl *ctls;              // [R]
+    const uint16_t *arep;   // replica of each active chunk
+    const uint16_t *crep;   // replica of each rebin tile
+    int R;
+    int cap;                // largest capacity
+    long long cells;        // padded cells, all replicas
+    long long active;       // padded active slots, all replicas
+    long long N;            // disks, all replicas
+};
+
+// Scratch (caller's work buffer): u32 per-tile totals of the rebin, u64
+// trial/accept partials per granule of active slots (accumulated by every
+// sub-sweep, folded into the control blocks on demand), FP64 partials.
 struct Work {
-    uint32_t *scan;    // scan_partials(C) entries
-    uint32_t *cnt;     // 10 * count_stride(C) entries
-    double *f64;       // kMsdBlocksMax entries
+    uint32_t *scan;              // cells / kRebinTile entries
+    unsigned long long *cnt;     // [2][cnt_stride]
+    double *f64;                 // kMsdBlocksMax entries
     int cnt_stride;
 };
 
+inline long long scan_entries(long long cells) { return cells / kRebinTile + 8; }
+inline long long count_stride(long long active) { return active / kGranule + 8; }
+
 // ---- launch wrappers (defined in mpmc_kernels.hip) ----
-// Sub-sweep of one checkerboard set; set >= 0 explicit (its counters go to
-// the lone slot, folded by launch_fold_lone), set < 0 means the sweep's slot
-// (-1 - set) of the shuffled set order (counters folded by the rebin).  The
-// workgroup size is at most 256 (LDS: 8 * cap float2 per lane).
-hipError_t launch_subsweep(const Geom &g, float2 *pos, const uint32_t *start, float2 *acc,
-                           uint32_t *tag, Ctl *ctl, const Work &w, int n_moves, int set,
-                           int lanes_per_cell, int block, hipStream_t st);
-
-// Shift (f, d) -- or the sweep's own draws when f < 0 -- and rebuild the
-// cell lists into the *_out buffers.  advance != 0 increments the sweep.
-hipError_t launch_fold_lone(const Work &w, Ctl *ctl, hipStream_t st);
-
-// With f < 0 it also folds the four sub-sweeps' counters (sub_block = their
-// workgroup size) into the control block.
-hipError_t launch_rebin(const Geom &g, const float2 *pos, const uint32_t *start,
+// Sub-sweep of every replica; set >= 0 is the same explicit set everywhere,
+// set < 0 is each replica's slot (-1 - set) of its own shuffled set order.
+// The workgroup size is 64, 128, 192 or 256 (reduced for wide cells).
+hipError_t launch_subsweep(const Tables &t, float2 *pos, const uint32_t *start, float2 *acc,
+                           uint32_t *tag, const Work &w, int set, int block, hipStream_t st);
+// Add the counter partials into each replica's control block; clear them.
+hipError_t launch_fold_counters(const Tables &t, const Work &w, hipStream_t st);
+// Shift (f, d) -- or each replica's own draws when f < 0 -- and rebuild the
+// cell lists into the *_out buffers; advance moves every replica on to its
+// next sweep (only with f < 0).
+hipError_t launch_rebin(const Tables &t, const float2 *pos, const uint32_t *start,
                         const float2 *acc, const uint32_t *tag, float2 *pos_out,
                         uint32_t *start_out, float2 *acc_out, uint32_t *tag_out,
-                        const Work &w, Ctl *ctl, int f, float d, int advance, int block,
-                        int sub_block, hipStream_t st);
-
-hipError_t launch_pair_histogram(const Geom &g, const float2 *pos, const uint32_t *start,
-                                 Ctl *ctl, int reset, int block, hipStream_t st);
-hipError_t launch_pressure_fit(const Geom &g, Ctl *ctl, hipStream_t st);
-hipError_t launch_count_overlaps(const Geom &g, const float2 *pos, const uint32_t *start,
-                                 Ctl *ctl, int block, hipStream_t st);
-hipError_t launch_msd(const Geom &g, const float2 *acc, const Work &w, Ctl *ctl,
-                      hipStream_t st);
-// apply == 0 only opens a new tuner window (records the counters).
-hipError_t launch_tune(const Geom &g, Ctl *ctl, int apply, hipStream_t st);
+                        const Work &w, int f, float d, int advance, hipStream_t st);
+hipError_t launch_pair_histogram(const Tables &t, const float2 *pos, const uint32_t *start,
+                                 int reset, hipStream_t st);
+hipError_t launch_pressure_fit(const Tables &t, int replica, hipStream_t st);
+hipError_t launch_count_overlaps(const Tables &t, const float2 *pos, const uint32_t *start,
+                                 hipStream_t st);
+// Mean |acc|^2 over n accumulators (one replica's range) into ctl->msd.
+hipError_t launch_msd(const float2 *acc, long long n, Ctl *ctl, const Work &w, hipStream_t st);
+// apply == 0 only opens a new tuner window (records the counters); call after
+// launch_fold_counters.
+hipError_t launch_tune(const Tables &t, int apply, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, long long n, hipStream_t st);
-hipError_t launch_ctl_reset(const Geom &g, Ctl *ctl, unsigned long long sweep, unsigned int key0,
-                            unsigned int key1, float delta, hipStream_t st);
-hipError_t launch_ctl_set_key0(const Geom &g, Ctl *ctl, unsigned int key0, hipStream_t st);
-hipError_t launch_ctl_set_delta(Ctl *ctl, float delta, hipStream_t st);
-
-// Work-buffer sizes, from the smallest workgroup allowed.
-constexpr int kMinBlock = 64;
-constexpr int kMsdBlocksMax = 512;
-inline long long scan_partials(long long C) { return (C + kMinBlock - 1) / kMinBlock + 8; }
-inline long long count_stride(long long C) { return (C / 4 + kMinBlock - 1) / kMinBlock + 8; }
+// Reset the control block of replica r (every replica when r < 0) to sweep,
+// its initial key and delta.
+hipError_t launch_ctl_reset(const Tables &t, int replica, unsigned long long sweep,
+                            hipStream_t st);
+hipError_t launch_ctl_set_key0(const Tables &t, unsigned int key0, hipStream_t st);
+hipError_t launch_ctl_set_delta(const Tables &t, int replica, float delta, hipStream_t st);
+// Workgroup size the sub-sweep actually uses for a requested one.
+int subsweep_block(int cap, int block);
 
 }  // namespace mpmc

@@ -225,14 +225,15 @@ __device__ __forceinline__ unsigned block_exclusive_scan_u32(unsigned v, unsigne
 // One lane per active cell of set Q (Alg. 2).  The kernel is organised to
 // expose memory-level parallelism rather than to chase pointers:
 //   1. all 18 offsets of the 3x3 block are loaded at once;
-//   2. every position of the block is loaded at once (predicated by count);
-//      the Philox blocks of the cell are computed while the loads fly;
+//   2. every position of the block is loaded at once (unconditionally, at
+//      indices clamped into [0, N)); the Philox blocks of the cell are
+//      computed while the loads fly;
 //   3. neighbour disks are translated into the cell's frame (exactly -w, 0
 //      or +w, Sec. 3.1) and those that can reach the cell at all -- closer
 //      than 1.0001 to the cell rectangle, a superset of every disk a trial
 //      position inside the cell can overlap -- are compacted into this
-//      lane's column of an LDS table (row-major by entry, one column per
-//      lane, so a wave reads 64 consecutive float2 per row);
+//      lane's row of an LDS table (lane-major, odd row stride, so sixteen
+//      lanes reading entry k hit sixteen distinct bank pairs);
 //   4. the n_M trials run from registers (own cell) and LDS (neighbours).
 // Dropping unreachable disks cannot change a decision: a trial outside the
 // cell is rejected before any overlap test, and one inside it is at distance
@@ -242,27 +243,35 @@ constexpr float kReachEdge = 1.0001f;
 
 template <int CAP>
 __global__ void __launch_bounds__(256)
-k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
-           float2 *__restrict__ acc, uint32_t *__restrict__ tag, const Ctl *__restrict__ ctl,
-           uint32_t *__restrict__ cnt, int cnt_stride, int n_moves, int set, int ntile, int per)
+k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
+           float2 *__restrict__ acc, uint32_t *__restrict__ tag,
+           unsigned long long *__restrict__ cnt, int cnt_stride, int set, int ntile, int per)
 {
-    extern __shared__ float2 nbr[];   // [8 * CAP][blockDim.x]; reused for the counts
+    extern __shared__ float2 lds[];   // [blockDim.x][kRow]; reused for the counts
+    constexpr int kRow = 8 * CAP + 1;  // odd stride: 16 lanes hit distinct bank pairs
     const int tile = xcd_tile(per);
+    const long long slot0 = (long long)tile * blockDim.x;
+    const int r = tile < ntile ? (int)t.arep[slot0 / kActiveChunk] : 0;
+    const Rep &R = t.reps[r];
+    const Geom g = R.g;
+    Ctl *ctl = t.ctls + r;
     const unsigned long long s = ctl->sweep;
     const uint32_t k0 = ctl->key0, k1 = ctl->key1;
     const float delta = ctl->delta;
+    const int n_moves = R.n_moves;
     const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
 
     int Q = set;
     if (Q < 0) Q = (int)((ctl->draw[s & 1ull].order >> (8 * (-1 - set))) & 0xFFu);
     const int qx = Q & 1, qy = Q >> 1;
     const int hx = g.mx >> 1, hy = g.my >> 1;
-    const int gid = tile * (int)blockDim.x + (int)threadIdx.x;
-    const int L = (int)blockDim.x, lane = (int)threadIdx.x;
+    const long long gid = slot0 + (long long)threadIdx.x - R.ab;   // within the replica
+    float2 *const nbr = lds + threadIdx.x * kRow;   // this lane's neighbour list
+    const uint32_t *const st = start + R.cb;        // this replica's offsets
 
     unsigned n_trials = 0, n_acc = 0;
-    if (tile < ntile && gid < hx * hy) {
-        const int iy = gid / hx, ix = gid - iy * hx;
+    if (tile < ntile && gid < (long long)hx * hy) {
+        const int iy = (int)(gid / hx), ix = (int)(gid - (long long)iy * hx);
         const int cx = 2 * ix + qx, cy = 2 * iy + qy;
         const int c = cy * g.mx + cx;
         const int xl = cx == 0 ? g.mx - 1 : cx - 1;
@@ -276,14 +285,14 @@ k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
             const int row = q / 3 == 0 ? yd : (q / 3 == 1 ? cy : yu);
             const int col = q % 3 == 0 ? xl : (q % 3 == 1 ? cx : xr);
             const int cc = row * g.mx + col;
-            rb[q] = start[cc];
-            rn[q] = start[cc + 1];
+            rb[q] = st[cc];
+            rn[q] = st[cc + 1];
         }
         bool bad = false;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             rn[q] -= rb[q];
-            bad |= rn[q] > (uint32_t)CAP;
+            bad |= rn[q] > (uint32_t)g.cap;
         }
         int n = (int)rn[4];
         if (bad) {
@@ -295,7 +304,7 @@ k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
             const bool has_acc = acc != nullptr, has_tag = tag != nullptr;
             // 2. all positions of the block in flight together: unconditional
             // loads at indices clamped into [0, N), selected afterwards
-            const uint32_t last = (uint32_t)(g.N - 1);
+            const uint32_t last = (uint32_t)(t.N - 1);
             float2 nv[9][CAP];
 #pragma unroll
             for (int q = 0; q < 9; ++q)
@@ -353,10 +362,17 @@ k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
                         const float ey = ra == 0 ? -oy : oy - g.wy;
                         reach = ex * ex + ey * ey < kReach2;
                     }
-                    nbr[K * L + lane] = make_float2(ox, oy);   // row K <= slots seen so far
+                    nbr[K] = make_float2(ox, oy);   // row K <= slots seen so far
                     K += (i < (int)rn[q] && reach) ? 1 : 0;
                 }
             }
+            // pad to a multiple of four with a disk that overlaps nothing;
+            // the padded rows stay below 8 * CAP because K <= 8 * CAP
+            const int K4 = (K + 3) & ~3;
+            const float2 far = make_float2(1.0e6f, 1.0e6f);
+            if (K + 0 < K4) nbr[K + 0] = far;
+            if (K + 1 < K4) nbr[K + 1] = far;
+            if (K + 2 < K4) nbr[K + 2] = far;
             // rng.shuffle(c.particles): Fisher-Yates over the stored list,
             // done on a packed permutation (nibble q = source slot of list
             // position q) and applied to the registers once.
@@ -379,10 +395,10 @@ k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
             }
             // 4. n_M trial moves on list[t mod n]: the registers are rotated
             // after every trial so that the particle moved is always entry 0.
-            for (int t = 0; t < n_moves; ++t) {
-                if (t > 0 && (t & 3) == 0) W = philox((uint32_t)c, s_lo, s_hi, (uint32_t)(t >> 2), k0, k1);
+            for (int tr = 0; tr < n_moves; ++tr) {
+                if (tr > 0 && (tr & 3) == 0) W = philox((uint32_t)c, s_lo, s_hi, (uint32_t)(tr >> 2), k0, k1);
                 float dx, dy;
-                displacement(word_of(W, t & 3), delta, dx, dy);
+                displacement(word_of(W, tr & 3), delta, dx, dy);
                 const float xm = px[0] + dx;
                 const float ym = py[0] + dy;
                 bool ok = xm > 0.0f && xm <= g.wx && ym > 0.0f && ym <= g.wy;
@@ -397,12 +413,18 @@ k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
                         }
                     }
                 }
-                for (int k = 0; ok && k < K; ++k) {
-                    const float2 e = nbr[k * L + lane];
-                    const float ddx = xm - e.x;
-                    const float ddy = ym - e.y;
-                    const float r2 = ddx * ddx + ddy * ddy;
-                    ok = !(r2 < 1.0f);
+                // neighbours four at a time (two paired LDS reads); the loop
+                // stops after the first group that holds an overlap
+                for (int k = 0; ok && k < K4; k += 4) {
+                    const float2 e0 = nbr[k], e1 = nbr[k + 1], e2 = nbr[k + 2], e3 = nbr[k + 3];
+                    const float d0x = xm - e0.x, d0y = ym - e0.y;
+                    const float d1x = xm - e1.x, d1y = ym - e1.y;
+                    const float d2x = xm - e2.x, d2y = ym - e2.y;
+                    const float d3x = xm - e3.x, d3y = ym - e3.y;
+                    // any r^2 < 1 <=> the smallest r^2 < 1 (all values finite)
+                    const float m = fminf(fminf(d0x * d0x + d0y * d0y, d1x * d1x + d1y * d1y),
+                                          fminf(d2x * d2x + d2y * d2y, d3x * d3x + d3y * d3y));
+                    ok = !(m < 1.0f);
                 }
                 if (ok) {
                     px[0] = xm;
@@ -438,81 +460,67 @@ k_subsweep(Geom g, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
             }
         }
     }
-    // Per-workgroup counts: a sweep's sub-sweep writes its slot (summed by the
-    // rebin's scan); a lone sub-sweep adds into the lone slot, whose entries
-    // each belong to one workgroup, and which is folded before the next read
-    // of the counters -- no contended atomics either way.
+    // The workgroup's counts are added to the partial of the granule holding
+    // its first slot.  Each granule entry belongs to one workgroup of a launch
+    // and launches are ordered, so the read-modify-write needs no atomics;
+    // the partials are folded into the control blocks on demand.
     __syncthreads();   // every lane is done with its neighbour table
-    unsigned *red = reinterpret_cast<unsigned *>(nbr);
+    unsigned *red = reinterpret_cast<unsigned *>(lds);
     const unsigned bt = block_sum_u32(n_trials, red);
     const unsigned ba = block_sum_u32(n_acc, red + 16);
-    if (threadIdx.x == 0 && tile < ntile) {
-        if (set < 0) {
-            const int slot = -1 - set;
-            cnt[(2 * slot) * cnt_stride + tile] = bt;
-            cnt[(2 * slot + 1) * cnt_stride + tile] = ba;
-        } else {
-            cnt[8 * cnt_stride + tile] += bt;
-            cnt[9 * cnt_stride + tile] += ba;
-        }
+    if (threadIdx.x == 0 && tile < ntile && bt) {
+        const long long gr = slot0 / kGranule;
+        cnt[gr] += bt;
+        cnt[cnt_stride + gr] += ba;
     }
 }
 
-// Sum the per-workgroup counts of `nslots` consecutive slots into the control
-// block (one workgroup of <= 1024 threads).  zero != 0 clears the slots read.
-__device__ __forceinline__ void fold_counters(uint32_t *cnt, int stride, int nslots, int ntile,
-                                              int zero, Ctl *ctl, unsigned long long *sh)
+// One workgroup per replica: add its granules' partials into its control
+// block and clear them.
+__global__ void __launch_bounds__(256) k_fold_counters(Tables t, unsigned long long *cnt, int stride)
 {
-    unsigned long long t = 0, a = 0;
-    for (int s = 0; s < nslots; ++s)
-        for (int i = threadIdx.x; i < ntile; i += blockDim.x) {
-            t += cnt[(2 * s) * stride + i];
-            a += cnt[(2 * s + 1) * stride + i];
-            if (zero) {
-                cnt[(2 * s) * stride + i] = 0u;
-                cnt[(2 * s + 1) * stride + i] = 0u;
-            }
-        }
+    __shared__ unsigned long long sh[8];
+    const Rep &R = t.reps[blockIdx.x];
+    const long long g0 = R.ab / kGranule, g1 = (R.ab + R.apad) / kGranule;
+    unsigned long long tr = 0, ac = 0;
+    for (long long i = g0 + threadIdx.x; i < g1; i += blockDim.x) {
+        tr += cnt[i];
+        ac += cnt[stride + i];
+        cnt[i] = 0ull;
+        cnt[stride + i] = 0ull;
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-        t += __shfl_xor(t, o, 64);
-        a += __shfl_xor(a, o, 64);
+        tr += __shfl_xor(tr, o, 64);
+        ac += __shfl_xor(ac, o, 64);
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
-        sh[wave] = t;
-        sh[16 + wave] = a;
+        sh[wave] = tr;
+        sh[4 + wave] = ac;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long T = 0, A = 0;
-        const int nw = (blockDim.x + 63) >> 6;
-        for (int q = 0; q < nw; ++q) {
-            T += sh[q];
-            A += sh[16 + q];
-        }
-        ctl->trials += T;
-        ctl->accepts += A;
+        Ctl *ctl = t.ctls + blockIdx.x;
+        ctl->trials += sh[0] + sh[1] + sh[2] + sh[3];
+        ctl->accepts += sh[4] + sh[5] + sh[6] + sh[7];
     }
-    __syncthreads();
-}
-
-// Fold the lone sub-sweeps' slot (8, 9) into the control block and clear it.
-__global__ void __launch_bounds__(1024) k_fold_lone(uint32_t *cnt, int stride, Ctl *ctl)
-{
-    __shared__ unsigned long long sh[32];
-    fold_counters(cnt + 8 * stride, stride, 1, stride, 1, ctl, sh);
 }
 
 // ----------------------------------------------------------------- rebin
 // Alg. 4 as a counting sort: new cell c holds the stayers of old c followed
 // by the leavers of the old cell in direction f, both in old list order.
-// Phase 1 counts per workgroup tile, phase 2 scans the tile totals, phase 3
-// recounts (same operations, same result), scans inside the tile and
-// scatters.  Each disk's decision is one rounded shifted coordinate tested
-// against (0, w].
+// Two kernels over tiles of 256 cells, one cell per thread:
+//   count   -- per tile, the number of disks its new cells receive;
+//   scatter -- each tile adds up the totals of its replica's earlier tiles,
+//              recounts (same operations, same result), scans inside the
+//              tile and writes offsets, positions, accumulators and tags.
+// Each disk's decision is one rounded shifted coordinate tested against
+// (0, w].  The first tile of each replica records the replica's shift (count
+// kernel) and moves the replica to its next sweep with its draws (scatter);
+// no other workgroup reads those fields, so no atomics are needed.
 struct RebinArgs {
-    Geom g;
+    Tables t;
     const float2 *pos;
     const uint32_t *start;
     const float2 *acc;
@@ -521,9 +529,8 @@ struct RebinArgs {
     uint32_t *start_out;
     float2 *acc_out;
     uint32_t *tag_out;
-    uint32_t *part;  // per-tile totals, then exclusive offsets
-    Ctl *ctl;
-    int f;
+    uint32_t *part;   // per-tile totals
+    int f;            // >= 0 explicit shift; < 0 each replica's own
     float d;
     int advance;
     int ntile;
@@ -536,139 +543,146 @@ __device__ __forceinline__ float shifted(float v, bool minus, float d)
 }
 
 template <bool SCATTER>
-__global__ void __launch_bounds__(1024) k_rebin(RebinArgs a)
+__global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
 {
     __shared__ unsigned red[16];
-    const Geom &g = a.g;
     const int tile = xcd_tile(a.per);
+    const long long cell0 = (long long)tile * kRebinTile;
+    const int r = tile < a.ntile ? (int)a.t.crep[tile] : 0;
+    const Rep &R = a.t.reps[r];
+    const Geom g = R.g;
+    Ctl *ctl = a.t.ctls + r;
     int f = a.f;
     float d = a.d;
-    if (f < 0) {   // the sweep's own draws (after the scan advanced the counter, the previous)
-        const unsigned long long s = a.ctl->sweep - ((SCATTER && a.advance) ? 1ull : 0ull);
-        f = a.ctl->draw[s & 1ull].f;
-        d = a.ctl->draw[s & 1ull].d;
+    if (f < 0) {
+        if (!SCATTER) {
+            const Ctl::Draw &dr = ctl->draw[ctl->sweep & 1ull];
+            f = dr.f;
+            d = dr.d;
+        } else {
+            f = ctl->shift_f;
+            d = ctl->shift_d;
+        }
     }
     const bool along_x = f < 2;
     const bool minus = (f == 0 || f == 2);   // +x / +y: t = v - d
     const float w = along_x ? g.wx : g.wy;
     const float sw = minus ? w : -w;         // translation into the receiving cell
+    const uint32_t *const st = a.start + R.cb;
 
-    const int c = tile * (int)blockDim.x + (int)threadIdx.x;
-    const bool valid = tile < a.ntile && c < g.C;
+    const long long cl = cell0 + (long long)threadIdx.x - R.cb;   // cell within the replica
+    const bool valid = tile < a.ntile && cl < g.C;
     uint32_t ob = 0, oe = 0, nbb = 0, nbe = 0;
     unsigned cnt = 0;
     if (valid) {
+        const int c = (int)cl;
         const int cy = c / g.mx, cx = c - cy * g.mx;
         int ncx = cx, ncy = cy;
         if (along_x) ncx = minus ? (cx == g.mx - 1 ? 0 : cx + 1) : (cx == 0 ? g.mx - 1 : cx - 1);
         else ncy = minus ? (cy == g.my - 1 ? 0 : cy + 1) : (cy == 0 ? g.my - 1 : cy - 1);
         const int nc = ncy * g.mx + ncx;
-        ob = a.start[c];
-        oe = a.start[c + 1];
-        nbb = a.start[nc];
-        nbe = a.start[nc + 1];
+        ob = st[c];
+        oe = st[c + 1];
+        nbb = st[nc];
+        nbe = st[nc + 1];
         for (uint32_t k = ob; k < oe; ++k) {
             const float2 v = a.pos[k];
-            const float t = shifted(along_x ? v.x : v.y, minus, d);
-            cnt += (t > 0.0f && t <= w) ? 1u : 0u;
+            const float tt = shifted(along_x ? v.x : v.y, minus, d);
+            cnt += (tt > 0.0f && tt <= w) ? 1u : 0u;
         }
         for (uint32_t k = nbb; k < nbe; ++k) {
             const float2 v = a.pos[k];
-            const float t = shifted(along_x ? v.x : v.y, minus, d);
-            cnt += (t > 0.0f && t <= w) ? 0u : 1u;
+            const float tt = shifted(along_x ? v.x : v.y, minus, d);
+            cnt += (tt > 0.0f && tt <= w) ? 0u : 1u;
         }
     }
+    const bool first = tile < a.ntile && cell0 == R.cb;
     if (!SCATTER) {
         const unsigned tot = block_sum_u32(cnt, red);
         if (threadIdx.x == 0 && tile < a.ntile) a.part[tile] = tot;
+        if (first && threadIdx.x == 0 && a.f < 0) {
+            ctl->shift_f = f;
+            ctl->shift_d = d;
+        }
         return;
     }
-    unsigned tot;
-    const unsigned off = block_exclusive_scan_u32(cnt, red, &tot);
-    if (valid) {
-        uint32_t o = a.part[tile] + off;
-        a.start_out[c] = o;
-        if (c == g.C - 1) a.start_out[g.C] = o + cnt;
-        if (cnt > (unsigned)g.cap) atomicOr(&a.ctl->errword, kErrCapacity);
-        const bool has_acc = a.acc != nullptr, has_tag = a.tag != nullptr;
-        for (uint32_t k = ob; k < oe; ++k) {
-            const float2 v = a.pos[k];
-            const float t = shifted(along_x ? v.x : v.y, minus, d);
-            if (t > 0.0f && t <= w) {
-                a.pos_out[o] = along_x ? make_float2(t, v.y) : make_float2(v.x, t);
-                if (has_acc) a.acc_out[o] = a.acc[k];
-                if (has_tag) a.tag_out[o] = a.tag[k];
-                ++o;
-            }
-        }
-        for (uint32_t k = nbb; k < nbe; ++k) {
-            const float2 v = a.pos[k];
-            const float t = shifted(along_x ? v.x : v.y, minus, d);
-            if (!(t > 0.0f && t <= w)) {
-                const float tt = t + sw;
-                a.pos_out[o] = along_x ? make_float2(tt, v.y) : make_float2(v.x, tt);
-                if (has_acc) a.acc_out[o] = a.acc[k];
-                if (has_tag) a.tag_out[o] = a.tag[k];
-                ++o;
-            }
-        }
-    }
-}
-
-// Exclusive scan of the per-tile totals in place (one workgroup).  It also
-// folds the sweep's sub-sweep counters and, when the shift is the sweep's own,
-// advances the sweep counter and records the next sweep's draws (the scatter
-// still finds this sweep's in the other half of the record): one thread of one
-// workgroup writes them, so no atomics are needed.
-__global__ void __launch_bounds__(1024)
-k_scan_tiles(uint32_t *part, int ntile, Ctl *ctl, long long N, uint32_t *cnt, int stride,
-             int nslots, int sub_tiles, int advance, float wx, float wy)
-{
-    __shared__ unsigned red[16];
-    __shared__ unsigned long long sh[32];
-    const int T = (int)blockDim.x;
-    const int chunk = (ntile + T - 1) / T;
-    const int b = (int)threadIdx.x * chunk;
-    const int e = min(ntile, b + chunk);
-    unsigned local = 0;
-    for (int i = b; i < e; ++i) local += part[i];
+    // offset of this tile: the replica's first disk plus its earlier tiles
+    unsigned pre = 0;
+    if (tile < a.ntile)
+        for (long long i = R.cb / kRebinTile + threadIdx.x; i < tile; i += kRebinTile) pre += a.part[i];
+    const unsigned before = block_sum_u32(pre, red);
     unsigned total;
-    unsigned run = block_exclusive_scan_u32(local, red, &total);
-    for (int i = b; i < e; ++i) {
-        const unsigned v = part[i];
-        part[i] = run;
-        run += v;
+    const unsigned off = block_exclusive_scan_u32(cnt, red, &total);
+    if (tile < a.ntile && cl < R.cpad) {
+        uint32_t o = (uint32_t)R.pb + before + off;
+        a.start_out[cell0 + threadIdx.x] = o;
+        if (cell0 + threadIdx.x == a.t.cells - 1) a.start_out[a.t.cells] = o + cnt;
+        if (valid) {
+            if (cl == g.C - 1 && (long long)(o + cnt) != R.pb + g.N) atomicOr(&ctl->errword, kErrCount);
+            if (cnt > (unsigned)g.cap) atomicOr(&ctl->errword, kErrCapacity);
+            const bool has_acc = a.acc != nullptr, has_tag = a.tag != nullptr;
+            for (uint32_t k = ob; k < oe; ++k) {
+                const float2 v = a.pos[k];
+                const float tt = shifted(along_x ? v.x : v.y, minus, d);
+                if (tt > 0.0f && tt <= w) {
+                    a.pos_out[o] = along_x ? make_float2(tt, v.y) : make_float2(v.x, tt);
+                    if (has_acc) a.acc_out[o] = a.acc[k];
+                    if (has_tag) a.tag_out[o] = a.tag[k];
+                    ++o;
+                }
+            }
+            for (uint32_t k = nbb; k < nbe; ++k) {
+                const float2 v = a.pos[k];
+                const float tt = shifted(along_x ? v.x : v.y, minus, d);
+                if (!(tt > 0.0f && tt <= w)) {
+                    const float t2 = tt + sw;
+                    a.pos_out[o] = along_x ? make_float2(t2, v.y) : make_float2(v.x, t2);
+                    if (has_acc) a.acc_out[o] = a.acc[k];
+                    if (has_tag) a.tag_out[o] = a.tag[k];
+                    ++o;
+                }
+            }
+        }
     }
-    if (threadIdx.x == 0 && (long long)total != N) atomicOr(&ctl->errword, kErrCount);
-    if (nslots > 0) fold_counters(cnt, stride, nslots, sub_tiles, 0, ctl, sh);
-    if (advance && threadIdx.x == 0) {
+    if (first && threadIdx.x == 0 && a.advance) {
         const unsigned long long s = ctl->sweep + 1ull;
-        store_draws(ctl, s, wx, wy);
+        store_draws(ctl, s, g.wx, g.wy);
         ctl->sweep = s;
     }
 }
 
 // ------------------------------------------------------ pair histogram
 // Ordered pairs (k, j != k) within reach, r^2 in k's frame as in the trial
-// moves, binned on E_b = (float)((1 + b 1e-4)^2) (Sec. 4).
-__global__ void __launch_bounds__(256)
-k_pair_hist(Geom g, const float2 *__restrict__ pos, const uint32_t *__restrict__ start,
-            Ctl *__restrict__ ctl, int Rx, int Ry, int ntile, int per)
+// moves, binned on E_b = (float)((1 + b 1e-4)^2) (Sec. 4).  Tiles of 256
+// cells, so each workgroup belongs to one replica and adds into its
+// histogram.
+__global__ void __launch_bounds__(kRebinTile)
+k_pair_hist(Tables t, const float2 *__restrict__ pos, const uint32_t *__restrict__ start,
+            int ntile, int per)
 {
     __shared__ float E[kHistBins + 1];
     __shared__ unsigned H[kHistBins];
     for (int i = threadIdx.x; i <= kHistBins; i += blockDim.x) {
-        const double r = 1.0 + (double)i * 1e-4;
-        E[i] = (float)(r * r);
+        const double rr = 1.0 + (double)i * 1e-4;
+        E[i] = (float)(rr * rr);
         if (i < kHistBins) H[i] = 0;
     }
     __syncthreads();
     const int tile = xcd_tile(per);
-    const int c = tile * (int)blockDim.x + (int)threadIdx.x;
-    if (tile < ntile && c < g.C) {
+    const long long cell0 = (long long)tile * kRebinTile;
+    const int r = tile < ntile ? (int)t.crep[tile] : 0;
+    const Rep &R = t.reps[r];
+    const Geom g = R.g;
+    const double rmax = 1.0 + kHistBins * 1e-4;
+    const int Rx = (double)g.wx >= rmax ? 1 : 2;
+    const int Ry = (double)g.wy >= rmax ? 1 : 2;
+    const uint32_t *const st = start + R.cb;
+    const long long cl = cell0 + (long long)threadIdx.x - R.cb;
+    if (tile < ntile && cl < g.C) {
+        const int c = (int)cl;
         const int cy = c / g.mx, cx = c - cy * g.mx;
         const float e0 = E[0], eN = E[kHistBins];
-        for (uint32_t k = start[c]; k < start[c + 1]; ++k) {
+        for (uint32_t k = st[c]; k < st[c + 1]; ++k) {
             const float2 pk = pos[k];
             for (int oy = -Ry; oy <= Ry; ++oy) {
                 const int ncy = (cy + oy + 2 * g.my) % g.my;
@@ -677,7 +691,7 @@ k_pair_hist(Geom g, const float2 *__restrict__ pos, const uint32_t *__restrict__
                     const int ncx = (cx + ox + 2 * g.mx) % g.mx;
                     const float tx = (float)ox * g.wx;
                     const int nc = ncy * g.mx + ncx;
-                    for (uint32_t j = start[nc]; j < start[nc + 1]; ++j) {
+                    for (uint32_t j = st[nc]; j < st[nc + 1]; ++j) {
                         if (j == k) continue;
                         const float2 v = pos[j];
                         const float qx = v.x + tx;
@@ -699,13 +713,17 @@ k_pair_hist(Geom g, const float2 *__restrict__ pos, const uint32_t *__restrict__
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kHistBins; i += blockDim.x)
-        if (H[i]) atomicAdd(&ctl->hist[i], (unsigned long long)H[i]);
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctl->hist_samples, 1ull);
+    if (tile < ntile) {
+        Ctl *ctl = t.ctls + r;
+        for (int i = threadIdx.x; i < kHistBins; i += blockDim.x)
+            if (H[i]) atomicAdd(&ctl->hist[i], (unsigned long long)H[i]);
+        if (cell0 == R.cb && threadIdx.x == 0) atomicAdd(&ctl->hist_samples, 1ull);
+    }
 }
 
-__global__ void k_hist_reset(Ctl *ctl)
+__global__ void k_hist_reset(Tables t)
 {
+    Ctl *ctl = t.ctls + blockIdx.x;
     for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) ctl->hist[i] = 0ull;
     if (threadIdx.x == 0) ctl->hist_samples = 0ull;
 }
@@ -713,12 +731,14 @@ __global__ void k_hist_reset(Ctl *ctl)
 // ------------------------------------------------------ contact fit (FP64)
 // g(R_i) from Eq. gR at the Eq. R points, unweighted least squares of a
 // degree-5 polynomial in (R - 1)/0.02 by Householder QR, P* from Eq. P.
-__global__ void __launch_bounds__(256) k_pressure_fit(Geom g, Ctl *ctl)
+__global__ void __launch_bounds__(256) k_pressure_fit(Tables t, int replica)
 {
     constexpr int NB = kHistBins, NC = 6;
     __shared__ double A[NB][NC];
     __shared__ double y[NB];
     __shared__ double v[NB];
+    const Geom g = t.reps[replica].g;
+    Ctl *ctl = t.ctls + replica;
     const unsigned long long S = ctl->hist_samples;
     const double box_x = (double)g.mx * (double)g.wx;
     const double box_y = (double)g.my * (double)g.wy;
@@ -727,10 +747,10 @@ __global__ void __launch_bounds__(256) k_pressure_fit(Geom g, Ctl *ctl)
     for (int i = threadIdx.x; i < NB; i += blockDim.x) {
         const double r0 = 1.0 + (double)i * dr;
         const double r1 = 1.0 + (double)(i + 1) * dr;
-        const double R = (2.0 / 3.0) * (r1 * r1 * r1 - r0 * r0 * r0) / (r1 * r1 - r0 * r0);
+        const double Ri = (2.0 / 3.0) * (r1 * r1 * r1 - r0 * r0 * r0) / (r1 * r1 - r0 * r0);
         const double n = (double)ctl->hist[i] / (double)(S ? S : 1ull);
-        y[i] = n / ((double)g.N * rho * 2.0 * pi * R * dr);
-        const double x = (R - 1.0) / cfit;
+        y[i] = n / ((double)g.N * rho * 2.0 * pi * Ri * dr);
+        const double x = (Ri - 1.0) / cfit;
         double xp = 1.0;
         for (int k = 0; k < NC; ++k) {
             A[i][k] = xp;
@@ -783,17 +803,23 @@ __global__ void __launch_bounds__(256) k_pressure_fit(Geom g, Ctl *ctl)
 // same pair can round to 1 - a few ulp, so the invariant allows that slack.
 constexpr float kOverlapR2 = 1.0f - 0x1p-16f;
 
-__global__ void __launch_bounds__(256)
-k_count_overlaps(Geom g, const float2 *__restrict__ pos, const uint32_t *__restrict__ start,
-                 Ctl *__restrict__ ctl, int ntile, int per)
+__global__ void __launch_bounds__(kRebinTile)
+k_count_overlaps(Tables t, const float2 *__restrict__ pos, const uint32_t *__restrict__ start,
+                 int ntile, int per)
 {
     __shared__ unsigned red[16];
     const int tile = xcd_tile(per);
-    const int c = tile * (int)blockDim.x + (int)threadIdx.x;
+    const long long cell0 = (long long)tile * kRebinTile;
+    const int r = tile < ntile ? (int)t.crep[tile] : 0;
+    const Rep &R = t.reps[r];
+    const Geom g = R.g;
+    const uint32_t *const st = start + R.cb;
+    const long long cl = cell0 + (long long)threadIdx.x - R.cb;
     unsigned bad = 0;
-    if (tile < ntile && c < g.C) {
+    if (tile < ntile && cl < g.C) {
+        const int c = (int)cl;
         const int cy = c / g.mx, cx = c - cy * g.mx;
-        for (uint32_t k = start[c]; k < start[c + 1]; ++k) {
+        for (uint32_t k = st[c]; k < st[c + 1]; ++k) {
             const float2 pk = pos[k];
             for (int oy = -1; oy <= 1; ++oy) {
                 const int ncy = (cy + oy + g.my) % g.my;
@@ -802,7 +828,7 @@ k_count_overlaps(Geom g, const float2 *__restrict__ pos, const uint32_t *__restr
                     const int ncx = (cx + ox + g.mx) % g.mx;
                     const float tx = ox < 0 ? -g.wx : (ox > 0 ? g.wx : 0.0f);
                     const int nc = ncy * g.mx + ncx;
-                    for (uint32_t j = start[nc]; j < start[nc + 1]; ++j) {
+                    for (uint32_t j = st[nc]; j < st[nc + 1]; ++j) {
                         if (j == k) continue;
                         const float2 v = pos[j];
                         const float ddx = pk.x - (v.x + tx);
@@ -814,13 +840,15 @@ k_count_overlaps(Geom g, const float2 *__restrict__ pos, const uint32_t *__restr
         }
     }
     const unsigned tot = block_sum_u32(bad, red);
-    if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&ctl->overlaps, (unsigned long long)tot);
+    if (threadIdx.x == 0 && tile < ntile && tot)
+        atomicAdd((unsigned long long *)&t.ctls[r].overlaps, (unsigned long long)tot);
 }
 
-__global__ void k_overlaps_reset(Ctl *ctl) { ctl->overlaps = 0; }
+__global__ void k_overlaps_reset(Tables t) { t.ctls[blockIdx.x].overlaps = 0; }
 
 // ------------------------------------------------------------- MSD
-// Deterministic FP64 reduction: fixed chunks per workgroup, fixed tree.
+// Deterministic FP64 reduction over one replica's disks: fixed chunks per
+// workgroup, fixed tree.
 constexpr int kMsdBlocks = kMsdBlocksMax;
 constexpr int kMsdThreads = 256;
 
@@ -861,19 +889,23 @@ k_msd_final(const double *__restrict__ part, int nb, long long N, Ctl *ctl)
 }
 
 // ------------------------------------------------------------- tuner
-// delta <- delta * clamp(a / 0.3, 0.5, 2), clamped to [1e-3, min(w)/2],
-// with a the acceptance of the window since the last update (FP64).
-__global__ void k_tune(Geom g, Ctl *ctl, int apply)
+// Per replica: delta <- delta * clamp(a / 0.3, 0.5, 2), clamped to
+// [1e-3, min(w)/2], with a the acceptance of the window since the last
+// update (FP64).
+__global__ void k_tune(Tables t, int apply)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const unsigned long long t = ctl->trials - ctl->win_trials;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= t.R) return;
+    Ctl *ctl = t.ctls + r;
+    const Geom g = t.reps[r].g;
+    const unsigned long long tr = ctl->trials - ctl->win_trials;
     const unsigned long long a = ctl->accepts - ctl->win_accepts;
-    if (apply && t > 0) {
-        const double ratio = (double)a / (double)t;
-        double r = ratio / 0.3;
-        if (r < 0.5) r = 0.5;
-        if (r > 2.0) r = 2.0;
-        double nd = (double)ctl->delta * r;
+    if (apply && tr > 0) {
+        const double ratio = (double)a / (double)tr;
+        double q = ratio / 0.3;
+        if (q < 0.5) q = 0.5;
+        if (q > 2.0) q = 2.0;
+        double nd = (double)ctl->delta * q;
         const double hi = 0.5 * (double)(g.wx < g.wy ? g.wx : g.wy);
         if (nd < 1e-3) nd = 1e-3;
         if (nd > hi) nd = hi;
@@ -890,62 +922,74 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t value, long long n)
     if (i < n) p[i] = value;
 }
 
-__global__ void k_ctl_reset(Ctl *ctl, unsigned long long sweep, unsigned int key0,
-                            unsigned int key1, float delta, float wx, float wy)
+// One workgroup per replica (first + blockIdx.x).
+__global__ void k_ctl_reset(Tables t, int first, unsigned long long sweep)
 {
+    const int r = first + (int)blockIdx.x;
+    Ctl *ctl = t.ctls + r;
+    const Rep &R = t.reps[r];
     if (threadIdx.x == 0) {
         ctl->sweep = sweep;
         ctl->trials = ctl->accepts = 0ull;
         ctl->win_trials = ctl->win_accepts = 0ull;
-        ctl->key0 = key0;
-        ctl->key1 = key1;
-        ctl->delta = delta;
+        ctl->key0 = R.key0;
+        ctl->key1 = R.key1;
+        ctl->delta = R.delta0;
         ctl->errword = 0u;
-        store_draws(ctl, sweep, wx, wy);
+        ctl->shift_f = 0;
+        ctl->shift_d = 0.0f;
         ctl->hist_samples = 0ull;
         ctl->overlaps = 0;
         ctl->msd = 0.0;
         for (int i = 0; i < 4; ++i) ctl->fit[i] = 0.0;
+        store_draws(ctl, sweep, R.g.wx, R.g.wy);
     }
     for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) ctl->hist[i] = 0ull;
 }
 
-__global__ void k_ctl_set_key0(Ctl *ctl, unsigned int key0, float wx, float wy)
+__global__ void k_ctl_set_key0(Tables t, unsigned int key0)
 {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= t.R) return;
+    Ctl *ctl = t.ctls + r;
     ctl->key0 = key0;
-    store_draws(ctl, ctl->sweep, wx, wy);
+    store_draws(ctl, ctl->sweep, t.reps[r].g.wx, t.reps[r].g.wy);
 }
-__global__ void k_ctl_set_delta(Ctl *ctl, float delta) { ctl->delta = delta; }
+
+__global__ void k_ctl_set_delta(Tables t, int first, int count, float delta)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) t.ctls[first + i].delta = delta;
+}
 
 inline int tiles_for(long long items, int block) { return (int)((items + block - 1) / block); }
-
-// Workgroup size of the sub-sweep: the requested one, reduced so that the
-// neighbour table (8 * cap float2 per lane) stays within 64 KB of LDS.
-inline int sub_block_for(const Geom &g, int block)
-{
-    const int fit = (65536 / (8 * g.cap * (int)sizeof(float2))) / 64 * 64;
-    return block < fit ? block : fit;
-}
 inline int per_xcd(int ntile) { return (ntile + 7) / 8; }
 
 }  // namespace
 
 // ================================================================ launches
-hipError_t launch_subsweep(const Geom &g, float2 *pos, const uint32_t *start, float2 *acc,
-                           uint32_t *tag, Ctl *ctl, const Work &w, int n_moves, int set,
-                           int lanes_per_cell, int block, hipStream_t st)
+// Workgroup size of the sub-sweep: the requested one, reduced so that the
+// neighbour table (8 * cap + 1 float2 per lane) stays within 64 KB of LDS;
+// always one of 64, 128, 192, 256, so it divides the active chunk.
+int subsweep_block(int cap, int block)
 {
-    if (lanes_per_cell != 1 || block > 256) return hipErrorInvalidValue;
-    block = sub_block_for(g, block);
-    const long long cells = (long long)(g.mx / 2) * (g.my / 2);
-    const int ntile = tiles_for(cells, block);
+    const int fit = (65536 / ((8 * cap + 1) * (int)sizeof(float2))) / 64 * 64;
+    return block < fit ? block : fit;
+}
+
+hipError_t launch_subsweep(const Tables &t, float2 *pos, const uint32_t *start, float2 *acc,
+                           uint32_t *tag, const Work &w, int set, int block, hipStream_t st)
+{
+    block = subsweep_block(t.cap, block);
+    if (block < 64 || block > 256 || block % 64 || kActiveChunk % block) return hipErrorInvalidValue;
+    const int ntile = tiles_for(t.active, block);
     const int per = per_xcd(ntile);
     const dim3 grid(8 * per), blk(block);
-    const size_t lds = (size_t)8 * g.cap * block * sizeof(float2);
+    const size_t lds = (size_t)(8 * t.cap + 1) * block * sizeof(float2);
 #define MPMC_SUB(CAP)                                                                          \
-    hipLaunchKernelGGL(k_subsweep<CAP>, grid, blk, lds, st, g, pos, start, acc, tag, ctl, w.cnt, \
-                       w.cnt_stride, n_moves, set, ntile, per)
-    switch (g.cap) {
+    hipLaunchKernelGGL(k_subsweep<CAP>, grid, blk, lds, st, t, pos, start, acc, tag, w.cnt,     \
+                       w.cnt_stride, set, ntile, per)
+    switch (t.cap) {
     case 4: MPMC_SUB(4); break;
     case 5: MPMC_SUB(5); break;
     case 6: MPMC_SUB(6); break;
@@ -956,82 +1000,69 @@ hipError_t launch_subsweep(const Geom &g, float2 *pos, const uint32_t *start, fl
     return hipGetLastError();
 }
 
-hipError_t launch_fold_lone(const Work &w, Ctl *ctl, hipStream_t st)
+hipError_t launch_fold_counters(const Tables &t, const Work &w, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fold_lone, dim3(1), dim3(1024), 0, st, w.cnt, w.cnt_stride, ctl);
+    hipLaunchKernelGGL(k_fold_counters, dim3(t.R), dim3(256), 0, st, t, w.cnt, w.cnt_stride);
     return hipGetLastError();
 }
 
-hipError_t launch_rebin(const Geom &g, const float2 *pos, const uint32_t *start,
+hipError_t launch_rebin(const Tables &t, const float2 *pos, const uint32_t *start,
                         const float2 *acc, const uint32_t *tag, float2 *pos_out,
                         uint32_t *start_out, float2 *acc_out, uint32_t *tag_out,
-                        const Work &w, Ctl *ctl, int f, float d, int advance, int block,
-                        int sub_block, hipStream_t st)
+                        const Work &w, int f, float d, int advance, hipStream_t st)
 {
     RebinArgs a;
-    a.g = g;
+    a.t = t;
     a.pos = pos; a.start = start; a.acc = acc; a.tag = tag;
     a.pos_out = pos_out; a.start_out = start_out; a.acc_out = acc_out; a.tag_out = tag_out;
     a.part = w.scan;
-    a.ctl = ctl;
     a.f = f; a.d = d;
     a.advance = (f < 0 && advance) ? 1 : 0;
-    a.ntile = tiles_for(g.C, block);
+    a.ntile = tiles_for(t.cells, kRebinTile);
     a.per = per_xcd(a.ntile);
-    const dim3 grid(8 * a.per), blk(block);
-    const int fold = (f < 0 && sub_block > 0) ? 4 : 0;
-    const int sub_tiles =
-        sub_block > 0 ? tiles_for((long long)(g.mx / 2) * (g.my / 2), sub_block_for(g, sub_block)) : 0;
+    const dim3 grid(8 * a.per), blk(kRebinTile);
     hipLaunchKernelGGL(k_rebin<false>, grid, blk, 0, st, a);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, w.scan, a.ntile, ctl, g.N, w.cnt,
-                       w.cnt_stride, fold, sub_tiles, (f < 0 && advance) ? 1 : 0, g.wx, g.wy);
     hipLaunchKernelGGL(k_rebin<true>, grid, blk, 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_pair_histogram(const Geom &g, const float2 *pos, const uint32_t *start,
-                                 Ctl *ctl, int reset, int block, hipStream_t st)
+hipError_t launch_pair_histogram(const Tables &t, const float2 *pos, const uint32_t *start,
+                                 int reset, hipStream_t st)
 {
-    (void)block;
-    if (reset) hipLaunchKernelGGL(k_hist_reset, dim3(1), dim3(256), 0, st, ctl);
-    const double rmax = 1.0 + kHistBins * 1e-4;
-    const int Rx = (double)g.wx >= rmax ? 1 : 2;
-    const int Ry = (double)g.wy >= rmax ? 1 : 2;
-    const int ntile = tiles_for(g.C, 256);
+    if (reset) hipLaunchKernelGGL(k_hist_reset, dim3(t.R), dim3(256), 0, st, t);
+    const int ntile = tiles_for(t.cells, kRebinTile);
     const int per = per_xcd(ntile);
-    hipLaunchKernelGGL(k_pair_hist, dim3(8 * per), dim3(256), 0, st, g, pos, start, ctl, Rx, Ry,
+    hipLaunchKernelGGL(k_pair_hist, dim3(8 * per), dim3(kRebinTile), 0, st, t, pos, start, ntile, per);
+    return hipGetLastError();
+}
+
+hipError_t launch_pressure_fit(const Tables &t, int replica, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pressure_fit, dim3(1), dim3(256), 0, st, t, replica);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_overlaps(const Tables &t, const float2 *pos, const uint32_t *start,
+                                 hipStream_t st)
+{
+    hipLaunchKernelGGL(k_overlaps_reset, dim3(t.R), dim3(1), 0, st, t);
+    const int ntile = tiles_for(t.cells, kRebinTile);
+    const int per = per_xcd(ntile);
+    hipLaunchKernelGGL(k_count_overlaps, dim3(8 * per), dim3(kRebinTile), 0, st, t, pos, start,
                        ntile, per);
     return hipGetLastError();
 }
 
-hipError_t launch_pressure_fit(const Geom &g, Ctl *ctl, hipStream_t st)
+hipError_t launch_msd(const float2 *acc, long long n, Ctl *ctl, const Work &w, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pressure_fit, dim3(1), dim3(256), 0, st, g, ctl);
+    hipLaunchKernelGGL(k_msd_partial, dim3(kMsdBlocks), dim3(kMsdThreads), 0, st, acc, n, w.f64);
+    hipLaunchKernelGGL(k_msd_final, dim3(1), dim3(kMsdThreads), 0, st, w.f64, kMsdBlocks, n, ctl);
     return hipGetLastError();
 }
 
-hipError_t launch_count_overlaps(const Geom &g, const float2 *pos, const uint32_t *start,
-                                 Ctl *ctl, int block, hipStream_t st)
+hipError_t launch_tune(const Tables &t, int apply, hipStream_t st)
 {
-    (void)block;
-    hipLaunchKernelGGL(k_overlaps_reset, dim3(1), dim3(1), 0, st, ctl);
-    const int ntile = tiles_for(g.C, 256);
-    const int per = per_xcd(ntile);
-    hipLaunchKernelGGL(k_count_overlaps, dim3(8 * per), dim3(256), 0, st, g, pos, start, ctl,
-                       ntile, per);
-    return hipGetLastError();
-}
-
-hipError_t launch_msd(const Geom &g, const float2 *acc, const Work &w, Ctl *ctl, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_msd_partial, dim3(kMsdBlocks), dim3(kMsdThreads), 0, st, acc, g.N, w.f64);
-    hipLaunchKernelGGL(k_msd_final, dim3(1), dim3(kMsdThreads), 0, st, w.f64, kMsdBlocks, g.N, ctl);
-    return hipGetLastError();
-}
-
-hipError_t launch_tune(const Geom &g, Ctl *ctl, int apply, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_tune, dim3(1), dim3(64), 0, st, g, ctl, apply);
+    hipLaunchKernelGGL(k_tune, dim3((t.R + 63) / 64), dim3(64), 0, st, t, apply);
     return hipGetLastError();
 }
 
@@ -1042,23 +1073,26 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, long long n, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_ctl_reset(const Geom &g, Ctl *ctl, unsigned long long sweep, unsigned int key0,
-                            unsigned int key1, float delta, hipStream_t st)
+hipError_t launch_ctl_reset(const Tables &t, int replica, unsigned long long sweep, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(256), 0, st, ctl, sweep, key0, key1, delta, g.wx,
-                       g.wy);
+    const int first = replica < 0 ? 0 : replica;
+    const int count = replica < 0 ? t.R : 1;
+    hipLaunchKernelGGL(k_ctl_reset, dim3(count), dim3(256), 0, st, t, first, sweep);
     return hipGetLastError();
 }
 
-hipError_t launch_ctl_set_key0(const Geom &g, Ctl *ctl, unsigned int key0, hipStream_t st)
+hipError_t launch_ctl_set_key0(const Tables &t, unsigned int key0, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ctl_set_key0, dim3(1), dim3(1), 0, st, ctl, key0, g.wx, g.wy);
+    hipLaunchKernelGGL(k_ctl_set_key0, dim3((t.R + 63) / 64), dim3(64), 0, st, t, key0);
     return hipGetLastError();
 }
 
-hipError_t launch_ctl_set_delta(Ctl *ctl, float delta, hipStream_t st)
+hipError_t launch_ctl_set_delta(const Tables &t, int replica, float delta, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ctl_set_delta, dim3(1), dim3(1), 0, st, ctl, delta);
+    const int first = replica < 0 ? 0 : replica;
+    const int count = replica < 0 ? t.R : 1;
+    hipLaunchKernelGGL(k_ctl_set_delta, dim3((count + 63) / 64), dim3(64), 0, st, t, first, count,
+                       delta);
     return hipGetLastError();
 }
 

@@ -53,6 +53,41 @@ def required_bytes(cfg: SystemConfig) -> dict:
     return {name: getattr(s, name) for name, _ in L.BufferSizes._fields_}
 
 
+def batch_required_bytes(cfgs) -> dict:
+    arr = (L.Params * len(cfgs))(*[c.to_c() for c in cfgs])
+    s = L.BufferSizes()
+    L.check(L.load().mpmc_batch_required_bytes(arr, len(cfgs), C.byref(s)))
+    return {name: getattr(s, name) for name, _ in L.BufferSizes._fields_}
+
+
+class _Buffers:
+    """Caller-owned device buffers for one handle (torch tensors)."""
+
+    def __init__(self, sizes: dict, device):
+        import torch
+
+        def buf(n):
+            return torch.empty(max(int(n), 256), dtype=torch.uint8, device=device)
+
+        self.t = {k: [buf(sizes[k]), buf(sizes[k])] for k in ("pos", "start")}
+        self.t["acc"] = [buf(sizes["acc"]), buf(sizes["acc"])] if sizes["acc"] else None
+        self.t["tag"] = [buf(sizes["tag"]), buf(sizes["tag"])] if sizes["tag"] else None
+        self.work = buf(sizes["work"])
+        self.ctl = buf(sizes["ctl"])
+        b = L.Buffers()
+        for i in range(2):
+            b.pos[i] = self.t["pos"][i].data_ptr()
+            b.start[i] = self.t["start"][i].data_ptr()
+            b.acc[i] = self.t["acc"][i].data_ptr() if self.t["acc"] else None
+            b.tag[i] = self.t["tag"][i].data_ptr() if self.t["tag"] else None
+        b.work = self.work.data_ptr()
+        b.ctl = self.ctl.data_ptr()
+        self.c = b
+
+    def __getitem__(self, k):
+        return self.t[k]
+
+
 class HardDiskSystem:
     """One system of hard disks resident on a GPU."""
 
@@ -69,27 +104,11 @@ class HardDiskSystem:
         self.wx = np.float32(self.geometry["w_x"])
         self.wy = np.float32(self.geometry["w_y"])
         self.cap = self.geometry["capacity"]
-
-        def buf(n):
-            return torch.empty(max(int(n), 256), dtype=torch.uint8, device=self.device)
-
-        self._bufs = {k: [buf(sizes[k]), buf(sizes[k])] for k in ("pos", "start")}
-        self._bufs["acc"] = [buf(sizes["acc"]), buf(sizes["acc"])] if sizes["acc"] else None
-        self._bufs["tag"] = [buf(sizes["tag"]), buf(sizes["tag"])] if sizes["tag"] else None
-        self._work = buf(sizes["work"])
-        self._ctl = buf(sizes["ctl"])
-        b = L.Buffers()
-        for i in range(2):
-            b.pos[i] = self._bufs["pos"][i].data_ptr()
-            b.start[i] = self._bufs["start"][i].data_ptr()
-            b.acc[i] = self._bufs["acc"][i].data_ptr() if self._bufs["acc"] else None
-            b.tag[i] = self._bufs["tag"][i].data_ptr() if self._bufs["tag"] else None
-        b.work = self._work.data_ptr()
-        b.ctl = self._ctl.data_ptr()
+        self._bufs = _Buffers(sizes, self.device)
         self.stream = torch.cuda.Stream(device=self.device)
         torch.cuda.synchronize(self.device)
         h = C.c_void_p()
-        L.check(self.lib.mpmc_init_system(C.byref(cfg.to_c()), C.byref(b),
+        L.check(self.lib.mpmc_init_system(C.byref(cfg.to_c()), C.byref(self._bufs.c),
                                           C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self._h = h
         self.block = 256
@@ -206,3 +225,112 @@ class HardDiskSystem:
     @property
     def box(self):
         return self.mx * np.float64(self.wx), self.my * np.float64(self.wy)
+
+
+class HardDiskBatch:
+    """Independent hard-disk systems of uneven N and packing fraction sharing
+    one handle: every kernel launch advances all of them, and replica r
+    evolves exactly as a HardDiskSystem built from cfgs[r] would."""
+
+    def __init__(self, cfgs, device: str = "cuda:0"):
+        import torch
+        self.cfgs = list(cfgs)
+        self.lib = L.load()
+        self.device = torch.device(device)
+        sizes = batch_required_bytes(self.cfgs)
+        self._bufs = _Buffers(sizes, self.device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        torch.cuda.synchronize(self.device)
+        arr = (L.Params * len(self.cfgs))(*[c.to_c() for c in self.cfgs])
+        h = C.c_void_p()
+        L.check(self.lib.mpmc_batch_init(arr, len(self.cfgs), C.byref(self._bufs.c),
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self.block = 256
+        self.R = len(self.cfgs)
+        self.geometries = []
+        for r in range(self.R):
+            g = L.Geometry()
+            L.check(self.lib.mpmc_replica_geometry(h, r, C.byref(g)))
+            self.geometries.append({name: getattr(g, name) for name, _ in L.Geometry._fields_})
+        self.N = sum(int(g["n_particles"]) for g in self.geometries)
+
+    close = HardDiskSystem.close
+    __del__ = HardDiskSystem.__del__
+    subsweep = HardDiskSystem.subsweep
+    shift_and_rebin = HardDiskSystem.shift_and_rebin
+    tune = HardDiskSystem.tune
+    set_launch = HardDiskSystem.set_launch
+    autotune = HardDiskSystem.autotune
+    synchronize = HardDiskSystem.synchronize
+    set_delta = HardDiskSystem.set_delta
+    reset_acc = HardDiskSystem.reset_acc
+    count_overlaps = HardDiskSystem.count_overlaps
+    counters = HardDiskSystem.counters
+    pair_histogram = HardDiskSystem.pair_histogram
+
+    def sweep(self, n: int = 1, seed: int | None = None):
+        s = self.cfgs[0].seed if seed is None else int(seed)
+        L.check(self.lib.mpmc_sweep(self._h, int(n), s))
+        if seed is not None:
+            for c in self.cfgs:
+                c.seed = int(seed)
+
+    def _cells(self, r):
+        g = self.geometries[r]
+        return g["cells_x"] * g["cells_y"]
+
+    def get_state(self, r: int):
+        n = int(self.geometries[r]["n_particles"])
+        xy = np.empty((n, 2), np.float32)
+        start = np.empty(self._cells(r) + 1, np.uint32)
+        sw = C.c_uint64()
+        L.check(self.lib.mpmc_replica_get_state(self._h, int(r), xy.ctypes.data if n else None,
+                                                start.ctypes.data, C.byref(sw)))
+        return xy, start, int(sw.value)
+
+    def set_state(self, r: int, xy, start, sweep: int = 0, tags=None):
+        xy = np.ascontiguousarray(xy, np.float32)
+        start = np.ascontiguousarray(start, np.uint32)
+        tp = None
+        if tags is not None:
+            tags = np.ascontiguousarray(tags, np.uint32)
+            tp = tags.ctypes.data
+        L.check(self.lib.mpmc_replica_set_state(self._h, int(r), xy.ctypes.data if xy.size else None,
+                                                start.ctypes.data, int(sweep), tp))
+
+    def aux(self, r: int):
+        n = int(self.geometries[r]["n_particles"])
+        acc = np.zeros((n, 2), np.float32) if self._bufs["acc"] else None
+        tag = np.zeros(n, np.uint32) if self._bufs["tag"] else None
+        L.check(self.lib.mpmc_replica_get_aux(self._h, int(r),
+                                              acc.ctypes.data if acc is not None and n else None,
+                                              tag.ctypes.data if tag is not None and n else None))
+        return acc, tag
+
+    def msd(self, r: int) -> float:
+        v = C.c_double()
+        L.check(self.lib.mpmc_replica_msd(self._h, int(r), C.byref(v)))
+        return v.value
+
+    def replica_counters(self, r: int):
+        t, a = C.c_uint64(), C.c_uint64()
+        L.check(self.lib.mpmc_replica_get_counters(self._h, int(r), C.byref(t), C.byref(a)))
+        return int(t.value), int(a.value)
+
+    def delta(self, r: int) -> np.float32:
+        d = C.c_float()
+        L.check(self.lib.mpmc_replica_get_delta(self._h, int(r), C.byref(d)))
+        return np.float32(d.value)
+
+    def set_replica_delta(self, r: int, delta: float):
+        L.check(self.lib.mpmc_replica_set_delta(self._h, int(r), float(np.float32(delta))))
+
+    def pressure_from_contact(self, r: int):
+        p, g0 = C.c_double(), C.c_double()
+        hist = np.zeros(L.HIST_BINS, np.uint64)
+        ns = C.c_uint64()
+        L.check(self.lib.mpmc_replica_pressure_from_contact(
+            self._h, int(r), C.byref(p), C.byref(g0), hist.ctypes.data_as(C.POINTER(C.c_uint64)),
+            C.byref(ns)))
+        return p.value, g0.value, hist, int(ns.value)

@@ -1,0 +1,45 @@
+"""Seeded synthetic workloads (inputs only: no step of the method lives here).
+
+The paper's measurements use synthetic hard-disk systems started from
+triangular lattices (Sec. 4, Tables 2 and 3); these recipes produce the
+parameters of such systems.  Both the HIP path's tests and the oracle's side
+of them take their inputs from here.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def large(phi: float = 0.70) -> dict:
+    """1024 x 1024 lattice (N = 1,048,576) with cells narrower than sqrt(2)
+    (capacity 4, about two disks per cell)."""
+    return dict(nx=1024, ny=1024, phi=phi, w_min=1.0, w_max=math.sqrt(2.0))
+
+
+def medium() -> dict:
+    """256 x 256 lattice (N = 65,536) at phi = 0.70, cells of width >= 1."""
+    return dict(nx=256, ny=256, phi=0.70, w_min=1.0, w_max=0.0)
+
+
+def small() -> dict:
+    """64 x 64 lattice (N = 4096) at phi = 0.60, cells of width >= 1."""
+    return dict(nx=64, ny=64, phi=0.60, w_min=1.0, w_max=0.0)
+
+
+def replicas(R: int = 64, seed: int = 1, n_min: int = 64, n_max: int = 512,
+             phi_lo: float = 0.65, phi_hi: float = 0.73) -> list[dict]:
+    """R square lattices n_r x n_r, N_r = n_r^2 log-uniform between n_min^2 and
+    n_max^2 (n_r even), packing fractions evenly spaced over [phi_lo, phi_hi],
+    cells of width >= 1.  Sizes come from numpy's PCG64 seeded with `seed`."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = rng.random(R)
+    half_lo, half_hi = n_min // 2, n_max // 2
+    out = []
+    for r in range(R):
+        k = int(round(half_lo * (half_hi / half_lo) ** float(u[r])))
+        n = 2 * min(max(k, half_lo), half_hi)
+        phi = phi_lo + (phi_hi - phi_lo) * (r / (R - 1) if R > 1 else 0.0)
+        out.append(dict(nx=n, ny=n, phi=phi, w_min=1.0, w_max=0.0))
+    return out

@@ -1,0 +1,256 @@
+"""Batched form: independent replicas of uneven N, packing fraction, cell
+width, delta and n_M in one handle.  Replica r must evolve bit for bit as the
+oracle's single system with the same parameters and key (seed, r), and as a
+single-system GPU run.  Needs an MI355X."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import OracleSystem
+from oracle import estimator as E
+
+pytestmark = pytest.mark.gpu
+
+FLAGS = 3
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1211_1646_amd as pkg
+    pkg.load()
+    return pkg
+
+
+# mixed capacities 4..7, grids, deltas and n_M (all small enough for the oracle)
+MIXED = [
+    dict(nx=20, ny=20, phi=0.70, w_max=math.sqrt(2.0), delta=0.15, n_moves=4),
+    dict(nx=32, ny=32, phi=0.60, w_max=0.0, delta=0.10, n_moves=1),
+    dict(nx=20, ny=20, phi=0.72, w_max=1.932, delta=0.12, n_moves=6),
+    dict(nx=16, ny=18, phi=0.45, w_max=1.664, delta=0.30, n_moves=3),
+    dict(nx=30, ny=30, phi=0.50, w_max=1.8, delta=0.20, n_moves=0),
+    dict(nx=48, ny=46, phi=0.68, w_max=0.0, delta=0.08, n_moves=9),
+]
+
+
+def configs(pkg, specs, seed=1, flags=FLAGS):
+    return [pkg.SystemConfig(lattice_nx=s["nx"], lattice_ny=s["ny"], phi=s["phi"], w_min=1.0,
+                             w_max=s.get("w_max", 0.0), delta=s.get("delta", 0.1),
+                             n_moves=s.get("n_moves", 4), seed=seed, replica=r, flags=flags)
+            for r, s in enumerate(specs)]
+
+
+def oracles(specs, seed=1, flags=FLAGS):
+    return [OracleSystem.lattice(s["nx"], s["ny"], s["phi"], w_min=1.0, w_max=s.get("w_max", 0.0),
+                                 delta=s.get("delta", 0.1), n_moves=s.get("n_moves", 4), seed=seed,
+                                 replica=r, flags=flags)
+            for r, s in enumerate(specs)]
+
+
+def assert_replica(B, r, O, what=""):
+    gx, gs, gsw = B.get_state(r)
+    ox, os_, osw = O.get_state()
+    assert gsw == osw, (what, r, gsw, osw)
+    assert np.array_equal(gs, os_), (what, r, "cell lists differ", int(np.argmax(gs != os_)))
+    bad = np.nonzero(np.any(gx.view(np.uint32) != ox.view(np.uint32), axis=1))[0]
+    assert bad.size == 0, (what, r, "positions differ", bad[:5])
+    ga, gt = B.aux(r)
+    oa, ot = O.aux()
+    if gt is not None:
+        assert np.array_equal(gt, ot), (what, r, "tags differ")
+    if ga is not None:
+        assert np.array_equal(ga.view(np.uint32), oa.view(np.uint32)), (what, r, "accumulators differ")
+    assert B.replica_counters(r) == O.counters(), (what, r, B.replica_counters(r), O.counters())
+
+
+def test_batch_initial_state_and_geometry(gpu):
+    B = gpu.HardDiskBatch(configs(gpu, MIXED))
+    Os = oracles(MIXED)
+    for r, O in enumerate(Os):
+        g = B.geometries[r]
+        assert (g["cells_x"], g["cells_y"]) == (O.mx, O.my)
+        assert np.float32(g["w_x"]) == O.wx and np.float32(g["w_y"]) == O.wy
+        assert_replica(B, r, O, "init")
+    assert B.count_overlaps() == 0
+
+
+def test_batch_sweeps_match_oracle_per_replica(gpu):
+    """Graph path (16) and eager sweeps (5): every replica bit-exact."""
+    B = gpu.HardDiskBatch(configs(gpu, MIXED))
+    Os = oracles(MIXED)
+    B.sweep(16)
+    B.sweep(5)
+    for r, O in enumerate(Os):
+        O.sweep(21)
+        assert_replica(B, r, O, "21 sweeps")
+    t = sum(O.counters()[0] for O in Os)
+    a = sum(O.counters()[1] for O in Os)
+    assert B.counters() == (t, a)
+    assert B.count_overlaps() == 0
+
+
+def test_batch_subsweeps_and_explicit_shifts(gpu):
+    B = gpu.HardDiskBatch(configs(gpu, MIXED))
+    Os = oracles(MIXED)
+    B.sweep(3)
+    for O in Os:
+        O.sweep(3)
+    for Q in (1, 3, 0, 2):
+        log("  batch subsweep Q=%d" % Q)
+        B.subsweep(Q)
+        for O in Os:
+            O.subsweep(Q)
+    wmin = min(min(O.wx, O.wy) for O in Os)
+    for f, d in ((0, np.float32(0.3)), (3, np.float32(0.5) * wmin), (1, np.float32(0.0))):
+        log("  batch shift f=%d d=%r" % (f, float(d)))
+        B.shift_and_rebin(f, d)
+        for O in Os:
+            O.shift(f, d)
+    for r, O in enumerate(Os):
+        assert_replica(B, r, O, "subsweeps + shifts")
+
+
+@pytest.mark.parametrize("block", [64, 192])
+def test_batch_launch_shape_does_not_change_results(gpu, block):
+    B = gpu.HardDiskBatch(configs(gpu, MIXED, seed=7))
+    Os = oracles(MIXED, seed=7)
+    B.set_launch(1, block)
+    B.sweep(18)
+    for r, O in enumerate(Os):
+        O.sweep(18)
+        assert_replica(B, r, O, "block %d" % block)
+
+
+def test_batch_seed_delta_and_tuner(gpu):
+    B = gpu.HardDiskBatch(configs(gpu, MIXED))
+    Os = oracles(MIXED)
+    B.sweep(4, seed=33)
+    for O in Os:
+        O.set_seed(33)
+        O.sweep(4)
+    B.set_replica_delta(2, 0.05)
+    Os[2].set_delta(np.float32(0.05))
+    window, n = 5, 4
+    B.tune(window, n)
+    for O in Os:
+        for _ in range(n):
+            t0, a0 = O.counters()
+            O.sweep(window)
+            t1, a1 = O.counters()
+            O.set_delta(oracle.tuned_delta(O.delta, t1 - t0, a1 - a0, O.wx, O.wy))
+    for r, O in enumerate(Os):
+        assert B.delta(r) == O.delta, (r, B.delta(r), O.delta)
+        assert_replica(B, r, O, "tuned")
+
+
+def test_batch_pressure_and_msd_per_replica(gpu):
+    specs = [MIXED[0], MIXED[1], MIXED[2], MIXED[5]]
+    B = gpu.HardDiskBatch(configs(gpu, specs))
+    Os = oracles(specs)
+    hist_o = [np.zeros(200, np.uint64) for _ in Os]
+    B.pair_histogram(reset=True)
+    for r, O in enumerate(Os):
+        hist_o[r] += O.pair_histogram()
+    for k in range(3):
+        B.sweep(4)
+        B.pair_histogram()
+        for r, O in enumerate(Os):
+            O.sweep(4)
+            hist_o[r] += O.pair_histogram()
+    for r, O in enumerate(Os):
+        p, g0, hist_g, ns = B.pressure_from_contact(r)
+        assert ns == 4
+        assert np.array_equal(hist_g, hist_o[r]), r
+        Lx, Ly = O.box
+        p_ref, g_ref = E.pressure_from_histogram(hist_o[r], 4, O.N, O.N / (Lx * Ly))
+        assert abs(p - p_ref) <= 1e-9 * abs(p_ref), (r, p, p_ref)
+        acc, _ = O.aux()
+        ref = float(np.mean((acc.astype(np.float64) ** 2).sum(axis=1)))
+        assert abs(B.msd(r) - ref) <= 1e-12 * ref, r
+
+
+def test_batch_grid_replicas_loaded_one_by_one(gpu):
+    """Replicas built as explicit grids stay unloaded until their state is set;
+    a bad state for one replica is rejected without touching the others."""
+    from paper_1211_1646_amd import _lib as L
+    src = oracles(MIXED[:3])
+    for O in src:
+        O.sweep(6)
+    cfgs = []
+    for r, O in enumerate(src):
+        xy, _, _ = O.get_state()
+        cfgs.append(gpu.SystemConfig(cells_x=O.mx, cells_y=O.my, cell_w_x=float(O.wx),
+                                     cell_w_y=float(O.wy), n_particles=len(xy),
+                                     delta=float(O.delta), n_moves=MIXED[r]["n_moves"], seed=1,
+                                     replica=r, flags=FLAGS))
+    B = gpu.HardDiskBatch(cfgs)
+    with pytest.raises(L.MPMCError) as e:
+        B.sweep(1)
+    assert e.value.status == L.MPMC_ESTATE
+    fresh = []
+    for r, O in enumerate(src):
+        xy, start, sweep = O.get_state()
+        _, tag = O.aux()
+        if r == 1:   # first an overlapping copy: rejected
+            bad = xy.copy()
+            k0 = int(np.argmax(np.diff(start) >= 2))
+            bad[start[k0] + 1] = bad[start[k0]]
+            with pytest.raises(L.MPMCError) as e:
+                B.set_state(r, bad, start, sweep, tag)
+            assert e.value.status == L.MPMC_EOVERLAP
+        B.set_state(r, xy, start, sweep, tag)
+        O2 = OracleSystem.grid(O.mx, O.my, O.wx, O.wy, delta=O.delta,
+                               n_moves=MIXED[r]["n_moves"], seed=1, replica=r, flags=FLAGS)
+        O2.set_state(xy, start, sweep, tag)
+        fresh.append(O2)
+    B.sweep(17)
+    for r, O in enumerate(fresh):
+        O.sweep(17)
+        assert_replica(B, r, O, "grid batch")
+
+
+def test_replica_recipe_batch_equals_sequential_single_runs(gpu):
+    """The 64-replica recipe (N_r log-uniform in [64^2, 512^2], phi over
+    [0.65, 0.73]): the batch and 64 separate single-system runs agree bit for
+    bit after 32 sweeps; the overlap invariant holds everywhere."""
+    from paper_1211_1646_amd import workloads as W
+    specs = W.replicas(64, seed=1)
+    cfgs = configs(gpu, specs, flags=0)
+    B = gpu.HardDiskBatch(cfgs)
+    log("  batch of %d replicas, N = %d" % (B.R, B.N))
+    B.autotune(16)   # four candidates x (16 + 16) sweeps of the chain
+    B.sweep(32)
+    assert B.count_overlaps() == 0
+    for r, cfg in enumerate(cfgs):
+        S = gpu.HardDiskSystem(cfg)
+        S.sweep(4 * 32 + 32)
+        bx, bs, bsw = B.get_state(r)
+        sx, ss, ssw = S.get_state()
+        assert bsw == ssw
+        assert np.array_equal(bs, ss), r
+        assert np.array_equal(bx.view(np.uint32), sx.view(np.uint32)), r
+        assert B.replica_counters(r) == S.counters(), r
+        S.close()
+
+
+def test_replica_recipe_small_replicas_match_oracle(gpu):
+    """Replicas of the recipe that the oracle runs in seconds: bit-exact."""
+    from paper_1211_1646_amd import workloads as W
+    specs = [s for s in W.replicas(64, seed=1) if s["nx"] <= 100][:6]
+    assert len(specs) >= 3
+    B = gpu.HardDiskBatch(configs(gpu, specs))
+    Os = oracles(specs)
+    B.sweep(20)
+    for r, O in enumerate(Os):
+        O.sweep(20)
+        assert_replica(B, r, O, "recipe")
