@@ -271,6 +271,57 @@ mpmc_status mpmc_set_launch(mpmc_handle h, int32_t lanes_per_cell, int32_t block
 mpmc_status mpmc_autotune(mpmc_handle h, int32_t sweeps, int32_t *block_out,
                           double *us_per_sweep_out);
 
+/* Every replica's counters since its init or set_state, current delta and,
+ * if msd is not NULL, mean |acc|^2 over its disks (FP64, fixed order), each
+ * an array of R entries (sync).  Any pointer may be NULL. */
+mpmc_status mpmc_batch_stats(mpmc_handle h, uint64_t *trials, uint64_t *accepts, float *delta,
+                             double *msd);
+
+/* ---- Learned move-size controller --------------------------------------
+ * Not part of the paper's method: it sets the free parameter delta (Sec.
+ * 3.3) between equilibration windows only, so the chain sampled afterwards
+ * with delta frozen is the paper's.  The network is a 3 -> 32 -> 32 -> 1
+ * perceptron with tanh hidden layers, FP32, MPMC_MLP_PARAMS parameters in
+ * one device vector laid out row-major as W1[32][3] b1[32] W2[32][32] b2[32]
+ * W3[1][32] b3[1].  Inputs of a replica: 20 (phi - 0.7), N/cells - 1.5 and
+ * 4 (a - 0.3), with a the acceptance of the last window; output y gives
+ * delta = 0.1 exp(y) clamped to [1e-3, min(w)/2].  All pointers below are
+ * device pointers; the calls only enqueue work (async). */
+#define MPMC_MLP_PARAMS 1217
+
+/* Controller in the chain (async): n_windows times, run window_sweeps
+ * sweeps of every replica, then set each replica's delta from the network
+ * W (device, MPMC_MLP_PARAMS floats) and that window's acceptance. */
+mpmc_status mpmc_control(mpmc_handle h, const float *W, int32_t window_sweeps, int32_t n_windows);
+
+/* Bytes of device workspace for mpmc_mlp_backward / mpmc_mlp_mse on n
+ * samples (host only). */
+mpmc_status mpmc_mlp_work_bytes(int32_t n, size_t *bytes);
+
+/* Y[i] = net(X[i][0..2]) for n samples; X row-major [n][3].  cache, if not
+ * NULL, receives the hidden activations [64][n] (feature-major) that
+ * mpmc_mlp_backward needs. */
+mpmc_status mpmc_mlp_forward(const float *W, const float *X, int32_t n, float *Y, float *cache,
+                             void *stream);
+
+/* Gradients of sum_i dY[i] * Y[i] with respect to the parameters (dW,
+ * MPMC_MLP_PARAMS floats, overwritten) and, if dX is not NULL, the inputs
+ * (dX [n][3]).  Per-workgroup partial sums are reduced in a fixed order, so
+ * results do not vary from run to run.  work: mpmc_mlp_work_bytes(n). */
+mpmc_status mpmc_mlp_backward(const float *W, const float *X, const float *cache, const float *dY,
+                              int32_t n, float *dW, float *dX, void *work, void *stream);
+
+/* Squared-error loss 1/(2n) sum (Y - T)^2 into *loss (device FP64) and its
+ * gradient dY = (Y - T)/n.  work: mpmc_mlp_work_bytes(n). */
+mpmc_status mpmc_mlp_mse(const float *Y, const float *T, int32_t n, float *dY, double *loss,
+                         void *work, void *stream);
+
+/* One Adam step (Kingma and Ba, ICLR 2015, Alg. 1) on n_params parameters:
+ * m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2, W <- W - lr m_hat /
+ * (sqrt(v_hat) + eps) with bias corrections 1/(1 - b^step), step >= 1. */
+mpmc_status mpmc_adam_step(float *W, float *m, float *v, const float *dW, int32_t n_params,
+                           float lr, float b1, float b2, float eps, int32_t step, void *stream);
+
 /* Wait for all work enqueued by this handle; reports MPMC_EDEVICE if a kernel
  * set the error word. */
 mpmc_status mpmc_synchronize(mpmc_handle h);

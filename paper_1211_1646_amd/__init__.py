@@ -8,7 +8,8 @@ rebuild of the cell lists (Alg. 4), pressure from the contact value of g(r)
 marshals arguments.
 """
 from ._lib import FLAG_ACC, FLAG_TAG, HIST_BINS, MPMCError, load  # noqa: F401
-from .system import HardDiskSystem, SystemConfig, geometry, required_bytes  # noqa: F401
+from .system import (HardDiskBatch, HardDiskSystem, SystemConfig, batch_required_bytes,  # noqa: F401
+                     geometry, required_bytes)
 
-__all__ = ["HardDiskSystem", "SystemConfig", "geometry", "required_bytes", "MPMCError",
-           "FLAG_ACC", "FLAG_TAG", "HIST_BINS", "load"]
+__all__ = ["HardDiskSystem", "HardDiskBatch", "SystemConfig", "geometry", "required_bytes",
+           "batch_required_bytes", "MPMCError", "FLAG_ACC", "FLAG_TAG", "HIST_BINS", "load"]

@@ -21,6 +21,7 @@ MPMC_ESTATE = -6
 FLAG_ACC = 1
 FLAG_TAG = 2
 HIST_BINS = 200
+MLP_PARAMS = 1217
 
 STATUS_NAMES = {0: "MPMC_OK", -1: "MPMC_EINVAL", -2: "MPMC_EGEOM", -3: "MPMC_EOVERLAP",
                 -4: "MPMC_EHIP", -5: "MPMC_EDEVICE", -6: "MPMC_ESTATE"}
@@ -101,6 +102,18 @@ _SIGNATURES = {
                                               C.POINTER(C.c_uint64)]),
     "mpmc_replica_set_delta": (C.c_int32, [_H, C.c_int32, C.c_float]),
     "mpmc_replica_get_delta": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_float)]),
+    "mpmc_batch_stats": (C.c_int32, [_H, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mpmc_control": (C.c_int32, [_H, C.c_void_p, C.c_int32, C.c_int32]),
+    "mpmc_mlp_work_bytes": (C.c_int32, [C.c_int32, C.POINTER(C.c_size_t)]),
+    "mpmc_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]),
+    "mpmc_mlp_backward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mpmc_mlp_mse": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p]),
+    "mpmc_adam_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                   C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32,
+                                   C.c_void_p]),
     "mpmc_destroy": (None, [_H]),
     "mpmc_last_error": (C.c_char_p, []),
 }

@@ -16,7 +16,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmpmc.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("mpmc_kernels.hip", "mpmc_api.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("mpmc_kernels.hip", "mpmc_mlp.hip",
+                                                       "mpmc_api.cpp")]
 ARCH = os.environ.get("MPMC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -991,6 +991,89 @@ mpmc_status mpmc_autotune(mpmc_handle h, int32_t sweeps, int32_t *block_out,
     return read_ctl(h);
 }
 
+mpmc_status mpmc_batch_stats(mpmc_handle h, uint64_t *trials, uint64_t *accepts, float *delta,
+                             double *msd)
+{
+    MPMC_NEED_STATE(h);
+    if (msd) {
+        if (!h->acc[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_ACC");
+        MPMC_HIP(mpmc::launch_msd_all(h->t, h->acc[h->cur], h->st));
+    }
+    const mpmc_status s = read_ctl(h);
+    if (s) return s;
+    for (int r = 0; r < h->R(); ++r) {
+        const Ctl &c = h->ctl_host[(size_t)r];
+        if (trials) trials[r] = c.trials;
+        if (accepts) accepts[r] = c.accepts;
+        if (delta) delta[r] = c.delta;
+        if (msd) msd[r] = c.msd;
+    }
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_control(mpmc_handle h, const float *W, int32_t window_sweeps, int32_t n_windows)
+{
+    if (!h || !W || window_sweeps < 1 || n_windows < 0)
+        return fail(MPMC_EINVAL, "bad controller arguments");
+    MPMC_NEED_STATE(h);
+    MPMC_HIP(mpmc::launch_fold_counters(h->t, h->work, h->st));
+    MPMC_HIP(mpmc::launch_control(h->t, W, 0, h->st));   // open the first window
+    for (int w = 0; w < n_windows; ++w) {
+        const mpmc_status s = run_sweeps(h, window_sweeps);
+        if (s) return s;
+        MPMC_HIP(mpmc::launch_fold_counters(h->t, h->work, h->st));
+        MPMC_HIP(mpmc::launch_control(h->t, W, 1, h->st));
+    }
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_mlp_work_bytes(int32_t n, size_t *bytes)
+{
+    if (n < 0 || !bytes) return fail(MPMC_EINVAL, "bad sample count");
+    *bytes = mpmc::mlp_work_bytes(n);
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_mlp_forward(const float *W, const float *X, int32_t n, float *Y, float *cache,
+                             void *stream)
+{
+    if (n < 0 || !W || (n > 0 && (!X || !Y))) return fail(MPMC_EINVAL, "bad forward arguments");
+    MPMC_HIP(mpmc::launch_mlp_forward(W, X, n, Y, cache, (hipStream_t)stream));
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_mlp_backward(const float *W, const float *X, const float *cache, const float *dY,
+                              int32_t n, float *dW, float *dX, void *work, void *stream)
+{
+    if (n < 0 || !W || !dW || !work || (n > 0 && (!X || !cache || !dY)))
+        return fail(MPMC_EINVAL, "bad backward arguments");
+    MPMC_HIP(mpmc::launch_mlp_backward(W, X, cache, dY, n, dW, dX, work, (hipStream_t)stream));
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_mlp_mse(const float *Y, const float *T, int32_t n, float *dY, double *loss,
+                         void *work, void *stream)
+{
+    if (n < 0 || !loss || !work || (n > 0 && (!Y || !T || !dY)))
+        return fail(MPMC_EINVAL, "bad loss arguments");
+    MPMC_HIP(mpmc::launch_mse(Y, T, n, dY, loss, work, (hipStream_t)stream));
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_adam_step(float *W, float *m, float *v, const float *dW, int32_t n_params,
+                           float lr, float b1, float b2, float eps, int32_t step, void *stream)
+{
+    if (n_params < 0 || step < 1 || (n_params > 0 && (!W || !m || !v || !dW)))
+        return fail(MPMC_EINVAL, "bad Adam arguments");
+    if (!(b1 >= 0.0f && b1 < 1.0f && b2 >= 0.0f && b2 < 1.0f && eps > 0.0f && lr >= 0.0f))
+        return fail(MPMC_EINVAL, "Adam hyper-parameters out of range");
+    const double c1 = 1.0 / (1.0 - std::pow((double)b1, (double)step));
+    const double c2 = 1.0 / (1.0 - std::pow((double)b2, (double)step));
+    MPMC_HIP(mpmc::launch_adam(W, m, v, dW, n_params, lr, b1, b2, eps, (float)c1, (float)c2,
+                               (hipStream_t)stream));
+    return MPMC_OK;
+}
+
 mpmc_status mpmc_synchronize(mpmc_handle h)
 {
     if (!h) return fail(MPMC_EINVAL, "null handle");

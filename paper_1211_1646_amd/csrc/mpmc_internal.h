@@ -22,6 +22,7 @@ constexpr int kRebinTile = 256;           // cells per rebin workgroup (one per 
 constexpr int kActiveChunk = 768;         // active-slot granularity (lcm of 64, 128, 192, 256)
 constexpr int kGranule = 64;              // counter partials: one per 64 active slots
 constexpr int kMsdBlocksMax = 512;
+constexpr int kMlpParams = 1217;          // 3 -> 32 -> 32 -> 1 network
 
 // Per-replica control block: everything a captured sweep graph reads or
 // writes that changes between launches lives here, not in kernel arguments.
@@ -133,5 +134,22 @@ hipError_t launch_ctl_set_key0(const Tables &t, unsigned int key0, hipStream_t s
 hipError_t launch_ctl_set_delta(const Tables &t, int replica, float delta, hipStream_t st);
 // Workgroup size the sub-sweep actually uses for a requested one.
 int subsweep_block(int cap, int block);
+// Mean |acc|^2 of every replica into its control block (one workgroup each).
+hipError_t launch_msd_all(const Tables &t, const float2 *acc, hipStream_t st);
+
+// ---- move-size network (defined in mpmc_mlp.hip) ----
+size_t mlp_work_bytes(int n);
+hipError_t launch_mlp_forward(const float *W, const float *X, int n, float *Y, float *cache,
+                              hipStream_t st);
+hipError_t launch_mlp_backward(const float *W, const float *X, const float *cache,
+                               const float *dY, int n, float *dW, float *dX, void *work,
+                               hipStream_t st);
+hipError_t launch_mse(const float *Y, const float *T, int n, float *dY, double *loss, void *work,
+                      hipStream_t st);
+hipError_t launch_adam(float *W, float *m, float *v, const float *g, int n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, hipStream_t st);
+// Controller step of every replica from its window counters (apply == 0
+// only opens a window); call after launch_fold_counters.
+hipError_t launch_control(const Tables &t, const float *W, int apply, hipStream_t st);
 
 }  // namespace mpmc

@@ -888,6 +888,27 @@ k_msd_final(const double *__restrict__ part, int nb, long long N, Ctl *ctl)
     if (threadIdx.x == 0) ctl->msd = N > 0 ? sh[0] / (double)N : 0.0;
 }
 
+// One workgroup per replica: its disks' |acc|^2 in a fixed order.
+__global__ void __launch_bounds__(kMsdThreads) k_msd_all(Tables t, const float2 *__restrict__ acc)
+{
+    __shared__ double sh[kMsdThreads];
+    const Rep &R = t.reps[blockIdx.x];
+    const float2 *a = acc + R.pb;
+    const long long N = R.g.N;
+    double s = 0.0;
+    for (long long i = threadIdx.x; i < N; i += kMsdThreads) {
+        const float2 v = a[i];
+        s += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kMsdThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) t.ctls[blockIdx.x].msd = N > 0 ? sh[0] / (double)N : 0.0;
+}
+
 // ------------------------------------------------------------- tuner
 // Per replica: delta <- delta * clamp(a / 0.3, 0.5, 2), clamped to
 // [1e-3, min(w)/2], with a the acceptance of the window since the last
@@ -1057,6 +1078,12 @@ hipError_t launch_msd(const float2 *acc, long long n, Ctl *ctl, const Work &w, h
 {
     hipLaunchKernelGGL(k_msd_partial, dim3(kMsdBlocks), dim3(kMsdThreads), 0, st, acc, n, w.f64);
     hipLaunchKernelGGL(k_msd_final, dim3(1), dim3(kMsdThreads), 0, st, w.f64, kMsdBlocks, n, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_msd_all(const Tables &t, const float2 *acc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_msd_all, dim3(t.R), dim3(kMsdThreads), 0, st, t, acc);
     return hipGetLastError();
 }
 

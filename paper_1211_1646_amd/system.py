@@ -140,6 +140,12 @@ class HardDiskSystem:
     def tune(self, window_sweeps: int, n_windows: int):
         L.check(self.lib.mpmc_tune(self._h, int(window_sweeps), int(n_windows)))
 
+    def control(self, net, window_sweeps: int, n_windows: int):
+        """The learned controller over n_windows windows (see MoveSizeNet)."""
+        net.stream.synchronize()
+        L.check(self.lib.mpmc_control(self._h, C.c_void_p(net.W.data_ptr()), int(window_sweeps),
+                                      int(n_windows)))
+
     def set_launch(self, lanes_per_cell: int = 1, block_size: int = 256):
         L.check(self.lib.mpmc_set_launch(self._h, int(lanes_per_cell), int(block_size)))
         self.block = int(block_size)
@@ -254,6 +260,23 @@ class HardDiskBatch:
             L.check(self.lib.mpmc_replica_geometry(h, r, C.byref(g)))
             self.geometries.append({name: getattr(g, name) for name, _ in L.Geometry._fields_})
         self.N = sum(int(g["n_particles"]) for g in self.geometries)
+
+    def stats(self, with_msd: bool = False):
+        """(trials[R], accepts[R], delta[R], msd[R] or None) of every replica."""
+        R = self.R
+        tr = np.zeros(R, np.uint64)
+        ac = np.zeros(R, np.uint64)
+        dl = np.zeros(R, np.float32)
+        msd = np.zeros(R, np.float64) if with_msd else None
+        L.check(self.lib.mpmc_batch_stats(self._h, tr.ctypes.data, ac.ctypes.data, dl.ctypes.data,
+                                          msd.ctypes.data if with_msd else None))
+        return tr, ac, dl, msd
+
+    def control(self, net, window_sweeps: int, n_windows: int):
+        """The learned controller over n_windows windows (see MoveSizeNet)."""
+        net.stream.synchronize()   # parameters written on the network's stream
+        L.check(self.lib.mpmc_control(self._h, C.c_void_p(net.W.data_ptr()), int(window_sweeps),
+                                      int(n_windows)))
 
     close = HardDiskSystem.close
     __del__ = HardDiskSystem.__del__
