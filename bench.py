@@ -10,7 +10,15 @@ sub-sweeps, the random grid shift and the rebuild of the cell lists).
 
 Prints one JSON line: trial moves per second over the timed sweeps, the
 sub-sweep kernel's achieved bandwidth against the HBM peak, and the CPU
-oracle timed on a bounded sample of the same workload.
+oracle timed on a bounded sample of the same workload.  Two more objects
+compare the batched and learned-controller forms with the plain form:
+  batched -- 64 replicas of uneven N (64^2 .. 512^2) and packing fraction
+             (0.65 .. 0.73) in one handle against the same 64 systems run
+             one after another (same chain, bit for bit);
+  learned -- a move-size network trained on samples the sweeps log, used
+             during equilibration of the 1M-disk workload, against the plain
+             tuner: mean-square displacement per second of production
+             sweeps with delta frozen, and P* with its standard error.
 """
 from __future__ import annotations
 
@@ -20,6 +28,8 @@ import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -42,6 +52,9 @@ def parse():
     ap.add_argument("--cpu-sweeps", type=int, default=0,
                     help="oracle sweeps for the CPU baseline (0 = sized to ~15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-sweeps", type=int, default=160)
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (a known byte count "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -69,6 +82,113 @@ def cpu_baseline(args, geo, trials_per_sweep_gpu):
     return {"value": (tr1 - tr0) / dt, "unit": "trial moves/s", "cores": 1, "kind": "oracle",
             "sample": "%d sweeps of the %d-disk workload from the lattice (%d trial moves, %.1f s, "
                       "serial C oracle, one thread)" % (n, geo["n_particles"], tr1 - tr0, dt)}
+
+
+def traffic_from_profile(kernel_src):
+    """HBM bytes per sub-sweep launch from the committed counter summary, if
+    it was taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "subsweep_1M_phi070_counters.md")
+    if not os.path.exists(path):
+        return None
+    digest = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(path):
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            vals[k.strip()] = v.strip().split()[0]
+    if vals.get("kernel source sha256/16") != digest:
+        return None
+    try:
+        return float(vals["hbm bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def batched_leg(args, pkg, torch):
+    """64-replica batch vs the same replicas one after another."""
+    from paper_1211_1646_amd import workloads as W
+    specs = W.replicas(64, seed=1)
+    cfgs = [pkg.SystemConfig(lattice_nx=s["nx"], lattice_ny=s["ny"], phi=s["phi"], w_min=1.0,
+                             delta=0.1, n_moves=args.n_moves, seed=1, replica=r,
+                             flags=pkg.FLAG_ACC) for r, s in enumerate(specs)]
+    n = args.batched_sweeps
+    B = pkg.HardDiskBatch(cfgs)
+    B.tune(10, 4)
+    blk, _ = B.autotune(16)
+    B.reset_acc()
+    tr0 = B.counters()[0]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    B.synchronize()
+    e0.record(B.stream)
+    B.sweep(n)
+    e1.record(B.stream)
+    e1.synchronize()
+    bsec = e0.elapsed_time(e1) * 1e-3
+    btr = B.counters()[0] - tr0
+    _, _, deltas, msd = B.stats(with_msd=True)
+    Ns = np.array([g["n_particles"] for g in B.geometries], np.float64)
+    b_msd_sum = float((Ns * msd).sum())
+    B.close()
+    # the same replicas, one handle each, one after another, with the same
+    # history (tuner windows, then the 4 x 32 sweeps the autotuner ran), so
+    # each timed window runs exactly the chain the batch ran
+    seq_sec, seq_tr, seq_msd = 0.0, 0, 0.0
+    for r, c in enumerate(cfgs):
+        S = pkg.HardDiskSystem(c)
+        S.tune(10, 4)
+        S.set_launch(1, blk)
+        S.sweep(4 * 32)
+        assert np.float32(S.delta) == np.float32(deltas[r])
+        t0 = S.counters()[0]
+        S.reset_acc()
+        e0.record(S.stream)
+        S.sweep(n)
+        e1.record(S.stream)
+        e1.synchronize()
+        seq_sec += e0.elapsed_time(e1) * 1e-3
+        seq_tr += S.counters()[0] - t0
+        seq_msd += float(Ns[r]) * S.msd()
+        S.close()
+    return {"replicas": len(cfgs), "disks": int(Ns.sum()), "sweeps": n,
+            "trial_moves_per_s": btr / bsec, "sequential_trial_moves_per_s": seq_tr / seq_sec,
+            "speedup": (btr / bsec) / (seq_tr / seq_sec),
+            "msd_sum_per_s": b_msd_sum / bsec, "sequential_msd_sum_per_s": seq_msd / seq_sec,
+            "subsweep_block": blk}
+
+
+def learned_leg(args, pkg, torch):
+    """Train the controller on logged windows, then compare it with the plain
+    tuner on the 1M-disk workload."""
+    from paper_1211_1646_amd import controller as ctl
+    phis = [0.65, 0.66, 0.67, 0.68, 0.69, 0.70, 0.71, 0.72, 0.73]
+    deltas = [0.02, 0.04, 0.06, 0.08, 0.10, 0.12, 0.14, 0.16, 0.18, 0.20, 0.22, 0.24, 0.26,
+              0.28, 0.30]
+    base = [pkg.SystemConfig(lattice_nx=64, lattice_ny=64, phi=p, w_max=math.sqrt(2.0),
+                             n_moves=args.n_moves, seed=1) for p in phis]
+    t0 = time.perf_counter()
+    net, info = ctl.train_controller(base, deltas, windows=740, window_sweeps=10, skip=20,
+                                     steps=2000)
+    train_s = time.perf_counter() - t0
+    res = {}
+    for mode in ("plain", "learned"):
+        cfg = pkg.SystemConfig(lattice_nx=args.lattice, lattice_ny=args.lattice, phi=args.phi,
+                               w_max=math.sqrt(2.0), delta=0.1, n_moves=args.n_moves, seed=1,
+                               flags=pkg.FLAG_ACC)
+        S = pkg.HardDiskSystem(cfg)
+        S.set_launch(1, args.block if args.block > 0 else 128)
+        res[mode] = ctl.equilibrate_and_measure(S, mode, net, eq_windows=30, window_sweeps=10,
+                                                prod_sweeps=1000, sample_every=10, blocks=10)
+        S.close()
+    pl, le = res["plain"], res["learned"]
+    comb = math.hypot(pl["P_se"], le["P_se"])
+    return {"workload": "N=%d phi=%.3f" % (args.lattice ** 2, args.phi),
+            "training_samples": info["samples"], "training_seconds": train_s,
+            "loss_first": info["loss_first"], "loss_last": info["loss_last"],
+            "labels": {"%.2f" % k: v for k, v in sorted(info["labels"].items())},
+            "plain": pl, "learned": le,
+            "msd_per_s_ratio": le["msd_per_s"] / pl["msd_per_s"],
+            "P_diff_in_combined_se": abs(le["P"] - pl["P"]) / comb if comb > 0 else None}
 
 
 def main():
@@ -152,7 +272,7 @@ def main():
     S.synchronize()
 
     out = {
-        "metric": "trial moves/sec at 1M disks phi=0.70",
+        "metric": "trial moves/sec at 1M disks phi=0.70; MSD/sec learned+batched vs plain",
         "value": value,
         "unit": "trial moves/s",
         "n_gpus": 1,
@@ -174,15 +294,23 @@ def main():
                    "subsweep_block": S.block,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profile(os.path.join(
+                         ROOT, "paper_1211_1646_amd", "csrc", "mpmc_kernels.hip")),
                      "kernel": "k_subsweep<4>", "kernel_avg_us": k_avg_ms * 1e3,
                      "kernel_median_us": kms[len(kms) // 2] * 1e3,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
+    S.close()
+    if not args.no_batched:
+        print("[bench] batched leg", file=sys.stderr, flush=True)
+        out["batched"] = batched_leg(args, pkg, torch)
+    if not args.no_learned:
+        print("[bench] learned-controller leg", file=sys.stderr, flush=True)
+        out["learned"] = learned_leg(args, pkg, torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args, geo, trials / args.steps)
-    S.close()
     print(json.dumps(out), flush=True)
 
 

@@ -222,3 +222,62 @@ def training_set(samples, best):
     X = features(samples["phi"], samples["occupancy"], samples["acceptance"]).astype(np.float32)
     T = target_of_delta(np.array([best[float(k)] for k in key])).astype(np.float32)
     return X, T
+
+
+def train_controller(cfgs, deltas, windows: int = 600, window_sweeps: int = 10, skip: int = 5,
+                     steps: int = 3000, lr: float = 3e-3, seed: int = 0, device: str = "cuda:0"):
+    """Log samples from one batch, label them, train a fresh network on the
+    GPU.  Returns (net, info) with the labels, sample count and losses."""
+    samples, secs = collect_samples(cfgs, deltas, windows, window_sweeps, skip=skip, device=device)
+    best = label_best_delta(samples)
+    X, T = training_set(samples, best)
+    net = MoveSizeNet(init_params(seed), device=device)
+    hist = net.train(X, T, steps, lr=lr, log_every=max(1, steps // 10))
+    info = {"samples": int(len(X)), "labels": best, "loss_first": hist[0], "loss_last": hist[-1],
+            "collect_seconds": secs}
+    return net, info
+
+
+def equilibrate_and_measure(sys_, mode: str, net=None, eq_windows: int = 50,
+                            window_sweeps: int = 10, prod_sweeps: int = 1000,
+                            sample_every: int = 10, blocks: int = 10):
+    """Equilibrate with the plain tuner ("plain") or the learned controller
+    ("learned"), freeze delta, then run prod_sweeps production sweeps timed
+    with HIP events on the system's stream.  Returns the displacement per
+    second (mean |acc|^2 over the production window / its sweep seconds) and
+    P* with the standard error over `blocks` blocks of contact histograms."""
+    import torch
+    if mode == "plain":
+        sys_.tune(window_sweeps, eq_windows)
+    elif mode == "learned":
+        sys_.control(net, window_sweeps, eq_windows)
+    else:
+        raise ValueError(mode)
+    sys_.synchronize()
+    delta = float(sys_.delta if not callable(sys_.delta) else sys_.delta(0))
+    sys_.reset_acc()
+    per_block = prod_sweeps // blocks
+    chunks = per_block // sample_every
+    ev = []
+    p_blocks = []
+    for b in range(blocks):
+        first = True
+        for k in range(chunks):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(sys_.stream)
+            sys_.sweep(sample_every)
+            e1.record(sys_.stream)
+            ev.append((e0, e1))
+            sys_.pair_histogram(reset=first)
+            first = False
+        p, _, _, _ = (sys_.pressure_from_contact() if not hasattr(sys_, "R")
+                      else sys_.pressure_from_contact(0))
+        p_blocks.append(p)
+    sys_.synchronize()
+    secs = sum(a.elapsed_time(b) for a, b in ev) * 1e-3
+    msd = sys_.msd() if not hasattr(sys_, "R") else sys_.msd(0)
+    p_blocks = np.array(p_blocks)
+    return {"mode": mode, "delta": delta, "sweeps": per_block * blocks, "seconds": secs,
+            "msd": msd, "msd_per_s": msd / secs, "msd_per_sweep": msd / (per_block * blocks),
+            "P": float(p_blocks.mean()),
+            "P_se": float(p_blocks.std(ddof=1) / math.sqrt(len(p_blocks)))}

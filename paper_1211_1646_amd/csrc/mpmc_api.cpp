@@ -209,7 +209,8 @@ size_t work_bytes(const Layout &L)
 {
     return align256((size_t)mpmc::scan_entries(L.cells) * 4) +
            align256((size_t)mpmc::count_stride(L.active) * 2 * 8) +
-           (size_t)mpmc::kMsdBlocksMax * sizeof(double) + 256;
+           align256((size_t)mpmc::kMsdBlocksMax * sizeof(double)) +
+           (size_t)L.active * mpmc::ovf_per_slot(L.cap) * 8 + 256;
 }
 
 // Control buffer: Ctl[R], Rep[R], replica of each active chunk, replica of
@@ -538,6 +539,8 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
         h->work.cnt_stride = (int)mpmc::count_stride(L.active);
         w += align256((size_t)mpmc::count_stride(L.active) * 2 * 8);
         h->work.f64 = (double *)w;
+        w += align256((size_t)mpmc::kMsdBlocksMax * sizeof(double));
+        h->work.ovf = (float2 *)w;
     }
     const CtlLayout cl = ctl_layout(L);
     char *cb = (char *)b->ctl;

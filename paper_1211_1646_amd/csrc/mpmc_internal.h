@@ -23,6 +23,7 @@ constexpr int kActiveChunk = 768;         // active-slot granularity (lcm of 64,
 constexpr int kGranule = 64;              // counter partials: one per 64 active slots
 constexpr int kMsdBlocksMax = 512;
 constexpr int kMlpParams = 1217;          // 3 -> 32 -> 32 -> 1 network
+constexpr int kNbrLds = 16;               // reachable neighbours a lane keeps in LDS
 
 // Per-replica control block: everything a captured sweep graph reads or
 // writes that changes between launches lives here, not in kernel arguments.
@@ -89,16 +90,19 @@ struct Tables {
 
 // Scratch (caller's work buffer): u32 per-tile totals of the rebin, u64
 // trial/accept partials per granule of active slots (accumulated by every
-// sub-sweep, folded into the control blocks on demand), FP64 partials.
+// sub-sweep, folded into the control blocks on demand), FP64 partials, and
+// per active slot the reachable neighbours beyond the first kNbrLds.
 struct Work {
     uint32_t *scan;              // cells / kRebinTile entries
     unsigned long long *cnt;     // [2][cnt_stride]
     double *f64;                 // kMsdBlocksMax entries
+    float2 *ovf;                 // [active][ovf_per_slot(cap)]
     int cnt_stride;
 };
 
 inline long long scan_entries(long long cells) { return cells / kRebinTile + 8; }
 inline long long count_stride(long long active) { return active / kGranule + 8; }
+inline int ovf_per_slot(int cap) { return 8 * cap > kNbrLds ? 8 * cap - kNbrLds : 0; }
 
 // ---- launch wrappers (defined in mpmc_kernels.hip) ----
 // Sub-sweep of every replica; set >= 0 is the same explicit set everywhere,

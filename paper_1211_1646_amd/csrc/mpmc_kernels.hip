@@ -241,14 +241,34 @@ __device__ __forceinline__ unsigned block_exclusive_scan_u32(unsigned v, unsigne
 constexpr float kReach2 = 1.0001f;
 constexpr float kReachEdge = 1.0001f;
 
+// Smallest r^2 from (xm, ym) to four neighbour entries; any r^2 < 1 iff the
+// smallest is (all values finite).
+__device__ __forceinline__ float min_r2(float xm, float ym, const float2 *e)
+{
+    const float2 e0 = e[0], e1 = e[1], e2 = e[2], e3 = e[3];
+    const float d0x = xm - e0.x, d0y = ym - e0.y;
+    const float d1x = xm - e1.x, d1y = ym - e1.y;
+    const float d2x = xm - e2.x, d2y = ym - e2.y;
+    const float d3x = xm - e3.x, d3y = ym - e3.y;
+    return fminf(fminf(d0x * d0x + d0y * d0y, d1x * d1x + d1y * d1y),
+                 fminf(d2x * d2x + d2y * d2y, d3x * d3x + d3y * d3y));
+}
+
 template <int CAP>
 __global__ void __launch_bounds__(256)
 k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
            float2 *__restrict__ acc, uint32_t *__restrict__ tag,
-           unsigned long long *__restrict__ cnt, int cnt_stride, int set, int ntile, int per)
+           unsigned long long *__restrict__ cnt, int cnt_stride, float2 *__restrict__ ovf_all,
+           int set, int ntile, int per)
 {
     extern __shared__ float2 lds[];   // [blockDim.x][kRow]; reused for the counts
-    constexpr int kRow = 8 * CAP + 1;  // odd stride: 16 lanes hit distinct bank pairs
+    // The first kL reachable neighbours of a lane live in its LDS row (odd
+    // stride: 16 lanes hit distinct bank pairs); the rare rest, up to 8 CAP
+    // in all, in the lane's own overflow entries in global memory.  A small
+    // row keeps the LDS per workgroup low enough for four waves per SIMD.
+    constexpr int kL = 8 * CAP < kNbrLds ? 8 * CAP : kNbrLds;
+    constexpr int kO = 8 * CAP - kL;
+    constexpr int kRow = kL + 1;
     const int tile = xcd_tile(per);
     const long long slot0 = (long long)tile * blockDim.x;
     const int r = tile < ntile ? (int)t.arep[slot0 / kActiveChunk] : 0;
@@ -267,6 +287,7 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
     const int hx = g.mx >> 1, hy = g.my >> 1;
     const long long gid = slot0 + (long long)threadIdx.x - R.ab;   // within the replica
     float2 *const nbr = lds + threadIdx.x * kRow;   // this lane's neighbour list
+    float2 *const ovf = ovf_all + (size_t)(slot0 + (long long)threadIdx.x) * kO;
     const uint32_t *const st = start + R.cb;        // this replica's offsets
 
     unsigned n_trials = 0, n_acc = 0;
@@ -362,7 +383,10 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
                         const float ey = ra == 0 ? -oy : oy - g.wy;
                         reach = ex * ex + ey * ey < kReach2;
                     }
-                    nbr[K] = make_float2(ox, oy);   // row K <= slots seen so far
+                    // entry K <= slots seen so far < 8 CAP
+                    const float2 v = make_float2(ox, oy);
+                    if (kO == 0 || K < kL) nbr[K] = v;
+                    else ovf[K - kL] = v;
                     K += (i < (int)rn[q] && reach) ? 1 : 0;
                 }
             }
@@ -370,9 +394,15 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
             // the padded rows stay below 8 * CAP because K <= 8 * CAP
             const int K4 = (K + 3) & ~3;
             const float2 far = make_float2(1.0e6f, 1.0e6f);
-            if (K + 0 < K4) nbr[K + 0] = far;
-            if (K + 1 < K4) nbr[K + 1] = far;
-            if (K + 2 < K4) nbr[K + 2] = far;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                const int k = K + e;
+                if (k < K4) {
+                    if (kO == 0 || k < kL) nbr[k] = far;
+                    else ovf[k - kL] = far;
+                }
+            }
+            const int KL = K4 < kL ? K4 : kL;   // kL is a multiple of four
             // rng.shuffle(c.particles): Fisher-Yates over the stored list,
             // done on a packed permutation (nibble q = source slot of list
             // position q) and applied to the registers once.
@@ -415,17 +445,11 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
                 }
                 // neighbours four at a time (two paired LDS reads); the loop
                 // stops after the first group that holds an overlap
-                for (int k = 0; ok && k < K4; k += 4) {
-                    const float2 e0 = nbr[k], e1 = nbr[k + 1], e2 = nbr[k + 2], e3 = nbr[k + 3];
-                    const float d0x = xm - e0.x, d0y = ym - e0.y;
-                    const float d1x = xm - e1.x, d1y = ym - e1.y;
-                    const float d2x = xm - e2.x, d2y = ym - e2.y;
-                    const float d3x = xm - e3.x, d3y = ym - e3.y;
-                    // any r^2 < 1 <=> the smallest r^2 < 1 (all values finite)
-                    const float m = fminf(fminf(d0x * d0x + d0y * d0y, d1x * d1x + d1y * d1y),
-                                          fminf(d2x * d2x + d2y * d2y, d3x * d3x + d3y * d3y));
-                    ok = !(m < 1.0f);
-                }
+                for (int k = 0; ok && k < KL; k += 4)
+                    ok = !(min_r2(xm, ym, nbr + k) < 1.0f);
+                if (kO > 0)
+                    for (int k = kL; ok && k < K4; k += 4)
+                        ok = !(min_r2(xm, ym, ovf + (k - kL)) < 1.0f);
                 if (ok) {
                     px[0] = xm;
                     py[0] = ym;
@@ -989,12 +1013,13 @@ inline int per_xcd(int ntile) { return (ntile + 7) / 8; }
 }  // namespace
 
 // ================================================================ launches
-// Workgroup size of the sub-sweep: the requested one, reduced so that the
-// neighbour table (8 * cap + 1 float2 per lane) stays within 64 KB of LDS;
+// Workgroup size of the sub-sweep: the requested one, reduced if the LDS
+// neighbour rows would exceed 64 KB (they do not for rows of 17 float2);
 // always one of 64, 128, 192, 256, so it divides the active chunk.
 int subsweep_block(int cap, int block)
 {
-    const int fit = (65536 / ((8 * cap + 1) * (int)sizeof(float2))) / 64 * 64;
+    const int row = (8 * cap < kNbrLds ? 8 * cap : kNbrLds) + 1;
+    const int fit = (65536 / (row * (int)sizeof(float2))) / 64 * 64;
     return block < fit ? block : fit;
 }
 
@@ -1006,10 +1031,11 @@ hipError_t launch_subsweep(const Tables &t, float2 *pos, const uint32_t *start, 
     const int ntile = tiles_for(t.active, block);
     const int per = per_xcd(ntile);
     const dim3 grid(8 * per), blk(block);
-    const size_t lds = (size_t)(8 * t.cap + 1) * block * sizeof(float2);
+    const int row = (8 * t.cap < kNbrLds ? 8 * t.cap : kNbrLds) + 1;
+    const size_t lds = (size_t)row * block * sizeof(float2);
 #define MPMC_SUB(CAP)                                                                          \
     hipLaunchKernelGGL(k_subsweep<CAP>, grid, blk, lds, st, t, pos, start, acc, tag, w.cnt,     \
-                       w.cnt_stride, set, ntile, per)
+                       w.cnt_stride, w.ovf, set, ntile, per)
     switch (t.cap) {
     case 4: MPMC_SUB(4); break;
     case 5: MPMC_SUB(5); break;
