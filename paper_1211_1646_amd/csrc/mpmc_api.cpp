@@ -548,6 +548,7 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
     h->t.reps = (const Rep *)(cb + cl.reps);
     h->t.arep = (const uint16_t *)(cb + cl.arep);
     h->t.crep = (const uint16_t *)(cb + cl.crep);
+    h->t.rep0 = L.reps[0];
     h->t.R = n;
     h->t.cap = L.cap;
     h->t.cells = L.cells;

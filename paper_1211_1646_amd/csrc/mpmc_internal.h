@@ -38,15 +38,17 @@ struct alignas(256) Ctl {
     unsigned int errword;            // kErr* bits set by kernels
     int shift_f;                     // the running sweep's shift, recorded by the
     float shift_d;                   //   rebin's count kernel for its scatter
-    // Sweep-global draws of sweep s in draw[s & 1]: set order (byte q = set
-    // of slot q), shift direction f and distance d.  Written when the sweep
-    // counter or the key changes, read by every launch of the sweep.
+    // Sweep-global draws of the current sweep: set order (byte q = set of
+    // slot q), shift direction f and distance d.  Read by every launch of the
+    // sweep; rewritten when the key changes and by the rebin's scatter kernel
+    // when it advances the sweep, after the count kernel (the last reader of
+    // the old draws) has finished.
     struct Draw {
         unsigned int order;
         int f;
         float d;
         unsigned int pad;
-    } draw[2];
+    } draw;
     unsigned long long hist_samples; // configurations in hist[]
     double fit[4];                   // P*, g(sigma+), rho, status
     long long overlaps;              // ordered overlapping pairs (count kernel)
@@ -77,6 +79,7 @@ struct Rep {
 // Device tables of a handle (in the caller's control buffer), passed to the
 // kernels by value.
 struct Tables {
+    Rep rep0;               // replica 0 by value: a single system needs no table load
     const Rep *reps;        // [R]
     Ctl *ctls;              // [R]
     const uint16_t *arep;   // replica of each active chunk

@@ -38,10 +38,11 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        // one 32 x 32 -> 64-bit product per multiplier gives both halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         c0 = hi1 ^ c1 ^ k0;
         c1 = lo1;
         c2 = hi0 ^ c3 ^ k1;
@@ -108,7 +109,7 @@ __device__ __forceinline__ Draws sweep_draws(unsigned long long s, uint32_t k0, 
 __device__ __forceinline__ void store_draws(Ctl *ctl, unsigned long long s, float wx, float wy)
 {
     const Draws D = sweep_draws(s, ctl->key0, ctl->key1, wx, wy);
-    Ctl::Draw &r = ctl->draw[s & 1ull];
+    Ctl::Draw &r = ctl->draw;
     r.order = D.order;
     r.f = D.f;
     r.d = D.d;
@@ -165,6 +166,18 @@ __device__ __forceinline__ uint32_t nib_swap(uint32_t P, int i, int j)
     P &= ~((0xFu << (4 * i)) | (0xFu << (4 * j)));
     return P | (vj << (4 * i)) | (vi << (4 * j));
 }
+
+// Replica of a workgroup and its table entry.  With one replica both are
+// known from the kernel arguments, which saves two dependent loads.
+__device__ __forceinline__ int chunk_replica(const Tables &t, bool in, long long chunk)
+{
+    return (t.R == 1 || !in) ? 0 : (int)t.arep[chunk];
+}
+__device__ __forceinline__ int tile_replica(const Tables &t, bool in, int tile)
+{
+    return (t.R == 1 || !in) ? 0 : (int)t.crep[tile];
+}
+__device__ __forceinline__ Rep rep_of(const Tables &t, int r) { return t.R == 1 ? t.rep0 : t.reps[r]; }
 
 // Workgroup id -> logical tile, so that consecutive tiles (neighbouring
 // cells) run on the same XCD: workgroups are dispatched round-robin over the
@@ -271,8 +284,8 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
     constexpr int kRow = kL + 1;
     const int tile = xcd_tile(per);
     const long long slot0 = (long long)tile * blockDim.x;
-    const int r = tile < ntile ? (int)t.arep[slot0 / kActiveChunk] : 0;
-    const Rep &R = t.reps[r];
+    const int r = chunk_replica(t, tile < ntile, slot0 / kActiveChunk);
+    const Rep R = rep_of(t, r);
     const Geom g = R.g;
     Ctl *ctl = t.ctls + r;
     const unsigned long long s = ctl->sweep;
@@ -282,7 +295,7 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
     const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
 
     int Q = set;
-    if (Q < 0) Q = (int)((ctl->draw[s & 1ull].order >> (8 * (-1 - set))) & 0xFFu);
+    if (Q < 0) Q = (int)((ctl->draw.order >> (8 * (-1 - set))) & 0xFFu);
     const int qx = Q & 1, qy = Q >> 1;
     const int hx = g.mx >> 1, hy = g.my >> 1;
     const long long gid = slot0 + (long long)threadIdx.x - R.ab;   // within the replica
@@ -485,17 +498,18 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
         }
     }
     // The workgroup's counts are added to the partial of the granule holding
-    // its first slot.  Each granule entry belongs to one workgroup of a launch
-    // and launches are ordered, so the read-modify-write needs no atomics;
-    // the partials are folded into the control blocks on demand.
+    // its first slot.  Each granule entry belongs to one workgroup of a
+    // launch, so the adds never contend; the partials are folded into the
+    // control blocks on demand.
     __syncthreads();   // every lane is done with its neighbour table
     unsigned *red = reinterpret_cast<unsigned *>(lds);
     const unsigned bt = block_sum_u32(n_trials, red);
     const unsigned ba = block_sum_u32(n_acc, red + 16);
     if (threadIdx.x == 0 && tile < ntile && bt) {
+        // no-return atomics: the wave does not wait for a read of the partial
         const long long gr = slot0 / kGranule;
-        cnt[gr] += bt;
-        cnt[cnt_stride + gr] += ba;
+        atomicAdd(&cnt[gr], (unsigned long long)bt);
+        atomicAdd(&cnt[cnt_stride + gr], (unsigned long long)ba);
     }
 }
 
@@ -540,9 +554,12 @@ __global__ void __launch_bounds__(256) k_fold_counters(Tables t, unsigned long l
 //              recounts (same operations, same result), scans inside the
 //              tile and writes offsets, positions, accumulators and tags.
 // Each disk's decision is one rounded shifted coordinate tested against
-// (0, w].  The first tile of each replica records the replica's shift (count
-// kernel) and moves the replica to its next sweep with its draws (scatter);
-// no other workgroup reads those fields, so no atomics are needed.
+// (0, w].  A thread loads all CAP slots of both cells at once (indices
+// clamped into [0, N), selected by count afterwards), so a cell costs one
+// memory round trip, not one per disk.  The first tile of each replica
+// records the replica's shift (count kernel) and moves the replica to its
+// next sweep with its draws (scatter); no other workgroup reads those
+// fields, so no atomics are needed.
 struct RebinArgs {
     Tables t;
     const float2 *pos;
@@ -566,23 +583,22 @@ __device__ __forceinline__ float shifted(float v, bool minus, float d)
     return minus ? v - d : v + d;
 }
 
-template <bool SCATTER>
+template <bool SCATTER, int CAP>
 __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
 {
     __shared__ unsigned red[16];
     const int tile = xcd_tile(a.per);
     const long long cell0 = (long long)tile * kRebinTile;
-    const int r = tile < a.ntile ? (int)a.t.crep[tile] : 0;
-    const Rep &R = a.t.reps[r];
+    const int r = tile_replica(a.t, tile < a.ntile, tile);
+    const Rep R = rep_of(a.t, r);
     const Geom g = R.g;
     Ctl *ctl = a.t.ctls + r;
     int f = a.f;
     float d = a.d;
     if (f < 0) {
         if (!SCATTER) {
-            const Ctl::Draw &dr = ctl->draw[ctl->sweep & 1ull];
-            f = dr.f;
-            d = dr.d;
+            f = ctl->draw.f;
+            d = ctl->draw.d;
         } else {
             f = ctl->shift_f;
             d = ctl->shift_d;
@@ -593,11 +609,15 @@ __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
     const float w = along_x ? g.wx : g.wy;
     const float sw = minus ? w : -w;         // translation into the receiving cell
     const uint32_t *const st = a.start + R.cb;
+    const uint32_t last = (uint32_t)(a.t.N - 1);
 
     const long long cl = cell0 + (long long)threadIdx.x - R.cb;   // cell within the replica
-    const bool valid = tile < a.ntile && cl < g.C;
-    uint32_t ob = 0, oe = 0, nbb = 0, nbe = 0;
-    unsigned cnt = 0;
+    // (with no disks at all there is nothing to load: every cell is empty)
+    const bool valid = tile < a.ntile && cl < g.C && a.t.N > 0;
+    uint32_t ob = 0, nbb = 0;
+    int no = 0, nn = 0;
+    unsigned stay = 0, leave = 0;   // bit i: own slot i stays / neighbour slot i leaves
+    float2 own[CAP], nb[CAP];
     if (valid) {
         const int c = (int)cl;
         const int cy = c / g.mx, cx = c - cy * g.mx;
@@ -606,20 +626,30 @@ __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
         else ncy = minus ? (cy == g.my - 1 ? 0 : cy + 1) : (cy == 0 ? g.my - 1 : cy - 1);
         const int nc = ncy * g.mx + ncx;
         ob = st[c];
-        oe = st[c + 1];
+        const uint32_t oe = st[c + 1];
         nbb = st[nc];
-        nbe = st[nc + 1];
-        for (uint32_t k = ob; k < oe; ++k) {
-            const float2 v = a.pos[k];
-            const float tt = shifted(along_x ? v.x : v.y, minus, d);
-            cnt += (tt > 0.0f && tt <= w) ? 1u : 0u;
+        const uint32_t nbe = st[nc + 1];
+        no = (int)(oe - ob);
+        nn = (int)(nbe - nbb);
+        if (no > CAP || nn > CAP) {
+            atomicOr(&ctl->errword, kErrCapacity);
+            no = no > CAP ? CAP : no;
+            nn = nn > CAP ? CAP : nn;
         }
-        for (uint32_t k = nbb; k < nbe; ++k) {
-            const float2 v = a.pos[k];
-            const float tt = shifted(along_x ? v.x : v.y, minus, d);
-            cnt += (tt > 0.0f && tt <= w) ? 0u : 1u;
+#pragma unroll
+        for (int i = 0; i < CAP; ++i) {
+            own[i] = a.pos[min(ob + (uint32_t)i, last)];
+            nb[i] = a.pos[min(nbb + (uint32_t)i, last)];
+        }
+#pragma unroll
+        for (int i = 0; i < CAP; ++i) {
+            const float to = shifted(along_x ? own[i].x : own[i].y, minus, d);
+            const float tn = shifted(along_x ? nb[i].x : nb[i].y, minus, d);
+            if (i < no && to > 0.0f && to <= w) stay |= 1u << i;
+            if (i < nn && !(tn > 0.0f && tn <= w)) leave |= 1u << i;
         }
     }
+    const unsigned cnt = (unsigned)(__popc(stay) + __popc(leave));
     const bool first = tile < a.ntile && cell0 == R.cb;
     if (!SCATTER) {
         const unsigned tot = block_sum_u32(cnt, red);
@@ -645,24 +675,24 @@ __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
             if (cl == g.C - 1 && (long long)(o + cnt) != R.pb + g.N) atomicOr(&ctl->errword, kErrCount);
             if (cnt > (unsigned)g.cap) atomicOr(&ctl->errword, kErrCapacity);
             const bool has_acc = a.acc != nullptr, has_tag = a.tag != nullptr;
-            for (uint32_t k = ob; k < oe; ++k) {
-                const float2 v = a.pos[k];
-                const float tt = shifted(along_x ? v.x : v.y, minus, d);
-                if (tt > 0.0f && tt <= w) {
-                    a.pos_out[o] = along_x ? make_float2(tt, v.y) : make_float2(v.x, tt);
-                    if (has_acc) a.acc_out[o] = a.acc[k];
-                    if (has_tag) a.tag_out[o] = a.tag[k];
+#pragma unroll
+            for (int i = 0; i < CAP; ++i) {
+                if (stay & (1u << i)) {
+                    const float tt = shifted(along_x ? own[i].x : own[i].y, minus, d);
+                    a.pos_out[o] = along_x ? make_float2(tt, own[i].y) : make_float2(own[i].x, tt);
+                    if (has_acc) a.acc_out[o] = a.acc[ob + i];
+                    if (has_tag) a.tag_out[o] = a.tag[ob + i];
                     ++o;
                 }
             }
-            for (uint32_t k = nbb; k < nbe; ++k) {
-                const float2 v = a.pos[k];
-                const float tt = shifted(along_x ? v.x : v.y, minus, d);
-                if (!(tt > 0.0f && tt <= w)) {
+#pragma unroll
+            for (int i = 0; i < CAP; ++i) {
+                if (leave & (1u << i)) {
+                    const float tt = shifted(along_x ? nb[i].x : nb[i].y, minus, d);
                     const float t2 = tt + sw;
-                    a.pos_out[o] = along_x ? make_float2(t2, v.y) : make_float2(v.x, t2);
-                    if (has_acc) a.acc_out[o] = a.acc[k];
-                    if (has_tag) a.tag_out[o] = a.tag[k];
+                    a.pos_out[o] = along_x ? make_float2(t2, nb[i].y) : make_float2(nb[i].x, t2);
+                    if (has_acc) a.acc_out[o] = a.acc[nbb + i];
+                    if (has_tag) a.tag_out[o] = a.tag[nbb + i];
                     ++o;
                 }
             }
@@ -694,8 +724,8 @@ k_pair_hist(Tables t, const float2 *__restrict__ pos, const uint32_t *__restrict
     __syncthreads();
     const int tile = xcd_tile(per);
     const long long cell0 = (long long)tile * kRebinTile;
-    const int r = tile < ntile ? (int)t.crep[tile] : 0;
-    const Rep &R = t.reps[r];
+    const int r = tile_replica(t, tile < ntile, tile);
+    const Rep R = rep_of(t, r);
     const Geom g = R.g;
     const double rmax = 1.0 + kHistBins * 1e-4;
     const int Rx = (double)g.wx >= rmax ? 1 : 2;
@@ -834,8 +864,8 @@ k_count_overlaps(Tables t, const float2 *__restrict__ pos, const uint32_t *__res
     __shared__ unsigned red[16];
     const int tile = xcd_tile(per);
     const long long cell0 = (long long)tile * kRebinTile;
-    const int r = tile < ntile ? (int)t.crep[tile] : 0;
-    const Rep &R = t.reps[r];
+    const int r = tile_replica(t, tile < ntile, tile);
+    const Rep R = rep_of(t, r);
     const Geom g = R.g;
     const uint32_t *const st = start + R.cb;
     const long long cl = cell0 + (long long)threadIdx.x - R.cb;
@@ -1068,8 +1098,19 @@ hipError_t launch_rebin(const Tables &t, const float2 *pos, const uint32_t *star
     a.ntile = tiles_for(t.cells, kRebinTile);
     a.per = per_xcd(a.ntile);
     const dim3 grid(8 * a.per), blk(kRebinTile);
-    hipLaunchKernelGGL(k_rebin<false>, grid, blk, 0, st, a);
-    hipLaunchKernelGGL(k_rebin<true>, grid, blk, 0, st, a);
+#define MPMC_REBIN(CAP)                                                                        \
+    do {                                                                                       \
+        hipLaunchKernelGGL((k_rebin<false, CAP>), grid, blk, 0, st, a);                         \
+        hipLaunchKernelGGL((k_rebin<true, CAP>), grid, blk, 0, st, a);                          \
+    } while (0)
+    switch (t.cap) {
+    case 4: MPMC_REBIN(4); break;
+    case 5: MPMC_REBIN(5); break;
+    case 6: MPMC_REBIN(6); break;
+    case 7: MPMC_REBIN(7); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef MPMC_REBIN
     return hipGetLastError();
 }
 
