@@ -46,7 +46,8 @@ def parse():
     ap.add_argument("--lattice", type=int, default=1024)
     ap.add_argument("--n-moves", type=int, default=4)
     ap.add_argument("--block", type=int, default=0,
-                    help="sub-sweep workgroup size; 0 = pick with the autotuner during warm-up")
+                    help="sub-sweep workgroup size; 0 = pick the shape with the autotuner")
+    ap.add_argument("--lanes", type=int, default=1, help="lanes per cell when --block is given")
     ap.add_argument("--kernel-samples", type=int, default=200,
                     help="sub-sweep launches timed one by one with HIP events")
     ap.add_argument("--cpu-sweeps", type=int, default=0,
@@ -84,9 +85,10 @@ def cpu_baseline(args, geo, trials_per_sweep_gpu):
                       "serial C oracle, one thread)" % (n, geo["n_particles"], tr1 - tr0, dt)}
 
 
-def traffic_from_profile(kernel_src):
+def traffic_from_profile(kernel_src, kernel_name):
     """HBM bytes per sub-sweep launch from the committed counter summary, if
-    it was taken on the current kernel source (else None)."""
+    it was taken on the current kernel source and the same kernel (else
+    None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "subsweep_1M_phi070_counters.md")
     if not os.path.exists(path):
@@ -97,7 +99,7 @@ def traffic_from_profile(kernel_src):
         if line.startswith("- ") and ": " in line:
             k, v = line[2:].split(": ", 1)
             vals[k.strip()] = v.strip().split()[0]
-    if vals.get("kernel source sha256/16") != digest:
+    if vals.get("kernel source sha256/16") != digest or vals.get("kernel") != kernel_name.split("<")[0]:
         return None
     try:
         return float(vals["hbm bytes per launch"])
@@ -115,7 +117,7 @@ def batched_leg(args, pkg, torch):
     n = args.batched_sweeps
     B = pkg.HardDiskBatch(cfgs)
     B.tune(10, 4)
-    blk, _ = B.autotune(16)
+    lanes, blk, _ = B.autotune(16)
     B.reset_acc()
     tr0 = B.counters()[0]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -129,16 +131,17 @@ def batched_leg(args, pkg, torch):
     _, _, deltas, msd = B.stats(with_msd=True)
     Ns = np.array([g["n_particles"] for g in B.geometries], np.float64)
     b_msd_sum = float((Ns * msd).sum())
+    n_candidates = B.AUTOTUNE_CANDIDATES
     B.close()
     # the same replicas, one handle each, one after another, with the same
-    # history (tuner windows, then the 4 x 32 sweeps the autotuner ran), so
-    # each timed window runs exactly the chain the batch ran
+    # history (tuner windows, then the sweeps the autotuner ran), so each
+    # timed window runs exactly the chain the batch ran
     seq_sec, seq_tr, seq_msd = 0.0, 0, 0.0
     for r, c in enumerate(cfgs):
         S = pkg.HardDiskSystem(c)
         S.tune(10, 4)
-        S.set_launch(1, blk)
-        S.sweep(4 * 32)
+        S.set_launch(lanes, blk)
+        S.sweep(n_candidates * 32)
         assert np.float32(S.delta) == np.float32(deltas[r])
         t0 = S.counters()[0]
         S.reset_acc()
@@ -154,10 +157,10 @@ def batched_leg(args, pkg, torch):
             "trial_moves_per_s": btr / bsec, "sequential_trial_moves_per_s": seq_tr / seq_sec,
             "speedup": (btr / bsec) / (seq_tr / seq_sec),
             "msd_sum_per_s": b_msd_sum / bsec, "sequential_msd_sum_per_s": seq_msd / seq_sec,
-            "subsweep_block": blk}
+            "subsweep_lanes_per_cell": lanes, "subsweep_block": blk}
 
 
-def learned_leg(args, pkg, torch):
+def learned_leg(args, pkg, torch, lanes_main, block_main):
     """Train the controller on logged windows, then compare it with the plain
     tuner on the 1M-disk workload."""
     from paper_1211_1646_amd import controller as ctl
@@ -176,7 +179,7 @@ def learned_leg(args, pkg, torch):
                                w_max=math.sqrt(2.0), delta=0.1, n_moves=args.n_moves, seed=1,
                                flags=pkg.FLAG_ACC)
         S = pkg.HardDiskSystem(cfg)
-        S.set_launch(1, args.block if args.block > 0 else 128)
+        S.set_launch(lanes_main, block_main)
         res[mode] = ctl.equilibrate_and_measure(S, mode, net, eq_windows=30, window_sweeps=10,
                                                 prod_sweeps=1000, sample_every=10, blocks=10)
         S.close()
@@ -224,12 +227,12 @@ def main():
     delta = float(S.delta)
     # launch shape: autotuned (shape never changes results), or as given
     if args.block > 0:
-        S.set_launch(1, args.block)
+        S.set_launch(args.lanes, args.block)
         tuned = None
     else:
         tuned = S.autotune(16)
-    print("[bench] warm-up done, delta=%.5f, sub-sweep block %d%s" % (
-        delta, S.block, " (autotuned, %.1f us/sweep)" % tuned[1] if tuned else ""),
+    print("[bench] warm-up done, delta=%.5f, sub-sweep %d lanes per cell, block %d%s" % (
+        delta, S.lanes, S.block, " (autotuned, %.1f us/sweep)" % tuned[2] if tuned else ""),
         file=sys.stderr, flush=True)
 
     # timed sweeps: one captured graph per 16 sweeps, events on the system's stream
@@ -286,6 +289,9 @@ def main():
     # written back (8 N / 4)
     bytes_per_launch = 8.0 * N + 4.0 * (C + 1) + 2.0 * N
     achieved = bytes_per_launch / (k_avg_ms * 1e-3) / 1e9
+    cap = geo["capacity"]
+    kernel_name = ("k_subsweep<%d>" % cap if S.lanes == 1
+                   else "k_subsweep_mc<%d, %d>" % (cap, S.lanes))
     S.synchronize()
 
     out = {
@@ -308,13 +314,14 @@ def main():
                    "sweeps_per_s": args.steps / secs,
                    "acceptance": (t1_acc - t0_acc) / max(trials, 1),
                    "trial_moves_per_sweep": trials / args.steps,
+                   "subsweep_lanes_per_cell": S.lanes,
                    "subsweep_block": S.block,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_from_profile(os.path.join(
-                         ROOT, "paper_1211_1646_amd", "csrc", "mpmc_kernels.hip")),
-                     "kernel": "k_subsweep<4>", "kernel_avg_us": k_avg_ms * 1e3,
+                         ROOT, "paper_1211_1646_amd", "csrc", "mpmc_kernels.hip"), kernel_name),
+                     "kernel": kernel_name, "kernel_avg_us": k_avg_ms * 1e3,
                      "kernel_timing": "%d launches in one captured graph, HIP events around the "
                                       "replay on the system's stream" % ks,
                      "kernel_single_launch_median_us": kms[len(kms) // 2] * 1e3,
@@ -326,7 +333,8 @@ def main():
         out["batched"] = batched_leg(args, pkg, torch)
     if not args.no_learned:
         print("[bench] learned-controller leg", file=sys.stderr, flush=True)
-        out["learned"] = learned_leg(args, pkg, torch)
+        out["learned"] = learned_leg(args, pkg, torch, out["config"]["subsweep_lanes_per_cell"],
+                                     out["config"]["subsweep_block"])
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args, geo, trials / args.steps)

@@ -256,19 +256,22 @@ mpmc_status mpmc_replica_get_delta(mpmc_handle h, int32_t r, float *delta);
  * on the device, for each replica from its own counts. */
 mpmc_status mpmc_tune(mpmc_handle h, int32_t window_sweeps, int32_t n_windows);
 
-/* Launch shape: lanes cooperating on one cell (1) and workgroup size (64,
- * 128, 192 or 256; reduced where a wider cell's neighbour table would exceed
- * 64 KB of LDS).  Results do not depend on it. */
+/* Launch shape of the sub-sweep: lanes cooperating on one active cell (1, 2
+ * or 4: the group splits the neighbour cells, their filtering and the
+ * overlap tests, and combines its verdicts) and workgroup size in lanes (64,
+ * 128, 192 or 256; reduced where the neighbour rows would exceed 64 KB of
+ * LDS).  Results do not depend on either: every comparison is the same. */
 mpmc_status mpmc_set_launch(mpmc_handle h, int32_t lanes_per_cell, int32_t block_size);
 
 /* Autotuner for the launch shape.  Only shape knobs that leave results bit
- * for bit unchanged are searched (the sub-sweep workgroup size: 64, 128, 192,
- * 256), so the sweeps it times are ordinary sweeps of the chain: for each
- * candidate it runs `sweeps` sweeps to capture and warm the graph, then
- * times `sweeps` more with HIP events on the stream, and finally keeps the
- * fastest shape.  `sweeps` >= 16; the chain advances by 2 * sweeps per
- * candidate.  sync.  Either output may be NULL. */
-mpmc_status mpmc_autotune(mpmc_handle h, int32_t sweeps, int32_t *block_out,
+ * for bit unchanged are searched (lanes per cell 1, 2, 4 times workgroup
+ * size 64, 128, 192, 256: twelve candidates), so the sweeps it times are
+ * ordinary sweeps of the chain: for each candidate it runs `sweeps` sweeps
+ * to capture and warm the graph, then times `sweeps` more with HIP events on
+ * the stream, and finally keeps the fastest shape.  `sweeps` >= 16; the chain
+ * advances by 2 * sweeps per candidate (24 * sweeps in all).  sync.  Any
+ * output may be NULL. */
+mpmc_status mpmc_autotune(mpmc_handle h, int32_t sweeps, int32_t *lanes_out, int32_t *block_out,
                           double *us_per_sweep_out);
 
 /* Every replica's counters since its init or set_state, current delta and,

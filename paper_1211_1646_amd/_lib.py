@@ -82,7 +82,8 @@ _SIGNATURES = {
     "mpmc_get_delta": (C.c_int32, [_H, C.POINTER(C.c_float)]),
     "mpmc_tune": (C.c_int32, [_H, C.c_int32, C.c_int32]),
     "mpmc_set_launch": (C.c_int32, [_H, C.c_int32, C.c_int32]),
-    "mpmc_autotune": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "mpmc_autotune": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_double)]),
     "mpmc_synchronize": (C.c_int32, [_H]),
     "mpmc_batch_required_bytes": (C.c_int32, [C.POINTER(Params), C.c_int32, C.POINTER(BufferSizes)]),
     "mpmc_batch_init": (C.c_int32, [C.POINTER(Params), C.c_int32, C.POINTER(Buffers), C.c_void_p,

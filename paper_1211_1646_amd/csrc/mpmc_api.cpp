@@ -258,7 +258,8 @@ struct mpmc_system {
     uint32_t *tag[2];
     mpmc::Work work;
     int cur;
-    int block;
+    int block;                    // sub-sweep workgroup size
+    int lanes;                    // sub-sweep lanes per active cell
     std::vector<uint32_t> key0;   // current key word 0 of each replica
     std::vector<char> loaded;     // replica holds a valid, overlap-free state
     bool ready;                   // every replica is loaded
@@ -301,7 +302,7 @@ mpmc_status read_ctl(mpmc_system *h)
 mpmc_status enqueue_subsweep(mpmc_system *h, int set)
 {
     MPMC_HIP(mpmc::launch_subsweep(h->t, h->pos[h->cur], h->start[h->cur], h->acc[h->cur],
-                                   h->tag[h->cur], h->work, set, h->block, h->st));
+                                   h->tag[h->cur], h->work, set, h->block, h->lanes, h->st));
     return MPMC_OK;
 }
 
@@ -556,6 +557,7 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
     h->t.N = L.N;
     h->cur = 0;
     h->block = 256;
+    h->lanes = 1;
     h->key0.resize((size_t)n);
     for (int r = 0; r < n; ++r) h->key0[(size_t)r] = p[r].seed;
     h->loaded.assign((size_t)n, 0);
@@ -946,51 +948,56 @@ mpmc_status mpmc_tune(mpmc_handle h, int32_t window_sweeps, int32_t n_windows)
 mpmc_status mpmc_set_launch(mpmc_handle h, int32_t lanes_per_cell, int32_t block_size)
 {
     if (!h) return fail(MPMC_EINVAL, "null handle");
-    if (lanes_per_cell != 1)
-        return fail(MPMC_EINVAL, "lanes_per_cell must be 1");
+    if (lanes_per_cell != 1 && lanes_per_cell != 2 && lanes_per_cell != 4)
+        return fail(MPMC_EINVAL, "lanes_per_cell must be 1, 2 or 4");
     if (block_size < 64 || block_size > 256 || block_size % 64)
         return fail(MPMC_EINVAL, "block size must be a multiple of 64 in [64, 256]");
-    if (block_size != h->block) drop_graphs(h);
+    if (block_size != h->block || lanes_per_cell != h->lanes) drop_graphs(h);
     h->block = block_size;
+    h->lanes = lanes_per_cell;
     return MPMC_OK;
 }
 
-mpmc_status mpmc_autotune(mpmc_handle h, int32_t sweeps, int32_t *block_out,
+mpmc_status mpmc_autotune(mpmc_handle h, int32_t sweeps, int32_t *lanes_out, int32_t *block_out,
                           double *us_per_sweep_out)
 {
     if (!h || sweeps < 16) return fail(MPMC_EINVAL, "autotune needs at least 16 sweeps per candidate");
     MPMC_NEED_STATE(h);
     if (!h->st) return fail(MPMC_EINVAL, "autotune needs a non-default stream");
-    const int candidates[] = {64, 128, 192, 256};
     hipEvent_t e0, e1;
     MPMC_HIP(hipEventCreate(&e0));
     MPMC_HIP(hipEventCreate(&e1));
-    int best = h->block;
+    int best_b = h->block, best_l = h->lanes;
     float best_ms = -1.0f;
     mpmc_status s = MPMC_OK;
-    for (int b : candidates) {
-        s = mpmc_set_launch(h, 1, b);
-        if (s) break;
-        s = run_sweeps(h, sweeps);   // capture and warm
-        if (s) break;
-        float ms = 0.0f;
-        if (hipEventRecord(e0, h->st) != hipSuccess || (s = run_sweeps(h, sweeps)) != MPMC_OK ||
-            hipEventRecord(e1, h->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            if (!s) s = fail(MPMC_EHIP, "autotune timing failed");
-            break;
+    for (int l : {1, 2, 4}) {
+        for (int b : {64, 128, 192, 256}) {
+            s = mpmc_set_launch(h, l, b);
+            if (s) break;
+            s = run_sweeps(h, sweeps);   // capture and warm
+            if (s) break;
+            float ms = 0.0f;
+            if (hipEventRecord(e0, h->st) != hipSuccess || (s = run_sweeps(h, sweeps)) != MPMC_OK ||
+                hipEventRecord(e1, h->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                if (!s) s = fail(MPMC_EHIP, "autotune timing failed");
+                break;
+            }
+            if (best_ms < 0.0f || ms < best_ms) {
+                best_ms = ms;
+                best_b = b;
+                best_l = l;
+            }
         }
-        if (best_ms < 0.0f || ms < best_ms) {
-            best_ms = ms;
-            best = b;
-        }
+        if (s) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (s) return s;
-    s = mpmc_set_launch(h, 1, best);
+    s = mpmc_set_launch(h, best_l, best_b);
     if (s) return s;
-    if (block_out) *block_out = best;
+    if (lanes_out) *lanes_out = best_l;
+    if (block_out) *block_out = best_b;
     if (us_per_sweep_out) *us_per_sweep_out = 1e3 * (double)best_ms / (double)sweeps;
     return read_ctl(h);
 }

@@ -110,9 +110,11 @@ inline int ovf_per_slot(int cap) { return 8 * cap > kNbrLds ? 8 * cap - kNbrLds 
 // ---- launch wrappers (defined in mpmc_kernels.hip) ----
 // Sub-sweep of every replica; set >= 0 is the same explicit set everywhere,
 // set < 0 is each replica's slot (-1 - set) of its own shuffled set order.
-// The workgroup size is 64, 128, 192 or 256 (reduced for wide cells).
+// lanes (1, 2 or 4) lanes work on each active cell; the workgroup size is
+// 64, 128, 192 or 256 lanes (reduced if the LDS rows would not fit).
 hipError_t launch_subsweep(const Tables &t, float2 *pos, const uint32_t *start, float2 *acc,
-                           uint32_t *tag, const Work &w, int set, int block, hipStream_t st);
+                           uint32_t *tag, const Work &w, int set, int block, int lanes,
+                           hipStream_t st);
 // Add the counter partials into each replica's control block; clear them.
 hipError_t launch_fold_counters(const Tables &t, const Work &w, hipStream_t st);
 // Shift (f, d) -- or each replica's own draws when f < 0 -- and rebuild the
@@ -140,7 +142,7 @@ hipError_t launch_ctl_reset(const Tables &t, int replica, unsigned long long swe
 hipError_t launch_ctl_set_key0(const Tables &t, unsigned int key0, hipStream_t st);
 hipError_t launch_ctl_set_delta(const Tables &t, int replica, float delta, hipStream_t st);
 // Workgroup size the sub-sweep actually uses for a requested one.
-int subsweep_block(int cap, int block);
+int subsweep_block(int cap, int block, int lanes);
 // Mean |acc|^2 of every replica into its control block (one workgroup each).
 hipError_t launch_msd_all(const Tables &t, const float2 *acc, hipStream_t st);
 

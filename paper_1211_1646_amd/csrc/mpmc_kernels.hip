@@ -513,6 +513,277 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
     }
 }
 
+// Exchange with the neighbouring lane of a group of two or four (DPP quad
+// permutations [1,0,3,2] and [2,3,0,1]; groups are quad-aligned).
+__device__ __forceinline__ uint32_t lane_xor1(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t lane_xor2(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+}
+template <int LPC>
+__device__ __forceinline__ bool group_all(bool v)
+{
+    uint32_t x = v ? 1u : 0u;
+    if (LPC >= 2) x &= lane_xor1(x);
+    if (LPC >= 4) x &= lane_xor2(x);
+    return x != 0u;
+}
+template <int LPC>
+__device__ __forceinline__ bool group_any(bool v)
+{
+    uint32_t x = v ? 1u : 0u;
+    if (LPC >= 2) x |= lane_xor1(x);
+    if (LPC >= 4) x |= lane_xor2(x);
+    return x != 0u;
+}
+
+// The sub-sweep with LPC = 2 or 4 lanes per active cell: the same chain as
+// k_subsweep, with the work that dominates a lane split across its group.
+// Each lane loads the own cell and 8 / LPC of the neighbour cells (one
+// corner and one edge cell per pair of them), filters and keeps those
+// neighbours, and tests the trial positions against them; the group ANDs
+// the verdicts (DPP), so every lane of the group sees the same accept
+// decision and carries the same own-cell state.  Even lanes draw the cell's
+// first trial block, odd lanes its first shuffle block, and the pair swaps
+// them.  Every comparison is the one k_subsweep makes, so the results are
+// identical; the gain is twice or four times the waves in flight, each with
+// a shorter chain of dependent work, where a launch has too few cells to
+// hide latency.
+template <int CAP, int LPC>
+__global__ void __launch_bounds__(256)
+k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
+              float2 *__restrict__ acc, uint32_t *__restrict__ tag,
+              unsigned long long *__restrict__ cnt, int cnt_stride, float2 *__restrict__ ovf_all,
+              int set, int ntile, int per)
+{
+    extern __shared__ float2 lds[];
+    constexpr int NB = 8 / LPC;             // neighbour cells per lane
+    constexpr int kE = NB * CAP;            // neighbour slots per lane
+    constexpr int kL = kE < kNbrLds ? kE : kNbrLds;
+    constexpr int kO = kE - kL;
+    constexpr int kRow = kL + 1;
+    const int tile = xcd_tile(per);
+    const long long lane0 = (long long)tile * blockDim.x;
+    const long long slot0 = lane0 / LPC;
+    const int r = chunk_replica(t, tile < ntile, slot0 / kActiveChunk);
+    const Rep R = rep_of(t, r);
+    const Geom g = R.g;
+    Ctl *ctl = t.ctls + r;
+    const unsigned long long s = ctl->sweep;
+    const uint32_t k0 = ctl->key0, k1 = ctl->key1;
+    const float delta = ctl->delta;
+    const int n_moves = R.n_moves;
+    const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
+
+    int Q = set;
+    if (Q < 0) Q = (int)((ctl->draw.order >> (8 * (-1 - set))) & 0xFFu);
+    const int qx = Q & 1, qy = Q >> 1;
+    const int hx = g.mx >> 1, hy = g.my >> 1;
+    const int h = (int)(threadIdx.x % LPC);
+    const long long gid = slot0 + (long long)(threadIdx.x / LPC) - R.ab;   // cell within the replica
+    float2 *const nbr = lds + threadIdx.x * kRow;
+    float2 *const ovf = ovf_all + (size_t)(lane0 + (long long)threadIdx.x) * kO;
+    const uint32_t *const st = start + R.cb;
+
+    unsigned n_trials = 0, n_acc = 0;
+    if (tile < ntile && gid < (long long)hx * hy) {
+        const int iy = (int)(gid / hx), ix = (int)(gid - (long long)iy * hx);
+        const int cx = 2 * ix + qx, cy = 2 * iy + qy;
+        const int c = cy * g.mx + cx;
+        const int xl = cx == 0 ? g.mx - 1 : cx - 1;
+        const int xr = cx == g.mx - 1 ? 0 : cx + 1;
+        const int yd = cy == 0 ? g.my - 1 : cy - 1;
+        const int yu = cy == g.my - 1 ? 0 : cy + 1;
+        // own cell and this lane's neighbour cells: q = 3 row + col over
+        // {0, 1, 2, 3, 5, 6, 7, 8}, lane h taking entries h NB .. h NB + NB - 1
+        const uint32_t b0 = st[c];
+        int n = (int)(st[c + 1] - b0);
+        uint32_t rb[NB], rn[NB];
+        int qa[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int e = h * NB + j;
+            const int q = e < 4 ? e : e + 1;
+            qa[j] = q;
+            const int ra = q / 3, cb = q - 3 * (q / 3);
+            const int row = ra == 0 ? yd : (ra == 1 ? cy : yu);
+            const int col = cb == 0 ? xl : (cb == 1 ? cx : xr);
+            const int cc = row * g.mx + col;
+            rb[j] = st[cc];
+            rn[j] = st[cc + 1] - rb[j];
+        }
+        bool bad = n > g.cap;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) bad |= rn[j] > (uint32_t)g.cap;
+        bad = group_any<LPC>(bad);
+        if (bad) {
+            if (h == 0) atomicOr((unsigned int *)&ctl->errword, kErrCapacity);
+            n = 0;
+        }
+        if (n > 0) {
+            const bool has_acc = acc != nullptr, has_tag = tag != nullptr;
+            const uint32_t last = (uint32_t)(t.N - 1);
+            float2 nv[NB][CAP];
+            float px[CAP], py[CAP], ax[CAP], ay[CAP];
+            uint32_t tg[CAP];
+#pragma unroll
+            for (int i = 0; i < CAP; ++i) {
+                const float2 v = pos[min(b0 + (uint32_t)i, last)];
+                px[i] = v.x;
+                py[i] = v.y;
+                ax[i] = ay[i] = 0.0f;
+                tg[i] = 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int i = 0; i < CAP; ++i) nv[j][i] = pos[min(rb[j] + (uint32_t)i, last)];
+            if (has_acc) {
+#pragma unroll
+                for (int i = 0; i < CAP; ++i) {
+                    const float2 a = acc[min(b0 + (uint32_t)i, last)];
+                    ax[i] = a.x;
+                    ay[i] = a.y;
+                }
+            }
+            if (has_tag) {
+#pragma unroll
+                for (int i = 0; i < CAP; ++i) tg[i] = tag[min(b0 + (uint32_t)i, last)];
+            }
+            // first trial block on even lanes, first shuffle block on odd
+            // lanes, then swapped within the pair
+            const uint4 mine = philox((uint32_t)c, s_lo, s_hi, (h & 1) ? kTagShuffle : 0u, k0, k1);
+            const uint4 other = make_uint4(lane_xor1(mine.x), lane_xor1(mine.y), lane_xor1(mine.z),
+                                           lane_xor1(mine.w));
+            uint4 W = (h & 1) ? other : mine;
+            uint4 Wsh = (h & 1) ? mine : other;
+            // this lane's neighbours in the cell's frame, reachable ones kept
+            int K = 0;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int q = qa[j];
+                const int ra = q / 3, cb = q - 3 * (q / 3);
+#pragma unroll
+                for (int i = 0; i < CAP; ++i) {
+                    float ox = nv[j][i].x, oy = nv[j][i].y;
+                    ox = cb == 0 ? ox - g.wx : (cb == 2 ? ox + g.wx : ox);
+                    oy = ra == 0 ? oy - g.wy : (ra == 2 ? oy + g.wy : oy);
+                    const float ex = cb == 0 ? -ox : ox - g.wx;
+                    const float ey = ra == 0 ? -oy : oy - g.wy;
+                    bool reach;
+                    if (ra == 1) reach = cb == 0 ? ox > -kReachEdge : ox < g.wx + kReachEdge;
+                    else if (cb == 1) reach = ra == 0 ? oy > -kReachEdge : oy < g.wy + kReachEdge;
+                    else reach = ex * ex + ey * ey < kReach2;
+                    const float2 v = make_float2(ox, oy);
+                    if (kO == 0 || K < kL) nbr[K] = v;
+                    else ovf[K - kL] = v;
+                    K += (i < (int)rn[j] && reach) ? 1 : 0;
+                }
+            }
+            const int K4 = (K + 3) & ~3;
+            const float2 far = make_float2(1.0e6f, 1.0e6f);
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                const int k = K + e;
+                if (k < K4) {
+                    if (kO == 0 || k < kL) nbr[k] = far;
+                    else ovf[k - kL] = far;
+                }
+            }
+            const int KL = K4 < kL ? K4 : kL;
+            uint32_t P = 0x76543210u;
+            for (int k = 0; k < n - 1; ++k) {
+                if (k > 0 && (k & 3) == 0)
+                    Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle + (uint32_t)(k >> 2), k0, k1);
+                const int i = n - 1 - k;
+                const int j = (int)bounded(word_of(Wsh, k & 3), (uint32_t)(i + 1));
+                P = nib_swap(P, i, j);
+            }
+            if (n > 1) {
+                rperm(px, P);
+                rperm(py, P);
+                if (has_acc) {
+                    rperm(ax, P);
+                    rperm(ay, P);
+                }
+                if (has_tag) rperm(tg, P);
+            }
+            for (int tr = 0; tr < n_moves; ++tr) {
+                if (tr > 0 && (tr & 3) == 0) W = philox((uint32_t)c, s_lo, s_hi, (uint32_t)(tr >> 2), k0, k1);
+                float dx, dy;
+                displacement(word_of(W, tr & 3), delta, dx, dy);
+                const float xm = px[0] + dx;
+                const float ym = py[0] + dy;
+                bool ok = xm > 0.0f && xm <= g.wx && ym > 0.0f && ym <= g.wy;
+                if (ok) {
+#pragma unroll
+                    for (int q = 1; q < CAP; ++q) {
+                        if (q < n) {
+                            const float ddx = xm - px[q];
+                            const float ddy = ym - py[q];
+                            const float r2 = ddx * ddx + ddy * ddy;
+                            ok = ok && !(r2 < 1.0f);
+                        }
+                    }
+                }
+                for (int k = 0; ok && k < KL; k += 4)
+                    ok = !(min_r2(xm, ym, nbr + k) < 1.0f);
+                if (kO > 0)
+                    for (int k = kL; ok && k < K4; k += 4)
+                        ok = !(min_r2(xm, ym, ovf + (k - kL)) < 1.0f);
+                ok = group_all<LPC>(ok);
+                if (ok) {
+                    px[0] = xm;
+                    py[0] = ym;
+                    if (has_acc) {
+                        ax[0] = ax[0] + dx;
+                        ay[0] = ay[0] + dy;
+                    }
+                    ++n_acc;
+                }
+                if (n > 1) {
+                    rrot(px, n);
+                    rrot(py, n);
+                    if (has_acc) {
+                        rrot(ax, n);
+                        rrot(ay, n);
+                    }
+                    if (has_tag) rrot(tg, n);
+                }
+            }
+            n_trials = (unsigned)n_moves;
+            // the group shares the writes: lane h stores list positions o
+            // with o mod LPC == h
+            const int r0 = n_moves % n;
+#pragma unroll
+            for (int q = 0; q < CAP; ++q) {
+                if (q < n) {
+                    int o = q + r0;
+                    o = o >= n ? o - n : o;
+                    if (o % LPC == h) {
+                        pos[b0 + o] = make_float2(px[q], py[q]);
+                        if (has_acc) acc[b0 + o] = make_float2(ax[q], ay[q]);
+                        if (has_tag && n > 1) tag[b0 + o] = tg[q];
+                    }
+                }
+            }
+            if (h != 0) n_trials = n_acc = 0;   // counted once per cell
+        }
+    }
+    __syncthreads();
+    unsigned *red = reinterpret_cast<unsigned *>(lds);
+    const unsigned bt = block_sum_u32(n_trials, red);
+    const unsigned ba = block_sum_u32(n_acc, red + 16);
+    if (threadIdx.x == 0 && tile < ntile && bt) {
+        const long long gr = slot0 / kGranule;
+        atomicAdd(&cnt[gr], (unsigned long long)bt);
+        atomicAdd(&cnt[cnt_stride + gr], (unsigned long long)ba);
+    }
+}
+
 // One workgroup per replica: add its granules' partials into its control
 // block and clear them.
 __global__ void __launch_bounds__(256) k_fold_counters(Tables t, unsigned long long *cnt, int stride)
@@ -1046,26 +1317,40 @@ inline int per_xcd(int ntile) { return (ntile + 7) / 8; }
 // Workgroup size of the sub-sweep: the requested one, reduced if the LDS
 // neighbour rows would exceed 64 KB (they do not for rows of 17 float2);
 // always one of 64, 128, 192, 256, so it divides the active chunk.
-int subsweep_block(int cap, int block)
+int subsweep_block(int cap, int block, int lanes)
 {
-    const int row = (8 * cap < kNbrLds ? 8 * cap : kNbrLds) + 1;
+    const int e = 8 / lanes * cap;
+    const int row = (e < kNbrLds ? e : kNbrLds) + 1;
     const int fit = (65536 / (row * (int)sizeof(float2))) / 64 * 64;
     return block < fit ? block : fit;
 }
 
 hipError_t launch_subsweep(const Tables &t, float2 *pos, const uint32_t *start, float2 *acc,
-                           uint32_t *tag, const Work &w, int set, int block, hipStream_t st)
+                           uint32_t *tag, const Work &w, int set, int block, int lanes,
+                           hipStream_t st)
 {
-    block = subsweep_block(t.cap, block);
-    if (block < 64 || block > 256 || block % 64 || kActiveChunk % block) return hipErrorInvalidValue;
-    const int ntile = tiles_for(t.active, block);
+    if (lanes != 1 && lanes != 2 && lanes != 4) return hipErrorInvalidValue;
+    block = subsweep_block(t.cap, block, lanes);
+    if (block < 64 || block > 256 || block % 64 || (kActiveChunk * lanes) % block)
+        return hipErrorInvalidValue;
+    const int ntile = tiles_for(t.active * lanes, block);
     const int per = per_xcd(ntile);
     const dim3 grid(8 * per), blk(block);
-    const int row = (8 * t.cap < kNbrLds ? 8 * t.cap : kNbrLds) + 1;
+    const int e = 8 / lanes * t.cap;
+    const int row = (e < kNbrLds ? e : kNbrLds) + 1;
     const size_t lds = (size_t)row * block * sizeof(float2);
 #define MPMC_SUB(CAP)                                                                          \
-    hipLaunchKernelGGL(k_subsweep<CAP>, grid, blk, lds, st, t, pos, start, acc, tag, w.cnt,     \
-                       w.cnt_stride, w.ovf, set, ntile, per)
+    do {                                                                                       \
+        if (lanes == 1)                                                                        \
+            hipLaunchKernelGGL(k_subsweep<CAP>, grid, blk, lds, st, t, pos, start, acc, tag,    \
+                               w.cnt, w.cnt_stride, w.ovf, set, ntile, per);                    \
+        else if (lanes == 2)                                                                   \
+            hipLaunchKernelGGL((k_subsweep_mc<CAP, 2>), grid, blk, lds, st, t, pos, start, acc, \
+                               tag, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);               \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_subsweep_mc<CAP, 4>), grid, blk, lds, st, t, pos, start, acc, \
+                               tag, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);               \
+    } while (0)
     switch (t.cap) {
     case 4: MPMC_SUB(4); break;
     case 5: MPMC_SUB(5); break;

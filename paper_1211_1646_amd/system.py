@@ -112,6 +112,7 @@ class HardDiskSystem:
                                           C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self._h = h
         self.block = 256
+        self.lanes = 1
 
     # ----------------------------------------------------------- lifecycle
     def close(self):
@@ -148,15 +149,20 @@ class HardDiskSystem:
 
     def set_launch(self, lanes_per_cell: int = 1, block_size: int = 256):
         L.check(self.lib.mpmc_set_launch(self._h, int(lanes_per_cell), int(block_size)))
+        self.lanes = int(lanes_per_cell)
         self.block = int(block_size)
 
+    AUTOTUNE_CANDIDATES = 12   # lanes {1, 2, 4} x workgroup {64, 128, 192, 256}
+
     def autotune(self, sweeps: int = 32):
-        """Pick the fastest sub-sweep workgroup size (results are identical
-        for every shape); returns (block, microseconds per sweep)."""
-        b, us = C.c_int32(), C.c_double()
-        L.check(self.lib.mpmc_autotune(self._h, int(sweeps), C.byref(b), C.byref(us)))
+        """Pick the fastest sub-sweep launch shape (results are identical for
+        every shape); the chain advances by 2 * sweeps per candidate.
+        Returns (lanes per cell, workgroup size, microseconds per sweep)."""
+        l, b, us = C.c_int32(), C.c_int32(), C.c_double()
+        L.check(self.lib.mpmc_autotune(self._h, int(sweeps), C.byref(l), C.byref(b), C.byref(us)))
+        self.lanes = int(l.value)
         self.block = int(b.value)
-        return self.block, us.value
+        return self.lanes, self.block, us.value
 
     def synchronize(self):
         L.check(self.lib.mpmc_synchronize(self._h))
@@ -253,6 +259,7 @@ class HardDiskBatch:
                                          C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self._h = h
         self.block = 256
+        self.lanes = 1
         self.R = len(self.cfgs)
         self.geometries = []
         for r in range(self.R):
@@ -285,6 +292,7 @@ class HardDiskBatch:
     tune = HardDiskSystem.tune
     set_launch = HardDiskSystem.set_launch
     autotune = HardDiskSystem.autotune
+    AUTOTUNE_CANDIDATES = HardDiskSystem.AUTOTUNE_CANDIDATES
     synchronize = HardDiskSystem.synchronize
     set_delta = HardDiskSystem.set_delta
     reset_acc = HardDiskSystem.reset_acc

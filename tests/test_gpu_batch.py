@@ -120,15 +120,15 @@ def test_batch_subsweeps_and_explicit_shifts(gpu):
         assert_replica(B, r, O, "subsweeps + shifts")
 
 
-@pytest.mark.parametrize("block", [64, 192])
-def test_batch_launch_shape_does_not_change_results(gpu, block):
+@pytest.mark.parametrize("lanes,block", [(1, 64), (1, 192), (2, 128), (4, 256)])
+def test_batch_launch_shape_does_not_change_results(gpu, lanes, block):
     B = gpu.HardDiskBatch(configs(gpu, MIXED, seed=7))
     Os = oracles(MIXED, seed=7)
-    B.set_launch(1, block)
+    B.set_launch(lanes, block)
     B.sweep(18)
     for r, O in enumerate(Os):
         O.sweep(18)
-        assert_replica(B, r, O, "block %d" % block)
+        assert_replica(B, r, O, "lanes %d block %d" % (lanes, block))
 
 
 def test_batch_seed_delta_and_tuner(gpu):
@@ -228,12 +228,12 @@ def test_replica_recipe_batch_equals_sequential_single_runs(gpu):
     cfgs = configs(gpu, specs, flags=0)
     B = gpu.HardDiskBatch(cfgs)
     log("  batch of %d replicas, N = %d" % (B.R, B.N))
-    B.autotune(16)   # four candidates x (16 + 16) sweeps of the chain
+    B.autotune(16)   # every candidate runs 16 + 16 sweeps of the chain
     B.sweep(32)
     assert B.count_overlaps() == 0
     for r, cfg in enumerate(cfgs):
         S = gpu.HardDiskSystem(cfg)
-        S.sweep(4 * 32 + 32)
+        S.sweep(B.AUTOTUNE_CANDIDATES * 32 + 32)
         bx, bs, bsw = B.get_state(r)
         sx, ss, ssw = S.get_state()
         assert bsw == ssw

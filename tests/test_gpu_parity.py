@@ -162,20 +162,42 @@ def test_graph_path_matches_eager_path(gpu):
     assert_same(G1, O, "graph odd")
 
 
+@pytest.mark.parametrize("lanes", [1, 2, 4])
 @pytest.mark.parametrize("block", [64, 128, 192, 256])
-def test_launch_shape_does_not_change_results(gpu, block):
+def test_launch_shape_does_not_change_results(gpu, lanes, block):
     G, O = lattice_pair(gpu, 40, 40, 0.70, math.sqrt(2.0), delta=0.15, seed=9)
-    G.set_launch(1, block)
+    G.set_launch(lanes, block)
     G.sweep(20)
     O.sweep(20)
-    assert_same(G, O, "block %d" % block)
+    assert_same(G, O, "lanes %d block %d" % (lanes, block))
+
+
+@pytest.mark.parametrize("lanes", [2, 4])
+@pytest.mark.parametrize("nx,ny,phi,w_max", CONFIGS)
+def test_lane_groups_match_for_every_capacity(gpu, lanes, nx, ny, phi, w_max):
+    """Lane groups on capacities 4-7 and n_M from 0 to 9: single sub-sweeps
+    and whole sweeps bit-exact."""
+    G, O = lattice_pair(gpu, nx, ny, phi, w_max, delta=0.2)
+    O.sweep(5)
+    G, O = grid_pair(gpu, O, delta=0.2)
+    G.set_launch(lanes, 128)
+    for Q in (3, 1, 0, 2):
+        G.subsweep(Q)
+        O.subsweep(Q)
+        assert_same(G, O, "lanes %d subsweep %d" % (lanes, Q))
+    for n_moves in (0, 1, 6, 9):
+        Gm, Om = lattice_pair(gpu, nx, ny, phi, w_max, delta=0.17, n_moves=n_moves, seed=n_moves + 2)
+        Gm.set_launch(lanes, 64)
+        Gm.sweep(17)
+        Om.sweep(17)
+        assert_same(Gm, Om, "lanes %d n_M %d" % (lanes, n_moves))
 
 
 def test_autotune_leaves_the_chain_alone(gpu):
     G, O = lattice_pair(gpu, 64, 64, 0.70, math.sqrt(2.0), delta=0.12, seed=6)
-    block, us = G.autotune(16)
-    assert block in (64, 128, 192, 256) and us > 0
-    O.sweep(4 * 2 * 16)
+    lanes, block, us = G.autotune(16)
+    assert lanes in (1, 2, 4) and block in (64, 128, 192, 256) and us > 0
+    O.sweep(G.AUTOTUNE_CANDIDATES * 2 * 16)
     assert_same(G, O, "autotuned")
     G.sweep(20)
     O.sweep(20)
