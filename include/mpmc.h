@@ -64,6 +64,7 @@ typedef int32_t mpmc_status;
 
 #define MPMC_FLAG_ACC 1u   /* keep per-disk displacement accumulators (MSD) */
 #define MPMC_FLAG_TAG 2u   /* keep per-disk identity tags */
+#define MPMC_FLAG_ACCEPT_LOG 4u /* keep per-cell accept bits of the latest update */
 
 #define MPMC_HIST_BINS 200 /* contact histogram: 200 bins of 1e-4 sigma */
 
@@ -111,6 +112,7 @@ typedef struct mpmc_buffer_sizes {
     size_t work;  /* scratch: scan partials and reductions                     */
     size_t ctl;   /* control block: sweep counter, key, delta, counters,
                      error word, contact histogram                             */
+    size_t accept_log; /* uint32 per cell (MPMC_FLAG_ACCEPT_LOG), else 0        */
 } mpmc_buffer_sizes;
 
 /* Device pointers, each 256-byte aligned, sizes as reported above. */
@@ -121,6 +123,7 @@ typedef struct mpmc_buffers {
     void *tag[2];   /* NULL unless MPMC_FLAG_TAG */
     void *work;
     void *ctl;
+    void *accept_log; /* NULL unless MPMC_FLAG_ACCEPT_LOG */
 } mpmc_buffers;
 
 /* Geometry of a parameter set (Sec. 3.1, Fig. 3).  Host only, no GPU use.
@@ -224,6 +227,14 @@ mpmc_status mpmc_replica_set_state(mpmc_handle h, int32_t r, const float *xy,
 /* Copy accumulators acc[2N] and tags[N] to host memory (sync), list order. */
 mpmc_status mpmc_get_aux(mpmc_handle h, float *acc, uint32_t *tags);
 mpmc_status mpmc_replica_get_aux(mpmc_handle h, int32_t r, float *acc, uint32_t *tags);
+
+/* Accept bits (MPMC_FLAG_ACCEPT_LOG; Alg. 2's accept decisions): bits[c],
+ * c over the cells in row-major order, has bit s set when trial s (s < 32)
+ * of cell c's latest update was accepted.  A sweep updates every cell once,
+ * so after a sweep this is that sweep's accept/reject sequence of every cell
+ * in the grid before its shift; empty cells give 0 (sync). */
+mpmc_status mpmc_get_accept_log(mpmc_handle h, uint32_t *bits);
+mpmc_status mpmc_replica_get_accept_log(mpmc_handle h, int32_t r, uint32_t *bits);
 
 /* Clear the displacement accumulators of every replica (async). */
 mpmc_status mpmc_reset_acc(mpmc_handle h);

@@ -85,6 +85,7 @@ def lib():
                          ("oracle_get_counters", [vp, u64p, u64p]),
                          ("oracle_get_state", [vp, f32p, u32p, u64p]),
                          ("oracle_get_aux", [vp, f32p, u32p]),
+                         ("oracle_get_accept_log", [vp, u32p]),
                          ("oracle_reset_acc", [vp]),
                          ("oracle_hist_edges", [f32p])]:
             getattr(L, name).argtypes = at
@@ -306,6 +307,13 @@ class OracleSystem:
 
     def reset_acc(self):
         lib().oracle_reset_acc(self._h)
+
+    def accept_log(self):
+        """Bit s of entry c: trial s (s < 32) of cell c's latest update was
+        accepted (row-major cells)."""
+        out = np.zeros(self.mx * self.my, np.uint32)
+        lib().oracle_get_accept_log(self._h, _ptr(out, C.c_uint32))
+        return out
 
     def count_overlaps(self):
         return int(lib().oracle_count_overlaps(self._h))

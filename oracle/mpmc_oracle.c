@@ -203,6 +203,9 @@ typedef struct oracle_sys {
     float *acc_x, *acc_y, *dacc_x, *dacc_y;
     uint32_t *tag, *dtag;
     int *n, *n_dbl;
+    /* bit s of accept_bits[c]: trial s (s < 32) of the cell's latest update
+     * was accepted; a sweep updates every cell once */
+    uint32_t *accept_bits;
 } oracle_sys;
 
 #define FLAG_ACC 1
@@ -234,6 +237,7 @@ static oracle_sys *alloc_sys(int mx, int my, float wx, float wy, int cap,
     S->dtag = (uint32_t *)xcalloc(slots, sizeof(uint32_t));
     S->n = (int *)xcalloc((size_t)S->C, sizeof(int));
     S->n_dbl = (int *)xcalloc((size_t)S->C, sizeof(int));
+    S->accept_bits = (uint32_t *)xcalloc((size_t)S->C, sizeof(uint32_t));
     return S;
 }
 
@@ -243,6 +247,7 @@ void oracle_destroy(oracle_sys *S)
     free(S->disk_x); free(S->disk_y); free(S->dbl_x); free(S->dbl_y);
     free(S->acc_x); free(S->acc_y); free(S->dacc_x); free(S->dacc_y);
     free(S->tag); free(S->dtag); free(S->n); free(S->n_dbl);
+    free(S->accept_bits);
     free(S);
 }
 
@@ -394,6 +399,7 @@ static void cell_update(oracle_sys *S, int cx, int cy)
 {
     int c = cy * S->mx + cx;
     int n = S->n[c];
+    S->accept_bits[c] = 0;
     if (n == 0) return; /* nothing to move (Alg. 2) */
     int base = c * S->cap;
     uint32_t words[4];
@@ -425,8 +431,15 @@ static void cell_update(oracle_sys *S, int cx, int cy)
                 S->acc_y[slot] = S->acc_y[slot] + dy;
             }
             S->accepts += 1;
+            if (s < 32) S->accept_bits[c] |= 1u << s;
         }
     }
+}
+
+/* The accept bits of every cell (C entries, row-major cells). */
+void oracle_get_accept_log(const oracle_sys *S, uint32_t *out)
+{
+    memcpy(out, S->accept_bits, sizeof(uint32_t) * (size_t)S->C);
 }
 
 /* Sub-sweep over checkerboard set Q (Eq. 1): cells with (cx mod 2) + 2 (cy

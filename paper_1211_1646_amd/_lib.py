@@ -20,6 +20,7 @@ MPMC_EDEVICE = -5
 MPMC_ESTATE = -6
 FLAG_ACC = 1
 FLAG_TAG = 2
+FLAG_ACCEPT_LOG = 4
 HIST_BINS = 200
 MLP_PARAMS = 1217
 
@@ -44,12 +45,14 @@ class Geometry(C.Structure):
 
 class BufferSizes(C.Structure):
     _fields_ = [("pos", C.c_size_t), ("start", C.c_size_t), ("acc", C.c_size_t),
-                ("tag", C.c_size_t), ("work", C.c_size_t), ("ctl", C.c_size_t)]
+                ("tag", C.c_size_t), ("work", C.c_size_t), ("ctl", C.c_size_t),
+                ("accept_log", C.c_size_t)]
 
 
 class Buffers(C.Structure):
     _fields_ = [("pos", C.c_void_p * 2), ("start", C.c_void_p * 2), ("acc", C.c_void_p * 2),
-                ("tag", C.c_void_p * 2), ("work", C.c_void_p), ("ctl", C.c_void_p)]
+                ("tag", C.c_void_p * 2), ("work", C.c_void_p), ("ctl", C.c_void_p),
+                ("accept_log", C.c_void_p)]
 
 
 class MPMCError(RuntimeError):
@@ -104,6 +107,8 @@ _SIGNATURES = {
     "mpmc_replica_set_delta": (C.c_int32, [_H, C.c_int32, C.c_float]),
     "mpmc_replica_get_delta": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_float)]),
     "mpmc_batch_stats": (C.c_int32, [_H, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mpmc_get_accept_log": (C.c_int32, [_H, C.c_void_p]),
+    "mpmc_replica_get_accept_log": (C.c_int32, [_H, C.c_int32, C.c_void_p]),
     "mpmc_control": (C.c_int32, [_H, C.c_void_p, C.c_int32, C.c_int32]),
     "mpmc_mlp_work_bytes": (C.c_int32, [C.c_int32, C.POINTER(C.c_size_t)]),
     "mpmc_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,

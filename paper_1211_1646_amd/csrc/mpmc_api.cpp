@@ -145,7 +145,8 @@ mpmc_status check_params(const mpmc_params *p, const mpmc_geometry &g)
     if (!(p->delta > 0.0f) || p->delta > 0.5f * std::min(g.w_x, g.w_y))
         return fail(MPMC_EINVAL, "delta must lie in (0, min(w)/2]");
     if (p->n_moves < 0 || p->n_moves > (1 << 20)) return fail(MPMC_EINVAL, "n_moves out of range");
-    if (p->flags & ~(MPMC_FLAG_ACC | MPMC_FLAG_TAG)) return fail(MPMC_EINVAL, "unknown flag");
+    if (p->flags & ~(MPMC_FLAG_ACC | MPMC_FLAG_TAG | MPMC_FLAG_ACCEPT_LOG))
+        return fail(MPMC_EINVAL, "unknown flag");
     return MPMC_OK;
 }
 
@@ -242,6 +243,7 @@ mpmc_status sizes_of(const mpmc_params *p, int n, mpmc_buffer_sizes *out)
     out->tag = (p[0].flags & MPMC_FLAG_TAG) ? align256(std::max<size_t>(4 * (size_t)L.N, 4)) : 0;
     out->work = work_bytes(L);
     out->ctl = ctl_layout(L).total;
+    out->accept_log = (p[0].flags & MPMC_FLAG_ACCEPT_LOG) ? align256(4 * (size_t)L.cells) : 0;
     return MPMC_OK;
 }
 
@@ -260,6 +262,7 @@ struct mpmc_system {
     int cur;
     int block;                    // sub-sweep workgroup size
     int lanes;                    // sub-sweep lanes per active cell
+    uint32_t *alog;               // per-cell accept bits, or null
     std::vector<uint32_t> key0;   // current key word 0 of each replica
     std::vector<char> loaded;     // replica holds a valid, overlap-free state
     bool ready;                   // every replica is loaded
@@ -302,7 +305,8 @@ mpmc_status read_ctl(mpmc_system *h)
 mpmc_status enqueue_subsweep(mpmc_system *h, int set)
 {
     MPMC_HIP(mpmc::launch_subsweep(h->t, h->pos[h->cur], h->start[h->cur], h->acc[h->cur],
-                                   h->tag[h->cur], h->work, set, h->block, h->lanes, h->st));
+                                   h->tag[h->cur], h->alog, h->work, set, h->block, h->lanes,
+                                   h->st));
     return MPMC_OK;
 }
 
@@ -496,6 +500,8 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
         if ((flags & MPMC_FLAG_TAG) && !b->tag[i]) return fail(MPMC_EINVAL, "tag buffers missing");
     }
     if (!b->work || !b->ctl) return fail(MPMC_EINVAL, "work/ctl buffers missing");
+    if ((flags & MPMC_FLAG_ACCEPT_LOG) && !b->accept_log)
+        return fail(MPMC_EINVAL, "accept_log buffer missing");
     // host-side states first, so that geometry errors allocate nothing
     std::vector<uint32_t> start_g((size_t)L.cells + 1);
     std::vector<float> xy_g(2 * (size_t)std::max(L.N, 1LL), 0.0f);
@@ -555,6 +561,7 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
     h->t.cells = L.cells;
     h->t.active = L.active;
     h->t.N = L.N;
+    h->alog = (flags & MPMC_FLAG_ACCEPT_LOG) ? (uint32_t *)b->accept_log : nullptr;
     h->cur = 0;
     h->block = 256;
     h->lanes = 1;
@@ -586,6 +593,7 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
     if (e == hipSuccess && h->acc[0]) e = mpmc::launch_fill_u32((uint32_t *)h->acc[0], 0u, 2 * L.N, h->st);
     if (e == hipSuccess)
         e = mpmc::launch_fill_u32((uint32_t *)h->work.cnt, 0u, 4LL * h->work.cnt_stride, h->st);
+    if (e == hipSuccess && h->alog) e = mpmc::launch_fill_u32(h->alog, 0u, L.cells, h->st);
     if (e == hipSuccess) e = mpmc::launch_ctl_reset(h->t, -1, 0, h->st);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     if (e != hipSuccess) {
@@ -826,6 +834,23 @@ mpmc_status mpmc_get_aux(mpmc_handle h, float *acc, uint32_t *tags)
 {
     MPMC_NEED_SINGLE(h);
     return mpmc_replica_get_aux(h, 0, acc, tags);
+}
+
+mpmc_status mpmc_replica_get_accept_log(mpmc_handle h, int32_t r, uint32_t *bits)
+{
+    MPMC_NEED_LOADED(h, r);
+    if (!bits) return fail(MPMC_EINVAL, "null argument");
+    if (!h->alog) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_ACCEPT_LOG");
+    const Rep &R = h->L.reps[(size_t)r];
+    MPMC_HIP(hipMemcpyAsync(bits, h->alog + R.cb, sizeof(uint32_t) * (size_t)R.g.C,
+                            hipMemcpyDeviceToHost, h->st));
+    return read_ctl(h);
+}
+
+mpmc_status mpmc_get_accept_log(mpmc_handle h, uint32_t *bits)
+{
+    MPMC_NEED_SINGLE(h);
+    return mpmc_replica_get_accept_log(h, 0, bits);
 }
 
 mpmc_status mpmc_reset_acc(mpmc_handle h)

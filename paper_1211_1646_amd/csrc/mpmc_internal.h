@@ -112,9 +112,10 @@ inline int ovf_per_slot(int cap) { return 8 * cap > kNbrLds ? 8 * cap - kNbrLds 
 // set < 0 is each replica's slot (-1 - set) of its own shuffled set order.
 // lanes (1, 2 or 4) lanes work on each active cell; the workgroup size is
 // 64, 128, 192 or 256 lanes (reduced if the LDS rows would not fit).
+// alog (may be null): per-cell accept bits of this launch's active cells.
 hipError_t launch_subsweep(const Tables &t, float2 *pos, const uint32_t *start, float2 *acc,
-                           uint32_t *tag, const Work &w, int set, int block, int lanes,
-                           hipStream_t st);
+                           uint32_t *tag, uint32_t *alog, const Work &w, int set, int block,
+                           int lanes, hipStream_t st);
 // Add the counter partials into each replica's control block; clear them.
 hipError_t launch_fold_counters(const Tables &t, const Work &w, hipStream_t st);
 // Shift (f, d) -- or each replica's own draws when f < 0 -- and rebuild the

@@ -270,7 +270,7 @@ __device__ __forceinline__ float min_r2(float xm, float ym, const float2 *e)
 template <int CAP>
 __global__ void __launch_bounds__(256)
 k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
-           float2 *__restrict__ acc, uint32_t *__restrict__ tag,
+           float2 *__restrict__ acc, uint32_t *__restrict__ tag, uint32_t *__restrict__ alog,
            unsigned long long *__restrict__ cnt, int cnt_stride, float2 *__restrict__ ovf_all,
            int set, int ntile, int per)
 {
@@ -304,10 +304,13 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
     const uint32_t *const st = start + R.cb;        // this replica's offsets
 
     unsigned n_trials = 0, n_acc = 0;
+    uint32_t abits = 0;
+    long long log_cell = -1;   // global cell index of this lane's cell, if any
     if (tile < ntile && gid < (long long)hx * hy) {
         const int iy = (int)(gid / hx), ix = (int)(gid - (long long)iy * hx);
         const int cx = 2 * ix + qx, cy = 2 * iy + qy;
         const int c = cy * g.mx + cx;
+        log_cell = R.cb + c;
         const int xl = cx == 0 ? g.mx - 1 : cx - 1;
         const int xr = cx == g.mx - 1 ? 0 : cx + 1;
         const int yd = cy == 0 ? g.my - 1 : cy - 1;
@@ -464,6 +467,7 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
                     for (int k = kL; ok && k < K4; k += 4)
                         ok = !(min_r2(xm, ym, ovf + (k - kL)) < 1.0f);
                 if (ok) {
+                    if (tr < 32) abits |= 1u << tr;
                     px[0] = xm;
                     py[0] = ym;
                     if (has_acc) {
@@ -501,6 +505,7 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
     // its first slot.  Each granule entry belongs to one workgroup of a
     // launch, so the adds never contend; the partials are folded into the
     // control blocks on demand.
+    if (alog && log_cell >= 0) alog[log_cell] = abits;
     __syncthreads();   // every lane is done with its neighbour table
     unsigned *red = reinterpret_cast<unsigned *>(lds);
     const unsigned bt = block_sum_u32(n_trials, red);
@@ -555,7 +560,7 @@ __device__ __forceinline__ bool group_any(bool v)
 template <int CAP, int LPC>
 __global__ void __launch_bounds__(256)
 k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
-              float2 *__restrict__ acc, uint32_t *__restrict__ tag,
+              float2 *__restrict__ acc, uint32_t *__restrict__ tag, uint32_t *__restrict__ alog,
               unsigned long long *__restrict__ cnt, int cnt_stride, float2 *__restrict__ ovf_all,
               int set, int ntile, int per)
 {
@@ -589,10 +594,13 @@ k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ s
     const uint32_t *const st = start + R.cb;
 
     unsigned n_trials = 0, n_acc = 0;
+    uint32_t abits = 0;
+    long long log_cell = -1;   // global cell index of this lane's cell, if any
     if (tile < ntile && gid < (long long)hx * hy) {
         const int iy = (int)(gid / hx), ix = (int)(gid - (long long)iy * hx);
         const int cx = 2 * ix + qx, cy = 2 * iy + qy;
         const int c = cy * g.mx + cx;
+        log_cell = R.cb + c;
         const int xl = cx == 0 ? g.mx - 1 : cx - 1;
         const int xr = cx == g.mx - 1 ? 0 : cx + 1;
         const int yd = cy == 0 ? g.my - 1 : cy - 1;
@@ -736,6 +744,7 @@ k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ s
                         ok = !(min_r2(xm, ym, ovf + (k - kL)) < 1.0f);
                 ok = group_all<LPC>(ok);
                 if (ok) {
+                    if (tr < 32) abits |= 1u << tr;
                     px[0] = xm;
                     py[0] = ym;
                     if (has_acc) {
@@ -773,6 +782,7 @@ k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ s
             if (h != 0) n_trials = n_acc = 0;   // counted once per cell
         }
     }
+    if (alog && log_cell >= 0 && h == 0) alog[log_cell] = abits;
     __syncthreads();
     unsigned *red = reinterpret_cast<unsigned *>(lds);
     const unsigned bt = block_sum_u32(n_trials, red);
@@ -931,10 +941,25 @@ __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
         }
         return;
     }
-    // offset of this tile: the replica's first disk plus its earlier tiles
+    // offset of this tile: the replica's first disk plus its earlier tiles.
+    // Sixteen totals per thread are loaded at once (indices clamped to the
+    // last earlier tile, the excess masked), so up to 4096 earlier tiles cost
+    // one memory round trip rather than one per sixteenth of them.
     unsigned pre = 0;
-    if (tile < a.ntile)
-        for (long long i = R.cb / kRebinTile + threadIdx.x; i < tile; i += kRebinTile) pre += a.part[i];
+    if (tile < a.ntile) {
+        const long long first = R.cb / kRebinTile;
+        for (long long base = first; base < tile; base += 16LL * kRebinTile) {
+            unsigned v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const long long i = base + threadIdx.x + (long long)u * kRebinTile;
+                v[u] = a.part[i < tile ? i : tile - 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                pre += (base + threadIdx.x + (long long)u * kRebinTile < tile) ? v[u] : 0u;
+        }
+    }
     const unsigned before = block_sum_u32(pre, red);
     unsigned total;
     const unsigned off = block_exclusive_scan_u32(cnt, red, &total);
@@ -1326,8 +1351,8 @@ int subsweep_block(int cap, int block, int lanes)
 }
 
 hipError_t launch_subsweep(const Tables &t, float2 *pos, const uint32_t *start, float2 *acc,
-                           uint32_t *tag, const Work &w, int set, int block, int lanes,
-                           hipStream_t st)
+                           uint32_t *tag, uint32_t *alog, const Work &w, int set, int block,
+                           int lanes, hipStream_t st)
 {
     if (lanes != 1 && lanes != 2 && lanes != 4) return hipErrorInvalidValue;
     block = subsweep_block(t.cap, block, lanes);
@@ -1343,13 +1368,13 @@ hipError_t launch_subsweep(const Tables &t, float2 *pos, const uint32_t *start, 
     do {                                                                                       \
         if (lanes == 1)                                                                        \
             hipLaunchKernelGGL(k_subsweep<CAP>, grid, blk, lds, st, t, pos, start, acc, tag,    \
-                               w.cnt, w.cnt_stride, w.ovf, set, ntile, per);                    \
+                               alog, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);              \
         else if (lanes == 2)                                                                   \
             hipLaunchKernelGGL((k_subsweep_mc<CAP, 2>), grid, blk, lds, st, t, pos, start, acc, \
-                               tag, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);               \
+                               tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);         \
         else                                                                                   \
             hipLaunchKernelGGL((k_subsweep_mc<CAP, 4>), grid, blk, lds, st, t, pos, start, acc, \
-                               tag, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);               \
+                               tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);         \
     } while (0)
     switch (t.cap) {
     case 4: MPMC_SUB(4); break;

@@ -74,6 +74,7 @@ class _Buffers:
         self.t["tag"] = [buf(sizes["tag"]), buf(sizes["tag"])] if sizes["tag"] else None
         self.work = buf(sizes["work"])
         self.ctl = buf(sizes["ctl"])
+        self.alog = buf(sizes["accept_log"]) if sizes["accept_log"] else None
         b = L.Buffers()
         for i in range(2):
             b.pos[i] = self.t["pos"][i].data_ptr()
@@ -82,6 +83,7 @@ class _Buffers:
             b.tag[i] = self.t["tag"][i].data_ptr() if self.t["tag"] else None
         b.work = self.work.data_ptr()
         b.ctl = self.ctl.data_ptr()
+        b.accept_log = self.alog.data_ptr() if self.alog is not None else None
         self.c = b
 
     def __getitem__(self, k):
@@ -204,6 +206,12 @@ class HardDiskSystem:
 
     def reset_acc(self):
         L.check(self.lib.mpmc_reset_acc(self._h))
+
+    def accept_log(self):
+        """Per-cell accept bits of each cell's latest update (row-major)."""
+        out = np.zeros(self.C, np.uint32)
+        L.check(self.lib.mpmc_get_accept_log(self._h, out.ctypes.data))
+        return out
 
     def msd(self) -> float:
         v = C.c_double()
@@ -338,6 +346,11 @@ class HardDiskBatch:
                                               acc.ctypes.data if acc is not None and n else None,
                                               tag.ctypes.data if tag is not None and n else None))
         return acc, tag
+
+    def accept_log(self, r: int):
+        out = np.zeros(self._cells(r), np.uint32)
+        L.check(self.lib.mpmc_replica_get_accept_log(self._h, int(r), out.ctypes.data))
+        return out
 
     def msd(self, r: int) -> float:
         v = C.c_double()

@@ -254,3 +254,14 @@ def test_replica_recipe_small_replicas_match_oracle(gpu):
     for r, O in enumerate(Os):
         O.sweep(20)
         assert_replica(B, r, O, "recipe")
+
+
+def test_batch_accept_log_per_replica(gpu):
+    specs = MIXED[:4]
+    B = gpu.HardDiskBatch(configs(gpu, specs, flags=FLAGS | 4))
+    Os = oracles(specs, flags=FLAGS | 4)
+    for k in range(5):
+        B.sweep(1)
+        for r, O in enumerate(Os):
+            O.sweep(1)
+            assert np.array_equal(B.accept_log(r), O.accept_log()), (k, r)

@@ -345,3 +345,20 @@ def test_large_workload_full_size(gpu, phi):
     O.sweep(16)
     assert_same(G, O, "16 sweeps")
     assert G.count_overlaps() == O.count_overlaps() == 0
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+@pytest.mark.parametrize("nx,ny,phi,w_max", [(64, 64, 0.60, 0.0), (20, 20, 0.72, 1.932)])
+def test_accept_log_matches_every_sweep(gpu, lanes, nx, ny, phi, w_max):
+    """The accept/reject sequence of every cell, sweep after sweep, equals
+    the oracle's bit for bit (n_M = 4 and 9)."""
+    for n_moves in (4, 9):
+        G, O = lattice_pair(gpu, nx, ny, phi, w_max, delta=0.12, n_moves=n_moves, seed=5,
+                            flags=FLAGS | 4)
+        G.set_launch(lanes, 128)
+        for k in range(12):
+            G.sweep(1)
+            O.sweep(1)
+            gl, ol = G.accept_log(), O.accept_log()
+            assert np.array_equal(gl, ol), (k, int(np.argmax(gl != ol)))
+        assert_same(G, O, "accept log run")

@@ -341,3 +341,39 @@ def test_two_disk_separation_density():
     assert below == 0
     m, se = E.mean_and_error(inner, min_blocks=32)
     assert abs(m - 0.5) < max(4 * se, 0.01), (m, se)
+
+
+@pytest.mark.parametrize("n_moves", [1, 3])
+def test_accept_log_matches_what_moved(n_moves):
+    """The accept bits of a sub-sweep agree with what actually moved, an
+    observable the bits are not computed from: with one trial per cell, a
+    cell's multiset of positions changes iff its bit 0 is set (a proposal is
+    never zero); bits only occupy positions below n_M; empty active cells
+    log 0; the bits of the active cells add up to the accepted moves."""
+    O = OracleSystem.lattice(24, 24, 0.70, w_max=math.sqrt(2.0), delta=0.18, n_moves=n_moves,
+                             seed=3)
+    O.sweep(4)
+    for Q in (0, 3, 1, 2):
+        xy0, st0, _ = O.get_state()
+        a0 = O.counters()[1]
+        O.subsweep(Q)
+        xy1, st1, _ = O.get_state()
+        assert np.array_equal(st0, st1)
+        log = O.accept_log()
+        cnt = np.diff(st0.astype(np.int64))
+        active = np.zeros(O.mx * O.my, bool)
+        for c in range(O.mx * O.my):
+            cy, cx = divmod(c, O.mx)
+            active[c] = (cx & 1) + 2 * (cy & 1) == Q
+        moved_bits = 0
+        for c in np.nonzero(active)[0]:
+            bits = int(log[c])
+            assert bits >> n_moves == 0
+            if cnt[c] == 0:
+                assert bits == 0
+            moved_bits += bin(bits).count("1")
+            if n_moves == 1:
+                a = np.sort(xy0[st0[c]:st0[c + 1]].view(np.uint64).ravel())
+                b = np.sort(xy1[st1[c]:st1[c + 1]].view(np.uint64).ravel())
+                assert (bits & 1) == (0 if np.array_equal(a, b) else 1), c
+        assert moved_bits == O.counters()[1] - a0
