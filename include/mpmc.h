@@ -261,6 +261,13 @@ mpmc_status mpmc_get_delta(mpmc_handle h, float *delta);
 mpmc_status mpmc_replica_set_delta(mpmc_handle h, int32_t r, float delta);
 mpmc_status mpmc_replica_get_delta(mpmc_handle h, int32_t r, float *delta);
 
+/* n_M, the trial moves per active cell and sub-sweep (Alg. 1), of every
+ * replica or of replica r, from the next launch on (sync: waits for the
+ * stream, rewrites the replica table, re-captures the sweep graphs).  It
+ * changes the chain, as delta does; 0 <= n_moves <= 2^20. */
+mpmc_status mpmc_set_n_moves(mpmc_handle h, int32_t n_moves);
+mpmc_status mpmc_replica_set_n_moves(mpmc_handle h, int32_t r, int32_t n_moves);
+
 /* Plain acceptance-ratio tuner for equilibration (async): n_windows times,
  * run window_sweeps sweeps, then with a = accepts/trials of that window
  * set delta <- delta * clamp(a/0.3, 0.5, 2), clamped to [1e-3, min(w)/2],

@@ -108,6 +108,8 @@ _SIGNATURES = {
     "mpmc_replica_get_delta": (C.c_int32, [_H, C.c_int32, C.POINTER(C.c_float)]),
     "mpmc_batch_stats": (C.c_int32, [_H, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mpmc_get_accept_log": (C.c_int32, [_H, C.c_void_p]),
+    "mpmc_set_n_moves": (C.c_int32, [_H, C.c_int32]),
+    "mpmc_replica_set_n_moves": (C.c_int32, [_H, C.c_int32, C.c_int32]),
     "mpmc_replica_get_accept_log": (C.c_int32, [_H, C.c_int32, C.c_void_p]),
     "mpmc_control": (C.c_int32, [_H, C.c_void_p, C.c_int32, C.c_int32]),
     "mpmc_mlp_work_bytes": (C.c_int32, [C.c_int32, C.POINTER(C.c_size_t)]),

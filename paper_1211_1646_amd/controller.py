@@ -281,3 +281,31 @@ def equilibrate_and_measure(sys_, mode: str, net=None, eq_windows: int = 50,
             "msd": msd, "msd_per_s": msd / secs, "msd_per_sweep": msd / (per_block * blocks),
             "P": float(p_blocks.mean()),
             "P_se": float(p_blocks.std(ddof=1) / math.sqrt(len(p_blocks)))}
+
+
+def autotune_moves(sys_, candidates=(1, 2, 4, 8), window_sweeps: int = 64):
+    """Choose n_M (trial moves per active cell and sub-sweep) by mean-square
+    displacement per second: each candidate runs window_sweeps sweeps from
+    the state the previous one left, timed with HIP events on the system's
+    stream.  n_M changes the chain, so this belongs to equilibration, like
+    the delta tuners; every candidate's chain is a valid one.  The system
+    must keep displacement accumulators.  Returns (best n_M, {n_M: MSD/s})."""
+    import torch
+    rates = {}
+    for n in candidates:
+        sys_.set_n_moves(int(n))
+        sys_.sweep(16)                      # re-capture the graph
+        sys_.reset_acc()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        sys_.synchronize()
+        e0.record(sys_.stream)
+        sys_.sweep(window_sweeps)
+        e1.record(sys_.stream)
+        e1.synchronize()
+        secs = e0.elapsed_time(e1) * 1e-3
+        msd = sys_.msd() if not hasattr(sys_, "R") else sum(
+            g["n_particles"] * sys_.msd(r) for r, g in enumerate(sys_.geometries)) / sys_.N
+        rates[int(n)] = msd / secs
+    best = max(rates, key=rates.get)
+    sys_.set_n_moves(best)
+    return best, rates

@@ -939,6 +939,36 @@ mpmc_status mpmc_set_delta(mpmc_handle h, float delta)
     return MPMC_OK;
 }
 
+// n_M lives in the replica table (and, for replica 0, in the kernel
+// arguments captured by the sweep graphs): rewrite both, drop the graphs.
+static mpmc_status set_n_moves(mpmc_system *h, int r0, int r1, int32_t n_moves)
+{
+    if (n_moves < 0 || n_moves > (1 << 20)) return fail(MPMC_EINVAL, "n_moves out of range");
+    MPMC_HIP(hipStreamSynchronize(h->st));   // no launch in flight reads the table
+    for (int r = r0; r < r1; ++r) {
+        h->L.reps[(size_t)r].n_moves = n_moves;
+        h->p[(size_t)r].n_moves = n_moves;
+        MPMC_HIP(hipMemcpyAsync((Rep *)h->t.reps + r, &h->L.reps[(size_t)r], sizeof(Rep),
+                                hipMemcpyHostToDevice, h->st));
+    }
+    h->t.rep0 = h->L.reps[0];
+    drop_graphs(h);
+    MPMC_HIP(hipStreamSynchronize(h->st));
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_set_n_moves(mpmc_handle h, int32_t n_moves)
+{
+    if (!h) return fail(MPMC_EINVAL, "null handle");
+    return set_n_moves(h, 0, h->R(), n_moves);
+}
+
+mpmc_status mpmc_replica_set_n_moves(mpmc_handle h, int32_t r, int32_t n_moves)
+{
+    MPMC_NEED_REPLICA(h, r);
+    return set_n_moves(h, r, r + 1, n_moves);
+}
+
 mpmc_status mpmc_replica_get_delta(mpmc_handle h, int32_t r, float *delta)
 {
     MPMC_NEED_REPLICA(h, r);

@@ -179,6 +179,10 @@ class HardDiskSystem:
     def set_delta(self, delta: float):
         L.check(self.lib.mpmc_set_delta(self._h, float(np.float32(delta))))
 
+    def set_n_moves(self, n_moves: int):
+        """Trial moves per active cell and sub-sweep (changes the chain)."""
+        L.check(self.lib.mpmc_set_n_moves(self._h, int(n_moves)))
+
     # --------------------------------------------------------------- state
     def get_state(self):
         xy = np.empty((self.N, 2), np.float32)
@@ -303,6 +307,10 @@ class HardDiskBatch:
     AUTOTUNE_CANDIDATES = HardDiskSystem.AUTOTUNE_CANDIDATES
     synchronize = HardDiskSystem.synchronize
     set_delta = HardDiskSystem.set_delta
+    set_n_moves = HardDiskSystem.set_n_moves
+
+    def set_replica_n_moves(self, r: int, n_moves: int):
+        L.check(self.lib.mpmc_replica_set_n_moves(self._h, int(r), int(n_moves)))
     reset_acc = HardDiskSystem.reset_acc
     count_overlaps = HardDiskSystem.count_overlaps
     counters = HardDiskSystem.counters

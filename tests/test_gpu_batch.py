@@ -265,3 +265,18 @@ def test_batch_accept_log_per_replica(gpu):
         for r, O in enumerate(Os):
             O.sweep(1)
             assert np.array_equal(B.accept_log(r), O.accept_log()), (k, r)
+
+
+def test_batch_replica_n_moves(gpu):
+    specs = MIXED[:3]
+    B = gpu.HardDiskBatch(configs(gpu, specs))
+    Os = oracles(specs)
+    B.sweep(5)
+    B.set_replica_n_moves(1, 5)
+    B.sweep(17)
+    for r, O in enumerate(Os):
+        O.sweep(5)
+        if r == 1:
+            O.set_n_moves(5)
+        O.sweep(17)
+        assert_replica(B, r, O, "replica n_M")

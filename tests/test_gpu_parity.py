@@ -362,3 +362,16 @@ def test_accept_log_matches_every_sweep(gpu, lanes, nx, ny, phi, w_max):
             gl, ol = G.accept_log(), O.accept_log()
             assert np.array_equal(gl, ol), (k, int(np.argmax(gl != ol)))
         assert_same(G, O, "accept log run")
+
+
+def test_n_moves_change_mid_run(gpu):
+    """n_M changed between sweeps (graphs re-captured) on both sides."""
+    G, O = lattice_pair(gpu, 32, 32, 0.70, math.sqrt(2.0), delta=0.15, n_moves=4, seed=13)
+    G.sweep(17)
+    O.sweep(17)
+    for n in (1, 7, 4):
+        G.set_n_moves(n)
+        O.set_n_moves(n)
+        G.sweep(18)
+        O.sweep(18)
+        assert_same(G, O, "n_M %d" % n)
