@@ -254,6 +254,29 @@ __device__ __forceinline__ unsigned block_exclusive_scan_u32(unsigned v, unsigne
 constexpr float kReach2 = 1.0001f;
 constexpr float kReachEdge = 1.0001f;
 
+// Neighbour disk p of the cell in row ra, column cb (0, 1, 2 = -1, 0, +1) of
+// the 3x3 block, translated into the centre cell's frame by exactly -w, 0 or
+// +w (adding 0 is skipped: x + 0 == x for x > 0), and whether it can reach
+// the centre cell: one comparison for an edge cell, the distance to the
+// shared corner for a corner cell.
+__device__ __forceinline__ float2 frame_of(float2 p, int ra, int cb, float wx, float wy,
+                                           bool &reach)
+{
+    float ox = p.x, oy = p.y;
+    if (cb == 0) ox = ox - wx;
+    if (cb == 2) ox = ox + wx;
+    if (ra == 0) oy = oy - wy;
+    if (ra == 2) oy = oy + wy;
+    if (ra == 1) reach = cb == 0 ? ox > -kReachEdge : ox < wx + kReachEdge;
+    else if (cb == 1) reach = ra == 0 ? oy > -kReachEdge : oy < wy + kReachEdge;
+    else {
+        const float ex = cb == 0 ? -ox : ox - wx;
+        const float ey = ra == 0 ? -oy : oy - wy;
+        reach = ex * ex + ey * ey < kReach2;
+    }
+    return make_float2(ox, oy);
+}
+
 // Smallest r^2 from (xm, ym) to four neighbour entries; any r^2 < 1 iff the
 // smallest is (all values finite).
 __device__ __forceinline__ float min_r2(float xm, float ym, const float2 *e)
@@ -374,49 +397,48 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
             if (n > 1) Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle, k0, k1);
             uint4 W = make_uint4(0, 0, 0, 0);
             if (n_moves > 0) W = philox((uint32_t)c, s_lo, s_hi, 0u, k0, k1);
-            // 3. translate into the cell's frame (x - w, x or x + w: adding
-            // the exact translation 0 is skipped, x + 0 == x for x > 0), keep
-            // the disks that can reach the cell, compact them into LDS.  The
-            // reach test per neighbour: one comparison for the four edge
-            // cells, the distance to the shared corner for the four corners.
+            // 3. translate into the cell's frame, keep the disks that can
+            // reach the cell, compact them into the lane's LDS row.  The
+            // common path has no branch: an index past kL lands on the row's
+            // pad slot kL, which is never read; a lane with more than kL
+            // reachable neighbours writes the rest to its overflow entries in
+            // a second pass, taken only where needed.
             int K = 0;
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
                 if (q == 4) continue;
-                const int ra = q / 3, cb = q % 3;
 #pragma unroll
                 for (int i = 0; i < CAP; ++i) {
-                    float ox = nv[q][i].x, oy = nv[q][i].y;
-                    if (cb == 0) ox = ox - g.wx;
-                    if (cb == 2) ox = ox + g.wx;
-                    if (ra == 0) oy = oy - g.wy;
-                    if (ra == 2) oy = oy + g.wy;
                     bool reach;
-                    if (ra == 1) reach = cb == 0 ? ox > -kReachEdge : ox < g.wx + kReachEdge;
-                    else if (cb == 1) reach = ra == 0 ? oy > -kReachEdge : oy < g.wy + kReachEdge;
-                    else {
-                        const float ex = cb == 0 ? -ox : ox - g.wx;
-                        const float ey = ra == 0 ? -oy : oy - g.wy;
-                        reach = ex * ex + ey * ey < kReach2;
-                    }
-                    // entry K <= slots seen so far < 8 CAP
-                    const float2 v = make_float2(ox, oy);
-                    if (kO == 0 || K < kL) nbr[K] = v;
-                    else ovf[K - kL] = v;
+                    const float2 v = frame_of(nv[q][i], q / 3, q % 3, g.wx, g.wy, reach);
+                    nbr[K < kL ? K : kL] = v;
                     K += (i < (int)rn[q] && reach) ? 1 : 0;
                 }
             }
-            // pad to a multiple of four with a disk that overlaps nothing;
-            // the padded rows stay below 8 * CAP because K <= 8 * CAP
+            // pad to a multiple of four with a disk that overlaps nothing
+            // (entries stay below 8 CAP because K <= 8 CAP, a multiple of four)
             const int K4 = (K + 3) & ~3;
             const float2 far = make_float2(1.0e6f, 1.0e6f);
 #pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                const int k = K + e;
-                if (k < K4) {
-                    if (kO == 0 || k < kL) nbr[k] = far;
-                    else ovf[k - kL] = far;
+            for (int e = 0; e < 3; ++e)
+                if (K + e < K4 && K + e < kL) nbr[K + e] = far;
+            if (kO > 0 && K4 > kL) {
+                int k2 = 0;
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    if (q == 4) continue;
+#pragma unroll
+                    for (int i = 0; i < CAP; ++i) {
+                        bool reach;
+                        const float2 v = frame_of(nv[q][i], q / 3, q % 3, g.wx, g.wy, reach);
+                        const bool take = i < (int)rn[q] && reach;
+                        if (take && k2 >= kL) ovf[k2 - kL] = v;
+                        k2 += take ? 1 : 0;
+                    }
                 }
+#pragma unroll
+                for (int e = 0; e < 3; ++e)
+                    if (K + e < K4 && K + e >= kL) ovf[K + e - kL] = far;
             }
             const int KL = K4 < kL ? K4 : kL;   // kL is a multiple of four
             // rng.shuffle(c.particles): Fisher-Yates over the stored list,
@@ -669,37 +691,42 @@ k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ s
             uint4 W = (h & 1) ? other : mine;
             uint4 Wsh = (h & 1) ? mine : other;
             // this lane's neighbours in the cell's frame, reachable ones kept
+            // (branch-free common path and rare overflow pass, as in k_subsweep)
             int K = 0;
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 const int q = qa[j];
-                const int ra = q / 3, cb = q - 3 * (q / 3);
 #pragma unroll
                 for (int i = 0; i < CAP; ++i) {
-                    float ox = nv[j][i].x, oy = nv[j][i].y;
-                    ox = cb == 0 ? ox - g.wx : (cb == 2 ? ox + g.wx : ox);
-                    oy = ra == 0 ? oy - g.wy : (ra == 2 ? oy + g.wy : oy);
-                    const float ex = cb == 0 ? -ox : ox - g.wx;
-                    const float ey = ra == 0 ? -oy : oy - g.wy;
                     bool reach;
-                    if (ra == 1) reach = cb == 0 ? ox > -kReachEdge : ox < g.wx + kReachEdge;
-                    else if (cb == 1) reach = ra == 0 ? oy > -kReachEdge : oy < g.wy + kReachEdge;
-                    else reach = ex * ex + ey * ey < kReach2;
-                    const float2 v = make_float2(ox, oy);
-                    if (kO == 0 || K < kL) nbr[K] = v;
-                    else ovf[K - kL] = v;
+                    const float2 v = frame_of(nv[j][i], q / 3, q - 3 * (q / 3), g.wx, g.wy, reach);
+                    nbr[K < kL ? K : kL] = v;
                     K += (i < (int)rn[j] && reach) ? 1 : 0;
                 }
             }
             const int K4 = (K + 3) & ~3;
             const float2 far = make_float2(1.0e6f, 1.0e6f);
 #pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                const int k = K + e;
-                if (k < K4) {
-                    if (kO == 0 || k < kL) nbr[k] = far;
-                    else ovf[k - kL] = far;
+            for (int e = 0; e < 3; ++e)
+                if (K + e < K4 && K + e < kL) nbr[K + e] = far;
+            if (kO > 0 && K4 > kL) {
+                int k2 = 0;
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const int q = qa[j];
+#pragma unroll
+                    for (int i = 0; i < CAP; ++i) {
+                        bool reach;
+                        const float2 v =
+                            frame_of(nv[j][i], q / 3, q - 3 * (q / 3), g.wx, g.wy, reach);
+                        const bool take = i < (int)rn[j] && reach;
+                        if (take && k2 >= kL) ovf[k2 - kL] = v;
+                        k2 += take ? 1 : 0;
+                    }
                 }
+#pragma unroll
+                for (int e = 0; e < 3; ++e)
+                    if (K + e < K4 && K + e >= kL) ovf[K + e - kL] = far;
             }
             const int KL = K4 < kL ? K4 : kL;
             uint32_t P = 0x76543210u;
