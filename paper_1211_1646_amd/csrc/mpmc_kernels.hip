@@ -463,50 +463,54 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
             }
             // 4. n_M trial moves on list[t mod n]: the registers are rotated
             // after every trial so that the particle moved is always entry 0.
+            // The loop is uniform across the wave: the own-cell tests are
+            // predicated arithmetic, and the neighbour groups run to the
+            // wave's largest group count with each lane's own bound folded
+            // into the test, so no lane-dependent branch or exec-mask update
+            // sits in the loop.  (Which groups a lane tests, and in which
+            // order, cannot change "some neighbour is closer than 1".)
+            const int KLw = __ballot(KL >= 16) ? 16
+                            : __ballot(KL >= 12) ? 12
+                            : __ballot(KL >= 8) ? 8
+                            : __ballot(KL >= 4) ? 4 : 0;
             for (int tr = 0; tr < n_moves; ++tr) {
                 if (tr > 0 && (tr & 3) == 0) W = philox((uint32_t)c, s_lo, s_hi, (uint32_t)(tr >> 2), k0, k1);
                 float dx, dy;
                 displacement(word_of(W, tr & 3), delta, dx, dy);
                 const float xm = px[0] + dx;
                 const float ym = py[0] + dy;
-                bool ok = xm > 0.0f && xm <= g.wx && ym > 0.0f && ym <= g.wy;
-                if (ok) {
+                bool ok = (xm > 0.0f) & (xm <= g.wx) & (ym > 0.0f) & (ym <= g.wy);
 #pragma unroll
-                    for (int q = 1; q < CAP; ++q) {
-                        if (q < n) {
-                            const float ddx = xm - px[q];
-                            const float ddy = ym - py[q];
-                            const float r2 = ddx * ddx + ddy * ddy;
-                            ok = ok && !(r2 < 1.0f);
-                        }
-                    }
+                for (int q = 1; q < CAP; ++q) {
+                    const float ddx = xm - px[q];
+                    const float ddy = ym - py[q];
+                    const float r2 = ddx * ddx + ddy * ddy;
+                    ok = ok & ((q >= n) | !(r2 < 1.0f));
                 }
-                // neighbours four at a time (two paired LDS reads); the loop
-                // stops after the first group that holds an overlap
-                for (int k = 0; ok && k < KL; k += 4)
-                    ok = !(min_r2(xm, ym, nbr + k) < 1.0f);
-                if (kO > 0)
+                // neighbours four at a time (two paired LDS reads); entries
+                // past the lane's own count are ignored
+                for (int k = 0; k < KLw; k += 4) {
+                    const float m = min_r2(xm, ym, nbr + k);
+                    ok = ok & ((k >= KL) | !(m < 1.0f));
+                }
+                if (kO > 0 && K4 > kL)
                     for (int k = kL; ok && k < K4; k += 4)
                         ok = !(min_r2(xm, ym, ovf + (k - kL)) < 1.0f);
-                if (ok) {
-                    if (tr < 32) abits |= 1u << tr;
-                    px[0] = xm;
-                    py[0] = ym;
-                    if (has_acc) {
-                        ax[0] = ax[0] + dx;
-                        ay[0] = ay[0] + dy;
-                    }
-                    ++n_acc;
+                if (tr < 32) abits |= (ok ? 1u : 0u) << tr;
+                px[0] = ok ? xm : px[0];
+                py[0] = ok ? ym : py[0];
+                if (has_acc) {
+                    ax[0] = ok ? ax[0] + dx : ax[0];
+                    ay[0] = ok ? ay[0] + dy : ay[0];
                 }
-                if (n > 1) {
-                    rrot(px, n);
-                    rrot(py, n);
-                    if (has_acc) {
-                        rrot(ax, n);
-                        rrot(ay, n);
-                    }
-                    if (has_tag) rrot(tg, n);
+                n_acc += ok ? 1u : 0u;
+                rrot(px, n);   // the identity for n = 1
+                rrot(py, n);
+                if (has_acc) {
+                    rrot(ax, n);
+                    rrot(ay, n);
                 }
+                if (has_tag) rrot(tg, n);
             }
             n_trials = (unsigned)n_moves;
             // register entry q now holds list position (q + n_M) mod n
