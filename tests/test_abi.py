@@ -104,3 +104,62 @@ def test_package_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         L.load()
+
+
+def test_library_exports_nothing_but_the_c_abi():
+    """The internal C++ launch helpers stay out of the dynamic symbol table."""
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    names = [ln.split()[-1] for ln in out.splitlines() if ln.split()[1:2] == ["T"]]
+    assert names and all(n.startswith("mpmc_") for n in names), [n for n in names
+                                                                  if not n.startswith("mpmc_")]
+
+
+def _batch_sizes(cfgs):
+    import ctypes as C
+    arr = (L.Params * max(len(cfgs), 1))(*[c.to_c() for c in cfgs])
+    s = L.BufferSizes()
+    st = L.load().mpmc_batch_required_bytes(arr, len(cfgs), C.byref(s))
+    return st, s
+
+
+def test_batch_required_bytes_covers_the_replicas():
+    """Padded layout: cells rounded up (with at least one spare) to 256 per
+    replica, disks back to back; one control block per replica."""
+    from paper_1211_1646_amd import workloads as W
+    specs = W.replicas(8, seed=3)
+    cfgs = [SystemConfig(lattice_nx=s["nx"], lattice_ny=s["ny"], phi=s["phi"], delta=0.1,
+                         replica=r, flags=pkg.FLAG_ACC | pkg.FLAG_TAG | L.FLAG_ACCEPT_LOG)
+            for r, s in enumerate(specs)]
+    st, s = _batch_sizes(cfgs)
+    assert st == L.MPMC_OK
+    N = sum(sp["nx"] * sp["ny"] for sp in specs)
+    cells = 0
+    for c in cfgs:
+        g = geometry(c)
+        C_r = g["cells_x"] * g["cells_y"]
+        cells += (C_r + 1 + 255) // 256 * 256
+    assert s.pos >= 8 * N and s.pos < 8 * N + 256
+    assert s.acc == s.pos and s.tag >= 4 * N
+    assert s.start >= 4 * (cells + 1) and s.start < 4 * (cells + 1) + 256
+    assert s.accept_log >= 4 * cells
+    single = required_bytes(cfgs[0])
+    assert single["ctl"] < s.ctl
+    # one replica: the batch sizes are the single-system sizes
+    st1, s1 = _batch_sizes(cfgs[:1])
+    assert st1 == L.MPMC_OK and s1.pos == single["pos"] and s1.ctl == single["ctl"]
+
+
+def test_batch_argument_errors():
+    a = SystemConfig(lattice_nx=16, lattice_ny=16, phi=0.6, delta=0.1)
+    b = SystemConfig(lattice_nx=20, lattice_ny=20, phi=0.7, delta=0.1, flags=pkg.FLAG_ACC)
+    assert _batch_sizes([])[0] == L.MPMC_EINVAL                      # no replica
+    assert _batch_sizes([a, b])[0] == L.MPMC_EINVAL                  # flags differ
+    bad = SystemConfig(lattice_nx=16, lattice_ny=15, phi=0.6, delta=0.1)
+    assert _batch_sizes([a, bad])[0] == L.MPMC_EINVAL                # odd rows
+    wide = SystemConfig(lattice_nx=16, lattice_ny=16, phi=0.6, cells_x=4, cells_y=4, delta=0.1)
+    assert _batch_sizes([a, wide])[0] == L.MPMC_EGEOM                # cells too wide
+    big_delta = SystemConfig(lattice_nx=16, lattice_ny=16, phi=0.6, delta=0.9)
+    assert _batch_sizes([a, big_delta])[0] == L.MPMC_EINVAL          # delta > w/2
+    assert L.load().mpmc_last_error()
