@@ -532,13 +532,13 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
     // launch, so the adds never contend; the partials are folded into the
     // control blocks on demand.
     if (alog && log_cell >= 0) alog[log_cell] = abits;
-    __syncthreads();   // every lane is done with its neighbour table
-    unsigned *red = reinterpret_cast<unsigned *>(lds);
-    const unsigned bt = block_sum_u32(n_trials, red);
-    const unsigned ba = block_sum_u32(n_acc, red + 16);
-    if (threadIdx.x == 0 && tile < ntile && bt) {
-        // no-return atomics: the wave does not wait for a read of the partial
-        const long long gr = slot0 / kGranule;
+    // Counts are summed per wave (no barrier: a wave retires as soon as it is
+    // done, not when the slowest wave of its workgroup is) and added to the
+    // partial of the wave's 64-slot granule, which no other wave touches.
+    const unsigned bt = wave_sum_u32(n_trials);
+    const unsigned ba = wave_sum_u32(n_acc);
+    if ((threadIdx.x & 63u) == 0 && tile < ntile && bt) {
+        const long long gr = (slot0 + (long long)threadIdx.x) / kGranule;
         atomicAdd(&cnt[gr], (unsigned long long)bt);
         atomicAdd(&cnt[cnt_stride + gr], (unsigned long long)ba);
     }
@@ -814,12 +814,10 @@ k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ s
         }
     }
     if (alog && log_cell >= 0 && h == 0) alog[log_cell] = abits;
-    __syncthreads();
-    unsigned *red = reinterpret_cast<unsigned *>(lds);
-    const unsigned bt = block_sum_u32(n_trials, red);
-    const unsigned ba = block_sum_u32(n_acc, red + 16);
-    if (threadIdx.x == 0 && tile < ntile && bt) {
-        const long long gr = slot0 / kGranule;
+    const unsigned bt = wave_sum_u32(n_trials);   // per wave, no barrier
+    const unsigned ba = wave_sum_u32(n_acc);
+    if ((threadIdx.x & 63u) == 0 && tile < ntile && bt) {
+        const long long gr = (slot0 + (long long)(threadIdx.x / LPC)) / kGranule;
         atomicAdd(&cnt[gr], (unsigned long long)bt);
         atomicAdd(&cnt[cnt_stride + gr], (unsigned long long)ba);
     }

@@ -284,15 +284,18 @@ def test_batch_replica_n_moves(gpu):
 
 def test_batch_call_errors(gpu):
     from paper_1211_1646_amd import _lib as L
-    B = gpu.HardDiskBatch(configs(gpu, MIXED[:2]))
-    for call in (lambda: B.get_state(2), lambda: B.get_state(-1), lambda: B.msd(5),
-                 lambda: B.set_replica_delta(2, 0.1), lambda: B.set_replica_n_moves(3, 2)):
-        with pytest.raises(L.MPMCError) as e:
-            call()
-        assert e.value.status == L.MPMC_EINVAL
-    # the single-system getters refuse a batch
     import ctypes as C
+    B = gpu.HardDiskBatch(configs(gpu, MIXED[:2]))
+    lib, h = B.lib, B._h
     t = C.c_uint64()
+    d = C.c_double()
+    for status in (lib.mpmc_replica_get_state(h, 2, None, None, C.byref(t)),
+                   lib.mpmc_replica_get_state(h, -1, None, None, C.byref(t)),
+                   lib.mpmc_replica_msd(h, 5, C.byref(d)),
+                   lib.mpmc_replica_set_delta(h, 2, 0.1),
+                   lib.mpmc_replica_set_n_moves(h, 3, 2)):
+        assert status == L.MPMC_EINVAL
+    # the single-system getters refuse a batch
     with pytest.raises(L.MPMCError) as e:
         L.check(B.lib.mpmc_get_state(B._h, None, None, C.byref(t)))
     assert e.value.status == L.MPMC_EINVAL
