@@ -473,6 +473,14 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
                             : __ballot(KL >= 12) ? 12
                             : __ballot(KL >= 8) ? 8
                             : __ballot(KL >= 4) ? 4 : 0;
+            // far entries up to the wave's group count and in the own-cell
+            // slots past n, so that the trial loop needs no bounds at all
+            for (int k = KL; k < KLw; ++k) nbr[k] = far;
+#pragma unroll
+            for (int q = 1; q < CAP; ++q) {
+                px[q] = q < n ? px[q] : far.x;
+                py[q] = q < n ? py[q] : far.y;
+            }
             for (int tr = 0; tr < n_moves; ++tr) {
                 if (tr > 0 && (tr & 3) == 0) W = philox((uint32_t)c, s_lo, s_hi, (uint32_t)(tr >> 2), k0, k1);
                 float dx, dy;
@@ -485,13 +493,12 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
                     const float ddx = xm - px[q];
                     const float ddy = ym - py[q];
                     const float r2 = ddx * ddx + ddy * ddy;
-                    ok = ok & ((q >= n) | !(r2 < 1.0f));
+                    ok = ok & !(r2 < 1.0f);
                 }
-                // neighbours four at a time (two paired LDS reads); entries
-                // past the lane's own count are ignored
+                // neighbours four at a time (two paired LDS reads)
                 for (int k = 0; k < KLw; k += 4) {
                     const float m = min_r2(xm, ym, nbr + k);
-                    ok = ok & ((k >= KL) | !(m < 1.0f));
+                    ok = ok & !(m < 1.0f);
                 }
                 if (kO > 0 && K4 > kL)
                     for (int k = kL; ok && k < K4; k += 4)
