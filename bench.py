@@ -132,7 +132,29 @@ def batched_leg(args, pkg, torch):
     Ns = np.array([g["n_particles"] for g in B.geometries], np.float64)
     b_msd_sum = float((Ns * msd).sum())
     n_candidates = B.AUTOTUNE_CANDIDATES
+    eos_plain = eos_window(B, torch)
     B.close()
+    # the batched form with trials per cell picked by the n_M autotuner
+    # (chain-changing, so on a fresh batch with the same history up to it)
+    from paper_1211_1646_amd import controller as ctl
+    B2 = pkg.HardDiskBatch(cfgs)
+    B2.tune(10, 4)
+    B2.set_launch(lanes, blk)
+    best_nm, rates = ctl.autotune_moves(B2, (2, 4, 8, 16), window_sweeps=64)
+    B2.reset_acc()
+    B2.sweep(16)                      # graph re-captured for the chosen n_M
+    B2.reset_acc()
+    B2.synchronize()
+    e0.record(B2.stream)
+    B2.sweep(n)
+    e1.record(B2.stream)
+    e1.synchronize()
+    a_sec = e0.elapsed_time(e1) * 1e-3
+    _, _, _, msd2 = B2.stats(with_msd=True)
+    a_msd_sum = float((Ns * msd2).sum())
+    eos_auto = eos_window(B2, torch)
+    B2.close()
+    z = np.abs(eos_auto[0] - eos_plain[0]) / np.sqrt(eos_auto[1] ** 2 + eos_plain[1] ** 2)
     # the same replicas, one handle each, one after another, with the same
     # history (tuner windows, then the sweeps the autotuner ran), so each
     # timed window runs exactly the chain the batch ran
@@ -157,7 +179,28 @@ def batched_leg(args, pkg, torch):
             "trial_moves_per_s": btr / bsec, "sequential_trial_moves_per_s": seq_tr / seq_sec,
             "speedup": (btr / bsec) / (seq_tr / seq_sec),
             "msd_sum_per_s": b_msd_sum / bsec, "sequential_msd_sum_per_s": seq_msd / seq_sec,
-            "subsweep_lanes_per_cell": lanes, "subsweep_block": blk}
+            "subsweep_lanes_per_cell": lanes, "subsweep_block": blk,
+            "autotuned_n_moves": best_nm,
+            "autotune_msd_per_s_by_n_moves": {str(k): v for k, v in rates.items()},
+            "autotuned_msd_sum_per_s": a_msd_sum / a_sec,
+            "autotuned_vs_sequential_msd_per_s": (a_msd_sum / a_sec) / (seq_msd / seq_sec),
+            "eos_check": "P* per replica over 5 blocks after the timed window, n_M = %d vs the "
+                         "autotuned n_M: |dP| / combined SE mean %.2f, max %.2f over %d replicas"
+                         % (args.n_moves, float(z.mean()), float(z.max()), len(z))}
+
+
+def eos_window(B, torch, blocks=5, per_block=64, sample_every=16):
+    """P* of every replica of a batch: `blocks` blocks of `per_block` sweeps,
+    a contact histogram every `sample_every` sweeps; returns (mean, SE) per
+    replica over the blocks."""
+    P = np.zeros((blocks, B.R))
+    for b in range(blocks):
+        for k in range(per_block // sample_every):
+            B.sweep(sample_every)
+            B.pair_histogram(reset=(k == 0))
+        for r in range(B.R):
+            P[b, r] = B.pressure_from_contact(r)[0]
+    return P.mean(axis=0), P.std(axis=0, ddof=1) / math.sqrt(blocks)
 
 
 def learned_leg(args, pkg, torch, lanes_main, block_main):
