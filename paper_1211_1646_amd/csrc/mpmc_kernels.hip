@@ -355,6 +355,7 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
             bad |= rn[q] > (uint32_t)g.cap;
         }
         int n = (int)rn[4];
+        bad |= (unsigned long long)rb[4] + rn[4] > (unsigned long long)t.N;   // never write past N
         if (bad) {
             atomicOr((unsigned int *)&ctl->errword, kErrCapacity);
             n = 0;
@@ -534,10 +535,6 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
             }
         }
     }
-    // The workgroup's counts are added to the partial of the granule holding
-    // its first slot.  Each granule entry belongs to one workgroup of a
-    // launch, so the adds never contend; the partials are folded into the
-    // control blocks on demand.
     if (alog && log_cell >= 0) alog[log_cell] = abits;
     // Counts are summed per wave (no barrier: a wave retires as soon as it is
     // done, not when the slowest wave of its workgroup is) and added to the
@@ -657,6 +654,7 @@ k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ s
             rn[j] = st[cc + 1] - rb[j];
         }
         bool bad = n > g.cap;
+        bad |= (unsigned long long)b0 + (uint32_t)n > (unsigned long long)t.N;   // never write past N
 #pragma unroll
         for (int j = 0; j < NB; ++j) bad |= rn[j] > (uint32_t)g.cap;
         bad = group_any<LPC>(bad);
@@ -1007,26 +1005,30 @@ __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
             if (cl == g.C - 1 && (long long)(o + cnt) != R.pb + g.N) atomicOr(&ctl->errword, kErrCount);
             if (cnt > (unsigned)g.cap) atomicOr(&ctl->errword, kErrCapacity);
             const bool has_acc = a.acc != nullptr, has_tag = a.tag != nullptr;
+            // writes stay inside the replica's range whatever the totals say
+            // (a wrong total is reported, never written through)
+            const uint32_t lim = (uint32_t)(R.pb + g.N);
+            if (o + cnt > lim) atomicOr(&ctl->errword, kErrCount);
 #pragma unroll
             for (int i = 0; i < CAP; ++i) {
-                if (stay & (1u << i)) {
+                if ((stay & (1u << i)) && o < lim) {
                     const float tt = shifted(along_x ? own[i].x : own[i].y, minus, d);
                     a.pos_out[o] = along_x ? make_float2(tt, own[i].y) : make_float2(own[i].x, tt);
                     if (has_acc) a.acc_out[o] = a.acc[ob + i];
                     if (has_tag) a.tag_out[o] = a.tag[ob + i];
-                    ++o;
                 }
+                o += (stay >> i) & 1u;
             }
 #pragma unroll
             for (int i = 0; i < CAP; ++i) {
-                if (leave & (1u << i)) {
+                if ((leave & (1u << i)) && o < lim) {
                     const float tt = shifted(along_x ? nb[i].x : nb[i].y, minus, d);
                     const float t2 = tt + sw;
                     a.pos_out[o] = along_x ? make_float2(t2, nb[i].y) : make_float2(nb[i].x, t2);
                     if (has_acc) a.acc_out[o] = a.acc[nbb + i];
                     if (has_tag) a.tag_out[o] = a.tag[nbb + i];
-                    ++o;
                 }
+                o += (leave >> i) & 1u;
             }
         }
     }
@@ -1063,12 +1065,13 @@ k_pair_hist(Tables t, const float2 *__restrict__ pos, const uint32_t *__restrict
     const int Rx = (double)g.wx >= rmax ? 1 : 2;
     const int Ry = (double)g.wy >= rmax ? 1 : 2;
     const uint32_t *const st = start + R.cb;
+    const uint32_t nlim = (uint32_t)t.N;   // offsets are trusted only up to N
     const long long cl = cell0 + (long long)threadIdx.x - R.cb;
     if (tile < ntile && cl < g.C) {
         const int c = (int)cl;
         const int cy = c / g.mx, cx = c - cy * g.mx;
         const float e0 = E[0], eN = E[kHistBins];
-        for (uint32_t k = st[c]; k < st[c + 1]; ++k) {
+        for (uint32_t k = st[c], ke = min(st[c + 1], nlim); k < ke; ++k) {
             const float2 pk = pos[k];
             for (int oy = -Ry; oy <= Ry; ++oy) {
                 const int ncy = (cy + oy + 2 * g.my) % g.my;
@@ -1077,7 +1080,7 @@ k_pair_hist(Tables t, const float2 *__restrict__ pos, const uint32_t *__restrict
                     const int ncx = (cx + ox + 2 * g.mx) % g.mx;
                     const float tx = (float)ox * g.wx;
                     const int nc = ncy * g.mx + ncx;
-                    for (uint32_t j = st[nc]; j < st[nc + 1]; ++j) {
+                    for (uint32_t j = st[nc], je = min(st[nc + 1], nlim); j < je; ++j) {
                         if (j == k) continue;
                         const float2 v = pos[j];
                         const float qx = v.x + tx;
@@ -1200,12 +1203,13 @@ k_count_overlaps(Tables t, const float2 *__restrict__ pos, const uint32_t *__res
     const Rep R = rep_of(t, r);
     const Geom g = R.g;
     const uint32_t *const st = start + R.cb;
+    const uint32_t nlim = (uint32_t)t.N;   // offsets are trusted only up to N
     const long long cl = cell0 + (long long)threadIdx.x - R.cb;
     unsigned bad = 0;
     if (tile < ntile && cl < g.C) {
         const int c = (int)cl;
         const int cy = c / g.mx, cx = c - cy * g.mx;
-        for (uint32_t k = st[c]; k < st[c + 1]; ++k) {
+        for (uint32_t k = st[c], ke = min(st[c + 1], nlim); k < ke; ++k) {
             const float2 pk = pos[k];
             for (int oy = -1; oy <= 1; ++oy) {
                 const int ncy = (cy + oy + g.my) % g.my;
@@ -1214,7 +1218,7 @@ k_count_overlaps(Tables t, const float2 *__restrict__ pos, const uint32_t *__res
                     const int ncx = (cx + ox + g.mx) % g.mx;
                     const float tx = ox < 0 ? -g.wx : (ox > 0 ? g.wx : 0.0f);
                     const int nc = ncy * g.mx + ncx;
-                    for (uint32_t j = st[nc]; j < st[nc + 1]; ++j) {
+                    for (uint32_t j = st[nc], je = min(st[nc + 1], nlim); j < je; ++j) {
                         if (j == k) continue;
                         const float2 v = pos[j];
                         const float ddx = pk.x - (v.x + tx);
