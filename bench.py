@@ -18,7 +18,8 @@ compare the batched and learned-controller forms with the plain form:
   learned -- a move-size network trained on samples the sweeps log, used
              during equilibration of the 1M-disk workload, against the plain
              tuner: mean-square displacement per second of production
-             sweeps with delta frozen, and P* with its standard error.
+             sweeps with delta frozen, and P* with its standard error;
+  eos     -- beta P sigma^2 with block errors at phi = 0.700, 0.716, 0.720.
 """
 from __future__ import annotations
 
@@ -56,6 +57,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-sweeps", type=int, default=160)
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-eos", action="store_true")
+    ap.add_argument("--eos-equilibration", type=int, default=8000)
+    ap.add_argument("--eos-blocks", type=int, default=20)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (a known byte count "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -201,6 +205,50 @@ def eos_window(B, torch, blocks=5, per_block=64, sample_every=16):
         for r in range(B.R):
             P[b, r] = B.pressure_from_contact(r)[0]
     return P.mean(axis=0), P.std(axis=0, ddof=1) / math.sqrt(blocks)
+
+
+PAPER_TABLE2_1024 = {"0.698": 9.16934, "0.702": 9.1882, "0.706": 9.1859, "0.710": 9.1842,
+                     "0.714": 9.1819, "0.718": 9.1951}   # Table 2, N = 1024^2, MPMC
+
+
+def eos_leg(args, pkg, torch, lanes, block):
+    """beta P sigma^2 of the 1M-disk system at each packing fraction of the
+    large workload: plain tuner, equilibration, then production sweeps with a
+    contact histogram every 20 sweeps, P* per block of 200 sweeps."""
+    out = {}
+    for phi in (0.700, 0.716, 0.720):
+        cfg = pkg.SystemConfig(lattice_nx=args.lattice, lattice_ny=args.lattice, phi=phi,
+                               w_max=math.sqrt(2.0), delta=0.1, n_moves=args.n_moves, seed=1)
+        S = pkg.HardDiskSystem(cfg)
+        S.set_launch(lanes, block)
+        S.tune(10, 20)
+        S.sweep(args.eos_equilibration)
+        S.synchronize()
+        P = []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = S.counters()[0]
+        ms = 0.0
+        for b in range(args.eos_blocks):
+            for k in range(10):
+                e0.record(S.stream)
+                S.sweep(20)
+                e1.record(S.stream)
+                S.pair_histogram(reset=(k == 0))
+                e1.synchronize()
+                ms += e0.elapsed_time(e1)
+            P.append(S.pressure_from_contact()[0])
+        trials = S.counters()[0] - t0
+        P = np.array(P)
+        out["%.3f" % phi] = {"P": float(P.mean()), "P_se": float(P.std(ddof=1) / math.sqrt(len(P))),
+                             "blocks": len(P), "delta": float(S.delta),
+                             "trial_moves_per_s": trials / (ms * 1e-3)}
+        S.close()
+    out["equilibration_sweeps"] = args.eos_equilibration + 200
+    out["paper_table2_N1024sq"] = PAPER_TABLE2_1024
+    out["note"] = ("lattice start and ~1e4 sweeps; the paper equilibrates 3e8 sweeps from a "
+                   "compressed fluid and averages 8 runs of 1e9, so near the liquid-hexatic "
+                   "transition these values are context, not a reproduction")
+    return out
 
 
 def learned_leg(args, pkg, torch, lanes_main, block_main):
@@ -378,6 +426,10 @@ def main():
         print("[bench] learned-controller leg", file=sys.stderr, flush=True)
         out["learned"] = learned_leg(args, pkg, torch, out["config"]["subsweep_lanes_per_cell"],
                                      out["config"]["subsweep_block"])
+    if not args.no_eos:
+        print("[bench] equation-of-state leg", file=sys.stderr, flush=True)
+        out["eos"] = eos_leg(args, pkg, torch, out["config"]["subsweep_lanes_per_cell"],
+                             out["config"]["subsweep_block"])
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args, geo, trials / args.steps)

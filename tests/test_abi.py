@@ -163,3 +163,11 @@ def test_batch_argument_errors():
     big_delta = SystemConfig(lattice_nx=16, lattice_ny=16, phi=0.6, delta=0.9)
     assert _batch_sizes([a, big_delta])[0] == L.MPMC_EINVAL          # delta > w/2
     assert L.load().mpmc_last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "4"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr

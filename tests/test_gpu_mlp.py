@@ -252,3 +252,45 @@ def test_controller_step_matches_oracle(ctx):
         tol = d64 * (math.expm1(float(ey[0]) + 64 * U)) + 2 * U * d64
         log("  replica %d: a=%.4f delta gpu %.7g oracle %.7g tol %.2g" % (r, a / t, dl[r], d64, tol))
         assert abs(float(dl[r]) - d64) <= tol, (r, float(dl[r]), d64, tol)
+
+
+def test_controller_pipeline_small(ctx):
+    """Logged windows -> labels -> training on the GPU -> the controller in the
+    chain: samples have the expected shape, labels come from the delta grid,
+    the loss falls, and the controlled run keeps delta in range and the
+    state overlap-free."""
+    torch, pkg, ctl = ctx
+    phis = [0.62, 0.70]
+    deltas = [0.05, 0.10, 0.20]
+    base = [pkg.SystemConfig(lattice_nx=24, lattice_ny=24, phi=p, w_max=math.sqrt(2.0), n_moves=4,
+                             seed=1) for p in phis]
+    samples, secs = ctl.collect_samples(base, deltas, windows=6, window_sweeps=10, skip=2)
+    assert len(samples["phi"]) == len(phis) * len(deltas) * 6 and secs > 0
+    assert np.all((samples["acceptance"] >= 0) & (samples["acceptance"] <= 1))
+    assert np.all(samples["msd_per_sweep"] > 0)
+    best = ctl.label_best_delta(samples)
+    assert len(best) == 2 and all(min(abs(v - d) for d in deltas) < 1e-6 for v in best.values())
+    X, T = ctl.training_set(samples, best)
+    net = ctl.MoveSizeNet(ctl.init_params(0))
+    hist = net.train(X, T, 300, lr=3e-3, log_every=100)
+    assert hist[-1] < hist[0]
+    S = pkg.HardDiskSystem(pkg.SystemConfig(lattice_nx=32, lattice_ny=32, phi=0.68,
+                                            w_max=math.sqrt(2.0), delta=0.1, n_moves=4, seed=2))
+    S.control(net, 10, 5)
+    d = float(S.delta)
+    assert 1e-3 <= d <= 0.5 * min(float(S.wx), float(S.wy))
+    assert S.count_overlaps() == 0
+
+
+def test_n_moves_autotuner(ctx):
+    torch, pkg, ctl = ctx
+    S = pkg.HardDiskSystem(pkg.SystemConfig(lattice_nx=64, lattice_ny=64, phi=0.66,
+                                            w_max=math.sqrt(2.0), delta=0.12, n_moves=4, seed=3,
+                                            flags=pkg.FLAG_ACC))
+    best, rates = ctl.autotune_moves(S, (1, 4, 8), window_sweeps=32)
+    assert best in (1, 4, 8) and set(rates) == {1, 4, 8}
+    assert all(v > 0 for v in rates.values()) and rates[best] == max(rates.values())
+    t0, _ = S.counters()
+    S.sweep(1)
+    t1, _ = S.counters()
+    assert t1 > t0 and S.count_overlaps() == 0
