@@ -19,7 +19,10 @@ compare the batched and learned-controller forms with the plain form:
              during equilibration of the 1M-disk workload, against the plain
              tuner: mean-square displacement per second of production
              sweeps with delta frozen, and P* with its standard error;
-  eos     -- beta P sigma^2 with block errors at phi = 0.700, 0.716, 0.720.
+  eos     -- beta P sigma^2 with block errors at phi = 0.700, 0.716, 0.720;
+  table3  -- the paper's own throughput benchmark like for like: phi 0.698,
+             in-circle moves of radius 0.16, n_M = 4, N = 253^2 .. 3040^2,
+             median eta of 11 runs next to the paper's K20 figures.
 """
 from __future__ import annotations
 
@@ -58,6 +61,9 @@ def parse():
     ap.add_argument("--batched-sweeps", type=int, default=160)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-eos", action="store_true")
+    ap.add_argument("--no-table3", action="store_true",
+                    help="skip the paper's Table 3 benchmark (in-circle moves, N = 253^2 .. 3040^2)")
+    ap.add_argument("--table3-runs", type=int, default=11)
     ap.add_argument("--eos-equilibration", type=int, default=8000)
     ap.add_argument("--eos-blocks", type=int, default=20)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -205,6 +211,63 @@ def eos_window(B, torch, blocks=5, per_block=64, sample_every=16):
         for r in range(B.R):
             P[b, r] = B.pressure_from_contact(r)[0]
     return P.mean(axis=0), P.std(axis=0, ddof=1) / math.sqrt(blocks)
+
+
+PAPER_TABLE3_K20 = {"253": 6.23e8, "760": 9.83e8, "1520": 1.09e9, "3040": 1.09e9}  # eta, Table 3
+
+
+def table3_leg(args, pkg, torch):
+    """The paper's throughput benchmark (Table 3) like for like: phi = 0.698,
+    in-circle moves of radius 0.16, n_M = 4, cells as wide as the paper's,
+    N = 253^2 .. 3040^2.  Per N: the launch shape from the autotuner, then
+    11 runs from the lattice, each 100 warm-up and 100 timed sweeps (HIP
+    events on the system's stream); the median eta = trial moves / s."""
+    from paper_1211_1646_amd import workloads as W
+    out = {}
+    for side in W.PAPER_TABLE3_SIDES:
+        w = W.paper_benchmark(side)
+        cfg = pkg.SystemConfig(lattice_nx=w["nx"], lattice_ny=w["ny"], phi=w["phi"], w_min=1.0,
+                               w_max=w["w_max"], delta=w["delta"], n_moves=w["n_moves"], seed=1,
+                               flags=pkg.FLAG_DISK)
+        S = pkg.HardDiskSystem(cfg)
+        lanes, block, _ = S.autotune(16)
+        geo = S.geometry
+        S.close()
+        etas, accs = [], []
+        for run in range(args.table3_runs):
+            cfg.seed = 1 + run
+            S = pkg.HardDiskSystem(cfg)
+            S.set_launch(lanes, block)
+            S.sweep(100)
+            S.synchronize()
+            t0, a0 = S.counters()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(S.stream)
+            S.sweep(100)
+            e1.record(S.stream)
+            e1.synchronize()
+            t1, a1 = S.counters()
+            etas.append((t1 - t0) / (e0.elapsed_time(e1) * 1e-3))
+            accs.append((a1 - a0) / max(t1 - t0, 1))
+            S.close()
+        etas.sort()
+        med = etas[len(etas) // 2]
+        out[str(side)] = {
+            "N": geo["n_particles"], "cells": [geo["cells_x"], geo["cells_y"]],
+            "w": [geo["w_x"], geo["w_y"]], "mean_occupancy": geo["n_particles"] / (geo["cells_x"] * geo["cells_y"]),
+            "lanes": lanes, "block": block, "runs": len(etas),
+            "eta_median": med, "eta_min": etas[0], "eta_max": etas[-1],
+            "acceptance": float(np.median(accs)),
+            "paper_k20_eta": PAPER_TABLE3_K20[str(side)], "vs_paper_k20": med / PAPER_TABLE3_K20[str(side)]}
+        print("[bench] table 3, N=%d: eta %.4g (K20 %.3g, x%.1f)" % (
+            geo["n_particles"], med, PAPER_TABLE3_K20[str(side)], med / PAPER_TABLE3_K20[str(side)]),
+            file=sys.stderr, flush=True)
+    top = max(v["eta_median"] for v in out.values())
+    for v in out.values():
+        v["eta_over_max"] = v["eta_median"] / top
+    out["note"] = ("phi 0.698, in-circle moves d = 0.16, n_M = 4, cell width ~1.399 (the paper's grid "
+                   "rule on its square box); 253^2 is run as a 254 x 252 lattice")
+    return out
 
 
 PAPER_TABLE2_1024 = {"0.698": 9.16934, "0.702": 9.1882, "0.706": 9.1859, "0.710": 9.1842,
@@ -381,8 +444,9 @@ def main():
     bytes_per_launch = 8.0 * N + 4.0 * (C + 1) + 2.0 * N
     achieved = bytes_per_launch / (k_avg_ms * 1e-3) / 1e9
     cap = geo["capacity"]
-    kernel_name = ("k_subsweep<%d>" % cap if S.lanes == 1
-                   else "k_subsweep_mc<%d, %d>" % (cap, S.lanes))
+    # template arguments: capacity, [lanes per cell,] proposal (0 = square)
+    kernel_name = ("k_subsweep<%d, 0>" % cap if S.lanes == 1
+                   else "k_subsweep_mc<%d, %d, 0>" % (cap, S.lanes))
     S.synchronize()
 
     out = {
@@ -430,6 +494,9 @@ def main():
         print("[bench] equation-of-state leg", file=sys.stderr, flush=True)
         out["eos"] = eos_leg(args, pkg, torch, out["config"]["subsweep_lanes_per_cell"],
                              out["config"]["subsweep_block"])
+    if not args.no_table3:
+        print("[bench] paper table 3 leg", file=sys.stderr, flush=True)
+        out["table3"] = table3_leg(args, pkg, torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args, geo, trials / args.steps)

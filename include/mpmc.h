@@ -65,6 +65,14 @@ typedef int32_t mpmc_status;
 #define MPMC_FLAG_ACC 1u   /* keep per-disk displacement accumulators (MSD) */
 #define MPMC_FLAG_TAG 2u   /* keep per-disk identity tags */
 #define MPMC_FLAG_ACCEPT_LOG 4u /* keep per-cell accept bits of the latest update */
+/* Trial displacements uniform in the disk of radius delta, the paper's
+ * inCircle(d) proposal (Alg. 2), instead of the square (-delta, delta)^2.
+ * One trial word still makes one move: its high half gives the squared
+ * radius (2h+1)/2^17 of the disk, its low half the angle (2h+1) pi/65536,
+ * evaluated with FP32 Taylor series about 0 on (0, pi/4) and exact quarter
+ * turns.  The proposal is exactly symmetric.  Replicas of one batch may
+ * differ in this flag; all other flags must agree. */
+#define MPMC_FLAG_DISK 8u
 
 #define MPMC_HIST_BINS 200 /* contact histogram: 200 bins of 1e-4 sigma */
 

@@ -59,6 +59,8 @@ def lib():
         L.oracle_bounded.restype = C.c_uint32
         L.oracle_trial_displacement.argtypes = [C.c_uint32, C.c_float, f32p, f32p]
         L.oracle_trial_displacement.restype = None
+        L.oracle_disk_displacement.argtypes = [C.c_uint32, C.c_float, f32p, f32p]
+        L.oracle_disk_displacement.restype = None
         L.oracle_visit_sequence.argtypes = [C.c_int, C.c_int, i32p]
         L.oracle_visit_sequence.restype = None
         L.oracle_geometry.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
@@ -151,6 +153,12 @@ def trial_displacement(word: int, delta: float):
     return np.float32(dx.value), np.float32(dy.value)
 
 
+def disk_displacement(word: int, delta: float):
+    dx, dy = C.c_float(), C.c_float()
+    lib().oracle_disk_displacement(word, delta, C.byref(dx), C.byref(dy))
+    return np.float32(dx.value), np.float32(dy.value)
+
+
 def visit_sequence(n: int, n_moves: int):
     out = np.zeros(n_moves, np.int32)
     lib().oracle_visit_sequence(n, n_moves, _ptr(out, C.c_int))
@@ -186,6 +194,7 @@ class OracleSystem:
 
     FLAG_ACC = 1
     FLAG_TAG = 2
+    FLAG_DISK = 8
 
     def __init__(self, handle):
         self._h = handle

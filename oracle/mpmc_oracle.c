@@ -106,6 +106,72 @@ void oracle_trial_displacement(uint32_t word, float delta, float *dx, float *dy)
     *dy = uy * delta;
 }
 
+/* One trial word -> displacement uniform in the disk of radius delta
+ * (Alg. 2's inCircle(d), the paper's proposal).
+ *
+ * The high half hr picks the squared radius as the midpoint (2hr+1)/2^17 of
+ * one of 65536 equal sub-intervals of (0,1); its square root is uniform in
+ * area.  The low half ha picks the angle (2ha+1) pi / 65536: the top two
+ * bits are the quadrant q, the low 14 bits the angle inside it.  Inside a
+ * quadrant, angles past pi/4 are taken as the mirror image of an angle below
+ * pi/4 (cos and sin swap), so the two series below only ever see
+ * 0 < x < pi/4, where their Taylor remainders (order 11 and 12) are below
+ * 2e-9, far under FP32 rounding.  Turning by a quadrant only permutes and
+ * negates (c, s), exactly, so the words ha and ha ^ 0x8000 give exactly
+ * opposite displacements and the proposal is symmetric.  Every step is one
+ * FP32 operation (sqrtf is correctly rounded), in the order written. */
+static float sin_series(float x, float z)
+{
+    /* x - x^3/3! + x^5/5! - x^7/7! + x^9/9!, Horner in z = x^2 */
+    float p = 0x1.71de3ap-19f * z;   /* 1/9! */
+    p = p + -0x1.a01a02p-13f;        /* -1/7! */
+    p = p * z;
+    p = p + 0x1.111112p-7f;          /* 1/5! */
+    p = p * z;
+    p = p + -0x1.555556p-3f;         /* -1/3! */
+    return x + (x * z) * p;
+}
+
+static float cos_series(float z)
+{
+    /* 1 - x^2/2! + x^4/4! - x^6/6! + x^8/8! - x^10/10! */
+    float p = -0x1.27e4fcp-22f * z;  /* -1/10! */
+    p = p + 0x1.a01a02p-16f;         /* 1/8! */
+    p = p * z;
+    p = p + -0x1.6c16c2p-10f;        /* -1/6! */
+    p = p * z;
+    p = p + 0x1.555556p-5f;          /* 1/4! */
+    p = p * z;
+    p = p + -0.5f;                   /* -1/2! */
+    return 1.0f + z * p;
+}
+
+void oracle_disk_displacement(uint32_t word, float delta, float *dx, float *dy)
+{
+    uint32_t hr = word >> 16;
+    uint32_t ha = word & 0xFFFFu;
+    uint32_t q = ha >> 14;
+    uint32_t j = ha & 0x3FFFu;
+    uint32_t m = j < 8192u ? j : 16383u - j;          /* mirror about pi/4 */
+    float x = (float)(2u * m + 1u) * 0x1.921fb6p-15f; /* (2m+1) pi / 65536 */
+    float z = x * x;
+    float sn = sin_series(x, z);
+    float cs = cos_series(z);
+    float c = j < 8192u ? cs : sn;   /* cos and sin of the angle in the quadrant */
+    float s = j < 8192u ? sn : cs;
+    float a, b;                      /* turned by q quarter turns */
+    switch (q) {
+    case 0: a = c; b = s; break;
+    case 1: a = -s; b = c; break;
+    case 2: a = -c; b = -s; break;
+    default: a = s; b = -c; break;
+    }
+    float rho = sqrtf((float)(2u * hr + 1u) * 0x1p-17f);
+    float r = rho * delta;
+    *dx = r * a;
+    *dy = r * b;
+}
+
 /* Particle chosen by trial s of a cell update (Alg. 1, line 7): the list is
  * walked from the start and wraps around when n_M > n. */
 static int visit_slot(int s, int n) { return s % n; }
@@ -196,7 +262,7 @@ typedef struct oracle_sys {
     uint32_t key[2];
     uint64_t sweep;
     uint64_t trials, accepts;
-    int flags;      /* bit 0: displacement accumulators, bit 1: tags */
+    int flags;      /* bit 0: displacement accumulators, bit 1: tags, bit 3: disk moves */
     int cell_order; /* 0 row-major, 1 reversed, 2 scrambled (order test) */
     /* disk[c*cap + i] (Sec. 3.1), double buffer for the shift (Alg. 4) */
     float *disk_x, *disk_y, *dbl_x, *dbl_y;
@@ -210,6 +276,7 @@ typedef struct oracle_sys {
 
 #define FLAG_ACC 1
 #define FLAG_TAG 2
+#define FLAG_DISK 8 /* in-circle proposals instead of the square */
 
 static void *xcalloc(size_t n, size_t sz)
 {
@@ -418,7 +485,10 @@ static void cell_update(oracle_sys *S, int cx, int cy)
         if ((s & 3) == 0) stream_block((uint32_t)c, S->sweep, TAG_TRIAL + (uint32_t)(s >> 2), S->key, words);
         int slot = base + visit_slot(s, n);
         float dx, dy;
-        oracle_trial_displacement(words[s & 3], S->delta, &dx, &dy);
+        if (S->flags & FLAG_DISK)
+            oracle_disk_displacement(words[s & 3], S->delta, &dx, &dy);
+        else
+            oracle_trial_displacement(words[s & 3], S->delta, &dx, &dy);
         float xm = S->disk_x[slot] + dx;
         float ym = S->disk_y[slot] + dy;
         int in_cell = xm > 0.0f && xm <= S->wx && ym > 0.0f && ym <= S->wy;

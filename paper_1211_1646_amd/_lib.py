@@ -21,6 +21,7 @@ MPMC_ESTATE = -6
 FLAG_ACC = 1
 FLAG_TAG = 2
 FLAG_ACCEPT_LOG = 4
+FLAG_DISK = 8        # in-circle trial moves (the paper's proposal)
 HIST_BINS = 200
 MLP_PARAMS = 1217
 

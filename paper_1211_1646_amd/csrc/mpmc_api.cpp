@@ -145,7 +145,7 @@ mpmc_status check_params(const mpmc_params *p, const mpmc_geometry &g)
     if (!(p->delta > 0.0f) || p->delta > 0.5f * std::min(g.w_x, g.w_y))
         return fail(MPMC_EINVAL, "delta must lie in (0, min(w)/2]");
     if (p->n_moves < 0 || p->n_moves > (1 << 20)) return fail(MPMC_EINVAL, "n_moves out of range");
-    if (p->flags & ~(MPMC_FLAG_ACC | MPMC_FLAG_TAG | MPMC_FLAG_ACCEPT_LOG))
+    if (p->flags & ~(MPMC_FLAG_ACC | MPMC_FLAG_TAG | MPMC_FLAG_ACCEPT_LOG | MPMC_FLAG_DISK))
         return fail(MPMC_EINVAL, "unknown flag");
     return MPMC_OK;
 }
@@ -174,7 +174,8 @@ mpmc_status plan(const mpmc_params *p, int n, Layout *L)
         if (s) return s;
         s = check_params(&p[r], L->geo[(size_t)r]);
         if (s) return s;
-        if (p[r].flags != p[0].flags) return fail(MPMC_EINVAL, "replicas must share flags");
+        if ((p[r].flags ^ p[0].flags) & ~MPMC_FLAG_DISK)
+            return fail(MPMC_EINVAL, "replicas must share flags (all but MPMC_FLAG_DISK)");
         const mpmc_geometry &g = L->geo[(size_t)r];
         Rep &R = L->reps[(size_t)r];
         std::memset(&R, 0, sizeof R);
@@ -196,6 +197,7 @@ mpmc_status plan(const mpmc_params *p, int n, Layout *L)
         R.key0 = p[r].seed;
         R.key1 = p[r].replica;
         R.delta0 = p[r].delta;
+        R.disk = (p[r].flags & MPMC_FLAG_DISK) ? 1 : 0;
         L->cells += R.cpad;
         L->N += R.g.N;
         L->active += R.apad;
@@ -558,6 +560,11 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
     h->t.rep0 = L.reps[0];
     h->t.R = n;
     h->t.cap = L.cap;
+    {
+        int ndisk = 0;
+        for (const Rep &R : L.reps) ndisk += R.disk;
+        h->t.prop = ndisk == 0 ? 0 : (ndisk == n ? 1 : 2);
+    }
     h->t.cells = L.cells;
     h->t.active = L.active;
     h->t.N = L.N;

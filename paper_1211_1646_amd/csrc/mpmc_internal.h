@@ -73,7 +73,8 @@ struct Rep {
     int n_moves;
     unsigned int key0, key1;
     float delta0;
-    int pad[2];
+    int disk;            // 1: in-circle trial moves, 0: square
+    int pad;
 };
 
 // Device tables of a handle (in the caller's control buffer), passed to the
@@ -86,6 +87,7 @@ struct Tables {
     const uint16_t *crep;   // replica of each rebin tile
     int R;
     int cap;                // largest capacity
+    int prop;               // trial moves: 0 all square, 1 all in-circle, 2 per replica
     long long cells;        // padded cells, all replicas
     long long active;       // padded active slots, all replicas
     long long N;            // disks, all replicas

@@ -73,6 +73,55 @@ __device__ __forceinline__ void displacement(uint32_t u, float delta, float &dx,
     dy = uy * delta;
 }
 
+// In-circle trial displacement (Alg. 2's inCircle(d)) from one word.
+//   radius: sqrt of the midpoint (2 hr + 1) / 2^17 of one of 65536 equal parts
+//           of (0, 1) -- uniform in area -- times delta;
+//   angle:  (2 ha + 1) pi / 65536; bits 15..14 of ha are the quarter turn,
+//           bits 13..0 the angle inside the quarter.  Angles above pi/4 use
+//           the mirror angle below it with cos and sin exchanged, so the
+//           series only see (0, pi/4): Taylor to x^9 (sin) and x^10 (cos),
+//           remainders below 2e-9.
+// Every operation is a single FP32 operation in the order written
+// (contraction is off; sqrtf is the correctly rounded square root), and a
+// quarter turn only permutes and negates, so words differing in bit 15 give
+// exactly opposite moves.
+__device__ __forceinline__ void disk_displacement(uint32_t u, float delta, float &dx, float &dy)
+{
+    const uint32_t ha = u & 0xFFFFu;
+    const uint32_t jq = ha & 0x3FFFu;
+    const bool upper = jq >= 8192u;
+    const uint32_t m = upper ? 16383u - jq : jq;
+    const float x = (float)(2u * m + 1u) * 0x1.921fb6p-15f;     // pi / 65536
+    const float z = x * x;
+    float ps = 0x1.71de3ap-19f * z;                              // 1/9!
+    ps = ps + -0x1.a01a02p-13f;                                  // -1/7!
+    ps = ps * z;
+    ps = ps + 0x1.111112p-7f;                                    // 1/5!
+    ps = ps * z;
+    ps = ps + -0x1.555556p-3f;                                   // -1/3!
+    const float sn = x + (x * z) * ps;
+    float pc = -0x1.27e4fcp-22f * z;                             // -1/10!
+    pc = pc + 0x1.a01a02p-16f;                                   // 1/8!
+    pc = pc * z;
+    pc = pc + -0x1.6c16c2p-10f;                                  // -1/6!
+    pc = pc * z;
+    pc = pc + 0x1.555556p-5f;                                    // 1/4!
+    pc = pc * z;
+    pc = pc + -0.5f;                                             // -1/2!
+    const float cs = 1.0f + z * pc;
+    const float c = upper ? sn : cs;
+    const float sv = upper ? cs : sn;
+    // quarter turns: (c, s) -> (-s, c) -> (-c, -s) -> (s, -c)
+    const uint32_t q = ha >> 14;
+    const float a0 = (q & 1u) ? sv : c;
+    const float b0 = (q & 1u) ? c : sv;
+    const float a = ((q + 1u) & 2u) ? -a0 : a0;
+    const float b = (q & 2u) ? -b0 : b0;
+    const float r = __builtin_sqrtf((float)(2u * (u >> 16) + 1u) * 0x1p-17f) * delta;
+    dx = r * a;
+    dy = r * b;
+}
+
 struct Draws {
     uint32_t order;   // byte q = set processed in slot q
     int f;
@@ -290,7 +339,7 @@ __device__ __forceinline__ float min_r2(float xm, float ym, const float2 *e)
                  fminf(d2x * d2x + d2y * d2y, d3x * d3x + d3y * d3y));
 }
 
-template <int CAP>
+template <int CAP, int PROP>
 __global__ void __launch_bounds__(256)
 k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
            float2 *__restrict__ acc, uint32_t *__restrict__ tag, uint32_t *__restrict__ alog,
@@ -315,6 +364,8 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
     const uint32_t k0 = ctl->key0, k1 = ctl->key1;
     const float delta = ctl->delta;
     const int n_moves = R.n_moves;
+    // proposal: fixed for the launch (PROP 0 square, 1 in-circle) or per replica
+    const bool disk = PROP == 2 ? R.disk != 0 : PROP == 1;
     const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
 
     int Q = set;
@@ -485,7 +536,10 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
             for (int tr = 0; tr < n_moves; ++tr) {
                 if (tr > 0 && (tr & 3) == 0) W = philox((uint32_t)c, s_lo, s_hi, (uint32_t)(tr >> 2), k0, k1);
                 float dx, dy;
-                displacement(word_of(W, tr & 3), delta, dx, dy);
+                if (disk)
+                    disk_displacement(word_of(W, tr & 3), delta, dx, dy);
+                else
+                    displacement(word_of(W, tr & 3), delta, dx, dy);
                 const float xm = px[0] + dx;
                 const float ym = py[0] + dy;
                 bool ok = (xm > 0.0f) & (xm <= g.wx) & (ym > 0.0f) & (ym <= g.wy);
@@ -587,7 +641,7 @@ __device__ __forceinline__ bool group_any(bool v)
 // identical; the gain is twice or four times the waves in flight, each with
 // a shorter chain of dependent work, where a launch has too few cells to
 // hide latency.
-template <int CAP, int LPC>
+template <int CAP, int LPC, int PROP>
 __global__ void __launch_bounds__(256)
 k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
               float2 *__restrict__ acc, uint32_t *__restrict__ tag, uint32_t *__restrict__ alog,
@@ -611,6 +665,8 @@ k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ s
     const uint32_t k0 = ctl->key0, k1 = ctl->key1;
     const float delta = ctl->delta;
     const int n_moves = R.n_moves;
+    // proposal: fixed for the launch (PROP 0 square, 1 in-circle) or per replica
+    const bool disk = PROP == 2 ? R.disk != 0 : PROP == 1;
     const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
 
     int Q = set;
@@ -758,7 +814,10 @@ k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ s
             for (int tr = 0; tr < n_moves; ++tr) {
                 if (tr > 0 && (tr & 3) == 0) W = philox((uint32_t)c, s_lo, s_hi, (uint32_t)(tr >> 2), k0, k1);
                 float dx, dy;
-                displacement(word_of(W, tr & 3), delta, dx, dy);
+                if (disk)
+                    disk_displacement(word_of(W, tr & 3), delta, dx, dy);
+                else
+                    displacement(word_of(W, tr & 3), delta, dx, dy);
                 const float xm = px[0] + dx;
                 const float ym = py[0] + dy;
                 bool ok = xm > 0.0f && xm <= g.wx && ym > 0.0f && ym <= g.wy;
@@ -1404,25 +1463,33 @@ hipError_t launch_subsweep(const Tables &t, float2 *pos, const uint32_t *start, 
     const int e = 8 / lanes * t.cap;
     const int row = (e < kNbrLds ? e : kNbrLds) + 1;
     const size_t lds = (size_t)row * block * sizeof(float2);
-#define MPMC_SUB(CAP)                                                                          \
+#define MPMC_SUB(CAP, PROP)                                                                    \
     do {                                                                                       \
         if (lanes == 1)                                                                        \
-            hipLaunchKernelGGL(k_subsweep<CAP>, grid, blk, lds, st, t, pos, start, acc, tag,    \
-                               alog, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);              \
+            hipLaunchKernelGGL((k_subsweep<CAP, PROP>), grid, blk, lds, st, t, pos, start, acc,  \
+                               tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);         \
         else if (lanes == 2)                                                                   \
-            hipLaunchKernelGGL((k_subsweep_mc<CAP, 2>), grid, blk, lds, st, t, pos, start, acc, \
-                               tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);         \
+            hipLaunchKernelGGL((k_subsweep_mc<CAP, 2, PROP>), grid, blk, lds, st, t, pos, start, \
+                               acc, tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);    \
         else                                                                                   \
-            hipLaunchKernelGGL((k_subsweep_mc<CAP, 4>), grid, blk, lds, st, t, pos, start, acc, \
-                               tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);         \
+            hipLaunchKernelGGL((k_subsweep_mc<CAP, 4, PROP>), grid, blk, lds, st, t, pos, start, \
+                               acc, tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);    \
     } while (0)
+#define MPMC_SUB_P(CAP)                                                                        \
+    do {                                                                                       \
+        if (t.prop == 0) MPMC_SUB(CAP, 0);                                                     \
+        else if (t.prop == 1) MPMC_SUB(CAP, 1);                                                \
+        else MPMC_SUB(CAP, 2);                                                                 \
+    } while (0)
+    if (t.prop < 0 || t.prop > 2) return hipErrorInvalidValue;
     switch (t.cap) {
-    case 4: MPMC_SUB(4); break;
-    case 5: MPMC_SUB(5); break;
-    case 6: MPMC_SUB(6); break;
-    case 7: MPMC_SUB(7); break;
+    case 4: MPMC_SUB_P(4); break;
+    case 5: MPMC_SUB_P(5); break;
+    case 6: MPMC_SUB_P(6); break;
+    case 7: MPMC_SUB_P(7); break;
     default: return hipErrorInvalidValue;
     }
+#undef MPMC_SUB_P
 #undef MPMC_SUB
     return hipGetLastError();
 }

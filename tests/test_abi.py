@@ -163,6 +163,14 @@ def test_batch_argument_errors():
     big_delta = SystemConfig(lattice_nx=16, lattice_ny=16, phi=0.6, delta=0.9)
     assert _batch_sizes([a, big_delta])[0] == L.MPMC_EINVAL          # delta > w/2
     assert L.load().mpmc_last_error()
+    # the proposal may differ between replicas; other flags may not
+    d = SystemConfig(lattice_nx=20, lattice_ny=20, phi=0.7, delta=0.1, flags=pkg.FLAG_DISK)
+    assert _batch_sizes([a, d])[0] == L.MPMC_OK
+    ad = SystemConfig(lattice_nx=20, lattice_ny=20, phi=0.7, delta=0.1,
+                      flags=pkg.FLAG_DISK | pkg.FLAG_ACC)
+    assert _batch_sizes([d, ad])[0] == L.MPMC_EINVAL
+    unknown = SystemConfig(lattice_nx=16, lattice_ny=16, phi=0.6, delta=0.1, flags=16)
+    assert _batch_sizes([unknown])[0] == L.MPMC_EINVAL
 
 
 def test_bench_refuses_more_than_one_gpu():

@@ -99,6 +99,25 @@ def test_batch_sweeps_match_oracle_per_replica(gpu):
     assert B.count_overlaps() == 0
 
 
+def test_batch_mixed_proposals(gpu):
+    """Replicas may differ in the proposal: even replicas move in the square,
+    odd ones in the disk (MPMC_FLAG_DISK); each matches its own oracle."""
+    flags = [FLAGS | (gpu.FLAG_DISK if r % 2 else 0) for r in range(len(MIXED))]
+    cfgs = configs(gpu, MIXED)
+    for c, f in zip(cfgs, flags):
+        c.flags = f
+    B = gpu.HardDiskBatch(cfgs)
+    B.sweep(16)
+    B.sweep(3)
+    for r, s in enumerate(MIXED):
+        O = OracleSystem.lattice(s["nx"], s["ny"], s["phi"], w_min=1.0, w_max=s.get("w_max", 0.0),
+                                 delta=s.get("delta", 0.1), n_moves=s.get("n_moves", 4), seed=1,
+                                 replica=r, flags=flags[r])
+        O.sweep(19)
+        assert_replica(B, r, O, "mixed proposals")
+    assert B.count_overlaps() == 0
+
+
 def test_batch_subsweeps_and_explicit_shifts(gpu):
     B = gpu.HardDiskBatch(configs(gpu, MIXED))
     Os = oracles(MIXED)

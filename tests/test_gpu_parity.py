@@ -193,6 +193,37 @@ def test_lane_groups_match_for_every_capacity(gpu, lanes, nx, ny, phi, w_max):
         assert_same(Gm, Om, "lanes %d n_M %d" % (lanes, n_moves))
 
 
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+@pytest.mark.parametrize("nx,ny,phi,w_max", CONFIGS)
+def test_in_circle_moves_match(gpu, lanes, nx, ny, phi, w_max):
+    """In-circle trial moves (the paper's proposal, MPMC_FLAG_DISK) on every
+    capacity and lane count: sweeps bit-exact, accumulators included (they
+    hold the sum of the accepted moves' FP32 components), with n_M = 4 and
+    n_M = 7 and delta up to w/2."""
+    flags = FLAGS | gpu.FLAG_DISK
+    for n_moves, delta in ((4, 0.16), (7, 0.45)):
+        G, O = lattice_pair(gpu, nx, ny, phi, w_max, delta=delta, n_moves=n_moves, seed=11,
+                            flags=flags)
+        G.set_launch(lanes, 128)
+        G.sweep(19)
+        O.sweep(19)
+        assert_same(G, O, "in-circle lanes %d n_M %d" % (lanes, n_moves))
+        assert G.count_overlaps() == 0
+
+
+def test_in_circle_and_square_moves_differ(gpu):
+    """The flag really switches the proposal: same key, same start, the two
+    chains part after the first sweep (and each matches its own oracle)."""
+    Gs, Os = lattice_pair(gpu, 24, 24, 0.70, math.sqrt(2.0), delta=0.16, seed=4)
+    Gd, Od = lattice_pair(gpu, 24, 24, 0.70, math.sqrt(2.0), delta=0.16, seed=4,
+                          flags=FLAGS | gpu.FLAG_DISK)
+    for G, O in ((Gs, Os), (Gd, Od)):
+        G.sweep(3)
+        O.sweep(3)
+        assert_same(G, O)
+    assert not np.array_equal(Gs.get_state()[0], Gd.get_state()[0])
+
+
 def test_autotune_leaves_the_chain_alone(gpu):
     G, O = lattice_pair(gpu, 64, 64, 0.70, math.sqrt(2.0), delta=0.12, seed=6)
     lanes, block, us = G.autotune(16)
@@ -345,6 +376,40 @@ def test_large_workload_full_size(gpu, phi):
     O.sweep(16)
     assert_same(G, O, "16 sweeps")
     assert G.count_overlaps() == O.count_overlaps() == 0
+
+
+def _paper_pair(gpu, side, seed=1):
+    from paper_1211_1646_amd import workloads as W
+    w = W.paper_benchmark(side)
+    return lattice_pair(gpu, w["nx"], w["ny"], w["phi"], w["w_max"], delta=w["delta"],
+                        n_moves=w["n_moves"], seed=seed, flags=gpu.FLAG_DISK)
+
+
+def test_paper_benchmark_smallest_matches(gpu):
+    """The paper's Table 3 benchmark at its smallest N (253^2, run as a
+    254 x 252 lattice; in-circle moves of radius 0.16, n_M = 4): 100 warm-up
+    sweeps as the benchmark runs them, in the autotuned launch shape, equal
+    the oracle's whole state; so do 100 more."""
+    G, O = _paper_pair(gpu, 253)
+    lanes, block, _ = G.autotune(16)
+    O.sweep(G.AUTOTUNE_CANDIDATES * 2 * 16)
+    assert_same(G, O, "autotune")
+    for k in range(2):
+        G.sweep(100)
+        O.sweep(100)
+        assert_same(G, O, "paper benchmark %d00 sweeps, lanes %d block %d" % (k + 1, lanes, block))
+    assert G.count_overlaps() == 0
+
+
+def test_paper_benchmark_largest_full_size(gpu):
+    """N = 9,241,600 (3040^2), the largest Table 3 size, with the paper's
+    proposal: the whole state after 8 sweeps (captured graph path) equals the
+    oracle's."""
+    G, O = _paper_pair(gpu, 3040, seed=2)
+    G.sweep(8)
+    O.sweep(8)
+    assert_same(G, O, "3040^2, 8 sweeps")
+    assert G.count_overlaps() == 0
 
 
 @pytest.mark.parametrize("lanes", [1, 2])

@@ -289,6 +289,65 @@ def test_single_disk_acceptance_closed_form():
     assert n == 4 * 100000
 
 
+def test_single_disk_acceptance_closed_form_in_circle():
+    """One disk, uniformly placed in its cell, displaced uniformly in the
+    disk of radius delta (the paper's proposal): with |dx|, |dy| <= delta <=
+    w/2 the move stays in the cell with probability
+    E[(1 - |dx|/wx)(1 - |dy|/wy)] = 1 - 4 delta/(3 pi) (1/wx + 1/wy)
+    + delta^2 / (2 pi wx wy), since E|dx| = 4 delta / (3 pi) and
+    E|dx dy| = delta^2 / (2 pi) for a uniform point of the disk."""
+    wx, wy = np.float32(1.2), np.float32(1.5)
+    delta = np.float32(0.5)
+    S = OracleSystem.grid(4, 6, wx, wy, delta=delta, n_moves=4, seed=17,
+                          flags=OracleSystem.FLAG_DISK)
+    start = np.zeros(25, np.uint32)
+    start[1:] = 1
+    S.set_state(np.array([[0.6, 0.7]], np.float32), start)
+    S.sweep(200)
+    t0, a0 = S.counters()
+    S.sweep(100000)
+    t1, a1 = S.counters()
+    n = t1 - t0
+    p_hat = (a1 - a0) / n
+    d, x, y = float(delta), float(wx), float(wy)
+    p = 1 - 4 * d / (3 * math.pi) * (1 / x + 1 / y) + d * d / (2 * math.pi * x * y)
+    se = math.sqrt(p * (1 - p) / n)
+    assert abs(p_hat - p) < 10 * se, (p_hat, p, se)
+    # the square proposal's rate would be far off: the two are told apart
+    p_sq = (1 - d / (2 * x)) * (1 - d / (2 * y))
+    assert abs(p_hat - p_sq) > 30 * se
+
+
+def test_single_disk_in_circle_displacements():
+    """Accepted in-circle moves of a lone disk deep inside a wide cell are
+    uniform in the disk: mean 0, variance delta^2 / 4 per component, mean
+    length 2 delta / 3, never longer than delta, components uncorrelated."""
+    w = np.float32(1.9)
+    delta = np.float32(0.05)
+    S = OracleSystem.grid(4, 4, w, w, delta=delta, n_moves=1, seed=23,
+                          flags=OracleSystem.FLAG_ACC | OracleSystem.FLAG_DISK)
+    start = np.zeros(17, np.uint32)
+    start[1:] = 1
+    steps = []
+    xy = np.array([[0.95, 0.95]], np.float32)
+    for k in range(4000):
+        S.set_state(xy, start, sweep=k)
+        S.subsweep(0)
+        acc, _ = S.aux()
+        steps.append(acc[0].astype(np.float64))
+    st = np.array(steps)
+    r = np.hypot(st[:, 0], st[:, 1])
+    assert r.max() < float(delta)
+    v = float(delta) ** 2 / 4
+    assert abs(st[:, 0].mean()) < 5 * math.sqrt(v / len(st))
+    assert abs(st[:, 1].mean()) < 5 * math.sqrt(v / len(st))
+    assert abs(st[:, 0].var() / v - 1) < 0.1
+    assert abs(st[:, 1].var() / v - 1) < 0.1
+    # E r = 2 delta / 3, Var r = delta^2 / 18
+    assert abs(r.mean() - 2 * float(delta) / 3) < 5 * float(delta) / math.sqrt(18 * len(st))
+    assert abs(np.corrcoef(st[:, 0], st[:, 1])[0, 1]) < 0.1
+
+
 def test_single_disk_displacements():
     """Accepted displacements of a lone disk are symmetric, with variance
     delta^2 / 3 per component when the disk sits deep inside a wide cell, and
@@ -316,11 +375,13 @@ def test_single_disk_displacements():
     assert abs(np.corrcoef(st[:, 0], st[:, 1])[0, 1]) < 0.1
 
 
-def test_two_disk_separation_density():
+@pytest.mark.parametrize("flags", [0, OracleSystem.FLAG_DISK])
+def test_two_disk_separation_density(flags):
     """Two disks in a periodic box: in equilibrium the minimum-image
-    separation has density proportional to r on [1, min(L)/2]."""
+    separation has density proportional to r on [1, min(L)/2], with square
+    and with in-circle proposals alike (both are symmetric)."""
     w = np.float32(1.25)
-    S = OracleSystem.grid(6, 6, w, w, delta=np.float32(0.6), n_moves=4, seed=29)
+    S = OracleSystem.grid(6, 6, w, w, delta=np.float32(0.6), n_moves=4, seed=29, flags=flags)
     start = np.zeros(37, np.uint32)
     start[1:] = 2
     S.set_state(np.array([[0.3, 0.3], [1.2, 1.1]], np.float32), start)

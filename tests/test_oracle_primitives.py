@@ -1,5 +1,6 @@
 """Pins for the oracle's primitives: Philox, the integer and displacement maps,
 the visit rule, geometry and the tuner arithmetic.  CPU only."""
+import math
 import os
 import shutil
 import subprocess
@@ -85,6 +86,54 @@ def test_displacement_map_exhaustive():
         assert np.array_equal(dx, -dx[::-1])          # symmetric proposal
         assert np.all(np.abs(dx) < delta)
         assert dx.min() == -dx.max()
+
+
+def _disk_moves(words, delta):
+    out = np.empty((len(words), 2), np.float32)
+    for i, w in enumerate(words):
+        out[i] = oracle.disk_displacement(int(w), delta)
+    return out
+
+
+def test_disk_displacement_angles_exhaustive():
+    """In-circle proposal (Alg. 2's inCircle), angle half: for every one of
+    the 65536 angle words, the move points along (2h+1) pi / 65536 to within
+    FP32 rounding; flipping bit 15 gives exactly the opposite move and adding
+    a quarter (bit 14) turns it exactly by 90 degrees, so the proposal is
+    symmetric; its length does not depend on the angle beyond rounding."""
+    delta = np.float32(0.16)
+    ha = np.arange(65536, dtype=np.uint32)
+    for hr in (0, 40000, 65535):
+        d = _disk_moves((hr << 16) | ha, delta).astype(np.float64)
+        r = float(np.float32(np.sqrt(np.float64((2 * hr + 1) / 131072.0)))) * float(delta)
+        theta = (2 * ha.astype(np.float64) + 1) * math.pi / 65536
+        assert np.abs(d[:, 0] / r - np.cos(theta)).max() < 3e-7
+        assert np.abs(d[:, 1] / r - np.sin(theta)).max() < 3e-7
+        opp = d[ha ^ 0x8000]
+        assert np.array_equal(opp, -d)
+        turned = d[(ha + 0x4000) & 0xFFFF]
+        assert np.array_equal(turned[:, 0], -d[:, 1]) and np.array_equal(turned[:, 1], d[:, 0])
+        assert np.abs(np.hypot(d[:, 0], d[:, 1]) / r - 1).max() < 4e-7
+
+
+def test_disk_displacement_radii_exhaustive():
+    """Radius half: the squared length of the move, over the 65536 radius
+    words at a fixed angle, is uniform on (0, delta^2) -- the fraction of
+    words with |move| <= t delta is t^2 to within one word -- so the move is
+    uniform in area; every move lies strictly inside the disk."""
+    for delta in (np.float32(0.16), np.float32(0.7071)):
+        hr = np.arange(65536, dtype=np.uint32)
+        for ha in (0x1234, 0xBEEF):
+            d = _disk_moves((hr << 16) | ha, delta).astype(np.float64)
+            rr = np.hypot(d[:, 0], d[:, 1]) / float(delta)
+            assert rr.max() < 1.0 and rr.min() > 0.0
+            assert np.all(np.diff(rr) >= -1e-6)          # monotone in the word
+            for t in np.linspace(0.05, 1.0, 20):
+                frac = np.count_nonzero(rr <= t) / 65536.0
+                assert abs(frac - t * t) < 2.0 / 65536 + 1e-6, (t, frac)
+        # the same four moves at the centre angle of each quadrant
+        q = _disk_moves([(65535 << 16) | (0x2000 + 0x4000 * k) for k in range(4)], delta)
+        assert np.array_equal(q[2], -q[0]) and np.array_equal(q[3], -q[1])
 
 
 def test_visit_rule_paper_example():
