@@ -71,8 +71,16 @@ typedef int32_t mpmc_status;
  * radius (2h+1)/2^17 of the disk, its low half the angle (2h+1) pi/65536,
  * evaluated with FP32 Taylor series about 0 on (0, pi/4) and exact quarter
  * turns.  The proposal is exactly symmetric.  Replicas of one batch may
- * differ in this flag; all other flags must agree. */
+ * differ in this flag and in the two below; the buffer flags above must
+ * agree. */
 #define MPMC_FLAG_DISK 8u
+/* Diagnostics, for the balance test of Sec. 2.4 (Table 1): switch off the
+ * shuffle of each cell's particle list (cells are then visited in stored
+ * order, which breaks detailed balance), or the shuffle of the order of the
+ * four checkerboard sets (always a, b, c, d; the paper finds this harmless).
+ * All other random draws are unchanged.  Replicas may differ in them. */
+#define MPMC_FLAG_NO_PARTICLE_SHUFFLE 16u
+#define MPMC_FLAG_NO_SET_SHUFFLE 32u
 
 #define MPMC_HIST_BINS 200 /* contact histogram: 200 bins of 1e-4 sigma */
 

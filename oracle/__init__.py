@@ -195,6 +195,8 @@ class OracleSystem:
     FLAG_ACC = 1
     FLAG_TAG = 2
     FLAG_DISK = 8
+    FLAG_NO_PARTICLE_SHUFFLE = 16
+    FLAG_NO_SET_SHUFFLE = 32
 
     def __init__(self, handle):
         self._h = handle

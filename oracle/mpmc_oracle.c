@@ -262,7 +262,8 @@ typedef struct oracle_sys {
     uint32_t key[2];
     uint64_t sweep;
     uint64_t trials, accepts;
-    int flags;      /* bit 0: displacement accumulators, bit 1: tags, bit 3: disk moves */
+    int flags;      /* bit 0: displacement accumulators, bit 1: tags, bit 3: disk moves,
+                       bits 4, 5: no particle / no set shuffle */
     int cell_order; /* 0 row-major, 1 reversed, 2 scrambled (order test) */
     /* disk[c*cap + i] (Sec. 3.1), double buffer for the shift (Alg. 4) */
     float *disk_x, *disk_y, *dbl_x, *dbl_y;
@@ -277,6 +278,11 @@ typedef struct oracle_sys {
 #define FLAG_ACC 1
 #define FLAG_TAG 2
 #define FLAG_DISK 8 /* in-circle proposals instead of the square */
+/* The two shuffles the paper switches off in its balance test (Sec. 2.4,
+ * Table 1).  Without the particle shuffle detailed balance is lost; the
+ * set shuffle is not needed for correct sampling.  Diagnostic only. */
+#define FLAG_NO_PARTICLE_SHUFFLE 16
+#define FLAG_NO_SET_SHUFFLE 32
 
 static void *xcalloc(size_t n, size_t sz)
 {
@@ -472,8 +478,10 @@ static void cell_update(oracle_sys *S, int cx, int cy)
     uint32_t words[4];
 
     /* rng.shuffle(c.particles): Fisher-Yates (Durstenfeld) over the stored
-     * list; the k-th draw (k = 0,1,...) picks the partner of position n-1-k. */
-    for (int k = 0; k < n - 1; ++k) {
+     * list; the k-th draw (k = 0,1,...) picks the partner of position n-1-k.
+     * Skipped, and the list visited in stored order, under the ablation. */
+    int shuffles = (S->flags & FLAG_NO_PARTICLE_SHUFFLE) ? 0 : n - 1;
+    for (int k = 0; k < shuffles; ++k) {
         if ((k & 3) == 0) stream_block((uint32_t)c, S->sweep, TAG_SHUFFLE + (uint32_t)(k >> 2), S->key, words);
         int i = n - 1 - k;
         int j = (int)oracle_bounded(words[k & 3], (uint32_t)(i + 1));
@@ -615,7 +623,9 @@ void oracle_sweep_draws(const oracle_sys *S, uint64_t sweep, int order[4], int *
     uint32_t G[4];
     stream_block(CELL_GLOBAL, sweep, TAG_SWEEP, S->key, G);
     for (int i = 0; i < 4; ++i) order[i] = i;
-    for (int i = 3; i >= 1; --i) {
+    /* the set-order shuffle, skipped under the ablation (a, b, c, d always);
+     * f and d come from G[3] either way */
+    for (int i = 3; i >= 1 && !(S->flags & FLAG_NO_SET_SHUFFLE); --i) {
         int j = (int)oracle_bounded(G[3 - i], (uint32_t)(i + 1));
         int t = order[i]; order[i] = order[j]; order[j] = t;
     }

@@ -7,9 +7,11 @@ rebuild of the cell lists (Alg. 4), pressure from the contact value of g(r)
 (Sec. 4).  The work runs in libmpmc.so (include/mpmc.h); this package only
 marshals arguments.
 """
-from ._lib import FLAG_ACC, FLAG_ACCEPT_LOG, FLAG_DISK, FLAG_TAG, HIST_BINS, MPMCError, load  # noqa: F401
+from ._lib import (FLAG_ACC, FLAG_ACCEPT_LOG, FLAG_DISK, FLAG_NO_PARTICLE_SHUFFLE,  # noqa: F401
+                   FLAG_NO_SET_SHUFFLE, FLAG_TAG, HIST_BINS, MPMCError, load)
 from .system import (HardDiskBatch, HardDiskSystem, SystemConfig, batch_required_bytes,  # noqa: F401
                      geometry, required_bytes)
 
 __all__ = ["HardDiskSystem", "HardDiskBatch", "SystemConfig", "geometry", "required_bytes",
-           "batch_required_bytes", "MPMCError", "FLAG_ACC", "FLAG_ACCEPT_LOG", "FLAG_DISK", "FLAG_TAG", "HIST_BINS", "load"]
+           "batch_required_bytes", "MPMCError", "FLAG_ACC", "FLAG_ACCEPT_LOG", "FLAG_DISK", "FLAG_NO_PARTICLE_SHUFFLE",
+           "FLAG_NO_SET_SHUFFLE", "FLAG_TAG", "HIST_BINS", "load"]

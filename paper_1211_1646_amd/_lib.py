@@ -22,6 +22,8 @@ FLAG_ACC = 1
 FLAG_TAG = 2
 FLAG_ACCEPT_LOG = 4
 FLAG_DISK = 8        # in-circle trial moves (the paper's proposal)
+FLAG_NO_PARTICLE_SHUFFLE = 16  # diagnostic: breaks detailed balance (Table 1)
+FLAG_NO_SET_SHUFFLE = 32       # diagnostic: sets always a, b, c, d (Table 1)
 HIST_BINS = 200
 MLP_PARAMS = 1217
 

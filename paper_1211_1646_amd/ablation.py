@@ -1,0 +1,120 @@
+"""The balance test of Table 1 on the GPU: P* of hard disks with the particle
+shuffle and the checkerboard-set shuffle switched on or off (Sec. 2.4).
+
+One batch holds `per_case` independent replicas of each of the four cases,
+interleaved (replica r runs case r mod 4 with Philox key (seed, r)), all at
+the same N, packing fraction, proposal (in-circle, d = 0.16, n_M = 4 by
+default: the paper's tuned values) and cells narrower than sqrt(2).  After
+`equilibration` sweeps from the lattice, every replica takes a contact
+histogram every `sample_every` sweeps for `production` sweeps, with P* per
+block; a case's P* is the mean over its replicas of their time averages, and
+its standard error comes from the spread between those independent replicas.
+
+    python -m paper_1211_1646_amd.ablation --phi 0.708 --side 256
+
+prints one JSON line per packing fraction.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+from ._lib import FLAG_DISK, FLAG_NO_PARTICLE_SHUFFLE, FLAG_NO_SET_SHUFFLE
+from .system import HardDiskBatch, SystemConfig
+
+# (particle shuffle, set shuffle) -> flags; Table 1's row order
+CASES = (("yes", "yes", 0),
+         ("yes", "no", FLAG_NO_SET_SHUFFLE),
+         ("no", "yes", FLAG_NO_PARTICLE_SHUFFLE),
+         ("no", "no", FLAG_NO_PARTICLE_SHUFFLE | FLAG_NO_SET_SHUFFLE))
+
+# Table 1 (N = 256^2): P* for the four cases at phi = 0.698, 0.708, 0.716
+PAPER_TABLE1 = {"0.698": (9.17079, 9.1707, 9.1716, 9.1715),
+                "0.708": (9.18214, 9.1821, 9.1876, 9.1873),
+                "0.716": (9.1774, 9.1775, 9.1831, 9.1823)}
+
+
+def shuffle_ablation(phi: float, side: int = 256, per_case: int = 16,
+                     equilibration: int = 400_000, production: int = 400_000,
+                     sample_every: int = 100, blocks: int = 10, n_moves: int = 4,
+                     delta: float = 0.16, in_circle: bool = True, seed: int = 1,
+                     progress=None) -> dict:
+    R = 4 * per_case
+    disk = FLAG_DISK if in_circle else 0
+    cfgs = [SystemConfig(lattice_nx=side, lattice_ny=side, phi=phi, w_min=1.0,
+                         w_max=math.sqrt(2.0), delta=delta, n_moves=n_moves, seed=seed,
+                         replica=r, flags=CASES[r % 4][2] | disk) for r in range(R)]
+    B = HardDiskBatch(cfgs)
+    t0 = time.time()
+    chunk = 50_000
+    done = 0
+    while done < equilibration:
+        k = min(chunk, equilibration - done)
+        B.sweep(k)
+        B.synchronize()
+        done += k
+        if progress:
+            progress("phi %.3f equilibration %d / %d (%.0f s)" % (phi, done, equilibration,
+                                                                 time.time() - t0))
+    per_block = production // blocks
+    samples = max(1, per_block // sample_every)
+    P = np.zeros((blocks, R))
+    for b in range(blocks):
+        for k in range(samples):
+            B.sweep(sample_every)
+            B.pair_histogram(reset=(k == 0))
+        for r in range(R):
+            P[b, r] = B.pressure_from_contact(r)[0]
+        if progress:
+            progress("phi %.3f block %d / %d (%.0f s)" % (phi, b + 1, blocks, time.time() - t0))
+    tr, ac, _, _ = B.stats()
+    B.close()
+    per_replica = P.mean(axis=0)
+    key = "%.3f" % phi
+    out = {"phi": phi, "N": side * side, "replicas_per_case": per_case,
+           "equilibration_sweeps": equilibration, "production_sweeps": production,
+           "proposal": "in-circle" if in_circle else "square", "delta": delta,
+           "n_moves": n_moves, "seconds": time.time() - t0, "cases": []}
+    for i, (ps, cs, _) in enumerate(CASES):
+        v = per_replica[i::4]
+        case = {"particle_shuffle": ps, "set_shuffle": cs, "P": float(v.mean()),
+                "P_se": float(v.std(ddof=1) / math.sqrt(len(v))),
+                "acceptance": float(ac[i::4].sum() / max(tr[i::4].sum(), 1))}
+        if key in PAPER_TABLE1:
+            case["paper_P"] = PAPER_TABLE1[key][i]
+        out["cases"].append(case)
+    ref = out["cases"][0]
+    for c in out["cases"][1:]:
+        d = c["P"] - ref["P"]
+        c["minus_both_shuffled"] = d
+        c["z"] = d / math.sqrt(c["P_se"] ** 2 + ref["P_se"] ** 2)
+        if "paper_P" in c:
+            c["paper_minus_both_shuffled"] = c["paper_P"] - ref["paper_P"]
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--phi", type=float, nargs="+", default=[0.708])
+    ap.add_argument("--side", type=int, default=256)
+    ap.add_argument("--per-case", type=int, default=16)
+    ap.add_argument("--equilibration", type=int, default=400_000)
+    ap.add_argument("--production", type=int, default=400_000)
+    ap.add_argument("--sample-every", type=int, default=100)
+    ap.add_argument("--blocks", type=int, default=10)
+    ap.add_argument("--square", action="store_true", help="square trial moves instead of in-circle")
+    ap.add_argument("--seed", type=int, default=1)
+    a = ap.parse_args()
+    for phi in a.phi:
+        r = shuffle_ablation(phi, a.side, a.per_case, a.equilibration, a.production,
+                             a.sample_every, a.blocks, in_circle=not a.square, seed=a.seed,
+                             progress=lambda m: print("[ablation] " + m, flush=True))
+        print(json.dumps(r), flush=True)
+
+
+if __name__ == "__main__":
+    main()

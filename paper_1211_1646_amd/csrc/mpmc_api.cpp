@@ -140,12 +140,16 @@ mpmc_status derive_geometry(const mpmc_params *p, mpmc_geometry *g)
     return MPMC_OK;
 }
 
+// Flags that change only the chain, not the buffers: may differ between replicas.
+constexpr uint32_t kChainFlags =
+    MPMC_FLAG_DISK | MPMC_FLAG_NO_PARTICLE_SHUFFLE | MPMC_FLAG_NO_SET_SHUFFLE;
+
 mpmc_status check_params(const mpmc_params *p, const mpmc_geometry &g)
 {
     if (!(p->delta > 0.0f) || p->delta > 0.5f * std::min(g.w_x, g.w_y))
         return fail(MPMC_EINVAL, "delta must lie in (0, min(w)/2]");
     if (p->n_moves < 0 || p->n_moves > (1 << 20)) return fail(MPMC_EINVAL, "n_moves out of range");
-    if (p->flags & ~(MPMC_FLAG_ACC | MPMC_FLAG_TAG | MPMC_FLAG_ACCEPT_LOG | MPMC_FLAG_DISK))
+    if (p->flags & ~(MPMC_FLAG_ACC | MPMC_FLAG_TAG | MPMC_FLAG_ACCEPT_LOG | kChainFlags))
         return fail(MPMC_EINVAL, "unknown flag");
     return MPMC_OK;
 }
@@ -174,8 +178,8 @@ mpmc_status plan(const mpmc_params *p, int n, Layout *L)
         if (s) return s;
         s = check_params(&p[r], L->geo[(size_t)r]);
         if (s) return s;
-        if ((p[r].flags ^ p[0].flags) & ~MPMC_FLAG_DISK)
-            return fail(MPMC_EINVAL, "replicas must share flags (all but MPMC_FLAG_DISK)");
+        if ((p[r].flags ^ p[0].flags) & ~kChainFlags)
+            return fail(MPMC_EINVAL, "replicas must share the buffer flags (ACC, TAG, ACCEPT_LOG)");
         const mpmc_geometry &g = L->geo[(size_t)r];
         Rep &R = L->reps[(size_t)r];
         std::memset(&R, 0, sizeof R);
@@ -198,6 +202,8 @@ mpmc_status plan(const mpmc_params *p, int n, Layout *L)
         R.key1 = p[r].replica;
         R.delta0 = p[r].delta;
         R.disk = (p[r].flags & MPMC_FLAG_DISK) ? 1 : 0;
+        R.ablate = ((p[r].flags & MPMC_FLAG_NO_PARTICLE_SHUFFLE) ? mpmc::kAblateParticleShuffle : 0) |
+                   ((p[r].flags & MPMC_FLAG_NO_SET_SHUFFLE) ? mpmc::kAblateSetShuffle : 0);
         L->cells += R.cpad;
         L->N += R.g.N;
         L->active += R.apad;
@@ -561,9 +567,12 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
     h->t.R = n;
     h->t.cap = L.cap;
     {
-        int ndisk = 0;
-        for (const Rep &R : L.reps) ndisk += R.disk;
-        h->t.prop = ndisk == 0 ? 0 : (ndisk == n ? 1 : 2);
+        int ndisk = 0, noshuf = 0;
+        for (const Rep &R : L.reps) {
+            ndisk += R.disk;
+            noshuf += (R.ablate & mpmc::kAblateParticleShuffle) ? 1 : 0;
+        }
+        h->t.prop = noshuf > 0 ? 2 : (ndisk == 0 ? 0 : (ndisk == n ? 1 : 2));
     }
     h->t.cells = L.cells;
     h->t.active = L.active;

@@ -24,6 +24,8 @@ constexpr int kGranule = 64;              // counter partials: one per 64 active
 constexpr int kMsdBlocksMax = 512;
 constexpr int kMlpParams = 1217;          // 3 -> 32 -> 32 -> 1 network
 constexpr int kNbrLds = 16;               // reachable neighbours a lane keeps in LDS
+constexpr int kAblateParticleShuffle = 1; // Rep::ablate: visit cells in stored order
+constexpr int kAblateSetShuffle = 2;      // Rep::ablate: sets always a, b, c, d
 
 // Per-replica control block: everything a captured sweep graph reads or
 // writes that changes between launches lives here, not in kernel arguments.
@@ -74,7 +76,7 @@ struct Rep {
     unsigned int key0, key1;
     float delta0;
     int disk;            // 1: in-circle trial moves, 0: square
-    int pad;
+    int ablate;          // kAblate* bits: shuffles switched off (Table 1)
 };
 
 // Device tables of a handle (in the caller's control buffer), passed to the
@@ -87,7 +89,8 @@ struct Tables {
     const uint16_t *crep;   // replica of each rebin tile
     int R;
     int cap;                // largest capacity
-    int prop;               // trial moves: 0 all square, 1 all in-circle, 2 per replica
+    int prop;               // sub-sweep variant: 0 all square, 1 all in-circle, 2 per replica
+                            // (mixed proposals or the particle-shuffle ablation)
     long long cells;        // padded cells, all replicas
     long long active;       // padded active slots, all replicas
     long long N;            // disks, all replicas

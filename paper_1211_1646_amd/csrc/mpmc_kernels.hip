@@ -133,13 +133,14 @@ struct Draws {
 // d = u (w_f / 2) from its low 24 bits.  The order is kept as four bytes of
 // one register so that no array is indexed at run time.
 __device__ __forceinline__ Draws sweep_draws(unsigned long long s, uint32_t k0, uint32_t k1,
-                                             float wx, float wy)
+                                             float wx, float wy, bool shuffle_sets)
 {
     const uint4 G = philox(kCellGlobal, (uint32_t)s, (uint32_t)(s >> 32), kTagSweep, k0, k1);
     Draws D;
     uint32_t ord = 0x03020100u;
 #pragma unroll
     for (int i = 3; i >= 1; --i) {
+        if (!shuffle_sets) break;   // the set-shuffle ablation (Table 1): a, b, c, d
         const uint32_t j = bounded(word_of(G, 3 - i), (uint32_t)(i + 1));
         const uint32_t oi = (ord >> (8 * i)) & 0xFFu;
         const uint32_t oj = (ord >> (8 * j)) & 0xFFu;
@@ -155,9 +156,10 @@ __device__ __forceinline__ Draws sweep_draws(unsigned long long s, uint32_t k0, 
 }
 
 // Record the draws of sweep s in the control block (one thread).
-__device__ __forceinline__ void store_draws(Ctl *ctl, unsigned long long s, float wx, float wy)
+__device__ __forceinline__ void store_draws(Ctl *ctl, unsigned long long s, const Rep &R)
 {
-    const Draws D = sweep_draws(s, ctl->key0, ctl->key1, wx, wy);
+    const Draws D = sweep_draws(s, ctl->key0, ctl->key1, R.g.wx, R.g.wy,
+                                (R.ablate & kAblateSetShuffle) == 0);
     Ctl::Draw &r = ctl->draw;
     r.order = D.order;
     r.f = D.f;
@@ -364,8 +366,10 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
     const uint32_t k0 = ctl->key0, k1 = ctl->key1;
     const float delta = ctl->delta;
     const int n_moves = R.n_moves;
-    // proposal: fixed for the launch (PROP 0 square, 1 in-circle) or per replica
+    // proposal: fixed for the launch (PROP 0 square, 1 in-circle) or per
+    // replica (PROP 2, which also carries the particle-shuffle ablation)
     const bool disk = PROP == 2 ? R.disk != 0 : PROP == 1;
+    const bool shuffle = PROP == 2 ? (R.ablate & kAblateParticleShuffle) == 0 : true;
     const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
 
     int Q = set;
@@ -446,7 +450,7 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
             // Philox blocks of this cell: one shuffle block (n <= 5) and the
             // first trial block, issued while the loads are outstanding.
             uint4 Wsh = make_uint4(0, 0, 0, 0);
-            if (n > 1) Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle, k0, k1);
+            if (n > 1 && shuffle) Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle, k0, k1);
             uint4 W = make_uint4(0, 0, 0, 0);
             if (n_moves > 0) W = philox((uint32_t)c, s_lo, s_hi, 0u, k0, k1);
             // 3. translate into the cell's frame, keep the disks that can
@@ -497,14 +501,15 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
             // done on a packed permutation (nibble q = source slot of list
             // position q) and applied to the registers once.
             uint32_t P = 0x76543210u;
-            for (int k = 0; k < n - 1; ++k) {
+            const int nshuf = shuffle ? n - 1 : 0;
+            for (int k = 0; k < nshuf; ++k) {
                 if (k > 0 && (k & 3) == 0)
                     Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle + (uint32_t)(k >> 2), k0, k1);
                 const int i = n - 1 - k;
                 const int j = (int)bounded(word_of(Wsh, k & 3), (uint32_t)(i + 1));
                 P = nib_swap(P, i, j);
             }
-            if (n > 1) {
+            if (nshuf > 0) {
                 rperm(px, P);
                 rperm(py, P);
                 if (has_acc) {
@@ -665,8 +670,10 @@ k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ s
     const uint32_t k0 = ctl->key0, k1 = ctl->key1;
     const float delta = ctl->delta;
     const int n_moves = R.n_moves;
-    // proposal: fixed for the launch (PROP 0 square, 1 in-circle) or per replica
+    // proposal: fixed for the launch (PROP 0 square, 1 in-circle) or per
+    // replica (PROP 2, which also carries the particle-shuffle ablation)
     const bool disk = PROP == 2 ? R.disk != 0 : PROP == 1;
+    const bool shuffle = PROP == 2 ? (R.ablate & kAblateParticleShuffle) == 0 : true;
     const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
 
     int Q = set;
@@ -795,14 +802,15 @@ k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ s
             }
             const int KL = K4 < kL ? K4 : kL;
             uint32_t P = 0x76543210u;
-            for (int k = 0; k < n - 1; ++k) {
+            const int nshuf = shuffle ? n - 1 : 0;
+            for (int k = 0; k < nshuf; ++k) {
                 if (k > 0 && (k & 3) == 0)
                     Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle + (uint32_t)(k >> 2), k0, k1);
                 const int i = n - 1 - k;
                 const int j = (int)bounded(word_of(Wsh, k & 3), (uint32_t)(i + 1));
                 P = nib_swap(P, i, j);
             }
-            if (n > 1) {
+            if (nshuf > 0) {
                 rperm(px, P);
                 rperm(py, P);
                 if (has_acc) {
@@ -1093,7 +1101,7 @@ __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
     }
     if (first && threadIdx.x == 0 && a.advance) {
         const unsigned long long s = ctl->sweep + 1ull;
-        store_draws(ctl, s, g.wx, g.wy);
+        store_draws(ctl, s, R);
         ctl->sweep = s;
     }
 }
@@ -1412,7 +1420,7 @@ __global__ void k_ctl_reset(Tables t, int first, unsigned long long sweep)
         ctl->overlaps = 0;
         ctl->msd = 0.0;
         for (int i = 0; i < 4; ++i) ctl->fit[i] = 0.0;
-        store_draws(ctl, sweep, R.g.wx, R.g.wy);
+        store_draws(ctl, sweep, R);
     }
     for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) ctl->hist[i] = 0ull;
 }
@@ -1423,7 +1431,7 @@ __global__ void k_ctl_set_key0(Tables t, unsigned int key0)
     if (r >= t.R) return;
     Ctl *ctl = t.ctls + r;
     ctl->key0 = key0;
-    store_draws(ctl, ctl->sweep, t.reps[r].g.wx, t.reps[r].g.wy);
+    store_draws(ctl, ctl->sweep, t.reps[r]);
 }
 
 __global__ void k_ctl_set_delta(Tables t, int first, int count, float delta)

@@ -118,6 +118,27 @@ def test_batch_mixed_proposals(gpu):
     assert B.count_overlaps() == 0
 
 
+def test_batch_mixed_shuffle_ablations(gpu):
+    """Replicas with and without the particle / set shuffles of Table 1, and
+    with either proposal, in one batch: each matches its own oracle."""
+    choices = [0, gpu.FLAG_NO_PARTICLE_SHUFFLE, gpu.FLAG_NO_SET_SHUFFLE,
+               gpu.FLAG_NO_PARTICLE_SHUFFLE | gpu.FLAG_NO_SET_SHUFFLE | gpu.FLAG_DISK,
+               gpu.FLAG_DISK, gpu.FLAG_NO_SET_SHUFFLE | gpu.FLAG_DISK]
+    flags = [FLAGS | choices[r % len(choices)] for r in range(len(MIXED))]
+    cfgs = configs(gpu, MIXED)
+    for c, f in zip(cfgs, flags):
+        c.flags = f
+    B = gpu.HardDiskBatch(cfgs)
+    B.sweep(16)
+    B.sweep(5)
+    for r, s in enumerate(MIXED):
+        O = OracleSystem.lattice(s["nx"], s["ny"], s["phi"], w_min=1.0, w_max=s.get("w_max", 0.0),
+                                 delta=s.get("delta", 0.1), n_moves=s.get("n_moves", 4), seed=1,
+                                 replica=r, flags=flags[r])
+        O.sweep(21)
+        assert_replica(B, r, O, "mixed ablations")
+
+
 def test_batch_subsweeps_and_explicit_shifts(gpu):
     B = gpu.HardDiskBatch(configs(gpu, MIXED))
     Os = oracles(MIXED)

@@ -211,6 +211,24 @@ def test_in_circle_moves_match(gpu, lanes, nx, ny, phi, w_max):
         assert G.count_overlaps() == 0
 
 
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+@pytest.mark.parametrize("ablate", ["particle", "set", "both"])
+def test_shuffle_ablations_match(gpu, lanes, ablate):
+    """The balance-test switches of Table 1 (no particle shuffle, no set
+    shuffle, both off), with square and in-circle moves, on capacities 4 and
+    7: sweeps bit-exact."""
+    bits = {"particle": gpu.FLAG_NO_PARTICLE_SHUFFLE, "set": gpu.FLAG_NO_SET_SHUFFLE,
+            "both": gpu.FLAG_NO_PARTICLE_SHUFFLE | gpu.FLAG_NO_SET_SHUFFLE}[ablate]
+    for extra in (0, gpu.FLAG_DISK):
+        for nx, ny, phi, w_max in ((24, 24, 0.70, math.sqrt(2.0)), (20, 20, 0.72, 1.932)):
+            G, O = lattice_pair(gpu, nx, ny, phi, w_max, delta=0.15, n_moves=5, seed=21,
+                                flags=FLAGS | bits | extra)
+            G.set_launch(lanes, 128)
+            G.sweep(17)
+            O.sweep(17)
+            assert_same(G, O, "ablation %s lanes %d flags %d" % (ablate, lanes, bits | extra))
+
+
 def test_in_circle_and_square_moves_differ(gpu):
     """The flag really switches the proposal: same key, same start, the two
     chains part after the first sweep (and each matches its own oracle)."""

@@ -265,6 +265,61 @@ def test_set_order_is_uniform_and_shift_is_uniform():
     assert kstest(ds, "uniform").pvalue > 1e-4
 
 
+def test_set_shuffle_ablation_fixes_the_order_only():
+    """Without the set shuffle (Table 1's "CB. No") the sets run a, b, c, d
+    in every sweep, while the shift direction and distance are the ones the
+    shuffled chain draws for the same sweep and key."""
+    A = OracleSystem.lattice(8, 8, 0.5)
+    B = OracleSystem.lattice(8, 8, 0.5, flags=OracleSystem.FLAG_NO_SET_SHUFFLE)
+    orders = set()
+    for s in range(500):
+        oa, fa, da = A.draws(s)
+        ob, fb, db = B.draws(s)
+        orders.add(tuple(oa))
+        assert ob == [0, 1, 2, 3]
+        assert (fa, da) == (fb, db)
+    assert len(orders) == 24
+
+
+def _moved_tags(flags, sweeps=3000):
+    """One cell of three well-separated disks, one trial per cell: the tag
+    of the disk each accepted trial moved, and whether storage order held."""
+    w = np.float32(1.9)
+    S = OracleSystem.grid(4, 4, w, w, delta=np.float32(0.05), n_moves=1, seed=41,
+                          flags=OracleSystem.FLAG_TAG | flags)
+    xy = np.array([[0.3, 0.3], [1.5, 0.3], [0.3, 1.5]], np.float32)
+    start = np.zeros(17, np.uint32)
+    start[1:] = 3
+    tag = np.array([10, 11, 12], np.uint32)
+    moved, kept_order = [], True
+    for k in range(sweeps):
+        S.set_state(xy, start, sweep=k, tag=tag)
+        S.subsweep(0)
+        xy1, _, _ = S.get_state()
+        _, tag1 = S.aux()
+        kept_order &= bool(np.array_equal(tag1, tag))
+        for j in range(3):
+            i = int(np.nonzero(tag == tag1[j])[0][0])
+            if not np.array_equal(xy1[j], xy[i]):
+                moved.append(int(tag1[j]))
+    return moved, kept_order
+
+
+def test_particle_shuffle_ablation_visits_in_stored_order():
+    """Without the particle shuffle (Table 1's "P. No") the one trial of a
+    cell always goes to the first disk of the stored list, and the list is
+    not reordered; with it, each of the three disks is chosen a third of the
+    time (chi-square) and the stored order changes."""
+    from scipy.stats import chi2
+    moved, kept = _moved_tags(OracleSystem.FLAG_NO_PARTICLE_SHUFFLE)
+    assert kept and len(moved) > 2500 and set(moved) == {10}
+    moved, kept = _moved_tags(0)
+    assert not kept
+    cnt = np.bincount(np.array(moved) - 10, minlength=3).astype(float)
+    e = cnt.sum() / 3
+    assert chi2.sf(((cnt - e) ** 2 / e).sum(), 2) > 1e-4
+
+
 # ------------------------------------------------- closed-form equilibria
 def test_single_disk_acceptance_closed_form():
     """One disk, uniformly placed in its cell, displaced uniformly in the
