@@ -20,10 +20,11 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    Calls marked "async" only enqueue work on it; calls marked "sync" wait
  *    for it and copy results to host memory.
- *  - Positions are FP32 cell-local coordinates in (0, w] per axis, stored in
- *    compressed-row form: cells in row-major order c = cy*cells_x + cx, the
- *    particles of cell c at xy[2*k], xy[2*k+1] for start[c] <= k < start[c+1],
- *    start[cells] = N.
+ *  - Positions are FP32 cell-local coordinates in (0, w] per axis.  The
+ *    state calls exchange them in compressed-row form: cells in row-major
+ *    order c = cy*cells_x + cx, the particles of cell c at xy[2*k],
+ *    xy[2*k+1] for start[c] <= k < start[c+1], start[cells] = N.  (The
+ *    device buffers hold them in per-cell slots; see mpmc_buffer_sizes.)
  *  - Every call returns MPMC_OK (0) or a negative status; mpmc_last_error()
  *    gives a message for the calling thread's last failure.  Argument and
  *    geometry errors are detected on the host before anything is enqueued.
@@ -117,15 +118,18 @@ typedef struct mpmc_geometry {
     double density;        /* n_particles / (box_x * box_y)                    */
 } mpmc_geometry;
 
-/* Bytes the caller must provide for each buffer.  pos/start/acc/tag are
+/* Bytes the caller must provide for each buffer.  pos/count/acc/tag are
  * ping-pong pairs: each of the two halves needs the reported size.  acc and
- * tag are 0 unless the corresponding flag is set. */
+ * tag are 0 unless the corresponding flag is set.  On the device the disks
+ * sit in fixed slots, capacity-many per cell (the paper's disk[x, y, i],
+ * Sec. 3.1; the largest capacity of a batch's replicas), with a count per
+ * cell; the state calls below exchange compact lists. */
 typedef struct mpmc_buffer_sizes {
-    size_t pos;   /* float2 per particle                                       */
-    size_t start; /* uint32 per cell + 1                                       */
-    size_t acc;   /* float2 per particle (MPMC_FLAG_ACC)                        */
-    size_t tag;   /* uint32 per particle (MPMC_FLAG_TAG)                        */
-    size_t work;  /* scratch: scan partials and reductions                     */
+    size_t pos;   /* float2 per slot (cells x capacity)                        */
+    size_t count; /* uint32 per cell                                           */
+    size_t acc;   /* float2 per slot (MPMC_FLAG_ACC)                            */
+    size_t tag;   /* uint32 per slot (MPMC_FLAG_TAG)                            */
+    size_t work;  /* scratch: completion counters, partials, reductions        */
     size_t ctl;   /* control block: sweep counter, key, delta, counters,
                      error word, contact histogram                             */
     size_t accept_log; /* uint32 per cell (MPMC_FLAG_ACCEPT_LOG), else 0        */
@@ -134,7 +138,7 @@ typedef struct mpmc_buffer_sizes {
 /* Device pointers, each 256-byte aligned, sizes as reported above. */
 typedef struct mpmc_buffers {
     void *pos[2];
-    void *start[2];
+    void *count[2];
     void *acc[2];   /* NULL unless MPMC_FLAG_ACC */
     void *tag[2];   /* NULL unless MPMC_FLAG_TAG */
     void *work;

@@ -47,13 +47,13 @@ class Geometry(C.Structure):
 
 
 class BufferSizes(C.Structure):
-    _fields_ = [("pos", C.c_size_t), ("start", C.c_size_t), ("acc", C.c_size_t),
+    _fields_ = [("pos", C.c_size_t), ("count", C.c_size_t), ("acc", C.c_size_t),
                 ("tag", C.c_size_t), ("work", C.c_size_t), ("ctl", C.c_size_t),
                 ("accept_log", C.c_size_t)]
 
 
 class Buffers(C.Structure):
-    _fields_ = [("pos", C.c_void_p * 2), ("start", C.c_void_p * 2), ("acc", C.c_void_p * 2),
+    _fields_ = [("pos", C.c_void_p * 2), ("count", C.c_void_p * 2), ("acc", C.c_void_p * 2),
                 ("tag", C.c_void_p * 2), ("work", C.c_void_p), ("ctl", C.c_void_p),
                 ("accept_log", C.c_void_p)]
 

@@ -216,8 +216,7 @@ mpmc_status plan(const mpmc_params *p, int n, Layout *L)
 
 size_t work_bytes(const Layout &L)
 {
-    return align256((size_t)mpmc::scan_entries(L.cells) * 4) +
-           align256((size_t)mpmc::count_stride(L.active) * 2 * 8) +
+    return align256((size_t)mpmc::count_stride(L.active) * 2 * 8) +
            align256((size_t)mpmc::kMsdBlocksMax * sizeof(double)) +
            (size_t)L.active * mpmc::ovf_per_slot(L.cap) * 8 + 256;
 }
@@ -245,10 +244,11 @@ mpmc_status sizes_of(const mpmc_params *p, int n, mpmc_buffer_sizes *out)
     Layout L;
     const mpmc_status s = plan(p, n, &L);
     if (s) return s;
-    out->pos = align256(std::max<size_t>(8 * (size_t)L.N, 8));
-    out->start = align256(4 * (size_t)(L.cells + 1));
-    out->acc = (p[0].flags & MPMC_FLAG_ACC) ? align256(std::max<size_t>(8 * (size_t)L.N, 8)) : 0;
-    out->tag = (p[0].flags & MPMC_FLAG_TAG) ? align256(std::max<size_t>(4 * (size_t)L.N, 4)) : 0;
+    const size_t slots = (size_t)L.cells * (size_t)L.cap;   // L.cap slots per cell
+    out->pos = align256(8 * slots);
+    out->count = align256(4 * (size_t)L.cells);
+    out->acc = (p[0].flags & MPMC_FLAG_ACC) ? align256(8 * slots) : 0;
+    out->tag = (p[0].flags & MPMC_FLAG_TAG) ? align256(4 * slots) : 0;
     out->work = work_bytes(L);
     out->ctl = ctl_layout(L).total;
     out->accept_log = (p[0].flags & MPMC_FLAG_ACCEPT_LOG) ? align256(4 * (size_t)L.cells) : 0;
@@ -262,8 +262,8 @@ struct mpmc_system {
     Layout L;
     mpmc::Tables t;
     hipStream_t st;
-    float2 *pos[2];
-    uint32_t *start[2];
+    float2 *pos[2];     // slots: t.cap per cell
+    uint32_t *count[2]; // disks per cell
     float2 *acc[2];
     uint32_t *tag[2];
     mpmc::Work work;
@@ -312,7 +312,7 @@ mpmc_status read_ctl(mpmc_system *h)
 
 mpmc_status enqueue_subsweep(mpmc_system *h, int set)
 {
-    MPMC_HIP(mpmc::launch_subsweep(h->t, h->pos[h->cur], h->start[h->cur], h->acc[h->cur],
+    MPMC_HIP(mpmc::launch_subsweep(h->t, h->cur, h->pos[h->cur], h->count[h->cur], h->acc[h->cur],
                                    h->tag[h->cur], h->alog, h->work, set, h->block, h->lanes,
                                    h->st));
     return MPMC_OK;
@@ -321,8 +321,8 @@ mpmc_status enqueue_subsweep(mpmc_system *h, int set)
 mpmc_status enqueue_rebin(mpmc_system *h, int f, float d, int advance)
 {
     const int o = h->cur ^ 1;
-    MPMC_HIP(mpmc::launch_rebin(h->t, h->pos[h->cur], h->start[h->cur], h->acc[h->cur],
-                                h->tag[h->cur], h->pos[o], h->start[o], h->acc[o], h->tag[o],
+    MPMC_HIP(mpmc::launch_rebin(h->t, h->cur, h->pos[h->cur], h->count[h->cur], h->acc[h->cur],
+                                h->tag[h->cur], h->pos[o], h->count[o], h->acc[o], h->tag[o],
                                 h->work, f, d, advance, h->st));
     h->cur = o;
     return MPMC_OK;
@@ -388,14 +388,31 @@ mpmc_status validate_host_state(const Rep &R, const float *xy, const uint32_t *s
     return MPMC_OK;
 }
 
-// Offsets of replica r in global numbering, padded cells included:
-// out[0 .. cpad) (the entry after them belongs to the next replica).  Entries
-// past C hold N_r, so the padding cells take up whatever start[C] leaves.
-void global_offsets(const Rep &R, const uint32_t *start, uint32_t *out)
+// A replica's compact lists (xy, start, tags in its own numbering) laid out
+// in its slots: counts for its cpad cells (padding cells empty) and S slots
+// per cell; unused slots hold zeros.
+struct SlotState {
+    std::vector<uint32_t> count;   // [cpad]
+    std::vector<float> xy;         // [cpad * S * 2]
+    std::vector<uint32_t> tag;     // [cpad * S]
+};
+
+void to_slots(const Rep &R, int S, const float *xy, const uint32_t *start, const uint32_t *tags,
+              SlotState &o)
 {
-    for (long long c = 0; c < R.cpad; ++c) {
-        const uint32_t v = c <= R.g.C ? start[c] : (uint32_t)R.g.N;
-        out[c] = (uint32_t)R.pb + v;
+    const size_t cells = (size_t)R.cpad;
+    o.count.assign(cells, 0u);
+    o.xy.assign(cells * (size_t)S * 2, 0.0f);
+    o.tag.assign(cells * (size_t)S, 0u);
+    for (int c = 0; c < R.g.C; ++c) {
+        const uint32_t b = start[c], n = start[c + 1] - start[c];
+        o.count[(size_t)c] = n;
+        for (uint32_t i = 0; i < n; ++i) {
+            const size_t k = (size_t)c * S + i;
+            o.xy[2 * k] = xy[2 * (size_t)(b + i)];
+            o.xy[2 * k + 1] = xy[2 * (size_t)(b + i) + 1];
+            o.tag[k] = tags ? tags[b + i] : b + i;
+        }
     }
 }
 
@@ -439,11 +456,50 @@ mpmc_status build_lattice(const mpmc_params &p, const Rep &R, std::vector<float>
     return validate_host_state(R, xy.data(), start.data());
 }
 
+// Copy a replica's counts (and, if asked, one float2 slot array) to the host;
+// the caller synchronises (read_ctl) before using them.
+mpmc_status read_slots(mpmc_system *h, const Rep &R, const float2 *dev, std::vector<float2> *out,
+                       std::vector<uint32_t> &cnt)
+{
+    const size_t S = (size_t)h->t.cap, n = (size_t)R.g.C * S;
+    cnt.resize(std::max<size_t>((size_t)R.g.C, 1));
+    if (R.g.C > 0)
+        MPMC_HIP(hipMemcpyAsync(cnt.data(), h->count[h->cur] + R.cb, sizeof(uint32_t) * (size_t)R.g.C,
+                                hipMemcpyDeviceToHost, h->st));
+    if (out && dev) {
+        out->resize(std::max<size_t>(n, 1));
+        if (n) MPMC_HIP(hipMemcpyAsync(out->data(), dev + (size_t)R.cb * S, sizeof(float2) * n,
+                                       hipMemcpyDeviceToHost, h->st));
+    }
+    return MPMC_OK;
+}
+
+// Slots -> compact lists in the replica's own numbering: xy (if both given)
+// and start[C + 1] (if given).  Fails if the counts do not add up to N.
+mpmc_status compact_lists(const Rep &R, int S, const std::vector<uint32_t> &cnt, const float2 *slots,
+                          float2 *xy, uint32_t *start)
+{
+    uint64_t total = 0;
+    for (int c = 0; c < R.g.C; ++c) {
+        if (cnt[(size_t)c] > (uint32_t)R.g.cap) return fail(MPMC_EDEVICE, "cell above capacity");
+        total += cnt[(size_t)c];
+    }
+    if ((long long)total != R.g.N) return fail(MPMC_EDEVICE, "cell counts do not add up to N");
+    uint32_t k = 0;
+    for (int c = 0; c < R.g.C; ++c) {
+        if (start) start[c] = k;
+        for (uint32_t i = 0; i < cnt[(size_t)c]; ++i, ++k)
+            if (slots && xy) xy[k] = slots[(size_t)c * S + i];
+    }
+    if (start) start[R.g.C] = k;
+    return MPMC_OK;
+}
+
 // Overlap check of the loaded replicas in the kernels' metric; marks them
 // loaded when clean.
 mpmc_status check_loaded(mpmc_system *h, const std::vector<int> &which)
 {
-    MPMC_HIP(mpmc::launch_count_overlaps(h->t, h->pos[h->cur], h->start[h->cur], h->st));
+    MPMC_HIP(mpmc::launch_count_overlaps(h->t, h->pos[h->cur], h->count[h->cur], h->st));
     mpmc_status s = read_ctl(h);
     if (s) return s;
     for (int r : which)
@@ -457,32 +513,24 @@ mpmc_status check_loaded(mpmc_system *h, const std::vector<int> &which)
     return MPMC_OK;
 }
 
-// Load replica r's state into the current half.  The padded tail of its
-// offsets and the next replica's first offset are unchanged because N_r is.
+// Load replica r's state into the current half (its cells and slots only).
 mpmc_status upload_replica(mpmc_system *h, int r, const float *xy, const uint32_t *start,
                            uint64_t sweep, const uint32_t *tags)
 {
     const Rep &R = h->L.reps[(size_t)r];
-    const long long N = R.g.N;
+    const int S = h->t.cap;
+    const size_t slots = (size_t)R.cpad * (size_t)S, s0 = (size_t)R.cb * (size_t)S;
     h->loaded[(size_t)r] = 0;
     h->ready = false;
-    std::vector<uint32_t> off((size_t)R.cpad);
-    global_offsets(R, start, off.data());
+    SlotState o;
+    to_slots(R, S, xy, start, tags, o);
     const int c = h->cur;
-    if (N > 0)
-        MPMC_HIP(hipMemcpyAsync(h->pos[c] + R.pb, xy, sizeof(float2) * (size_t)N, hipMemcpyHostToDevice, h->st));
-    MPMC_HIP(hipMemcpyAsync(h->start[c] + R.cb, off.data(), sizeof(uint32_t) * (size_t)R.cpad,
+    MPMC_HIP(hipMemcpyAsync(h->pos[c] + s0, o.xy.data(), sizeof(float2) * slots, hipMemcpyHostToDevice, h->st));
+    MPMC_HIP(hipMemcpyAsync(h->count[c] + R.cb, o.count.data(), sizeof(uint32_t) * (size_t)R.cpad,
                             hipMemcpyHostToDevice, h->st));
-    std::vector<uint32_t> idx;
-    if (h->tag[c] && N > 0) {
-        if (!tags) {
-            idx.resize((size_t)N);
-            for (long long k = 0; k < N; ++k) idx[(size_t)k] = (uint32_t)k;
-            tags = idx.data();
-        }
-        MPMC_HIP(hipMemcpyAsync(h->tag[c] + R.pb, tags, sizeof(uint32_t) * (size_t)N, hipMemcpyHostToDevice, h->st));
-    }
-    if (h->acc[c]) MPMC_HIP(mpmc::launch_fill_u32((uint32_t *)(h->acc[c] + R.pb), 0u, 2 * N, h->st));
+    if (h->tag[c])
+        MPMC_HIP(hipMemcpyAsync(h->tag[c] + s0, o.tag.data(), sizeof(uint32_t) * slots, hipMemcpyHostToDevice, h->st));
+    if (h->acc[c]) MPMC_HIP(mpmc::launch_fill_u32((uint32_t *)(h->acc[c] + s0), 0u, 2 * (long long)slots, h->st));
     // counters of the other replicas are kept: fold them before the reset
     MPMC_HIP(mpmc::launch_fold_counters(h->t, h->work, h->st));
     MPMC_HIP(mpmc::launch_ctl_reset(h->t, r, sweep, h->st));
@@ -503,7 +551,7 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
     if (s) return s;
     const uint32_t flags = p[0].flags;
     for (int i = 0; i < 2; ++i) {
-        if (!b->pos[i] || !b->start[i]) return fail(MPMC_EINVAL, "pos/start buffers missing");
+        if (!b->pos[i] || !b->count[i]) return fail(MPMC_EINVAL, "pos/count buffers missing");
         if ((flags & MPMC_FLAG_ACC) && !b->acc[i]) return fail(MPMC_EINVAL, "acc buffers missing");
         if ((flags & MPMC_FLAG_TAG) && !b->tag[i]) return fail(MPMC_EINVAL, "tag buffers missing");
     }
@@ -511,30 +559,29 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
     if ((flags & MPMC_FLAG_ACCEPT_LOG) && !b->accept_log)
         return fail(MPMC_EINVAL, "accept_log buffer missing");
     // host-side states first, so that geometry errors allocate nothing
-    std::vector<uint32_t> start_g((size_t)L.cells + 1);
-    std::vector<float> xy_g(2 * (size_t)std::max(L.N, 1LL), 0.0f);
-    std::vector<uint32_t> tag_g((size_t)std::max(L.N, 1LL), 0);
+    const int S = L.cap;
+    std::vector<uint32_t> count_g((size_t)L.cells, 0u);
+    std::vector<float> xy_g((size_t)L.cells * (size_t)S * 2, 0.0f);
+    std::vector<uint32_t> tag_g((size_t)L.cells * (size_t)S, 0u);
     std::vector<int> lattice;
     for (int r = 0; r < n; ++r) {
         const Rep &R = L.reps[(size_t)r];
-        std::vector<float> xy;
-        std::vector<uint32_t> st, tg;
         if (p[r].lattice_nx > 0) {
+            std::vector<float> xy;
+            std::vector<uint32_t> st, tg;
             s = build_lattice(p[r], R, xy, st, tg);
             if (s) return s;
-            std::copy(xy.begin(), xy.end(), xy_g.begin() + 2 * R.pb);
-            std::copy(tg.begin(), tg.end(), tag_g.begin() + R.pb);
+            SlotState o;
+            to_slots(R, S, xy.data(), st.data(), tg.data(), o);
+            std::copy(o.count.begin(), o.count.end(), count_g.begin() + R.cb);
+            std::copy(o.xy.begin(), o.xy.end(), xy_g.begin() + 2 * (size_t)R.cb * S);
+            std::copy(o.tag.begin(), o.tag.end(), tag_g.begin() + (size_t)R.cb * S);
             lattice.push_back(r);
-        } else {
-            // placeholder until set_state: every real cell empty; the
-            // replica's disks (zeros) sit in its first padding cell, which no
-            // kernel reads, so every offset stays inside the position buffer
-            st.assign((size_t)R.g.C + 1, 0);
-            if (R.g.N == 0) lattice.push_back(r);   // empty grid: already valid
+        } else if (R.g.N == 0) {
+            lattice.push_back(r);   // empty grid: already valid
         }
-        global_offsets(R, st.data(), start_g.data() + R.cb);
+        // (other replicas: every cell empty until set_state)
     }
-    start_g[(size_t)L.cells] = (uint32_t)L.N;
 
     mpmc_system *h = new mpmc_system();
     h->p.assign(p, p + n);
@@ -542,14 +589,12 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
     h->st = (hipStream_t)stream;
     for (int i = 0; i < 2; ++i) {
         h->pos[i] = (float2 *)b->pos[i];
-        h->start[i] = (uint32_t *)b->start[i];
+        h->count[i] = (uint32_t *)b->count[i];
         h->acc[i] = (flags & MPMC_FLAG_ACC) ? (float2 *)b->acc[i] : nullptr;
         h->tag[i] = (flags & MPMC_FLAG_TAG) ? (uint32_t *)b->tag[i] : nullptr;
     }
     {
         char *w = (char *)b->work;
-        h->work.scan = (uint32_t *)w;
-        w += align256((size_t)mpmc::scan_entries(L.cells) * 4);
         h->work.cnt = (unsigned long long *)w;
         h->work.cnt_stride = (int)mpmc::count_stride(L.active);
         w += align256((size_t)mpmc::count_stride(L.active) * 2 * 8);
@@ -603,10 +648,14 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
     hipError_t e = up(cb + cl.reps, L.reps.data(), sizeof(Rep) * (size_t)n);
     if (e == hipSuccess) e = up(cb + cl.arep, arep.data(), arep.size() * 2);
     if (e == hipSuccess) e = up(cb + cl.crep, crep.data(), crep.size() * 2);
-    if (e == hipSuccess) e = up(h->pos[0], xy_g.data(), sizeof(float2) * (size_t)L.N);
-    if (e == hipSuccess) e = up(h->start[0], start_g.data(), sizeof(uint32_t) * start_g.size());
-    if (e == hipSuccess && h->tag[0]) e = up(h->tag[0], tag_g.data(), sizeof(uint32_t) * (size_t)L.N);
-    if (e == hipSuccess && h->acc[0]) e = mpmc::launch_fill_u32((uint32_t *)h->acc[0], 0u, 2 * L.N, h->st);
+    const long long slots = L.cells * (long long)S;
+    if (e == hipSuccess) e = up(h->pos[0], xy_g.data(), sizeof(float2) * (size_t)slots);
+    if (e == hipSuccess) e = up(h->count[0], count_g.data(), sizeof(uint32_t) * count_g.size());
+    // the other half: counts of padding cells are read by nothing but kept 0
+    if (e == hipSuccess) e = mpmc::launch_fill_u32(h->count[1], 0u, L.cells, h->st);
+    if (e == hipSuccess && h->tag[0]) e = up(h->tag[0], tag_g.data(), sizeof(uint32_t) * (size_t)slots);
+    if (e == hipSuccess && h->acc[0]) e = mpmc::launch_fill_u32((uint32_t *)h->acc[0], 0u, 2 * slots, h->st);
+
     if (e == hipSuccess)
         e = mpmc::launch_fill_u32((uint32_t *)h->work.cnt, 0u, 4LL * h->work.cnt_stride, h->st);
     if (e == hipSuccess && h->alog) e = mpmc::launch_fill_u32(h->alog, 0u, L.cells, h->st);
@@ -749,7 +798,7 @@ mpmc_status mpmc_pair_histogram(mpmc_handle h, int32_t reset)
         if (R.g.mx < 2 * Rx + 2 || R.g.my < 2 * Ry + 2)
             return fail(MPMC_EGEOM, "grid too small for the histogram's reach");
     }
-    MPMC_HIP(mpmc::launch_pair_histogram(h->t, h->pos[h->cur], h->start[h->cur], reset, h->st));
+    MPMC_HIP(mpmc::launch_pair_histogram(h->t, h->pos[h->cur], h->count[h->cur], reset, h->st));
     return MPMC_OK;
 }
 
@@ -789,17 +838,15 @@ mpmc_status mpmc_replica_get_state(mpmc_handle h, int32_t r, float *xy, uint32_t
 {
     MPMC_NEED_LOADED(h, r);
     const Rep &R = h->L.reps[(size_t)r];
-    if (xy && R.g.N > 0)
-        MPMC_HIP(hipMemcpyAsync(xy, h->pos[h->cur] + R.pb, sizeof(float2) * (size_t)R.g.N,
-                                hipMemcpyDeviceToHost, h->st));
-    if (start)
-        MPMC_HIP(hipMemcpyAsync(start, h->start[h->cur] + R.cb, sizeof(uint32_t) * ((size_t)R.g.C + 1),
-                                hipMemcpyDeviceToHost, h->st));
-    const mpmc_status s = read_ctl(h);
+    std::vector<uint32_t> cnt;
+    std::vector<float2> slots;
+    mpmc_status s = read_slots(h, R, h->pos[h->cur], xy ? &slots : nullptr, cnt);
     if (s) return s;
-    if (start)
-        for (int c = 0; c <= R.g.C; ++c) start[c] -= (uint32_t)R.pb;
-    if (sweep) *sweep = h->ctl_host[(size_t)r].sweep;
+    s = read_ctl(h);
+    if (s) return s;
+    s = compact_lists(R, h->t.cap, cnt, xy ? slots.data() : nullptr, (float2 *)xy, start);
+    if (s) return s;
+    if (sweep) *sweep = h->ctl_host[(size_t)r].sweep_at[h->cur];
     return MPMC_OK;
 }
 
@@ -831,19 +878,30 @@ mpmc_status mpmc_replica_get_aux(mpmc_handle h, int32_t r, float *acc, uint32_t 
 {
     MPMC_NEED_LOADED(h, r);
     const Rep &R = h->L.reps[(size_t)r];
-    if (acc) {
-        if (!h->acc[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_ACC");
-        if (R.g.N > 0)
-            MPMC_HIP(hipMemcpyAsync(acc, h->acc[h->cur] + R.pb, sizeof(float2) * (size_t)R.g.N,
-                                    hipMemcpyDeviceToHost, h->st));
-    }
+    if (acc && !h->acc[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_ACC");
+    if (tags && !h->tag[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_TAG");
+    std::vector<uint32_t> cnt;
+    std::vector<float2> as;
+    mpmc_status s = read_slots(h, R, acc ? h->acc[h->cur] : nullptr, acc ? &as : nullptr, cnt);
+    if (s) return s;
+    std::vector<uint32_t> ts;
     if (tags) {
-        if (!h->tag[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_TAG");
-        if (R.g.N > 0)
-            MPMC_HIP(hipMemcpyAsync(tags, h->tag[h->cur] + R.pb, sizeof(uint32_t) * (size_t)R.g.N,
-                                    hipMemcpyDeviceToHost, h->st));
+        const size_t S = (size_t)h->t.cap, n = (size_t)R.g.C * S;
+        ts.resize(std::max<size_t>(n, 1));
+        if (n) MPMC_HIP(hipMemcpyAsync(ts.data(), h->tag[h->cur] + (size_t)R.cb * S, sizeof(uint32_t) * n,
+                                       hipMemcpyDeviceToHost, h->st));
     }
-    return read_ctl(h);
+    s = read_ctl(h);
+    if (s) return s;
+    s = compact_lists(R, h->t.cap, cnt, acc ? as.data() : nullptr, (float2 *)acc, nullptr);
+    if (s) return s;
+    if (tags) {
+        const int S = h->t.cap;
+        size_t k = 0;
+        for (int c = 0; c < R.g.C; ++c)
+            for (uint32_t i = 0; i < cnt[(size_t)c]; ++i) tags[k++] = ts[(size_t)c * S + i];
+    }
+    return MPMC_OK;
 }
 
 mpmc_status mpmc_get_aux(mpmc_handle h, float *acc, uint32_t *tags)
@@ -873,7 +931,8 @@ mpmc_status mpmc_reset_acc(mpmc_handle h)
 {
     MPMC_NEED_STATE(h);
     if (!h->acc[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_ACC");
-    MPMC_HIP(mpmc::launch_fill_u32((uint32_t *)h->acc[h->cur], 0u, 2 * h->L.N, h->st));
+    MPMC_HIP(mpmc::launch_fill_u32((uint32_t *)h->acc[h->cur], 0u, 2 * h->L.cells * (long long)h->t.cap,
+                                   h->st));
     return MPMC_OK;
 }
 
@@ -883,7 +942,7 @@ mpmc_status mpmc_replica_msd(mpmc_handle h, int32_t r, double *msd)
     if (!msd) return fail(MPMC_EINVAL, "null argument");
     if (!h->acc[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_ACC");
     const Rep &R = h->L.reps[(size_t)r];
-    MPMC_HIP(mpmc::launch_msd(h->acc[h->cur] + R.pb, R.g.N, h->t.ctls + r, h->work, h->st));
+    MPMC_HIP(mpmc::launch_msd(h->t, r, R.g.N, h->acc[h->cur], h->count[h->cur], h->work, h->st));
     const mpmc_status s = read_ctl(h);
     if (s) return s;
     *msd = h->ctl_host[(size_t)r].msd;
@@ -900,7 +959,7 @@ mpmc_status mpmc_count_overlaps(mpmc_handle h, int64_t *pairs)
 {
     MPMC_NEED_STATE(h);
     if (!pairs) return fail(MPMC_EINVAL, "null argument");
-    MPMC_HIP(mpmc::launch_count_overlaps(h->t, h->pos[h->cur], h->start[h->cur], h->st));
+    MPMC_HIP(mpmc::launch_count_overlaps(h->t, h->pos[h->cur], h->count[h->cur], h->st));
     const mpmc_status s = read_ctl(h);
     if (s) return s;
     int64_t total = 0;
@@ -1079,7 +1138,7 @@ mpmc_status mpmc_batch_stats(mpmc_handle h, uint64_t *trials, uint64_t *accepts,
     MPMC_NEED_STATE(h);
     if (msd) {
         if (!h->acc[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_ACC");
-        MPMC_HIP(mpmc::launch_msd_all(h->t, h->acc[h->cur], h->st));
+        MPMC_HIP(mpmc::launch_msd_all(h->t, h->acc[h->cur], h->count[h->cur], h->st));
     }
     const mpmc_status s = read_ctl(h);
     if (s) return s;

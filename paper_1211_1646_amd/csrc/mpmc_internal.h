@@ -30,7 +30,11 @@ constexpr int kAblateSetShuffle = 2;      // Rep::ablate: sets always a, b, c, d
 // Per-replica control block: everything a captured sweep graph reads or
 // writes that changes between launches lives here, not in kernel arguments.
 struct alignas(256) Ctl {
-    unsigned long long sweep;        // current sweep index s
+    // Current sweep index s, by buffer parity: a launch that reads ping-pong
+    // half p reads sweep_at[p] and draw_at[p]; the rebin, which reads half p
+    // and writes half p ^ 1, writes slot p ^ 1 (s + 1 and its draws, or a
+    // copy for an explicit shift), so no launch writes what it reads.
+    unsigned long long sweep_at[2];
     unsigned long long trials;       // trial moves since init / set_state (folded)
     unsigned long long accepts;      // accepted moves (folded)
     unsigned long long win_trials;   // counters at the start of the tuner window
@@ -38,19 +42,14 @@ struct alignas(256) Ctl {
     unsigned int key0, key1;         // Philox key (seed, replica)
     float delta;                     // maximum trial displacement
     unsigned int errword;            // kErr* bits set by kernels
-    int shift_f;                     // the running sweep's shift, recorded by the
-    float shift_d;                   //   rebin's count kernel for its scatter
-    // Sweep-global draws of the current sweep: set order (byte q = set of
-    // slot q), shift direction f and distance d.  Read by every launch of the
-    // sweep; rewritten when the key changes and by the rebin's scatter kernel
-    // when it advances the sweep, after the count kernel (the last reader of
-    // the old draws) has finished.
+    // Sweep-global draws of sweep_at[p]: set order (byte q = set of slot q),
+    // shift direction f and distance d.  Rewritten when the key changes.
     struct Draw {
         unsigned int order;
         int f;
         float d;
         unsigned int pad;
-    } draw;
+    } draw_at[2];
     unsigned long long hist_samples; // configurations in hist[]
     double fit[4];                   // P*, g(sigma+), rho, status
     long long overlaps;              // ordered overlapping pairs (count kernel)
@@ -96,19 +95,17 @@ struct Tables {
     long long N;            // disks, all replicas
 };
 
-// Scratch (caller's work buffer): u32 per-tile totals of the rebin, u64
-// trial/accept partials per granule of active slots (accumulated by every
-// sub-sweep, folded into the control blocks on demand), FP64 partials, and
-// per active slot the reachable neighbours beyond the first kNbrLds.
+// Scratch (caller's work buffer): u64 trial/accept partials per granule of
+// active slots (accumulated by every sub-sweep, folded into the control
+// blocks on demand), FP64 partials, and per active slot the reachable
+// neighbours beyond the first kNbrLds.
 struct Work {
-    uint32_t *scan;              // cells / kRebinTile entries
     unsigned long long *cnt;     // [2][cnt_stride]
     double *f64;                 // kMsdBlocksMax entries
     float2 *ovf;                 // [active][ovf_per_slot(cap)]
     int cnt_stride;
 };
 
-inline long long scan_entries(long long cells) { return cells / kRebinTile + 8; }
 inline long long count_stride(long long active) { return active / kGranule + 8; }
 inline int ovf_per_slot(int cap) { return 8 * cap > kNbrLds ? 8 * cap - kNbrLds : 0; }
 
@@ -118,25 +115,27 @@ inline int ovf_per_slot(int cap) { return 8 * cap > kNbrLds ? 8 * cap - kNbrLds 
 // lanes (1, 2 or 4) lanes work on each active cell; the workgroup size is
 // 64, 128, 192 or 256 lanes (reduced if the LDS rows would not fit).
 // alog (may be null): per-cell accept bits of this launch's active cells.
-hipError_t launch_subsweep(const Tables &t, float2 *pos, const uint32_t *start, float2 *acc,
-                           uint32_t *tag, uint32_t *alog, const Work &w, int set, int block,
-                           int lanes, hipStream_t st);
+// par: the ping-pong half being read (selects the sweep slot).
+hipError_t launch_subsweep(const Tables &t, int par, float2 *pos, const uint32_t *count,
+                           float2 *acc, uint32_t *tag, uint32_t *alog, const Work &w, int set,
+                           int block, int lanes, hipStream_t st);
 // Add the counter partials into each replica's control block; clear them.
 hipError_t launch_fold_counters(const Tables &t, const Work &w, hipStream_t st);
 // Shift (f, d) -- or each replica's own draws when f < 0 -- and rebuild the
-// cell lists into the *_out buffers; advance moves every replica on to its
-// next sweep (only with f < 0).
-hipError_t launch_rebin(const Tables &t, const float2 *pos, const uint32_t *start,
+// cell lists into the *_out buffers (half par ^ 1); advance moves every
+// replica on to its next sweep (only with f < 0).
+hipError_t launch_rebin(const Tables &t, int par, const float2 *pos, const uint32_t *count,
                         const float2 *acc, const uint32_t *tag, float2 *pos_out,
-                        uint32_t *start_out, float2 *acc_out, uint32_t *tag_out,
+                        uint32_t *count_out, float2 *acc_out, uint32_t *tag_out,
                         const Work &w, int f, float d, int advance, hipStream_t st);
-hipError_t launch_pair_histogram(const Tables &t, const float2 *pos, const uint32_t *start,
+hipError_t launch_pair_histogram(const Tables &t, const float2 *pos, const uint32_t *count,
                                  int reset, hipStream_t st);
 hipError_t launch_pressure_fit(const Tables &t, int replica, hipStream_t st);
-hipError_t launch_count_overlaps(const Tables &t, const float2 *pos, const uint32_t *start,
+hipError_t launch_count_overlaps(const Tables &t, const float2 *pos, const uint32_t *count,
                                  hipStream_t st);
-// Mean |acc|^2 over n accumulators (one replica's range) into ctl->msd.
-hipError_t launch_msd(const float2 *acc, long long n, Ctl *ctl, const Work &w, hipStream_t st);
+// Mean |acc|^2 over the N disks of one replica into its control block.
+hipError_t launch_msd(const Tables &t, int replica, long long N, const float2 *acc,
+                      const uint32_t *count, const Work &w, hipStream_t st);
 // apply == 0 only opens a new tuner window (records the counters); call after
 // launch_fold_counters.
 hipError_t launch_tune(const Tables &t, int apply, hipStream_t st);
@@ -150,7 +149,7 @@ hipError_t launch_ctl_set_delta(const Tables &t, int replica, float delta, hipSt
 // Workgroup size the sub-sweep actually uses for a requested one.
 int subsweep_block(int cap, int block, int lanes);
 // Mean |acc|^2 of every replica into its control block (one workgroup each).
-hipError_t launch_msd_all(const Tables &t, const float2 *acc, hipStream_t st);
+hipError_t launch_msd_all(const Tables &t, const float2 *acc, const uint32_t *count, hipStream_t st);
 
 // ---- move-size network (defined in mpmc_mlp.hip) ----
 size_t mlp_work_bytes(int n);

@@ -4,14 +4,17 @@
 // simulations on GPUs" -- Alg. 1 (sweep), Alg. 2 (sub-sweep), Alg. 4 (cell
 // shift), Sec. 4 (contact-value pressure, Eqs. gR, R, P).
 //
-// Data layout in device memory (compressed rows, struct-of-arrays):
-//   pos[N]     float2 cell-local coordinates in (0, w], cells in row-major
-//              order, each cell's particles contiguous;
-//   start[C+1] uint32 offsets, start[C] = N;
-//   acc[N]     float2 displacement accumulators (optional), tag[N] (optional).
-// A sub-sweep writes only the active cells' own ranges and reads the eight
-// inactive neighbours, so it updates in place; the rebin writes the other
-// ping-pong half.
+// Data layout in device memory (the paper's disk[x, y, i], Sec. 3.1):
+//   count[C]      uint32 disks per cell, cells in row-major order;
+//   pos[C][CAP]   float2 cell-local coordinates in (0, w], slots [0, count)
+//                 used, CAP = the largest capacity of the handle's replicas;
+//   acc[C][CAP]   float2 displacement accumulators (optional), tag[C][CAP]
+//                 (optional), in the same slots.
+// Fixed slots let a kernel load a cell's count and its disks together, in
+// one memory round trip, and let the rebin write each new cell without a
+// scan.  A sub-sweep writes only the active cells' own slots and reads the
+// eight inactive neighbours, so it updates in place; the rebin writes the
+// other ping-pong half.
 //
 // Every floating-point expression is written so that each operation rounds
 // once (no contraction); the library is built with -ffp-contract=off and the
@@ -155,12 +158,14 @@ __device__ __forceinline__ Draws sweep_draws(unsigned long long s, uint32_t k0, 
     return D;
 }
 
-// Record the draws of sweep s in the control block (one thread).
-__device__ __forceinline__ void store_draws(Ctl *ctl, unsigned long long s, const Rep &R)
+// Record sweep s and its draws in sweep slot p of the control block (one
+// thread).
+__device__ __forceinline__ void store_draws(Ctl *ctl, int p, unsigned long long s, const Rep &R)
 {
     const Draws D = sweep_draws(s, ctl->key0, ctl->key1, R.g.wx, R.g.wy,
                                 (R.ablate & kAblateSetShuffle) == 0);
-    Ctl::Draw &r = ctl->draw;
+    ctl->sweep_at[p] = s;
+    Ctl::Draw &r = ctl->draw_at[p];
     r.order = D.order;
     r.f = D.f;
     r.d = D.d;
@@ -286,11 +291,12 @@ __device__ __forceinline__ unsigned block_exclusive_scan_u32(unsigned v, unsigne
 }
 
 // ------------------------------------------------------------ sub-sweep
-// One lane per active cell of set Q (Alg. 2).  The kernel is organised to
-// expose memory-level parallelism rather than to chase pointers:
-//   1. all 18 offsets of the 3x3 block are loaded at once;
-//   2. every position of the block is loaded at once (unconditionally, at
-//      indices clamped into [0, N)); the Philox blocks of the cell are
+// One lane per active cell of set Q (Alg. 2).  Disks live in fixed slots,
+// CAP per cell (the paper's disk[x, y, i], Sec. 3.1), so the kernel exposes
+// memory-level parallelism rather than chasing pointers:
+//   1-2. the nine counts of the 3x3 block and all its 9 CAP slots are loaded
+//      at once, in one memory round trip (slots past a count hold stale
+//      values and are masked afterwards); the Philox blocks of the cell are
 //      computed while the loads fly;
 //   3. neighbour disks are translated into the cell's frame (exactly -w, 0
 //      or +w, Sec. 3.1) and those that can reach the cell at all -- closer
@@ -343,7 +349,7 @@ __device__ __forceinline__ float min_r2(float xm, float ym, const float2 *e)
 
 template <int CAP, int PROP>
 __global__ void __launch_bounds__(256)
-k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
+k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restrict__ count,
            float2 *__restrict__ acc, uint32_t *__restrict__ tag, uint32_t *__restrict__ alog,
            unsigned long long *__restrict__ cnt, int cnt_stride, float2 *__restrict__ ovf_all,
            int set, int ntile, int per)
@@ -362,7 +368,7 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
     const Rep R = rep_of(t, r);
     const Geom g = R.g;
     Ctl *ctl = t.ctls + r;
-    const unsigned long long s = ctl->sweep;
+    const unsigned long long s = ctl->sweep_at[par];
     const uint32_t k0 = ctl->key0, k1 = ctl->key1;
     const float delta = ctl->delta;
     const int n_moves = R.n_moves;
@@ -373,13 +379,14 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
     const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
 
     int Q = set;
-    if (Q < 0) Q = (int)((ctl->draw.order >> (8 * (-1 - set))) & 0xFFu);
+    if (Q < 0) Q = (int)((ctl->draw_at[par].order >> (8 * (-1 - set))) & 0xFFu);
     const int qx = Q & 1, qy = Q >> 1;
     const int hx = g.mx >> 1, hy = g.my >> 1;
     const long long gid = slot0 + (long long)threadIdx.x - R.ab;   // within the replica
     float2 *const nbr = lds + threadIdx.x * kRow;   // this lane's neighbour list
     float2 *const ovf = ovf_all + (size_t)(slot0 + (long long)threadIdx.x) * kO;
-    const uint32_t *const st = start + R.cb;        // this replica's offsets
+    const uint32_t *const cn = count + R.cb;        // this replica's cell counts
+    const size_t sb = (size_t)R.cb * CAP;           // and its first slot
 
     unsigned n_trials = 0, n_acc = 0;
     uint32_t abits = 0;
@@ -393,39 +400,36 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
         const int xr = cx == g.mx - 1 ? 0 : cx + 1;
         const int yd = cy == 0 ? g.my - 1 : cy - 1;
         const int yu = cy == g.my - 1 ? 0 : cy + 1;
-        // 1. offsets of the nine cells q = 3*row + col, row/col 0,1,2 = -1,0,+1
-        uint32_t rb[9], rn[9];
+        // 1-2. counts and slots of the nine cells q = 3*row + col (row/col
+        // 0, 1, 2 = -1, 0, +1), all in flight together
+        uint32_t rn[9];
+        float2 nv[9][CAP];
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             const int row = q / 3 == 0 ? yd : (q / 3 == 1 ? cy : yu);
             const int col = q % 3 == 0 ? xl : (q % 3 == 1 ? cx : xr);
             const int cc = row * g.mx + col;
-            rb[q] = st[cc];
-            rn[q] = st[cc + 1];
+            rn[q] = cn[cc];
+#pragma unroll
+            for (int i = 0; i < CAP; ++i) nv[q][i] = pos[sb + (size_t)cc * CAP + (size_t)i];
         }
+        // the cell's first shuffle block and first trial block, computed
+        // while the loads are outstanding
+        uint4 Wsh = make_uint4(0, 0, 0, 0);
+        if (shuffle) Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle, k0, k1);
+        uint4 W = make_uint4(0, 0, 0, 0);
+        if (n_moves > 0) W = philox((uint32_t)c, s_lo, s_hi, 0u, k0, k1);
         bool bad = false;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            rn[q] -= rb[q];
-            bad |= rn[q] > (uint32_t)g.cap;
-        }
+        for (int q = 0; q < 9; ++q) bad |= rn[q] > (uint32_t)g.cap;
         int n = (int)rn[4];
-        bad |= (unsigned long long)rb[4] + rn[4] > (unsigned long long)t.N;   // never write past N
         if (bad) {
             atomicOr((unsigned int *)&ctl->errword, kErrCapacity);
             n = 0;
         }
         if (n > 0) {
-            const uint32_t b0 = rb[4];
+            const size_t b0 = sb + (size_t)c * CAP;   // own slots
             const bool has_acc = acc != nullptr, has_tag = tag != nullptr;
-            // 2. all positions of the block in flight together: unconditional
-            // loads at indices clamped into [0, N), selected afterwards
-            const uint32_t last = (uint32_t)(t.N - 1);
-            float2 nv[9][CAP];
-#pragma unroll
-            for (int q = 0; q < 9; ++q)
-#pragma unroll
-                for (int i = 0; i < CAP; ++i) nv[q][i] = pos[min(rb[q] + (uint32_t)i, last)];
             float px[CAP], py[CAP], ax[CAP], ay[CAP];
             uint32_t tg[CAP];
 #pragma unroll
@@ -438,21 +442,15 @@ k_subsweep(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ star
             if (has_acc) {
 #pragma unroll
                 for (int q = 0; q < CAP; ++q) {
-                    const float2 a = acc[min(b0 + (uint32_t)q, last)];
+                    const float2 a = acc[b0 + (size_t)q];
                     ax[q] = a.x;
                     ay[q] = a.y;
                 }
             }
             if (has_tag) {
 #pragma unroll
-                for (int q = 0; q < CAP; ++q) tg[q] = tag[min(b0 + (uint32_t)q, last)];
+                for (int q = 0; q < CAP; ++q) tg[q] = tag[b0 + (size_t)q];
             }
-            // Philox blocks of this cell: one shuffle block (n <= 5) and the
-            // first trial block, issued while the loads are outstanding.
-            uint4 Wsh = make_uint4(0, 0, 0, 0);
-            if (n > 1 && shuffle) Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle, k0, k1);
-            uint4 W = make_uint4(0, 0, 0, 0);
-            if (n_moves > 0) W = philox((uint32_t)c, s_lo, s_hi, 0u, k0, k1);
             // 3. translate into the cell's frame, keep the disks that can
             // reach the cell, compact them into the lane's LDS row.  The
             // common path has no branch: an index past kL lands on the row's
@@ -648,7 +646,7 @@ __device__ __forceinline__ bool group_any(bool v)
 // hide latency.
 template <int CAP, int LPC, int PROP>
 __global__ void __launch_bounds__(256)
-k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ start,
+k_subsweep_mc(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restrict__ count,
               float2 *__restrict__ acc, uint32_t *__restrict__ tag, uint32_t *__restrict__ alog,
               unsigned long long *__restrict__ cnt, int cnt_stride, float2 *__restrict__ ovf_all,
               int set, int ntile, int per)
@@ -666,7 +664,7 @@ k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ s
     const Rep R = rep_of(t, r);
     const Geom g = R.g;
     Ctl *ctl = t.ctls + r;
-    const unsigned long long s = ctl->sweep;
+    const unsigned long long s = ctl->sweep_at[par];
     const uint32_t k0 = ctl->key0, k1 = ctl->key1;
     const float delta = ctl->delta;
     const int n_moves = R.n_moves;
@@ -677,14 +675,15 @@ k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ s
     const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
 
     int Q = set;
-    if (Q < 0) Q = (int)((ctl->draw.order >> (8 * (-1 - set))) & 0xFFu);
+    if (Q < 0) Q = (int)((ctl->draw_at[par].order >> (8 * (-1 - set))) & 0xFFu);
     const int qx = Q & 1, qy = Q >> 1;
     const int hx = g.mx >> 1, hy = g.my >> 1;
     const int h = (int)(threadIdx.x % LPC);
     const long long gid = slot0 + (long long)(threadIdx.x / LPC) - R.ab;   // cell within the replica
     float2 *const nbr = lds + threadIdx.x * kRow;
     float2 *const ovf = ovf_all + (size_t)(lane0 + (long long)threadIdx.x) * kO;
-    const uint32_t *const st = start + R.cb;
+    const uint32_t *const cn = count + R.cb;        // this replica's cell counts
+    const size_t sb = (size_t)R.cb * CAP;           // and its first slot
 
     unsigned n_trials = 0, n_acc = 0;
     uint32_t abits = 0;
@@ -699,11 +698,20 @@ k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ s
         const int yd = cy == 0 ? g.my - 1 : cy - 1;
         const int yu = cy == g.my - 1 ? 0 : cy + 1;
         // own cell and this lane's neighbour cells: q = 3 row + col over
-        // {0, 1, 2, 3, 5, 6, 7, 8}, lane h taking entries h NB .. h NB + NB - 1
-        const uint32_t b0 = st[c];
-        int n = (int)(st[c + 1] - b0);
-        uint32_t rb[NB], rn[NB];
+        // {0, 1, 2, 3, 5, 6, 7, 8}, lane h taking entries h NB .. h NB + NB - 1;
+        // counts and slots all in flight together
+        const size_t b0 = sb + (size_t)c * CAP;   // own slots
+        int n = (int)cn[c];
+        float px[CAP], py[CAP];
+#pragma unroll
+        for (int i = 0; i < CAP; ++i) {
+            const float2 v = pos[b0 + (size_t)i];
+            px[i] = v.x;
+            py[i] = v.y;
+        }
+        uint32_t rn[NB];
         int qa[NB];
+        float2 nv[NB][CAP];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             const int e = h * NB + j;
@@ -713,11 +721,18 @@ k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ s
             const int row = ra == 0 ? yd : (ra == 1 ? cy : yu);
             const int col = cb == 0 ? xl : (cb == 1 ? cx : xr);
             const int cc = row * g.mx + col;
-            rb[j] = st[cc];
-            rn[j] = st[cc + 1] - rb[j];
+            rn[j] = cn[cc];
+#pragma unroll
+            for (int i = 0; i < CAP; ++i) nv[j][i] = pos[sb + (size_t)cc * CAP + (size_t)i];
         }
+        // first trial block on even lanes, first shuffle block on odd lanes,
+        // then swapped within the pair (computed while the loads fly)
+        const uint4 mine = philox((uint32_t)c, s_lo, s_hi, (h & 1) ? kTagShuffle : 0u, k0, k1);
+        const uint4 other = make_uint4(lane_xor1(mine.x), lane_xor1(mine.y), lane_xor1(mine.z),
+                                       lane_xor1(mine.w));
+        uint4 W = (h & 1) ? other : mine;
+        uint4 Wsh = (h & 1) ? mine : other;
         bool bad = n > g.cap;
-        bad |= (unsigned long long)b0 + (uint32_t)n > (unsigned long long)t.N;   // never write past N
 #pragma unroll
         for (int j = 0; j < NB; ++j) bad |= rn[j] > (uint32_t)g.cap;
         bad = group_any<LPC>(bad);
@@ -727,41 +742,25 @@ k_subsweep_mc(Tables t, float2 *__restrict__ pos, const uint32_t *__restrict__ s
         }
         if (n > 0) {
             const bool has_acc = acc != nullptr, has_tag = tag != nullptr;
-            const uint32_t last = (uint32_t)(t.N - 1);
-            float2 nv[NB][CAP];
-            float px[CAP], py[CAP], ax[CAP], ay[CAP];
+            float ax[CAP], ay[CAP];
             uint32_t tg[CAP];
 #pragma unroll
             for (int i = 0; i < CAP; ++i) {
-                const float2 v = pos[min(b0 + (uint32_t)i, last)];
-                px[i] = v.x;
-                py[i] = v.y;
                 ax[i] = ay[i] = 0.0f;
                 tg[i] = 0u;
             }
-#pragma unroll
-            for (int j = 0; j < NB; ++j)
-#pragma unroll
-                for (int i = 0; i < CAP; ++i) nv[j][i] = pos[min(rb[j] + (uint32_t)i, last)];
             if (has_acc) {
 #pragma unroll
                 for (int i = 0; i < CAP; ++i) {
-                    const float2 a = acc[min(b0 + (uint32_t)i, last)];
+                    const float2 a = acc[b0 + (size_t)i];
                     ax[i] = a.x;
                     ay[i] = a.y;
                 }
             }
             if (has_tag) {
 #pragma unroll
-                for (int i = 0; i < CAP; ++i) tg[i] = tag[min(b0 + (uint32_t)i, last)];
+                for (int i = 0; i < CAP; ++i) tg[i] = tag[b0 + (size_t)i];
             }
-            // first trial block on even lanes, first shuffle block on odd
-            // lanes, then swapped within the pair
-            const uint4 mine = philox((uint32_t)c, s_lo, s_hi, (h & 1) ? kTagShuffle : 0u, k0, k1);
-            const uint4 other = make_uint4(lane_xor1(mine.x), lane_xor1(mine.y), lane_xor1(mine.z),
-                                           lane_xor1(mine.w));
-            uint4 W = (h & 1) ? other : mine;
-            uint4 Wsh = (h & 1) ? mine : other;
             // this lane's neighbours in the cell's frame, reachable ones kept
             // (branch-free common path and rare overflow pass, as in k_subsweep)
             int K = 0;
@@ -928,31 +927,26 @@ __global__ void __launch_bounds__(256) k_fold_counters(Tables t, unsigned long l
 }
 
 // ----------------------------------------------------------------- rebin
-// Alg. 4 as a counting sort: new cell c holds the stayers of old c followed
-// by the leavers of the old cell in direction f, both in old list order.
-// Two kernels over tiles of 256 cells, one cell per thread:
-//   count   -- per tile, the number of disks its new cells receive;
-//   scatter -- each tile adds up the totals of its replica's earlier tiles,
-//              recounts (same operations, same result), scans inside the
-//              tile and writes offsets, positions, accumulators and tags.
-// Each disk's decision is one rounded shifted coordinate tested against
-// (0, w].  A thread loads all CAP slots of both cells at once (indices
-// clamped into [0, N), selected by count afterwards), so a cell costs one
-// memory round trip, not one per disk.  The first tile of each replica
-// records the replica's shift (count kernel) and moves the replica to its
-// next sweep with its draws (scatter); no other workgroup reads those
-// fields, so no atomics are needed.
+// Alg. 4 on the slot layout: new cell c holds the stayers of old c followed
+// by the leavers of the old cell in direction f, both in old slot order.
+// One thread per cell, tiles of 256 cells; a thread loads the counts and all
+// CAP slots of both cells at once -- one memory round trip -- and writes its
+// new list straight into the other buffer, so no scan is needed.  Each
+// disk's decision is one rounded shifted coordinate tested against (0, w].
+// The first workgroup of each replica writes the replica's sweep slot of
+// the half it writes: the next sweep and its draws when the shift is the
+// sweep's own, else a copy of the current slot.
 struct RebinArgs {
     Tables t;
     const float2 *pos;
-    const uint32_t *start;
+    const uint32_t *count;
     const float2 *acc;
     const uint32_t *tag;
     float2 *pos_out;
-    uint32_t *start_out;
+    uint32_t *count_out;
     float2 *acc_out;
     uint32_t *tag_out;
-    uint32_t *part;   // per-tile totals
+    int par;          // half read; the other is written
     int f;            // >= 0 explicit shift; < 0 each replica's own
     float d;
     int advance;
@@ -965,40 +959,31 @@ __device__ __forceinline__ float shifted(float v, bool minus, float d)
     return minus ? v - d : v + d;
 }
 
-template <bool SCATTER, int CAP>
+template <int CAP>
 __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
 {
-    __shared__ unsigned red[16];
     const int tile = xcd_tile(a.per);
+    if (tile >= a.ntile) return;
     const long long cell0 = (long long)tile * kRebinTile;
-    const int r = tile_replica(a.t, tile < a.ntile, tile);
+    const int r = tile_replica(a.t, true, tile);
     const Rep R = rep_of(a.t, r);
     const Geom g = R.g;
     Ctl *ctl = a.t.ctls + r;
     int f = a.f;
     float d = a.d;
     if (f < 0) {
-        if (!SCATTER) {
-            f = ctl->draw.f;
-            d = ctl->draw.d;
-        } else {
-            f = ctl->shift_f;
-            d = ctl->shift_d;
-        }
+        f = ctl->draw_at[a.par].f;
+        d = ctl->draw_at[a.par].d;
     }
     const bool along_x = f < 2;
     const bool minus = (f == 0 || f == 2);   // +x / +y: t = v - d
     const float w = along_x ? g.wx : g.wy;
     const float sw = minus ? w : -w;         // translation into the receiving cell
-    const uint32_t *const st = a.start + R.cb;
-    const uint32_t last = (uint32_t)(a.t.N - 1);
 
     const long long cl = cell0 + (long long)threadIdx.x - R.cb;   // cell within the replica
-    // (with no disks at all there is nothing to load: every cell is empty)
-    const bool valid = tile < a.ntile && cl < g.C && a.t.N > 0;
-    uint32_t ob = 0, nbb = 0;
-    int no = 0, nn = 0;
+    const bool valid = cl < g.C;
     unsigned stay = 0, leave = 0;   // bit i: own slot i stays / neighbour slot i leaves
+    size_t ob = 0, nbb = 0;         // first slots of the two cells
     float2 own[CAP], nb[CAP];
     if (valid) {
         const int c = (int)cl;
@@ -1007,21 +992,20 @@ __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
         if (along_x) ncx = minus ? (cx == g.mx - 1 ? 0 : cx + 1) : (cx == 0 ? g.mx - 1 : cx - 1);
         else ncy = minus ? (cy == g.my - 1 ? 0 : cy + 1) : (cy == 0 ? g.my - 1 : cy - 1);
         const int nc = ncy * g.mx + ncx;
-        ob = st[c];
-        const uint32_t oe = st[c + 1];
-        nbb = st[nc];
-        const uint32_t nbe = st[nc + 1];
-        no = (int)(oe - ob);
-        nn = (int)(nbe - nbb);
-        if (no > CAP || nn > CAP) {
-            atomicOr(&ctl->errword, kErrCapacity);
-            no = no > CAP ? CAP : no;
-            nn = nn > CAP ? CAP : nn;
-        }
+        ob = (size_t)(R.cb + c) * CAP;
+        nbb = (size_t)(R.cb + nc) * CAP;
+        int no = (int)a.count[R.cb + c];
+        int nn = (int)a.count[R.cb + nc];
+        // all CAP slots of both cells with the counts, one round trip
 #pragma unroll
         for (int i = 0; i < CAP; ++i) {
-            own[i] = a.pos[min(ob + (uint32_t)i, last)];
-            nb[i] = a.pos[min(nbb + (uint32_t)i, last)];
+            own[i] = a.pos[ob + (size_t)i];
+            nb[i] = a.pos[nbb + (size_t)i];
+        }
+        if (no > g.cap || nn > g.cap) {
+            atomicOr(&ctl->errword, kErrCapacity);
+            no = no > g.cap ? g.cap : no;
+            nn = nn > g.cap ? g.cap : nn;
         }
 #pragma unroll
         for (int i = 0; i < CAP; ++i) {
@@ -1032,77 +1016,45 @@ __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
         }
     }
     const unsigned cnt = (unsigned)(__popc(stay) + __popc(leave));
-    const bool first = tile < a.ntile && cell0 == R.cb;
-    if (!SCATTER) {
-        const unsigned tot = block_sum_u32(cnt, red);
-        if (threadIdx.x == 0 && tile < a.ntile) a.part[tile] = tot;
-        if (first && threadIdx.x == 0 && a.f < 0) {
-            ctl->shift_f = f;
-            ctl->shift_d = d;
-        }
-        return;
-    }
-    // offset of this tile: the replica's first disk plus its earlier tiles.
-    // Sixteen totals per thread are loaded at once (indices clamped to the
-    // last earlier tile, the excess masked), so up to 4096 earlier tiles cost
-    // one memory round trip rather than one per sixteenth of them.
-    unsigned pre = 0;
-    if (tile < a.ntile) {
-        const long long first = R.cb / kRebinTile;
-        for (long long base = first; base < tile; base += 16LL * kRebinTile) {
-            unsigned v[16];
+    if (valid) {
+        const bool has_acc = a.acc != nullptr, has_tag = a.tag != nullptr;
+        if (cnt > (unsigned)g.cap) atomicOr(&ctl->errword, kErrCapacity);
+        a.count_out[cell0 + threadIdx.x] = cnt > (unsigned)g.cap ? (unsigned)g.cap : cnt;
+        // the new list of this cell, in its own CAP slots (never past them)
+        size_t o = ob;
+        const size_t oe = ob + (size_t)g.cap;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const long long i = base + threadIdx.x + (long long)u * kRebinTile;
-                v[u] = a.part[i < tile ? i : tile - 1];
+        for (int i = 0; i < CAP; ++i) {
+            if ((stay & (1u << i)) && o < oe) {
+                const float tt = shifted(along_x ? own[i].x : own[i].y, minus, d);
+                a.pos_out[o] = along_x ? make_float2(tt, own[i].y) : make_float2(own[i].x, tt);
+                if (has_acc) a.acc_out[o] = a.acc[ob + (size_t)i];
+                if (has_tag) a.tag_out[o] = a.tag[ob + (size_t)i];
             }
-#pragma unroll
-            for (int u = 0; u < 16; ++u)
-                pre += (base + threadIdx.x + (long long)u * kRebinTile < tile) ? v[u] : 0u;
+            o += (stay >> i) & 1u;
         }
-    }
-    const unsigned before = block_sum_u32(pre, red);
-    unsigned total;
-    const unsigned off = block_exclusive_scan_u32(cnt, red, &total);
-    if (tile < a.ntile && cl < R.cpad) {
-        uint32_t o = (uint32_t)R.pb + before + off;
-        a.start_out[cell0 + threadIdx.x] = o;
-        if (cell0 + threadIdx.x == a.t.cells - 1) a.start_out[a.t.cells] = o + cnt;
-        if (valid) {
-            if (cl == g.C - 1 && (long long)(o + cnt) != R.pb + g.N) atomicOr(&ctl->errword, kErrCount);
-            if (cnt > (unsigned)g.cap) atomicOr(&ctl->errword, kErrCapacity);
-            const bool has_acc = a.acc != nullptr, has_tag = a.tag != nullptr;
-            // writes stay inside the replica's range whatever the totals say
-            // (a wrong total is reported, never written through)
-            const uint32_t lim = (uint32_t)(R.pb + g.N);
-            if (o + cnt > lim) atomicOr(&ctl->errword, kErrCount);
 #pragma unroll
-            for (int i = 0; i < CAP; ++i) {
-                if ((stay & (1u << i)) && o < lim) {
-                    const float tt = shifted(along_x ? own[i].x : own[i].y, minus, d);
-                    a.pos_out[o] = along_x ? make_float2(tt, own[i].y) : make_float2(own[i].x, tt);
-                    if (has_acc) a.acc_out[o] = a.acc[ob + i];
-                    if (has_tag) a.tag_out[o] = a.tag[ob + i];
-                }
-                o += (stay >> i) & 1u;
+        for (int i = 0; i < CAP; ++i) {
+            if ((leave & (1u << i)) && o < oe) {
+                const float tt = shifted(along_x ? nb[i].x : nb[i].y, minus, d);
+                const float t2 = tt + sw;
+                a.pos_out[o] = along_x ? make_float2(t2, nb[i].y) : make_float2(nb[i].x, t2);
+                if (has_acc) a.acc_out[o] = a.acc[nbb + (size_t)i];
+                if (has_tag) a.tag_out[o] = a.tag[nbb + (size_t)i];
             }
-#pragma unroll
-            for (int i = 0; i < CAP; ++i) {
-                if ((leave & (1u << i)) && o < lim) {
-                    const float tt = shifted(along_x ? nb[i].x : nb[i].y, minus, d);
-                    const float t2 = tt + sw;
-                    a.pos_out[o] = along_x ? make_float2(t2, nb[i].y) : make_float2(nb[i].x, t2);
-                    if (has_acc) a.acc_out[o] = a.acc[nbb + i];
-                    if (has_tag) a.tag_out[o] = a.tag[nbb + i];
-                }
-                o += (leave >> i) & 1u;
-            }
+            o += (leave >> i) & 1u;
         }
+    } else if (cl < R.cpad) {
+        a.count_out[cell0 + threadIdx.x] = 0u;   // padding cells stay empty
     }
-    if (first && threadIdx.x == 0 && a.advance) {
-        const unsigned long long s = ctl->sweep + 1ull;
-        store_draws(ctl, s, R);
-        ctl->sweep = s;
+    if (cell0 == R.cb && threadIdx.x == 0) {
+        const unsigned long long s = ctl->sweep_at[a.par];
+        if (a.advance) {
+            store_draws(ctl, a.par ^ 1, s + 1ull, R);
+        } else {
+            ctl->sweep_at[a.par ^ 1] = s;
+            ctl->draw_at[a.par ^ 1] = ctl->draw_at[a.par];
+        }
     }
 }
 
@@ -1112,7 +1064,7 @@ __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
 // cells, so each workgroup belongs to one replica and adds into its
 // histogram.
 __global__ void __launch_bounds__(kRebinTile)
-k_pair_hist(Tables t, const float2 *__restrict__ pos, const uint32_t *__restrict__ start,
+k_pair_hist(Tables t, const float2 *__restrict__ pos, const uint32_t *__restrict__ count,
             int ntile, int per)
 {
     __shared__ float E[kHistBins + 1];
@@ -1131,15 +1083,16 @@ k_pair_hist(Tables t, const float2 *__restrict__ pos, const uint32_t *__restrict
     const double rmax = 1.0 + kHistBins * 1e-4;
     const int Rx = (double)g.wx >= rmax ? 1 : 2;
     const int Ry = (double)g.wy >= rmax ? 1 : 2;
-    const uint32_t *const st = start + R.cb;
-    const uint32_t nlim = (uint32_t)t.N;   // offsets are trusted only up to N
+    const uint32_t *const cn = count + R.cb;
+    const float2 *const pr = pos + (size_t)R.cb * t.cap;   // slots: t.cap per cell
     const long long cl = cell0 + (long long)threadIdx.x - R.cb;
     if (tile < ntile && cl < g.C) {
         const int c = (int)cl;
         const int cy = c / g.mx, cx = c - cy * g.mx;
         const float e0 = E[0], eN = E[kHistBins];
-        for (uint32_t k = st[c], ke = min(st[c + 1], nlim); k < ke; ++k) {
-            const float2 pk = pos[k];
+        const uint32_t nk = min(cn[c], (uint32_t)g.cap);   // counts trusted only up to capacity
+        for (uint32_t k = 0; k < nk; ++k) {
+            const float2 pk = pr[(size_t)c * t.cap + k];
             for (int oy = -Ry; oy <= Ry; ++oy) {
                 const int ncy = (cy + oy + 2 * g.my) % g.my;
                 const float ty = (float)oy * g.wy;
@@ -1147,9 +1100,9 @@ k_pair_hist(Tables t, const float2 *__restrict__ pos, const uint32_t *__restrict
                     const int ncx = (cx + ox + 2 * g.mx) % g.mx;
                     const float tx = (float)ox * g.wx;
                     const int nc = ncy * g.mx + ncx;
-                    for (uint32_t j = st[nc], je = min(st[nc + 1], nlim); j < je; ++j) {
-                        if (j == k) continue;
-                        const float2 v = pos[j];
+                    for (uint32_t j = 0, je = min(cn[nc], (uint32_t)g.cap); j < je; ++j) {
+                        if (nc == c && j == k) continue;
+                        const float2 v = pr[(size_t)nc * t.cap + j];
                         const float qx = v.x + tx;
                         const float qy = v.y + ty;
                         const float ddx = pk.x - qx;
@@ -1260,7 +1213,7 @@ __global__ void __launch_bounds__(256) k_pressure_fit(Tables t, int replica)
 constexpr float kOverlapR2 = 1.0f - 0x1p-16f;
 
 __global__ void __launch_bounds__(kRebinTile)
-k_count_overlaps(Tables t, const float2 *__restrict__ pos, const uint32_t *__restrict__ start,
+k_count_overlaps(Tables t, const float2 *__restrict__ pos, const uint32_t *__restrict__ count,
                  int ntile, int per)
 {
     __shared__ unsigned red[16];
@@ -1269,15 +1222,16 @@ k_count_overlaps(Tables t, const float2 *__restrict__ pos, const uint32_t *__res
     const int r = tile_replica(t, tile < ntile, tile);
     const Rep R = rep_of(t, r);
     const Geom g = R.g;
-    const uint32_t *const st = start + R.cb;
-    const uint32_t nlim = (uint32_t)t.N;   // offsets are trusted only up to N
+    const uint32_t *const cn = count + R.cb;
+    const float2 *const pr = pos + (size_t)R.cb * t.cap;   // slots: t.cap per cell
     const long long cl = cell0 + (long long)threadIdx.x - R.cb;
     unsigned bad = 0;
     if (tile < ntile && cl < g.C) {
         const int c = (int)cl;
         const int cy = c / g.mx, cx = c - cy * g.mx;
-        for (uint32_t k = st[c], ke = min(st[c + 1], nlim); k < ke; ++k) {
-            const float2 pk = pos[k];
+        const uint32_t nk = min(cn[c], (uint32_t)g.cap);   // counts trusted only up to capacity
+        for (uint32_t k = 0; k < nk; ++k) {
+            const float2 pk = pr[(size_t)c * t.cap + k];
             for (int oy = -1; oy <= 1; ++oy) {
                 const int ncy = (cy + oy + g.my) % g.my;
                 const float ty = oy < 0 ? -g.wy : (oy > 0 ? g.wy : 0.0f);
@@ -1285,9 +1239,9 @@ k_count_overlaps(Tables t, const float2 *__restrict__ pos, const uint32_t *__res
                     const int ncx = (cx + ox + g.mx) % g.mx;
                     const float tx = ox < 0 ? -g.wx : (ox > 0 ? g.wx : 0.0f);
                     const int nc = ncy * g.mx + ncx;
-                    for (uint32_t j = st[nc], je = min(st[nc + 1], nlim); j < je; ++j) {
-                        if (j == k) continue;
-                        const float2 v = pos[j];
+                    for (uint32_t j = 0, je = min(cn[nc], (uint32_t)g.cap); j < je; ++j) {
+                        if (nc == c && j == k) continue;
+                        const float2 v = pr[(size_t)nc * t.cap + j];
                         const float ddx = pk.x - (v.x + tx);
                         const float ddy = pk.y - (v.y + ty);
                         bad += (ddx * ddx + ddy * ddy < kOverlapR2) ? 1u : 0u;
@@ -1304,26 +1258,37 @@ k_count_overlaps(Tables t, const float2 *__restrict__ pos, const uint32_t *__res
 __global__ void k_overlaps_reset(Tables t) { t.ctls[blockIdx.x].overlaps = 0; }
 
 // ------------------------------------------------------------- MSD
-// Deterministic FP64 reduction over one replica's disks: fixed chunks per
-// workgroup, fixed tree.
-constexpr int kMsdBlocks = kMsdBlocksMax;
+// Deterministic FP64 reduction of |acc|^2 over a replica's disks, in cell
+// and slot order (the order of the compact lists): one workgroup per
+// replica, each thread a fixed stride of slots, a fixed tree at the end.
 constexpr int kMsdThreads = 256;
+constexpr int kMsdBlocks = kMsdBlocksMax;
 
+// One replica over kMsdBlocks workgroups: workgroup b sums a fixed range of
+// cells, the final kernel adds the partials in order.
 __global__ void __launch_bounds__(kMsdThreads)
-k_msd_partial(const float2 *__restrict__ acc, long long N, double *__restrict__ part)
+k_msd_partial(Tables t, int r, const float2 *__restrict__ acc, const uint32_t *__restrict__ count,
+              double *__restrict__ part)
 {
     __shared__ double sh[kMsdThreads];
-    const long long chunk = (N + gridDim.x - 1) / gridDim.x;
-    const long long b = (long long)blockIdx.x * chunk;
-    const long long e = b + chunk < N ? b + chunk : N;
+    const Rep R = rep_of(t, r);
+    const long long S = t.cap;
+    const long long chunk = ((long long)R.g.C + gridDim.x - 1) / gridDim.x;
+    const long long c0 = (long long)blockIdx.x * chunk;
+    const long long c1 = c0 + chunk < R.g.C ? c0 + chunk : (long long)R.g.C;
+    const float2 *a = acc + (size_t)R.cb * S;
+    const uint32_t *cn = count + R.cb;
     double s = 0.0;
-    for (long long i = b + threadIdx.x; i < e; i += blockDim.x) {
-        const float2 a = acc[i];
-        s += (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+    for (long long i = c0 * S + threadIdx.x; i < c1 * S; i += kMsdThreads) {
+        const long long c = i / S;
+        if (i - c * S < (long long)cn[c]) {
+            const float2 v = a[i];
+            s += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+        }
     }
     sh[threadIdx.x] = s;
     __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    for (int o = kMsdThreads / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
@@ -1345,17 +1310,23 @@ k_msd_final(const double *__restrict__ part, int nb, long long N, Ctl *ctl)
     if (threadIdx.x == 0) ctl->msd = N > 0 ? sh[0] / (double)N : 0.0;
 }
 
-// One workgroup per replica: its disks' |acc|^2 in a fixed order.
-__global__ void __launch_bounds__(kMsdThreads) k_msd_all(Tables t, const float2 *__restrict__ acc)
+// Every replica, one workgroup each.
+__global__ void __launch_bounds__(kMsdThreads)
+k_msd_all(Tables t, const float2 *__restrict__ acc, const uint32_t *__restrict__ count)
 {
     __shared__ double sh[kMsdThreads];
-    const Rep &R = t.reps[blockIdx.x];
-    const float2 *a = acc + R.pb;
-    const long long N = R.g.N;
+    const Rep R = rep_of(t, blockIdx.x);
+    const long long S = t.cap;
+    const long long slots = (long long)R.g.C * S;
+    const float2 *a = acc + (size_t)R.cb * S;
+    const uint32_t *cn = count + R.cb;
     double s = 0.0;
-    for (long long i = threadIdx.x; i < N; i += kMsdThreads) {
-        const float2 v = a[i];
-        s += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+    for (long long i = threadIdx.x; i < slots; i += kMsdThreads) {
+        const long long c = i / S;
+        if (i - c * S < (long long)cn[c]) {
+            const float2 v = a[i];
+            s += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+        }
     }
     sh[threadIdx.x] = s;
     __syncthreads();
@@ -1363,7 +1334,7 @@ __global__ void __launch_bounds__(kMsdThreads) k_msd_all(Tables t, const float2 
         if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) t.ctls[blockIdx.x].msd = N > 0 ? sh[0] / (double)N : 0.0;
+    if (threadIdx.x == 0) t.ctls[blockIdx.x].msd = R.g.N > 0 ? sh[0] / (double)R.g.N : 0.0;
 }
 
 // ------------------------------------------------------------- tuner
@@ -1407,20 +1378,18 @@ __global__ void k_ctl_reset(Tables t, int first, unsigned long long sweep)
     Ctl *ctl = t.ctls + r;
     const Rep &R = t.reps[r];
     if (threadIdx.x == 0) {
-        ctl->sweep = sweep;
         ctl->trials = ctl->accepts = 0ull;
         ctl->win_trials = ctl->win_accepts = 0ull;
         ctl->key0 = R.key0;
         ctl->key1 = R.key1;
         ctl->delta = R.delta0;
         ctl->errword = 0u;
-        ctl->shift_f = 0;
-        ctl->shift_d = 0.0f;
         ctl->hist_samples = 0ull;
         ctl->overlaps = 0;
         ctl->msd = 0.0;
         for (int i = 0; i < 4; ++i) ctl->fit[i] = 0.0;
-        store_draws(ctl, sweep, R);
+        store_draws(ctl, 0, sweep, R);
+        store_draws(ctl, 1, sweep, R);
     }
     for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) ctl->hist[i] = 0ull;
 }
@@ -1431,7 +1400,8 @@ __global__ void k_ctl_set_key0(Tables t, unsigned int key0)
     if (r >= t.R) return;
     Ctl *ctl = t.ctls + r;
     ctl->key0 = key0;
-    store_draws(ctl, ctl->sweep, t.reps[r]);
+    store_draws(ctl, 0, ctl->sweep_at[0], t.reps[r]);
+    store_draws(ctl, 1, ctl->sweep_at[1], t.reps[r]);
 }
 
 __global__ void k_ctl_set_delta(Tables t, int first, int count, float delta)
@@ -1457,9 +1427,9 @@ int subsweep_block(int cap, int block, int lanes)
     return block < fit ? block : fit;
 }
 
-hipError_t launch_subsweep(const Tables &t, float2 *pos, const uint32_t *start, float2 *acc,
-                           uint32_t *tag, uint32_t *alog, const Work &w, int set, int block,
-                           int lanes, hipStream_t st)
+hipError_t launch_subsweep(const Tables &t, int par, float2 *pos, const uint32_t *count,
+                           float2 *acc, uint32_t *tag, uint32_t *alog, const Work &w, int set,
+                           int block, int lanes, hipStream_t st)
 {
     if (lanes != 1 && lanes != 2 && lanes != 4) return hipErrorInvalidValue;
     block = subsweep_block(t.cap, block, lanes);
@@ -1474,14 +1444,16 @@ hipError_t launch_subsweep(const Tables &t, float2 *pos, const uint32_t *start, 
 #define MPMC_SUB(CAP, PROP)                                                                    \
     do {                                                                                       \
         if (lanes == 1)                                                                        \
-            hipLaunchKernelGGL((k_subsweep<CAP, PROP>), grid, blk, lds, st, t, pos, start, acc,  \
-                               tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);         \
+            hipLaunchKernelGGL((k_subsweep<CAP, PROP>), grid, blk, lds, st, t, par, pos, count,  \
+                               acc, tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);    \
         else if (lanes == 2)                                                                   \
-            hipLaunchKernelGGL((k_subsweep_mc<CAP, 2, PROP>), grid, blk, lds, st, t, pos, start, \
-                               acc, tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);    \
+            hipLaunchKernelGGL((k_subsweep_mc<CAP, 2, PROP>), grid, blk, lds, st, t, par, pos,   \
+                               count, acc, tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile,  \
+                               per);                                                           \
         else                                                                                   \
-            hipLaunchKernelGGL((k_subsweep_mc<CAP, 4, PROP>), grid, blk, lds, st, t, pos, start, \
-                               acc, tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);    \
+            hipLaunchKernelGGL((k_subsweep_mc<CAP, 4, PROP>), grid, blk, lds, st, t, par, pos,   \
+                               count, acc, tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile,  \
+                               per);                                                           \
     } while (0)
 #define MPMC_SUB_P(CAP)                                                                        \
     do {                                                                                       \
@@ -1508,26 +1480,23 @@ hipError_t launch_fold_counters(const Tables &t, const Work &w, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_rebin(const Tables &t, const float2 *pos, const uint32_t *start,
+hipError_t launch_rebin(const Tables &t, int par, const float2 *pos, const uint32_t *count,
                         const float2 *acc, const uint32_t *tag, float2 *pos_out,
-                        uint32_t *start_out, float2 *acc_out, uint32_t *tag_out,
+                        uint32_t *count_out, float2 *acc_out, uint32_t *tag_out,
                         const Work &w, int f, float d, int advance, hipStream_t st)
 {
+    (void)w;
     RebinArgs a;
     a.t = t;
-    a.pos = pos; a.start = start; a.acc = acc; a.tag = tag;
-    a.pos_out = pos_out; a.start_out = start_out; a.acc_out = acc_out; a.tag_out = tag_out;
-    a.part = w.scan;
+    a.par = par;
+    a.pos = pos; a.count = count; a.acc = acc; a.tag = tag;
+    a.pos_out = pos_out; a.count_out = count_out; a.acc_out = acc_out; a.tag_out = tag_out;
     a.f = f; a.d = d;
     a.advance = (f < 0 && advance) ? 1 : 0;
     a.ntile = tiles_for(t.cells, kRebinTile);
     a.per = per_xcd(a.ntile);
     const dim3 grid(8 * a.per), blk(kRebinTile);
-#define MPMC_REBIN(CAP)                                                                        \
-    do {                                                                                       \
-        hipLaunchKernelGGL((k_rebin<false, CAP>), grid, blk, 0, st, a);                         \
-        hipLaunchKernelGGL((k_rebin<true, CAP>), grid, blk, 0, st, a);                          \
-    } while (0)
+#define MPMC_REBIN(CAP) hipLaunchKernelGGL((k_rebin<CAP>), grid, blk, 0, st, a)
     switch (t.cap) {
     case 4: MPMC_REBIN(4); break;
     case 5: MPMC_REBIN(5); break;
@@ -1539,13 +1508,13 @@ hipError_t launch_rebin(const Tables &t, const float2 *pos, const uint32_t *star
     return hipGetLastError();
 }
 
-hipError_t launch_pair_histogram(const Tables &t, const float2 *pos, const uint32_t *start,
+hipError_t launch_pair_histogram(const Tables &t, const float2 *pos, const uint32_t *count,
                                  int reset, hipStream_t st)
 {
     if (reset) hipLaunchKernelGGL(k_hist_reset, dim3(t.R), dim3(256), 0, st, t);
     const int ntile = tiles_for(t.cells, kRebinTile);
     const int per = per_xcd(ntile);
-    hipLaunchKernelGGL(k_pair_hist, dim3(8 * per), dim3(kRebinTile), 0, st, t, pos, start, ntile, per);
+    hipLaunchKernelGGL(k_pair_hist, dim3(8 * per), dim3(kRebinTile), 0, st, t, pos, count, ntile, per);
     return hipGetLastError();
 }
 
@@ -1555,27 +1524,30 @@ hipError_t launch_pressure_fit(const Tables &t, int replica, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_count_overlaps(const Tables &t, const float2 *pos, const uint32_t *start,
+hipError_t launch_count_overlaps(const Tables &t, const float2 *pos, const uint32_t *count,
                                  hipStream_t st)
 {
     hipLaunchKernelGGL(k_overlaps_reset, dim3(t.R), dim3(1), 0, st, t);
     const int ntile = tiles_for(t.cells, kRebinTile);
     const int per = per_xcd(ntile);
-    hipLaunchKernelGGL(k_count_overlaps, dim3(8 * per), dim3(kRebinTile), 0, st, t, pos, start,
+    hipLaunchKernelGGL(k_count_overlaps, dim3(8 * per), dim3(kRebinTile), 0, st, t, pos, count,
                        ntile, per);
     return hipGetLastError();
 }
 
-hipError_t launch_msd(const float2 *acc, long long n, Ctl *ctl, const Work &w, hipStream_t st)
+hipError_t launch_msd(const Tables &t, int replica, long long N, const float2 *acc,
+                      const uint32_t *count, const Work &w, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_msd_partial, dim3(kMsdBlocks), dim3(kMsdThreads), 0, st, acc, n, w.f64);
-    hipLaunchKernelGGL(k_msd_final, dim3(1), dim3(kMsdThreads), 0, st, w.f64, kMsdBlocks, n, ctl);
+    hipLaunchKernelGGL(k_msd_partial, dim3(kMsdBlocks), dim3(kMsdThreads), 0, st, t, replica, acc,
+                       count, w.f64);
+    hipLaunchKernelGGL(k_msd_final, dim3(1), dim3(kMsdThreads), 0, st, w.f64, kMsdBlocks, N,
+                       t.ctls + replica);
     return hipGetLastError();
 }
 
-hipError_t launch_msd_all(const Tables &t, const float2 *acc, hipStream_t st)
+hipError_t launch_msd_all(const Tables &t, const float2 *acc, const uint32_t *count, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_msd_all, dim3(t.R), dim3(kMsdThreads), 0, st, t, acc);
+    hipLaunchKernelGGL(k_msd_all, dim3(t.R), dim3(kMsdThreads), 0, st, t, acc, count);
     return hipGetLastError();
 }
 

@@ -69,7 +69,7 @@ class _Buffers:
         def buf(n):
             return torch.empty(max(int(n), 256), dtype=torch.uint8, device=device)
 
-        self.t = {k: [buf(sizes[k]), buf(sizes[k])] for k in ("pos", "start")}
+        self.t = {k: [buf(sizes[k]), buf(sizes[k])] for k in ("pos", "count")}
         self.t["acc"] = [buf(sizes["acc"]), buf(sizes["acc"])] if sizes["acc"] else None
         self.t["tag"] = [buf(sizes["tag"]), buf(sizes["tag"])] if sizes["tag"] else None
         self.work = buf(sizes["work"])
@@ -78,7 +78,7 @@ class _Buffers:
         b = L.Buffers()
         for i in range(2):
             b.pos[i] = self.t["pos"][i].data_ptr()
-            b.start[i] = self.t["start"][i].data_ptr()
+            b.count[i] = self.t["count"][i].data_ptr()
             b.acc[i] = self.t["acc"][i].data_ptr() if self.t["acc"] else None
             b.tag[i] = self.t["tag"][i].data_ptr() if self.t["tag"] else None
         b.work = self.work.data_ptr()

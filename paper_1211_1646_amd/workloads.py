@@ -54,7 +54,8 @@ def replicas(R: int = 64, seed: int = 1, n_min: int = 64, n_max: int = 512,
              phi_lo: float = 0.65, phi_hi: float = 0.73) -> list[dict]:
     """R square lattices n_r x n_r, N_r = n_r^2 log-uniform between n_min^2 and
     n_max^2 (n_r even), packing fractions evenly spaced over [phi_lo, phi_hi],
-    cells of width >= 1.  Sizes come from numpy's PCG64 seeded with `seed`."""
+    cells narrower than sqrt(2) (the paper's choice, capacity 4, about 1.7
+    disks per cell).  Sizes come from numpy's PCG64 seeded with `seed`."""
     rng = np.random.Generator(np.random.PCG64(seed))
     u = rng.random(R)
     half_lo, half_hi = n_min // 2, n_max // 2
@@ -63,5 +64,5 @@ def replicas(R: int = 64, seed: int = 1, n_min: int = 64, n_max: int = 512,
         k = int(round(half_lo * (half_hi / half_lo) ** float(u[r])))
         n = 2 * min(max(k, half_lo), half_hi)
         phi = phi_lo + (phi_hi - phi_lo) * (r / (R - 1) if R > 1 else 0.0)
-        out.append(dict(nx=n, ny=n, phi=phi, w_min=1.0, w_max=0.0))
+        out.append(dict(nx=n, ny=n, phi=phi, w_min=1.0, w_max=math.sqrt(2.0)))
     return out

@@ -76,8 +76,9 @@ def test_required_bytes():
     s = required_bytes(cfg)
     g = geometry(cfg)
     N, C = g["n_particles"], g["cells_x"] * g["cells_y"]
-    assert s["pos"] >= 8 * N and s["acc"] >= 8 * N and s["tag"] >= 4 * N
-    assert s["start"] >= 4 * (C + 1)
+    cap = g["capacity"]
+    assert s["pos"] >= 8 * C * cap and s["acc"] >= 8 * C * cap and s["tag"] >= 4 * C * cap
+    assert s["count"] >= 4 * C
     assert all(v % 256 == 0 for v in s.values())
     assert required_bytes(SystemConfig(lattice_nx=64, lattice_ny=64, phi=0.6))["acc"] == 0
 
@@ -126,7 +127,8 @@ def _batch_sizes(cfgs):
 
 def test_batch_required_bytes_covers_the_replicas():
     """Padded layout: cells rounded up (with at least one spare) to 256 per
-    replica, disks back to back; one control block per replica."""
+    replica, the largest capacity's slots per cell; one control block per
+    replica."""
     from paper_1211_1646_amd import workloads as W
     specs = W.replicas(8, seed=3)
     cfgs = [SystemConfig(lattice_nx=s["nx"], lattice_ny=s["ny"], phi=s["phi"], delta=0.1,
@@ -134,15 +136,16 @@ def test_batch_required_bytes_covers_the_replicas():
             for r, s in enumerate(specs)]
     st, s = _batch_sizes(cfgs)
     assert st == L.MPMC_OK
-    N = sum(sp["nx"] * sp["ny"] for sp in specs)
-    cells = 0
+    cells, cap = 0, 0
     for c in cfgs:
         g = geometry(c)
         C_r = g["cells_x"] * g["cells_y"]
         cells += (C_r + 1 + 255) // 256 * 256
-    assert s.pos >= 8 * N and s.pos < 8 * N + 256
-    assert s.acc == s.pos and s.tag >= 4 * N
-    assert s.start >= 4 * (cells + 1) and s.start < 4 * (cells + 1) + 256
+        cap = max(cap, g["capacity"])
+    # slots: the largest capacity per cell, for every (padded) cell
+    assert s.pos >= 8 * cells * cap and s.pos < 8 * cells * cap + 256
+    assert s.acc == s.pos and s.tag >= 4 * cells * cap
+    assert s.count >= 4 * cells and s.count < 4 * cells + 256
     assert s.accept_log >= 4 * cells
     single = required_bytes(cfgs[0])
     assert single["ctl"] < s.ctl
