@@ -171,6 +171,16 @@ def batched_leg(args, pkg, torch):
     eos_auto = eos_window(B2, torch)
     B2.close()
     z = np.abs(eos_auto[0] - eos_plain[0]) / np.sqrt(eos_auto[1] ** 2 + eos_plain[1] ** 2)
+    # control: the same n_M = 4 batch with another seed and the same history
+    # length -- the spread two runs of one chain show in this check
+    cfgs3 = [pkg.SystemConfig(**{**c.__dict__, "seed": 2}) for c in cfgs]
+    B3 = pkg.HardDiskBatch(cfgs3)
+    B3.tune(10, 4)
+    B3.set_launch(lanes, blk)
+    B3.sweep(n_candidates * 32 + n + args.batched_relax)
+    eos_ctrl = eos_window(B3, torch)
+    B3.close()
+    z0 = np.abs(eos_ctrl[0] - eos_plain[0]) / np.sqrt(eos_ctrl[1] ** 2 + eos_plain[1] ** 2)
     # the same replicas, one handle each, one after another, with the same
     # history (tuner windows, then the sweeps the autotuner ran), so each
     # timed window runs exactly the chain the batch ran
@@ -204,7 +214,10 @@ def batched_leg(args, pkg, torch):
                          "timed window, n_M = %d vs the autotuned n_M: |dP| / combined SE mean %.2f, "
                          "max %.2f over %d replicas"
                          % (args.batched_relax, args.n_moves, float(z.mean()), float(z.max()), len(z)),
-            "eos_z": [float(v) for v in z]}
+            "eos_z": [float(v) for v in z],
+            "eos_control": "same check between two n_M = %d batches with seeds 1 and 2: mean %.2f, "
+                           "max %.2f" % (args.n_moves, float(z0.mean()), float(z0.max())),
+            "eos_z_control": [float(v) for v in z0]}
 
 
 def eos_window(B, torch, blocks=8, per_block=256, sample_every=16):
