@@ -97,10 +97,10 @@ def cpu_baseline(args, geo, trials_per_sweep_gpu):
                       "serial C oracle, one thread)" % (n, geo["n_particles"], tr1 - tr0, dt)}
 
 
-def traffic_from_profile(kernel_src, kernel_name):
-    """HBM bytes per sub-sweep launch from the committed counter summary, if
-    it was taken on the current kernel source and the same kernel (else
-    None)."""
+def traffic_from_profile(kernel_src, kernel_name, key="hbm bytes per launch"):
+    """A figure of the committed counter summary (HBM bytes per sub-sweep
+    launch by default), if it was taken on the current kernel source and the
+    same kernel (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "subsweep_1M_phi070_counters.md")
     if not os.path.exists(path):
@@ -114,7 +114,7 @@ def traffic_from_profile(kernel_src, kernel_name):
     if vals.get("kernel source sha256/16") != digest or vals.get("kernel") != kernel_name.split("<")[0]:
         return None
     try:
-        return float(vals["hbm bytes per launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
 
@@ -497,6 +497,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_from_profile(os.path.join(
                          ROOT, "paper_1211_1646_amd", "csrc", "mpmc_kernels.hip"), kernel_name),
+                     "valu_busy": traffic_from_profile(os.path.join(
+                         ROOT, "paper_1211_1646_amd", "csrc", "mpmc_kernels.hip"), kernel_name,
+                         "valu busy fraction"),
                      "kernel": kernel_name, "kernel_avg_us": k_avg_ms * 1e3,
                      "kernel_timing": "%d launches in one captured graph, HIP events around the "
                                       "replay on the system's stream" % ks,
