@@ -14,7 +14,9 @@ oracle timed on a bounded sample of the same workload.  Two more objects
 compare the batched and learned-controller forms with the plain form:
   batched -- 64 replicas of uneven N (64^2 .. 512^2) and packing fraction
              (0.65 .. 0.73) in one handle against the same 64 systems run
-             one after another (same chain, bit for bit);
+             one after another (same chain, bit for bit); with n_M from the
+             autotuner; and learned+batched: the trained network sets delta
+             during equilibration, n_M autotuned, against the plain systems;
   learned -- a move-size network trained on samples the sweeps log, used
              during equilibration of the 1M-disk workload, against the plain
              tuner: mean-square displacement per second of production
@@ -119,8 +121,10 @@ def traffic_from_profile(kernel_src, kernel_name, key="hbm bytes per launch"):
         return None
 
 
-def batched_leg(args, pkg, torch):
-    """64-replica batch vs the same replicas one after another."""
+def batched_leg(args, pkg, torch, net=None):
+    """64-replica batch vs the same replicas one after another; with a trained
+    move-size network also the learned+batched form (network-set delta during
+    the equilibration windows, autotuned n_M)."""
     from paper_1211_1646_amd import workloads as W
     specs = W.replicas(64, seed=1)
     cfgs = [pkg.SystemConfig(lattice_nx=s["nx"], lattice_ny=s["ny"], phi=s["phi"], w_min=s["w_min"],
@@ -171,6 +175,30 @@ def batched_leg(args, pkg, torch):
     eos_auto = eos_window(B2, torch)
     B2.close()
     z = np.abs(eos_auto[0] - eos_plain[0]) / np.sqrt(eos_auto[1] ** 2 + eos_plain[1] ** 2)
+    # learned + batched: the network sets every replica's delta in the four
+    # equilibration windows where the plain form runs its tuner, then delta
+    # is frozen and n_M is the autotuned one
+    lb = None
+    if net is not None:
+        B4 = pkg.HardDiskBatch(cfgs)
+        B4.control(net, 10, 4)
+        B4.set_launch(lanes, blk)
+        B4.set_n_moves(best_nm)
+        B4.sweep(n_candidates * 32)
+        B4.reset_acc()
+        B4.synchronize()
+        e0.record(B4.stream)
+        B4.sweep(n)
+        e1.record(B4.stream)
+        e1.synchronize()
+        l_sec = e0.elapsed_time(e1) * 1e-3
+        _, _, l_deltas, msd4 = B4.stats(with_msd=True)
+        l_msd_sum = float((Ns * msd4).sum())
+        B4.sweep(args.batched_relax)
+        eos_lb = eos_window(B4, torch)
+        B4.close()
+        z4 = np.abs(eos_lb[0] - eos_plain[0]) / np.sqrt(eos_lb[1] ** 2 + eos_plain[1] ** 2)
+        lb = (l_msd_sum / l_sec, l_deltas, z4)
     # control: the same n_M = 4 batch with another seed and the same history
     # length -- the spread two runs of one chain show in this check
     cfgs3 = [pkg.SystemConfig(**{**c.__dict__, "seed": 2}) for c in cfgs]
@@ -201,7 +229,7 @@ def batched_leg(args, pkg, torch):
         seq_tr += S.counters()[0] - t0
         seq_msd += float(Ns[r]) * S.msd()
         S.close()
-    return {"replicas": len(cfgs), "disks": int(Ns.sum()), "sweeps": n,
+    out = {"replicas": len(cfgs), "disks": int(Ns.sum()), "sweeps": n,
             "trial_moves_per_s": btr / bsec, "sequential_trial_moves_per_s": seq_tr / seq_sec,
             "speedup": (btr / bsec) / (seq_tr / seq_sec),
             "msd_sum_per_s": b_msd_sum / bsec, "sequential_msd_sum_per_s": seq_msd / seq_sec,
@@ -218,6 +246,17 @@ def batched_leg(args, pkg, torch):
             "eos_control": "same check between two n_M = %d batches with seeds 1 and 2: mean %.2f, "
                            "max %.2f" % (args.n_moves, float(z0.mean()), float(z0.max())),
             "eos_z_control": [float(v) for v in z0]}
+    if lb is not None:
+        out["learned_batched"] = {
+            "msd_sum_per_s": lb[0],
+            "vs_sequential_plain_msd_per_s": lb[0] / (seq_msd / seq_sec),
+            "n_moves": best_nm,
+            "delta_range": [float(np.min(lb[1])), float(np.max(lb[1]))],
+            "plain_delta_range": [float(np.min(deltas)), float(np.max(deltas))],
+            "eos_check": "P* vs the plain n_M = %d batch, same check: |dP| / combined SE mean "
+                         "%.2f, max %.2f" % (args.n_moves, float(lb[2].mean()), float(lb[2].max())),
+            "eos_z": [float(v) for v in lb[2]]}
+    return out
 
 
 def eos_window(B, torch, blocks=8, per_block=256, sample_every=16):
@@ -366,7 +405,7 @@ def learned_leg(args, pkg, torch, lanes_main, block_main):
             "labels": {"%.2f" % k: v for k, v in sorted(info["labels"].items())},
             "plain": pl, "learned": le,
             "msd_per_s_ratio": le["msd_per_s"] / pl["msd_per_s"],
-            "P_diff_in_combined_se": abs(le["P"] - pl["P"]) / comb if comb > 0 else None}
+            "P_diff_in_combined_se": abs(le["P"] - pl["P"]) / comb if comb > 0 else None}, net
 
 
 def main():
@@ -507,13 +546,14 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
     S.close()
-    if not args.no_batched:
-        print("[bench] batched leg", file=sys.stderr, flush=True)
-        out["batched"] = batched_leg(args, pkg, torch)
+    net = None
     if not args.no_learned:
         print("[bench] learned-controller leg", file=sys.stderr, flush=True)
-        out["learned"] = learned_leg(args, pkg, torch, out["config"]["subsweep_lanes_per_cell"],
-                                     out["config"]["subsweep_block"])
+        out["learned"], net = learned_leg(args, pkg, torch, out["config"]["subsweep_lanes_per_cell"],
+                                          out["config"]["subsweep_block"])
+    if not args.no_batched:
+        print("[bench] batched leg", file=sys.stderr, flush=True)
+        out["batched"] = batched_leg(args, pkg, torch, net)
     if not args.no_eos:
         print("[bench] equation-of-state leg", file=sys.stderr, flush=True)
         out["eos"] = eos_leg(args, pkg, torch, out["config"]["subsweep_lanes_per_cell"],

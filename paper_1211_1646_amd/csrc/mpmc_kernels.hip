@@ -536,6 +536,11 @@ k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restri
                 px[q] = q < n ? px[q] : far.x;
                 py[q] = q < n ? py[q] : far.y;
             }
+            // the lane's row, read once into registers: the neighbours do not
+            // move during the cell update, so the trials test registers only
+            float2 nr[kL];
+#pragma unroll
+            for (int k = 0; k < kL; ++k) nr[k] = k < KLw ? nbr[k] : far;
             for (int tr = 0; tr < n_moves; ++tr) {
                 if (tr > 0 && (tr & 3) == 0) W = philox((uint32_t)c, s_lo, s_hi, (uint32_t)(tr >> 2), k0, k1);
                 float dx, dy;
@@ -553,10 +558,13 @@ k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restri
                     const float r2 = ddx * ddx + ddy * ddy;
                     ok = ok & !(r2 < 1.0f);
                 }
-                // neighbours four at a time (two paired LDS reads)
-                for (int k = 0; k < KLw; k += 4) {
-                    const float m = min_r2(xm, ym, nbr + k);
-                    ok = ok & !(m < 1.0f);
+                // neighbours four at a time, up to the wave's group count
+#pragma unroll
+                for (int k = 0; k < kL; k += 4) {
+                    if (k < KLw) {
+                        const float m = min_r2(xm, ym, nr + k);
+                        ok = ok & !(m < 1.0f);
+                    }
                 }
                 if (kO > 0 && K4 > kL)
                     for (int k = kL; ok && k < K4; k += 4)
