@@ -6,6 +6,7 @@ never does; it shares no code with it.
 
 Contents
   * ``mpmc_oracle.c``  serial checkerboard chain (Alg. 1, 2, 4 of the paper)
+  * ``sphere_oracle.c`` the same chain for hard spheres in 3D (``spheres.py``)
   * ``serial_ref.c``   FP64 single-particle Metropolis (statistical reference)
   * ``estimator.py``   FP64 pressure from the contact value (Sec. 4)
   * ``mlp.py``         FP64 move-size network (forward / backward / Adam)
@@ -20,7 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["mpmc_oracle.c", "serial_ref.c"]
+_SOURCES = ["mpmc_oracle.c", "serial_ref.c", "sphere_oracle.c"]
 HIST_BINS = 200
 
 

@@ -90,3 +90,52 @@ def virial_pressure_ratio(phi: float) -> float:
     b3 = 4.0 / 3.0 - np.sqrt(3.0) / np.pi
     b4 = 2.0 - 9.0 * np.sqrt(3.0) / (2.0 * np.pi) + 10.0 / np.pi ** 2
     return 1.0 + 2.0 * phi + 4.0 * b3 * phi ** 2 + 8.0 * b4 * phi ** 3
+
+
+# ---------------------------------------------------------------- 3D spheres
+# The same estimator for hard spheres (the method in d = 3): the sampling
+# point is the volume-weighted mean radius of the shell [r_i, r_{i+1}), g is
+# the pair count over N rho times the shell's surface 4 pi R^2 dr at that
+# radius, the contact value comes from the same degree-5 fit, and the
+# pressure from the contact theorem in 3D, beta P / rho = 1 + (2 pi / 3) rho
+# g(sigma+) (sigma = 1).
+
+
+def sampling_points_3d(nbins: int = NBINS, dr: float = DR) -> np.ndarray:
+    i = np.arange(nbins, dtype=np.float64)
+    r0 = 1.0 + i * dr
+    r1 = 1.0 + (i + 1.0) * dr
+    return 0.75 * (r1 ** 4 - r0 ** 4) / (r1 ** 3 - r0 ** 3)
+
+
+def pair_correlation_3d(hist, n_samples: float, N: float, rho: float, dr: float = DR):
+    hist = np.asarray(hist, dtype=np.float64) / float(n_samples)
+    R = sampling_points_3d(len(hist), dr)
+    return R, hist / (N * rho * 4.0 * np.pi * R * R * dr)
+
+
+def contact_value_3d(hist, n_samples, N, rho, dr=DR, c=FIT_RANGE, degree=DEGREE) -> float:
+    R, g = pair_correlation_3d(hist, n_samples, N, rho, dr)
+    keep = (R > 1.0) & (R <= 1.0 + c)
+    x = (R[keep] - 1.0) / c
+    X = np.vander(x, degree + 1, increasing=True)
+    coef, *_ = np.linalg.lstsq(X, g[keep], rcond=None)
+    return float(coef[0])
+
+
+def pressure_3d(rho: float, g_contact: float) -> float:
+    return rho * (1.0 + (2.0 * np.pi / 3.0) * rho * g_contact)
+
+
+def pressure_from_histogram_3d(hist, n_samples, N, rho, **kw):
+    g0 = contact_value_3d(hist, n_samples, N, rho, **kw)
+    return pressure_3d(rho, g0), g0
+
+
+def virial_pressure_ratio_3d(eta: float) -> float:
+    """Low-density equation of state of hard spheres, beta P / rho through
+    eta^5, from the textbook virial coefficients: 4 (B2), 10 (B3/B2^2 = 5/8),
+    18.3648 (B4/B2^3 = 0.2869495, known in closed form), 28.2245 and 39.8151
+    (B5, B6, computed numerically in the literature)."""
+    c = (4.0, 10.0, 18.3648, 28.2245, 39.8151)
+    return 1.0 + sum(ck * eta ** (k + 1) for k, ck in enumerate(c))
