@@ -193,7 +193,7 @@ mpmc_status mpmc_sweep(mpmc_handle h, int64_t n_sweeps, uint32_t seed);
  * each replica's own.) */
 
 /* One sub-sweep of checkerboard set `set` (0..3 = a..d of Eq. 1) with the
- * current sweep's cell streams (Alg. 1 lines 4-13, Alg. 2).  async. */
+ * current sweep's cell streams (Alg. 1, Alg. 2).  async. */
 mpmc_status mpmc_subsweep(mpmc_handle h, int32_t set);
 
 /* shift_and_rebin (Alg. 4).  f in 0..3 (+x, -x, +y, -y) with 0 <= d <= w_f/2

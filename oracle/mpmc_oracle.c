@@ -172,7 +172,7 @@ void oracle_disk_displacement(uint32_t word, float delta, float *dx, float *dy)
     *dy = r * b;
 }
 
-/* Particle chosen by trial s of a cell update (Alg. 1, line 7): the list is
+/* Particle chosen by trial s of a cell update (Alg. 1): the list is
  * walked from the start and wraps around when n_M > n. */
 static int visit_slot(int s, int n) { return s % n; }
 
@@ -423,7 +423,7 @@ void oracle_get_counters(const oracle_sys *S, uint64_t *trials, uint64_t *accept
 }
 
 /* ------------------------------------------------------------------------
- * One cell update (Alg. 1 lines 5-12, Alg. 2).
+ * One cell update (Alg. 1, Alg. 2).
  * ------------------------------------------------------------------------ */
 static int wrap(int i, int m) { return (i % m + m) % m; }
 
@@ -488,7 +488,7 @@ static void cell_update(oracle_sys *S, int cx, int cy)
         swap_slots(S, base + i, base + j);
     }
 
-    /* n_M trial moves, particle list[s mod n] (Alg. 1 lines 6-12). */
+    /* n_M trial moves, particle list[s mod n] (Alg. 1). */
     for (int s = 0; s < S->n_moves; ++s) {
         if ((s & 3) == 0) stream_block((uint32_t)c, S->sweep, TAG_TRIAL + (uint32_t)(s >> 2), S->key, words);
         int slot = base + visit_slot(s, n);

@@ -131,7 +131,7 @@ struct Draws {
     float d;
 };
 
-// The sweep-global block (Alg. 1 lines 2 and 15-16): Fisher-Yates order of
+// The sweep-global block (Alg. 1): Fisher-Yates order of
 // the four sets from words 0..2; f from the top two bits of word 3 and
 // d = u (w_f / 2) from its low 24 bits.  The order is kept as four bytes of
 // one register so that no array is indexed at run time.

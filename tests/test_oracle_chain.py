@@ -213,7 +213,7 @@ def test_many_shifts_lose_nothing():
 
 # ------------------------------------------------------------- shuffling
 def test_particle_shuffle_is_uniform():
-    """Alg. 1 line 5: with n_M = 0 a sub-sweep only permutes each active cell;
+    """Alg. 1: with n_M = 0 a sub-sweep only permutes each active cell;
     over many cells and sweeps all n! orders of n = 2, 3, 4 particles are
     equally likely (chi-square)."""
     S = OracleSystem.lattice(48, 48, 0.72, w_max=1.932, n_moves=0, seed=21,
