@@ -1,4 +1,5 @@
-"""ctypes declarations of the C ABI in include/mpmc.h (argument marshalling only).
+"""ctypes declarations of the C ABI in include/mpmc.h and include/mpmc_sphere.h
+(argument marshalling only).
 
 Loading fails loudly when libmpmc.so has not been built: there is no
 fallback implementation of any step.
@@ -56,6 +57,32 @@ class Buffers(C.Structure):
     _fields_ = [("pos", C.c_void_p * 2), ("count", C.c_void_p * 2), ("acc", C.c_void_p * 2),
                 ("tag", C.c_void_p * 2), ("work", C.c_void_p), ("ctl", C.c_void_p),
                 ("accept_log", C.c_void_p)]
+
+
+class SphereParams(C.Structure):
+    _fields_ = [("lattice_nx", C.c_int32), ("lattice_ny", C.c_int32), ("lattice_nz", C.c_int32),
+                ("eta", C.c_double), ("cells_x", C.c_int32), ("cells_y", C.c_int32),
+                ("cells_z", C.c_int32), ("w_max", C.c_double), ("cell_w_x", C.c_float),
+                ("cell_w_y", C.c_float), ("cell_w_z", C.c_float), ("n_particles", C.c_int64),
+                ("delta", C.c_float), ("n_moves", C.c_int32), ("seed", C.c_uint32),
+                ("replica", C.c_uint32), ("flags", C.c_uint32)]
+
+
+class SphereGeometry(C.Structure):
+    _fields_ = [("n_particles", C.c_int64), ("cells_x", C.c_int32), ("cells_y", C.c_int32),
+                ("cells_z", C.c_int32), ("w_x", C.c_float), ("w_y", C.c_float),
+                ("w_z", C.c_float), ("box_x", C.c_double), ("box_y", C.c_double),
+                ("box_z", C.c_double), ("density", C.c_double)]
+
+
+class SphereBufferSizes(C.Structure):
+    _fields_ = [("pos", C.c_size_t), ("count", C.c_size_t), ("tag", C.c_size_t),
+                ("work", C.c_size_t), ("ctl", C.c_size_t)]
+
+
+class SphereBuffers(C.Structure):
+    _fields_ = [("pos", C.c_void_p * 2), ("count", C.c_void_p * 2), ("tag", C.c_void_p * 2),
+                ("work", C.c_void_p), ("ctl", C.c_void_p)]
 
 
 class MPMCError(RuntimeError):
@@ -125,6 +152,26 @@ _SIGNATURES = {
     "mpmc_adam_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                    C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32,
                                    C.c_void_p]),
+    "mpmc_sphere_geometry_of": (C.c_int32, [C.POINTER(SphereParams), C.POINTER(SphereGeometry)]),
+    "mpmc_sphere_required_bytes": (C.c_int32, [C.POINTER(SphereParams),
+                                               C.POINTER(SphereBufferSizes)]),
+    "mpmc_sphere_init": (C.c_int32, [C.POINTER(SphereParams), C.POINTER(SphereBuffers),
+                                     C.c_void_p, C.POINTER(C.c_void_p)]),
+    "mpmc_sphere_sweep": (C.c_int32, [_H, C.c_int64]),
+    "mpmc_sphere_subsweep": (C.c_int32, [_H, C.c_int32]),
+    "mpmc_sphere_shift": (C.c_int32, [_H, C.c_int32, C.c_float]),
+    "mpmc_sphere_get_state": (C.c_int32, [_H, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.POINTER(C.c_uint64)]),
+    "mpmc_sphere_set_state": (C.c_int32, [_H, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p]),
+    "mpmc_sphere_get_counters": (C.c_int32, [_H, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "mpmc_sphere_set_delta": (C.c_int32, [_H, C.c_float]),
+    "mpmc_sphere_get_delta": (C.c_int32, [_H, C.POINTER(C.c_float)]),
+    "mpmc_sphere_pair_histogram": (C.c_int32, [_H, C.c_int32]),
+    "mpmc_sphere_pressure": (C.c_int32, [_H, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                         C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "mpmc_sphere_count_overlaps": (C.c_int32, [_H, C.POINTER(C.c_int64)]),
+    "mpmc_sphere_synchronize": (C.c_int32, [_H]),
+    "mpmc_sphere_destroy": (None, [_H]),
     "mpmc_destroy": (None, [_H]),
     "mpmc_last_error": (C.c_char_p, []),
 }

@@ -4,7 +4,8 @@
 
 Flags: -O3, no floating-point contraction (bit-exact with the CPU oracle's
 specification), packed-FP32 instructions disabled, position-independent
-shared library exporting the C ABI of include/mpmc.h.
+shared library exporting the C ABI of include/mpmc.h and
+include/mpmc_sphere.h.
 """
 from __future__ import annotations
 
@@ -17,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmpmc.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("mpmc_kernels.hip", "mpmc_mlp.hip",
-                                                       "mpmc_api.cpp")]
+                                                       "mpmc_api.cpp", "sphere_kernels.hip",
+                                                       "sphere_api.cpp")]
 ARCH = os.environ.get("MPMC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -709,6 +709,11 @@ mpmc_status check_delta(const mpmc_system *h, int r, float delta)
 
 }  // namespace
 
+namespace mpmc {
+// The calling thread's last failure message, shared with the sphere calls.
+void set_last_error(const char *msg) { g_last_error = msg; }
+}  // namespace mpmc
+
 extern "C" {
 
 const char *mpmc_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,78 @@
+// Internal declarations shared by the host side (sphere_api.cpp) and the
+// kernels (sphere_kernels.hip) of the 3D hard-sphere chain.  Not part of the
+// public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpmc {
+namespace sph {
+
+constexpr int kCap = 8;                  // spheres per cell (w < 2/sqrt(3))
+constexpr int kHistBins = 200;
+constexpr uint32_t kErrCapacity = 1u;    // a cell holds more than kCap spheres
+constexpr int kTile = 256;               // cells per rebin / histogram workgroup
+constexpr int kSubBlock = 64;            // lanes per sub-sweep workgroup (one wave)
+constexpr int kNbrList = 32;             // reachable neighbours a lane keeps in LDS
+
+// Control block: what a captured sweep graph reads or writes that changes
+// between launches.  sweep_at / draw_at are indexed by the ping-pong half a
+// launch reads; the rebin, which reads half p and writes p ^ 1, writes slot
+// p ^ 1, so no launch writes what it reads.
+struct alignas(256) Ctl3 {
+    unsigned long long sweep_at[2];
+    unsigned long long trials, accepts;   // folded counters
+    unsigned int key0, key1;
+    float delta;
+    unsigned int errword;
+    struct Draw {
+        unsigned int order;   // nibble q = set processed in slot q
+        int f;                // 0..5 = +x, -x, +y, -y, +z, -z
+        float d;
+        unsigned int pad;
+    } draw_at[2];
+    unsigned long long hist_samples;
+    double fit[4];                        // P, g(sigma+), rho, status
+    long long overlaps;
+    unsigned long long hist[kHistBins];
+};
+
+struct Geom3 {
+    int m[3];        // cells per axis (even, >= 4)
+    float w[3];      // cell widths
+    int C;           // cells
+    int active;      // active cells of one set: C / 8
+    long long N;
+    int n_moves;
+};
+
+// Sub-sweep counter partials: two u64 (trials, accepts) per sub-sweep
+// workgroup, accumulated by every sub-sweep and folded on demand.
+inline int subsweep_groups(const Geom3 &g) { return (g.active + kSubBlock - 1) / kSubBlock; }
+inline int xcd_groups(int tiles) { return 8 * ((tiles + 7) / 8); }
+
+hipError_t launch_subsweep3(const Geom3 &g, Ctl3 *ctl, int par, float4 *pos,
+                            const uint32_t *count, uint32_t *tag, unsigned long long *cnt,
+                            int set, hipStream_t st);
+hipError_t launch_fold3(const Geom3 &g, Ctl3 *ctl, unsigned long long *cnt, hipStream_t st);
+// f >= 0: explicit shift (f, d), sweep slot copied; f < 0: the sweep's own
+// draws, advance to the next sweep.
+hipError_t launch_rebin3(const Geom3 &g, Ctl3 *ctl, int par, const float4 *pos,
+                         const uint32_t *count, const uint32_t *tag, float4 *pos_out,
+                         uint32_t *count_out, uint32_t *tag_out, int f, float d, hipStream_t st);
+hipError_t launch_ctl_reset3(const Geom3 &g, Ctl3 *ctl, unsigned long long sweep,
+                             unsigned int key0, unsigned int key1, float delta, hipStream_t st);
+hipError_t launch_set_delta3(Ctl3 *ctl, float delta, hipStream_t st);
+hipError_t launch_pair_hist3(const Geom3 &g, Ctl3 *ctl, const float4 *pos, const uint32_t *count,
+                             int reset, hipStream_t st);
+hipError_t launch_pressure_fit3(const Geom3 &g, Ctl3 *ctl, hipStream_t st);
+hipError_t launch_count_overlaps3(const Geom3 &g, Ctl3 *ctl, const float4 *pos,
+                                  const uint32_t *count, hipStream_t st);
+
+}  // namespace sph
+
+// Record the calling thread's failure message (read by mpmc_last_error).
+void set_last_error(const char *msg);
+
+}  // namespace mpmc

@@ -1,0 +1,813 @@
+// HIP kernels of the hard-sphere chain (the method in d = 3) for gfx950.
+//
+// Method: Anderson et al., arXiv:1211.1646, stated for d dimensions (Sec. 2):
+// Alg. 1 (sweep) over 8 checkerboard sets, Alg. 2 (cell update) against the
+// 27-cell neighbourhood, Alg. 4 (cell shift) along one of 6 directions, and
+// the contact-value pressure of Sec. 4 in its 3D form.
+//
+// Data layout in device memory:
+//   count[C]    uint32 spheres per cell, c = (cz m_y + cy) m_x + cx;
+//   pos[C][8]   float4 (x, y, z, 0) cell-local coordinates in (0, w], slots
+//               [0, count) used -- one cell is one 128-byte line;
+//   tag[C][8]   uint32 identity of each sphere (optional).
+// A sub-sweep writes only the active cells' own slots and reads their 26
+// inactive neighbours, so it updates in place; the rebin writes the other
+// ping-pong half.
+//
+// Every floating-point expression rounds once per operation (the library is
+// built with -ffp-contract=off; the pragma below repeats it).
+#include "mpmc_device.h"
+#include "sphere_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace mpmc {
+namespace sph {
+namespace {
+
+constexpr uint32_t kTagShuffle = 0x40000000u;
+constexpr uint32_t kTagSweep = 0x80000000u;
+constexpr uint32_t kCellGlobal = 0xFFFFFFFFu;
+
+// One 16-bit half h of a trial word: the midpoint (2h + 1 - 65536) / 65536
+// of one of 65536 equal parts of (-1, 1).
+__device__ __forceinline__ float half_unit(uint32_t h)
+{
+    return (float)(2 * (int)h + 1 - 65536) * 0x1p-16f;
+}
+
+// Trial displacement from words a, b: x and y from the halves of a, z from
+// the high half of b, each times delta.
+__device__ __forceinline__ void displacement3(uint32_t a, uint32_t b, float delta, float &dx,
+                                              float &dy, float &dz)
+{
+    dx = half_unit(a >> 16) * delta;
+    dy = half_unit(a & 0xFFFFu) * delta;
+    dz = half_unit(b >> 16) * delta;
+}
+
+struct Draws3 {
+    uint32_t order;   // nibble q = set processed in slot q
+    int f;
+    float d;
+};
+
+// Draws of sweep s (Alg. 1 in d = 3): Fisher-Yates order of the 8 sets from
+// words u0..u6 of two global blocks, f = floor(6 u7 / 2^32), d = u (w_f / 2)
+// from the low 24 bits of word 0 of a third block.  The order is kept as
+// eight nibbles of one register, so nothing is indexed at run time.
+__device__ __forceinline__ Draws3 sweep_draws3(unsigned long long s, uint32_t k0, uint32_t k1,
+                                               const Geom3 &g)
+{
+    const uint32_t lo = (uint32_t)s, hi = (uint32_t)(s >> 32);
+    const uint4 A = philox(kCellGlobal, lo, hi, kTagSweep, k0, k1);
+    const uint4 B = philox(kCellGlobal, lo, hi, kTagSweep + 1u, k0, k1);
+    const uint4 G = philox(kCellGlobal, lo, hi, kTagSweep + 2u, k0, k1);
+    const uint32_t u[8] = {A.x, A.y, A.z, A.w, B.x, B.y, B.z, B.w};
+    uint32_t ord = 0x76543210u;
+#pragma unroll
+    for (int i = 7; i >= 1; --i) ord = nib_swap(ord, i, (int)bounded(u[7 - i], (uint32_t)(i + 1)));
+    Draws3 D;
+    D.order = ord;
+    D.f = (int)bounded(u[7], 6u);
+    const float wf = D.f < 2 ? g.w[0] : (D.f < 4 ? g.w[1] : g.w[2]);
+    const float ud = (float)(G.x & 0xFFFFFFu) * 0x1p-24f;
+    D.d = ud * (0.5f * wf);
+    return D;
+}
+
+__device__ __forceinline__ void store_draws3(Ctl3 *ctl, int p, unsigned long long s,
+                                             const Geom3 &g)
+{
+    const Draws3 D = sweep_draws3(s, ctl->key0, ctl->key1, g);
+    ctl->sweep_at[p] = s;
+    ctl->draw_at[p].order = D.order;
+    ctl->draw_at[p].f = D.f;
+    ctl->draw_at[p].d = D.d;
+}
+
+__device__ __forceinline__ int wrap_dn(int c, int m) { return c == 0 ? m - 1 : c - 1; }
+__device__ __forceinline__ int wrap_up(int c, int m) { return c == m - 1 ? 0 : c + 1; }
+
+// ------------------------------------------------------------ sub-sweep
+// One lane per active cell of set Q (Alg. 2 in d = 3):
+//   1. the 27 counts and the cell's own 8 slots are loaded together, and the
+//      cell's first Philox blocks are computed while they are in flight;
+//   2. the neighbours' spheres are loaded slot by slot over the 26 cells
+//      (slot i of every cell in one batch, only while some lane of the wave
+//      has a cell with more than i spheres), translated into the cell's
+//      frame by exactly -w, 0 or +w, and those that can reach the cell --
+//      squared distance to the cell's box below 1.0001, a superset of every
+//      sphere a trial position inside the cell can overlap -- are compacted
+//      into this lane's column of an LDS table;
+//   3. the column is read back into registers and the n_M trials run from
+//      registers only.  A lane with more reachable neighbours than the table
+//      holds also tests every neighbour straight from memory (rare).
+// Dropping unreachable spheres cannot change a decision: a trial outside
+// the cell is rejected before any overlap test, and one inside it is at
+// squared distance >= 1 from every dropped sphere, also after FP32 rounding.
+constexpr float kReach2 = 1.0001f;
+constexpr float kFar = 1.0e6f;
+
+// Smallest r^2 from (xm, ym, zm) to entries k .. k+3; some r^2 < 1 iff the
+// smallest is (all values finite).
+__device__ __forceinline__ float min_r2_4(float xm, float ym, float zm, const float *ex,
+                                          const float *ey, const float *ez)
+{
+    float m = 3.0e38f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const float dx = xm - ex[e];
+        const float dy = ym - ey[e];
+        const float dz = zm - ez[e];
+        m = fminf(m, (dx * dx + dy * dy) + dz * dz);
+    }
+    return m;
+}
+
+// Neighbour offset o in {-1, 0, +1} applied to a coordinate (adding 0 is
+// skipped: v + 0 == v for v > 0).
+__device__ __forceinline__ float frame(float v, int o, float w)
+{
+    return o < 0 ? v - w : (o > 0 ? v + w : v);
+}
+__device__ __forceinline__ float gap(float v, int o, float w)
+{
+    return o < 0 ? -v : (o > 0 ? v - w : 0.0f);
+}
+
+// The rare path: does (xm, ym, zm) overlap any sphere of the 26 neighbour
+// cells?  Reads counts and slots from memory (they do not change during the
+// sub-sweep: no active cell is another's neighbour).
+__device__ bool overlap_from_memory(const Geom3 &g, const float4 *__restrict__ pos,
+                                    const uint32_t *__restrict__ count, int cx, int cy, int cz,
+                                    float xm, float ym, float zm)
+{
+    bool hit = false;
+    for (int q = 0; q < 27 && !hit; ++q) {
+        if (q == 13) continue;
+        const int ox = q % 3 - 1, oy = (q / 3) % 3 - 1, oz = q / 9 - 1;
+        const int nx = ox < 0 ? wrap_dn(cx, g.m[0]) : (ox > 0 ? wrap_up(cx, g.m[0]) : cx);
+        const int ny = oy < 0 ? wrap_dn(cy, g.m[1]) : (oy > 0 ? wrap_up(cy, g.m[1]) : cy);
+        const int nz = oz < 0 ? wrap_dn(cz, g.m[2]) : (oz > 0 ? wrap_up(cz, g.m[2]) : cz);
+        const int nc = (nz * g.m[1] + ny) * g.m[0] + nx;
+        const uint32_t cn = min(count[nc], (uint32_t)kCap);
+        for (uint32_t j = 0; j < cn; ++j) {
+            const float4 v = pos[(size_t)nc * kCap + j];
+            const float dx = xm - frame(v.x, ox, g.w[0]);
+            const float dy = ym - frame(v.y, oy, g.w[1]);
+            const float dz = zm - frame(v.z, oz, g.w[2]);
+            hit |= (dx * dx + dy * dy) + dz * dz < 1.0f;
+        }
+    }
+    return hit;
+}
+
+__global__ void __launch_bounds__(kSubBlock)
+k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
+            const uint32_t *__restrict__ count, uint32_t *__restrict__ tag,
+            unsigned long long *__restrict__ cnt, int set, int ntile, int per)
+{
+    __shared__ float lx[kNbrList][kSubBlock];   // entry k of lane l at [k][l]:
+    __shared__ float ly[kNbrList][kSubBlock];   // the 64 lanes of a wave read
+    __shared__ float lz[kNbrList][kSubBlock];   // 64 consecutive words
+    const int tile = xcd_tile(per);
+    const int lane = threadIdx.x;
+    const int a = tile * kSubBlock + lane;
+    unsigned n_trials = 0, n_acc = 0;
+    const bool live = tile < ntile && a < g.active;
+    const unsigned long long s = ctl->sweep_at[par];
+    const uint32_t k0 = ctl->key0, k1 = ctl->key1;
+    const float delta = ctl->delta;
+    const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
+    int Q = set;
+    if (Q < 0) Q = (int)((ctl->draw_at[par].order >> (4 * (-1 - set))) & 0xFu);
+    const int hx = g.m[0] >> 1, hy = g.m[1] >> 1;
+    const int aa = live ? a : 0;
+    const int ix = aa % hx, iy = (aa / hx) % hy, iz = aa / (hx * hy);
+    const int cx = 2 * ix + (Q & 1), cy = 2 * iy + ((Q >> 1) & 1), cz = 2 * iz + (Q >> 2);
+    const int X[3] = {wrap_dn(cx, g.m[0]), cx, wrap_up(cx, g.m[0])};
+    const int Y[3] = {wrap_dn(cy, g.m[1]), cy, wrap_up(cy, g.m[1])};
+    const int Z[3] = {wrap_dn(cz, g.m[2]), cz, wrap_up(cz, g.m[2])};
+    const int c = (cz * g.m[1] + cy) * g.m[0] + cx;
+    const size_t b0 = (size_t)c * kCap;
+
+    // 1. counts of the 3x3x3 block (q = 9 (oz+1) + 3 (oy+1) + (ox+1)) and
+    // the own slots, all in flight together
+    uint32_t nn[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q)
+        nn[q] = live ? count[(Z[q / 9] * g.m[1] + Y[(q / 3) % 3]) * g.m[0] + X[q % 3]] : 0u;
+    float px[kCap], py[kCap], pz[kCap];
+    uint32_t tg[kCap];
+#pragma unroll
+    for (int q = 0; q < kCap; ++q) {
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (live) v = pos[b0 + (size_t)q];
+        px[q] = v.x;
+        py[q] = v.y;
+        pz[q] = v.z;
+        tg[q] = 0u;
+    }
+    const bool has_tag = tag != nullptr;
+    if (has_tag && live) {
+#pragma unroll
+        for (int q = 0; q < kCap; ++q) tg[q] = tag[b0 + (size_t)q];
+    }
+    uint4 Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle, k0, k1);
+    uint4 W = make_uint4(0, 0, 0, 0);
+    if (g.n_moves > 0) W = philox((uint32_t)c, s_lo, s_hi, 0u, k0, k1);
+    bool bad = false;
+    uint32_t nmax = 0;
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+        bad |= nn[q] > (uint32_t)kCap;
+        if (q != 13) nmax = max(nmax, nn[q]);
+    }
+    int n = (int)nn[13];
+    if (bad) {
+        atomicOr(&ctl->errword, kErrCapacity);
+        n = 0;
+    }
+    if (n == 0) nmax = 0;
+
+    // 2. neighbours, slot by slot; K counts every reachable one, the first
+    // kNbrList go to the LDS column
+    int K = 0;
+    for (int i = 0; i < kCap; ++i) {
+        if (__ballot(nmax > (uint32_t)i) == 0ull) break;
+        float4 v[27];
+#pragma unroll
+        for (int q = 0; q < 27; ++q) {
+            v[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (q != 13 && nmax > (uint32_t)i && nn[q] > (uint32_t)i)
+                v[q] = pos[(size_t)((Z[q / 9] * g.m[1] + Y[(q / 3) % 3]) * g.m[0] + X[q % 3]) * kCap +
+                           (size_t)i];
+        }
+#pragma unroll
+        for (int q = 0; q < 27; ++q) {
+            if (q == 13) continue;
+            const int ox = q % 3 - 1, oy = (q / 3) % 3 - 1, oz = q / 9 - 1;
+            const float qx = frame(v[q].x, ox, g.w[0]);
+            const float qy = frame(v[q].y, oy, g.w[1]);
+            const float qz = frame(v[q].z, oz, g.w[2]);
+            const float gx = gap(qx, ox, g.w[0]);
+            const float gy = gap(qy, oy, g.w[1]);
+            const float gz = gap(qz, oz, g.w[2]);
+            const bool take = nmax > (uint32_t)i && nn[q] > (uint32_t)i &&
+                              (gx * gx + gy * gy) + gz * gz < kReach2;
+            if (take && K < kNbrList) {
+                lx[K][lane] = qx;
+                ly[K][lane] = qy;
+                lz[K][lane] = qz;
+            }
+            K += take ? 1 : 0;
+        }
+    }
+    const int KL = K < kNbrList ? K : kNbrList;
+    // entries up to the wave's largest count in groups of four: far spheres
+    // past each lane's own count
+    int KLw = KL;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) KLw = max(KLw, __shfl_xor(KLw, o, 64));
+    KLw = (KLw + 3) & ~3;
+    for (int k = KL; k < KLw; ++k) {
+        lx[k][lane] = kFar;
+        ly[k][lane] = kFar;
+        lz[k][lane] = kFar;
+    }
+
+    if (n > 0) {
+        // rng.shuffle(c.particles): Fisher-Yates over the stored list on a
+        // packed permutation (nibble q = source slot of list position q),
+        // applied to the registers once
+        uint32_t P = 0x76543210u;
+        for (int k = 0; k < n - 1; ++k) {
+            if (k > 0 && (k & 3) == 0)
+                Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle + (uint32_t)(k >> 2), k0, k1);
+            const int i = n - 1 - k;
+            P = nib_swap(P, i, (int)bounded(word_of(Wsh, k & 3), (uint32_t)(i + 1)));
+        }
+        if (n > 1) {
+            rperm(px, P);
+            rperm(py, P);
+            rperm(pz, P);
+            if (has_tag) rperm(tg, P);
+        }
+#pragma unroll
+        for (int q = 1; q < kCap; ++q) {
+            px[q] = q < n ? px[q] : kFar;
+            py[q] = q < n ? py[q] : kFar;
+            pz[q] = q < n ? pz[q] : kFar;
+        }
+    }
+    // 3. the column, read once into registers (a lane with n = 0 still reads
+    // its far entries: the loop bounds are the wave's)
+    float rx[kNbrList], ry[kNbrList], rz[kNbrList];
+#pragma unroll
+    for (int k = 0; k < kNbrList; ++k) {
+        rx[k] = k < KLw ? lx[k][lane] : kFar;
+        ry[k] = k < KLw ? ly[k][lane] : kFar;
+        rz[k] = k < KLw ? lz[k][lane] : kFar;
+    }
+    if (n > 0) {
+        const bool spill = K > kNbrList;
+        for (int t = 0; t < g.n_moves; ++t) {
+            if (t > 0 && (t & 1) == 0) W = philox((uint32_t)c, s_lo, s_hi, (uint32_t)(t >> 1), k0, k1);
+            float dx, dy, dz;
+            displacement3((t & 1) ? W.z : W.x, (t & 1) ? W.w : W.y, delta, dx, dy, dz);
+            const float xm = px[0] + dx;
+            const float ym = py[0] + dy;
+            const float zm = pz[0] + dz;
+            bool ok = (xm > 0.0f) & (xm <= g.w[0]) & (ym > 0.0f) & (ym <= g.w[1]) &
+                      (zm > 0.0f) & (zm <= g.w[2]);
+#pragma unroll
+            for (int q = 1; q < kCap; ++q) {
+                const float ddx = xm - px[q];
+                const float ddy = ym - py[q];
+                const float ddz = zm - pz[q];
+                ok = ok & !((ddx * ddx + ddy * ddy) + ddz * ddz < 1.0f);
+            }
+#pragma unroll
+            for (int k = 0; k < kNbrList; k += 4)
+                if (k < KLw) ok = ok & !(min_r2_4(xm, ym, zm, rx + k, ry + k, rz + k) < 1.0f);
+            if (spill && ok) ok = !overlap_from_memory(g, pos, count, cx, cy, cz, xm, ym, zm);
+            px[0] = ok ? xm : px[0];
+            py[0] = ok ? ym : py[0];
+            pz[0] = ok ? zm : pz[0];
+            n_acc += ok ? 1u : 0u;
+            rrot(px, n);   // the identity for n = 1
+            rrot(py, n);
+            rrot(pz, n);
+            if (has_tag) rrot(tg, n);
+        }
+        n_trials = (unsigned)g.n_moves;
+        // register entry q now holds list position (q + n_M) mod n
+        const int r0 = g.n_moves % n;
+#pragma unroll
+        for (int q = 0; q < kCap; ++q) {
+            if (q < n) {
+                int o = q + r0;
+                o = o >= n ? o - n : o;
+                pos[b0 + (size_t)o] = make_float4(px[q], py[q], pz[q], 0.0f);
+                if (has_tag && n > 1) tag[b0 + (size_t)o] = tg[q];
+            }
+        }
+    }
+    // this workgroup's partials (one wave; the same entry in every launch)
+    const unsigned bt = wave_sum_u32(n_trials);
+    const unsigned ba = wave_sum_u32(n_acc);
+    if (lane == 0 && tile < ntile && bt) {
+        cnt[2 * tile] += (unsigned long long)bt;
+        cnt[2 * tile + 1] += (unsigned long long)ba;
+    }
+}
+
+// Add the partials into the control block and clear them (one workgroup).
+__global__ void __launch_bounds__(256) k_fold3(Ctl3 *ctl, unsigned long long *cnt, int groups)
+{
+    __shared__ unsigned long long sh[8];
+    unsigned long long tr = 0, ac = 0;
+    for (int i = threadIdx.x; i < groups; i += blockDim.x) {
+        tr += cnt[2 * i];
+        ac += cnt[2 * i + 1];
+        cnt[2 * i] = 0ull;
+        cnt[2 * i + 1] = 0ull;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        tr += __shfl_xor(tr, o, 64);
+        ac += __shfl_xor(ac, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[wave] = tr;
+        sh[4 + wave] = ac;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctl->trials += sh[0] + sh[1] + sh[2] + sh[3];
+        ctl->accepts += sh[4] + sh[5] + sh[6] + sh[7];
+    }
+}
+
+// ----------------------------------------------------------------- rebin
+// Alg. 4 in d = 3 on the slot layout: new cell c holds the stayers of old c
+// followed by the spheres of the old neighbour in direction f that move in,
+// both in old slot order.  One thread per cell; the counts and all 8 slots
+// of both cells are loaded in one round trip.  The first workgroup writes
+// the sweep slot of the half it writes: the next sweep and its draws when
+// the shift is the sweep's own, else a copy of the current slot.
+struct Rebin3Args {
+    Geom3 g;
+    Ctl3 *ctl;
+    const float4 *pos;
+    const uint32_t *count;
+    const uint32_t *tag;
+    float4 *pos_out;
+    uint32_t *count_out;
+    uint32_t *tag_out;
+    int par;
+    int f;        // >= 0 explicit; < 0 the sweep's own
+    float d;
+    int ntile;
+    int per;
+};
+
+__global__ void __launch_bounds__(kTile) k_rebin3(Rebin3Args a)
+{
+    const int tile = xcd_tile(a.per);
+    if (tile >= a.ntile) return;
+    const Geom3 &g = a.g;
+    Ctl3 *ctl = a.ctl;
+    int f = a.f;
+    float d = a.d;
+    if (f < 0) {
+        f = ctl->draw_at[a.par].f;
+        d = ctl->draw_at[a.par].d;
+    }
+    const int ax = f >> 1;
+    const bool minus = (f & 1) == 0;   // +x, +y, +z: t = v - d, leavers come from cell + 1
+    const float w = g.w[ax];
+    const float sw = minus ? w : -w;
+    const int c = tile * kTile + (int)threadIdx.x;
+    if (c < g.C) {
+        const int cx = c % g.m[0], cy = (c / g.m[0]) % g.m[1], cz = c / (g.m[0] * g.m[1]);
+        int n3[3] = {cx, cy, cz};
+        const int cc = ax == 0 ? cx : (ax == 1 ? cy : cz);
+        const int mm = g.m[ax];
+        const int nv = minus ? (cc == mm - 1 ? 0 : cc + 1) : (cc == 0 ? mm - 1 : cc - 1);
+        if (ax == 0) n3[0] = nv;
+        else if (ax == 1) n3[1] = nv;
+        else n3[2] = nv;
+        const int nc = (n3[2] * g.m[1] + n3[1]) * g.m[0] + n3[0];
+        const size_t ob = (size_t)c * kCap, nbb = (size_t)nc * kCap;
+        int no = (int)a.count[c];
+        int nn = (int)a.count[nc];
+        float4 own[kCap], nb[kCap];
+#pragma unroll
+        for (int i = 0; i < kCap; ++i) {
+            own[i] = a.pos[ob + (size_t)i];
+            nb[i] = a.pos[nbb + (size_t)i];
+        }
+        if (no > kCap || nn > kCap) {
+            atomicOr(&ctl->errword, kErrCapacity);
+            no = min(no, kCap);
+            nn = min(nn, kCap);
+        }
+        unsigned stay = 0, leave = 0;
+        float to[kCap], tn[kCap];
+#pragma unroll
+        for (int i = 0; i < kCap; ++i) {
+            const float vo = ax == 0 ? own[i].x : (ax == 1 ? own[i].y : own[i].z);
+            const float vn = ax == 0 ? nb[i].x : (ax == 1 ? nb[i].y : nb[i].z);
+            to[i] = minus ? vo - d : vo + d;
+            tn[i] = minus ? vn - d : vn + d;
+            if (i < no && to[i] > 0.0f && to[i] <= w) stay |= 1u << i;
+            if (i < nn && !(tn[i] > 0.0f && tn[i] <= w)) leave |= 1u << i;
+        }
+        const unsigned k = (unsigned)(__popc(stay) + __popc(leave));
+        if (k > (unsigned)kCap) atomicOr(&ctl->errword, kErrCapacity);
+        a.count_out[c] = k > (unsigned)kCap ? (unsigned)kCap : k;
+        const bool has_tag = a.tag != nullptr;
+        size_t o = ob;
+        const size_t oe = ob + (size_t)kCap;
+#pragma unroll
+        for (int i = 0; i < kCap; ++i) {
+            if ((stay & (1u << i)) && o < oe) {
+                float4 v = own[i];
+                if (ax == 0) v.x = to[i];
+                else if (ax == 1) v.y = to[i];
+                else v.z = to[i];
+                v.w = 0.0f;
+                a.pos_out[o] = v;
+                if (has_tag) a.tag_out[o] = a.tag[ob + (size_t)i];
+            }
+            o += (stay >> i) & 1u;
+        }
+#pragma unroll
+        for (int i = 0; i < kCap; ++i) {
+            if ((leave & (1u << i)) && o < oe) {
+                float4 v = nb[i];
+                const float t2 = tn[i] + sw;
+                if (ax == 0) v.x = t2;
+                else if (ax == 1) v.y = t2;
+                else v.z = t2;
+                v.w = 0.0f;
+                a.pos_out[o] = v;
+                if (has_tag) a.tag_out[o] = a.tag[nbb + (size_t)i];
+            }
+            o += (leave >> i) & 1u;
+        }
+    }
+    if (tile == 0 && threadIdx.x == 0) {
+        const unsigned long long s = ctl->sweep_at[a.par];
+        if (a.f < 0) {
+            store_draws3(ctl, a.par ^ 1, s + 1ull, g);
+        } else {
+            ctl->sweep_at[a.par ^ 1] = s;
+            ctl->draw_at[a.par ^ 1] = ctl->draw_at[a.par];
+        }
+    }
+}
+
+// ---------------------------------------------------------- control block
+__global__ void __launch_bounds__(256)
+k_ctl_reset3(Geom3 g, Ctl3 *ctl, unsigned long long sweep, unsigned int key0, unsigned int key1,
+             float delta)
+{
+    for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) ctl->hist[i] = 0ull;
+    if (threadIdx.x == 0) {
+        ctl->trials = ctl->accepts = 0ull;
+        ctl->key0 = key0;
+        ctl->key1 = key1;
+        ctl->delta = delta;
+        ctl->errword = 0u;
+        ctl->hist_samples = 0ull;
+        for (int k = 0; k < 4; ++k) ctl->fit[k] = 0.0;
+        ctl->overlaps = 0;
+        store_draws3(ctl, 0, sweep, g);
+        ctl->sweep_at[1] = ctl->sweep_at[0];
+        ctl->draw_at[1] = ctl->draw_at[0];
+        ctl->draw_at[0].pad = ctl->draw_at[1].pad = 0u;
+    }
+}
+
+__global__ void k_set_delta3(Ctl3 *ctl, float delta) { ctl->delta = delta; }
+
+// ------------------------------------------------------ pair histogram
+// Ordered pairs (k, j != k) with r^2 in k's frame, translations o w with
+// o in [-R, R] per axis (R = 2 where w < 1.02), binned on
+// E_b = (float)((1 + b 1e-4)^2).  One thread per cell.
+__global__ void __launch_bounds__(kTile)
+k_pair_hist3(Geom3 g, Ctl3 *ctl, const float4 *__restrict__ pos,
+             const uint32_t *__restrict__ count, int ntile, int per)
+{
+    __shared__ float E[kHistBins + 1];
+    __shared__ unsigned H[kHistBins];
+    for (int i = threadIdx.x; i <= kHistBins; i += blockDim.x) {
+        const double rr = 1.0 + (double)i * 1e-4;
+        E[i] = (float)(rr * rr);
+        if (i < kHistBins) H[i] = 0;
+    }
+    __syncthreads();
+    const int tile = xcd_tile(per);
+    const double rmax = 1.0 + kHistBins * 1e-4;
+    int Rr[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) Rr[q] = (double)g.w[q] >= rmax ? 1 : 2;
+    const int c = tile * kTile + (int)threadIdx.x;
+    if (tile < ntile && c < g.C) {
+        const int cx = c % g.m[0], cy = (c / g.m[0]) % g.m[1], cz = c / (g.m[0] * g.m[1]);
+        const float e0 = E[0], eN = E[kHistBins];
+        const uint32_t nk = min(count[c], (uint32_t)kCap);
+        for (uint32_t k = 0; k < nk; ++k) {
+            const float4 pk = pos[(size_t)c * kCap + k];
+            for (int oz = -Rr[2]; oz <= Rr[2]; ++oz) {
+                const int ncz = (cz + oz + 2 * g.m[2]) % g.m[2];
+                const float tz = (float)oz * g.w[2];
+                for (int oy = -Rr[1]; oy <= Rr[1]; ++oy) {
+                    const int ncy = (cy + oy + 2 * g.m[1]) % g.m[1];
+                    const float ty = (float)oy * g.w[1];
+                    for (int ox = -Rr[0]; ox <= Rr[0]; ++ox) {
+                        const int ncx = (cx + ox + 2 * g.m[0]) % g.m[0];
+                        const float tx = (float)ox * g.w[0];
+                        const int nc = (ncz * g.m[1] + ncy) * g.m[0] + ncx;
+                        for (uint32_t j = 0, je = min(count[nc], (uint32_t)kCap); j < je; ++j) {
+                            if (nc == c && j == k) continue;
+                            const float4 v = pos[(size_t)nc * kCap + j];
+                            const float ddx = pk.x - (v.x + tx);
+                            const float ddy = pk.y - (v.y + ty);
+                            const float ddz = pk.z - (v.z + tz);
+                            const float r2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
+                            if (r2 < e0 || r2 >= eN) continue;
+                            int lo = 0, hi = kHistBins;
+                            while (hi - lo > 1) {
+                                const int mid = (lo + hi) >> 1;
+                                if (r2 >= E[mid]) lo = mid;
+                                else hi = mid;
+                            }
+                            atomicAdd(&H[lo], 1u);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (tile < ntile) {
+        for (int i = threadIdx.x; i < kHistBins; i += blockDim.x)
+            if (H[i]) atomicAdd(&ctl->hist[i], (unsigned long long)H[i]);
+        if (tile == 0 && threadIdx.x == 0) atomicAdd(&ctl->hist_samples, 1ull);
+    }
+}
+
+__global__ void k_hist_reset3(Ctl3 *ctl)
+{
+    for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) ctl->hist[i] = 0ull;
+    if (threadIdx.x == 0) ctl->hist_samples = 0ull;
+}
+
+// ------------------------------------------------------ contact fit (FP64)
+// g(R_i) = n_i / (S N rho 4 pi R_i^2 dr) at the volume-weighted shell radii
+// R_i = 3/4 (r1^4 - r0^4) / (r1^3 - r0^3); unweighted least squares of a
+// degree-5 polynomial in (R - 1)/0.02 by Householder QR; the contact
+// theorem in 3D, beta P = rho (1 + 2 pi/3 rho g(sigma+)).
+__global__ void __launch_bounds__(256) k_pressure_fit3(Geom3 g, Ctl3 *ctl)
+{
+    constexpr int NB = kHistBins, NC = 6;
+    __shared__ double A[NB][NC];
+    __shared__ double y[NB];
+    __shared__ double v[NB];
+    const unsigned long long S = ctl->hist_samples;
+    const double vol = ((double)g.m[0] * (double)g.w[0]) * ((double)g.m[1] * (double)g.w[1]) *
+                       ((double)g.m[2] * (double)g.w[2]);
+    const double rho = (double)g.N / vol;
+    const double dr = 1e-4, cfit = 0.02, pi = 3.14159265358979323846;
+    for (int i = threadIdx.x; i < NB; i += blockDim.x) {
+        const double r0 = 1.0 + (double)i * dr;
+        const double r1 = 1.0 + (double)(i + 1) * dr;
+        const double r02 = r0 * r0, r12 = r1 * r1;
+        const double Ri = 0.75 * (r12 * r12 - r02 * r02) / (r12 * r1 - r02 * r0);
+        const double n = (double)ctl->hist[i] / (double)(S ? S : 1ull);
+        y[i] = n / ((double)g.N * rho * 4.0 * pi * Ri * Ri * dr);
+        const double x = (Ri - 1.0) / cfit;
+        double xp = 1.0;
+        for (int k = 0; k < NC; ++k) {
+            A[i][k] = xp;
+            xp *= x;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    if (S == 0) {
+        ctl->fit[3] = -1.0;
+        return;
+    }
+    for (int k = 0; k < NC; ++k) {
+        double norm2 = 0.0;
+        for (int i = k; i < NB; ++i) norm2 += A[i][k] * A[i][k];
+        const double norm = sqrt(norm2);
+        const double alpha = A[k][k] > 0.0 ? -norm : norm;
+        double vn2 = 0.0;
+        for (int i = k; i < NB; ++i) {
+            v[i] = A[i][k] - (i == k ? alpha : 0.0);
+            vn2 += v[i] * v[i];
+        }
+        if (vn2 == 0.0) continue;
+        for (int j = k; j < NC; ++j) {
+            double dot = 0.0;
+            for (int i = k; i < NB; ++i) dot += v[i] * A[i][j];
+            const double sc = 2.0 * dot / vn2;
+            for (int i = k; i < NB; ++i) A[i][j] -= sc * v[i];
+        }
+        double dot = 0.0;
+        for (int i = k; i < NB; ++i) dot += v[i] * y[i];
+        const double sc = 2.0 * dot / vn2;
+        for (int i = k; i < NB; ++i) y[i] -= sc * v[i];
+    }
+    double coef[NC];
+    for (int k = NC - 1; k >= 0; --k) {
+        double acc = y[k];
+        for (int j = k + 1; j < NC; ++j) acc -= A[k][j] * coef[j];
+        coef[k] = acc / A[k][k];
+    }
+    ctl->fit[0] = rho * (1.0 + (2.0 * pi / 3.0) * rho * coef[0]);
+    ctl->fit[1] = coef[0];
+    ctl->fit[2] = rho;
+    ctl->fit[3] = 1.0;
+}
+
+// ------------------------------------------------------ overlap count
+// Ordered pairs with r^2 < 1 - 2^-16 in either sphere's frame (the trial
+// moves test r^2 < 1 in the mover's frame; seen from the partner the same
+// pair may round a few ulp below 1).
+constexpr float kOverlapR2 = 1.0f - 0x1p-16f;
+
+__global__ void __launch_bounds__(kTile)
+k_count_overlaps3(Geom3 g, Ctl3 *ctl, const float4 *__restrict__ pos,
+                  const uint32_t *__restrict__ count, int ntile, int per)
+{
+    __shared__ unsigned red[4];
+    const int tile = xcd_tile(per);
+    const int c = tile * kTile + (int)threadIdx.x;
+    unsigned bad = 0;
+    if (tile < ntile && c < g.C) {
+        const int cx = c % g.m[0], cy = (c / g.m[0]) % g.m[1], cz = c / (g.m[0] * g.m[1]);
+        const uint32_t nk = min(count[c], (uint32_t)kCap);
+        for (uint32_t k = 0; k < nk; ++k) {
+            const float4 pk = pos[(size_t)c * kCap + k];
+            for (int q = 0; q < 27; ++q) {
+                const int ox = q % 3 - 1, oy = (q / 3) % 3 - 1, oz = q / 9 - 1;
+                const int nx = (cx + ox + g.m[0]) % g.m[0];
+                const int ny = (cy + oy + g.m[1]) % g.m[1];
+                const int nz = (cz + oz + g.m[2]) % g.m[2];
+                const int nc = (nz * g.m[1] + ny) * g.m[0] + nx;
+                for (uint32_t j = 0, je = min(count[nc], (uint32_t)kCap); j < je; ++j) {
+                    if (nc == c && j == k) continue;
+                    const float4 v = pos[(size_t)nc * kCap + j];
+                    const float ddx = pk.x - frame(v.x, ox, g.w[0]);
+                    const float ddy = pk.y - frame(v.y, oy, g.w[1]);
+                    const float ddz = pk.z - frame(v.z, oz, g.w[2]);
+                    bad += ((ddx * ddx + ddy * ddy) + ddz * ddz < kOverlapR2) ? 1u : 0u;
+                }
+            }
+        }
+    }
+    bad = wave_sum_u32(bad);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = bad;
+    __syncthreads();
+    if (threadIdx.x == 0 && tile < ntile) {
+        const unsigned tot = red[0] + red[1] + red[2] + red[3];
+        if (tot) atomicAdd((unsigned long long *)&ctl->overlaps, (unsigned long long)tot);
+    }
+}
+
+__global__ void k_overlaps_reset3(Ctl3 *ctl) { ctl->overlaps = 0; }
+
+}  // namespace
+
+// ---------------------------------------------------------------- launches
+hipError_t launch_subsweep3(const Geom3 &g, Ctl3 *ctl, int par, float4 *pos,
+                            const uint32_t *count, uint32_t *tag, unsigned long long *cnt,
+                            int set, hipStream_t st)
+{
+    const int ntile = subsweep_groups(g);
+    const int grid = xcd_groups(ntile);
+    hipLaunchKernelGGL(k_subsweep3, dim3(grid), dim3(kSubBlock), 0, st, g, ctl, par, pos, count,
+                       tag, cnt, set, ntile, grid / 8);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold3(const Geom3 &g, Ctl3 *ctl, unsigned long long *cnt, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fold3, dim3(1), dim3(256), 0, st, ctl, cnt, subsweep_groups(g));
+    return hipGetLastError();
+}
+
+hipError_t launch_rebin3(const Geom3 &g, Ctl3 *ctl, int par, const float4 *pos,
+                         const uint32_t *count, const uint32_t *tag, float4 *pos_out,
+                         uint32_t *count_out, uint32_t *tag_out, int f, float d, hipStream_t st)
+{
+    Rebin3Args a;
+    a.g = g;
+    a.ctl = ctl;
+    a.pos = pos;
+    a.count = count;
+    a.tag = tag;
+    a.pos_out = pos_out;
+    a.count_out = count_out;
+    a.tag_out = tag_out;
+    a.par = par;
+    a.f = f;
+    a.d = d;
+    a.ntile = (g.C + kTile - 1) / kTile;
+    const int grid = xcd_groups(a.ntile);
+    a.per = grid / 8;
+    hipLaunchKernelGGL(k_rebin3, dim3(grid), dim3(kTile), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_reset3(const Geom3 &g, Ctl3 *ctl, unsigned long long sweep,
+                             unsigned int key0, unsigned int key1, float delta, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ctl_reset3, dim3(1), dim3(256), 0, st, g, ctl, sweep, key0, key1, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_delta3(Ctl3 *ctl, float delta, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_delta3, dim3(1), dim3(1), 0, st, ctl, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_hist3(const Geom3 &g, Ctl3 *ctl, const float4 *pos, const uint32_t *count,
+                             int reset, hipStream_t st)
+{
+    if (reset) hipLaunchKernelGGL(k_hist_reset3, dim3(1), dim3(256), 0, st, ctl);
+    const int ntile = (g.C + kTile - 1) / kTile;
+    const int grid = xcd_groups(ntile);
+    hipLaunchKernelGGL(k_pair_hist3, dim3(grid), dim3(kTile), 0, st, g, ctl, pos, count, ntile,
+                       grid / 8);
+    return hipGetLastError();
+}
+
+hipError_t launch_pressure_fit3(const Geom3 &g, Ctl3 *ctl, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pressure_fit3, dim3(1), dim3(256), 0, st, g, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_overlaps3(const Geom3 &g, Ctl3 *ctl, const float4 *pos,
+                                  const uint32_t *count, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_overlaps_reset3, dim3(1), dim3(1), 0, st, ctl);
+    const int ntile = (g.C + kTile - 1) / kTile;
+    const int grid = xcd_groups(ntile);
+    hipLaunchKernelGGL(k_count_overlaps3, dim3(grid), dim3(kTile), 0, st, g, ctl, pos, count,
+                       ntile, grid / 8);
+    return hipGetLastError();
+}
+
+}  // namespace sph
+}  // namespace mpmc

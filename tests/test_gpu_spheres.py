@@ -1,0 +1,272 @@
+"""Parity of the hard-sphere HIP path (through the C ABI) with the 3D CPU
+oracle: bit-exact cell lists, positions, tags and counters after sub-sweeps,
+shifts and whole sweeps; the contact histogram exactly and the pressure fit
+within FP64 rounding.  Needs an MI355X."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import estimator as E
+from oracle.spheres import SphereOracle
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1211_1646_amd as pkg
+    pkg.load()
+    return pkg
+
+
+def lattice_pair(pkg, n, eta, delta=0.1, n_moves=4, seed=1, replica=0, w_max=0.0):
+    log("  sphere lattice pair n=%s eta=%.3f delta=%.3f n_moves=%d seed=%d"
+        % (n, eta, delta, n_moves, seed))
+    cfg = pkg.SphereConfig(lattice_nx=n[0], lattice_ny=n[1], lattice_nz=n[2], eta=eta,
+                           w_max=w_max, delta=delta, n_moves=n_moves, seed=seed,
+                           replica=replica, flags=pkg.FLAG_TAG)
+    G = pkg.HardSphereSystem(cfg)
+    O = SphereOracle.lattice(*n, eta, w_max=w_max, delta=delta, n_moves=n_moves, seed=seed,
+                             replica=replica)
+    return G, O
+
+
+def grid_pair(pkg, m, w, xyz, start, tags, sweep=0, delta=0.1, n_moves=4, seed=1, replica=0):
+    log("  sphere grid pair m=%s N=%d delta=%.3f n_moves=%d" % (m, len(xyz), delta, n_moves))
+    cfg = pkg.SphereConfig(cells_x=m[0], cells_y=m[1], cells_z=m[2], cell_w_x=float(w[0]),
+                           cell_w_y=float(w[1]), cell_w_z=float(w[2]), n_particles=len(xyz),
+                           delta=delta, n_moves=n_moves, seed=seed, replica=replica,
+                           flags=pkg.FLAG_TAG)
+    G = pkg.HardSphereSystem(cfg)
+    G.set_state(xyz, start, sweep, tags)
+    O = SphereOracle.grid(m, w, len(xyz), delta=delta, n_moves=n_moves, seed=seed,
+                          replica=replica)
+    O.set_state(xyz, start, tags, sweep)
+    return G, O
+
+
+def assert_same(G, O, what=""):
+    gx, gs, gsw, gt = G.get_state(with_tags=True)
+    ox, os_, ot, osw = O.get_state()
+    assert gsw == osw, (what, gsw, osw)
+    assert np.array_equal(gs, os_), "cell lists differ " + what
+    assert np.array_equal(gt, ot), "tags differ " + what
+    bad = np.nonzero(gx.view(np.uint32) != ox.view(np.uint32))[0]
+    assert bad.size == 0, "positions differ %s at %s" % (what, bad[:5])
+    assert G.counters() == tuple(O.counters()), (what, G.counters(), O.counters())
+
+
+def test_lattice_start_matches(gpu):
+    for n, eta in [((10, 10, 10), 0.3), ((8, 10, 12), 0.45), ((6, 6, 6), math.pi / 6)]:
+        G, O = lattice_pair(gpu, n, eta)
+        assert_same(G, O, "start %s" % (n,))
+        assert G.count_overlaps() == 0
+        G.close()
+
+
+@pytest.mark.parametrize("eta,n_moves", [(0.3, 4), (0.45, 7), (0.5, 1), (0.45, 0)])
+def test_each_subsweep_and_shift(gpu, eta, n_moves):
+    G, O = lattice_pair(gpu, (12, 10, 14), eta, delta=0.15, n_moves=n_moves, seed=7)
+    for Q in (5, 0, 3, 6, 1, 7, 2, 4):
+        G.subsweep(Q)
+        O.subsweep(Q)
+        assert_same(G, O, "after set %d" % Q)
+    for f in range(6):
+        d = np.float32(0.5 * O.w[f // 2] * (0.1 + 0.15 * f))
+        G.shift(f, float(d))
+        O.shift(f, d)
+        assert_same(G, O, "after shift f=%d" % f)
+        G.subsweep(f)
+        O.subsweep(f)
+        assert_same(G, O, "after set %d following shift %d" % (f, f))
+    G.close()
+
+
+def test_shift_by_zero_and_half_a_cell(gpu):
+    G, O = lattice_pair(gpu, (10, 10, 10), 0.4, seed=3)
+    G.sweep(3)
+    O.sweep(3)
+    for f, frac in [(0, 0.0), (1, 0.5), (4, 0.5), (5, 0.0), (2, 0.5)]:
+        d = np.float32(frac * 0.5 * O.w[f // 2])
+        G.shift(f, float(d))
+        O.shift(f, d)
+        assert_same(G, O, "shift f=%d d=%r" % (f, d))
+    G.close()
+
+
+@pytest.mark.parametrize("n,eta,delta,n_moves,seed,sweeps", [
+    ((10, 10, 10), 0.3, 0.1, 4, 1, 5),
+    ((12, 8, 16), 0.45, 0.12, 4, 2, 37),     # 37 = two captured graphs + 5 direct sweeps
+    ((14, 14, 14), 0.5, 0.05, 9, 3, 20),
+    ((16, 16, 16), 0.2, 0.3, 3, 4, 17),
+    ((10, 10, 10), 0.1, 0.4, 1, 5, 40)])
+def test_sweeps_match(gpu, n, eta, delta, n_moves, seed, sweeps):
+    G, O = lattice_pair(gpu, n, eta, delta=delta, n_moves=n_moves, seed=seed)
+    G.sweep(sweeps)
+    O.sweep(sweeps)
+    assert_same(G, O, "after %d sweeps" % sweeps)
+    assert G.count_overlaps() == 0
+    G.close()
+
+
+def test_set_state_then_continue(gpu):
+    G0, O = lattice_pair(gpu, (10, 12, 10), 0.45, delta=0.1, n_moves=4, seed=11)
+    G0.close()
+    O.sweep(13)
+    xyz, start, tags, sweep = O.get_state()
+    G, O2 = grid_pair(gpu, O.m, O.w, xyz, start, tags, sweep, delta=0.1, n_moves=4, seed=11)
+    assert_same(G, O2, "after set_state")
+    G.sweep(19)
+    O2.sweep(19)
+    assert_same(G, O2, "19 sweeps after set_state")
+    G.close()
+
+
+def test_other_keys_give_other_chains(gpu):
+    G1, O1 = lattice_pair(gpu, (10, 10, 10), 0.4, seed=5, replica=0)
+    G2, O2 = lattice_pair(gpu, (10, 10, 10), 0.4, seed=5, replica=1)
+    for G, O in ((G1, O1), (G2, O2)):
+        G.sweep(4)
+        O.sweep(4)
+        assert_same(G, O, "keyed")
+    assert not np.array_equal(G1.get_state()[0], G2.get_state()[0])
+    G1.close()
+    G2.close()
+
+
+def fcc_state(cells_fcc, eta, offset=0.137):
+    """A face-centred cubic crystal (4 spheres per cubic unit cell) at packing
+    fraction eta in a periodic box, in cells of the smallest even count per
+    axis narrower than 2/sqrt(3), as compact lists with lattice tags."""
+    rho = 6.0 * eta / math.pi
+    a = (4.0 / rho) ** (1.0 / 3.0)
+    L = cells_fcc * a
+    limit = 2.0 / math.sqrt(3.0) * (1.0 - 1e-5)
+    m = int(math.ceil(L / limit))
+    m += m & 1
+    while L / m >= limit:
+        m += 2
+    w = np.float32(L / m)
+    basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+    g = np.array([(i, j, k) for k in range(cells_fcc) for j in range(cells_fcc)
+                  for i in range(cells_fcc)], np.float64)
+    pts = ((g[:, None, :] + basis[None, :, :]).reshape(-1, 3) + offset) * a
+    pts = np.mod(pts, m * np.float64(w))
+    cell3 = np.clip(np.ceil(pts / np.float64(w)).astype(np.int64) - 1, 0, m - 1)
+    loc = (pts - cell3 * np.float64(w)).astype(np.float32)
+    assert (loc > 0).all() and (loc <= w).all()
+    cell = (cell3[:, 2] * m + cell3[:, 1]) * m + cell3[:, 0]
+    order = np.argsort(cell, kind="stable")
+    counts = np.bincount(cell, minlength=m ** 3)
+    start = np.concatenate([[0], np.cumsum(counts)]).astype(np.uint32)
+    return (m, m, m), np.float32([w, w, w]), loc[order], start, order.astype(np.uint32)
+
+
+def reachable_counts(m, w, xyz, start):
+    """Per cell, the spheres of its 26 neighbours whose squared distance to
+    the cell's box is below 1.0001 (the sub-sweep's LDS list length)."""
+    w = float(w[0])
+    M = m[0]
+    counts = np.diff(start.astype(np.int64))
+    out = np.zeros(M ** 3, np.int64)
+    cell_of = np.repeat(np.arange(M ** 3), counts)
+    cz, cy, cx = cell_of // (M * M), (cell_of // M) % M, cell_of % M
+    gpos = np.stack([cx * w + xyz[:, 0], cy * w + xyz[:, 1], cz * w + xyz[:, 2]], 1)
+    Lb = M * w
+    for c in range(M ** 3):
+        z, y, x = c // (M * M), (c // M) % M, c % M
+        lo = np.array([x * w, y * w, z * w])
+        d = gpos - lo
+        d -= Lb * np.round((d - w / 2) / Lb)          # nearest image around the box centre
+        gap = np.maximum(0.0, np.maximum(-d, d - w))
+        near = ((gap ** 2).sum(1) < 1.0001) & (cell_of != c)
+        out[c] = near.sum()
+    return out
+
+
+def test_dense_crystal_exercises_the_spill_path(gpu):
+    """An FCC crystal at eta = 0.70 puts more reachable neighbours around
+    many cells than the kernel's LDS list holds; those lanes also test every
+    neighbour straight from memory, and the chain must still be bit-exact."""
+    m, w, xyz, start, tags = fcc_state(8, 0.70)
+    K = reachable_counts(m, w, xyz, start)
+    log("  reachable neighbours per cell: max %d, cells above 32: %d" % (K.max(), (K > 32).sum()))
+    assert (K > 32).sum() > 10
+    G, O = grid_pair(gpu, m, w, xyz, start, tags, 0, delta=0.03, n_moves=6, seed=9)
+    G.sweep(3)
+    O.sweep(3)
+    assert_same(G, O, "dense crystal, 3 sweeps")
+    assert G.counters()[1] > 0
+    G.sweep(16)
+    O.sweep(16)
+    assert_same(G, O, "dense crystal, 19 sweeps")
+    G.close()
+
+
+def test_pair_histogram_and_pressure(gpu):
+    G, O = lattice_pair(gpu, (12, 12, 12), 0.4, delta=0.15, n_moves=4, seed=13)
+    hist = np.zeros(200, np.float64)
+    for k in range(6):
+        G.sweep(10)
+        O.sweep(10)
+        G.pair_histogram(reset=(k == 0))
+        hist += O.pair_histogram()
+    p, g0, gh, ns = G.pressure()
+    assert ns == 6
+    assert np.array_equal(gh, hist.astype(np.uint64))
+    rho = G.density
+    p_ref, g_ref = E.pressure_from_histogram_3d(hist, 6, G.N, rho)
+    log("  P %.6f (oracle %.6f), g %.6f (oracle %.6f)" % (p, p_ref, g0, g_ref))
+    assert abs(g0 - g_ref) <= 1e-9 * abs(g_ref)
+    assert abs(p - p_ref) <= 1e-9 * abs(p_ref)
+    G.close()
+
+
+def test_full_size_one_million_spheres(gpu):
+    """The benchmark configuration (100^3 spheres at eta = 0.45, n_M = 4),
+    compared in full after three sweeps (the oracle takes about half a second
+    per sweep at this size)."""
+    G, O = lattice_pair(gpu, (100, 100, 100), 0.45, delta=0.1, n_moves=4, seed=1)
+    G.sweep(3)
+    O.sweep(3)
+    assert_same(G, O, "1M spheres, 3 sweeps")
+    G.close()
+
+
+def test_argument_errors(gpu):
+    from paper_1211_1646_amd import _lib as L
+    G, _ = lattice_pair(gpu, (10, 10, 10), 0.3)
+    for call in (lambda: G.subsweep(8), lambda: G.subsweep(-1), lambda: G.shift(6, 0.1),
+                 lambda: G.shift(0, 0.6), lambda: G.set_delta(0.6), lambda: G.set_delta(0.0)):
+        with pytest.raises(L.MPMCError) as e:
+            call()
+        assert e.value.status == L.MPMC_EINVAL
+    xyz, start, _ = G.get_state()
+    # two spheres in x-neighbouring cells of one row, moved 0.01 apart
+    counts = np.diff(start.astype(np.int64))
+    M = G.m[0]
+    pair = next(c for c in range(G.C - 1)
+                if c % M != M - 1 and counts[c] >= 1 and counts[c + 1] >= 1)
+    a, b = int(start[pair]), int(start[pair + 1])
+    bad = xyz.copy()
+    bad[a, 0] = G.w[0]
+    bad[b] = (np.float32(0.01), bad[a, 1], bad[a, 2])
+    with pytest.raises(L.MPMCError) as e:
+        G.set_state(bad, start, 0)
+    assert e.value.status == L.MPMC_EOVERLAP
+    bad = xyz.copy()
+    bad[0, 2] = 5.0
+    with pytest.raises(L.MPMCError) as e:
+        G.set_state(bad, start, 0)
+    assert e.value.status == L.MPMC_ESTATE
+    G.close()
