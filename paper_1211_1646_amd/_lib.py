@@ -170,6 +170,7 @@ _SIGNATURES = {
     "mpmc_sphere_pressure": (C.c_int32, [_H, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                          C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "mpmc_sphere_count_overlaps": (C.c_int32, [_H, C.POINTER(C.c_int64)]),
+    "mpmc_sphere_set_launch": (C.c_int32, [_H, C.c_int32]),
     "mpmc_sphere_synchronize": (C.c_int32, [_H]),
     "mpmc_sphere_destroy": (None, [_H]),
     "mpmc_destroy": (None, [_H]),

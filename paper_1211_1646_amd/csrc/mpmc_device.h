@@ -1,7 +1,7 @@
 // Device helpers shared by the hard-disk (mpmc_kernels.hip) and hard-sphere
 // (sphere_kernels.hip) kernels: the counter-based random numbers, per-lane
 // register arrays indexed only at compile time, the XCD-aware workgroup
-// order and a wave reduction.  Not part of the public ABI.
+// order, a wave reduction and the votes of a lane group.  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -109,6 +109,33 @@ __device__ __forceinline__ unsigned wave_sum_u32(unsigned v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
+}
+
+// Exchange with the neighbouring lane of a group of two or four (DPP quad
+// permutations [1,0,3,2] and [2,3,0,1]; groups are quad-aligned).
+__device__ __forceinline__ uint32_t lane_xor1(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t lane_xor2(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+}
+template <int LPC>
+__device__ __forceinline__ bool group_all(bool v)
+{
+    uint32_t x = v ? 1u : 0u;
+    if (LPC >= 2) x &= lane_xor1(x);
+    if (LPC >= 4) x &= lane_xor2(x);
+    return x != 0u;
+}
+template <int LPC>
+__device__ __forceinline__ bool group_any(bool v)
+{
+    uint32_t x = v ? 1u : 0u;
+    if (LPC >= 2) x |= lane_xor1(x);
+    if (LPC >= 4) x |= lane_xor2(x);
+    return x != 0u;
 }
 
 }  // namespace mpmc

@@ -514,33 +514,6 @@ k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restri
     }
 }
 
-// Exchange with the neighbouring lane of a group of two or four (DPP quad
-// permutations [1,0,3,2] and [2,3,0,1]; groups are quad-aligned).
-__device__ __forceinline__ uint32_t lane_xor1(uint32_t v)
-{
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
-}
-__device__ __forceinline__ uint32_t lane_xor2(uint32_t v)
-{
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
-}
-template <int LPC>
-__device__ __forceinline__ bool group_all(bool v)
-{
-    uint32_t x = v ? 1u : 0u;
-    if (LPC >= 2) x &= lane_xor1(x);
-    if (LPC >= 4) x &= lane_xor2(x);
-    return x != 0u;
-}
-template <int LPC>
-__device__ __forceinline__ bool group_any(bool v)
-{
-    uint32_t x = v ? 1u : 0u;
-    if (LPC >= 2) x |= lane_xor1(x);
-    if (LPC >= 4) x |= lane_xor2(x);
-    return x != 0u;
-}
-
 // The sub-sweep with LPC = 2 or 4 lanes per active cell: the same chain as
 // k_subsweep, with the work that dominates a lane split across its group.
 // Each lane loads the own cell and 8 / LPC of the neighbour cells (one

@@ -32,6 +32,7 @@ struct mpmc_sphere {
     unsigned long long *cnt;
     Ctl3 *ctl;
     int cur;
+    int lanes;   // sub-sweep lanes per active cell
     bool loaded;
     hipGraphExec_t graph[2];
     Ctl3 ctl_host;
@@ -41,6 +42,7 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kGraphSweeps = 16;   // sweeps per captured graph (even)
+constexpr int kDefaultLanes = 4;   // sub-sweep lanes per active cell
 
 mpmc_status fail(mpmc_status st, const std::string &msg)
 {
@@ -115,7 +117,9 @@ mpmc_status derive(const mpmc_sphere_params *p, Geom3 &g)
         g.w[k] = w[k];
     }
     const long long C = (long long)m[0] * m[1] * m[2];
-    if (C * kCap > 0x7FFFFFFFll) return fail(MPMC_EGEOM, "grid too large for 32-bit slot indices");
+    // the sub-sweep addresses the slot array with 32-bit byte offsets
+    if (C * kCap * (long long)sizeof(float4) > 0x7FFFFF00ll)
+        return fail(MPMC_EGEOM, "grid too large (at most 2^24 cells)");
     if (g.N < 0 || g.N > C * kCap) return fail(MPMC_EINVAL, "particle count outside [0, 8 cells]");
     if (!(p->delta > 0.0f) || p->delta > 0.5f * std::min(w[0], std::min(w[1], w[2])))
         return fail(MPMC_EINVAL, "delta must lie in (0, min(w)/2]");
@@ -162,7 +166,7 @@ mpmc_status read_ctl(mpmc_sphere *h)
 mpmc_status enqueue_subsweep(mpmc_sphere *h, int set)
 {
     SPH_HIP(mpmc::sph::launch_subsweep3(h->g, h->ctl, h->cur, h->pos[h->cur], h->count[h->cur],
-                                        h->tag[h->cur], h->cnt, set, h->st));
+                                        h->tag[h->cur], h->cnt, set, h->lanes, h->st));
     return MPMC_OK;
 }
 
@@ -392,6 +396,7 @@ mpmc_status mpmc_sphere_init(const mpmc_sphere_params *p, const mpmc_sphere_buff
     h->cnt = (unsigned long long *)b->work;
     h->ctl = (Ctl3 *)b->ctl;
     h->cur = 0;
+    h->lanes = kDefaultLanes;
     h->loaded = false;
     h->graph[0] = h->graph[1] = nullptr;
     if (p->lattice_nx > 0) {
@@ -559,6 +564,18 @@ mpmc_status mpmc_sphere_count_overlaps(mpmc_sphere_handle h, int64_t *pairs)
     const mpmc_status s = read_ctl(h);
     if (s) return s;
     *pairs = h->ctl_host.overlaps;
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_sphere_set_launch(mpmc_sphere_handle h, int32_t lanes_per_cell)
+{
+    if (!h || !(lanes_per_cell == 1 || lanes_per_cell == 2 || lanes_per_cell == 4))
+        return fail(MPMC_EINVAL, "lanes per cell must be 1, 2 or 4");
+    if (lanes_per_cell != h->lanes) {
+        SPH_HIP(hipStreamSynchronize(h->st));
+        drop_graphs(h);
+        h->lanes = lanes_per_cell;
+    }
     return MPMC_OK;
 }
 

@@ -47,14 +47,19 @@ struct Geom3 {
     int n_moves;
 };
 
-// Sub-sweep counter partials: two u64 (trials, accepts) per sub-sweep
-// workgroup, accumulated by every sub-sweep and folded on demand.
-inline int subsweep_groups(const Geom3 &g) { return (g.active + kSubBlock - 1) / kSubBlock; }
+// Sub-sweep workgroups for `lanes` (1, 2 or 4) lanes per active cell, and
+// the counter partials: two u64 (trials, accepts) per workgroup of the
+// widest launch, accumulated by every sub-sweep and folded on demand.
+inline int subsweep_tiles(const Geom3 &g, int lanes)
+{
+    return (int)(((long long)g.active * lanes + kSubBlock - 1) / kSubBlock);
+}
+inline int subsweep_groups(const Geom3 &g) { return subsweep_tiles(g, 4); }
 inline int xcd_groups(int tiles) { return 8 * ((tiles + 7) / 8); }
 
 hipError_t launch_subsweep3(const Geom3 &g, Ctl3 *ctl, int par, float4 *pos,
                             const uint32_t *count, uint32_t *tag, unsigned long long *cnt,
-                            int set, hipStream_t st);
+                            int set, int lanes, hipStream_t st);
 hipError_t launch_fold3(const Geom3 &g, Ctl3 *ctl, unsigned long long *cnt, hipStream_t st);
 // f >= 0: explicit shift (f, d), sweep slot copied; f < 0: the sweep's own
 // draws, advance to the next sweep.

@@ -90,24 +90,38 @@ __device__ __forceinline__ int wrap_dn(int c, int m) { return c == 0 ? m - 1 : c
 __device__ __forceinline__ int wrap_up(int c, int m) { return c == m - 1 ? 0 : c + 1; }
 
 // ------------------------------------------------------------ sub-sweep
-// One lane per active cell of set Q (Alg. 2 in d = 3):
-//   1. the 27 counts and the cell's own 8 slots are loaded together, and the
-//      cell's first Philox blocks are computed while they are in flight;
-//   2. the neighbours' spheres are loaded slot by slot over the 26 cells
-//      (slot i of every cell in one batch, only while some lane of the wave
-//      has a cell with more than i spheres), translated into the cell's
-//      frame by exactly -w, 0 or +w, and those that can reach the cell --
-//      squared distance to the cell's box below 1.0001, a superset of every
-//      sphere a trial position inside the cell can overlap -- are compacted
-//      into this lane's column of an LDS table;
+// A group of LPC = 1, 2 or 4 lanes per active cell of set Q (Alg. 2 in
+// d = 3).  Every lane of a group holds the cell's own spheres and draws the
+// same random numbers; lane h takes neighbour cells h NB .. h NB + NB - 1
+// of the 26 (NB = ceil(26 / LPC)), and a trial is accepted when every lane
+// of the group finds no overlap (a DPP vote):
+//   1. in one round trip: the own count and 8 slots, and the count and
+//      first slot (first two with four lanes per cell) of each of the lane's
+//      neighbour cells; the cell's first Philox blocks are computed while
+//      they are in flight;
+//   2. the further slots are loaded slot by slot (slot i of all the lane's
+//      cells in one batch, only while some lane of the wave has a cell with
+//      more than i spheres); every neighbour is translated into the cell's
+//      frame by exactly -w, 0 or +w, and those that can reach a trial
+//      position -- squared distance below 1.0001 to the box that holds
+//      every trial position of this update (the cell's spheres' bounding
+//      box grown by the most they can move, cut to the cell), a superset of
+//      every sphere a trial can overlap -- are compacted into this lane's
+//      column of an LDS table;
 //   3. the column is read back into registers and the n_M trials run from
-//      registers only.  A lane with more reachable neighbours than the table
-//      holds also tests every neighbour straight from memory (rare).
+//      registers only.  A lane with more reachable neighbours than its
+//      column holds also tests every neighbour straight from memory (rare).
 // Dropping unreachable spheres cannot change a decision: a trial outside
-// the cell is rejected before any overlap test, and one inside it is at
-// squared distance >= 1 from every dropped sphere, also after FP32 rounding.
+// the cell is rejected before any overlap test, and one inside it lies in
+// the box, at squared distance >= 1 from every dropped sphere, also after
+// FP32 rounding.
 constexpr float kReach2 = 1.0001f;
 constexpr float kFar = 1.0e6f;
+// Buffer descriptor word 3 of the gfx9 family (raw, range-checked 32-bit
+// dwords), and an offset past the end of any slot array: the geometry check
+// keeps C * 8 * 16 bytes below 2^31.
+constexpr int kBufferWord3 = 0x00020000;
+constexpr int kPastEnd = 0x7FFFFFF0;
 
 // Smallest r^2 from (xm, ym, zm) to entries k .. k+3; some r^2 < 1 iff the
 // smallest is (all values finite).
@@ -163,17 +177,35 @@ __device__ bool overlap_from_memory(const Geom3 &g, const float4 *__restrict__ p
     return hit;
 }
 
+// The cell (cx, cy, cz) shifted by o in {-1, 0, +1} per axis, as a cell index.
+__device__ __forceinline__ int cell_at(const Geom3 &g, const int X[3], const int Y[3],
+                                       const int Z[3], int ox, int oy, int oz)
+{
+    const int x = ox < 0 ? X[0] : (ox > 0 ? X[2] : X[1]);
+    const int y = oy < 0 ? Y[0] : (oy > 0 ? Y[2] : Y[1]);
+    const int z = oz < 0 ? Z[0] : (oz > 0 ? Z[2] : Z[1]);
+    return (z * g.m[1] + y) * g.m[0] + x;
+}
+
+template <int LPC>
 __global__ void __launch_bounds__(kSubBlock)
 k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
             const uint32_t *__restrict__ count, uint32_t *__restrict__ tag,
             unsigned long long *__restrict__ cnt, int set, int ntile, int per)
 {
-    __shared__ float lx[kNbrList][kSubBlock];   // entry k of lane l at [k][l]:
-    __shared__ float ly[kNbrList][kSubBlock];   // the 64 lanes of a wave read
-    __shared__ float lz[kNbrList][kSubBlock];   // 64 consecutive words
+    constexpr int NB = (26 + LPC - 1) / LPC;                  // neighbour cells per lane
+    constexpr int kL = LPC == 1 ? kNbrList : (LPC == 2 ? 24 : 16);   // LDS list per lane
+    constexpr int kU = LPC == 4 ? 2 : 1;                      // slots loaded with the counts
+    // entry k of lane l at [k][l] (the 64 lanes of a wave read 64 consecutive
+    // words); row kL is a pad row that takes the writes of dropped entries,
+    // so that no write needs a branch
+    __shared__ float lx[kL + 1][kSubBlock];
+    __shared__ float ly[kL + 1][kSubBlock];
+    __shared__ float lz[kL + 1][kSubBlock];
     const int tile = xcd_tile(per);
     const int lane = threadIdx.x;
-    const int a = tile * kSubBlock + lane;
+    const int h = lane % LPC;                                 // rank in the lane group
+    const int a = (tile * kSubBlock + lane) / LPC;            // active cell of the group
     unsigned n_trials = 0, n_acc = 0;
     const bool live = tile < ntile && a < g.active;
     const unsigned long long s = ctl->sweep_at[par];
@@ -183,7 +215,7 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     int Q = set;
     if (Q < 0) Q = (int)((ctl->draw_at[par].order >> (4 * (-1 - set))) & 0xFu);
     const int hx = g.m[0] >> 1, hy = g.m[1] >> 1;
-    const int aa = live ? a : 0;
+    const int aa = live ? a : 0;   // a lane past the end reads cell 0's block and drops it
     const int ix = aa % hx, iy = (aa / hx) % hy, iz = aa / (hx * hy);
     const int cx = 2 * ix + (Q & 1), cy = 2 * iy + ((Q >> 1) & 1), cz = 2 * iz + (Q >> 2);
     const int X[3] = {wrap_dn(cx, g.m[0]), cx, wrap_up(cx, g.m[0])};
@@ -192,79 +224,138 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     const int c = (cz * g.m[1] + cy) * g.m[0] + cx;
     const size_t b0 = (size_t)c * kCap;
 
-    // 1. counts of the 3x3x3 block (q = 9 (oz+1) + 3 (oy+1) + (ox+1)) and
-    // the own slots, all in flight together
-    uint32_t nn[27];
-#pragma unroll
-    for (int q = 0; q < 27; ++q)
-        nn[q] = live ? count[(Z[q / 9] * g.m[1] + Y[(q / 3) % 3]) * g.m[0] + X[q % 3]] : 0u;
+    // 1. in one round trip: the own count and slots, and for each of this
+    // lane's neighbour cells (entries h NB .. h NB + NB - 1 of the 26, in
+    // the order q = 9 (oz+1) + 3 (oy+1) + (ox+1) without the centre) its
+    // count and its first kU slots.  Every address is inside the grid, so
+    // the loads are issued unconditionally and masked afterwards.
+    const uint32_t n_raw = live ? count[c] : 0u;
     float px[kCap], py[kCap], pz[kCap];
     uint32_t tg[kCap];
 #pragma unroll
     for (int q = 0; q < kCap; ++q) {
-        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (live) v = pos[b0 + (size_t)q];
+        const float4 v = pos[b0 + (size_t)q];
         px[q] = v.x;
         py[q] = v.y;
         pz[q] = v.z;
         tg[q] = 0u;
     }
     const bool has_tag = tag != nullptr;
-    if (has_tag && live) {
+    if (has_tag) {
 #pragma unroll
         for (int q = 0; q < kCap; ++q) tg[q] = tag[b0 + (size_t)q];
+    }
+    int cq[NB], oq[NB];       // neighbour cell and its offset code q
+    uint32_t nn[NB];
+    float4 v0[NB][kU];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int e = h * NB + j;
+        const bool valid = live && e < 26;
+        const int q = e < 13 ? e : e + 1;
+        oq[j] = q;
+        const int cell = cell_at(g, X, Y, Z, q % 3 - 1, (q / 3) % 3 - 1, q / 9 - 1);
+        cq[j] = cell;
+        const uint32_t cnt_j = count[cell];
+        nn[j] = valid ? cnt_j : 0u;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) v0[j][u] = pos[(size_t)cell * kCap + (size_t)u];
     }
     uint4 Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle, k0, k1);
     uint4 W = make_uint4(0, 0, 0, 0);
     if (g.n_moves > 0) W = philox((uint32_t)c, s_lo, s_hi, 0u, k0, k1);
-    bool bad = false;
+    bool bad = n_raw > (uint32_t)kCap;
     uint32_t nmax = 0;
 #pragma unroll
-    for (int q = 0; q < 27; ++q) {
-        bad |= nn[q] > (uint32_t)kCap;
-        if (q != 13) nmax = max(nmax, nn[q]);
+    for (int j = 0; j < NB; ++j) {
+        bad |= nn[j] > (uint32_t)kCap;
+        nmax = max(nmax, nn[j]);
     }
-    int n = (int)nn[13];
-    if (bad) {
-        atomicOr(&ctl->errword, kErrCapacity);
-        n = 0;
-    }
+    if (bad) atomicOr(&ctl->errword, kErrCapacity);
+    // a cell above capacity anywhere in the group's block: skip the update
+    const bool skip = group_any<LPC>(bad);
+    const int n = skip ? 0 : (int)n_raw;
     if (n == 0) nmax = 0;
+    nmax = min(nmax, (uint32_t)kCap);
 
-    // 2. neighbours, slot by slot; K counts every reachable one, the first
-    // kNbrList go to the LDS column
-    int K = 0;
-    for (int i = 0; i < kCap; ++i) {
-        if (__ballot(nmax > (uint32_t)i) == 0ull) break;
-        float4 v[27];
+    // The box that holds every trial position of this cell update: a sphere
+    // of the cell moves at most k = ceil(n_M / n) times, each time by at most
+    // delta per axis (plus a rounding of at most 1e-7 here), and a trial
+    // outside the cell is rejected before any overlap test.  The margin
+    // 1e-5 covers the rounding of the box itself.
+    float blo[3] = {0.0f, 0.0f, 0.0f}, bhi[3] = {g.w[0], g.w[1], g.w[2]};
+    if (n > 0) {
+        float mn[3] = {px[0], py[0], pz[0]}, mx[3] = {px[0], py[0], pz[0]};
 #pragma unroll
-        for (int q = 0; q < 27; ++q) {
-            v[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (q != 13 && nmax > (uint32_t)i && nn[q] > (uint32_t)i)
-                v[q] = pos[(size_t)((Z[q / 9] * g.m[1] + Y[(q / 3) % 3]) * g.m[0] + X[q % 3]) * kCap +
-                           (size_t)i];
+        for (int q = 1; q < kCap; ++q) {
+            const bool in = q < n;
+            mn[0] = in ? fminf(mn[0], px[q]) : mn[0];
+            mx[0] = in ? fmaxf(mx[0], px[q]) : mx[0];
+            mn[1] = in ? fminf(mn[1], py[q]) : mn[1];
+            mx[1] = in ? fmaxf(mx[1], py[q]) : mx[1];
+            mn[2] = in ? fminf(mn[2], pz[q]) : mn[2];
+            mx[2] = in ? fmaxf(mx[2], pz[q]) : mx[2];
         }
+        const int kmv = (g.n_moves + n - 1) / n;
+        const float e = (float)kmv * (delta * 1.000001f + 2e-7f) + 1e-5f;
 #pragma unroll
-        for (int q = 0; q < 27; ++q) {
-            if (q == 13) continue;
-            const int ox = q % 3 - 1, oy = (q / 3) % 3 - 1, oz = q / 9 - 1;
-            const float qx = frame(v[q].x, ox, g.w[0]);
-            const float qy = frame(v[q].y, oy, g.w[1]);
-            const float qz = frame(v[q].z, oz, g.w[2]);
-            const float gx = gap(qx, ox, g.w[0]);
-            const float gy = gap(qy, oy, g.w[1]);
-            const float gz = gap(qz, oz, g.w[2]);
-            const bool take = nmax > (uint32_t)i && nn[q] > (uint32_t)i &&
-                              (gx * gx + gy * gy) + gz * gz < kReach2;
-            if (take && K < kNbrList) {
-                lx[K][lane] = qx;
-                ly[K][lane] = qy;
-                lz[K][lane] = qz;
-            }
-            K += take ? 1 : 0;
+        for (int ax = 0; ax < 3; ++ax) {
+            blo[ax] = fmaxf(mn[ax] - e, 0.0f);
+            bhi[ax] = fminf(mx[ax] + e, g.w[ax]);
         }
     }
-    const int KL = K < kNbrList ? K : kNbrList;
+
+    // 2. translate into the cell's frame, keep what can reach the box;
+    // K counts every kept sphere, the first kL go to the LDS column
+    int K = 0;
+    auto take = [&](const float4 &v, int q) {
+        const int ox = q % 3 - 1, oy = (q / 3) % 3 - 1, oz = q / 9 - 1;
+        const float qx = frame(v.x, ox, g.w[0]);
+        const float qy = frame(v.y, oy, g.w[1]);
+        const float qz = frame(v.z, oz, g.w[2]);
+        const float gx = fmaxf(fmaxf(blo[0] - qx, qx - bhi[0]), 0.0f);
+        const float gy = fmaxf(fmaxf(blo[1] - qy, qy - bhi[1]), 0.0f);
+        const float gz = fmaxf(fmaxf(blo[2] - qz, qz - bhi[2]), 0.0f);
+        return make_float4(qx, qy, qz, (gx * gx + gy * gy) + gz * gz);
+    };
+    auto put = [&](const float4 &f, bool keep) {
+        const int row = (keep && K < kL) ? K : kL;
+        lx[row][lane] = f.x;
+        ly[row][lane] = f.y;
+        lz[row][lane] = f.z;
+        K += keep ? 1 : 0;
+    };
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const float4 f = take(v0[j][u], oq[j]);
+            put(f, nmax > (uint32_t)u && nn[j] > (uint32_t)u && f.w < kReach2);
+        }
+    }
+    // the rest slot by slot, while some lane of the wave has a cell with
+    // more than i spheres.  These are raw buffer loads over the slot array:
+    // a slot a lane does not need gets an offset past the buffer's end,
+    // which the hardware's range check turns into zeros without a memory
+    // access, so neither a branch nor a wasted cache line is spent on it.
+    const __amdgpu_buffer_rsrc_t slots = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)pos, (short)0, (int)((unsigned)g.C * (unsigned)(kCap * sizeof(float4))), kBufferWord3);
+    for (int i = kU; i < kCap; ++i) {
+        if (__ballot(nmax > (uint32_t)i) == 0ull) break;
+        float4 v[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const bool need = nmax > (uint32_t)i && nn[j] > (uint32_t)i;
+            const int off = need ? (cq[j] * kCap + i) * (int)sizeof(float4) : kPastEnd;
+            v[j] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(slots, off, 0, 0));
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const float4 f = take(v[j], oq[j]);
+            put(f, nmax > (uint32_t)i && nn[j] > (uint32_t)i && f.w < kReach2);
+        }
+    }
+    const int KL = K < kL ? K : kL;
     // entries up to the wave's largest count in groups of four: far spheres
     // past each lane's own count
     int KLw = KL;
@@ -280,7 +371,7 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     if (n > 0) {
         // rng.shuffle(c.particles): Fisher-Yates over the stored list on a
         // packed permutation (nibble q = source slot of list position q),
-        // applied to the registers once
+        // applied to the registers once; every lane of the group does the same
         uint32_t P = 0x76543210u;
         for (int k = 0; k < n - 1; ++k) {
             if (k > 0 && (k & 3) == 0)
@@ -301,17 +392,17 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
             pz[q] = q < n ? pz[q] : kFar;
         }
     }
-    // 3. the column, read once into registers (a lane with n = 0 still reads
-    // its far entries: the loop bounds are the wave's)
-    float rx[kNbrList], ry[kNbrList], rz[kNbrList];
+    // 3. the column, read once into registers (the loop bounds are the wave's)
+    float rx[kL], ry[kL], rz[kL];
 #pragma unroll
-    for (int k = 0; k < kNbrList; ++k) {
+    for (int k = 0; k < kL; ++k) {
         rx[k] = k < KLw ? lx[k][lane] : kFar;
         ry[k] = k < KLw ? ly[k][lane] : kFar;
         rz[k] = k < KLw ? lz[k][lane] : kFar;
     }
     if (n > 0) {
-        const bool spill = K > kNbrList;
+        // the whole group takes this branch (n is the group's own count)
+        const bool spill = K > kL;
         for (int t = 0; t < g.n_moves; ++t) {
             if (t > 0 && (t & 1) == 0) W = philox((uint32_t)c, s_lo, s_hi, (uint32_t)(t >> 1), k0, k1);
             float dx, dy, dz;
@@ -329,28 +420,31 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
                 ok = ok & !((ddx * ddx + ddy * ddy) + ddz * ddz < 1.0f);
             }
 #pragma unroll
-            for (int k = 0; k < kNbrList; k += 4)
+            for (int k = 0; k < kL; k += 4)
                 if (k < KLw) ok = ok & !(min_r2_4(xm, ym, zm, rx + k, ry + k, rz + k) < 1.0f);
             if (spill && ok) ok = !overlap_from_memory(g, pos, count, cx, cy, cz, xm, ym, zm);
+            ok = group_all<LPC>(ok);
             px[0] = ok ? xm : px[0];
             py[0] = ok ? ym : py[0];
             pz[0] = ok ? zm : pz[0];
-            n_acc += ok ? 1u : 0u;
+            n_acc += (ok && h == 0) ? 1u : 0u;
             rrot(px, n);   // the identity for n = 1
             rrot(py, n);
             rrot(pz, n);
             if (has_tag) rrot(tg, n);
         }
-        n_trials = (unsigned)g.n_moves;
-        // register entry q now holds list position (q + n_M) mod n
-        const int r0 = g.n_moves % n;
+        if (h == 0) {
+            n_trials = (unsigned)g.n_moves;
+            // register entry q now holds list position (q + n_M) mod n
+            const int r0 = g.n_moves % n;
 #pragma unroll
-        for (int q = 0; q < kCap; ++q) {
-            if (q < n) {
-                int o = q + r0;
-                o = o >= n ? o - n : o;
-                pos[b0 + (size_t)o] = make_float4(px[q], py[q], pz[q], 0.0f);
-                if (has_tag && n > 1) tag[b0 + (size_t)o] = tg[q];
+            for (int q = 0; q < kCap; ++q) {
+                if (q < n) {
+                    int o = q + r0;
+                    o = o >= n ? o - n : o;
+                    pos[b0 + (size_t)o] = make_float4(px[q], py[q], pz[q], 0.0f);
+                    if (has_tag && n > 1) tag[b0 + (size_t)o] = tg[q];
+                }
             }
         }
     }
@@ -730,12 +824,19 @@ __global__ void k_overlaps_reset3(Ctl3 *ctl) { ctl->overlaps = 0; }
 // ---------------------------------------------------------------- launches
 hipError_t launch_subsweep3(const Geom3 &g, Ctl3 *ctl, int par, float4 *pos,
                             const uint32_t *count, uint32_t *tag, unsigned long long *cnt,
-                            int set, hipStream_t st)
+                            int set, int lanes, hipStream_t st)
 {
-    const int ntile = subsweep_groups(g);
+    const int ntile = subsweep_tiles(g, lanes);
     const int grid = xcd_groups(ntile);
-    hipLaunchKernelGGL(k_subsweep3, dim3(grid), dim3(kSubBlock), 0, st, g, ctl, par, pos, count,
-                       tag, cnt, set, ntile, grid / 8);
+    if (lanes == 4)
+        hipLaunchKernelGGL(k_subsweep3<4>, dim3(grid), dim3(kSubBlock), 0, st, g, ctl, par, pos,
+                           count, tag, cnt, set, ntile, grid / 8);
+    else if (lanes == 2)
+        hipLaunchKernelGGL(k_subsweep3<2>, dim3(grid), dim3(kSubBlock), 0, st, g, ctl, par, pos,
+                           count, tag, cnt, set, ntile, grid / 8);
+    else
+        hipLaunchKernelGGL(k_subsweep3<1>, dim3(grid), dim3(kSubBlock), 0, st, g, ctl, par, pos,
+                           count, tag, cnt, set, ntile, grid / 8);
     return hipGetLastError();
 }
 

@@ -117,6 +117,10 @@ class HardSphereSystem:
     def synchronize(self):
         L.check(self.lib.mpmc_sphere_synchronize(self._h))
 
+    def set_launch(self, lanes_per_cell: int):
+        """Sub-sweep lanes per active cell (1, 2 or 4); results do not change."""
+        L.check(self.lib.mpmc_sphere_set_launch(self._h, int(lanes_per_cell)))
+
     def set_delta(self, delta: float):
         L.check(self.lib.mpmc_sphere_set_delta(self._h, float(delta)))
 

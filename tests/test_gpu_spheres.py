@@ -29,25 +29,29 @@ def gpu():
     return pkg
 
 
-def lattice_pair(pkg, n, eta, delta=0.1, n_moves=4, seed=1, replica=0, w_max=0.0):
-    log("  sphere lattice pair n=%s eta=%.3f delta=%.3f n_moves=%d seed=%d"
-        % (n, eta, delta, n_moves, seed))
+def lattice_pair(pkg, n, eta, delta=0.1, n_moves=4, seed=1, replica=0, w_max=0.0, lanes=4):
+    log("  sphere lattice pair n=%s eta=%.3f delta=%.3f n_moves=%d seed=%d lanes=%d"
+        % (n, eta, delta, n_moves, seed, lanes))
     cfg = pkg.SphereConfig(lattice_nx=n[0], lattice_ny=n[1], lattice_nz=n[2], eta=eta,
                            w_max=w_max, delta=delta, n_moves=n_moves, seed=seed,
                            replica=replica, flags=pkg.FLAG_TAG)
     G = pkg.HardSphereSystem(cfg)
+    G.set_launch(lanes)
     O = SphereOracle.lattice(*n, eta, w_max=w_max, delta=delta, n_moves=n_moves, seed=seed,
                              replica=replica)
     return G, O
 
 
-def grid_pair(pkg, m, w, xyz, start, tags, sweep=0, delta=0.1, n_moves=4, seed=1, replica=0):
-    log("  sphere grid pair m=%s N=%d delta=%.3f n_moves=%d" % (m, len(xyz), delta, n_moves))
+def grid_pair(pkg, m, w, xyz, start, tags, sweep=0, delta=0.1, n_moves=4, seed=1, replica=0,
+              lanes=4):
+    log("  sphere grid pair m=%s N=%d delta=%.3f n_moves=%d lanes=%d"
+        % (m, len(xyz), delta, n_moves, lanes))
     cfg = pkg.SphereConfig(cells_x=m[0], cells_y=m[1], cells_z=m[2], cell_w_x=float(w[0]),
                            cell_w_y=float(w[1]), cell_w_z=float(w[2]), n_particles=len(xyz),
                            delta=delta, n_moves=n_moves, seed=seed, replica=replica,
                            flags=pkg.FLAG_TAG)
     G = pkg.HardSphereSystem(cfg)
+    G.set_launch(lanes)
     G.set_state(xyz, start, sweep, tags)
     O = SphereOracle.grid(m, w, len(xyz), delta=delta, n_moves=n_moves, seed=seed,
                           replica=replica)
@@ -74,9 +78,9 @@ def test_lattice_start_matches(gpu):
         G.close()
 
 
-@pytest.mark.parametrize("eta,n_moves", [(0.3, 4), (0.45, 7), (0.5, 1), (0.45, 0)])
-def test_each_subsweep_and_shift(gpu, eta, n_moves):
-    G, O = lattice_pair(gpu, (12, 10, 14), eta, delta=0.15, n_moves=n_moves, seed=7)
+@pytest.mark.parametrize("eta,n_moves,lanes", [(0.3, 4, 4), (0.45, 7, 1), (0.5, 1, 2), (0.45, 0, 4)])
+def test_each_subsweep_and_shift(gpu, eta, n_moves, lanes):
+    G, O = lattice_pair(gpu, (12, 10, 14), eta, delta=0.15, n_moves=n_moves, seed=7, lanes=lanes)
     for Q in (5, 0, 3, 6, 1, 7, 2, 4):
         G.subsweep(Q)
         O.subsweep(Q)
@@ -104,14 +108,15 @@ def test_shift_by_zero_and_half_a_cell(gpu):
     G.close()
 
 
-@pytest.mark.parametrize("n,eta,delta,n_moves,seed,sweeps", [
-    ((10, 10, 10), 0.3, 0.1, 4, 1, 5),
-    ((12, 8, 16), 0.45, 0.12, 4, 2, 37),     # 37 = two captured graphs + 5 direct sweeps
-    ((14, 14, 14), 0.5, 0.05, 9, 3, 20),
-    ((16, 16, 16), 0.2, 0.3, 3, 4, 17),
-    ((10, 10, 10), 0.1, 0.4, 1, 5, 40)])
-def test_sweeps_match(gpu, n, eta, delta, n_moves, seed, sweeps):
-    G, O = lattice_pair(gpu, n, eta, delta=delta, n_moves=n_moves, seed=seed)
+@pytest.mark.parametrize("n,eta,delta,n_moves,seed,sweeps,lanes", [
+    ((10, 10, 10), 0.3, 0.1, 4, 1, 5, 4),
+    ((12, 8, 16), 0.45, 0.12, 4, 2, 37, 4),     # 37 = two captured graphs + 5 direct sweeps
+    ((12, 8, 16), 0.45, 0.12, 4, 2, 37, 1),
+    ((14, 14, 14), 0.5, 0.05, 9, 3, 20, 2),
+    ((16, 16, 16), 0.2, 0.3, 3, 4, 17, 4),
+    ((10, 10, 10), 0.1, 0.4, 1, 5, 40, 2)])
+def test_sweeps_match(gpu, n, eta, delta, n_moves, seed, sweeps, lanes):
+    G, O = lattice_pair(gpu, n, eta, delta=delta, n_moves=n_moves, seed=seed, lanes=lanes)
     G.sweep(sweeps)
     O.sweep(sweeps)
     assert_same(G, O, "after %d sweeps" % sweeps)
@@ -172,37 +177,48 @@ def fcc_state(cells_fcc, eta, offset=0.137):
     return (m, m, m), np.float32([w, w, w]), loc[order], start, order.astype(np.uint32)
 
 
-def reachable_counts(m, w, xyz, start):
-    """Per cell, the spheres of its 26 neighbours whose squared distance to
-    the cell's box is below 1.0001 (the sub-sweep's LDS list length)."""
+def trial_box_counts(m, w, xyz, start, n_moves, delta):
+    """Per occupied cell, the spheres of its 26 neighbours whose squared
+    distance is below 1.0001 to the box that holds every trial position of
+    the cell's update (the own spheres' bounding box grown by
+    ceil(n_M / n) (delta + 2e-7) + 1e-5 and cut to the cell): the length of
+    the sub-sweep's neighbour list for a lane per cell."""
     w = float(w[0])
     M = m[0]
     counts = np.diff(start.astype(np.int64))
-    out = np.zeros(M ** 3, np.int64)
     cell_of = np.repeat(np.arange(M ** 3), counts)
     cz, cy, cx = cell_of // (M * M), (cell_of // M) % M, cell_of % M
     gpos = np.stack([cx * w + xyz[:, 0], cy * w + xyz[:, 1], cz * w + xyz[:, 2]], 1)
     Lb = M * w
+    out = np.zeros(M ** 3, np.int64)
     for c in range(M ** 3):
+        n = counts[c]
+        if n == 0:
+            continue
+        own = xyz[start[c]:start[c + 1]].astype(np.float64)
+        e = -(-n_moves // n) * (delta + 2e-7) + 1e-5
+        lo, hi = np.maximum(own.min(0) - e, 0.0), np.minimum(own.max(0) + e, w)
         z, y, x = c // (M * M), (c // M) % M, c % M
-        lo = np.array([x * w, y * w, z * w])
-        d = gpos - lo
-        d -= Lb * np.round((d - w / 2) / Lb)          # nearest image around the box centre
-        gap = np.maximum(0.0, np.maximum(-d, d - w))
-        near = ((gap ** 2).sum(1) < 1.0001) & (cell_of != c)
-        out[c] = near.sum()
+        d = gpos - np.array([x * w, y * w, z * w])
+        d -= Lb * np.round((d - w / 2) / Lb)          # nearest image around the cell
+        gap = np.maximum(0.0, np.maximum(lo - d, d - hi))
+        out[c] = (((gap ** 2).sum(1) < 1.0001) & (cell_of != c)).sum()
     return out
 
 
-def test_dense_crystal_exercises_the_spill_path(gpu):
-    """An FCC crystal at eta = 0.70 puts more reachable neighbours around
-    many cells than the kernel's LDS list holds; those lanes also test every
-    neighbour straight from memory, and the chain must still be bit-exact."""
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+def test_dense_crystal_exercises_the_spill_path(gpu, lanes):
+    """An FCC crystal at eta = 0.70 with n_M = 16 puts more reachable
+    neighbours around many cells than the 32-entry list of a lane per cell
+    holds; those lanes also test every neighbour straight from memory.  The
+    same dense state runs with two and four lanes per cell (lists of 24 and
+    16 over a half and a quarter of the neighbour cells).  The chain must be
+    bit-exact in every case."""
     m, w, xyz, start, tags = fcc_state(8, 0.70)
-    K = reachable_counts(m, w, xyz, start)
-    log("  reachable neighbours per cell: max %d, cells above 32: %d" % (K.max(), (K > 32).sum()))
+    K = trial_box_counts(m, w, xyz, start, 16, 0.05)
+    log("  neighbour list per cell: max %d, cells above 32: %d" % (K.max(), (K > 32).sum()))
     assert (K > 32).sum() > 10
-    G, O = grid_pair(gpu, m, w, xyz, start, tags, 0, delta=0.03, n_moves=6, seed=9)
+    G, O = grid_pair(gpu, m, w, xyz, start, tags, 0, delta=0.05, n_moves=16, seed=9, lanes=lanes)
     G.sweep(3)
     O.sweep(3)
     assert_same(G, O, "dense crystal, 3 sweeps")
@@ -211,6 +227,24 @@ def test_dense_crystal_exercises_the_spill_path(gpu):
     O.sweep(16)
     assert_same(G, O, "dense crystal, 19 sweeps")
     G.close()
+
+
+def test_launch_shapes_give_one_chain(gpu):
+    """Lanes per cell change only how the work is split: 1, 2 and 4 give the
+    same state bit for bit, from the lattice and across launch-shape changes
+    in the middle of a run."""
+    states = []
+    for lanes in (1, 2, 4):
+        G, _ = lattice_pair(gpu, (12, 12, 12), 0.45, delta=0.08, n_moves=5, seed=21, lanes=lanes)
+        G.sweep(9)
+        G.set_launch(1 if lanes == 4 else 4)
+        G.sweep(20)
+        states.append(G.get_state(with_tags=True) + (G.counters(),))
+        G.close()
+    for st in states[1:]:
+        assert np.array_equal(st[0].view(np.uint32), states[0][0].view(np.uint32))
+        assert np.array_equal(st[1], states[0][1]) and np.array_equal(st[3], states[0][3])
+        assert st[2] == states[0][2] and st[4] == states[0][4]
 
 
 def test_pair_histogram_and_pressure(gpu):
@@ -247,7 +281,8 @@ def test_argument_errors(gpu):
     from paper_1211_1646_amd import _lib as L
     G, _ = lattice_pair(gpu, (10, 10, 10), 0.3)
     for call in (lambda: G.subsweep(8), lambda: G.subsweep(-1), lambda: G.shift(6, 0.1),
-                 lambda: G.shift(0, 0.6), lambda: G.set_delta(0.6), lambda: G.set_delta(0.0)):
+                 lambda: G.shift(0, 0.6), lambda: G.set_delta(0.6), lambda: G.set_delta(0.0),
+                 lambda: G.set_launch(3), lambda: G.set_launch(8)):
         with pytest.raises(L.MPMCError) as e:
             call()
         assert e.value.status == L.MPMC_EINVAL
