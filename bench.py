@@ -24,7 +24,10 @@ compare the batched and learned-controller forms with the plain form:
   eos     -- beta P sigma^2 with block errors at phi = 0.700, 0.716, 0.720;
   table3  -- the paper's own throughput benchmark like for like: phi 0.698,
              in-circle moves of radius 0.16, n_M = 4, N = 253^2 .. 3040^2,
-             median eta of 11 runs next to the paper's K20 figures.
+             median eta of 11 runs next to the paper's K20 figures;
+  spheres -- the same chain in three dimensions: 100^3 hard spheres at
+             eta = 0.45, n_M = 4, delta = 0.05, trial moves per second and
+             the sub-sweep kernel against the HBM peak.
 """
 from __future__ import annotations
 
@@ -68,6 +71,7 @@ def parse():
     ap.add_argument("--no-table3", action="store_true",
                     help="skip the paper's Table 3 benchmark (in-circle moves, N = 253^2 .. 3040^2)")
     ap.add_argument("--table3-runs", type=int, default=11)
+    ap.add_argument("--no-spheres", action="store_true", help="skip the 3D hard-sphere leg")
     ap.add_argument("--eos-equilibration", type=int, default=8000)
     ap.add_argument("--eos-blocks", type=int, default=20)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -99,12 +103,13 @@ def cpu_baseline(args, geo, trials_per_sweep_gpu):
                       "serial C oracle, one thread)" % (n, geo["n_particles"], tr1 - tr0, dt)}
 
 
-def traffic_from_profile(kernel_src, kernel_name, key="hbm bytes per launch"):
-    """A figure of the committed counter summary (HBM bytes per sub-sweep
+def traffic_from_profile(kernel_src, kernel_name, key="hbm bytes per launch",
+                         profile="subsweep_1M_phi070_counters.md"):
+    """A figure of a committed counter summary (HBM bytes per sub-sweep
     launch by default), if it was taken on the current kernel source and the
     same kernel (else None)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "subsweep_1M_phi070_counters.md")
+    path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
     digest = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
@@ -119,6 +124,32 @@ def traffic_from_profile(kernel_src, kernel_name, key="hbm bytes per launch"):
         return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def spheres_leg(args):
+    """The 3D chain: 100^3 spheres at eta = 0.45 (see sphere_throughput.py)."""
+    from paper_1211_1646_amd import sphere_throughput as ST
+    r = ST.measure(side=100, eta=0.45, n_moves=4, delta=0.05, warmup=100, steps=500,
+                   kernel_samples=64)
+    src = os.path.join(ROOT, "paper_1211_1646_amd", "csrc", "sphere_kernels.hip")
+    prof = "sphere_subsweep_1M_eta045_counters.md"
+    r["roofline"]["traffic"] = traffic_from_profile(src, "k_subsweep3", profile=prof)
+    r["roofline"]["valu_busy"] = traffic_from_profile(src, "k_subsweep3", "valu busy fraction",
+                                                      profile=prof)
+    return r
+
+
+def cpu_baseline_spheres():
+    """The 3D oracle on three sweeps of the same 100^3-sphere workload."""
+    from oracle.spheres import SphereOracle
+    O = SphereOracle.lattice(100, 100, 100, 0.45, delta=0.05, n_moves=4, seed=1)
+    t0 = time.perf_counter()
+    O.sweep(3)
+    dt = time.perf_counter() - t0
+    tr, _ = O.counters()
+    return {"value": tr / dt, "unit": "trial moves/s", "cores": 1, "kind": "oracle",
+            "sample": "3 sweeps of the 1,000,000-sphere workload from the lattice (%d trial moves, "
+                      "%.1f s, serial C oracle, one thread)" % (tr, dt)}
 
 
 def batched_leg(args, pkg, torch, net=None):
@@ -561,9 +592,14 @@ def main():
     if not args.no_table3:
         print("[bench] paper table 3 leg", file=sys.stderr, flush=True)
         out["table3"] = table3_leg(args, pkg, torch)
+    if not args.no_spheres:
+        print("[bench] hard-sphere leg", file=sys.stderr, flush=True)
+        out["spheres"] = spheres_leg(args)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args, geo, trials / args.steps)
+        if not args.no_spheres:
+            out["cpu_baseline"]["spheres"] = cpu_baseline_spheres()
     print(json.dumps(out), flush=True)
 
 

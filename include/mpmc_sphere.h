@@ -181,7 +181,7 @@ mpmc_status mpmc_sphere_pressure(mpmc_sphere_handle h, double *p_star, double *g
 mpmc_status mpmc_sphere_count_overlaps(mpmc_sphere_handle h, int64_t *pairs);
 
 /* Launch shape of the sub-sweep: 1, 2 or 4 lanes per active cell (default
- * 4).  The lanes of a group split the 26 neighbour cells and their overlap
+ * 1).  The lanes of a group split the 26 neighbour cells and their overlap
  * tests and combine their verdicts; every comparison is the same, so the
  * results do not depend on it (sync: waits for the stream, drops the sweep
  * graphs). */

@@ -42,7 +42,7 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kGraphSweeps = 16;   // sweeps per captured graph (even)
-constexpr int kDefaultLanes = 4;   // sub-sweep lanes per active cell
+constexpr int kDefaultLanes = 1;   // sub-sweep lanes per active cell
 
 mpmc_status fail(mpmc_status st, const std::string &msg)
 {
