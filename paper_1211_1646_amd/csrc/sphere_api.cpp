@@ -254,7 +254,7 @@ mpmc_status upload(mpmc_sphere *h, const float *xyz, const uint32_t *start, uint
         const uint32_t b = start[c], n = start[c + 1] - start[c];
         cnt[(size_t)c] = n;
         for (uint32_t i = 0; i < n; ++i) {
-            const size_t k = (size_t)c * kCap + i, src = (size_t)(b + i);
+            const size_t k = mpmc::sph::slot_of(g.C, c, (int)i), src = (size_t)(b + i);
             slots[k] = make_float4(xyz[3 * src], xyz[3 * src + 1], xyz[3 * src + 2], 0.0f);
             if (!tg.empty()) tg[k] = tags ? tags[src] : (uint32_t)src;
         }
@@ -473,7 +473,7 @@ mpmc_status mpmc_sphere_get_state(mpmc_sphere_handle h, float *xyz, uint32_t *st
     for (int c = 0; c < g.C; ++c) {
         if (start) start[c] = k;
         for (uint32_t i = 0; i < cnt[(size_t)c]; ++i, ++k) {
-            const size_t sl = (size_t)c * kCap + i;
+            const size_t sl = mpmc::sph::slot_of(g.C, c, (int)i);
             if (xyz) {
                 xyz[3 * (size_t)k] = slots[sl].x;
                 xyz[3 * (size_t)k + 1] = slots[sl].y;

@@ -10,6 +10,7 @@ namespace mpmc {
 namespace sph {
 
 constexpr int kCap = 8;                  // spheres per cell (w < 2/sqrt(3))
+constexpr int kPrim = 4;                 // slots in a cell's primary line
 constexpr int kHistBins = 200;
 constexpr uint32_t kErrCapacity = 1u;    // a cell holds more than kCap spheres
 constexpr int kTile = 256;               // cells per rebin / histogram workgroup
@@ -46,6 +47,17 @@ struct Geom3 {
     long long N;
     int n_moves;
 };
+
+// Slot i of cell c among the C cells' slots: slots 0..3 sit in the cell's
+// 64-byte primary line (4 c + i), slots 4..7 -- needed only by the rare
+// cells with more than four spheres -- in an overflow region after every
+// primary line (4 C + 4 c + i - 4).  A cell's usual spheres then share one
+// 64-byte line, half the bytes of eight slots.
+__host__ __device__ inline size_t slot_of(int C, int c, int i)
+{
+    return i < kPrim ? (size_t)c * kPrim + (size_t)i
+                     : (size_t)kPrim * (size_t)C + (size_t)c * kPrim + (size_t)(i - kPrim);
+}
 
 // Sub-sweep workgroups for `lanes` (1, 2 or 4) lanes per active cell, and
 // the counter partials: two u64 (trials, accepts) per workgroup of the

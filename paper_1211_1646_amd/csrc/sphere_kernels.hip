@@ -7,9 +7,11 @@
 //
 // Data layout in device memory:
 //   count[C]    uint32 spheres per cell, c = (cz m_y + cy) m_x + cx;
-//   pos[C][8]   float4 (x, y, z, 0) cell-local coordinates in (0, w], slots
-//               [0, count) used -- one cell is one 128-byte line;
-//   tag[C][8]   uint32 identity of each sphere (optional).
+//   pos[8 C]    float4 (x, y, z, 0) cell-local coordinates in (0, w], slots
+//               [0, count) used: slots 0..3 of cell c in its 64-byte primary
+//               line at 4 c, slots 4..7 in an overflow region at 4 C + 4 c
+//               (slot_of);
+//   tag[8 C]    uint32 identity of each sphere (optional), same slots.
 // A sub-sweep writes only the active cells' own slots and reads their 26
 // inactive neighbours, so it updates in place; the rebin writes the other
 // ping-pong half.
@@ -167,7 +169,7 @@ __device__ bool overlap_from_memory(const Geom3 &g, const float4 *__restrict__ p
         const int nc = (nz * g.m[1] + ny) * g.m[0] + nx;
         const uint32_t cn = min(count[nc], (uint32_t)kCap);
         for (uint32_t j = 0; j < cn; ++j) {
-            const float4 v = pos[(size_t)nc * kCap + j];
+            const float4 v = pos[slot_of(g.C, nc, (int)j)];
             const float dx = xm - frame(v.x, ox, g.w[0]);
             const float dy = ym - frame(v.y, oy, g.w[1]);
             const float dz = zm - frame(v.z, oz, g.w[2]);
@@ -222,7 +224,7 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     const int Y[3] = {wrap_dn(cy, g.m[1]), cy, wrap_up(cy, g.m[1])};
     const int Z[3] = {wrap_dn(cz, g.m[2]), cz, wrap_up(cz, g.m[2])};
     const int c = (cz * g.m[1] + cy) * g.m[0] + cx;
-    const size_t b0 = (size_t)c * kCap;
+    const size_t b0 = (size_t)c * kPrim;   // the own primary line
 
     // 1. in one round trip: the own count and slots, and for each of this
     // lane's neighbour cells (entries h NB .. h NB + NB - 1 of the 26, in
@@ -234,7 +236,8 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     uint32_t tg[kCap];
 #pragma unroll
     for (int q = 0; q < kCap; ++q) {
-        const float4 v = pos[b0 + (size_t)q];
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (q < kPrim) v = pos[b0 + (size_t)q];   // the primary line, unconditionally
         px[q] = v.x;
         py[q] = v.y;
         pz[q] = v.z;
@@ -243,7 +246,7 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     const bool has_tag = tag != nullptr;
     if (has_tag) {
 #pragma unroll
-        for (int q = 0; q < kCap; ++q) tg[q] = tag[b0 + (size_t)q];
+        for (int q = 0; q < kPrim; ++q) tg[q] = tag[b0 + (size_t)q];
     }
     int cq[NB], oq[NB];       // neighbour cell and its offset code q
     uint32_t nn[NB];
@@ -259,7 +262,7 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
         const uint32_t cnt_j = count[cell];
         nn[j] = valid ? cnt_j : 0u;
 #pragma unroll
-        for (int u = 0; u < kU; ++u) v0[j][u] = pos[(size_t)cell * kCap + (size_t)u];
+        for (int u = 0; u < kU; ++u) v0[j][u] = pos[(size_t)cell * kPrim + (size_t)u];
     }
     uint4 Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle, k0, k1);
     uint4 W = make_uint4(0, 0, 0, 0);
@@ -277,6 +280,22 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     const int n = skip ? 0 : (int)n_raw;
     if (n == 0) nmax = 0;
     nmax = min(nmax, (uint32_t)kCap);
+
+    // own slots 4..7, only where some lane of the wave has more than four
+    // spheres (out-of-range offsets read nothing for the others)
+    const __amdgpu_buffer_rsrc_t slots = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)pos, (short)0, (int)((unsigned)g.C * (unsigned)(kCap * sizeof(float4))), kBufferWord3);
+    if (__ballot(n > kPrim) != 0ull) {
+#pragma unroll
+        for (int q = kPrim; q < kCap; ++q) {
+            const int off = n > q ? (int)slot_of(g.C, c, q) * (int)sizeof(float4) : kPastEnd;
+            const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(slots, off, 0, 0));
+            px[q] = v.x;
+            py[q] = v.y;
+            pz[q] = v.z;
+            if (has_tag && n > q) tg[q] = tag[slot_of(g.C, c, q)];
+        }
+    }
 
     // The box that holds every trial position of this cell update: a sphere
     // of the cell moves at most k = ceil(n_M / n) times, each time by at most
@@ -338,15 +357,13 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     // a slot a lane does not need gets an offset past the buffer's end,
     // which the hardware's range check turns into zeros without a memory
     // access, so neither a branch nor a wasted cache line is spent on it.
-    const __amdgpu_buffer_rsrc_t slots = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)pos, (short)0, (int)((unsigned)g.C * (unsigned)(kCap * sizeof(float4))), kBufferWord3);
     for (int i = kU; i < kCap; ++i) {
         if (__ballot(nmax > (uint32_t)i) == 0ull) break;
         float4 v[NB];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             const bool need = nmax > (uint32_t)i && nn[j] > (uint32_t)i;
-            const int off = need ? (cq[j] * kCap + i) * (int)sizeof(float4) : kPastEnd;
+            const int off = need ? (int)slot_of(g.C, cq[j], i) * (int)sizeof(float4) : kPastEnd;
             v[j] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(slots, off, 0, 0));
         }
 #pragma unroll
@@ -442,8 +459,9 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
                 if (q < n) {
                     int o = q + r0;
                     o = o >= n ? o - n : o;
-                    pos[b0 + (size_t)o] = make_float4(px[q], py[q], pz[q], 0.0f);
-                    if (has_tag && n > 1) tag[b0 + (size_t)o] = tg[q];
+                    const size_t so = slot_of(g.C, c, o);
+                    pos[so] = make_float4(px[q], py[q], pz[q], 0.0f);
+                    if (has_tag && n > 1) tag[so] = tg[q];
                 }
             }
         }
@@ -535,14 +553,25 @@ __global__ void __launch_bounds__(kTile) k_rebin3(Rebin3Args a)
         else if (ax == 1) n3[1] = nv;
         else n3[2] = nv;
         const int nc = (n3[2] * g.m[1] + n3[1]) * g.m[0] + n3[0];
-        const size_t ob = (size_t)c * kCap, nbb = (size_t)nc * kCap;
         int no = (int)a.count[c];
         int nn = (int)a.count[nc];
+        // both primary lines with the counts; the overflow slots only for
+        // cells with more than four spheres
         float4 own[kCap], nb[kCap];
 #pragma unroll
         for (int i = 0; i < kCap; ++i) {
-            own[i] = a.pos[ob + (size_t)i];
-            nb[i] = a.pos[nbb + (size_t)i];
+            own[i] = nb[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (i < kPrim) {
+                own[i] = a.pos[slot_of(g.C, c, i)];
+                nb[i] = a.pos[slot_of(g.C, nc, i)];
+            }
+        }
+        if (no > kPrim || nn > kPrim) {
+#pragma unroll
+            for (int i = kPrim; i < kCap; ++i) {
+                if (i < no) own[i] = a.pos[slot_of(g.C, c, i)];
+                if (i < nn) nb[i] = a.pos[slot_of(g.C, nc, i)];
+            }
         }
         if (no > kCap || nn > kCap) {
             atomicOr(&ctl->errword, kErrCapacity);
@@ -564,32 +593,31 @@ __global__ void __launch_bounds__(kTile) k_rebin3(Rebin3Args a)
         if (k > (unsigned)kCap) atomicOr(&ctl->errword, kErrCapacity);
         a.count_out[c] = k > (unsigned)kCap ? (unsigned)kCap : k;
         const bool has_tag = a.tag != nullptr;
-        size_t o = ob;
-        const size_t oe = ob + (size_t)kCap;
+        int o = 0;   // next slot of the new list (never past the cell's 8)
 #pragma unroll
         for (int i = 0; i < kCap; ++i) {
-            if ((stay & (1u << i)) && o < oe) {
+            if ((stay & (1u << i)) && o < kCap) {
                 float4 v = own[i];
                 if (ax == 0) v.x = to[i];
                 else if (ax == 1) v.y = to[i];
                 else v.z = to[i];
                 v.w = 0.0f;
-                a.pos_out[o] = v;
-                if (has_tag) a.tag_out[o] = a.tag[ob + (size_t)i];
+                a.pos_out[slot_of(g.C, c, o)] = v;
+                if (has_tag) a.tag_out[slot_of(g.C, c, o)] = a.tag[slot_of(g.C, c, i)];
             }
             o += (stay >> i) & 1u;
         }
 #pragma unroll
         for (int i = 0; i < kCap; ++i) {
-            if ((leave & (1u << i)) && o < oe) {
+            if ((leave & (1u << i)) && o < kCap) {
                 float4 v = nb[i];
                 const float t2 = tn[i] + sw;
                 if (ax == 0) v.x = t2;
                 else if (ax == 1) v.y = t2;
                 else v.z = t2;
                 v.w = 0.0f;
-                a.pos_out[o] = v;
-                if (has_tag) a.tag_out[o] = a.tag[nbb + (size_t)i];
+                a.pos_out[slot_of(g.C, c, o)] = v;
+                if (has_tag) a.tag_out[slot_of(g.C, c, o)] = a.tag[slot_of(g.C, nc, i)];
             }
             o += (leave >> i) & 1u;
         }
@@ -656,7 +684,7 @@ k_pair_hist3(Geom3 g, Ctl3 *ctl, const float4 *__restrict__ pos,
         const float e0 = E[0], eN = E[kHistBins];
         const uint32_t nk = min(count[c], (uint32_t)kCap);
         for (uint32_t k = 0; k < nk; ++k) {
-            const float4 pk = pos[(size_t)c * kCap + k];
+            const float4 pk = pos[slot_of(g.C, c, (int)k)];
             for (int oz = -Rr[2]; oz <= Rr[2]; ++oz) {
                 const int ncz = (cz + oz + 2 * g.m[2]) % g.m[2];
                 const float tz = (float)oz * g.w[2];
@@ -669,7 +697,7 @@ k_pair_hist3(Geom3 g, Ctl3 *ctl, const float4 *__restrict__ pos,
                         const int nc = (ncz * g.m[1] + ncy) * g.m[0] + ncx;
                         for (uint32_t j = 0, je = min(count[nc], (uint32_t)kCap); j < je; ++j) {
                             if (nc == c && j == k) continue;
-                            const float4 v = pos[(size_t)nc * kCap + j];
+                            const float4 v = pos[slot_of(g.C, nc, (int)j)];
                             const float ddx = pk.x - (v.x + tx);
                             const float ddy = pk.y - (v.y + ty);
                             const float ddz = pk.z - (v.z + tz);
@@ -790,7 +818,7 @@ k_count_overlaps3(Geom3 g, Ctl3 *ctl, const float4 *__restrict__ pos,
         const int cx = c % g.m[0], cy = (c / g.m[0]) % g.m[1], cz = c / (g.m[0] * g.m[1]);
         const uint32_t nk = min(count[c], (uint32_t)kCap);
         for (uint32_t k = 0; k < nk; ++k) {
-            const float4 pk = pos[(size_t)c * kCap + k];
+            const float4 pk = pos[slot_of(g.C, c, (int)k)];
             for (int q = 0; q < 27; ++q) {
                 const int ox = q % 3 - 1, oy = (q / 3) % 3 - 1, oz = q / 9 - 1;
                 const int nx = (cx + ox + g.m[0]) % g.m[0];
@@ -799,7 +827,7 @@ k_count_overlaps3(Geom3 g, Ctl3 *ctl, const float4 *__restrict__ pos,
                 const int nc = (nz * g.m[1] + ny) * g.m[0] + nx;
                 for (uint32_t j = 0, je = min(count[nc], (uint32_t)kCap); j < je; ++j) {
                     if (nc == c && j == k) continue;
-                    const float4 v = pos[(size_t)nc * kCap + j];
+                    const float4 v = pos[slot_of(g.C, nc, (int)j)];
                     const float ddx = pk.x - frame(v.x, ox, g.w[0]);
                     const float ddy = pk.y - frame(v.y, oy, g.w[1]);
                     const float ddz = pk.z - frame(v.z, oz, g.w[2]);
