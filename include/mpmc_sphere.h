@@ -93,8 +93,8 @@ typedef struct mpmc_sphere_geometry {
 /* Device buffer sizes.  pos, count and tag are ping-pong pairs: each half
  * needs the reported size.  On the device the spheres sit in fixed slots,
  * MPMC_SPHERE_CAPACITY per cell, as float4 (x, y, z, 0), with a uint32
- * count per cell: slots 0..3 of cell c in its 64-byte primary line, slots
- * 4..7 in an overflow region after all primary lines. */
+ * count per cell: slots 0..1 of cell c in its 32-byte primary line, slots
+ * 2..7 in an overflow region after all primary lines. */
 typedef struct mpmc_sphere_buffer_sizes {
     size_t pos;   /* float4 per slot (cells x 8)                 */
     size_t count; /* uint32 per cell                             */

@@ -10,7 +10,7 @@ namespace mpmc {
 namespace sph {
 
 constexpr int kCap = 8;                  // spheres per cell (w < 2/sqrt(3))
-constexpr int kPrim = 4;                 // slots in a cell's primary line
+constexpr int kPrim = 2;                 // slots in a cell's primary line
 constexpr int kHistBins = 200;
 constexpr uint32_t kErrCapacity = 1u;    // a cell holds more than kCap spheres
 constexpr int kTile = 256;               // cells per rebin / histogram workgroup
@@ -48,15 +48,16 @@ struct Geom3 {
     int n_moves;
 };
 
-// Slot i of cell c among the C cells' slots: slots 0..3 sit in the cell's
-// 64-byte primary line (4 c + i), slots 4..7 -- needed only by the rare
-// cells with more than four spheres -- in an overflow region after every
-// primary line (4 C + 4 c + i - 4).  A cell's usual spheres then share one
-// 64-byte line, half the bytes of eight slots.
+// Slot i of cell c among the C cells' slots: slots 0..1 sit in the cell's
+// 32-byte primary line (2 c + i), slots 2..7 -- needed only by the cells
+// with more than two spheres, about one in ten at eta = 0.45 -- in an
+// overflow region after every primary line (2 C + 6 c + i - 2).  A cell's
+// usual spheres then share one 32-byte sector instead of a 128-byte line of
+// eight slots.
 __host__ __device__ inline size_t slot_of(int C, int c, int i)
 {
     return i < kPrim ? (size_t)c * kPrim + (size_t)i
-                     : (size_t)kPrim * (size_t)C + (size_t)c * kPrim + (size_t)(i - kPrim);
+                     : (size_t)kPrim * (size_t)C + (size_t)c * (kCap - kPrim) + (size_t)(i - kPrim);
 }
 
 // Sub-sweep workgroups for `lanes` (1, 2 or 4) lanes per active cell, and

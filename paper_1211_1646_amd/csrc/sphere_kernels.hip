@@ -8,8 +8,8 @@
 // Data layout in device memory:
 //   count[C]    uint32 spheres per cell, c = (cz m_y + cy) m_x + cx;
 //   pos[8 C]    float4 (x, y, z, 0) cell-local coordinates in (0, w], slots
-//               [0, count) used: slots 0..3 of cell c in its 64-byte primary
-//               line at 4 c, slots 4..7 in an overflow region at 4 C + 4 c
+//               [0, count) used: slots 0..1 of cell c in its 32-byte primary
+//               line at 2 c, slots 2..7 in an overflow region at 2 C + 6 c
 //               (slot_of);
 //   tag[8 C]    uint32 identity of each sphere (optional), same slots.
 // A sub-sweep writes only the active cells' own slots and reads their 26
@@ -281,7 +281,7 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     if (n == 0) nmax = 0;
     nmax = min(nmax, (uint32_t)kCap);
 
-    // own slots 4..7, only where some lane of the wave has more than four
+    // own overflow slots, only where some lane of the wave has more than kPrim
     // spheres (out-of-range offsets read nothing for the others)
     const __amdgpu_buffer_rsrc_t slots = __builtin_amdgcn_make_buffer_rsrc(
         (void *)pos, (short)0, (int)((unsigned)g.C * (unsigned)(kCap * sizeof(float4))), kBufferWord3);
@@ -556,7 +556,7 @@ __global__ void __launch_bounds__(kTile) k_rebin3(Rebin3Args a)
         int no = (int)a.count[c];
         int nn = (int)a.count[nc];
         // both primary lines with the counts; the overflow slots only for
-        // cells with more than four spheres
+        // cells with more than kPrim spheres
         float4 own[kCap], nb[kCap];
 #pragma unroll
         for (int i = 0; i < kCap; ++i) {
