@@ -197,7 +197,8 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
 {
     constexpr int NB = (26 + LPC - 1) / LPC;                  // neighbour cells per lane
     constexpr int kL = LPC == 1 ? kNbrList : (LPC == 2 ? 24 : 16);   // LDS list per lane
-    constexpr int kU = LPC == 4 ? 2 : 1;                      // slots loaded with the counts
+    // slots loaded with the counts: never past the primary line
+    constexpr int kU = (LPC == 4 ? 2 : 1) < kPrim ? (LPC == 4 ? 2 : 1) : kPrim;
     // entry k of lane l at [k][l] (the 64 lanes of a wave read 64 consecutive
     // words); row kL is a pad row that takes the writes of dropped entries,
     // so that no write needs a branch
@@ -262,7 +263,7 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
         const uint32_t cnt_j = count[cell];
         nn[j] = valid ? cnt_j : 0u;
 #pragma unroll
-        for (int u = 0; u < kU; ++u) v0[j][u] = pos[(size_t)cell * kPrim + (size_t)u];
+        for (int u = 0; u < kU; ++u) v0[j][u] = pos[slot_of(g.C, cell, u)];
     }
     uint4 Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle, k0, k1);
     uint4 W = make_uint4(0, 0, 0, 0);
