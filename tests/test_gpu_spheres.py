@@ -305,3 +305,30 @@ def test_argument_errors(gpu):
         G.set_state(bad, start, 0)
     assert e.value.status == L.MPMC_ESTATE
     G.close()
+
+
+def test_low_density_equation_of_state_on_the_gpu(gpu):
+    """The GPU chain's own pressure, from its device histogram and fit, at
+    eta = 0.1 against the hard-sphere virial series 1 + 4 eta + 10 eta^2 +
+    18.36 eta^3 + ... (1.5216); 32^3 spheres, 20 blocks of 100 histograms."""
+    from oracle import estimator as E
+    eta = 0.10
+    cfg = gpu.SphereConfig(lattice_nx=32, lattice_ny=32, lattice_nz=32, eta=eta, delta=0.55,
+                           n_moves=4, seed=17)
+    G = gpu.HardSphereSystem(cfg)
+    G.sweep(200)
+    rho = G.density
+    P = []
+    for b in range(20):
+        for k in range(100):
+            G.sweep(2)
+            G.pair_histogram(reset=(k == 0))
+        p, _, _, ns = G.pressure()
+        assert ns == 100
+        P.append(p / rho)
+    m, se = E.mean_and_error(P, min_blocks=8)
+    log("  beta P / rho = %.5f +- %.5f, virial series %.5f" % (m, se, E.virial_pressure_ratio_3d(eta)))
+    assert abs(m - E.virial_pressure_ratio_3d(eta)) < 4 * se + 2e-3, (m, se)
+    assert m - 1.4 > 3 * se
+    assert G.count_overlaps() == 0
+    G.close()
