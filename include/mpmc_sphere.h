@@ -161,6 +161,14 @@ mpmc_status mpmc_sphere_get_counters(mpmc_sphere_handle h, uint64_t *trials, uin
 mpmc_status mpmc_sphere_set_delta(mpmc_sphere_handle h, float delta);
 mpmc_status mpmc_sphere_get_delta(mpmc_sphere_handle h, float *delta);
 
+/* Plain acceptance tuner for equilibration (async): n_windows times, run
+ * window_sweeps sweeps, then with a = accepts/trials of that window set
+ * delta <- delta * clamp(a/0.3, 0.5, 2) in FP64, clamped to
+ * [1e-3, min(w)/2] and rounded once to FP32, on the device.  delta is a free
+ * parameter of the method (Sec. 3.3); freeze it (stop tuning) before
+ * sampling.  window_sweeps >= 1, n_windows >= 0. */
+mpmc_status mpmc_sphere_tune(mpmc_sphere_handle h, int32_t window_sweeps, int32_t n_windows);
+
 /* Accumulate the ordered-pair contact histogram of the current
  * configuration (Sec. 4's estimator in d = 3: 200 bins of width 1e-4 on
  * [1, 1.02), binned on FP32 r^2 edges (float)((1 + b 1e-4)^2)).  reset != 0

@@ -426,6 +426,10 @@ int sphere_set_state(sphere_sys *S, const float *xyz, const uint32_t *start, con
     return SPH_OK;
 }
 
+void sphere_set_delta(sphere_sys *S, float delta) { S->delta = delta; }
+
+float sphere_get_delta(const sphere_sys *S) { return S->delta; }
+
 void sphere_counters(const sphere_sys *S, uint64_t *trials, uint64_t *accepts)
 {
     *trials = S->trials;

@@ -52,6 +52,10 @@ def lib():
         L.sphere_pair_histogram.restype = None
         L.sphere_count_overlaps.argtypes = [vp]
         L.sphere_count_overlaps.restype = C.c_int64
+        L.sphere_set_delta.argtypes = [vp, C.c_float]
+        L.sphere_set_delta.restype = None
+        L.sphere_get_delta.argtypes = [vp]
+        L.sphere_get_delta.restype = C.c_float
         _L = L
     return _L
 
@@ -164,3 +168,10 @@ class SphereOracle:
 
     def count_overlaps(self):
         return int(lib().sphere_count_overlaps(self._h))
+
+    @property
+    def delta(self):
+        return np.float32(lib().sphere_get_delta(self._h))
+
+    def set_delta(self, delta):
+        lib().sphere_set_delta(self._h, np.float32(delta))

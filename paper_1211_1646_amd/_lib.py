@@ -166,6 +166,7 @@ _SIGNATURES = {
     "mpmc_sphere_get_counters": (C.c_int32, [_H, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "mpmc_sphere_set_delta": (C.c_int32, [_H, C.c_float]),
     "mpmc_sphere_get_delta": (C.c_int32, [_H, C.POINTER(C.c_float)]),
+    "mpmc_sphere_tune": (C.c_int32, [_H, C.c_int32, C.c_int32]),
     "mpmc_sphere_pair_histogram": (C.c_int32, [_H, C.c_int32]),
     "mpmc_sphere_pressure": (C.c_int32, [_H, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                          C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),

@@ -522,6 +522,21 @@ mpmc_status mpmc_sphere_get_delta(mpmc_sphere_handle h, float *delta)
     return MPMC_OK;
 }
 
+mpmc_status mpmc_sphere_tune(mpmc_sphere_handle h, int32_t window_sweeps, int32_t n_windows)
+{
+    if (!h || window_sweeps < 1 || n_windows < 0) return fail(MPMC_EINVAL, "bad tuner arguments");
+    SPH_NEED_STATE(h);
+    SPH_HIP(mpmc::sph::launch_fold3(h->g, h->ctl, h->cnt, h->st));
+    SPH_HIP(mpmc::sph::launch_tune3(h->g, h->ctl, 0, h->st));   // open the first window
+    for (int w = 0; w < n_windows; ++w) {
+        const mpmc_status s = run_sweeps(h, window_sweeps);
+        if (s) return s;
+        SPH_HIP(mpmc::sph::launch_fold3(h->g, h->ctl, h->cnt, h->st));
+        SPH_HIP(mpmc::sph::launch_tune3(h->g, h->ctl, 1, h->st));
+    }
+    return MPMC_OK;
+}
+
 mpmc_status mpmc_sphere_pair_histogram(mpmc_sphere_handle h, int32_t reset)
 {
     SPH_NEED_STATE(h);

@@ -24,6 +24,8 @@ constexpr int kNbrList = 32;             // reachable neighbours a lane keeps in
 struct alignas(256) Ctl3 {
     unsigned long long sweep_at[2];
     unsigned long long trials, accepts;   // folded counters
+    unsigned long long win_trials;        // counters at the start of the tuner window
+    unsigned long long win_accepts;
     unsigned int key0, key1;
     float delta;
     unsigned int errword;
@@ -82,6 +84,9 @@ hipError_t launch_rebin3(const Geom3 &g, Ctl3 *ctl, int par, const float4 *pos,
 hipError_t launch_ctl_reset3(const Geom3 &g, Ctl3 *ctl, unsigned long long sweep,
                              unsigned int key0, unsigned int key1, float delta, hipStream_t st);
 hipError_t launch_set_delta3(Ctl3 *ctl, float delta, hipStream_t st);
+// Plain acceptance tuner: apply == 0 only opens a window (records the
+// counters); call after launch_fold3.
+hipError_t launch_tune3(const Geom3 &g, Ctl3 *ctl, int apply, hipStream_t st);
 hipError_t launch_pair_hist3(const Geom3 &g, Ctl3 *ctl, const float4 *pos, const uint32_t *count,
                              int reset, hipStream_t st);
 hipError_t launch_pressure_fit3(const Geom3 &g, Ctl3 *ctl, hipStream_t st);

@@ -642,6 +642,7 @@ k_ctl_reset3(Geom3 g, Ctl3 *ctl, unsigned long long sweep, unsigned int key0, un
     for (int i = threadIdx.x; i < kHistBins; i += blockDim.x) ctl->hist[i] = 0ull;
     if (threadIdx.x == 0) {
         ctl->trials = ctl->accepts = 0ull;
+        ctl->win_trials = ctl->win_accepts = 0ull;
         ctl->key0 = key0;
         ctl->key1 = key1;
         ctl->delta = delta;
@@ -657,6 +658,29 @@ k_ctl_reset3(Geom3 g, Ctl3 *ctl, unsigned long long sweep, unsigned int key0, un
 }
 
 __global__ void k_set_delta3(Ctl3 *ctl, float delta) { ctl->delta = delta; }
+
+// The plain tuner between equilibration windows: with a = accepts / trials
+// of the window, delta <- delta clamp(a / 0.3, 0.5, 2), clamped to
+// [1e-3, min(w) / 2], in FP64 and rounded once to FP32 (the same rule as
+// for disks, with the smallest of three widths).
+__global__ void k_tune3(Geom3 g, Ctl3 *ctl, int apply)
+{
+    const unsigned long long tr = ctl->trials - ctl->win_trials;
+    const unsigned long long a = ctl->accepts - ctl->win_accepts;
+    if (apply && tr > 0) {
+        double q = ((double)a / (double)tr) / 0.3;
+        if (q < 0.5) q = 0.5;
+        if (q > 2.0) q = 2.0;
+        double nd = (double)ctl->delta * q;
+        const float wmin = fminf(g.w[0], fminf(g.w[1], g.w[2]));
+        const double hi = 0.5 * (double)wmin;
+        if (nd < 1e-3) nd = 1e-3;
+        if (nd > hi) nd = hi;
+        ctl->delta = (float)nd;
+    }
+    ctl->win_trials = ctl->trials;
+    ctl->win_accepts = ctl->accepts;
+}
 
 // ------------------------------------------------------ pair histogram
 // Ordered pairs (k, j != k) with r^2 in k's frame, translations o w with
@@ -908,6 +932,12 @@ hipError_t launch_ctl_reset3(const Geom3 &g, Ctl3 *ctl, unsigned long long sweep
 hipError_t launch_set_delta3(Ctl3 *ctl, float delta, hipStream_t st)
 {
     hipLaunchKernelGGL(k_set_delta3, dim3(1), dim3(1), 0, st, ctl, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_tune3(const Geom3 &g, Ctl3 *ctl, int apply, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tune3, dim3(1), dim3(1), 0, st, g, ctl, apply);
     return hipGetLastError();
 }
 

@@ -124,6 +124,11 @@ class HardSphereSystem:
     def set_delta(self, delta: float):
         L.check(self.lib.mpmc_sphere_set_delta(self._h, float(delta)))
 
+    def tune(self, window_sweeps: int, n_windows: int):
+        """Plain acceptance tuner: n_windows windows of window_sweeps sweeps,
+        delta rescaled towards 30 % acceptance after each (on the device)."""
+        L.check(self.lib.mpmc_sphere_tune(self._h, int(window_sweeps), int(n_windows)))
+
     def delta(self) -> np.float32:
         v = C.c_float()
         L.check(self.lib.mpmc_sphere_get_delta(self._h, C.byref(v)))

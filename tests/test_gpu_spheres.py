@@ -247,6 +247,30 @@ def test_launch_shapes_give_one_chain(gpu):
         assert st[2] == states[0][2] and st[4] == states[0][4]
 
 
+@pytest.mark.parametrize("window", [10, 17])
+def test_plain_tuner_matches_the_oracle(gpu, window):
+    """mpmc_sphere_tune against the oracle stepped window by window with the
+    tuner rule (the disks' rule with the smallest of the three widths); a
+    17-sweep window runs one captured graph and one direct sweep."""
+    from oracle import tuned_delta
+    G, O = lattice_pair(gpu, (12, 12, 12), 0.45, delta=0.3, n_moves=4, seed=23)
+    G.tune(window, 5)
+    deltas = [O.delta]
+    for _ in range(5):
+        t0, a0 = O.counters()
+        O.sweep(window)
+        t1, a1 = O.counters()
+        O.set_delta(tuned_delta(O.delta, t1 - t0, a1 - a0, min(O.w[0], O.w[1]), O.w[2]))
+        deltas.append(O.delta)
+    log("  delta by window: %s" % ", ".join("%.5f" % d for d in deltas))
+    assert G.delta() == O.delta and O.delta != deltas[0]
+    assert_same(G, O, "after tuning")
+    G.sweep(7)
+    O.sweep(7)
+    assert_same(G, O, "7 sweeps after tuning")
+    G.close()
+
+
 def test_pair_histogram_and_pressure(gpu):
     G, O = lattice_pair(gpu, (12, 12, 12), 0.4, delta=0.15, n_moves=4, seed=13)
     hist = np.zeros(200, np.float64)
@@ -282,7 +306,8 @@ def test_argument_errors(gpu):
     G, _ = lattice_pair(gpu, (10, 10, 10), 0.3)
     for call in (lambda: G.subsweep(8), lambda: G.subsweep(-1), lambda: G.shift(6, 0.1),
                  lambda: G.shift(0, 0.6), lambda: G.set_delta(0.6), lambda: G.set_delta(0.0),
-                 lambda: G.set_launch(3), lambda: G.set_launch(8)):
+                 lambda: G.set_launch(3), lambda: G.set_launch(8), lambda: G.tune(0, 1),
+                 lambda: G.tune(5, -1)):
         with pytest.raises(L.MPMCError) as e:
             call()
         assert e.value.status == L.MPMC_EINVAL
