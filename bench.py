@@ -26,8 +26,9 @@ compare the batched and learned-controller forms with the plain form:
              in-circle moves of radius 0.16, n_M = 4, N = 253^2 .. 3040^2,
              median eta of 11 runs next to the paper's K20 figures;
   spheres -- the same chain in three dimensions: 100^3 hard spheres at
-             eta = 0.45, n_M = 4, delta = 0.05, trial moves per second and
-             the sub-sweep kernel against the HBM peak.
+             eta = 0.45, n_M = 4, delta tuned to about 30 % acceptance during
+             warm-up, trial moves per second and the sub-sweep kernel against
+             the HBM peak.
 """
 from __future__ import annotations
 
@@ -139,10 +140,11 @@ def spheres_leg(args):
     return r
 
 
-def cpu_baseline_spheres():
-    """The 3D oracle on three sweeps of the same 100^3-sphere workload."""
+def cpu_baseline_spheres(delta):
+    """The 3D oracle on three sweeps of the same 100^3-sphere workload (the
+    GPU leg's tuned delta, from the lattice)."""
     from oracle.spheres import SphereOracle
-    O = SphereOracle.lattice(100, 100, 100, 0.45, delta=0.05, n_moves=4, seed=1)
+    O = SphereOracle.lattice(100, 100, 100, 0.45, delta=delta, n_moves=4, seed=1)
     t0 = time.perf_counter()
     O.sweep(3)
     dt = time.perf_counter() - t0
@@ -599,7 +601,7 @@ def main():
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args, geo, trials / args.steps)
         if not args.no_spheres:
-            out["cpu_baseline"]["spheres"] = cpu_baseline_spheres()
+            out["cpu_baseline"]["spheres"] = cpu_baseline_spheres(out["spheres"]["delta"])
     print(json.dumps(out), flush=True)
 
 

@@ -2,11 +2,13 @@
 
 Workload: side^3 spheres from the simple cubic lattice at packing fraction
 eta (default 100^3 = 1,000,000 at eta = 0.45, a fluid), cells narrower than
-2/sqrt(3) (92^3 cells, capacity 8), n_M = 4 trial moves per active cell,
-delta fixed.  After `warmup` sweeps, `steps` sweeps are timed with HIP
-events on the system's stream (trial moves per second); then the sub-sweep
-kernel alone: `kernel_samples` launches (the eight sets in turn) captured
-into one graph and replayed between two events.
+2/sqrt(3) (92^3 cells, capacity 8), n_M = 4 trial moves per active cell.
+The `warmup` sweeps run the plain tuner in windows of 10 sweeps (delta
+towards 30 % acceptance from the given start), then delta is frozen and
+`steps` sweeps are timed with HIP events on the system's stream (trial
+moves per second); then the sub-sweep kernel alone: `kernel_samples`
+launches (the eight sets in turn) captured into one graph and replayed
+between two events.
 
     python -m paper_1211_1646_amd.sphere_throughput --side 100 --eta 0.45
 
@@ -46,8 +48,11 @@ def measure(side: int = 100, eta: float = 0.45, n_moves: int = 4, delta: float =
     N, C = S.N, S.C
     if lanes:
         S.set_launch(lanes)
-    S.sweep(warmup)
+    windows = warmup // 10
+    S.tune(10, windows)
+    S.sweep(warmup - 10 * windows)
     S.synchronize()
+    delta = float(S.delta())
     tr0, ac0 = S.counters()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(S.stream)
@@ -76,10 +81,11 @@ def measure(side: int = 100, eta: float = 0.45, n_moves: int = 4, delta: float =
     bpl = algorithmic_bytes(N, C)
     achieved = bpl / (k_ms * 1e-3) / 1e9
     return {"workload": "hard spheres N=%d (%d^3 simple cubic lattice), eta=%.3f, cells %dx%dx%d "
-                        "(w=%.5f, capacity 8), n_M=%d, delta=%.3f"
+                        "(w=%.5f, capacity 8), n_M=%d, delta=%.5f tuned to ~30%% acceptance"
                         % (N, side, eta, S.m[0], S.m[1], S.m[2], S.w[0], n_moves, delta),
             "trial_moves_per_s": trials / (ms * 1e-3), "us_per_sweep": ms * 1e3 / steps,
-            "steps": steps, "warmup": warmup, "acceptance": (ac1 - ac0) / max(trials, 1),
+            "steps": steps, "warmup": warmup, "delta": delta,
+            "acceptance": (ac1 - ac0) / max(trials, 1),
             "trial_moves_per_sweep": trials / steps, "overlaps_after": overlaps,
             "lanes_per_cell": lanes or "library default",
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -95,7 +101,7 @@ def main():
     ap.add_argument("--side", type=int, default=100)
     ap.add_argument("--eta", type=float, default=0.45)
     ap.add_argument("--n-moves", type=int, default=4)
-    ap.add_argument("--delta", type=float, default=0.05)
+    ap.add_argument("--delta", type=float, default=0.05, help="starting delta of the tuner")
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--kernel-samples", type=int, default=64)
