@@ -33,6 +33,9 @@
  *   S8 shift: as in 2D along the axis of f.
  *   S9 pair histogram: ordered pairs within reach, r^2 bins on FP32 edges
  *      (1 + b 1e-4)^2 computed in FP64.
+ *   S10 displacement accumulators: an accepted move adds its displacement
+ *      to the sphere's accumulator, one FP32 add per axis; accumulators go
+ *      with their sphere through shuffles and shifts and start at zero.
  * Every floating-point operation is one rounded FP32 operation in the order
  * written (compiled with -ffp-contract=off).
  */
@@ -64,6 +67,8 @@ typedef struct sphere_sys {
     int *n2;           /* shift double buffers */
     float *x2;
     uint32_t *tag2;
+    float *acc;        /* [C][SPH_CAP][3] displacement accumulated by accepted moves */
+    float *acc2;
     float delta;
     int n_moves;
     uint32_t key[2];
@@ -109,10 +114,13 @@ static sphere_sys *alloc_sys(const int m[3], const float w[3], int64_t N)
     S->n2 = (int *)calloc(C, sizeof(int));
     S->x = (float *)calloc(C * SPH_CAP * 3, sizeof(float));
     S->x2 = (float *)calloc(C * SPH_CAP * 3, sizeof(float));
+    S->acc = (float *)calloc(C * SPH_CAP * 3, sizeof(float));
+    S->acc2 = (float *)calloc(C * SPH_CAP * 3, sizeof(float));
     S->tag = (uint32_t *)calloc(C * SPH_CAP, sizeof(uint32_t));
     S->tag2 = (uint32_t *)calloc(C * SPH_CAP, sizeof(uint32_t));
-    if (!S->n || !S->n2 || !S->x || !S->x2 || !S->tag || !S->tag2) {
+    if (!S->n || !S->n2 || !S->x || !S->x2 || !S->tag || !S->tag2 || !S->acc || !S->acc2) {
         free(S->n); free(S->n2); free(S->x); free(S->x2); free(S->tag); free(S->tag2);
+        free(S->acc); free(S->acc2);
         free(S);
         return NULL;
     }
@@ -123,6 +131,7 @@ void sphere_destroy(sphere_sys *S)
 {
     if (!S) return;
     free(S->n); free(S->n2); free(S->x); free(S->x2); free(S->tag); free(S->tag2);
+    free(S->acc); free(S->acc2);
     free(S);
 }
 
@@ -256,6 +265,9 @@ static void swap_slots(sphere_sys *S, int a, int b)
     uint32_t u = S->tag[a];
     S->tag[a] = S->tag[b];
     S->tag[b] = u;
+    memcpy(t, &S->acc[3 * (size_t)a], sizeof t);
+    memcpy(&S->acc[3 * (size_t)a], &S->acc[3 * (size_t)b], sizeof t);
+    memcpy(&S->acc[3 * (size_t)b], t, sizeof t);
 }
 
 /* One cell update (the 3D Alg. 2): shuffle the list, then n_M trials on
@@ -287,6 +299,8 @@ static void cell_update(sphere_sys *S, const int cc[3])
         S->trials += 1;
         if (in_cell && !overlaps(S, cc, slot, xm)) {
             memcpy(p, xm, sizeof xm);
+            float *ac = &S->acc[3 * (size_t)slot];
+            for (int a = 0; a < 3; ++a) ac[a] = ac[a] + d[a];
             S->accepts += 1;
         }
     }
@@ -359,6 +373,8 @@ int sphere_shift(sphere_sys *S, int f, float d)
                         memcpy(q, p, sizeof q);
                         q[ax] = pass == 0 ? t : (sgn > 0 ? t + w : t - w);
                         memcpy(&S->x2[3 * (size_t)(c * SPH_CAP + k)], q, sizeof q);
+                        memcpy(&S->acc2[3 * (size_t)(c * SPH_CAP + k)], &S->acc[3 * (size_t)slot],
+                               3 * sizeof(float));
                         S->tag2[c * SPH_CAP + k] = S->tag[slot];
                         ++k;
                     }
@@ -366,6 +382,7 @@ int sphere_shift(sphere_sys *S, int f, float d)
                 S->n2[c] = k;
             }
     float *tf = S->x; S->x = S->x2; S->x2 = tf;
+    tf = S->acc; S->acc = S->acc2; S->acc2 = tf;
     uint32_t *tu = S->tag; S->tag = S->tag2; S->tag2 = tu;
     int *ti = S->n; S->n = S->n2; S->n2 = ti;
     return bad ? SPH_ESTATE : SPH_OK;
@@ -421,9 +438,19 @@ int sphere_set_state(sphere_sys *S, const float *xyz, const uint32_t *start, con
             S->tag[c * SPH_CAP + i] = tags ? tags[k] : k;
         }
     }
+    memset(S->acc, 0, sizeof(float) * 3 * SPH_CAP * (size_t)S->C);
     S->sweep = sweep;
     S->trials = S->accepts = 0;
     return SPH_OK;
+}
+
+/* Displacement accumulators acc[N][3] in cell (list) order. */
+void sphere_get_acc(const sphere_sys *S, float *acc)
+{
+    size_t k = 0;
+    for (int c = 0; c < S->C; ++c)
+        for (int i = 0; i < S->n[c]; ++i, ++k)
+            memcpy(&acc[3 * k], &S->acc[3 * (size_t)(c * SPH_CAP + i)], 3 * sizeof(float));
 }
 
 void sphere_set_delta(sphere_sys *S, float delta) { S->delta = delta; }

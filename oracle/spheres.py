@@ -52,6 +52,8 @@ def lib():
         L.sphere_pair_histogram.restype = None
         L.sphere_count_overlaps.argtypes = [vp]
         L.sphere_count_overlaps.restype = C.c_int64
+        L.sphere_get_acc.argtypes = [vp, f32p]
+        L.sphere_get_acc.restype = None
         L.sphere_set_delta.argtypes = [vp, C.c_float]
         L.sphere_set_delta.restype = None
         L.sphere_get_delta.argtypes = [vp]
@@ -168,6 +170,12 @@ class SphereOracle:
 
     def count_overlaps(self):
         return int(lib().sphere_count_overlaps(self._h))
+
+    def acc(self):
+        """Displacement accumulators [N, 3] in list order."""
+        out = np.zeros((self.N, 3), np.float32)
+        lib().sphere_get_acc(self._h, _p(out, C.c_float))
+        return out
 
     @property
     def delta(self):

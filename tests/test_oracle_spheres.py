@@ -265,3 +265,30 @@ def test_low_density_equation_of_state():
     m, se = E.mean_and_error(P, min_blocks=8)
     assert abs(m - E.virial_pressure_ratio_3d(eta)) < 4 * se + 2e-3, (m, se)
     assert m - 1.4 > 3 * se
+
+
+def test_accumulators_track_each_sphere_displacement():
+    """The accumulators (S10) equal each sphere's displacement since the start,
+    found independently from FP64 global positions by identity tag (minimum
+    image, less the grid shifts of the sweeps' draws): they add every
+    accepted move, follow their sphere through shuffles and shifts, and
+    start at zero."""
+    S = SphereOracle.lattice(10, 10, 10, 0.3, delta=0.2, n_moves=4, seed=5)
+    _, _, tags, _ = S.get_state()
+    x0 = np.zeros((S.N, 3))
+    x0[tags] = S.global_positions()
+    assert not S.acc().any()
+    S.sweep(40)
+    _, _, tags, _ = S.get_state()
+    L = np.array(S.box)
+    # global positions are taken on the shifted grid: every sweep's shift
+    # (S5, S8) translates all of them by -d (f even) or +d (f odd) along its axis
+    grid = np.zeros(3)
+    for s in range(40):
+        _, f, dd = S.draws(s)
+        grid[f // 2] += -float(dd) if f % 2 == 0 else float(dd)
+    d = S.global_positions() - x0[tags] - grid
+    d -= L * np.round(d / L)
+    a = S.acc().astype(np.float64)
+    assert np.abs(a).max() > 0.2
+    assert np.abs(d - a).max() < 1e-4
