@@ -75,7 +75,8 @@ typedef struct mpmc_sphere_params {
     int32_t n_moves;     /* n_M: trial moves per active cell per sub-sweep, >= 0  */
     uint32_t seed;       /* Philox key word 0                                     */
     uint32_t replica;    /* Philox key word 1                                     */
-    uint32_t flags;      /* 0 or MPMC_FLAG_TAG (keep per-sphere identity tags)    */
+    uint32_t flags;      /* MPMC_FLAG_TAG (identity tags), MPMC_FLAG_ACC          */
+                         /*   (displacement accumulators), or 0                   */
 } mpmc_sphere_params;
 
 /* Derived geometry.  The lattice's site (i, j, k) sits at
@@ -99,7 +100,8 @@ typedef struct mpmc_sphere_buffer_sizes {
     size_t pos;   /* float4 per slot (cells x 8)                 */
     size_t count; /* uint32 per cell                             */
     size_t tag;   /* uint32 per slot (MPMC_FLAG_TAG), else 0     */
-    size_t work;  /* counter partials of the sub-sweep           */
+    size_t acc;   /* float4 per slot (MPMC_FLAG_ACC), else 0     */
+    size_t work;  /* counter partials, MSD partials              */
     size_t ctl;   /* control block: sweep counter, key, delta,
                      counters, error word, contact histogram     */
 } mpmc_sphere_buffer_sizes;
@@ -108,6 +110,7 @@ typedef struct mpmc_sphere_buffers {
     void *pos[2];
     void *count[2];
     void *tag[2];  /* NULL unless MPMC_FLAG_TAG */
+    void *acc[2];  /* NULL unless MPMC_FLAG_ACC */
     void *work;
     void *ctl;
 } mpmc_sphere_buffers;
@@ -195,6 +198,16 @@ mpmc_status mpmc_sphere_count_overlaps(mpmc_sphere_handle h, int64_t *pairs);
  * results do not depend on it (sync: waits for the stream, drops the sweep
  * graphs). */
 mpmc_status mpmc_sphere_set_launch(mpmc_sphere_handle h, int32_t lanes_per_cell);
+
+/* Displacement accumulators (MPMC_FLAG_ACC): every accepted move adds its
+ * displacement, one FP32 add per axis, to its sphere's accumulator, which
+ * follows the sphere through shuffles and shifts; init, set_state and
+ * reset_acc zero them.  get_acc copies acc[3N] in list order (sync); msd
+ * gives mean |acc|^2 over the spheres, FP64 in a fixed order (sync);
+ * reset_acc zeroes them (async).  MPMC_EINVAL without the flag. */
+mpmc_status mpmc_sphere_get_acc(mpmc_sphere_handle h, float *acc);
+mpmc_status mpmc_sphere_msd(mpmc_sphere_handle h, double *msd);
+mpmc_status mpmc_sphere_reset_acc(mpmc_sphere_handle h);
 
 /* Wait for the handle's work; reports MPMC_EDEVICE for a set error word. */
 mpmc_status mpmc_sphere_synchronize(mpmc_sphere_handle h);

@@ -77,12 +77,12 @@ class SphereGeometry(C.Structure):
 
 class SphereBufferSizes(C.Structure):
     _fields_ = [("pos", C.c_size_t), ("count", C.c_size_t), ("tag", C.c_size_t),
-                ("work", C.c_size_t), ("ctl", C.c_size_t)]
+                ("acc", C.c_size_t), ("work", C.c_size_t), ("ctl", C.c_size_t)]
 
 
 class SphereBuffers(C.Structure):
     _fields_ = [("pos", C.c_void_p * 2), ("count", C.c_void_p * 2), ("tag", C.c_void_p * 2),
-                ("work", C.c_void_p), ("ctl", C.c_void_p)]
+                ("acc", C.c_void_p * 2), ("work", C.c_void_p), ("ctl", C.c_void_p)]
 
 
 class MPMCError(RuntimeError):
@@ -172,6 +172,9 @@ _SIGNATURES = {
                                          C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "mpmc_sphere_count_overlaps": (C.c_int32, [_H, C.POINTER(C.c_int64)]),
     "mpmc_sphere_set_launch": (C.c_int32, [_H, C.c_int32]),
+    "mpmc_sphere_get_acc": (C.c_int32, [_H, C.c_void_p]),
+    "mpmc_sphere_msd": (C.c_int32, [_H, C.POINTER(C.c_double)]),
+    "mpmc_sphere_reset_acc": (C.c_int32, [_H]),
     "mpmc_sphere_synchronize": (C.c_int32, [_H]),
     "mpmc_sphere_destroy": (None, [_H]),
     "mpmc_destroy": (None, [_H]),

@@ -29,7 +29,9 @@ struct mpmc_sphere {
     float4 *pos[2];
     uint32_t *count[2];
     uint32_t *tag[2];
+    float4 *acc[2];
     unsigned long long *cnt;
+    double *msd_part;   // per-tile partials of the MSD reduction (in the work buffer)
     Ctl3 *ctl;
     int cur;
     int lanes;   // sub-sweep lanes per active cell
@@ -82,8 +84,8 @@ mpmc_status derive(const mpmc_sphere_params *p, Geom3 &g)
 {
     if (!p) return fail(MPMC_EINVAL, "null argument");
     std::memset(&g, 0, sizeof g);
-    if (p->flags & ~(uint32_t)MPMC_FLAG_TAG)
-        return fail(MPMC_EINVAL, "spheres take no flag but MPMC_FLAG_TAG");
+    if (p->flags & ~(uint32_t)(MPMC_FLAG_TAG | MPMC_FLAG_ACC))
+        return fail(MPMC_EINVAL, "spheres take no flags but MPMC_FLAG_TAG and MPMC_FLAG_ACC");
     if (p->n_moves < 0 || p->n_moves > (1 << 20)) return fail(MPMC_EINVAL, "n_moves must lie in [0, 2^20]");
     int m[3];
     float w[3];
@@ -129,12 +131,20 @@ mpmc_status derive(const mpmc_sphere_params *p, Geom3 &g)
     return MPMC_OK;
 }
 
+// The work buffer: sub-sweep counter partials, then the MSD partials.
+size_t counter_bytes(const Geom3 &g)
+{
+    return align256(2 * sizeof(unsigned long long) * (size_t)mpmc::sph::subsweep_groups(g));
+}
+
 void sizes_of(const mpmc_sphere_params *p, const Geom3 &g, mpmc_sphere_buffer_sizes *o)
 {
     o->pos = align256(sizeof(float4) * (size_t)g.C * kCap);
     o->count = align256(sizeof(uint32_t) * (size_t)g.C);
     o->tag = (p->flags & MPMC_FLAG_TAG) ? align256(sizeof(uint32_t) * (size_t)g.C * kCap) : 0;
-    o->work = align256(2 * sizeof(unsigned long long) * (size_t)mpmc::sph::subsweep_groups(g));
+    o->acc = (p->flags & MPMC_FLAG_ACC) ? o->pos : 0;
+    const size_t tiles = (size_t)((g.C + mpmc::sph::kTile - 1) / mpmc::sph::kTile);
+    o->work = counter_bytes(g) + align256(sizeof(double) * tiles);
     o->ctl = align256(sizeof(Ctl3));
 }
 
@@ -166,7 +176,8 @@ mpmc_status read_ctl(mpmc_sphere *h)
 mpmc_status enqueue_subsweep(mpmc_sphere *h, int set)
 {
     SPH_HIP(mpmc::sph::launch_subsweep3(h->g, h->ctl, h->cur, h->pos[h->cur], h->count[h->cur],
-                                        h->tag[h->cur], h->cnt, set, h->lanes, h->st));
+                                        h->tag[h->cur], h->acc[h->cur], h->cnt, set, h->lanes,
+                                        h->st));
     return MPMC_OK;
 }
 
@@ -174,8 +185,8 @@ mpmc_status enqueue_rebin(mpmc_sphere *h, int f, float d)
 {
     const int o = h->cur ^ 1;
     SPH_HIP(mpmc::sph::launch_rebin3(h->g, h->ctl, h->cur, h->pos[h->cur], h->count[h->cur],
-                                     h->tag[h->cur], h->pos[o], h->count[o], h->tag[o], f, d,
-                                     h->st));
+                                     h->tag[h->cur], h->acc[h->cur], h->pos[o], h->count[o],
+                                     h->tag[o], h->acc[o], f, d, h->st));
     h->cur = o;
     return MPMC_OK;
 }
@@ -271,6 +282,7 @@ mpmc_status upload(mpmc_sphere *h, const float *xyz, const uint32_t *start, uint
     SPH_HIP(mpmc::sph::launch_ctl_reset3(g, h->ctl, sweep, h->p.seed, h->p.replica, h->p.delta, h->st));
     SPH_HIP(hipMemsetAsync(h->cnt, 0, 2 * sizeof(unsigned long long) * (size_t)mpmc::sph::subsweep_groups(g),
                            h->st));
+    if (h->acc[0]) SPH_HIP(mpmc::sph::launch_zero4(h->acc[0], (long long)g.C * kCap, h->st));
     SPH_HIP(mpmc::sph::launch_count_overlaps3(g, h->ctl, h->pos[0], h->count[0], h->st));
     h->loaded = false;
     s = read_ctl(h);
@@ -376,10 +388,12 @@ mpmc_status mpmc_sphere_init(const mpmc_sphere_params *p, const mpmc_sphere_buff
     mpmc_status s = derive(p, g);
     if (s) return s;
     const bool want_tag = (p->flags & MPMC_FLAG_TAG) != 0;
+    const bool want_acc = (p->flags & MPMC_FLAG_ACC) != 0;
     for (int i = 0; i < 2; ++i) {
-        if (!b->pos[i] || !b->count[i] || (want_tag && !b->tag[i]))
+        if (!b->pos[i] || !b->count[i] || (want_tag && !b->tag[i]) || (want_acc && !b->acc[i]))
             return fail(MPMC_EINVAL, "missing device buffer");
-        if (((uintptr_t)b->pos[i] | (uintptr_t)b->count[i] | (uintptr_t)(want_tag ? b->tag[i] : nullptr)) & 255u)
+        if (((uintptr_t)b->pos[i] | (uintptr_t)b->count[i] | (uintptr_t)(want_tag ? b->tag[i] : nullptr) |
+             (uintptr_t)(want_acc ? b->acc[i] : nullptr)) & 255u)
             return fail(MPMC_EINVAL, "device buffers must be 256-byte aligned");
     }
     if (!b->work || !b->ctl || (((uintptr_t)b->work | (uintptr_t)b->ctl) & 255u))
@@ -392,8 +406,10 @@ mpmc_status mpmc_sphere_init(const mpmc_sphere_params *p, const mpmc_sphere_buff
         h->pos[i] = (float4 *)b->pos[i];
         h->count[i] = (uint32_t *)b->count[i];
         h->tag[i] = want_tag ? (uint32_t *)b->tag[i] : nullptr;
+        h->acc[i] = want_acc ? (float4 *)b->acc[i] : nullptr;
     }
     h->cnt = (unsigned long long *)b->work;
+    h->msd_part = (double *)((char *)b->work + counter_bytes(g));
     h->ctl = (Ctl3 *)b->ctl;
     h->cur = 0;
     h->lanes = kDefaultLanes;
@@ -591,6 +607,55 @@ mpmc_status mpmc_sphere_set_launch(mpmc_sphere_handle h, int32_t lanes_per_cell)
         drop_graphs(h);
         h->lanes = lanes_per_cell;
     }
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_sphere_get_acc(mpmc_sphere_handle h, float *acc)
+{
+    SPH_NEED_STATE(h);
+    if (!acc) return fail(MPMC_EINVAL, "null argument");
+    if (!h->acc[0]) return fail(MPMC_EINVAL, "accumulators need MPMC_FLAG_ACC");
+    const Geom3 &g = h->g;
+    std::vector<uint32_t> cnt((size_t)g.C);
+    std::vector<float4> slots((size_t)g.C * kCap);
+    SPH_HIP(hipMemcpyAsync(cnt.data(), h->count[h->cur], sizeof(uint32_t) * cnt.size(),
+                           hipMemcpyDeviceToHost, h->st));
+    SPH_HIP(hipMemcpyAsync(slots.data(), h->acc[h->cur], sizeof(float4) * slots.size(),
+                           hipMemcpyDeviceToHost, h->st));
+    const mpmc_status s = read_ctl(h);
+    if (s) return s;
+    size_t k = 0;
+    for (int c = 0; c < g.C; ++c) {
+        if (cnt[(size_t)c] > (uint32_t)kCap) return fail(MPMC_EDEVICE, "cell above capacity");
+        for (uint32_t i = 0; i < cnt[(size_t)c]; ++i, ++k) {
+            if ((long long)k >= g.N) return fail(MPMC_EDEVICE, "cell counts exceed N");
+            const float4 &v = slots[mpmc::sph::slot_of(g.C, c, (int)i)];
+            acc[3 * k] = v.x;
+            acc[3 * k + 1] = v.y;
+            acc[3 * k + 2] = v.z;
+        }
+    }
+    if ((long long)k != g.N) return fail(MPMC_EDEVICE, "cell counts do not add up to N");
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_sphere_msd(mpmc_sphere_handle h, double *msd)
+{
+    SPH_NEED_STATE(h);
+    if (!msd) return fail(MPMC_EINVAL, "null argument");
+    if (!h->acc[0]) return fail(MPMC_EINVAL, "the MSD needs MPMC_FLAG_ACC");
+    SPH_HIP(mpmc::sph::launch_msd3(h->g, h->ctl, h->acc[h->cur], h->count[h->cur], h->msd_part, h->st));
+    const mpmc_status s = read_ctl(h);
+    if (s) return s;
+    *msd = h->ctl_host.msd;
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_sphere_reset_acc(mpmc_sphere_handle h)
+{
+    SPH_NEED_STATE(h);
+    if (!h->acc[0]) return fail(MPMC_EINVAL, "accumulators need MPMC_FLAG_ACC");
+    SPH_HIP(mpmc::sph::launch_zero4(h->acc[h->cur], (long long)h->g.C * kCap, h->st));
     return MPMC_OK;
 }
 

@@ -38,6 +38,7 @@ struct alignas(256) Ctl3 {
     unsigned long long hist_samples;
     double fit[4];                        // P, g(sigma+), rho, status
     long long overlaps;
+    double msd;                           // mean |acc|^2
     unsigned long long hist[kHistBins];
 };
 
@@ -73,14 +74,20 @@ inline int subsweep_groups(const Geom3 &g) { return subsweep_tiles(g, 4); }
 inline int xcd_groups(int tiles) { return 8 * ((tiles + 7) / 8); }
 
 hipError_t launch_subsweep3(const Geom3 &g, Ctl3 *ctl, int par, float4 *pos,
-                            const uint32_t *count, uint32_t *tag, unsigned long long *cnt,
-                            int set, int lanes, hipStream_t st);
+                            const uint32_t *count, uint32_t *tag, float4 *acc,
+                            unsigned long long *cnt, int set, int lanes, hipStream_t st);
 hipError_t launch_fold3(const Geom3 &g, Ctl3 *ctl, unsigned long long *cnt, hipStream_t st);
 // f >= 0: explicit shift (f, d), sweep slot copied; f < 0: the sweep's own
 // draws, advance to the next sweep.
 hipError_t launch_rebin3(const Geom3 &g, Ctl3 *ctl, int par, const float4 *pos,
-                         const uint32_t *count, const uint32_t *tag, float4 *pos_out,
-                         uint32_t *count_out, uint32_t *tag_out, int f, float d, hipStream_t st);
+                         const uint32_t *count, const uint32_t *tag, const float4 *acc,
+                         float4 *pos_out, uint32_t *count_out, uint32_t *tag_out, float4 *acc_out,
+                         int f, float d, hipStream_t st);
+// Mean |acc|^2 over the spheres into ctl->msd (FP64, fixed order); part
+// holds ceil(C / kTile) doubles.
+hipError_t launch_msd3(const Geom3 &g, Ctl3 *ctl, const float4 *acc, const uint32_t *count,
+                       double *part, hipStream_t st);
+hipError_t launch_zero4(float4 *p, long long n, hipStream_t st);
 hipError_t launch_ctl_reset3(const Geom3 &g, Ctl3 *ctl, unsigned long long sweep,
                              unsigned int key0, unsigned int key1, float delta, hipStream_t st);
 hipError_t launch_set_delta3(Ctl3 *ctl, float delta, hipStream_t st);

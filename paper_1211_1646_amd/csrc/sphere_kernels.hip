@@ -11,7 +11,9 @@
 //               [0, count) used: slots 0..1 of cell c in its 32-byte primary
 //               line at 2 c, slots 2..7 in an overflow region at 2 C + 6 c
 //               (slot_of);
-//   tag[8 C]    uint32 identity of each sphere (optional), same slots.
+//   tag[8 C]    uint32 identity of each sphere (optional), same slots;
+//   acc[8 C]    float4 displacement accumulated by accepted moves (optional),
+//               same slots.
 // A sub-sweep writes only the active cells' own slots and reads their 26
 // inactive neighbours, so it updates in place; the rebin writes the other
 // ping-pong half.
@@ -193,7 +195,8 @@ template <int LPC>
 __global__ void __launch_bounds__(kSubBlock)
 k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
             const uint32_t *__restrict__ count, uint32_t *__restrict__ tag,
-            unsigned long long *__restrict__ cnt, int set, int ntile, int per)
+            float4 *__restrict__ acc, unsigned long long *__restrict__ cnt, int set, int ntile,
+            int per)
 {
     constexpr int NB = (26 + LPC - 1) / LPC;                  // neighbour cells per lane
     constexpr int kL = LPC == 1 ? kNbrList : (LPC == 2 ? 24 : 16);   // LDS list per lane
@@ -249,6 +252,19 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
 #pragma unroll
         for (int q = 0; q < kPrim; ++q) tg[q] = tag[b0 + (size_t)q];
     }
+    const bool has_acc = acc != nullptr;
+    float ax[kCap], ay[kCap], az[kCap];
+#pragma unroll
+    for (int q = 0; q < kCap; ++q) ax[q] = ay[q] = az[q] = 0.0f;
+    if (has_acc) {
+#pragma unroll
+        for (int q = 0; q < kPrim; ++q) {
+            const float4 v = acc[b0 + (size_t)q];
+            ax[q] = v.x;
+            ay[q] = v.y;
+            az[q] = v.z;
+        }
+    }
     int cq[NB], oq[NB];       // neighbour cell and its offset code q
     uint32_t nn[NB];
     float4 v0[NB][kU];
@@ -295,6 +311,12 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
             py[q] = v.y;
             pz[q] = v.z;
             if (has_tag && n > q) tg[q] = tag[slot_of(g.C, c, q)];
+            if (has_acc && n > q) {
+                const float4 u = acc[slot_of(g.C, c, q)];
+                ax[q] = u.x;
+                ay[q] = u.y;
+                az[q] = u.z;
+            }
         }
     }
 
@@ -402,6 +424,11 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
             rperm(py, P);
             rperm(pz, P);
             if (has_tag) rperm(tg, P);
+            if (has_acc) {
+                rperm(ax, P);
+                rperm(ay, P);
+                rperm(az, P);
+            }
         }
 #pragma unroll
         for (int q = 1; q < kCap; ++q) {
@@ -445,11 +472,21 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
             px[0] = ok ? xm : px[0];
             py[0] = ok ? ym : py[0];
             pz[0] = ok ? zm : pz[0];
+            if (has_acc) {
+                ax[0] = ok ? ax[0] + dx : ax[0];
+                ay[0] = ok ? ay[0] + dy : ay[0];
+                az[0] = ok ? az[0] + dz : az[0];
+            }
             n_acc += (ok && h == 0) ? 1u : 0u;
             rrot(px, n);   // the identity for n = 1
             rrot(py, n);
             rrot(pz, n);
             if (has_tag) rrot(tg, n);
+            if (has_acc) {
+                rrot(ax, n);
+                rrot(ay, n);
+                rrot(az, n);
+            }
         }
         if (h == 0) {
             n_trials = (unsigned)g.n_moves;
@@ -463,6 +500,7 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
                     const size_t so = slot_of(g.C, c, o);
                     pos[so] = make_float4(px[q], py[q], pz[q], 0.0f);
                     if (has_tag && n > 1) tag[so] = tg[q];
+                    if (has_acc) acc[so] = make_float4(ax[q], ay[q], az[q], 0.0f);
                 }
             }
         }
@@ -517,9 +555,11 @@ struct Rebin3Args {
     const float4 *pos;
     const uint32_t *count;
     const uint32_t *tag;
+    const float4 *acc;
     float4 *pos_out;
     uint32_t *count_out;
     uint32_t *tag_out;
+    float4 *acc_out;
     int par;
     int f;        // >= 0 explicit; < 0 the sweep's own
     float d;
@@ -605,6 +645,7 @@ __global__ void __launch_bounds__(kTile) k_rebin3(Rebin3Args a)
                 v.w = 0.0f;
                 a.pos_out[slot_of(g.C, c, o)] = v;
                 if (has_tag) a.tag_out[slot_of(g.C, c, o)] = a.tag[slot_of(g.C, c, i)];
+                if (a.acc) a.acc_out[slot_of(g.C, c, o)] = a.acc[slot_of(g.C, c, i)];
             }
             o += (stay >> i) & 1u;
         }
@@ -619,6 +660,7 @@ __global__ void __launch_bounds__(kTile) k_rebin3(Rebin3Args a)
                 v.w = 0.0f;
                 a.pos_out[slot_of(g.C, c, o)] = v;
                 if (has_tag) a.tag_out[slot_of(g.C, c, o)] = a.tag[slot_of(g.C, nc, i)];
+                if (a.acc) a.acc_out[slot_of(g.C, c, o)] = a.acc[slot_of(g.C, nc, i)];
             }
             o += (leave >> i) & 1u;
         }
@@ -872,24 +914,65 @@ k_count_overlaps3(Geom3 g, Ctl3 *ctl, const float4 *__restrict__ pos,
 
 __global__ void k_overlaps_reset3(Ctl3 *ctl) { ctl->overlaps = 0; }
 
+// ------------------------------------------------------------------ MSD
+// Mean |acc|^2 over the N spheres, FP64, in a fixed order: one partial per
+// tile of kTile cells (its lanes' sums folded in a fixed tree), then one
+// thread adds the partials in tile order.
+__global__ void __launch_bounds__(kTile)
+k_msd3_partial(Geom3 g, const float4 *__restrict__ acc, const uint32_t *__restrict__ count,
+               double *__restrict__ part)
+{
+    __shared__ double sh[kTile];
+    const int c = blockIdx.x * kTile + (int)threadIdx.x;
+    double v = 0.0;
+    if (c < g.C) {
+        const uint32_t n = min(count[c], (uint32_t)kCap);
+        for (uint32_t i = 0; i < n; ++i) {
+            const float4 a = acc[slot_of(g.C, c, (int)i)];
+            v += ((double)a.x * a.x + (double)a.y * a.y) + (double)a.z * a.z;
+        }
+    }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = kTile / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_msd3_final(Geom3 g, Ctl3 *ctl, const double *part, int nb)
+{
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[b];
+    ctl->msd = g.N > 0 ? s / (double)g.N : 0.0;
+}
+
+__global__ void k_zero4(float4 *p, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launches
 hipError_t launch_subsweep3(const Geom3 &g, Ctl3 *ctl, int par, float4 *pos,
-                            const uint32_t *count, uint32_t *tag, unsigned long long *cnt,
-                            int set, int lanes, hipStream_t st)
+                            const uint32_t *count, uint32_t *tag, float4 *acc,
+                            unsigned long long *cnt, int set, int lanes, hipStream_t st)
 {
     const int ntile = subsweep_tiles(g, lanes);
     const int grid = xcd_groups(ntile);
     if (lanes == 4)
         hipLaunchKernelGGL(k_subsweep3<4>, dim3(grid), dim3(kSubBlock), 0, st, g, ctl, par, pos,
-                           count, tag, cnt, set, ntile, grid / 8);
+                           count, tag, acc, cnt, set, ntile, grid / 8);
     else if (lanes == 2)
         hipLaunchKernelGGL(k_subsweep3<2>, dim3(grid), dim3(kSubBlock), 0, st, g, ctl, par, pos,
-                           count, tag, cnt, set, ntile, grid / 8);
+                           count, tag, acc, cnt, set, ntile, grid / 8);
     else
         hipLaunchKernelGGL(k_subsweep3<1>, dim3(grid), dim3(kSubBlock), 0, st, g, ctl, par, pos,
-                           count, tag, cnt, set, ntile, grid / 8);
+                           count, tag, acc, cnt, set, ntile, grid / 8);
     return hipGetLastError();
 }
 
@@ -900,8 +983,9 @@ hipError_t launch_fold3(const Geom3 &g, Ctl3 *ctl, unsigned long long *cnt, hipS
 }
 
 hipError_t launch_rebin3(const Geom3 &g, Ctl3 *ctl, int par, const float4 *pos,
-                         const uint32_t *count, const uint32_t *tag, float4 *pos_out,
-                         uint32_t *count_out, uint32_t *tag_out, int f, float d, hipStream_t st)
+                         const uint32_t *count, const uint32_t *tag, const float4 *acc,
+                         float4 *pos_out, uint32_t *count_out, uint32_t *tag_out, float4 *acc_out,
+                         int f, float d, hipStream_t st)
 {
     Rebin3Args a;
     a.g = g;
@@ -909,9 +993,11 @@ hipError_t launch_rebin3(const Geom3 &g, Ctl3 *ctl, int par, const float4 *pos,
     a.pos = pos;
     a.count = count;
     a.tag = tag;
+    a.acc = acc;
     a.pos_out = pos_out;
     a.count_out = count_out;
     a.tag_out = tag_out;
+    a.acc_out = acc_out;
     a.par = par;
     a.f = f;
     a.d = d;
@@ -919,6 +1005,22 @@ hipError_t launch_rebin3(const Geom3 &g, Ctl3 *ctl, int par, const float4 *pos,
     const int grid = xcd_groups(a.ntile);
     a.per = grid / 8;
     hipLaunchKernelGGL(k_rebin3, dim3(grid), dim3(kTile), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_msd3(const Geom3 &g, Ctl3 *ctl, const float4 *acc, const uint32_t *count,
+                       double *part, hipStream_t st)
+{
+    const int nb = (g.C + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_msd3_partial, dim3(nb), dim3(kTile), 0, st, g, acc, count, part);
+    hipLaunchKernelGGL(k_msd3_final, dim3(1), dim3(64), 0, st, g, ctl, part, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero4(float4 *p, long long n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero4, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 

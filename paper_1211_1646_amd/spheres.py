@@ -77,6 +77,7 @@ class HardSphereSystem:
 
         self._t = {k: [buf(sizes[k]), buf(sizes[k])] for k in ("pos", "count")}
         self._t["tag"] = [buf(sizes["tag"]), buf(sizes["tag"])] if sizes["tag"] else None
+        self._t["acc"] = [buf(sizes["acc"]), buf(sizes["acc"])] if sizes["acc"] else None
         self._work = buf(sizes["work"])
         self._ctl = buf(sizes["ctl"])
         b = L.SphereBuffers()
@@ -84,6 +85,7 @@ class HardSphereSystem:
             b.pos[i] = self._t["pos"][i].data_ptr()
             b.count[i] = self._t["count"][i].data_ptr()
             b.tag[i] = self._t["tag"][i].data_ptr() if self._t["tag"] else None
+            b.acc[i] = self._t["acc"][i].data_ptr() if self._t["acc"] else None
         b.work = self._work.data_ptr()
         b.ctl = self._ctl.data_ptr()
         self.stream = torch.cuda.Stream(device=self.device)
@@ -162,6 +164,21 @@ class HardSphereSystem:
         t, a = C.c_uint64(), C.c_uint64()
         L.check(self.lib.mpmc_sphere_get_counters(self._h, C.byref(t), C.byref(a)))
         return int(t.value), int(a.value)
+
+    def acc(self):
+        """Displacement accumulators [N, 3] in list order (MPMC_FLAG_ACC)."""
+        out = np.empty((self.N, 3), np.float32)
+        L.check(self.lib.mpmc_sphere_get_acc(self._h, out.ctypes.data))
+        return out
+
+    def msd(self) -> float:
+        """Mean |acc|^2 over the spheres, reduced on the device in FP64."""
+        v = C.c_double()
+        L.check(self.lib.mpmc_sphere_msd(self._h, C.byref(v)))
+        return v.value
+
+    def reset_acc(self):
+        L.check(self.lib.mpmc_sphere_reset_acc(self._h))
 
     def count_overlaps(self) -> int:
         v = C.c_int64()

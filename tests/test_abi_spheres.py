@@ -64,12 +64,15 @@ def test_sphere_required_bytes():
     assert s["count"] >= 4 * C_ and s["tag"] >= 4 * 8 * C_
     assert s["ctl"] > 0 and s["work"] > 0
     s0 = sphere_required_bytes(SphereConfig(lattice_nx=10, lattice_ny=10, lattice_nz=10, eta=0.3))
-    assert s0["tag"] == 0
+    assert s0["tag"] == 0 and s0["acc"] == 0
+    s1 = sphere_required_bytes(SphereConfig(lattice_nx=10, lattice_ny=10, lattice_nz=10, eta=0.3,
+                                            flags=L.FLAG_ACC))
+    assert s1["acc"] == s1["pos"] and s1["work"] >= 8 * ((C_ + 255) // 256)
 
 
 @pytest.mark.parametrize("kw,status", [
     (dict(lattice_nx=10, lattice_ny=10, lattice_nz=10, eta=0.6), L.MPMC_EINVAL),
-    (dict(lattice_nx=10, lattice_ny=10, lattice_nz=10, eta=0.3, flags=L.FLAG_ACC), L.MPMC_EINVAL),
+    (dict(lattice_nx=10, lattice_ny=10, lattice_nz=10, eta=0.3, flags=L.FLAG_DISK), L.MPMC_EINVAL),
     (dict(lattice_nx=10, lattice_ny=10, lattice_nz=10, eta=0.3, delta=0.6), L.MPMC_EINVAL),
     (dict(lattice_nx=10, lattice_ny=10, lattice_nz=10, eta=0.3, n_moves=-1), L.MPMC_EINVAL),
     (dict(lattice_nx=10, lattice_ny=10, lattice_nz=10, eta=0.3, cells_x=13), L.MPMC_EGEOM),

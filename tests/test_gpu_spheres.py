@@ -271,6 +271,31 @@ def test_plain_tuner_matches_the_oracle(gpu, window):
     G.close()
 
 
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_accumulators_and_msd_match_the_oracle(gpu, lanes):
+    """MPMC_FLAG_ACC: the accumulators bit for bit against the oracle's (S10)
+    after sweeps through graphs and shifts, the device MSD against the FP64
+    mean of the oracle's accumulators, and reset_acc."""
+    n, eta = (12, 10, 14), 0.45
+    cfg = gpu.SphereConfig(lattice_nx=n[0], lattice_ny=n[1], lattice_nz=n[2], eta=eta, delta=0.12,
+                           n_moves=5, seed=31, flags=gpu.FLAG_TAG | gpu.FLAG_ACC)
+    G = gpu.HardSphereSystem(cfg)
+    G.set_launch(lanes)
+    O = SphereOracle.lattice(*n, eta, delta=0.12, n_moves=5, seed=31)
+    assert not G.acc().any()
+    G.sweep(37)
+    O.sweep(37)
+    assert_same(G, O, "with accumulators")
+    ga, oa = G.acc(), O.acc()
+    assert np.abs(oa).max() > 0.1
+    assert np.array_equal(ga.view(np.uint32), oa.view(np.uint32)), "accumulators differ"
+    ref = float(np.mean(np.sum(oa.astype(np.float64) ** 2, axis=1)))
+    assert abs(G.msd() - ref) <= 1e-12 * ref
+    G.reset_acc()
+    assert not G.acc().any() and G.msd() == 0.0
+    G.close()
+
+
 def test_pair_histogram_and_pressure(gpu):
     G, O = lattice_pair(gpu, (12, 12, 12), 0.4, delta=0.15, n_moves=4, seed=13)
     hist = np.zeros(200, np.float64)
@@ -307,7 +332,7 @@ def test_argument_errors(gpu):
     for call in (lambda: G.subsweep(8), lambda: G.subsweep(-1), lambda: G.shift(6, 0.1),
                  lambda: G.shift(0, 0.6), lambda: G.set_delta(0.6), lambda: G.set_delta(0.0),
                  lambda: G.set_launch(3), lambda: G.set_launch(8), lambda: G.tune(0, 1),
-                 lambda: G.tune(5, -1)):
+                 lambda: G.tune(5, -1), lambda: G.acc(), lambda: G.msd(), lambda: G.reset_acc()):
         with pytest.raises(L.MPMCError) as e:
             call()
         assert e.value.status == L.MPMC_EINVAL
