@@ -191,7 +191,7 @@ __device__ __forceinline__ int cell_at(const Geom3 &g, const int X[3], const int
     return (z * g.m[1] + y) * g.m[0] + x;
 }
 
-template <int LPC>
+template <int LPC, bool ACC>
 __global__ void __launch_bounds__(kSubBlock)
 k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
             const uint32_t *__restrict__ count, uint32_t *__restrict__ tag,
@@ -252,7 +252,9 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
 #pragma unroll
         for (int q = 0; q < kPrim; ++q) tg[q] = tag[b0 + (size_t)q];
     }
-    const bool has_acc = acc != nullptr;
+    // accumulators are a compile-time variant, so that the plain chain
+    // carries no registers for them
+    constexpr bool has_acc = ACC;
     float ax[kCap], ay[kCap], az[kCap];
 #pragma unroll
     for (int q = 0; q < kCap; ++q) ax[q] = ay[q] = az[q] = 0.0f;
@@ -964,15 +966,18 @@ hipError_t launch_subsweep3(const Geom3 &g, Ctl3 *ctl, int par, float4 *pos,
 {
     const int ntile = subsweep_tiles(g, lanes);
     const int grid = xcd_groups(ntile);
-    if (lanes == 4)
-        hipLaunchKernelGGL(k_subsweep3<4>, dim3(grid), dim3(kSubBlock), 0, st, g, ctl, par, pos,
-                           count, tag, acc, cnt, set, ntile, grid / 8);
-    else if (lanes == 2)
-        hipLaunchKernelGGL(k_subsweep3<2>, dim3(grid), dim3(kSubBlock), 0, st, g, ctl, par, pos,
-                           count, tag, acc, cnt, set, ntile, grid / 8);
-    else
-        hipLaunchKernelGGL(k_subsweep3<1>, dim3(grid), dim3(kSubBlock), 0, st, g, ctl, par, pos,
-                           count, tag, acc, cnt, set, ntile, grid / 8);
+#define SPH_SUB(L, A)                                                                         \
+    hipLaunchKernelGGL((k_subsweep3<L, A>), dim3(grid), dim3(kSubBlock), 0, st, g, ctl, par, pos, \
+                       count, tag, acc, cnt, set, ntile, grid / 8)
+    const bool a = acc != nullptr;
+    if (lanes == 4) {
+        if (a) SPH_SUB(4, true); else SPH_SUB(4, false);
+    } else if (lanes == 2) {
+        if (a) SPH_SUB(2, true); else SPH_SUB(2, false);
+    } else {
+        if (a) SPH_SUB(1, true); else SPH_SUB(1, false);
+    }
+#undef SPH_SUB
     return hipGetLastError();
 }
 
