@@ -50,14 +50,17 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000, help="timed sweeps")
-    ap.add_argument("--warmup", type=int, default=200, help="untimed sweeps (tuner runs here)")
+    ap.add_argument("--steps", type=int, default=1000, help="timed sweeps (>= 1)")
+    ap.add_argument("--warmup", type=int, default=200,
+                    help="untimed sweeps after the fixed set-up (tuner, launch shape); < 0 reads as 0")
     ap.add_argument("--phi", type=float, default=0.70)
     ap.add_argument("--lattice", type=int, default=1024)
     ap.add_argument("--n-moves", type=int, default=4)
     ap.add_argument("--block", type=int, default=0,
                     help="sub-sweep workgroup size; 0 = pick the shape with the autotuner")
     ap.add_argument("--lanes", type=int, default=1, help="lanes per cell when --block is given")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the all-core oracle run (0 = every host core)")
     ap.add_argument("--kernel-samples", type=int, default=200,
                     help="sub-sweep launches timed one by one with HIP events")
     ap.add_argument("--cpu-sweeps", type=int, default=0,
@@ -81,27 +84,60 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(args, geo, trials_per_sweep_gpu):
-    """The CPU oracle (serial C, one thread) on the same workload: a bounded
-    number of sweeps from the same lattice, timed with a monotonic clock."""
+def host_cpu():
+    """Model name and logical core count of the host CPU."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, cores
+
+
+def cpu_baseline(args, geo):
+    """The CPU oracle on the same workload: a bounded number of sweeps from
+    the lattice, timed with a monotonic clock, once on one thread and once
+    with OpenMP over the active cells of each sub-sweep on every host core
+    (the cells of a set are independent, so the chain is the same)."""
     import oracle
-    O = oracle.OracleSystem.lattice(args.lattice, args.lattice, args.phi, w_max=math.sqrt(2.0),
-                                    delta=0.1, n_moves=args.n_moves, seed=1)
-    O.sweep(1)                                   # touch memory once
-    n = args.cpu_sweeps
-    if n <= 0:
+    model, ncores = host_cpu()
+    threads = args.cpu_threads if args.cpu_threads > 0 else ncores
+
+    def timed(nthreads, budget_s):
+        O = oracle.OracleSystem.lattice(args.lattice, args.lattice, args.phi, w_max=math.sqrt(2.0),
+                                        delta=0.1, n_moves=args.n_moves, seed=1)
+        used = O.set_threads(nthreads)
+        O.sweep(1)                                   # touch memory once
+        n = args.cpu_sweeps
+        if n <= 0:
+            t0 = time.perf_counter()
+            O.sweep(2)
+            per = (time.perf_counter() - t0) / 2
+            n = max(3, min(400, int(budget_s / max(per, 1e-6))))
+        tr0, _ = O.counters()
         t0 = time.perf_counter()
-        O.sweep(2)
-        per = (time.perf_counter() - t0) / 2
-        n = max(3, min(200, int(15.0 / max(per, 1e-6))))
-    tr0, _ = O.counters()
-    t0 = time.perf_counter()
-    O.sweep(n)
-    dt = time.perf_counter() - t0
-    tr1, _ = O.counters()
-    return {"value": (tr1 - tr0) / dt, "unit": "trial moves/s", "cores": 1, "kind": "oracle",
-            "sample": "%d sweeps of the %d-disk workload from the lattice (%d trial moves, %.1f s, "
-                      "serial C oracle, one thread)" % (n, geo["n_particles"], tr1 - tr0, dt)}
+        O.sweep(n)
+        dt = time.perf_counter() - t0
+        tr1, _ = O.counters()
+        return (tr1 - tr0) / dt, n, tr1 - tr0, dt, used
+
+    v1, n1, t1, d1, _ = timed(1, 12.0)
+    vall, nall, tall, dall, used = timed(threads, 8.0)
+    return {"value": vall, "unit": "trial moves/s", "cores": used, "kind": "oracle",
+            "sample": "%d sweeps of the %d-disk workload from the lattice (%d trial moves, %.1f s), "
+                      "C oracle with OpenMP over the active cells of each sub-sweep on %d threads"
+                      % (nall, geo["n_particles"], tall, dall, used),
+            "host_cpu": model, "host_logical_cores": ncores,
+            "one_thread": {"value": v1, "unit": "trial moves/s", "cores": 1,
+                           "sample": "%d sweeps (%d trial moves, %.1f s), serial C oracle"
+                                     % (n1, t1, d1)}}
 
 
 def traffic_from_profile(kernel_src, kernel_name, key="hbm bytes per launch",
@@ -441,12 +477,69 @@ def learned_leg(args, pkg, torch, lanes_main, block_main):
             "P_diff_in_combined_se": abs(le["P"] - pl["P"]) / comb if comb > 0 else None}, net
 
 
+TUNER_WINDOWS = 20          # plain tuner during set-up: 20 windows ...
+TUNER_WINDOW_SWEEPS = 10    # ... of 10 sweeps (delta to ~30 % acceptance, then frozen)
+GRAPH_SWEEPS = 16           # sweeps per captured graph in the library
+
+
+def warmup_plan(warmup: int, steps: int) -> dict:
+    """Untimed work before the timed sweeps.  A fixed set-up -- the plain
+    tuner over TUNER_WINDOWS windows, then (unless a launch shape is given)
+    the launch-shape autotuner -- and then `warmup` extra sweeps, read as 0
+    when negative.  The timed `steps` sweeps are graph launches only: the
+    library's 16-sweep graph steps // 16 times and one graph of the rest."""
+    if steps < 1:
+        raise ValueError("--steps must be at least 1")
+    return {"tuner_windows": TUNER_WINDOWS, "tuner_window_sweeps": TUNER_WINDOW_SWEEPS,
+            "tuner_sweeps": TUNER_WINDOWS * TUNER_WINDOW_SWEEPS,
+            "extra_sweeps": max(0, int(warmup)),
+            "timed_graph_launches": steps // GRAPH_SWEEPS + (1 if steps % GRAPH_SWEEPS else 0)}
+
+
+def kernel_time(S, torch, launches):
+    """Mean duration of one sub-sweep launch: `launches` launches (the four
+    sets in turn, as inside a sweep) captured into one graph on the system's
+    stream and replayed between two HIP events on that stream, after one
+    untimed replay.  Each launch's share includes the graph's gap before the
+    next node, so this is an upper bound on the kernel's own duration."""
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=S.stream):
+        for i in range(launches):
+            S.subsweep(i % 4)
+    with torch.cuda.stream(S.stream):
+        g.replay()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(S.stream)
+        g.replay()
+        e1.record(S.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / launches
+    del g
+    return ms
+
+
+def side_leg(name, out, fn):
+    """Run one optional leg; a failure is recorded in the line, not raised,
+    so that the headline figure is always printed."""
+    print("[bench] %s leg" % name, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    try:
+        out[name] = fn()
+    except Exception as e:  # noqa: BLE001 -- reported in the JSON line
+        out[name] = {"error": "%s: %s" % (type(e).__name__, e)}
+    print("[bench] %s leg done in %.1f s" % (name, time.perf_counter() - t0), file=sys.stderr,
+          flush=True)
+    return out[name]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    plan = warmup_plan(args.warmup, args.steps)
     import torch
     import paper_1211_1646_amd as pkg
 
@@ -466,23 +559,27 @@ def main():
     geo = S.geometry
     N, C = geo["n_particles"], geo["cells_x"] * geo["cells_y"]
 
-    # warm-up: tune delta to ~30 % acceptance in windows of 10 sweeps, then freeze
-    windows = max(1, args.warmup // 10)
-    S.tune(10, windows)
-    S.sweep(args.warmup - 10 * windows)
+    # set-up: delta tuned to ~30 % acceptance, then frozen; launch shape
+    S.tune(plan["tuner_window_sweeps"], plan["tuner_windows"])
     S.synchronize()
     delta = float(S.delta)
-    # launch shape: autotuned (shape never changes results), or as given
     if args.block > 0:
         S.set_launch(args.lanes, args.block)
         tuned = None
     else:
         tuned = S.autotune(16)
-    print("[bench] warm-up done, delta=%.5f, sub-sweep %d lanes per cell, block %d%s" % (
-        delta, S.lanes, S.block, " (autotuned, %.1f us/sweep)" % tuned[2] if tuned else ""),
-        file=sys.stderr, flush=True)
+    if plan["extra_sweeps"]:
+        S.sweep(plan["extra_sweeps"])
+    S.prepare_sweeps(args.steps)   # capture now: the timed region only launches graphs
+    S.synchronize()
+    print("[bench] set-up done: delta=%.5f after %d tuner sweeps, sub-sweep %d lanes per cell, "
+          "block %d%s, %d more warm-up sweeps" % (
+              delta, plan["tuner_sweeps"], S.lanes, S.block,
+              " (autotuned, %.1f us/sweep)" % tuned[2] if tuned else "", plan["extra_sweeps"]),
+          file=sys.stderr, flush=True)
 
-    # timed sweeps: one captured graph per 16 sweeps, events on the system's stream
+    # timed sweeps: graph launches only, HIP events on the system's stream,
+    # synchronised on both sides
     t0_trials, t0_acc = S.counters()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -492,6 +589,7 @@ def main():
     S.sweep(args.steps)
     ev1.record(S.stream)
     ev1.synchronize()
+    torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     gpu_ms = ev0.elapsed_time(ev1)
     t1_trials, t1_acc = S.counters()
@@ -502,35 +600,9 @@ def main():
           % (args.steps, gpu_ms, wall, value, (t1_acc - t0_acc) / max(trials, 1)),
           file=sys.stderr, flush=True)
 
-    # dominant kernel: the sub-sweep.  ks launches (the four sets in turn) are
-    # captured into one graph on the system's stream, as inside a sweep, and
-    # the graph is replayed between two HIP events on that stream: the mean
-    # per launch is kernel time plus the graph's inter-node gap.  The same
-    # launches are also timed one by one between events (launch overhead
-    # included) for reference.
+    # dominant kernel: the sub-sweep (four launches per sweep)
     ks = max(4, args.kernel_samples)
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g, stream=S.stream):
-        for i in range(ks):
-            S.subsweep(i % 4)
-    with torch.cuda.stream(S.stream):
-        g.replay()                      # warm
-        ge0 = torch.cuda.Event(enable_timing=True)
-        ge1 = torch.cuda.Event(enable_timing=True)
-        ge0.record(S.stream)
-        g.replay()
-        ge1.record(S.stream)
-    ge1.synchronize()
-    k_avg_ms = ge0.elapsed_time(ge1) / ks
-    del g
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(ks)]
-    for i in range(ks):
-        evs[i][0].record(S.stream)
-        S.subsweep(i % 4)
-        evs[i][1].record(S.stream)
-    evs[-1][1].synchronize()
-    kms = sorted(a.elapsed_time(b) for a, b in evs)
+    k_avg_ms = kernel_time(S, torch, ks)
     # algorithmic bytes per sub-sweep launch: every position read once (8 N),
     # every cell count read once (4 C), the active quarter of positions
     # written back (8 N / 4)
@@ -541,6 +613,7 @@ def main():
     kernel_name = ("k_subsweep<%d, 0>" % cap if S.lanes == 1
                    else "k_subsweep_mc<%d, %d, 0>" % (cap, S.lanes))
     S.synchronize()
+    src = os.path.join(ROOT, "paper_1211_1646_amd", "csrc", "mpmc_kernels.hip")
 
     out = {
         "metric": "trial moves/sec at 1M disks phi=0.70; MSD/sec learned+batched vs plain",
@@ -564,44 +637,43 @@ def main():
                    "trial_moves_per_sweep": trials / args.steps,
                    "subsweep_lanes_per_cell": S.lanes,
                    "subsweep_block": S.block,
+                   "tuner_sweeps": plan["tuner_sweeps"],
+                   "autotune_sweeps": 2 * 16 * S.AUTOTUNE_CANDIDATES if tuned else 0,
+                   "extra_warmup_sweeps": plan["extra_sweeps"],
+                   "timed_graph_launches": plan["timed_graph_launches"],
+                   "wall_s_timed": wall,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_from_profile(os.path.join(
-                         ROOT, "paper_1211_1646_amd", "csrc", "mpmc_kernels.hip"), kernel_name),
-                     "valu_busy": traffic_from_profile(os.path.join(
-                         ROOT, "paper_1211_1646_amd", "csrc", "mpmc_kernels.hip"), kernel_name,
-                         "valu busy fraction"),
+                     "traffic": traffic_from_profile(src, kernel_name),
+                     "valu_busy": traffic_from_profile(src, kernel_name, "valu busy fraction"),
                      "kernel": kernel_name, "kernel_avg_us": k_avg_ms * 1e3,
                      "kernel_timing": "%d launches in one captured graph, HIP events around the "
-                                      "replay on the system's stream" % ks,
-                     "kernel_single_launch_median_us": kms[len(kms) // 2] * 1e3,
+                                      "replay on the system's stream (graph gaps included)" % ks,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
     S.close()
+    lanes_main, block_main = out["config"]["subsweep_lanes_per_cell"], out["config"]["subsweep_block"]
     net = None
     if not args.no_learned:
-        print("[bench] learned-controller leg", file=sys.stderr, flush=True)
-        out["learned"], net = learned_leg(args, pkg, torch, out["config"]["subsweep_lanes_per_cell"],
-                                          out["config"]["subsweep_block"])
+        res = side_leg("learned", out, lambda: learned_leg(args, pkg, torch, lanes_main, block_main))
+        if isinstance(res, tuple):
+            out["learned"], net = res
     if not args.no_batched:
-        print("[bench] batched leg", file=sys.stderr, flush=True)
-        out["batched"] = batched_leg(args, pkg, torch, net)
+        side_leg("batched", out, lambda: batched_leg(args, pkg, torch, net))
     if not args.no_eos:
-        print("[bench] equation-of-state leg", file=sys.stderr, flush=True)
-        out["eos"] = eos_leg(args, pkg, torch, out["config"]["subsweep_lanes_per_cell"],
-                             out["config"]["subsweep_block"])
+        side_leg("eos", out, lambda: eos_leg(args, pkg, torch, lanes_main, block_main))
     if not args.no_table3:
-        print("[bench] paper table 3 leg", file=sys.stderr, flush=True)
-        out["table3"] = table3_leg(args, pkg, torch)
+        side_leg("table3", out, lambda: table3_leg(args, pkg, torch))
     if not args.no_spheres:
-        print("[bench] hard-sphere leg", file=sys.stderr, flush=True)
-        out["spheres"] = spheres_leg(args)
+        side_leg("spheres", out, lambda: spheres_leg(args))
     if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args, geo, trials / args.steps)
-        if not args.no_spheres:
-            out["cpu_baseline"]["spheres"] = cpu_baseline_spheres(out["spheres"]["delta"])
+        cb = side_leg("cpu_baseline", out, lambda: cpu_baseline(args, geo))
+        if not args.no_spheres and "error" not in cb and "delta" in out.get("spheres", {}):
+            try:
+                cb["spheres"] = cpu_baseline_spheres(out["spheres"]["delta"])
+            except Exception as e:  # noqa: BLE001
+                cb["spheres"] = {"error": "%s: %s" % (type(e).__name__, e)}
     print(json.dumps(out), flush=True)
 
 

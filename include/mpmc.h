@@ -186,11 +186,23 @@ mpmc_status mpmc_replica_geometry(mpmc_handle h, int32_t r, mpmc_geometry *out);
 
 /* sweep(n_sweeps, seed): n_sweeps full sweeps of Alg. 1 (async): the sweep's
  * set order, four sub-sweeps (Alg. 2), shift and rebin (Alg. 4), sweep += 1.
- * `seed` replaces key word 0 for these and later sweeps.  Long runs are
- * launched as captured hipGraphs of a fixed block of sweeps. */
+ * `seed` replaces key word 0 for these and later sweeps.  On a non-default
+ * stream every sweep is launched from a captured hipGraph: floor(n / 16)
+ * launches of a 16-sweep graph, then one graph of the n mod 16 rest; the
+ * graphs are captured on first use and kept (one of each per ping-pong
+ * half) until the launch shape or n_M changes.  On the default stream the
+ * kernels are launched one by one.  In a batch this is the batched sweep:
+ * one launch per step covers every replica.  Errors: MPMC_EINVAL for a
+ * negative count, MPMC_ESTATE without a loaded state, MPMC_EHIP. */
 mpmc_status mpmc_sweep(mpmc_handle h, int64_t n_sweeps, uint32_t seed);
 /* (In a batch, `seed` replaces key word 0 of every replica; key word 1 stays
  * each replica's own.) */
+
+/* Utility (timing support, no passage of the method): capture, without
+ * running anything, the graphs that a following mpmc_sweep(h, n_sweeps, .)
+ * will launch, so that call enqueues graph launches only (async; nothing is
+ * enqueued).  Errors as mpmc_sweep. */
+mpmc_status mpmc_prepare_sweeps(mpmc_handle h, int64_t n_sweeps);
 
 /* One sub-sweep of checkerboard set `set` (0..3 = a..d of Eq. 1) with the
  * current sweep's cell streams (Alg. 1, Alg. 2).  async. */
@@ -199,8 +211,12 @@ mpmc_status mpmc_subsweep(mpmc_handle h, int32_t set);
 /* shift_and_rebin (Alg. 4).  f in 0..3 (+x, -x, +y, -y) with 0 <= d <= w_f/2
  * shifts by the given amount and leaves the sweep counter alone; f = -1 takes
  * f and d from the current sweep's draws and then advances the sweep counter
- * (the last step of a sweep).  The cell lists are rebuilt by counting sort
- * and prefix scan into the other ping-pong half.  async. */
+ * (the last step of a sweep).  The cell lists are rebuilt into the other
+ * ping-pong half by a per-cell gather into fixed slots: new cell c receives
+ * the disks of old c that stay (0 < shifted coordinate <= w), in slot order,
+ * followed by the disks that leave the old cell on the shift side, in slot
+ * order -- Alg. 4's list order, with no scan because every cell owns
+ * `capacity` slots.  async. */
 mpmc_status mpmc_shift_and_rebin(mpmc_handle h, int32_t f, float d);
 
 /* Accumulate the ordered-pair contact histogram of the current configuration

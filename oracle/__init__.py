@@ -33,7 +33,7 @@ def build(force: bool = True) -> str:
         if all(os.path.getmtime(s) <= built for s in srcs):
             return _LIB_PATH
     tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-ffp-contract=off", "-fno-fast-math",
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
            "-fPIC", "-shared", "-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
@@ -79,6 +79,8 @@ def lib():
         L.oracle_destroy.restype = None
         L.oracle_info.argtypes = [vp, i32p, i32p, f32p, f32p, i32p, C.POINTER(C.c_int64)]
         L.oracle_info.restype = None
+        L.oracle_set_threads.argtypes = [vp, C.c_int]
+        L.oracle_set_threads.restype = C.c_int
         for name, at in [("oracle_set_delta", [vp, C.c_float]),
                          ("oracle_set_seed", [vp, C.c_uint32]),
                          ("oracle_set_n_moves", [vp, C.c_int]),
@@ -272,6 +274,11 @@ class OracleSystem:
 
     def set_n_moves(self, n):
         lib().oracle_set_n_moves(self._h, n)
+
+    def set_threads(self, n):
+        """OpenMP threads over the cells of each sub-sweep (the chain is the
+        same for any count); returns the count in effect."""
+        return int(lib().oracle_set_threads(self._h, int(n)))
 
     def set_cell_order(self, mode):
         lib().oracle_set_cell_order(self._h, mode)

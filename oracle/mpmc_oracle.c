@@ -265,6 +265,7 @@ typedef struct oracle_sys {
     int flags;      /* bit 0: displacement accumulators, bit 1: tags, bit 3: disk moves,
                        bits 4, 5: no particle / no set shuffle */
     int cell_order; /* 0 row-major, 1 reversed, 2 scrambled (order test) */
+    int threads;    /* OpenMP threads over the cells of one set (default 1) */
     /* disk[c*cap + i] (Sec. 3.1), double buffer for the shift (Alg. 4) */
     float *disk_x, *disk_y, *dbl_x, *dbl_y;
     float *acc_x, *acc_y, *dacc_x, *dacc_y;
@@ -297,6 +298,7 @@ static oracle_sys *alloc_sys(int mx, int my, float wx, float wy, int cap,
     oracle_sys *S = (oracle_sys *)xcalloc(1, sizeof(oracle_sys));
     S->mx = mx; S->my = my; S->C = mx * my; S->cap = cap;
     S->wx = wx; S->wy = wy; S->flags = flags;
+    S->threads = 1;
     size_t slots = (size_t)S->C * (size_t)cap;
     S->disk_x = (float *)xcalloc(slots, sizeof(float));
     S->disk_y = (float *)xcalloc(slots, sizeof(float));
@@ -468,7 +470,9 @@ static int overlaps(const oracle_sys *S, int cx, int cy, int self, float xm, flo
     return 0;
 }
 
-static void cell_update(oracle_sys *S, int cx, int cy)
+/* One cell update; the cell's trials and accepts are added to *trials and
+ * *accepts, so that cells of one set can be updated by several threads. */
+static void cell_update(oracle_sys *S, int cx, int cy, uint64_t *trials, uint64_t *accepts)
 {
     int c = cy * S->mx + cx;
     int n = S->n[c];
@@ -500,7 +504,7 @@ static void cell_update(oracle_sys *S, int cx, int cy)
         float xm = S->disk_x[slot] + dx;
         float ym = S->disk_y[slot] + dy;
         int in_cell = xm > 0.0f && xm <= S->wx && ym > 0.0f && ym <= S->wy;
-        S->trials += 1;
+        *trials += 1;
         if (in_cell && !overlaps(S, cx, cy, slot, xm, ym)) {
             S->disk_x[slot] = xm;
             S->disk_y[slot] = ym;
@@ -508,7 +512,7 @@ static void cell_update(oracle_sys *S, int cx, int cy)
                 S->acc_x[slot] = S->acc_x[slot] + dx;
                 S->acc_y[slot] = S->acc_y[slot] + dy;
             }
-            S->accepts += 1;
+            *accepts += 1;
             if (s < 32) S->accept_bits[c] |= 1u << s;
         }
     }
@@ -529,13 +533,34 @@ void oracle_subsweep(oracle_sys *S, int Q)
     int qx = Q & 1, qy = (Q >> 1) & 1;
     int hx = S->mx / 2, hy = S->my / 2;
     int count = hx * hy;
+    uint64_t trials = 0, accepts = 0;
+    /* Several threads only split the (independent) cells of the set among
+     * them; each cell's update is the serial one. */
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(S->threads) schedule(static) reduction(+ : trials, accepts) if (S->threads > 1)
+#endif
     for (int k = 0; k < count; ++k) {
         int idx = k;
         if (S->cell_order == 1) idx = count - 1 - k;
         else if (S->cell_order == 2) idx = (int)(((int64_t)k * 7919 + 13) % count);
         int ix = idx % hx, iy = idx / hx;
-        cell_update(S, 2 * ix + qx, 2 * iy + qy);
+        cell_update(S, 2 * ix + qx, 2 * iy + qy, &trials, &accepts);
     }
+    S->trials += trials;
+    S->accepts += accepts;
+}
+
+/* Threads used by every later sub-sweep (1 = serial; without OpenMP the
+ * library is serial whatever is asked).  Returns the number in effect. */
+int oracle_set_threads(oracle_sys *S, int threads)
+{
+#ifdef _OPENMP
+    S->threads = threads < 1 ? 1 : threads;
+#else
+    (void)threads;
+    S->threads = 1;
+#endif
+    return S->threads;
 }
 
 /* ------------------------------------------------------------------------

@@ -99,6 +99,7 @@ _SIGNATURES = {
     "mpmc_init_system": (C.c_int32, [C.POINTER(Params), C.POINTER(Buffers), C.c_void_p,
                                      C.POINTER(C.c_void_p)]),
     "mpmc_sweep": (C.c_int32, [_H, C.c_int64, C.c_uint32]),
+    "mpmc_prepare_sweeps": (C.c_int32, [_H, C.c_int64]),
     "mpmc_subsweep": (C.c_int32, [_H, C.c_int32]),
     "mpmc_shift_and_rebin": (C.c_int32, [_H, C.c_int32, C.c_float]),
     "mpmc_pair_histogram": (C.c_int32, [_H, C.c_int32]),

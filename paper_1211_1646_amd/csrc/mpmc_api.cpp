@@ -274,7 +274,9 @@ struct mpmc_system {
     std::vector<uint32_t> key0;   // current key word 0 of each replica
     std::vector<char> loaded;     // replica holds a valid, overlap-free state
     bool ready;                   // every replica is loaded
-    hipGraphExec_t graph[2];
+    hipGraphExec_t graph[2];      // kGraphSweeps sweeps from ping-pong half 0 / 1
+    hipGraphExec_t tail[2];       // tail_n[p] (< kGraphSweeps) sweeps from half p
+    int tail_n[2];
     std::vector<Ctl> ctl_host;
     int R() const { return (int)p.size(); }
 };
@@ -283,11 +285,17 @@ namespace {
 
 void drop_graphs(mpmc_system *h)
 {
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
         if (h->graph[i]) {
             (void)hipGraphExecDestroy(h->graph[i]);
             h->graph[i] = nullptr;
         }
+        if (h->tail[i]) {
+            (void)hipGraphExecDestroy(h->tail[i]);
+            h->tail[i] = nullptr;
+        }
+        h->tail_n[i] = 0;
+    }
 }
 
 // Fold the counter partials, copy every control block to the host, wait,
@@ -337,31 +345,70 @@ mpmc_status enqueue_sweep(mpmc_system *h)
     return enqueue_rebin(h, -1, 0.0f, 1);
 }
 
+// Capture n sweeps starting from the current ping-pong half into *ex (the
+// stream is only recorded, nothing runs).
+mpmc_status capture_sweeps(mpmc_system *h, int n, hipGraphExec_t *ex)
+{
+    const int cur0 = h->cur;
+    hipGraph_t graph = nullptr;
+    MPMC_HIP(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+    mpmc_status s = MPMC_OK;
+    for (int k = 0; k < n && s == MPMC_OK; ++k) s = enqueue_sweep(h);
+    const hipError_t e = hipStreamEndCapture(h->st, &graph);
+    h->cur = cur0;
+    if (s) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    if (e != hipSuccess) return fail(MPMC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    const hipError_t ei = hipGraphInstantiate(ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        *ex = nullptr;
+        return fail(MPMC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    return MPMC_OK;
+}
+
+// Make sure the graphs that n sweeps from the current half launch exist:
+// the kGraphSweeps graph of this half (an even count, so every full graph
+// starts on the same half) and the graph of the n mod kGraphSweeps rest.
+mpmc_status prepare_sweeps(mpmc_system *h, int64_t n)
+{
+    if (!h->st) return MPMC_OK;   // the null stream cannot be captured: eager launches
+    const int p = h->cur;
+    if (n >= kGraphSweeps && !h->graph[p]) {
+        const mpmc_status s = capture_sweeps(h, kGraphSweeps, &h->graph[p]);
+        if (s) return s;
+    }
+    const int rest = (int)(n % kGraphSweeps);
+    if (rest > 0 && (!h->tail[p] || h->tail_n[p] != rest)) {
+        if (h->tail[p]) {
+            (void)hipGraphExecDestroy(h->tail[p]);
+            h->tail[p] = nullptr;
+            h->tail_n[p] = 0;
+        }
+        const mpmc_status s = capture_sweeps(h, rest, &h->tail[p]);
+        if (s) return s;
+        h->tail_n[p] = rest;
+    }
+    return MPMC_OK;
+}
+
+// n sweeps as graph launches only (eager launches on the null stream).
 mpmc_status run_sweeps(mpmc_system *h, int64_t n)
 {
     if (h->st) {
-        while (n >= kGraphSweeps) {
-            hipGraphExec_t &ex = h->graph[h->cur];
-            if (!ex) {
-                const int cur0 = h->cur;
-                hipGraph_t graph = nullptr;
-                MPMC_HIP(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
-                mpmc_status s = MPMC_OK;
-                for (int k = 0; k < kGraphSweeps && s == MPMC_OK; ++k) s = enqueue_sweep(h);
-                const hipError_t e = hipStreamEndCapture(h->st, &graph);
-                h->cur = cur0;
-                if (s) return s;
-                if (e != hipSuccess) return fail(MPMC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-                const hipError_t ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(graph);
-                if (ei != hipSuccess) {
-                    ex = nullptr;
-                    return fail(MPMC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
-                }
-            }
-            MPMC_HIP(hipGraphLaunch(ex, h->st));
-            n -= kGraphSweeps;
+        const mpmc_status s = prepare_sweeps(h, n);
+        if (s) return s;
+        const int p = h->cur;
+        for (int64_t k = 0; k < n / kGraphSweeps; ++k) MPMC_HIP(hipGraphLaunch(h->graph[p], h->st));
+        const int rest = (int)(n % kGraphSweeps);
+        if (rest > 0) {
+            MPMC_HIP(hipGraphLaunch(h->tail[p], h->st));
+            h->cur = p ^ (rest & 1);
         }
+        return MPMC_OK;
     }
     for (; n > 0; --n) {
         const mpmc_status s = enqueue_sweep(h);
@@ -631,6 +678,8 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
     h->loaded.assign((size_t)n, 0);
     h->ready = false;
     h->graph[0] = h->graph[1] = nullptr;
+    h->tail[0] = h->tail[1] = nullptr;
+    h->tail_n[0] = h->tail_n[1] = 0;
     h->ctl_host.resize((size_t)n);
 
     std::vector<uint16_t> arep((size_t)(L.active / mpmc::kActiveChunk));
@@ -772,6 +821,13 @@ mpmc_status mpmc_sweep(mpmc_handle h, int64_t n_sweeps, uint32_t seed)
         std::fill(h->key0.begin(), h->key0.end(), seed);
     }
     return run_sweeps(h, n_sweeps);
+}
+
+mpmc_status mpmc_prepare_sweeps(mpmc_handle h, int64_t n_sweeps)
+{
+    if (!h || n_sweeps < 0) return fail(MPMC_EINVAL, "bad handle or sweep count");
+    MPMC_NEED_STATE(h);
+    return prepare_sweeps(h, n_sweeps);
 }
 
 mpmc_status mpmc_subsweep(mpmc_handle h, int32_t set)

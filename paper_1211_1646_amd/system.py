@@ -134,6 +134,10 @@ class HardDiskSystem:
         if seed is not None:
             self.cfg.seed = int(seed)
 
+    def prepare_sweeps(self, n: int):
+        """Capture the graphs a following sweep(n) launches (runs nothing)."""
+        L.check(self.lib.mpmc_prepare_sweeps(self._h, int(n)))
+
     def subsweep(self, set_index: int):
         L.check(self.lib.mpmc_subsweep(self._h, int(set_index)))
 
@@ -298,6 +302,7 @@ class HardDiskBatch:
                                       int(n_windows)))
 
     close = HardDiskSystem.close
+    prepare_sweeps = HardDiskSystem.prepare_sweeps
     __del__ = HardDiskSystem.__del__
     subsweep = HardDiskSystem.subsweep
     shift_and_rebin = HardDiskSystem.shift_and_rebin
