@@ -150,10 +150,11 @@ typedef struct mpmc_buffers {
  * Errors: MPMC_EINVAL for bad lattice/phi, MPMC_EGEOM for an unusable grid. */
 mpmc_status mpmc_geometry_of(const mpmc_params *p, mpmc_geometry *out);
 
-/* Buffer sizes for a parameter set.  Host only, no GPU use. */
+/* Utility (no passage of the method): buffer sizes for a parameter set.
+ * Host only, no GPU use. */
 mpmc_status mpmc_required_bytes(const mpmc_params *p, mpmc_buffer_sizes *out);
 
-/* Buffer sizes for n_replicas systems, per_replica[0 .. n_replicas).  All
+/* Utility: buffer sizes for n_replicas systems, per_replica[0 .. n_replicas).  All
  * replicas must share `flags`.  In the shared layout each replica's cells
  * are padded to a multiple of 256 (at least one padding cell) and its active
  * cells to a multiple of 768.  Host only.  Errors as mpmc_geometry_of, plus MPMC_EINVAL for
@@ -178,10 +179,10 @@ mpmc_status mpmc_init_system(const mpmc_params *p, const mpmc_buffers *b, void *
 mpmc_status mpmc_batch_init(const mpmc_params *per_replica, int32_t n_replicas,
                             const mpmc_buffers *b, void *stream, mpmc_handle *out);
 
-/* Number of replicas of a handle. */
+/* Utility: number of replicas of a handle. */
 mpmc_status mpmc_num_replicas(mpmc_handle h, int32_t *n);
 
-/* Geometry of replica r (host only). */
+/* Geometry of replica r (Sec. 3.1, Fig. 3; host only). */
 mpmc_status mpmc_replica_geometry(mpmc_handle h, int32_t r, mpmc_geometry *out);
 
 /* sweep(n_sweeps, seed): n_sweeps full sweeps of Alg. 1 (async): the sweep's
@@ -239,7 +240,8 @@ mpmc_status mpmc_replica_pressure_from_contact(mpmc_handle h, int32_t r, double 
                                                double *g_contact, uint64_t *hist,
                                                uint64_t *n_samples);
 
-/* Copy the state to host memory (sync): xy[2N] local coordinates,
+/* Utility (state transfer for checkpoints and tests): copy the state to
+ * host memory (sync): xy[2N] local coordinates,
  * start[cells+1], sweep counter.  Any pointer may be NULL. */
 mpmc_status mpmc_get_state(mpmc_handle h, float *xy, uint32_t *start, uint64_t *sweep);
 /* Replica r's state in its own numbering: xy[2 N_r], start[C_r + 1] with
@@ -247,7 +249,8 @@ mpmc_status mpmc_get_state(mpmc_handle h, float *xy, uint32_t *start, uint64_t *
 mpmc_status mpmc_replica_get_state(mpmc_handle h, int32_t r, float *xy, uint32_t *start,
                                    uint64_t *sweep);
 
-/* Load a state from host memory (sync).  Validates offsets, per-cell
+/* Utility (state transfer): load a state from host memory (sync).
+ * Validates offsets, per-cell
  * capacity and coordinate ranges on the host (MPMC_ESTATE) and overlaps on
  * the device (MPMC_EOVERLAP); tags may be NULL (then 0..N-1 in list order);
  * accumulators are cleared.  N must equal the n_particles the buffers were
@@ -260,7 +263,9 @@ mpmc_status mpmc_set_state(mpmc_handle h, const float *xy, const uint32_t *start
 mpmc_status mpmc_replica_set_state(mpmc_handle h, int32_t r, const float *xy,
                                    const uint32_t *start, uint64_t sweep, const uint32_t *tags);
 
-/* Copy accumulators acc[2N] and tags[N] to host memory (sync), list order. */
+/* Utility: copy accumulators acc[2N] and tags[N] to host memory (sync),
+ * list order.  The accumulators measure diffusion (mean-square
+ * displacement); the paper has no such observable. */
 mpmc_status mpmc_get_aux(mpmc_handle h, float *acc, uint32_t *tags);
 mpmc_status mpmc_replica_get_aux(mpmc_handle h, int32_t r, float *acc, uint32_t *tags);
 
@@ -272,25 +277,29 @@ mpmc_status mpmc_replica_get_aux(mpmc_handle h, int32_t r, float *acc, uint32_t 
 mpmc_status mpmc_get_accept_log(mpmc_handle h, uint32_t *bits);
 mpmc_status mpmc_replica_get_accept_log(mpmc_handle h, int32_t r, uint32_t *bits);
 
-/* Clear the displacement accumulators of every replica (async). */
+/* Utility: clear the displacement accumulators of every replica (async). */
 mpmc_status mpmc_reset_acc(mpmc_handle h);
 
 /* Mean squared displacement mean(|acc|^2) over all disks, FP64, fixed
- * reduction order (sync). */
+ * reduction order (sync).  Not in the paper: the diffusion figure of merit
+ * of the move-size controller below. */
 mpmc_status mpmc_msd(mpmc_handle h, double *msd);
 mpmc_status mpmc_replica_msd(mpmc_handle h, int32_t r, double *msd);
 
-/* Number of ordered overlapping pairs in the kernels' metric, summed over
- * the replicas (sync). */
+/* Utility (invariant check: hard disks never overlap, Sec. 2.1): number of
+ * ordered pairs closer than 1 - 2^-20 in r^2 in the kernels' metric, summed
+ * over the replicas (sync). */
 mpmc_status mpmc_count_overlaps(mpmc_handle h, int64_t *pairs);
 
-/* Trial moves and accepted moves since init or the last set_state, summed
+/* Trial moves (the paper's throughput eta counts them per second, Sec. 5)
+ * and accepted moves since init or the last set_state, summed
  * over the replicas (sync); the replica form gives one replica's. */
 mpmc_status mpmc_get_counters(mpmc_handle h, uint64_t *trials, uint64_t *accepts);
 mpmc_status mpmc_replica_get_counters(mpmc_handle h, int32_t r, uint64_t *trials,
                                       uint64_t *accepts);
 
-/* Maximum trial displacement delta (async set / sync get).  mpmc_set_delta
+/* Maximum trial displacement delta, the free parameter d of Sec. 3.3
+ * (async set / sync get).  mpmc_set_delta
  * sets every replica's; the replica forms one replica's. */
 mpmc_status mpmc_set_delta(mpmc_handle h, float delta);
 mpmc_status mpmc_get_delta(mpmc_handle h, float *delta);
@@ -304,20 +313,23 @@ mpmc_status mpmc_replica_get_delta(mpmc_handle h, int32_t r, float *delta);
 mpmc_status mpmc_set_n_moves(mpmc_handle h, int32_t n_moves);
 mpmc_status mpmc_replica_set_n_moves(mpmc_handle h, int32_t r, int32_t n_moves);
 
-/* Plain acceptance-ratio tuner for equilibration (async): n_windows times,
+/* Plain acceptance-ratio tuner for equilibration (not in the paper, which
+ * fixes d; it only sets delta before production) (async): n_windows times,
  * run window_sweeps sweeps, then with a = accepts/trials of that window
  * set delta <- delta * clamp(a/0.3, 0.5, 2), clamped to [1e-3, min(w)/2],
  * on the device, for each replica from its own counts. */
 mpmc_status mpmc_tune(mpmc_handle h, int32_t window_sweeps, int32_t n_windows);
 
-/* Launch shape of the sub-sweep: lanes cooperating on one active cell (1, 2
+/* Utility (performance only): launch shape of the sub-sweep: lanes
+ * cooperating on one active cell (1, 2
  * or 4: the group splits the neighbour cells, their filtering and the
  * overlap tests, and combines its verdicts) and workgroup size in lanes (64,
  * 128, 192 or 256; reduced where the neighbour rows would exceed 64 KB of
  * LDS).  Results do not depend on either: every comparison is the same. */
 mpmc_status mpmc_set_launch(mpmc_handle h, int32_t lanes_per_cell, int32_t block_size);
 
-/* Autotuner for the launch shape.  Only shape knobs that leave results bit
+/* Utility (performance only): autotuner for the launch shape.  Only shape
+ * knobs that leave results bit
  * for bit unchanged are searched (lanes per cell 1, 2, 4 times workgroup
  * size 64, 128, 192, 256: twelve candidates), so the sweeps it times are
  * ordinary sweeps of the chain: for each candidate it runs `sweeps` sweeps
@@ -328,7 +340,8 @@ mpmc_status mpmc_set_launch(mpmc_handle h, int32_t lanes_per_cell, int32_t block
 mpmc_status mpmc_autotune(mpmc_handle h, int32_t sweeps, int32_t *lanes_out, int32_t *block_out,
                           double *us_per_sweep_out);
 
-/* Every replica's counters since its init or set_state, current delta and,
+/* Utility: every replica's counters since its init or set_state, current
+ * delta and,
  * if msd is not NULL, mean |acc|^2 over its disks (FP64, fixed order), each
  * an array of R entries (sync).  Any pointer may be NULL. */
 mpmc_status mpmc_batch_stats(mpmc_handle h, uint64_t *trials, uint64_t *accepts, float *delta,
@@ -351,8 +364,8 @@ mpmc_status mpmc_batch_stats(mpmc_handle h, uint64_t *trials, uint64_t *accepts,
  * W (device, MPMC_MLP_PARAMS floats) and that window's acceptance. */
 mpmc_status mpmc_control(mpmc_handle h, const float *W, int32_t window_sweeps, int32_t n_windows);
 
-/* Bytes of device workspace for mpmc_mlp_backward / mpmc_mlp_mse on n
- * samples (host only). */
+/* Utility: bytes of device workspace for mpmc_mlp_backward / mpmc_mlp_mse
+ * on n samples (host only). */
 mpmc_status mpmc_mlp_work_bytes(int32_t n, size_t *bytes);
 
 /* Y[i] = net(X[i][0..2]) for n samples; X row-major [n][3].  cache, if not
@@ -379,14 +392,15 @@ mpmc_status mpmc_mlp_mse(const float *Y, const float *T, int32_t n, float *dY, d
 mpmc_status mpmc_adam_step(float *W, float *m, float *v, const float *dW, int32_t n_params,
                            float lr, float b1, float b2, float eps, int32_t step, void *stream);
 
-/* Wait for all work enqueued by this handle; reports MPMC_EDEVICE if a kernel
- * set the error word. */
+/* Utility: wait for all work enqueued by this handle; reports MPMC_EDEVICE
+ * if a kernel set the error word. */
 mpmc_status mpmc_synchronize(mpmc_handle h);
 
-/* Free the handle and its graphs (not the caller's buffers). */
+/* Utility: free the handle and its graphs (not the caller's buffers). */
 void mpmc_destroy(mpmc_handle h);
 
-/* Message describing the calling thread's last failure ("" if none). */
+/* Utility: message describing the calling thread's last failure ("" if
+ * none). */
 const char *mpmc_last_error(void);
 
 #ifdef __cplusplus

@@ -115,16 +115,17 @@ typedef struct mpmc_sphere_buffers {
     void *ctl;
 } mpmc_sphere_buffers;
 
-/* Geometry of a parameter set (host only).  Errors: MPMC_EINVAL for a bad
+/* Geometry of a parameter set (Sec. 3.1 in d = 3; host only).  Errors: MPMC_EINVAL for a bad
  * lattice, eta, delta, n_moves or flags; MPMC_EGEOM for cell counts that are
  * odd or below 4, or widths outside [1, 2/sqrt(3)). */
 mpmc_status mpmc_sphere_geometry_of(const mpmc_sphere_params *p, mpmc_sphere_geometry *out);
 
-/* Buffer sizes for a parameter set (host only). */
+/* Utility: buffer sizes for a parameter set (host only). */
 mpmc_status mpmc_sphere_required_bytes(const mpmc_sphere_params *p,
                                        mpmc_sphere_buffer_sizes *out);
 
-/* Build the system and upload it on `stream` (sync): the lattice when
+/* Build the system (N spheres at packing fraction eta; the method in
+ * d = 3, Sec. 2.1) and upload it on `stream` (sync): the lattice when
  * lattice_nx > 0, else an empty grid to be filled by mpmc_sphere_set_state.
  * Sweep 0, counters 0, delta and key from p. */
 mpmc_status mpmc_sphere_init(const mpmc_sphere_params *p, const mpmc_sphere_buffers *b,
@@ -146,21 +147,22 @@ mpmc_status mpmc_sphere_subsweep(mpmc_sphere_handle h, int32_t set);
  * direction f that move in, both in stored order.  async. */
 mpmc_status mpmc_sphere_shift(mpmc_sphere_handle h, int32_t f, float d);
 
-/* Copy the state to host memory (sync): xyz[3N], start[cells + 1], tags[N]
+/* Utility (state transfer): copy the state to host memory (sync): xyz[3N], start[cells + 1], tags[N]
  * (MPMC_FLAG_TAG), sweep counter.  Any pointer may be NULL. */
 mpmc_status mpmc_sphere_get_state(mpmc_sphere_handle h, float *xyz, uint32_t *start,
                                   uint32_t *tags, uint64_t *sweep);
 
-/* Load a state (sync).  Offsets, capacity and coordinate ranges are checked
+/* Utility (state transfer): load a state (sync).  Offsets, capacity and coordinate ranges are checked
  * on the host (MPMC_ESTATE), overlaps on the device (MPMC_EOVERLAP); tags may
  * be NULL (then 0..N-1 in list order).  Counters restart at 0. */
 mpmc_status mpmc_sphere_set_state(mpmc_sphere_handle h, const float *xyz, const uint32_t *start,
                                   uint64_t sweep, const uint32_t *tags);
 
-/* Trial and accepted moves since init or set_state (sync). */
+/* Trial moves (counted by the paper's throughput eta, Sec. 5) and accepted
+ * moves since init or set_state (sync). */
 mpmc_status mpmc_sphere_get_counters(mpmc_sphere_handle h, uint64_t *trials, uint64_t *accepts);
 
-/* Maximum trial displacement (async set, 0 < delta <= min(w)/2; sync get). */
+/* Maximum trial displacement, the free parameter d of Sec. 3.3 (async set, 0 < delta <= min(w)/2; sync get). */
 mpmc_status mpmc_sphere_set_delta(mpmc_sphere_handle h, float delta);
 mpmc_status mpmc_sphere_get_delta(mpmc_sphere_handle h, float *delta);
 
@@ -189,17 +191,19 @@ mpmc_status mpmc_sphere_pair_histogram(mpmc_sphere_handle h, int32_t reset);
 mpmc_status mpmc_sphere_pressure(mpmc_sphere_handle h, double *p_star, double *g_contact,
                                  uint64_t *hist, uint64_t *n_samples);
 
-/* Ordered pairs closer than 1 - 2^-16 in squared distance (sync). */
+/* Utility (invariant check: hard spheres never overlap): ordered pairs
+ * closer than 1 - 2^-20 in squared distance (sync). */
 mpmc_status mpmc_sphere_count_overlaps(mpmc_sphere_handle h, int64_t *pairs);
 
-/* Launch shape of the sub-sweep: 1, 2 or 4 lanes per active cell (default
- * 1).  The lanes of a group split the 26 neighbour cells and their overlap
+/* Utility (performance only): launch shape of the sub-sweep: 1, 2 or 4
+ * lanes per active cell (default 1).  The lanes of a group split the 26 neighbour cells and their overlap
  * tests and combine their verdicts; every comparison is the same, so the
  * results do not depend on it (sync: waits for the stream, drops the sweep
  * graphs). */
 mpmc_status mpmc_sphere_set_launch(mpmc_sphere_handle h, int32_t lanes_per_cell);
 
-/* Displacement accumulators (MPMC_FLAG_ACC): every accepted move adds its
+/* Utility, not in the paper (diffusion measure): displacement accumulators
+ * (MPMC_FLAG_ACC): every accepted move adds its
  * displacement, one FP32 add per axis, to its sphere's accumulator, which
  * follows the sphere through shuffles and shifts; init, set_state and
  * reset_acc zero them.  get_acc copies acc[3N] in list order (sync); msd
@@ -209,10 +213,11 @@ mpmc_status mpmc_sphere_get_acc(mpmc_sphere_handle h, float *acc);
 mpmc_status mpmc_sphere_msd(mpmc_sphere_handle h, double *msd);
 mpmc_status mpmc_sphere_reset_acc(mpmc_sphere_handle h);
 
-/* Wait for the handle's work; reports MPMC_EDEVICE for a set error word. */
+/* Utility: wait for the handle's work; reports MPMC_EDEVICE for a set error
+ * word. */
 mpmc_status mpmc_sphere_synchronize(mpmc_sphere_handle h);
 
-/* Free the handle and its graphs (not the caller's buffers). */
+/* Utility: free the handle and its graphs (not the caller's buffers). */
 void mpmc_sphere_destroy(mpmc_sphere_handle h);
 
 #ifdef __cplusplus

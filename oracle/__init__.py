@@ -79,6 +79,8 @@ def lib():
         L.oracle_destroy.restype = None
         L.oracle_info.argtypes = [vp, i32p, i32p, f32p, f32p, i32p, C.POINTER(C.c_int64)]
         L.oracle_info.restype = None
+        L.oracle_min_pair_r2.argtypes = [vp]
+        L.oracle_min_pair_r2.restype = C.c_float
         L.oracle_set_threads.argtypes = [vp, C.c_int]
         L.oracle_set_threads.restype = C.c_int
         for name, at in [("oracle_set_delta", [vp, C.c_float]),
@@ -333,6 +335,11 @@ class OracleSystem:
         out = np.zeros(self.mx * self.my, np.uint32)
         lib().oracle_get_accept_log(self._h, _ptr(out, C.c_uint32))
         return out
+
+    def min_pair_r2(self):
+        """Smallest r^2 over ordered neighbour pairs, in the first disk's
+        frame (2.0 when there is none)."""
+        return float(lib().oracle_min_pair_r2(self._h))
 
     def count_overlaps(self):
         return int(lib().oracle_count_overlaps(self._h))

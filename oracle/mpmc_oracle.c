@@ -760,13 +760,52 @@ int oracle_set_state(oracle_sys *S, const float *xy, const uint32_t *start,
     return ORC_OK;
 }
 
-/* Invariant check: ordered pairs (k, j) with r^2 < 1 - 2^-16 evaluated in
- * k's frame as in the trial moves.  A move is tested in the mover's frame
- * (r^2 < 1); seen from the partner's frame the same pair may round to
- * 1 - a few ulp, so the invariant allows that much slack. */
+/* Smallest r^2 over ordered pairs (k, j != k) of the 3x3 neighbourhoods,
+ * evaluated in k's frame as in the trial moves (2.0 if there is no pair). */
+float oracle_min_pair_r2(const oracle_sys *S)
+{
+    float best = 2.0f;
+    for (int cy = 0; cy < S->my; ++cy)
+        for (int cx = 0; cx < S->mx; ++cx) {
+            int c = cy * S->mx + cx;
+            for (int i = 0; i < S->n[c]; ++i) {
+                int self = c * S->cap + i;
+                float xk = S->disk_x[self], yk = S->disk_y[self];
+                for (int oy = -1; oy <= 1; ++oy) {
+                    int ncy = wrap(cy + oy, S->my);
+                    float ty = oy < 0 ? -S->wy : (oy > 0 ? S->wy : 0.0f);
+                    for (int ox = -1; ox <= 1; ++ox) {
+                        int ncx = wrap(cx + ox, S->mx);
+                        float tx = ox < 0 ? -S->wx : (ox > 0 ? S->wx : 0.0f);
+                        int nc = ncy * S->mx + ncx;
+                        for (int j = 0; j < S->n[nc]; ++j) {
+                            int slot = nc * S->cap + j;
+                            if (slot == self) continue;
+                            float ddx = xk - (S->disk_x[slot] + tx);
+                            float ddy = yk - (S->disk_y[slot] + ty);
+                            float r2 = ddx * ddx + ddy * ddy;
+                            if (r2 < best) best = r2;
+                        }
+                    }
+                }
+            }
+        }
+    return best;
+}
+
+/* Invariant check: ordered pairs (k, j) with r^2 < 1 - 2^-20 evaluated in
+ * k's frame as in the trial moves.  Every accepted move has r^2 >= 1 in the
+ * mover's frame with the coordinates of that moment.  The pair can read
+ * lower later for two reasons, both rounding: (i) in the partner's frame the
+ * translation by w and the differences round differently (a few ulp of
+ * r^2 ~ 1, i.e. below 2^-21); (ii) each rebin re-expresses a coordinate in
+ * the new frame with one rounding of at most half an ulp of a value below 2
+ * (2^-24 absolute), so r moves by at most 2^-23 per rebin while neither disk
+ * of the pair moves.  1 - 2^-20 (about 9.5e-7) covers (i) plus a few tens of
+ * rebins of (ii); the tests also record the smallest r^2 reached. */
 int64_t oracle_count_overlaps(const oracle_sys *S)
 {
-    const float r2min = 1.0f - 0x1p-16f;
+    const float r2min = 1.0f - 0x1p-20f;
     int64_t bad = 0;
     for (int cy = 0; cy < S->my; ++cy)
         for (int cx = 0; cx < S->mx; ++cx) {

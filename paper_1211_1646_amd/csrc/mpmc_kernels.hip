@@ -166,31 +166,6 @@ __device__ __forceinline__ unsigned block_sum_u32(unsigned v, unsigned *scratch1
     return total;
 }
 
-// Exclusive prefix over the workgroup in thread order; *total gets the sum.
-__device__ __forceinline__ unsigned block_exclusive_scan_u32(unsigned v, unsigned *scratch16,
-                                                             unsigned *total)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    unsigned incl = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned n = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += n;
-    }
-    if (lane == 63) scratch16[wave] = incl;
-    __syncthreads();
-    unsigned before = 0, all = 0;
-    const int nw = (blockDim.x + 63) >> 6;
-    for (int q = 0; q < nw; ++q) {
-        const unsigned t = scratch16[q];
-        if (q < wave) before += t;
-        all += t;
-    }
-    __syncthreads();
-    *total = all;
-    return before + incl - v;
-}
-
 // ------------------------------------------------------------ sub-sweep
 // One lane per active cell of set Q (Alg. 2).  Disks live in fixed slots,
 // CAP per cell (the paper's disk[x, y, i], Sec. 3.1), so the kernel exposes
@@ -1089,10 +1064,12 @@ __global__ void __launch_bounds__(256) k_pressure_fit(Tables t, int replica)
 }
 
 // ------------------------------------------------------ overlap count
-// A pair overlaps when r^2 < 1 - 2^-16 in either disk's frame.  The trial
+// A pair overlaps when r^2 < 1 - 2^-20 in either disk's frame.  The trial
 // moves test r^2 < 1 in the mover's frame; seen from the partner's frame the
-// same pair can round to 1 - a few ulp, so the invariant allows that slack.
-constexpr float kOverlapR2 = 1.0f - 0x1p-16f;
+// same pair can round to 1 - a few ulp of r^2, and every rebin re-expresses
+// a coordinate with one rounding (at most 2^-24 absolute for values below
+// 2) while neither disk moves, so the invariant allows 2^-20.
+constexpr float kOverlapR2 = 1.0f - 0x1p-20f;
 
 __global__ void __launch_bounds__(kRebinTile)
 k_count_overlaps(Tables t, const float2 *__restrict__ pos, const uint32_t *__restrict__ count,

@@ -870,10 +870,11 @@ __global__ void __launch_bounds__(256) k_pressure_fit3(Geom3 g, Ctl3 *ctl)
 }
 
 // ------------------------------------------------------ overlap count
-// Ordered pairs with r^2 < 1 - 2^-16 in either sphere's frame (the trial
+// Ordered pairs with r^2 < 1 - 2^-20 in either sphere's frame (the trial
 // moves test r^2 < 1 in the mover's frame; seen from the partner the same
-// pair may round a few ulp below 1).
-constexpr float kOverlapR2 = 1.0f - 0x1p-16f;
+// pair may round a few ulp below 1, and each rebin re-expresses a
+// coordinate with one rounding while neither sphere moves).
+constexpr float kOverlapR2 = 1.0f - 0x1p-20f;
 
 __global__ void __launch_bounds__(kTile)
 k_count_overlaps3(Geom3 g, Ctl3 *ctl, const float4 *__restrict__ pos,

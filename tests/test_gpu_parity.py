@@ -427,6 +427,13 @@ def test_long_run_loses_nothing(gpu):
     assert G.count_overlaps() == 0
     t, a = G.counters()
     assert 0 < a < t
+    # the margin of the overlap invariant, measured: the smallest r^2 of any
+    # neighbour pair (in the first disk's frame) after 1e5 shifts
+    O = oracle.OracleSystem.grid(G.mx, G.my, wx, wy, delta=0.15, n_moves=4, seed=31)
+    O.set_state(xy, st, sw)
+    r2 = O.min_pair_r2()
+    log("  smallest r^2 after 1e5 shifts: 1 - %.3g" % (1.0 - r2))
+    assert r2 >= np.float32(1.0) - np.float32(2.0 ** -20)
 
 
 def test_paper_benchmark_smallest_matches(gpu):
