@@ -381,6 +381,20 @@ mpmc_status mpmc_mlp_forward(const float *W, const float *X, int32_t n, float *Y
 mpmc_status mpmc_mlp_backward(const float *W, const float *X, const float *cache, const float *dY,
                               int32_t n, float *dW, float *dX, void *work, void *stream);
 
+/* For callers that cannot allocate device memory or pass a workspace (code
+ * under hipGraph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): mpmc_mlp_backward with the same results, bit for bit, and the
+ * same kernels, but its per-workgroup gradient rows live in a device array
+ * of the library (4.6 MiB per GPU, kept until the process ends) instead of
+ * a `work` argument.  Allocates nothing.  n <= MPMC_MLP_NOALLOC_MAX_SAMPLES,
+ * else MPMC_EINVAL.  Every call on one GPU shares that GPU's array, so calls
+ * that overlap on one GPU (other streams, other threads) race; calls in
+ * order on one stream do not.  async. */
+#define MPMC_MLP_NOALLOC_MAX_SAMPLES 65536
+mpmc_status mpmc_mlp_backward_noalloc(const float *W, const float *X, const float *cache,
+                                      const float *dY, int32_t n, float *dW, float *dX,
+                                      void *stream);
+
 /* Squared-error loss 1/(2n) sum (Y - T)^2 into *loss (device FP64) and its
  * gradient dY = (Y - T)/n.  work: mpmc_mlp_work_bytes(n). */
 mpmc_status mpmc_mlp_mse(const float *Y, const float *T, int32_t n, float *dY, double *loss,

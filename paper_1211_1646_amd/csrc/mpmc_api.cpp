@@ -1253,6 +1253,18 @@ mpmc_status mpmc_mlp_backward(const float *W, const float *X, const float *cache
     return MPMC_OK;
 }
 
+mpmc_status mpmc_mlp_backward_noalloc(const float *W, const float *X, const float *cache,
+                                      const float *dY, int32_t n, float *dW, float *dX,
+                                      void *stream)
+{
+    if (n < 0 || !W || !dW || (n > 0 && (!X || !cache || !dY)))
+        return fail(MPMC_EINVAL, "bad backward arguments");
+    if (n > MPMC_MLP_NOALLOC_MAX_SAMPLES)
+        return fail(MPMC_EINVAL, "mpmc_mlp_backward_noalloc: n exceeds MPMC_MLP_NOALLOC_MAX_SAMPLES");
+    MPMC_HIP(mpmc::launch_mlp_backward_noalloc(W, X, cache, dY, n, dW, dX, (hipStream_t)stream));
+    return MPMC_OK;
+}
+
 mpmc_status mpmc_mlp_mse(const float *Y, const float *T, int32_t n, float *dY, double *loss,
                          void *work, void *stream)
 {

@@ -158,6 +158,11 @@ hipError_t launch_mlp_forward(const float *W, const float *X, int n, float *Y, f
 hipError_t launch_mlp_backward(const float *W, const float *X, const float *cache,
                                const float *dY, int n, float *dW, float *dX, void *work,
                                hipStream_t st);
+// The same backward pass with its gradient rows in the library's own device
+// array (no workspace argument, nothing allocated); n <= 65536.
+hipError_t launch_mlp_backward_noalloc(const float *W, const float *X, const float *cache,
+                                       const float *dY, int n, float *dW, float *dX,
+                                       hipStream_t st);
 hipError_t launch_mse(const float *Y, const float *T, int n, float *dY, double *loss, void *work,
                       hipStream_t st);
 hipError_t launch_adam(float *W, float *m, float *v, const float *g, int n, float lr, float b1,

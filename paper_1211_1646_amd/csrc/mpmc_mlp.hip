@@ -14,6 +14,8 @@
 //
 // Parameter vector (row-major, rows are outputs): W1[32][3] b1[32]
 // W2[32][32] b2[32] W3[1][32] b3[1] -- 1217 floats.
+#include <mutex>
+
 #include "mpmc_internal.h"
 
 #pragma clang fp contract(off)
@@ -24,6 +26,7 @@ namespace {
 constexpr int kH = 32;
 constexpr int oW1 = 0, oB1 = 96, oW2 = 128, oB2 = 1152, oW3 = 1184, oB3 = 1216;
 constexpr int kBwdBlock = 64;   // samples per backward workgroup
+constexpr int kNoAllocMaxSamples = 65536;   // largest n of the no-allocation backward
 constexpr int kRow = kBwdBlock + 1;
 
 __device__ __forceinline__ void stage_params(const float *__restrict__ W, float *P)
@@ -294,6 +297,60 @@ hipError_t launch_mlp_backward(const float *W, const float *X, const float *cach
 {
     const int rows = (n + kBwdBlock - 1) / kBwdBlock;
     float *part = (float *)work;
+    if (rows > 0)
+        hipLaunchKernelGGL(k_mlp_backward, dim3(rows), dim3(kBwdBlock), 0, st, W, X, cache, dY, n,
+                           dX, part);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, part, rows, dW);
+    return hipGetLastError();
+}
+
+namespace {
+
+// ------------------------------------------------- no-allocation backward
+// The backward pass's per-workgroup gradient rows in a device array of this
+// library, for callers that cannot allocate (code under graph capture, tight
+// serving loops): at most kNoAllocMaxSamples samples, kNoAllocMaxSamples /
+// kBwdBlock rows of kMlpParams floats (4.6 MiB), held by every GPU the
+// library runs on until the process ends.  Every call on one GPU shares that
+// GPU's copy: calls that overlap on one GPU race.  Each row is written in
+// full before the reduction reads it, so nothing needs clearing.
+constexpr int kNoAllocMaxRows = kNoAllocMaxSamples / kBwdBlock;
+static __device__ __align__(256) float scratch[(size_t)kNoAllocMaxRows * kMlpParams];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices];   // device address of scratch on each GPU
+
+// The device address of the current GPU's copy of scratch, looked up once
+// per device (the array's name is only a host-side stand-in).
+hipError_t scratch_of_current_device(float **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (float *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_mlp_backward_noalloc(const float *W, const float *X, const float *cache,
+                                       const float *dY, int n, float *dW, float *dX,
+                                       hipStream_t st)
+{
+    if (n < 0 || n > kNoAllocMaxSamples) return hipErrorInvalidValue;
+    float *part = nullptr;
+    const hipError_t e = scratch_of_current_device(&part);
+    if (e != hipSuccess) return e;
+    const int rows = (n + kBwdBlock - 1) / kBwdBlock;
     if (rows > 0)
         hipLaunchKernelGGL(k_mlp_backward, dim3(rows), dim3(kBwdBlock), 0, st, W, X, cache, dY, n,
                            dX, part);
