@@ -13,15 +13,20 @@ sub-sweep kernel's achieved bandwidth against the HBM peak, and the CPU
 oracle timed on a bounded sample of the same workload.  Two more objects
 compare the batched and learned-controller forms with the plain form:
   batched -- 64 replicas of uneven N (64^2 .. 512^2) and packing fraction
-             (0.65 .. 0.73) in one handle against the same 64 systems run
-             one after another (same chain, bit for bit); with n_M from the
-             autotuner; and learned+batched: the trained network sets delta
-             during equilibration, n_M autotuned, against the plain systems;
-  learned -- a move-size network trained on samples the sweeps log, used
-             during equilibration of the 1M-disk workload, against the plain
-             tuner: mean-square displacement per second of production
-             sweeps with delta frozen, and P* with its standard error;
-  eos     -- beta P sigma^2 with block errors at phi = 0.700, 0.716, 0.720;
+             (0.65 .. 0.73), all from one equilibrated batch state, in one
+             handle against the same 64 systems run one after another (same
+             chain, bit for bit); with n_M from the autotuner; and
+             learned+batched: the trained network sets delta, n_M
+             autotuned; P* per replica of each form against the plain batch
+             next to a seed control;
+  learned -- a move-size network trained on windows the sweeps log (256^2
+             systems, phi 0.65 .. 0.73), then at phi = 0.700, 0.716 and
+             0.720 both arms start from one equilibrated 1M-disk state: 20
+             windows of the network or the plain tuner, delta frozen, then
+             mean-square displacement per second of production sweeps and
+             beta P sigma^2 with its block error (the plain arm's P* is the
+             equilibrated equation of state, checked against Table 2);
+  eos     -- (with --eos) a short lattice-start P* at the three phi;
   table3  -- the paper's own throughput benchmark like for like: phi 0.698,
              in-circle moves of radius 0.16, n_M = 4, N = 253^2 .. 3040^2,
              median eta of 11 runs next to the paper's K20 figures;
@@ -68,10 +73,20 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-sweeps", type=int, default=160)
-    ap.add_argument("--batched-relax", type=int, default=20000,
-                    help="sweeps between the timed window and the batch's P* check")
+    ap.add_argument("--batched-equilibration", type=int, default=100000,
+                    help="sweeps from the lattices before the batched comparisons")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--no-eos", action="store_true")
+    ap.add_argument("--learned-equilibration", type=int, default=200000,
+                    help="sweeps from the lattice before the learned-vs-plain comparison")
+    ap.add_argument("--learned-production", type=int, default=4000)
+    ap.add_argument("--train-lattice", type=int, default=256,
+                    help="side of the lattices the controller's training windows come from")
+    ap.add_argument("--train-windows", type=int, default=300)
+    ap.add_argument("--no-eos", action="store_true",
+                    help="(kept for old command lines; the short EOS leg runs only with --eos)")
+    ap.add_argument("--eos", action="store_true",
+                    help="also run the short lattice-start EOS leg (equilibrated P* at the three "
+                         "phi comes from the learned leg's plain arms)")
     ap.add_argument("--no-table3", action="store_true",
                     help="skip the paper's Table 3 benchmark (in-circle moves, N = 253^2 .. 3040^2)")
     ap.add_argument("--table3-runs", type=int, default=11)
@@ -191,105 +206,108 @@ def cpu_baseline_spheres(delta):
 
 
 def batched_leg(args, pkg, torch, net=None):
-    """64-replica batch vs the same replicas one after another; with a trained
-    move-size network also the learned+batched form (network-set delta during
-    the equilibration windows, autotuned n_M)."""
+    """64 replicas of uneven N and packing fraction, all started from one
+    equilibrated batch state (plain tuner, then --batched-equilibration
+    sweeps from the lattices): the batched form against the same 64 systems
+    run one after another (bit for bit the same chain), the batched form
+    with n_M picked by the n_M autotuner, and with a trained network the
+    learned+batched form (network-set delta, autotuned n_M).  Each form's P*
+    per replica is compared with the plain batch's, next to a seed control."""
     from paper_1211_1646_amd import workloads as W
+    from paper_1211_1646_amd import controller as ctl
     specs = W.replicas(64, seed=1)
-    cfgs = [pkg.SystemConfig(lattice_nx=s["nx"], lattice_ny=s["ny"], phi=s["phi"], w_min=s["w_min"],
-                             w_max=s["w_max"], delta=0.1, n_moves=args.n_moves, seed=1, replica=r,
-                             flags=pkg.FLAG_ACC) for r, s in enumerate(specs)]
+    lat = [pkg.SystemConfig(lattice_nx=s["nx"], lattice_ny=s["ny"], phi=s["phi"], w_min=s["w_min"],
+                            w_max=s["w_max"], delta=0.1, n_moves=args.n_moves, seed=1, replica=r)
+           for r, s in enumerate(specs)]
+    t0 = time.perf_counter()
+    Beq = pkg.HardDiskBatch(lat)
+    Beq.tune(10, 20)
+    Beq.sweep(args.batched_equilibration)
+    states = [Beq.get_state(r) for r in range(Beq.R)]
+    geos = Beq.geometries
+    deltas = np.array([float(Beq.delta(r)) for r in range(Beq.R)], np.float32)
+    Beq.close()
+    eq_s = time.perf_counter() - t0
+
+    def grid_cfgs(seed=1):
+        return [pkg.SystemConfig(cells_x=g["cells_x"], cells_y=g["cells_y"], cell_w_x=g["w_x"],
+                                 cell_w_y=g["w_y"], n_particles=g["n_particles"],
+                                 delta=float(deltas[r]), n_moves=args.n_moves, seed=seed,
+                                 replica=r, flags=pkg.FLAG_ACC) for r, g in enumerate(geos)]
+
+    def loaded_batch(seed=1):
+        B = pkg.HardDiskBatch(grid_cfgs(seed))
+        for r, st in enumerate(states):
+            B.set_state(r, *st)
+        return B
+
+    def timed(B, n):
+        B.reset_acc()
+        tr0 = B.counters()[0]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        B.prepare_sweeps(n)
+        B.synchronize()
+        e0.record(B.stream)
+        B.sweep(n)
+        e1.record(B.stream)
+        e1.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3
+        _, _, dl, msd = B.stats(with_msd=True)
+        return sec, B.counters()[0] - tr0, dl, msd
+
+    cfgs = grid_cfgs()
+    Ns = np.array([g["n_particles"] for g in geos], np.float64)
     n = args.batched_sweeps
-    B = pkg.HardDiskBatch(cfgs)
-    B.tune(10, 4)
+    n_candidates = pkg.HardDiskBatch.AUTOTUNE_CANDIDATES
+    B = loaded_batch()
     lanes, blk, _ = B.autotune(16)
-    B.reset_acc()
-    tr0 = B.counters()[0]
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    B.synchronize()
-    e0.record(B.stream)
-    B.sweep(n)
-    e1.record(B.stream)
-    e1.synchronize()
-    bsec = e0.elapsed_time(e1) * 1e-3
-    btr = B.counters()[0] - tr0
-    _, _, deltas, msd = B.stats(with_msd=True)
-    Ns = np.array([g["n_particles"] for g in B.geometries], np.float64)
+    bsec, btr, _, msd = timed(B, n)
     b_msd_sum = float((Ns * msd).sum())
-    n_candidates = B.AUTOTUNE_CANDIDATES
-    # the P* check on replicas relaxed well past the lattice start: a larger
-    # n_M relaxes faster, which a check right after the timed window would see
-    B.sweep(args.batched_relax)
     eos_plain = eos_window(B, torch)
     B.close()
-    # the batched form with trials per cell picked by the n_M autotuner
-    # (chain-changing, so on a fresh batch with the same history up to it)
-    from paper_1211_1646_amd import controller as ctl
-    B2 = pkg.HardDiskBatch(cfgs)
-    B2.tune(10, 4)
+    # the batched form with trials per cell from the n_M autotuner
+    B2 = loaded_batch()
     B2.set_launch(lanes, blk)
     best_nm, rates = ctl.autotune_moves(B2, (2, 4, 8, 16), window_sweeps=64)
-    B2.reset_acc()
     B2.sweep(16)                      # graph re-captured for the chosen n_M
-    B2.reset_acc()
-    B2.synchronize()
-    e0.record(B2.stream)
-    B2.sweep(n)
-    e1.record(B2.stream)
-    e1.synchronize()
-    a_sec = e0.elapsed_time(e1) * 1e-3
-    _, _, _, msd2 = B2.stats(with_msd=True)
+    a_sec, _, _, msd2 = timed(B2, n)
     a_msd_sum = float((Ns * msd2).sum())
-    B2.sweep(args.batched_relax)
     eos_auto = eos_window(B2, torch)
     B2.close()
     z = np.abs(eos_auto[0] - eos_plain[0]) / np.sqrt(eos_auto[1] ** 2 + eos_plain[1] ** 2)
-    # learned + batched: the network sets every replica's delta in the four
-    # equilibration windows where the plain form runs its tuner, then delta
-    # is frozen and n_M is the autotuned one
     lb = None
     if net is not None:
-        B4 = pkg.HardDiskBatch(cfgs)
+        B4 = loaded_batch()
         B4.control(net, 10, 4)
         B4.set_launch(lanes, blk)
         B4.set_n_moves(best_nm)
-        B4.sweep(n_candidates * 32)
-        B4.reset_acc()
-        B4.synchronize()
-        e0.record(B4.stream)
-        B4.sweep(n)
-        e1.record(B4.stream)
-        e1.synchronize()
-        l_sec = e0.elapsed_time(e1) * 1e-3
-        _, _, l_deltas, msd4 = B4.stats(with_msd=True)
+        B4.sweep(16)
+        l_sec, _, l_deltas, msd4 = timed(B4, n)
         l_msd_sum = float((Ns * msd4).sum())
-        B4.sweep(args.batched_relax)
         eos_lb = eos_window(B4, torch)
         B4.close()
         z4 = np.abs(eos_lb[0] - eos_plain[0]) / np.sqrt(eos_lb[1] ** 2 + eos_plain[1] ** 2)
         lb = (l_msd_sum / l_sec, l_deltas, z4)
-    # control: the same n_M = 4 batch with another seed and the same history
-    # length -- the spread two runs of one chain show in this check
-    cfgs3 = [pkg.SystemConfig(**{**c.__dict__, "seed": 2}) for c in cfgs]
-    B3 = pkg.HardDiskBatch(cfgs3)
-    B3.tune(10, 4)
+    # control: the plain batch from the same states with another seed
+    B3 = loaded_batch(seed=2)
     B3.set_launch(lanes, blk)
-    B3.sweep(n_candidates * 32 + n + args.batched_relax)
+    B3.sweep(n_candidates * 32 + n)
     eos_ctrl = eos_window(B3, torch)
     B3.close()
     z0 = np.abs(eos_ctrl[0] - eos_plain[0]) / np.sqrt(eos_ctrl[1] ** 2 + eos_plain[1] ** 2)
-    # the same replicas, one handle each, one after another, with the same
-    # history (tuner windows, then the sweeps the autotuner ran), so each
-    # timed window runs exactly the chain the batch ran
+    # the same replicas, one handle each, one after another, through the same
+    # chain as the plain batch (the autotuner's sweeps, then the timed window)
     seq_sec, seq_tr, seq_msd = 0.0, 0, 0.0
     for r, c in enumerate(cfgs):
         S = pkg.HardDiskSystem(c)
-        S.tune(10, 4)
+        S.set_state(*states[r])
         S.set_launch(lanes, blk)
         S.sweep(n_candidates * 32)
-        assert np.float32(S.delta) == np.float32(deltas[r])
         t0 = S.counters()[0]
         S.reset_acc()
+        S.prepare_sweeps(n)
+        S.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(S.stream)
         S.sweep(n)
         e1.record(S.stream)
@@ -298,33 +316,37 @@ def batched_leg(args, pkg, torch, net=None):
         seq_tr += S.counters()[0] - t0
         seq_msd += float(Ns[r]) * S.msd()
         S.close()
+
+    def zsum(v):
+        return {"mean": float(v.mean()), "max": float(v.max()),
+                "frac_above_2": float((v > 2).mean()), "frac_above_3": float((v > 3).mean())}
+
     out = {"replicas": len(cfgs), "disks": int(Ns.sum()), "sweeps": n,
-            "trial_moves_per_s": btr / bsec, "sequential_trial_moves_per_s": seq_tr / seq_sec,
-            "speedup": (btr / bsec) / (seq_tr / seq_sec),
-            "msd_sum_per_s": b_msd_sum / bsec, "sequential_msd_sum_per_s": seq_msd / seq_sec,
-            "subsweep_lanes_per_cell": lanes, "subsweep_block": blk,
-            "autotuned_n_moves": best_nm,
-            "autotune_msd_per_s_by_n_moves": {str(k): v for k, v in rates.items()},
-            "autotuned_msd_sum_per_s": a_msd_sum / a_sec,
-            "autotuned_vs_sequential_msd_per_s": (a_msd_sum / a_sec) / (seq_msd / seq_sec),
-            "eos_check": "P* per replica over 8 blocks of 256 sweeps, after %d more sweeps past the "
-                         "timed window, n_M = %d vs the autotuned n_M: |dP| / combined SE mean %.2f, "
-                         "max %.2f over %d replicas"
-                         % (args.batched_relax, args.n_moves, float(z.mean()), float(z.max()), len(z)),
-            "eos_z": [float(v) for v in z],
-            "eos_control": "same check between two n_M = %d batches with seeds 1 and 2: mean %.2f, "
-                           "max %.2f" % (args.n_moves, float(z0.mean()), float(z0.max())),
-            "eos_z_control": [float(v) for v in z0]}
+           "equilibration_sweeps": args.batched_equilibration + 200,
+           "equilibration_seconds": eq_s,
+           "trial_moves_per_s": btr / bsec, "sequential_trial_moves_per_s": seq_tr / seq_sec,
+           "speedup": (btr / bsec) / (seq_tr / seq_sec),
+           "msd_sum_per_s": b_msd_sum / bsec, "sequential_msd_sum_per_s": seq_msd / seq_sec,
+           "subsweep_lanes_per_cell": lanes, "subsweep_block": blk,
+           "autotuned_n_moves": best_nm,
+           "autotune_msd_per_s_by_n_moves": {str(k): v for k, v in rates.items()},
+           "autotuned_msd_sum_per_s": a_msd_sum / a_sec,
+           "autotuned_vs_sequential_msd_per_s": (a_msd_sum / a_sec) / (seq_msd / seq_sec),
+           "eos_check": "P* per replica over 8 blocks of 256 sweeps after the timed window, from "
+                        "equilibrated states: autotuned n_M vs n_M = %d, |dP| / combined SE"
+                        % args.n_moves,
+           "eos_z": zsum(z),
+           "eos_z_control": zsum(z0),
+           "eos_control": "the n_M = %d batch with seed 2 against seed 1, same check" % args.n_moves}
     if lb is not None:
         out["learned_batched"] = {
             "msd_sum_per_s": lb[0],
             "vs_sequential_plain_msd_per_s": lb[0] / (seq_msd / seq_sec),
+            "vs_batched_plain_msd_per_s": lb[0] / (b_msd_sum / bsec),
             "n_moves": best_nm,
             "delta_range": [float(np.min(lb[1])), float(np.max(lb[1]))],
             "plain_delta_range": [float(np.min(deltas)), float(np.max(deltas))],
-            "eos_check": "P* vs the plain n_M = %d batch, same check: |dP| / combined SE mean "
-                         "%.2f, max %.2f" % (args.n_moves, float(lb[2].mean()), float(lb[2].max())),
-            "eos_z": [float(v) for v in lb[2]]}
+            "eos_z": zsum(lb[2])}
     return out
 
 
@@ -443,38 +465,91 @@ def eos_leg(args, pkg, torch, lanes, block):
     return out
 
 
+PAPER_TABLE2_INTERP = {"0.700": (9.16934 + 9.1882) / 2,      # Table 2, N = 1024^2, linear
+                       "0.716": (9.1819 + 9.1951) / 2}        # between the neighbouring phi
+
+
+def equilibrated_state(pkg, args, phi, sweeps, lanes, block):
+    """The 1M-disk system at phi after the plain tuner (20 windows of 10
+    sweeps) and `sweeps` more sweeps from the lattice: (cells, widths,
+    state).  Both arms of a comparison start from this same state."""
+    cfg = pkg.SystemConfig(lattice_nx=args.lattice, lattice_ny=args.lattice, phi=phi,
+                           w_max=math.sqrt(2.0), delta=0.1, n_moves=args.n_moves, seed=1)
+    S = pkg.HardDiskSystem(cfg)
+    S.set_launch(lanes, block)
+    S.tune(10, 20)
+    S.sweep(sweeps)
+    xy, st, sw = S.get_state()
+    geo = S.geometry
+    S.close()
+    return geo, (xy, st, sw)
+
+
+def arm_from_state(pkg, args, geo, state, lanes, block, seed):
+    """A fresh handle on the grid of `geo`, loaded with `state`, keeping
+    displacement accumulators."""
+    cfg = pkg.SystemConfig(cells_x=geo["cells_x"], cells_y=geo["cells_y"],
+                           cell_w_x=geo["w_x"], cell_w_y=geo["w_y"],
+                           n_particles=geo["n_particles"], delta=0.1, n_moves=args.n_moves,
+                           seed=seed, flags=pkg.FLAG_ACC)
+    S = pkg.HardDiskSystem(cfg)
+    S.set_state(*state)
+    S.set_launch(lanes, block)
+    return S
+
+
 def learned_leg(args, pkg, torch, lanes_main, block_main):
-    """Train the controller on logged windows, then compare it with the plain
-    tuner on the 1M-disk workload."""
+    """Train the controller on windows logged from 256^2-disk systems (the
+    medium workload's size) over phi 0.65 .. 0.73, then compare it with the
+    plain tuner on the 1M-disk workload at phi 0.700, 0.716 and 0.720, both
+    arms starting from one equilibrated state: 20 windows of 10 sweeps with
+    the tuner or the network, delta frozen, then production sweeps with
+    mean-square displacement per second and P* with its block error."""
     from paper_1211_1646_amd import controller as ctl
     phis = [0.65, 0.66, 0.67, 0.68, 0.69, 0.70, 0.71, 0.72, 0.73]
     deltas = [0.02, 0.04, 0.06, 0.08, 0.10, 0.12, 0.14, 0.16, 0.18, 0.20, 0.22, 0.24, 0.26,
               0.28, 0.30]
-    base = [pkg.SystemConfig(lattice_nx=64, lattice_ny=64, phi=p, w_max=math.sqrt(2.0),
-                             n_moves=args.n_moves, seed=1) for p in phis]
+    base = [pkg.SystemConfig(lattice_nx=args.train_lattice, lattice_ny=args.train_lattice, phi=p,
+                             w_max=math.sqrt(2.0), n_moves=args.n_moves, seed=1) for p in phis]
     t0 = time.perf_counter()
-    net, info = ctl.train_controller(base, deltas, windows=740, window_sweeps=10, skip=20,
-                                     steps=2000)
+    net, info = ctl.train_controller(base, deltas, windows=args.train_windows, window_sweeps=10,
+                                     skip=20, steps=2000)
     train_s = time.perf_counter() - t0
-    res = {}
-    for mode in ("plain", "learned"):
-        cfg = pkg.SystemConfig(lattice_nx=args.lattice, lattice_ny=args.lattice, phi=args.phi,
-                               w_max=math.sqrt(2.0), delta=0.1, n_moves=args.n_moves, seed=1,
-                               flags=pkg.FLAG_ACC)
-        S = pkg.HardDiskSystem(cfg)
-        S.set_launch(lanes_main, block_main)
-        res[mode] = ctl.equilibrate_and_measure(S, mode, net, eq_windows=30, window_sweeps=10,
-                                                prod_sweeps=1000, sample_every=10, blocks=10)
-        S.close()
-    pl, le = res["plain"], res["learned"]
-    comb = math.hypot(pl["P_se"], le["P_se"])
-    return {"workload": "N=%d phi=%.3f" % (args.lattice ** 2, args.phi),
-            "training_samples": info["samples"], "training_seconds": train_s,
-            "loss_first": info["loss_first"], "loss_last": info["loss_last"],
-            "labels": {"%.2f" % k: v for k, v in sorted(info["labels"].items())},
-            "plain": pl, "learned": le,
-            "msd_per_s_ratio": le["msd_per_s"] / pl["msd_per_s"],
-            "P_diff_in_combined_se": abs(le["P"] - pl["P"]) / comb if comb > 0 else None}, net
+    out = {"training": {"systems": "%d x %d disks, phi %.2f .. %.2f, %d deltas"
+                                   % (args.train_lattice, args.train_lattice, phis[0], phis[-1],
+                                      len(deltas)),
+                        "samples": info["samples"], "seconds": train_s,
+                        "loss_first": info["loss_first"], "loss_last": info["loss_last"],
+                        "labels": {"%.2f" % k: v for k, v in sorted(info["labels"].items())}},
+           "equilibration_sweeps": args.learned_equilibration + 200,
+           "production_sweeps": args.learned_production}
+    for phi in (0.700, 0.716, 0.720):
+        geo, state = equilibrated_state(pkg, args, phi, args.learned_equilibration, lanes_main,
+                                        block_main)
+        res = {}
+        for mode in ("plain", "learned"):
+            S = arm_from_state(pkg, args, geo, state, lanes_main, block_main, seed=11)
+            res[mode] = ctl.equilibrate_and_measure(S, mode, net, eq_windows=20, window_sweeps=10,
+                                                    prod_sweeps=args.learned_production,
+                                                    sample_every=10, blocks=10)
+            S.close()
+        pl, le = res["plain"], res["learned"]
+        comb = math.hypot(pl["P_se"], le["P_se"])
+        key = "%.3f" % phi
+        entry = {"plain": pl, "learned": le,
+                 "msd_per_s_ratio": le["msd_per_s"] / pl["msd_per_s"],
+                 "P_diff_in_combined_se": abs(le["P"] - pl["P"]) / comb if comb > 0 else None,
+                 "equal_eos_accuracy": bool(comb > 0 and abs(le["P"] - pl["P"]) <= 3 * comb
+                                            and le["P_se"] <= 1.25 * pl["P_se"])}
+        if key in PAPER_TABLE2_INTERP:
+            ref = PAPER_TABLE2_INTERP[key]
+            entry["plain_P_vs_table2_interp"] = {"table2": ref, "rel": pl["P"] / ref - 1.0,
+                                                 "within_0.2pct": abs(pl["P"] / ref - 1.0) <= 2e-3}
+        out[key] = entry
+        print("[bench] learned phi=%.3f: MSD/s x%.3f, P* %.4f (%.4f) vs %.4f (%.4f)"
+              % (phi, entry["msd_per_s_ratio"], le["P"], le["P_se"], pl["P"], pl["P_se"]),
+              file=sys.stderr, flush=True)
+    return out, net
 
 
 TUNER_WINDOWS = 20          # plain tuner during set-up: 20 windows ...
@@ -661,7 +736,7 @@ def main():
             out["learned"], net = res
     if not args.no_batched:
         side_leg("batched", out, lambda: batched_leg(args, pkg, torch, net))
-    if not args.no_eos:
+    if args.eos and not args.no_eos:
         side_leg("eos", out, lambda: eos_leg(args, pkg, torch, lanes_main, block_main))
     if not args.no_table3:
         side_leg("table3", out, lambda: table3_leg(args, pkg, torch))

@@ -269,6 +269,14 @@ mpmc_status mpmc_replica_set_state(mpmc_handle h, int32_t r, const float *xy,
 mpmc_status mpmc_get_aux(mpmc_handle h, float *acc, uint32_t *tags);
 mpmc_status mpmc_replica_get_aux(mpmc_handle h, int32_t r, float *acc, uint32_t *tags);
 
+/* Utility (state transfer): load displacement accumulators acc[2N] in the
+ * list order of the current state (the order mpmc_get_aux reports), so a
+ * checkpoint taken with mpmc_get_state + mpmc_get_aux resumes bit for bit
+ * after mpmc_set_state (which clears them) + mpmc_set_acc (sync).
+ * MPMC_EINVAL without MPMC_FLAG_ACC. */
+mpmc_status mpmc_set_acc(mpmc_handle h, const float *acc);
+mpmc_status mpmc_replica_set_acc(mpmc_handle h, int32_t r, const float *acc);
+
 /* Accept bits (MPMC_FLAG_ACCEPT_LOG; Alg. 2's accept decisions): bits[c],
  * c over the cells in row-major order, has bit s set when trial s (s < 32)
  * of cell c's latest update was accepted.  A sweep updates every cell once,

@@ -100,6 +100,8 @@ _SIGNATURES = {
                                      C.POINTER(C.c_void_p)]),
     "mpmc_sweep": (C.c_int32, [_H, C.c_int64, C.c_uint32]),
     "mpmc_prepare_sweeps": (C.c_int32, [_H, C.c_int64]),
+    "mpmc_set_acc": (C.c_int32, [_H, C.c_void_p]),
+    "mpmc_replica_set_acc": (C.c_int32, [_H, C.c_int32, C.c_void_p]),
     "mpmc_subsweep": (C.c_int32, [_H, C.c_int32]),
     "mpmc_shift_and_rebin": (C.c_int32, [_H, C.c_int32, C.c_float]),
     "mpmc_pair_histogram": (C.c_int32, [_H, C.c_int32]),

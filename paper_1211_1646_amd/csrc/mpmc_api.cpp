@@ -965,6 +965,36 @@ mpmc_status mpmc_replica_get_aux(mpmc_handle h, int32_t r, float *acc, uint32_t 
     return MPMC_OK;
 }
 
+mpmc_status mpmc_replica_set_acc(mpmc_handle h, int32_t r, const float *acc)
+{
+    MPMC_NEED_LOADED(h, r);
+    if (!acc) return fail(MPMC_EINVAL, "null argument");
+    if (!h->acc[h->cur]) return fail(MPMC_EINVAL, "system built without MPMC_FLAG_ACC");
+    const Rep &R = h->L.reps[(size_t)r];
+    std::vector<uint32_t> cnt;
+    mpmc_status s = read_slots(h, R, nullptr, nullptr, cnt);
+    if (s) return s;
+    s = read_ctl(h);   // waits for the counts
+    if (s) return s;
+    const size_t S = (size_t)h->t.cap, n = (size_t)R.g.C * S;
+    std::vector<float2> slots(std::max<size_t>(n, 1), make_float2(0.0f, 0.0f));
+    size_t k = 0;
+    for (int c = 0; c < R.g.C; ++c)
+        for (uint32_t i = 0; i < cnt[(size_t)c]; ++i, ++k)
+            slots[(size_t)c * S + i] = make_float2(acc[2 * k], acc[2 * k + 1]);
+    if ((long long)k != R.g.N) return fail(MPMC_EDEVICE, "cell counts do not add up to N");
+    if (n) MPMC_HIP(hipMemcpyAsync(h->acc[h->cur] + (size_t)R.cb * S, slots.data(), sizeof(float2) * n,
+                                   hipMemcpyHostToDevice, h->st));
+    MPMC_HIP(hipStreamSynchronize(h->st));   // the host array goes out of scope
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_set_acc(mpmc_handle h, const float *acc)
+{
+    MPMC_NEED_SINGLE(h);
+    return mpmc_replica_set_acc(h, 0, acc);
+}
+
 mpmc_status mpmc_get_aux(mpmc_handle h, float *acc, uint32_t *tags)
 {
     MPMC_NEED_SINGLE(h);

@@ -215,6 +215,11 @@ class HardDiskSystem:
     def reset_acc(self):
         L.check(self.lib.mpmc_reset_acc(self._h))
 
+    def set_acc(self, acc):
+        """Load accumulators [N][2] in the current list order (checkpoint resume)."""
+        acc = np.ascontiguousarray(acc, np.float32)
+        L.check(self.lib.mpmc_set_acc(self._h, acc.ctypes.data))
+
     def accept_log(self):
         """Per-cell accept bits of each cell's latest update (row-major)."""
         out = np.zeros(self.C, np.uint32)
@@ -350,6 +355,10 @@ class HardDiskBatch:
             tp = tags.ctypes.data
         L.check(self.lib.mpmc_replica_set_state(self._h, int(r), xy.ctypes.data if xy.size else None,
                                                 start.ctypes.data, int(sweep), tp))
+
+    def set_acc(self, r: int, acc):
+        acc = np.ascontiguousarray(acc, np.float32)
+        L.check(self.lib.mpmc_replica_set_acc(self._h, int(r), acc.ctypes.data))
 
     def aux(self, r: int):
         n = int(self.geometries[r]["n_particles"])
