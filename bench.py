@@ -675,20 +675,37 @@ def main():
           % (args.steps, gpu_ms, wall, value, (t1_acc - t0_acc) / max(trials, 1)),
           file=sys.stderr, flush=True)
 
-    # dominant kernel: the sub-sweep (four launches per sweep)
-    ks = max(4, args.kernel_samples)
-    k_avg_ms = kernel_time(S, torch, ks)
-    # algorithmic bytes per sub-sweep launch: every position read once (8 N),
-    # every cell count read once (4 C), the active quarter of positions
-    # written back (8 N / 4)
-    bytes_per_launch = 8.0 * N + 4.0 * C + 2.0 * N
-    achieved = bytes_per_launch / (k_avg_ms * 1e-3) / 1e9
     cap = geo["capacity"]
-    # template arguments: capacity, [lanes per cell,] proposal (0 = square)
-    kernel_name = ("k_subsweep<%d, 0>" % cap if S.lanes == 1
-                   else "k_subsweep_mc<%d, %d, 0>" % (cap, S.lanes))
+    fused = S.fused
+    if fused:
+        # dominant kernel: the fused sweep, one launch per sweep, so its mean
+        # launch time is the timed region's per sweep (graph gaps included);
+        # algorithmic bytes of a sweep: four sub-sweeps reading every
+        # position and count (4 (8 N + 4 C)), the active cells' write-backs
+        # (8 N), the rebuild reading and writing positions and counts
+        # (16 N + 8 C): 56 N + 24 C
+        ks = args.steps
+        k_avg_ms = gpu_ms / args.steps
+        bytes_per_launch = 56.0 * N + 24.0 * C
+        kernel_name = "k_sweep_fused<%d, 0>" % cap
+        timing = ("the timed region: %d sweeps, one launch each, HIP events on the system's "
+                  "stream (graph gaps included)" % args.steps)
+    else:
+        # dominant kernel: the sub-sweep (four launches per sweep); bytes per
+        # launch: every position read once (8 N), every cell count read once
+        # (4 C), the active quarter of positions written back (8 N / 4)
+        ks = max(4, args.kernel_samples)
+        k_avg_ms = kernel_time(S, torch, ks)
+        bytes_per_launch = 8.0 * N + 4.0 * C + 2.0 * N
+        # template arguments: capacity, [lanes per cell,] proposal (0 = square), one system
+        kernel_name = ("k_subsweep<%d, 0, true>" % cap if S.lanes == 1
+                       else "k_subsweep_mc<%d, %d, 0, true>" % (cap, S.lanes))
+        timing = ("%d launches in one captured graph, HIP events around the replay on the "
+                  "system's stream (graph gaps included)" % ks)
+    achieved = bytes_per_launch / (k_avg_ms * 1e-3) / 1e9
     S.synchronize()
     src = os.path.join(ROOT, "paper_1211_1646_amd", "csrc", "mpmc_kernels.hip")
+    prof = "sweep_fused_1M_phi070_counters.md" if fused else "subsweep_1M_phi070_counters.md"
 
     out = {
         "metric": "trial moves/sec at 1M disks phi=0.70; MSD/sec learned+batched vs plain",
@@ -710,6 +727,8 @@ def main():
                    "sweeps_per_s": args.steps / secs,
                    "acceptance": (t1_acc - t0_acc) / max(trials, 1),
                    "trial_moves_per_sweep": trials / args.steps,
+                   "sweep_kernel": "fused (one tiled launch per sweep)" if fused
+                                   else "four sub-sweep launches and a rebuild",
                    "subsweep_lanes_per_cell": S.lanes,
                    "subsweep_block": S.block,
                    "tuner_sweeps": plan["tuner_sweeps"],
@@ -720,11 +739,11 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_from_profile(src, kernel_name),
-                     "valu_busy": traffic_from_profile(src, kernel_name, "valu busy fraction"),
+                     "traffic": traffic_from_profile(src, kernel_name, profile=prof),
+                     "valu_busy": traffic_from_profile(src, kernel_name, "valu busy fraction",
+                                                       profile=prof),
                      "kernel": kernel_name, "kernel_avg_us": k_avg_ms * 1e3,
-                     "kernel_timing": "%d launches in one captured graph, HIP events around the "
-                                      "replay on the system's stream (graph gaps included)" % ks,
+                     "kernel_timing": timing,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
     S.close()

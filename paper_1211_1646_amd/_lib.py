@@ -100,6 +100,8 @@ _SIGNATURES = {
                                      C.POINTER(C.c_void_p)]),
     "mpmc_sweep": (C.c_int32, [_H, C.c_int64, C.c_uint32]),
     "mpmc_prepare_sweeps": (C.c_int32, [_H, C.c_int64]),
+    "mpmc_set_sweep_kernel": (C.c_int32, [_H, C.c_int32]),
+    "mpmc_get_sweep_kernel": (C.c_int32, [_H, C.POINTER(C.c_int32)]),
     "mpmc_set_acc": (C.c_int32, [_H, C.c_void_p]),
     "mpmc_replica_set_acc": (C.c_int32, [_H, C.c_int32, C.c_void_p]),
     "mpmc_subsweep": (C.c_int32, [_H, C.c_int32]),
@@ -150,6 +152,8 @@ _SIGNATURES = {
                                      C.c_void_p]),
     "mpmc_mlp_backward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mpmc_mlp_backward_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                              C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mpmc_mlp_mse": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p]),
     "mpmc_adam_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,

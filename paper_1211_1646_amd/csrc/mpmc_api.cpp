@@ -270,6 +270,7 @@ struct mpmc_system {
     int cur;
     int block;                    // sub-sweep workgroup size
     int lanes;                    // sub-sweep lanes per active cell
+    bool fused;                   // whole sweeps in one tiled launch where supported
     uint32_t *alog;               // per-cell accept bits, or null
     std::vector<uint32_t> key0;   // current key word 0 of each replica
     std::vector<char> loaded;     // replica holds a valid, overlap-free state
@@ -336,8 +337,20 @@ mpmc_status enqueue_rebin(mpmc_system *h, int f, float d, int advance)
     return MPMC_OK;
 }
 
+bool use_fused(const mpmc_system *h)
+{
+    return h->fused && mpmc::sweep_fused_supported(h->t, h->acc[0] != nullptr, h->tag[0] != nullptr);
+}
+
 mpmc_status enqueue_sweep(mpmc_system *h)
 {
+    if (use_fused(h)) {
+        const int o = h->cur ^ 1;
+        MPMC_HIP(mpmc::launch_sweep_fused(h->t, h->cur, h->pos[h->cur], h->count[h->cur], h->pos[o],
+                                          h->count[o], h->alog, h->work, h->st));
+        h->cur = o;
+        return MPMC_OK;
+    }
     for (int slot = 0; slot < 4; ++slot) {
         const mpmc_status s = enqueue_subsweep(h, -1 - slot);
         if (s) return s;
@@ -673,6 +686,7 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
     h->cur = 0;
     h->block = 256;
     h->lanes = 1;
+    h->fused = true;
     h->key0.resize((size_t)n);
     for (int r = 0; r < n; ++r) h->key0[(size_t)r] = p[r].seed;
     h->loaded.assign((size_t)n, 0);
@@ -1176,6 +1190,22 @@ mpmc_status mpmc_set_launch(mpmc_handle h, int32_t lanes_per_cell, int32_t block
     if (block_size != h->block || lanes_per_cell != h->lanes) drop_graphs(h);
     h->block = block_size;
     h->lanes = lanes_per_cell;
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_set_sweep_kernel(mpmc_handle h, int32_t fused)
+{
+    if (!h) return fail(MPMC_EINVAL, "null handle");
+    const bool f = fused != 0;
+    if (f != h->fused) drop_graphs(h);
+    h->fused = f;
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_get_sweep_kernel(mpmc_handle h, int32_t *fused)
+{
+    if (!h || !fused) return fail(MPMC_EINVAL, "null argument");
+    *fused = use_fused(h) ? 1 : 0;
     return MPMC_OK;
 }
 

@@ -128,6 +128,15 @@ hipError_t launch_rebin(const Tables &t, int par, const float2 *pos, const uint3
                         const float2 *acc, const uint32_t *tag, float2 *pos_out,
                         uint32_t *count_out, float2 *acc_out, uint32_t *tag_out,
                         const Work &w, int f, float d, int advance, hipStream_t st);
+// A whole sweep (the four sub-sweeps in the sweep's set order, then the
+// shift and rebuild with the sweep's own draws) in one launch: reads half
+// par, writes half par ^ 1 and advances the sweep.  The same chain as
+// launch_subsweep x 4 + launch_rebin, bit for bit.  Supported for a single
+// system of capacity 4 without accumulators or tags (accept bits are kept).
+bool sweep_fused_supported(const Tables &t, bool acc, bool tag);
+hipError_t launch_sweep_fused(const Tables &t, int par, const float2 *pos, const uint32_t *count,
+                              float2 *pos_out, uint32_t *count_out, uint32_t *alog, const Work &w,
+                              hipStream_t st);
 hipError_t launch_pair_histogram(const Tables &t, const float2 *pos, const uint32_t *count,
                                  int reset, hipStream_t st);
 hipError_t launch_pressure_fit(const Tables &t, int replica, hipStream_t st);

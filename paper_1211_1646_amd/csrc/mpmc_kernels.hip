@@ -223,7 +223,7 @@ __device__ __forceinline__ float min_r2(float xm, float ym, const float2 *e)
                  fminf(d2x * d2x + d2y * d2y, d3x * d3x + d3y * d3y));
 }
 
-template <int CAP, int PROP>
+template <int CAP, int PROP, bool ONE>
 __global__ void __launch_bounds__(256)
 k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restrict__ count,
            float2 *__restrict__ acc, uint32_t *__restrict__ tag, uint32_t *__restrict__ alog,
@@ -240,8 +240,10 @@ k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restri
     constexpr int kRow = kL + 1;
     const int tile = xcd_tile(per);
     const long long slot0 = (long long)tile * blockDim.x;
-    const int r = chunk_replica(t, tile < ntile, slot0 / kActiveChunk);
-    const Rep R = rep_of(t, r);
+    // ONE: a single system, whose table entry is a kernel argument (read
+    // with the other arguments, no dependent load)
+    const int r = ONE ? 0 : chunk_replica(t, tile < ntile, slot0 / kActiveChunk);
+    const Rep R = ONE ? t.rep0 : t.reps[r];
     const Geom g = R.g;
     Ctl *ctl = t.ctls + r;
     const unsigned long long s = ctl->sweep_at[par];
@@ -258,7 +260,7 @@ k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restri
     if (Q < 0) Q = (int)((ctl->draw_at[par].order >> (8 * (-1 - set))) & 0xFFu);
     const int qx = Q & 1, qy = Q >> 1;
     const int hx = g.mx >> 1, hy = g.my >> 1;
-    const long long gid = slot0 + (long long)threadIdx.x - R.ab;   // within the replica
+    const int gid = (int)(slot0 - R.ab) + (int)threadIdx.x;        // within the replica
     float2 *const nbr = lds + threadIdx.x * kRow;   // this lane's neighbour list
     float2 *const ovf = ovf_all + (size_t)(slot0 + (long long)threadIdx.x) * kO;
     const uint32_t *const cn = count + R.cb;        // this replica's cell counts
@@ -267,8 +269,8 @@ k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restri
     unsigned n_trials = 0, n_acc = 0;
     uint32_t abits = 0;
     long long log_cell = -1;   // global cell index of this lane's cell, if any
-    if (tile < ntile && gid < (long long)hx * hy) {
-        const int iy = (int)(gid / hx), ix = (int)(gid - (long long)iy * hx);
+    if (tile < ntile && gid < hx * hy) {
+        const int iy = (int)((unsigned)gid / (unsigned)hx), ix = gid - iy * hx;
         const int cx = 2 * ix + qx, cy = 2 * iy + qy;
         const int c = cy * g.mx + cx;
         log_cell = R.cb + c;
@@ -501,7 +503,7 @@ k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restri
 // identical; the gain is twice or four times the waves in flight, each with
 // a shorter chain of dependent work, where a launch has too few cells to
 // hide latency.
-template <int CAP, int LPC, int PROP>
+template <int CAP, int LPC, int PROP, bool ONE>
 __global__ void __launch_bounds__(256)
 k_subsweep_mc(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restrict__ count,
               float2 *__restrict__ acc, uint32_t *__restrict__ tag, uint32_t *__restrict__ alog,
@@ -517,8 +519,8 @@ k_subsweep_mc(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__res
     const int tile = xcd_tile(per);
     const long long lane0 = (long long)tile * blockDim.x;
     const long long slot0 = lane0 / LPC;
-    const int r = chunk_replica(t, tile < ntile, slot0 / kActiveChunk);
-    const Rep R = rep_of(t, r);
+    const int r = ONE ? 0 : chunk_replica(t, tile < ntile, slot0 / kActiveChunk);
+    const Rep R = ONE ? t.rep0 : t.reps[r];
     const Geom g = R.g;
     Ctl *ctl = t.ctls + r;
     const unsigned long long s = ctl->sweep_at[par];
@@ -536,7 +538,7 @@ k_subsweep_mc(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__res
     const int qx = Q & 1, qy = Q >> 1;
     const int hx = g.mx >> 1, hy = g.my >> 1;
     const int h = (int)(threadIdx.x % LPC);
-    const long long gid = slot0 + (long long)(threadIdx.x / LPC) - R.ab;   // cell within the replica
+    const int gid = (int)(slot0 - R.ab) + (int)(threadIdx.x / LPC);   // cell within the replica
     float2 *const nbr = lds + threadIdx.x * kRow;
     float2 *const ovf = ovf_all + (size_t)(lane0 + (long long)threadIdx.x) * kO;
     const uint32_t *const cn = count + R.cb;        // this replica's cell counts
@@ -545,8 +547,8 @@ k_subsweep_mc(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__res
     unsigned n_trials = 0, n_acc = 0;
     uint32_t abits = 0;
     long long log_cell = -1;   // global cell index of this lane's cell, if any
-    if (tile < ntile && gid < (long long)hx * hy) {
-        const int iy = (int)(gid / hx), ix = (int)(gid - (long long)iy * hx);
+    if (tile < ntile && gid < hx * hy) {
+        const int iy = (int)((unsigned)gid / (unsigned)hx), ix = gid - iy * hx;
         const int cx = 2 * ix + qx, cy = 2 * iy + qy;
         const int c = cy * g.mx + cx;
         log_cell = R.cb + c;
@@ -816,14 +818,14 @@ __device__ __forceinline__ float shifted(float v, bool minus, float d)
     return minus ? v - d : v + d;
 }
 
-template <int CAP>
+template <int CAP, bool ONE>
 __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
 {
     const int tile = xcd_tile(a.per);
     if (tile >= a.ntile) return;
     const long long cell0 = (long long)tile * kRebinTile;
-    const int r = tile_replica(a.t, true, tile);
-    const Rep R = rep_of(a.t, r);
+    const int r = ONE ? 0 : tile_replica(a.t, true, tile);
+    const Rep R = ONE ? a.t.rep0 : a.t.reps[r];
     const Geom g = R.g;
     Ctl *ctl = a.t.ctls + r;
     int f = a.f;
@@ -837,7 +839,7 @@ __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
     const float w = along_x ? g.wx : g.wy;
     const float sw = minus ? w : -w;         // translation into the receiving cell
 
-    const long long cl = cell0 + (long long)threadIdx.x - R.cb;   // cell within the replica
+    const int cl = (int)(cell0 - R.cb) + (int)threadIdx.x;        // cell within the replica
     const bool valid = cl < g.C;
     unsigned stay = 0, leave = 0;   // bit i: own slot i stays / neighbour slot i leaves
     size_t ob = 0, nbb = 0;         // first slots of the two cells
@@ -913,6 +915,327 @@ __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
             ctl->draw_at[a.par ^ 1] = ctl->draw_at[a.par];
         }
     }
+}
+
+// ------------------------------------------------------- fused sweep
+// A whole sweep (Alg. 1: the four sub-sweeps in the sweep's set order, then
+// Alg. 4's shift and rebuild) in one launch, tile by tile.  A workgroup owns
+// an interior of at most kFT x kFT cells and loads it with a halo of kFH = 5
+// cells into LDS; sub-sweep p (1..4) then updates the cells of its set in
+// the box [p, R - p) of the loaded region, so that after the fourth the box
+// [4, R - 4) holds the sweep's final state, and the rebuild of an interior
+// cell c needs only c and its neighbour in direction f, both inside it.  A
+// cell of the halo is updated by every tile that loads it, each time with
+// the same neighbourhood and the same Philox stream (keyed by the global
+// cell and the sweep), so every copy ends identical to the one its owner
+// computes: the result is the chain of the four separate launches, bit for
+// bit, while the cells are read from and written to device memory once per
+// sweep.  Only interior updates are counted (trials, accepts, accept bits).
+// Slots past a cell's count hold a far-away disk in LDS, so the overlap
+// tests need no masks; the 3x3 neighbourhood is tested in full (no reach
+// filter: with the data in LDS the filter costs what it saves).
+constexpr int kFT = 36;                  // interior cells per side (even)
+constexpr int kFH = 5;                   // halo: four sub-sweeps and the rebuild
+constexpr int kFR = kFT + 2 * kFH;       // loaded region per side (even)
+constexpr int kFBlock = 512;             // lanes per workgroup
+constexpr float kFar = 1.0e6f;
+// LDS layout: the region split into its four parity planes (cell (rx, ry)
+// in plane (rx & 1) + 2 (ry & 1) at (ry >> 1, rx >> 1)), one array per slot.
+// The active cells of a set are then consecutive in one plane, and so are
+// each of their neighbours in the other planes: lanes read consecutive
+// 8-byte words, free of bank conflicts.
+constexpr int kPW = kFR / 2;             // plane width
+constexpr int kPS = kPW * kPW;           // plane size
+constexpr int kRC = 4 * kPS;             // region cells
+
+__device__ __forceinline__ int lds_cell(int rx, int ry)
+{
+    return ((rx & 1) + 2 * (ry & 1)) * kPS + (ry >> 1) * kPW + (rx >> 1);
+}
+
+template <int CAP>
+constexpr size_t fused_lds_bytes()
+{
+    return (size_t)kRC * CAP * sizeof(float2) + (size_t)kRC;
+}
+
+struct FusedArgs {
+    Tables t;
+    const float2 *pos;
+    const uint32_t *count;
+    float2 *pos_out;
+    uint32_t *count_out;
+    uint32_t *alog;
+    unsigned long long *cnt;
+    int cnt_stride;
+    int par;
+    int tiles_x, tiles_y;
+    int per;
+};
+
+// One cell update (Alg. 2) on the LDS copy of the region: cell (rx, ry) of
+// the region, global cell c of the replica.  The same decisions, in the same
+// FP32 operations, as k_subsweep.
+template <int CAP, int PROP>
+__device__ __forceinline__ void fused_cell_update(float2 *sp, uint8_t *sn, int rx, int ry,
+                                                  uint32_t c, float wx, float wy,
+                                                  uint32_t s_lo, uint32_t s_hi, uint32_t k0,
+                                                  uint32_t k1, float delta, int n_moves,
+                                                  bool disk, bool shuffle, unsigned &n_acc,
+                                                  uint32_t &abits)
+{
+    const int r = lds_cell(rx, ry);
+    const int n = (int)sn[r];
+    if (n == 0) return;
+    uint4 Wsh = make_uint4(0, 0, 0, 0);
+    if (shuffle && n > 1) Wsh = philox(c, s_lo, s_hi, kTagShuffle, k0, k1);
+    uint4 W = make_uint4(0, 0, 0, 0);
+    if (n_moves > 0) W = philox(c, s_lo, s_hi, 0u, k0, k1);
+    float px[CAP], py[CAP];
+#pragma unroll
+    for (int i = 0; i < CAP; ++i) {
+        const float2 v = sp[i * kRC + r];
+        px[i] = v.x;
+        py[i] = v.y;
+    }
+    // the eight neighbours' slots in this cell's frame (exactly -w, 0, +w)
+    float nx[8 * CAP], ny[8 * CAP];
+#pragma unroll
+    for (int q = 0, e = 0; q < 9; ++q) {
+        if (q == 4) continue;
+        const int ra = q / 3, cb = q % 3;
+        const int rq = lds_cell(rx + cb - 1, ry + ra - 1);
+#pragma unroll
+        for (int i = 0; i < CAP; ++i, ++e) {
+            const float2 v = sp[i * kRC + rq];
+            float ox = v.x, oy = v.y;
+            if (cb == 0) ox = ox - wx;
+            if (cb == 2) ox = ox + wx;
+            if (ra == 0) oy = oy - wy;
+            if (ra == 2) oy = oy + wy;
+            nx[e] = ox;
+            ny[e] = oy;
+        }
+    }
+    uint32_t P = 0x76543210u;
+    const int nshuf = shuffle ? n - 1 : 0;
+    for (int k = 0; k < nshuf; ++k) {
+        if (k > 0 && (k & 3) == 0)
+            Wsh = philox(c, s_lo, s_hi, kTagShuffle + (uint32_t)(k >> 2), k0, k1);
+        const int i = n - 1 - k;
+        const int j = (int)bounded(word_of(Wsh, k & 3), (uint32_t)(i + 1));
+        P = nib_swap(P, i, j);
+    }
+    if (nshuf > 0) {
+        rperm(px, P);
+        rperm(py, P);
+    }
+    // rperm moved far entries into the list only if n < CAP, and only from
+    // slots >= n: the permutation leaves positions >= n in place
+    for (int tr = 0; tr < n_moves; ++tr) {
+        if (tr > 0 && (tr & 3) == 0) W = philox(c, s_lo, s_hi, (uint32_t)(tr >> 2), k0, k1);
+        float dx, dy;
+        if (disk)
+            disk_displacement(word_of(W, tr & 3), delta, dx, dy);
+        else
+            displacement(word_of(W, tr & 3), delta, dx, dy);
+        const float xm = px[0] + dx;
+        const float ym = py[0] + dy;
+        bool ok = (xm > 0.0f) & (xm <= wx) & (ym > 0.0f) & (ym <= wy);
+#pragma unroll
+        for (int q = 1; q < CAP; ++q) {
+            const float ddx = xm - px[q];
+            const float ddy = ym - py[q];
+            const float r2 = ddx * ddx + ddy * ddy;
+            ok = ok & !(r2 < 1.0f);
+        }
+#pragma unroll
+        for (int e = 0; e < 8 * CAP; e += 4) {
+            const float d0x = xm - nx[e], d0y = ym - ny[e];
+            const float d1x = xm - nx[e + 1], d1y = ym - ny[e + 1];
+            const float d2x = xm - nx[e + 2], d2y = ym - ny[e + 2];
+            const float d3x = xm - nx[e + 3], d3y = ym - ny[e + 3];
+            const float m = fminf(fminf(d0x * d0x + d0y * d0y, d1x * d1x + d1y * d1y),
+                                  fminf(d2x * d2x + d2y * d2y, d3x * d3x + d3y * d3y));
+            ok = ok & !(m < 1.0f);
+        }
+        if (tr < 32) abits |= (ok ? 1u : 0u) << tr;
+        px[0] = ok ? xm : px[0];
+        py[0] = ok ? ym : py[0];
+        n_acc += ok ? 1u : 0u;
+        rrot(px, n);
+        rrot(py, n);
+    }
+    // register entry q holds list position (q + n_M) mod n: back to LDS in
+    // list order (slots >= n keep their far entries)
+    const int r0 = n_moves % n;
+#pragma unroll
+    for (int o = 0; o < CAP; ++o) {
+        if (o < n) {
+            int q = o - r0;
+            q = q < 0 ? q + n : q;
+            sp[o * kRC + r] = make_float2(rsel(px, q), rsel(py, q));
+        }
+    }
+}
+
+template <int CAP, int PROP>
+__global__ void __launch_bounds__(kFBlock, 2) k_sweep_fused(FusedArgs a)
+{
+    extern __shared__ float2 lds_f[];
+    float2 *sp = lds_f;                                         // [CAP][kRC]
+    uint8_t *sn = (uint8_t *)(lds_f + (size_t)kRC * CAP);       // [kRC]
+    const int tile = xcd_tile(a.per);
+    const int ntile = a.tiles_x * a.tiles_y;
+    if (tile >= ntile) return;
+    const Rep R = a.t.rep0;
+    const Geom g = R.g;
+    Ctl *ctl = a.t.ctls;
+    const int tyi = tile / a.tiles_x, txi = tile - tyi * a.tiles_x;
+    const int x0 = txi * kFT, y0 = tyi * kFT;
+    const int wI = min(kFT, g.mx - x0), hI = min(kFT, g.my - y0);
+    const int RX = wI + 2 * kFH, RY = hI + 2 * kFH;
+    const unsigned long long s = ctl->sweep_at[a.par];
+    const uint32_t k0 = ctl->key0, k1 = ctl->key1;
+    const float delta = ctl->delta;
+    const uint32_t order = ctl->draw_at[a.par].order;
+    const int f = ctl->draw_at[a.par].f;
+    const float d = ctl->draw_at[a.par].d;
+    const int n_moves = R.n_moves;
+    const bool disk = PROP == 2 ? R.disk != 0 : PROP == 1;
+    const bool shuffle = PROP == 2 ? (R.ablate & kAblateParticleShuffle) == 0 : true;
+    const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
+    const uint32_t *cn = a.count + R.cb;
+    const float2 *pin = a.pos + (size_t)R.cb * CAP;
+
+    // load the region: cell (rx, ry) is global cell ((x0 - kFH + rx) mod mx,
+    // (y0 - kFH + ry) mod my); slots past the count hold a far disk
+    bool bad = false;
+    for (int i = threadIdx.x; i < RX * RY; i += kFBlock) {
+        const int ry = i / RX, rx = i - ry * RX;
+        int gx = x0 - kFH + rx, gy = y0 - kFH + ry;
+        gx = gx < 0 ? gx + g.mx : (gx >= g.mx ? gx - g.mx : gx);
+        gy = gy < 0 ? gy + g.my : (gy >= g.my ? gy - g.my : gy);
+        gx = gx < 0 ? gx + g.mx : (gx >= g.mx ? gx - g.mx : gx);   // grids narrower than
+        gy = gy < 0 ? gy + g.my : (gy >= g.my ? gy - g.my : gy);   // the halo wrap twice
+        const int c = gy * g.mx + gx;
+        uint32_t n = cn[c];
+        float2 v[CAP];
+#pragma unroll
+        for (int k = 0; k < CAP; ++k) v[k] = pin[(size_t)c * CAP + k];
+        if (n > (uint32_t)g.cap) {
+            bad = true;
+            n = 0;
+        }
+        const int r = lds_cell(rx, ry);
+        sn[r] = (uint8_t)n;
+#pragma unroll
+        for (int k = 0; k < CAP; ++k) sp[k * kRC + r] = k < (int)n ? v[k] : make_float2(kFar, kFar);
+    }
+    if (bad) atomicOr((unsigned int *)&ctl->errword, kErrCapacity);
+    __syncthreads();
+
+    // four sub-sweeps, each on its set's cells of a box one cell smaller
+    unsigned n_trials = 0, n_acc = 0;
+#pragma unroll 1
+    for (int p = 1; p <= 4; ++p) {
+        const int Q = (int)((order >> (8 * (p - 1))) & 0xFFu);
+        const int qx = Q & 1, qy = Q >> 1;
+        // region column rx is global column x0 - kFH + rx: parity of rx + 1
+        const int fx = p + (((p + 1) ^ qx) & 1), fy = p + (((p + 1) ^ qy) & 1);
+        const int nxa = (RX - p - fx + 1) >> 1, nya = (RY - p - fy + 1) >> 1;
+        for (int i = threadIdx.x; i < nxa * nya; i += kFBlock) {
+            const int iy = i / nxa, ix = i - iy * nxa;
+            const int rx = fx + 2 * ix, ry = fy + 2 * iy;
+            int gx = x0 - kFH + rx, gy = y0 - kFH + ry;
+            gx = gx < 0 ? gx + g.mx : (gx >= g.mx ? gx - g.mx : gx);
+            gy = gy < 0 ? gy + g.my : (gy >= g.my ? gy - g.my : gy);
+            gx = gx < 0 ? gx + g.mx : (gx >= g.mx ? gx - g.mx : gx);
+            gy = gy < 0 ? gy + g.my : (gy >= g.my ? gy - g.my : gy);
+            const uint32_t c = (uint32_t)(gy * g.mx + gx);
+            const bool inner = rx >= kFH && rx < kFH + wI && ry >= kFH && ry < kFH + hI;
+            unsigned acc_here = 0;
+            uint32_t bits = 0;
+            const int nbefore = (int)sn[lds_cell(rx, ry)];
+            fused_cell_update<CAP, PROP>(sp, sn, rx, ry, c, g.wx, g.wy, s_lo, s_hi, k0, k1,
+                                         delta, n_moves, disk, shuffle, acc_here, bits);
+            if (inner) {
+                n_acc += acc_here;
+                n_trials += nbefore > 0 ? (unsigned)n_moves : 0u;
+                if (a.alog) a.alog[R.cb + c] = bits;
+            }
+        }
+        __syncthreads();
+    }
+
+    // the shift and rebuild (Alg. 4) of the interior: new cell c holds the
+    // stayers of c, then the leavers of its neighbour in direction f
+    const bool along_x = f < 2;
+    const bool minus = (f == 0 || f == 2);   // +x / +y: t = v - d
+    const float w = along_x ? g.wx : g.wy;
+    const float swd = minus ? w : -w;
+    const int ddx = along_x ? (minus ? 1 : -1) : 0;
+    const int ddy = along_x ? 0 : (minus ? 1 : -1);
+    bool over = false;
+    for (int i = threadIdx.x; i < wI * hI; i += kFBlock) {
+        const int iy = i / wI, ix = i - iy * wI;
+        const int rx = kFH + ix, ry = kFH + iy;
+        const int ro = lds_cell(rx, ry), rn = lds_cell(rx + ddx, ry + ddy);
+        const int no = (int)sn[ro], nn = (int)sn[rn];
+        // candidates in list order (own slots, then the neighbour's), each
+        // kept by its one rounded shifted coordinate; kept candidate i goes
+        // to output slot popcount(keep below i)
+        float2 cand[2 * CAP];
+        uint32_t keep = 0u;
+#pragma unroll
+        for (int k = 0; k < CAP; ++k) {
+            const float2 v = sp[k * kRC + ro];
+            const float tt = shifted(along_x ? v.x : v.y, minus, d);
+            cand[k] = along_x ? make_float2(tt, v.y) : make_float2(v.x, tt);
+            keep |= (k < no && tt > 0.0f && tt <= w) ? 1u << k : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < CAP; ++k) {
+            const float2 v = sp[k * kRC + rn];
+            const float tt = shifted(along_x ? v.x : v.y, minus, d);
+            const float t2 = tt + swd;
+            cand[CAP + k] = along_x ? make_float2(t2, v.y) : make_float2(v.x, t2);
+            keep |= (k < nn && !(tt > 0.0f && tt <= w)) ? 1u << (CAP + k) : 0u;
+        }
+        float2 out[CAP];
+#pragma unroll
+        for (int k = 0; k < CAP; ++k) out[k] = make_float2(kFar, kFar);
+#pragma unroll
+        for (int i = 0; i < 2 * CAP; ++i) {
+            const bool kk = (keep >> i) & 1u;
+            const int idx = __popc(keep & ((1u << i) - 1u));
+#pragma unroll
+            for (int j = 0; j < CAP; ++j) out[j] = (kk && idx == j) ? cand[i] : out[j];
+        }
+        int o = __popc(keep);
+        if (o > g.cap) {
+            over = true;
+            o = g.cap;
+        }
+        const int c = (y0 + iy) * g.mx + (x0 + ix);
+        a.count_out[R.cb + c] = (uint32_t)o;
+#pragma unroll
+        for (int k = 0; k < CAP; ++k) a.pos_out[(size_t)(R.cb + c) * CAP + k] = out[k];
+    }
+    if (over) atomicOr((unsigned int *)&ctl->errword, kErrCapacity);
+    // padding cells of the replica (beyond C) keep count 0 in the half written
+    if (tile == 0)
+        for (long long i = g.C + threadIdx.x; i < R.cpad; i += kFBlock) a.count_out[R.cb + i] = 0u;
+    // counts per wave into a granule of the replica (folded on demand)
+    const unsigned bt = wave_sum_u32(n_trials);
+    const unsigned ba = wave_sum_u32(n_acc);
+    if ((threadIdx.x & 63u) == 0 && bt) {
+        const long long ng = R.apad / kGranule;
+        const long long gr = R.ab / kGranule + ((long long)tile * (kFBlock / 64) + threadIdx.x / 64) % ng;
+        atomicAdd(&a.cnt[gr], (unsigned long long)bt);
+        atomicAdd(&a.cnt[a.cnt_stride + gr], (unsigned long long)ba);
+    }
+    if (tile == 0 && threadIdx.x == 0) store_draws(ctl, a.par ^ 1, s + 1ull, R);
 }
 
 // ------------------------------------------------------ pair histogram
@@ -1300,19 +1623,25 @@ hipError_t launch_subsweep(const Tables &t, int par, float2 *pos, const uint32_t
     const int e = 8 / lanes * t.cap;
     const int row = (e < kNbrLds ? e : kNbrLds) + 1;
     const size_t lds = (size_t)row * block * sizeof(float2);
-#define MPMC_SUB(CAP, PROP)                                                                    \
+#define MPMC_SUB1(CAP, PROP, ONE)                                                              \
     do {                                                                                       \
         if (lanes == 1)                                                                        \
-            hipLaunchKernelGGL((k_subsweep<CAP, PROP>), grid, blk, lds, st, t, par, pos, count,  \
-                               acc, tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile, per);    \
+            hipLaunchKernelGGL((k_subsweep<CAP, PROP, ONE>), grid, blk, lds, st, t, par, pos,    \
+                               count, acc, tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile,  \
+                               per);                                                           \
         else if (lanes == 2)                                                                   \
-            hipLaunchKernelGGL((k_subsweep_mc<CAP, 2, PROP>), grid, blk, lds, st, t, par, pos,   \
-                               count, acc, tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile,  \
-                               per);                                                           \
+            hipLaunchKernelGGL((k_subsweep_mc<CAP, 2, PROP, ONE>), grid, blk, lds, st, t, par,   \
+                               pos, count, acc, tag, alog, w.cnt, w.cnt_stride, w.ovf, set,    \
+                               ntile, per);                                                    \
         else                                                                                   \
-            hipLaunchKernelGGL((k_subsweep_mc<CAP, 4, PROP>), grid, blk, lds, st, t, par, pos,   \
-                               count, acc, tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile,  \
-                               per);                                                           \
+            hipLaunchKernelGGL((k_subsweep_mc<CAP, 4, PROP, ONE>), grid, blk, lds, st, t, par,   \
+                               pos, count, acc, tag, alog, w.cnt, w.cnt_stride, w.ovf, set,    \
+                               ntile, per);                                                    \
+    } while (0)
+#define MPMC_SUB(CAP, PROP)                                                                    \
+    do {                                                                                       \
+        if (t.R == 1) MPMC_SUB1(CAP, PROP, true);                                              \
+        else MPMC_SUB1(CAP, PROP, false);                                                      \
     } while (0)
 #define MPMC_SUB_P(CAP)                                                                        \
     do {                                                                                       \
@@ -1330,12 +1659,44 @@ hipError_t launch_subsweep(const Tables &t, int par, float2 *pos, const uint32_t
     }
 #undef MPMC_SUB_P
 #undef MPMC_SUB
+#undef MPMC_SUB1
     return hipGetLastError();
 }
 
 hipError_t launch_fold_counters(const Tables &t, const Work &w, hipStream_t st)
 {
     hipLaunchKernelGGL(k_fold_counters, dim3(t.R), dim3(256), 0, st, t, w.cnt, w.cnt_stride);
+    return hipGetLastError();
+}
+
+bool sweep_fused_supported(const Tables &t, bool acc, bool tag)
+{
+    return t.R == 1 && t.cap == 4 && !acc && !tag;
+}
+
+hipError_t launch_sweep_fused(const Tables &t, int par, const float2 *pos, const uint32_t *count,
+                              float2 *pos_out, uint32_t *count_out, uint32_t *alog, const Work &w,
+                              hipStream_t st)
+{
+    if (t.R != 1 || t.cap != 4) return hipErrorInvalidValue;
+    FusedArgs a;
+    a.t = t;
+    a.pos = pos;
+    a.count = count;
+    a.pos_out = pos_out;
+    a.count_out = count_out;
+    a.alog = alog;
+    a.cnt = w.cnt;
+    a.cnt_stride = w.cnt_stride;
+    a.par = par;
+    a.tiles_x = (t.rep0.g.mx + kFT - 1) / kFT;
+    a.tiles_y = (t.rep0.g.my + kFT - 1) / kFT;
+    a.per = per_xcd(a.tiles_x * a.tiles_y);
+    const dim3 grid(8 * a.per), blk(kFBlock);
+    const size_t lds = fused_lds_bytes<4>();
+    if (t.prop == 0) hipLaunchKernelGGL((k_sweep_fused<4, 0>), grid, blk, lds, st, a);
+    else if (t.prop == 1) hipLaunchKernelGGL((k_sweep_fused<4, 1>), grid, blk, lds, st, a);
+    else hipLaunchKernelGGL((k_sweep_fused<4, 2>), grid, blk, lds, st, a);
     return hipGetLastError();
 }
 
@@ -1355,7 +1716,11 @@ hipError_t launch_rebin(const Tables &t, int par, const float2 *pos, const uint3
     a.ntile = tiles_for(t.cells, kRebinTile);
     a.per = per_xcd(a.ntile);
     const dim3 grid(8 * a.per), blk(kRebinTile);
-#define MPMC_REBIN(CAP) hipLaunchKernelGGL((k_rebin<CAP>), grid, blk, 0, st, a)
+#define MPMC_REBIN(CAP)                                                                        \
+    do {                                                                                       \
+        if (t.R == 1) hipLaunchKernelGGL((k_rebin<CAP, true>), grid, blk, 0, st, a);           \
+        else hipLaunchKernelGGL((k_rebin<CAP, false>), grid, blk, 0, st, a);                   \
+    } while (0)
     switch (t.cap) {
     case 4: MPMC_REBIN(4); break;
     case 5: MPMC_REBIN(5); break;

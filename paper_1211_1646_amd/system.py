@@ -134,6 +134,17 @@ class HardDiskSystem:
         if seed is not None:
             self.cfg.seed = int(seed)
 
+    def set_fused(self, on: bool = True):
+        """Whole sweeps in one tiled launch where supported (the default), or
+        four sub-sweep launches and a rebuild; the chain is the same."""
+        L.check(self.lib.mpmc_set_sweep_kernel(self._h, 1 if on else 0))
+
+    @property
+    def fused(self) -> bool:
+        v = C.c_int32()
+        L.check(self.lib.mpmc_get_sweep_kernel(self._h, C.byref(v)))
+        return bool(v.value)
+
     def prepare_sweeps(self, n: int):
         """Capture the graphs a following sweep(n) launches (runs nothing)."""
         L.check(self.lib.mpmc_prepare_sweeps(self._h, int(n)))
@@ -308,6 +319,8 @@ class HardDiskBatch:
 
     close = HardDiskSystem.close
     prepare_sweeps = HardDiskSystem.prepare_sweeps
+    set_fused = HardDiskSystem.set_fused
+    fused = HardDiskSystem.fused
     __del__ = HardDiskSystem.__del__
     subsweep = HardDiskSystem.subsweep
     shift_and_rebin = HardDiskSystem.shift_and_rebin
