@@ -337,14 +337,15 @@ mpmc_status mpmc_tune(mpmc_handle h, int32_t window_sweeps, int32_t n_windows);
 mpmc_status mpmc_set_launch(mpmc_handle h, int32_t lanes_per_cell, int32_t block_size);
 
 /* Utility (performance only): how mpmc_sweep launches a sweep.  fused != 0
- * (the default) runs each whole sweep -- the four sub-sweeps in the sweep's
- * set order, then the shift and rebuild -- as one tiled launch that keeps a
- * tile of cells with a five-cell halo in LDS and recomputes the halo's
- * updates, where that form is supported (a single system of capacity 4
- * without MPMC_FLAG_ACC or MPMC_FLAG_TAG); fused == 0, or an unsupported
- * system, launches the four sub-sweeps and the rebuild separately.  The
- * chain is the same, bit for bit.  mpmc_get_sweep_kernel reports whether
- * sweeps of this handle run fused (1) or not (0).  Host only. */
+ * (the default) runs each whole sweep of every replica -- the four
+ * sub-sweeps in the sweep's set order, then the shift and rebuild -- as one
+ * tiled launch that keeps a tile of cells with a five-cell halo in LDS and
+ * recomputes the halo's updates, where that form is supported (every
+ * replica of capacity 4, i.e. cells narrower than sqrt(2)); fused == 0, or
+ * an unsupported handle, launches the four sub-sweeps and the rebuild
+ * separately.  The chain is the same, bit for bit.  mpmc_get_sweep_kernel
+ * reports whether sweeps of this handle run fused (1) or not (0).  Host
+ * only. */
 mpmc_status mpmc_set_sweep_kernel(mpmc_handle h, int32_t fused);
 mpmc_status mpmc_get_sweep_kernel(mpmc_handle h, int32_t *fused);
 

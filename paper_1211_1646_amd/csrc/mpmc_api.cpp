@@ -162,6 +162,8 @@ struct Layout {
     std::vector<mpmc_geometry> geo;
     std::vector<Rep> reps;
     long long N = 0, cells = 0, active = 0;
+    long long ftiles = 0;   // fused-sweep tiles, all replicas
+    int ftile = 0;          // their side in cells
     int cap = 0;
 };
 
@@ -204,11 +206,18 @@ mpmc_status plan(const mpmc_params *p, int n, Layout *L)
         R.disk = (p[r].flags & MPMC_FLAG_DISK) ? 1 : 0;
         R.ablate = ((p[r].flags & MPMC_FLAG_NO_PARTICLE_SHUFFLE) ? mpmc::kAblateParticleShuffle : 0) |
                    ((p[r].flags & MPMC_FLAG_NO_SET_SHUFFLE) ? mpmc::kAblateSetShuffle : 0);
+        // tiles of the fused sweep, at the side the shared buffer flags call for
+        L->ftile = mpmc::fused_tile((p[0].flags & MPMC_FLAG_ACC) != 0, (p[0].flags & MPMC_FLAG_TAG) != 0);
+        R.tiles_x = (g.cells_x + L->ftile - 1) / L->ftile;
+        R.tiles_y = (g.cells_y + L->ftile - 1) / L->ftile;
+        R.tb = L->ftiles;
+        L->ftiles += (long long)R.tiles_x * R.tiles_y;
         L->cells += R.cpad;
         L->N += R.g.N;
         L->active += R.apad;
         L->cap = std::max(L->cap, R.g.cap);
     }
+    if (L->ftiles > 0x7FFFFF00LL) return fail(MPMC_EGEOM, "too many cells");
     if (L->N > 0xFFFFFF00LL) return fail(MPMC_EGEOM, "too many disks (32-bit offsets)");
     if (L->cells > 0x7FFFFF00LL) return fail(MPMC_EGEOM, "too many cells");
     return MPMC_OK;
@@ -224,7 +233,7 @@ size_t work_bytes(const Layout &L)
 // Control buffer: Ctl[R], Rep[R], replica of each active chunk, replica of
 // each rebin tile.
 struct CtlLayout {
-    size_t reps, arep, crep, total;
+    size_t reps, arep, crep, trep, total;
 };
 
 CtlLayout ctl_layout(const Layout &L)
@@ -234,7 +243,8 @@ CtlLayout ctl_layout(const Layout &L)
     c.reps = align256(R * sizeof(Ctl));
     c.arep = c.reps + align256(R * sizeof(Rep));
     c.crep = c.arep + align256((size_t)(L.active / mpmc::kActiveChunk) * 2);
-    c.total = c.crep + align256((size_t)(L.cells / mpmc::kRebinTile) * 2);
+    c.trep = c.crep + align256((size_t)(L.cells / mpmc::kRebinTile) * 2);
+    c.total = c.trep + align256((size_t)L.ftiles * 2);
     return c;
 }
 
@@ -337,17 +347,15 @@ mpmc_status enqueue_rebin(mpmc_system *h, int f, float d, int advance)
     return MPMC_OK;
 }
 
-bool use_fused(const mpmc_system *h)
-{
-    return h->fused && mpmc::sweep_fused_supported(h->t, h->acc[0] != nullptr, h->tag[0] != nullptr);
-}
+bool use_fused(const mpmc_system *h) { return h->fused && mpmc::sweep_fused_supported(h->t); }
 
 mpmc_status enqueue_sweep(mpmc_system *h)
 {
     if (use_fused(h)) {
-        const int o = h->cur ^ 1;
-        MPMC_HIP(mpmc::launch_sweep_fused(h->t, h->cur, h->pos[h->cur], h->count[h->cur], h->pos[o],
-                                          h->count[o], h->alog, h->work, h->st));
+        const int c = h->cur, o = c ^ 1;
+        MPMC_HIP(mpmc::launch_sweep_fused(h->t, c, h->pos[c], h->count[c], h->acc[c], h->tag[c],
+                                          h->pos[o], h->count[o], h->acc[o], h->tag[o], h->alog,
+                                          h->work, h->st));
         h->cur = o;
         return MPMC_OK;
     }
@@ -668,6 +676,9 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
     h->t.reps = (const Rep *)(cb + cl.reps);
     h->t.arep = (const uint16_t *)(cb + cl.arep);
     h->t.crep = (const uint16_t *)(cb + cl.crep);
+    h->t.trep = (const uint16_t *)(cb + cl.trep);
+    h->t.ftiles = L.ftiles;
+    h->t.ftile = L.ftile;
     h->t.rep0 = L.reps[0];
     h->t.R = n;
     h->t.cap = L.cap;
@@ -698,8 +709,11 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
 
     std::vector<uint16_t> arep((size_t)(L.active / mpmc::kActiveChunk));
     std::vector<uint16_t> crep((size_t)(L.cells / mpmc::kRebinTile));
+    std::vector<uint16_t> trep((size_t)L.ftiles);
     for (int r = 0; r < n; ++r) {
         const Rep &R = L.reps[(size_t)r];
+        for (long long i = R.tb; i < R.tb + (long long)R.tiles_x * R.tiles_y; ++i)
+            trep[(size_t)i] = (uint16_t)r;
         for (long long i = R.ab / mpmc::kActiveChunk; i < (R.ab + R.apad) / mpmc::kActiveChunk; ++i)
             arep[(size_t)i] = (uint16_t)r;
         for (long long i = R.cb / mpmc::kRebinTile; i < (R.cb + R.cpad) / mpmc::kRebinTile; ++i)
@@ -711,6 +725,7 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
     hipError_t e = up(cb + cl.reps, L.reps.data(), sizeof(Rep) * (size_t)n);
     if (e == hipSuccess) e = up(cb + cl.arep, arep.data(), arep.size() * 2);
     if (e == hipSuccess) e = up(cb + cl.crep, crep.data(), crep.size() * 2);
+    if (e == hipSuccess) e = up(cb + cl.trep, trep.data(), trep.size() * 2);
     const long long slots = L.cells * (long long)S;
     if (e == hipSuccess) e = up(h->pos[0], xy_g.data(), sizeof(float2) * (size_t)slots);
     if (e == hipSuccess) e = up(h->count[0], count_g.data(), sizeof(uint32_t) * count_g.size());

@@ -76,6 +76,8 @@ struct Rep {
     float delta0;
     int disk;            // 1: in-circle trial moves, 0: square
     int ablate;          // kAblate* bits: shuffles switched off (Table 1)
+    int tiles_x, tiles_y; // tiles of the fused sweep over this replica's grid
+    long long tb;        // the replica's first fused-sweep tile
 };
 
 // Device tables of a handle (in the caller's control buffer), passed to the
@@ -86,6 +88,9 @@ struct Tables {
     Ctl *ctls;              // [R]
     const uint16_t *arep;   // replica of each active chunk
     const uint16_t *crep;   // replica of each rebin tile
+    const uint16_t *trep;   // replica of each fused-sweep tile
+    long long ftiles;       // fused-sweep tiles, all replicas
+    int ftile;              // fused-sweep tile side (cells), set by the buffer flags
     int R;
     int cap;                // largest capacity
     int prop;               // sub-sweep variant: 0 all square, 1 all in-circle, 2 per replica
@@ -129,14 +134,17 @@ hipError_t launch_rebin(const Tables &t, int par, const float2 *pos, const uint3
                         uint32_t *count_out, float2 *acc_out, uint32_t *tag_out,
                         const Work &w, int f, float d, int advance, hipStream_t st);
 // A whole sweep (the four sub-sweeps in the sweep's set order, then the
-// shift and rebuild with the sweep's own draws) in one launch: reads half
-// par, writes half par ^ 1 and advances the sweep.  The same chain as
-// launch_subsweep x 4 + launch_rebin, bit for bit.  Supported for a single
-// system of capacity 4 without accumulators or tags (accept bits are kept).
-bool sweep_fused_supported(const Tables &t, bool acc, bool tag);
+// shift and rebuild with the sweep's own draws) of every replica in one
+// launch: reads half par, writes half par ^ 1 and advances every replica's
+// sweep.  The same chain as launch_subsweep x 4 + launch_rebin, bit for bit.
+// Supported when every replica has capacity 4 (slot layout of 4).
+// fused_tile: the tile side the handle's buffer flags call for.
+int fused_tile(bool acc, bool tag);
+bool sweep_fused_supported(const Tables &t);
 hipError_t launch_sweep_fused(const Tables &t, int par, const float2 *pos, const uint32_t *count,
-                              float2 *pos_out, uint32_t *count_out, uint32_t *alog, const Work &w,
-                              hipStream_t st);
+                              const float2 *acc, const uint32_t *tag, float2 *pos_out,
+                              uint32_t *count_out, float2 *acc_out, uint32_t *tag_out,
+                              uint32_t *alog, const Work &w, hipStream_t st);
 hipError_t launch_pair_histogram(const Tables &t, const float2 *pos, const uint32_t *count,
                                  int reset, hipStream_t st);
 hipError_t launch_pressure_fit(const Tables &t, int replica, hipStream_t st);

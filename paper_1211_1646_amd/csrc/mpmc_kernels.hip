@@ -920,83 +920,121 @@ __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
 // ------------------------------------------------------- fused sweep
 // A whole sweep (Alg. 1: the four sub-sweeps in the sweep's set order, then
 // Alg. 4's shift and rebuild) in one launch, tile by tile.  A workgroup owns
-// an interior of at most kFT x kFT cells and loads it with a halo of kFH = 5
-// cells into LDS; sub-sweep p (1..4) then updates the cells of its set in
-// the box [p, R - p) of the loaded region, so that after the fourth the box
-// [4, R - 4) holds the sweep's final state, and the rebuild of an interior
-// cell c needs only c and its neighbour in direction f, both inside it.  A
-// cell of the halo is updated by every tile that loads it, each time with
-// the same neighbourhood and the same Philox stream (keyed by the global
-// cell and the sweep), so every copy ends identical to the one its owner
-// computes: the result is the chain of the four separate launches, bit for
-// bit, while the cells are read from and written to device memory once per
-// sweep.  Only interior updates are counted (trials, accepts, accept bits).
-// Slots past a cell's count hold a far-away disk in LDS, so the overlap
-// tests need no masks; the 3x3 neighbourhood is tested in full (no reach
-// filter: with the data in LDS the filter costs what it saves).
-constexpr int kFT = 36;                  // interior cells per side (even)
+// an interior of at most TILE x TILE cells of one replica and loads it with
+// a halo of kFH = 5 cells into LDS; sub-sweep p (1..4) then updates the
+// cells of its set in the box [p, R - p) of the loaded region, so that after
+// the fourth the box [4, R - 4) holds the sweep's final state, and the
+// rebuild of an interior cell c needs only c and its neighbour in direction
+// f, both inside it.  A cell of the halo is updated by every tile that loads
+// it, each time with the same neighbourhood and the same Philox stream
+// (keyed by the cell and the sweep), so every copy ends identical to the one
+// its owner computes: the result is the chain of the four separate launches,
+// bit for bit, while the cells are read from and written to device memory
+// once per sweep.  Only interior updates are counted (trials, accepts,
+// accept bits).  Slots past a cell's count hold a far-away disk in LDS, so
+// the overlap tests need no masks; the 3x3 neighbourhood is tested in full
+// (no reach filter: with the data in LDS it costs what it saves).
+// Accumulators and tags, when kept, live in LDS beside the positions and
+// follow their disks; they take room, so the tile is smaller with them.
 constexpr int kFH = 5;                   // halo: four sub-sweeps and the rebuild
-constexpr int kFR = kFT + 2 * kFH;       // loaded region per side (even)
 constexpr int kFBlock = 512;             // lanes per workgroup
 constexpr float kFar = 1.0e6f;
-// LDS layout: the region split into its four parity planes (cell (rx, ry)
-// in plane (rx & 1) + 2 (ry & 1) at (ry >> 1, rx >> 1)), one array per slot.
-// The active cells of a set are then consecutive in one plane, and so are
-// each of their neighbours in the other planes: lanes read consecutive
-// 8-byte words, free of bank conflicts.
-constexpr int kPW = kFR / 2;             // plane width
-constexpr int kPS = kPW * kPW;           // plane size
-constexpr int kRC = 4 * kPS;             // region cells
 
-__device__ __forceinline__ int lds_cell(int rx, int ry)
-{
-    return ((rx & 1) + 2 * (ry & 1)) * kPS + (ry >> 1) * kPW + (rx >> 1);
-}
+// Tile geometry.  LDS layout: the region split into its four parity planes
+// (cell (rx, ry) in plane (rx & 1) + 2 (ry & 1) at (ry >> 1, rx >> 1)), one
+// array per slot.  The active cells of a set are then consecutive in one
+// plane, and so are each of their neighbours in the other planes: lanes
+// read consecutive words, free of bank conflicts.
+template <int TILE>
+struct FTile {
+    static constexpr int R = TILE + 2 * kFH;   // loaded region per side (even)
+    static constexpr int PW = R / 2;           // plane width
+    static constexpr int PS = PW * PW;         // plane size
+    static constexpr int RC = 4 * PS;          // region cells
+    __device__ static __forceinline__ int cell(int rx, int ry)
+    {
+        return ((rx & 1) + 2 * (ry & 1)) * PS + (ry >> 1) * PW + (rx >> 1);
+    }
+};
 
-template <int CAP>
+template <int CAP, int TILE, bool ACC, bool TAG>
 constexpr size_t fused_lds_bytes()
 {
-    return (size_t)kRC * CAP * sizeof(float2) + (size_t)kRC;
+    return (size_t)FTile<TILE>::RC *
+           (CAP * sizeof(float2) * (ACC ? 2 : 1) + (TAG ? CAP * sizeof(uint32_t) : 0) + 1);
 }
 
 struct FusedArgs {
     Tables t;
     const float2 *pos;
     const uint32_t *count;
+    const float2 *acc;
+    const uint32_t *tag;
     float2 *pos_out;
     uint32_t *count_out;
+    float2 *acc_out;
+    uint32_t *tag_out;
     uint32_t *alog;
     unsigned long long *cnt;
     int cnt_stride;
     int par;
-    int tiles_x, tiles_y;
     int per;
 };
 
+// The LDS copy of a region: positions, optional accumulators and tags, counts.
+template <int CAP, int TILE, bool ACC, bool TAG>
+struct FRegion {
+    float2 *sp;    // [CAP][RC]
+    float2 *sa;    // [CAP][RC] (ACC)
+    uint32_t *st;  // [CAP][RC] (TAG)
+    uint8_t *sn;   // [RC]
+    __device__ __forceinline__ FRegion(char *base)
+    {
+        constexpr int RC = FTile<TILE>::RC;
+        sp = (float2 *)base;
+        base += (size_t)RC * CAP * sizeof(float2);
+        sa = (float2 *)base;
+        if (ACC) base += (size_t)RC * CAP * sizeof(float2);
+        st = (uint32_t *)base;
+        if (TAG) base += (size_t)RC * CAP * sizeof(uint32_t);
+        sn = (uint8_t *)base;
+    }
+};
+
 // One cell update (Alg. 2) on the LDS copy of the region: cell (rx, ry) of
-// the region, global cell c of the replica.  The same decisions, in the same
-// FP32 operations, as k_subsweep.
-template <int CAP, int PROP>
-__device__ __forceinline__ void fused_cell_update(float2 *sp, uint8_t *sn, int rx, int ry,
-                                                  uint32_t c, float wx, float wy,
+// the region, cell c of the replica.  The same decisions, in the same FP32
+// operations, as k_subsweep.
+template <int CAP, int TILE, bool ACC, bool TAG>
+__device__ __forceinline__ void fused_cell_update(const FRegion<CAP, TILE, ACC, TAG> &L, int rx,
+                                                  int ry, uint32_t c, float wx, float wy,
                                                   uint32_t s_lo, uint32_t s_hi, uint32_t k0,
                                                   uint32_t k1, float delta, int n_moves,
                                                   bool disk, bool shuffle, unsigned &n_acc,
                                                   uint32_t &abits)
 {
-    const int r = lds_cell(rx, ry);
-    const int n = (int)sn[r];
+    using G = FTile<TILE>;
+    const int r = G::cell(rx, ry);
+    const int n = (int)L.sn[r];
     if (n == 0) return;
     uint4 Wsh = make_uint4(0, 0, 0, 0);
     if (shuffle && n > 1) Wsh = philox(c, s_lo, s_hi, kTagShuffle, k0, k1);
     uint4 W = make_uint4(0, 0, 0, 0);
     if (n_moves > 0) W = philox(c, s_lo, s_hi, 0u, k0, k1);
-    float px[CAP], py[CAP];
+    float px[CAP], py[CAP], ax[CAP], ay[CAP];
+    uint32_t tg[CAP];
 #pragma unroll
     for (int i = 0; i < CAP; ++i) {
-        const float2 v = sp[i * kRC + r];
+        const float2 v = L.sp[i * G::RC + r];
         px[i] = v.x;
         py[i] = v.y;
+        ax[i] = ay[i] = 0.0f;
+        tg[i] = 0u;
+        if (ACC) {
+            const float2 u = L.sa[i * G::RC + r];
+            ax[i] = u.x;
+            ay[i] = u.y;
+        }
+        if (TAG) tg[i] = L.st[i * G::RC + r];
     }
     // the eight neighbours' slots in this cell's frame (exactly -w, 0, +w)
     float nx[8 * CAP], ny[8 * CAP];
@@ -1004,10 +1042,10 @@ __device__ __forceinline__ void fused_cell_update(float2 *sp, uint8_t *sn, int r
     for (int q = 0, e = 0; q < 9; ++q) {
         if (q == 4) continue;
         const int ra = q / 3, cb = q % 3;
-        const int rq = lds_cell(rx + cb - 1, ry + ra - 1);
+        const int rq = G::cell(rx + cb - 1, ry + ra - 1);
 #pragma unroll
         for (int i = 0; i < CAP; ++i, ++e) {
-            const float2 v = sp[i * kRC + rq];
+            const float2 v = L.sp[i * G::RC + rq];
             float ox = v.x, oy = v.y;
             if (cb == 0) ox = ox - wx;
             if (cb == 2) ox = ox + wx;
@@ -1017,6 +1055,8 @@ __device__ __forceinline__ void fused_cell_update(float2 *sp, uint8_t *sn, int r
             ny[e] = oy;
         }
     }
+    // rng.shuffle(c.particles) as a packed permutation of the first n
+    // entries (entries >= n, far disks, stay in place)
     uint32_t P = 0x76543210u;
     const int nshuf = shuffle ? n - 1 : 0;
     for (int k = 0; k < nshuf; ++k) {
@@ -1029,9 +1069,12 @@ __device__ __forceinline__ void fused_cell_update(float2 *sp, uint8_t *sn, int r
     if (nshuf > 0) {
         rperm(px, P);
         rperm(py, P);
+        if (ACC) {
+            rperm(ax, P);
+            rperm(ay, P);
+        }
+        if (TAG) rperm(tg, P);
     }
-    // rperm moved far entries into the list only if n < CAP, and only from
-    // slots >= n: the permutation leaves positions >= n in place
     for (int tr = 0; tr < n_moves; ++tr) {
         if (tr > 0 && (tr & 3) == 0) W = philox(c, s_lo, s_hi, (uint32_t)(tr >> 2), k0, k1);
         float dx, dy;
@@ -1062,9 +1105,18 @@ __device__ __forceinline__ void fused_cell_update(float2 *sp, uint8_t *sn, int r
         if (tr < 32) abits |= (ok ? 1u : 0u) << tr;
         px[0] = ok ? xm : px[0];
         py[0] = ok ? ym : py[0];
+        if (ACC) {
+            ax[0] = ok ? ax[0] + dx : ax[0];
+            ay[0] = ok ? ay[0] + dy : ay[0];
+        }
         n_acc += ok ? 1u : 0u;
         rrot(px, n);
         rrot(py, n);
+        if (ACC) {
+            rrot(ax, n);
+            rrot(ay, n);
+        }
+        if (TAG) rrot(tg, n);
     }
     // register entry q holds list position (q + n_M) mod n: back to LDS in
     // list order (slots >= n keep their far entries)
@@ -1074,26 +1126,31 @@ __device__ __forceinline__ void fused_cell_update(float2 *sp, uint8_t *sn, int r
         if (o < n) {
             int q = o - r0;
             q = q < 0 ? q + n : q;
-            sp[o * kRC + r] = make_float2(rsel(px, q), rsel(py, q));
+            L.sp[o * G::RC + r] = make_float2(rsel(px, q), rsel(py, q));
+            if (ACC) L.sa[o * G::RC + r] = make_float2(rsel(ax, q), rsel(ay, q));
+            if (TAG) L.st[o * G::RC + r] = rsel(tg, q);
         }
     }
 }
 
-template <int CAP, int PROP>
+__device__ __forceinline__ int wrap_once(int v, int m) { return v < 0 ? v + m : (v >= m ? v - m : v); }
+
+template <int CAP, int PROP, bool ONE, int TILE, bool ACC, bool TAG>
 __global__ void __launch_bounds__(kFBlock, 2) k_sweep_fused(FusedArgs a)
 {
-    extern __shared__ float2 lds_f[];
-    float2 *sp = lds_f;                                         // [CAP][kRC]
-    uint8_t *sn = (uint8_t *)(lds_f + (size_t)kRC * CAP);       // [kRC]
+    using G = FTile<TILE>;
+    extern __shared__ char lds_fb[];
+    const FRegion<CAP, TILE, ACC, TAG> L(lds_fb);
     const int tile = xcd_tile(a.per);
-    const int ntile = a.tiles_x * a.tiles_y;
-    if (tile >= ntile) return;
-    const Rep R = a.t.rep0;
+    if (tile >= a.t.ftiles) return;
+    const int r = ONE ? 0 : (int)a.t.trep[tile];
+    const Rep R = ONE ? a.t.rep0 : a.t.reps[r];
     const Geom g = R.g;
-    Ctl *ctl = a.t.ctls;
-    const int tyi = tile / a.tiles_x, txi = tile - tyi * a.tiles_x;
-    const int x0 = txi * kFT, y0 = tyi * kFT;
-    const int wI = min(kFT, g.mx - x0), hI = min(kFT, g.my - y0);
+    Ctl *ctl = a.t.ctls + r;
+    const int lt = tile - (int)R.tb;            // tile within the replica
+    const int tyi = lt / R.tiles_x, txi = lt - tyi * R.tiles_x;
+    const int x0 = txi * TILE, y0 = tyi * TILE;
+    const int wI = min(TILE, g.mx - x0), hI = min(TILE, g.my - y0);
     const int RX = wI + 2 * kFH, RY = hI + 2 * kFH;
     const unsigned long long s = ctl->sweep_at[a.par];
     const uint32_t k0 = ctl->key0, k1 = ctl->key1;
@@ -1106,31 +1163,38 @@ __global__ void __launch_bounds__(kFBlock, 2) k_sweep_fused(FusedArgs a)
     const bool shuffle = PROP == 2 ? (R.ablate & kAblateParticleShuffle) == 0 : true;
     const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
     const uint32_t *cn = a.count + R.cb;
-    const float2 *pin = a.pos + (size_t)R.cb * CAP;
+    const size_t sb = (size_t)R.cb * CAP;   // the replica's first slot
 
-    // load the region: cell (rx, ry) is global cell ((x0 - kFH + rx) mod mx,
-    // (y0 - kFH + ry) mod my); slots past the count hold a far disk
+    // load the region: cell (rx, ry) is cell ((x0 - kFH + rx) mod mx,
+    // (y0 - kFH + ry) mod my) (grids narrower than the halo wrap twice);
+    // slots past the count hold a far disk
     bool bad = false;
     for (int i = threadIdx.x; i < RX * RY; i += kFBlock) {
         const int ry = i / RX, rx = i - ry * RX;
-        int gx = x0 - kFH + rx, gy = y0 - kFH + ry;
-        gx = gx < 0 ? gx + g.mx : (gx >= g.mx ? gx - g.mx : gx);
-        gy = gy < 0 ? gy + g.my : (gy >= g.my ? gy - g.my : gy);
-        gx = gx < 0 ? gx + g.mx : (gx >= g.mx ? gx - g.mx : gx);   // grids narrower than
-        gy = gy < 0 ? gy + g.my : (gy >= g.my ? gy - g.my : gy);   // the halo wrap twice
+        const int gx = wrap_once(wrap_once(x0 - kFH + rx, g.mx), g.mx);
+        const int gy = wrap_once(wrap_once(y0 - kFH + ry, g.my), g.my);
         const int c = gy * g.mx + gx;
         uint32_t n = cn[c];
-        float2 v[CAP];
+        float2 v[CAP], u[CAP];
+        uint32_t tv[CAP];
 #pragma unroll
-        for (int k = 0; k < CAP; ++k) v[k] = pin[(size_t)c * CAP + k];
+        for (int k = 0; k < CAP; ++k) {
+            v[k] = a.pos[sb + (size_t)c * CAP + k];
+            if (ACC) u[k] = a.acc[sb + (size_t)c * CAP + k];
+            if (TAG) tv[k] = a.tag[sb + (size_t)c * CAP + k];
+        }
         if (n > (uint32_t)g.cap) {
             bad = true;
             n = 0;
         }
-        const int r = lds_cell(rx, ry);
-        sn[r] = (uint8_t)n;
+        const int rr = G::cell(rx, ry);
+        L.sn[rr] = (uint8_t)n;
 #pragma unroll
-        for (int k = 0; k < CAP; ++k) sp[k * kRC + r] = k < (int)n ? v[k] : make_float2(kFar, kFar);
+        for (int k = 0; k < CAP; ++k) {
+            L.sp[k * G::RC + rr] = k < (int)n ? v[k] : make_float2(kFar, kFar);
+            if (ACC) L.sa[k * G::RC + rr] = u[k];
+            if (TAG) L.st[k * G::RC + rr] = tv[k];
+        }
     }
     if (bad) atomicOr((unsigned int *)&ctl->errword, kErrCapacity);
     __syncthreads();
@@ -1141,24 +1205,21 @@ __global__ void __launch_bounds__(kFBlock, 2) k_sweep_fused(FusedArgs a)
     for (int p = 1; p <= 4; ++p) {
         const int Q = (int)((order >> (8 * (p - 1))) & 0xFFu);
         const int qx = Q & 1, qy = Q >> 1;
-        // region column rx is global column x0 - kFH + rx: parity of rx + 1
+        // region column rx is column x0 - kFH + rx (x0 even): parity of rx + 1
         const int fx = p + (((p + 1) ^ qx) & 1), fy = p + (((p + 1) ^ qy) & 1);
         const int nxa = (RX - p - fx + 1) >> 1, nya = (RY - p - fy + 1) >> 1;
         for (int i = threadIdx.x; i < nxa * nya; i += kFBlock) {
             const int iy = i / nxa, ix = i - iy * nxa;
             const int rx = fx + 2 * ix, ry = fy + 2 * iy;
-            int gx = x0 - kFH + rx, gy = y0 - kFH + ry;
-            gx = gx < 0 ? gx + g.mx : (gx >= g.mx ? gx - g.mx : gx);
-            gy = gy < 0 ? gy + g.my : (gy >= g.my ? gy - g.my : gy);
-            gx = gx < 0 ? gx + g.mx : (gx >= g.mx ? gx - g.mx : gx);
-            gy = gy < 0 ? gy + g.my : (gy >= g.my ? gy - g.my : gy);
+            const int gx = wrap_once(wrap_once(x0 - kFH + rx, g.mx), g.mx);
+            const int gy = wrap_once(wrap_once(y0 - kFH + ry, g.my), g.my);
             const uint32_t c = (uint32_t)(gy * g.mx + gx);
             const bool inner = rx >= kFH && rx < kFH + wI && ry >= kFH && ry < kFH + hI;
             unsigned acc_here = 0;
             uint32_t bits = 0;
-            const int nbefore = (int)sn[lds_cell(rx, ry)];
-            fused_cell_update<CAP, PROP>(sp, sn, rx, ry, c, g.wx, g.wy, s_lo, s_hi, k0, k1,
-                                         delta, n_moves, disk, shuffle, acc_here, bits);
+            const int nbefore = (int)L.sn[G::cell(rx, ry)];
+            fused_cell_update<CAP, TILE, ACC, TAG>(L, rx, ry, c, g.wx, g.wy, s_lo, s_hi, k0, k1,
+                                                   delta, n_moves, disk, shuffle, acc_here, bits);
             if (inner) {
                 n_acc += acc_here;
                 n_trials += nbefore > 0 ? (unsigned)n_moves : 0u;
@@ -1180,37 +1241,52 @@ __global__ void __launch_bounds__(kFBlock, 2) k_sweep_fused(FusedArgs a)
     for (int i = threadIdx.x; i < wI * hI; i += kFBlock) {
         const int iy = i / wI, ix = i - iy * wI;
         const int rx = kFH + ix, ry = kFH + iy;
-        const int ro = lds_cell(rx, ry), rn = lds_cell(rx + ddx, ry + ddy);
-        const int no = (int)sn[ro], nn = (int)sn[rn];
+        const int ro = G::cell(rx, ry), rn = G::cell(rx + ddx, ry + ddy);
+        const int no = (int)L.sn[ro], nn = (int)L.sn[rn];
         // candidates in list order (own slots, then the neighbour's), each
         // kept by its one rounded shifted coordinate; kept candidate i goes
         // to output slot popcount(keep below i)
-        float2 cand[2 * CAP];
+        float2 cand[2 * CAP], cacc[2 * CAP];
+        uint32_t ctag[2 * CAP];
         uint32_t keep = 0u;
 #pragma unroll
         for (int k = 0; k < CAP; ++k) {
-            const float2 v = sp[k * kRC + ro];
+            const float2 v = L.sp[k * G::RC + ro];
             const float tt = shifted(along_x ? v.x : v.y, minus, d);
             cand[k] = along_x ? make_float2(tt, v.y) : make_float2(v.x, tt);
+            if (ACC) cacc[k] = L.sa[k * G::RC + ro];
+            if (TAG) ctag[k] = L.st[k * G::RC + ro];
             keep |= (k < no && tt > 0.0f && tt <= w) ? 1u << k : 0u;
         }
 #pragma unroll
         for (int k = 0; k < CAP; ++k) {
-            const float2 v = sp[k * kRC + rn];
+            const float2 v = L.sp[k * G::RC + rn];
             const float tt = shifted(along_x ? v.x : v.y, minus, d);
             const float t2 = tt + swd;
             cand[CAP + k] = along_x ? make_float2(t2, v.y) : make_float2(v.x, t2);
+            if (ACC) cacc[CAP + k] = L.sa[k * G::RC + rn];
+            if (TAG) ctag[CAP + k] = L.st[k * G::RC + rn];
             keep |= (k < nn && !(tt > 0.0f && tt <= w)) ? 1u << (CAP + k) : 0u;
         }
-        float2 out[CAP];
+        float2 out[CAP], oacc[CAP];
+        uint32_t otag[CAP];
 #pragma unroll
-        for (int k = 0; k < CAP; ++k) out[k] = make_float2(kFar, kFar);
+        for (int k = 0; k < CAP; ++k) {
+            out[k] = make_float2(kFar, kFar);
+            oacc[k] = make_float2(0.0f, 0.0f);
+            otag[k] = 0u;
+        }
 #pragma unroll
         for (int i = 0; i < 2 * CAP; ++i) {
             const bool kk = (keep >> i) & 1u;
             const int idx = __popc(keep & ((1u << i) - 1u));
 #pragma unroll
-            for (int j = 0; j < CAP; ++j) out[j] = (kk && idx == j) ? cand[i] : out[j];
+            for (int j = 0; j < CAP; ++j) {
+                const bool here = kk && idx == j;
+                out[j] = here ? cand[i] : out[j];
+                if (ACC) oacc[j] = here ? cacc[i] : oacc[j];
+                if (TAG) otag[j] = here ? ctag[i] : otag[j];
+            }
         }
         int o = __popc(keep);
         if (o > g.cap) {
@@ -1220,22 +1296,26 @@ __global__ void __launch_bounds__(kFBlock, 2) k_sweep_fused(FusedArgs a)
         const int c = (y0 + iy) * g.mx + (x0 + ix);
         a.count_out[R.cb + c] = (uint32_t)o;
 #pragma unroll
-        for (int k = 0; k < CAP; ++k) a.pos_out[(size_t)(R.cb + c) * CAP + k] = out[k];
+        for (int k = 0; k < CAP; ++k) {
+            a.pos_out[sb + (size_t)c * CAP + k] = out[k];
+            if (ACC) a.acc_out[sb + (size_t)c * CAP + k] = oacc[k];
+            if (TAG) a.tag_out[sb + (size_t)c * CAP + k] = otag[k];
+        }
     }
     if (over) atomicOr((unsigned int *)&ctl->errword, kErrCapacity);
     // padding cells of the replica (beyond C) keep count 0 in the half written
-    if (tile == 0)
+    if (lt == 0)
         for (long long i = g.C + threadIdx.x; i < R.cpad; i += kFBlock) a.count_out[R.cb + i] = 0u;
     // counts per wave into a granule of the replica (folded on demand)
     const unsigned bt = wave_sum_u32(n_trials);
     const unsigned ba = wave_sum_u32(n_acc);
     if ((threadIdx.x & 63u) == 0 && bt) {
         const long long ng = R.apad / kGranule;
-        const long long gr = R.ab / kGranule + ((long long)tile * (kFBlock / 64) + threadIdx.x / 64) % ng;
+        const long long gr = R.ab / kGranule + ((long long)lt * (kFBlock / 64) + threadIdx.x / 64) % ng;
         atomicAdd(&a.cnt[gr], (unsigned long long)bt);
         atomicAdd(&a.cnt[a.cnt_stride + gr], (unsigned long long)ba);
     }
-    if (tile == 0 && threadIdx.x == 0) store_draws(ctl, a.par ^ 1, s + 1ull, R);
+    if (lt == 0 && threadIdx.x == 0) store_draws(ctl, a.par ^ 1, s + 1ull, R);
 }
 
 // ------------------------------------------------------ pair histogram
@@ -1669,34 +1749,55 @@ hipError_t launch_fold_counters(const Tables &t, const Work &w, hipStream_t st)
     return hipGetLastError();
 }
 
-bool sweep_fused_supported(const Tables &t, bool acc, bool tag)
-{
-    return t.R == 1 && t.cap == 4 && !acc && !tag;
-}
+int fused_tile(bool acc, bool tag) { return tag ? 20 : (acc ? 24 : 36); }
+
+bool sweep_fused_supported(const Tables &t) { return t.cap == 4 && t.ftiles > 0; }
 
 hipError_t launch_sweep_fused(const Tables &t, int par, const float2 *pos, const uint32_t *count,
-                              float2 *pos_out, uint32_t *count_out, uint32_t *alog, const Work &w,
-                              hipStream_t st)
+                              const float2 *acc, const uint32_t *tag, float2 *pos_out,
+                              uint32_t *count_out, float2 *acc_out, uint32_t *tag_out,
+                              uint32_t *alog, const Work &w, hipStream_t st)
 {
-    if (t.R != 1 || t.cap != 4) return hipErrorInvalidValue;
+    if (!sweep_fused_supported(t)) return hipErrorInvalidValue;
+    const bool A = acc != nullptr, T = tag != nullptr;
+    if (t.ftile != fused_tile(A, T)) return hipErrorInvalidValue;
     FusedArgs a;
     a.t = t;
     a.pos = pos;
     a.count = count;
+    a.acc = acc;
+    a.tag = tag;
     a.pos_out = pos_out;
     a.count_out = count_out;
+    a.acc_out = acc_out;
+    a.tag_out = tag_out;
     a.alog = alog;
     a.cnt = w.cnt;
     a.cnt_stride = w.cnt_stride;
     a.par = par;
-    a.tiles_x = (t.rep0.g.mx + kFT - 1) / kFT;
-    a.tiles_y = (t.rep0.g.my + kFT - 1) / kFT;
-    a.per = per_xcd(a.tiles_x * a.tiles_y);
+    a.per = per_xcd((int)t.ftiles);
     const dim3 grid(8 * a.per), blk(kFBlock);
-    const size_t lds = fused_lds_bytes<4>();
-    if (t.prop == 0) hipLaunchKernelGGL((k_sweep_fused<4, 0>), grid, blk, lds, st, a);
-    else if (t.prop == 1) hipLaunchKernelGGL((k_sweep_fused<4, 1>), grid, blk, lds, st, a);
-    else hipLaunchKernelGGL((k_sweep_fused<4, 2>), grid, blk, lds, st, a);
+#define MPMC_FUSED(PROP, ONE, TL, AC, TG)                                                      \
+    hipLaunchKernelGGL((k_sweep_fused<4, PROP, ONE, TL, AC, TG>), grid, blk,                    \
+                       (fused_lds_bytes<4, TL, AC, TG>()), st, a)
+#define MPMC_FUSED_F(PROP, ONE)                                                                \
+    do {                                                                                       \
+        if (T && A) MPMC_FUSED(PROP, ONE, 20, true, true);                                     \
+        else if (T) MPMC_FUSED(PROP, ONE, 20, false, true);                                    \
+        else if (A) MPMC_FUSED(PROP, ONE, 24, true, false);                                    \
+        else MPMC_FUSED(PROP, ONE, 36, false, false);                                          \
+    } while (0)
+#define MPMC_FUSED_P(ONE)                                                                      \
+    do {                                                                                       \
+        if (t.prop == 0) MPMC_FUSED_F(0, ONE);                                                 \
+        else if (t.prop == 1) MPMC_FUSED_F(1, ONE);                                            \
+        else MPMC_FUSED_F(2, ONE);                                                             \
+    } while (0)
+    if (t.R == 1) MPMC_FUSED_P(true);
+    else MPMC_FUSED_P(false);
+#undef MPMC_FUSED_P
+#undef MPMC_FUSED_F
+#undef MPMC_FUSED
     return hipGetLastError();
 }
 

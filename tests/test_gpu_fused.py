@@ -120,14 +120,56 @@ def test_fused_equals_separate_launches(gpu):
 
 
 def test_fused_not_used_where_unsupported(gpu):
-    cfg = gpu.SystemConfig(lattice_nx=16, lattice_ny=16, phi=0.6, w_max=0.0, delta=0.1,
-                           n_moves=4, seed=1, flags=1)
-    S = gpu.HardDiskSystem(cfg)
-    assert not S.fused        # accumulators: separate launches
     cfg = gpu.SystemConfig(lattice_nx=16, lattice_ny=16, phi=0.7, w_max=1.932, delta=0.1,
                            n_moves=4, seed=1, flags=0)
     S = gpu.HardDiskSystem(cfg)
     assert S.geometry["capacity"] > 4 and not S.fused
+
+
+@pytest.mark.parametrize("flags", [1, 2, 3, 7])
+@pytest.mark.parametrize("nx,ny,phi", [(16, 16, 0.70), (72, 70, 0.70)])
+def test_fused_with_accumulators_and_tags(gpu, flags, nx, ny, phi):
+    """Accumulators (tile 24) and tags (tile 20) travel with their disks
+    through the fused sub-sweeps and the rebuild, bit for bit."""
+    G, O = pair(gpu, nx, ny, phi, flags=flags, seed=7)
+    assert G.fused
+    for k in range(3):
+        G.sweep(7)
+        O.sweep(7)
+        same(G, O, "flags %d block %d" % (flags, k))
+        ga, gt = G.aux()
+        oa, ot = O.aux()
+        if flags & 2:
+            assert np.array_equal(gt, ot), k
+        if flags & 1:
+            assert np.array_equal(ga.view(np.uint32), oa.view(np.uint32)), k
+            ref = float(np.mean((oa.astype(np.float64) ** 2).sum(axis=1)))
+            assert abs(G.msd() - ref) <= 1e-12 * max(ref, 1e-30), k
+
+
+def test_fused_batch_matches_single_runs(gpu):
+    """A batch of uneven replicas (capacity 4 each, one with in-circle moves,
+    one without the particle shuffle) in fused sweeps: each replica equals
+    its own oracle run, bit for bit, with accumulators and tags."""
+    specs = [(16, 16, 0.66, 0), (40, 36, 0.70, 8), (24, 26, 0.72, 16), (64, 60, 0.69, 0)]
+    cfgs = [gpu.SystemConfig(lattice_nx=a, lattice_ny=b, phi=ph, w_max=math.sqrt(2.0), delta=0.14,
+                             n_moves=4, seed=3, replica=r, flags=3 | fl)
+            for r, (a, b, ph, fl) in enumerate(specs)]
+    B = gpu.HardDiskBatch(cfgs)
+    assert B.fused
+    B.sweep(23)
+    for r, (a, b, ph, fl) in enumerate(specs):
+        O = OracleSystem.lattice(a, b, ph, w_max=math.sqrt(2.0), delta=0.14, n_moves=4, seed=3,
+                                 replica=r, flags=3 | fl)
+        O.sweep(23)
+        bx, bs, bsw = B.get_state(r)
+        ox, os_, osw = O.get_state()
+        assert bsw == osw == 23 and np.array_equal(bs, os_), r
+        assert np.array_equal(bx.view(np.uint32), ox.view(np.uint32)), r
+        ba, bt = B.aux(r)
+        oa, ot = O.aux()
+        assert np.array_equal(bt, ot) and np.array_equal(ba.view(np.uint32), oa.view(np.uint32)), r
+        assert B.replica_counters(r) == O.counters(), r
 
 
 @pytest.mark.timeout(900)
