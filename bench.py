@@ -687,7 +687,9 @@ def main():
         ks = args.steps
         k_avg_ms = gpu_ms / args.steps
         bytes_per_launch = 56.0 * N + 24.0 * C
-        kernel_name = "k_sweep_fused<%d, 0>" % cap
+        # template arguments: capacity, proposal (0 = square), one system, tile side,
+        # accumulators, tags
+        kernel_name = "k_sweep_fused<%d, 0, true, 36, false, false>" % cap
         timing = ("the timed region: %d sweeps, one launch each, HIP events on the system's "
                   "stream (graph gaps included)" % args.steps)
     else:
