@@ -178,6 +178,23 @@ def traffic_from_profile(kernel_src, kernel_name, key="hbm bytes per launch",
         return None
 
 
+VALU_PEAK_WAVE_INSTR = 256 * 4 * 2.4e9 / 4   # 1,024 SIMDs, one wave64 VALU instruction per 4 cycles
+
+
+def alu_roofline(src, kernel_name, profile, k_avg_ms):
+    """The same kernel against the VALU issue ceiling: wave64 VALU
+    instructions per launch (committed counter summary of the same kernel
+    source, else None) over this run's launch time, against 1,024 SIMDs
+    issuing one wave64 VALU instruction per 4 cycles at 2.4 GHz."""
+    n = traffic_from_profile(src, kernel_name, "valu wave instructions per launch", profile=profile)
+    if n is None:
+        return None
+    achieved = n / (k_avg_ms * 1e-3)
+    return {"unit": "wave64 VALU instructions/s", "achieved": achieved,
+            "peak": VALU_PEAK_WAVE_INSTR, "frac": achieved / VALU_PEAK_WAVE_INSTR,
+            "instructions_per_launch": n}
+
+
 def spheres_leg(args):
     """The 3D chain: 100^3 spheres at eta = 0.45 (see sphere_throughput.py)."""
     from paper_1211_1646_amd import sphere_throughput as ST
@@ -744,6 +761,7 @@ def main():
                      "traffic": traffic_from_profile(src, kernel_name, profile=prof),
                      "valu_busy": traffic_from_profile(src, kernel_name, "valu busy fraction",
                                                        profile=prof),
+                     "alu": alu_roofline(src, kernel_name, prof, k_avg_ms),
                      "kernel": kernel_name, "kernel_avg_us": k_avg_ms * 1e3,
                      "kernel_timing": timing,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
