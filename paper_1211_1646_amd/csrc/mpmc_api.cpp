@@ -162,10 +162,45 @@ struct Layout {
     std::vector<mpmc_geometry> geo;
     std::vector<Rep> reps;
     long long N = 0, cells = 0, active = 0;
-    long long ftiles = 0;   // fused-sweep tiles, all replicas
-    int ftile = 0;          // their side in cells
+    long long ftiles = 0;   // fused-sweep tiles, all replicas, at the chosen shape
+    long long ftiles_max = 0;   // ... at the smallest shape (sizes the tile table)
+    int ftile = 0;          // largest tile side the buffer flags allow
+    int ftx = 0, fty = 0;   // the chosen shape
     int cap = 0;
 };
+
+// The fused sweep's tile shape (tx, ty even, kFusedMinTile..ftile) for a
+// device of `cus` compute units, two workgroups resident per CU: the sweep
+// is VALU-bound, so its time is about the busiest CU's work, the tiles it
+// runs times the updates of one tile (the four sub-sweeps' boxes, the
+// interior grown by 3.5, 2.5, 1.5 and 0.5 cells on average per side).
+void choose_tiles(Layout *L, int cus)
+{
+    if (cus < 1) cus = 1;
+    double best = -1.0;
+    for (int tx = L->ftile; tx >= mpmc::kFusedMinTile; tx -= 2)
+        for (int ty = L->ftile; ty >= mpmc::kFusedMinTile; ty -= 2) {
+            long long tiles = 0;
+            for (const Rep &R : L->reps)
+                tiles += (long long)((R.g.mx + tx - 1) / tx) * ((R.g.my + ty - 1) / ty);
+            double work = 0.0;
+            for (int p = 1; p <= 4; ++p)
+                work += (tx + 2.0 * (4 - p) + 0.5) * (ty + 2.0 * (4 - p) + 0.5);
+            const double cost = (double)((tiles + cus - 1) / cus) * work + 1e-9 * (double)tiles * work;
+            if (best < 0.0 || cost < best) {
+                best = cost;
+                L->ftx = tx;
+                L->fty = ty;
+            }
+        }
+    L->ftiles = 0;
+    for (Rep &R : L->reps) {
+        R.tiles_x = (R.g.mx + L->ftx - 1) / L->ftx;
+        R.tiles_y = (R.g.my + L->fty - 1) / L->fty;
+        R.tb = L->ftiles;
+        L->ftiles += (long long)R.tiles_x * R.tiles_y;
+    }
+}
 
 mpmc_status plan(const mpmc_params *p, int n, Layout *L)
 {
@@ -206,18 +241,18 @@ mpmc_status plan(const mpmc_params *p, int n, Layout *L)
         R.disk = (p[r].flags & MPMC_FLAG_DISK) ? 1 : 0;
         R.ablate = ((p[r].flags & MPMC_FLAG_NO_PARTICLE_SHUFFLE) ? mpmc::kAblateParticleShuffle : 0) |
                    ((p[r].flags & MPMC_FLAG_NO_SET_SHUFFLE) ? mpmc::kAblateSetShuffle : 0);
-        // tiles of the fused sweep, at the side the shared buffer flags call for
+        // tiles of the fused sweep at the smallest shape (an upper bound for
+        // the tile table; the shape is chosen when the handle is built)
         L->ftile = mpmc::fused_tile((p[0].flags & MPMC_FLAG_ACC) != 0, (p[0].flags & MPMC_FLAG_TAG) != 0);
-        R.tiles_x = (g.cells_x + L->ftile - 1) / L->ftile;
-        R.tiles_y = (g.cells_y + L->ftile - 1) / L->ftile;
-        R.tb = L->ftiles;
-        L->ftiles += (long long)R.tiles_x * R.tiles_y;
+        const int mt = mpmc::kFusedMinTile;
+        L->ftiles_max += (long long)((g.cells_x + mt - 1) / mt) * ((g.cells_y + mt - 1) / mt);
         L->cells += R.cpad;
         L->N += R.g.N;
         L->active += R.apad;
         L->cap = std::max(L->cap, R.g.cap);
     }
-    if (L->ftiles > 0x7FFFFF00LL) return fail(MPMC_EGEOM, "too many cells");
+    if (L->ftiles_max > 0x7FFFFF00LL) return fail(MPMC_EGEOM, "too many cells");
+    choose_tiles(L, 256);   // a default shape; the handle re-chooses for its device
     if (L->N > 0xFFFFFF00LL) return fail(MPMC_EGEOM, "too many disks (32-bit offsets)");
     if (L->cells > 0x7FFFFF00LL) return fail(MPMC_EGEOM, "too many cells");
     return MPMC_OK;
@@ -244,7 +279,7 @@ CtlLayout ctl_layout(const Layout &L)
     c.arep = c.reps + align256(R * sizeof(Rep));
     c.crep = c.arep + align256((size_t)(L.active / mpmc::kActiveChunk) * 2);
     c.trep = c.crep + align256((size_t)(L.cells / mpmc::kRebinTile) * 2);
-    c.total = c.trep + align256((size_t)L.ftiles * 2);
+    c.total = c.trep + align256((size_t)L.ftiles_max * 2);
     return c;
 }
 
@@ -651,6 +686,13 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
         // (other replicas: every cell empty until set_state)
     }
 
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            cus > 0)
+            choose_tiles(&L, cus);
+    }
     mpmc_system *h = new mpmc_system();
     h->p.assign(p, p + n);
     h->L = L;
@@ -679,6 +721,8 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
     h->t.trep = (const uint16_t *)(cb + cl.trep);
     h->t.ftiles = L.ftiles;
     h->t.ftile = L.ftile;
+    h->t.ftx = L.ftx;
+    h->t.fty = L.fty;
     h->t.rep0 = L.reps[0];
     h->t.R = n;
     h->t.cap = L.cap;

@@ -90,7 +90,8 @@ struct Tables {
     const uint16_t *crep;   // replica of each rebin tile
     const uint16_t *trep;   // replica of each fused-sweep tile
     long long ftiles;       // fused-sweep tiles, all replicas
-    int ftile;              // fused-sweep tile side (cells), set by the buffer flags
+    int ftile;              // largest fused-sweep tile side (cells), set by the buffer flags
+    int ftx, fty;           // the tile shape in use (cells, even, at most ftile)
     int R;
     int cap;                // largest capacity
     int prop;               // sub-sweep variant: 0 all square, 1 all in-circle, 2 per replica
@@ -138,7 +139,9 @@ hipError_t launch_rebin(const Tables &t, int par, const float2 *pos, const uint3
 // launch: reads half par, writes half par ^ 1 and advances every replica's
 // sweep.  The same chain as launch_subsweep x 4 + launch_rebin, bit for bit.
 // Supported when every replica has capacity 4 (slot layout of 4).
-// fused_tile: the tile side the handle's buffer flags call for.
+// fused_tile: the largest tile side the handle's buffer flags allow (LDS
+// for two workgroups per CU); the shape in use is chosen per handle.
+constexpr int kFusedMinTile = 16;
 int fused_tile(bool acc, bool tag);
 bool sweep_fused_supported(const Tables &t);
 hipError_t launch_sweep_fused(const Tables &t, int par, const float2 *pos, const uint32_t *count,

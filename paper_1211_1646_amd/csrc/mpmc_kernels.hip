@@ -920,12 +920,14 @@ __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
 // ------------------------------------------------------- fused sweep
 // A whole sweep (Alg. 1: the four sub-sweeps in the sweep's set order, then
 // Alg. 4's shift and rebuild) in one launch, tile by tile.  A workgroup owns
-// an interior of at most TILE x TILE cells of one replica and loads it with
-// a halo of kFH = 5 cells into LDS; sub-sweep p (1..4) then updates the
-// cells of its set in the box [p, R - p) of the loaded region, so that after
-// the fourth the box [4, R - 4) holds the sweep's final state, and the
-// rebuild of an interior cell c needs only c and its neighbour in direction
-// f, both inside it.  A cell of the halo is updated by every tile that loads
+// an interior of tx x ty cells of one replica (at most TILE x TILE) and
+// loads it with a halo into LDS.  The rebuild of an interior cell c needs c
+// and its neighbour in direction f after the four sub-sweeps: box B4, the
+// interior extended by one cell towards f.  Sub-sweep p updates the cells
+// of its set in B_p, B4 grown by 4 - p cells on every side, so that every
+// update reads cells that already hold the state after sub-sweep p - 1; the
+// region loaded is B1 grown by one cell (at most kFH = 5 around the
+// interior).  A cell of the halo is updated by every tile that loads
 // it, each time with the same neighbourhood and the same Philox stream
 // (keyed by the cell and the sweep), so every copy ends identical to the one
 // its owner computes: the result is the chain of the four separate launches,
@@ -947,7 +949,7 @@ constexpr float kFar = 1.0e6f;
 // read consecutive words, free of bank conflicts.
 template <int TILE>
 struct FTile {
-    static constexpr int R = TILE + 2 * kFH;   // loaded region per side (even)
+    static constexpr int R = TILE + 2 * kFH;   // largest loaded region per side (even)
     static constexpr int PW = R / 2;           // plane width
     static constexpr int PS = PW * PW;         // plane size
     static constexpr int RC = 4 * PS;          // region cells
@@ -1149,9 +1151,8 @@ __global__ void __launch_bounds__(kFBlock, 2) k_sweep_fused(FusedArgs a)
     Ctl *ctl = a.t.ctls + r;
     const int lt = tile - (int)R.tb;            // tile within the replica
     const int tyi = lt / R.tiles_x, txi = lt - tyi * R.tiles_x;
-    const int x0 = txi * TILE, y0 = tyi * TILE;
-    const int wI = min(TILE, g.mx - x0), hI = min(TILE, g.my - y0);
-    const int RX = wI + 2 * kFH, RY = hI + 2 * kFH;
+    const int x0 = txi * a.t.ftx, y0 = tyi * a.t.fty;
+    const int wI = min(a.t.ftx, g.mx - x0), hI = min(a.t.fty, g.my - y0);
     const unsigned long long s = ctl->sweep_at[a.par];
     const uint32_t k0 = ctl->key0, k1 = ctl->key1;
     const float delta = ctl->delta;
@@ -1164,13 +1165,24 @@ __global__ void __launch_bounds__(kFBlock, 2) k_sweep_fused(FusedArgs a)
     const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
     const uint32_t *cn = a.count + R.cb;
     const size_t sb = (size_t)R.cb * CAP;   // the replica's first slot
+    // direction of the rebuild's neighbour and the box B4 it needs (region
+    // column rx is column x0 - kFH + rx)
+    const bool along_x = f < 2;
+    const bool minus = (f == 0 || f == 2);   // +x / +y: t = v - d
+    const int ddx = along_x ? (minus ? 1 : -1) : 0;
+    const int ddy = along_x ? 0 : (minus ? 1 : -1);
+    const int b4x0 = kFH + min(ddx, 0), b4x1 = kFH + wI + max(ddx, 0);
+    const int b4y0 = kFH + min(ddy, 0), b4y1 = kFH + hI + max(ddy, 0);
 
     // load the region: cell (rx, ry) is cell ((x0 - kFH + rx) mod mx,
     // (y0 - kFH + ry) mod my) (grids narrower than the halo wrap twice);
     // slots past the count hold a far disk
     bool bad = false;
-    for (int i = threadIdx.x; i < RX * RY; i += kFBlock) {
-        const int ry = i / RX, rx = i - ry * RX;
+    const int lx0 = b4x0 - 4, ly0 = b4y0 - 4;
+    const int LX = b4x1 + 4 - lx0, LY = b4y1 + 4 - ly0;
+    for (int i = threadIdx.x; i < LX * LY; i += kFBlock) {
+        const int iy = i / LX;
+        const int rx = lx0 + (i - iy * LX), ry = ly0 + iy;
         const int gx = wrap_once(wrap_once(x0 - kFH + rx, g.mx), g.mx);
         const int gy = wrap_once(wrap_once(y0 - kFH + ry, g.my), g.my);
         const int c = gy * g.mx + gx;
@@ -1205,9 +1217,11 @@ __global__ void __launch_bounds__(kFBlock, 2) k_sweep_fused(FusedArgs a)
     for (int p = 1; p <= 4; ++p) {
         const int Q = (int)((order >> (8 * (p - 1))) & 0xFFu);
         const int qx = Q & 1, qy = Q >> 1;
+        const int bx0 = b4x0 - (4 - p), bx1 = b4x1 + (4 - p);
+        const int by0 = b4y0 - (4 - p), by1 = b4y1 + (4 - p);
         // region column rx is column x0 - kFH + rx (x0 even): parity of rx + 1
-        const int fx = p + (((p + 1) ^ qx) & 1), fy = p + (((p + 1) ^ qy) & 1);
-        const int nxa = (RX - p - fx + 1) >> 1, nya = (RY - p - fy + 1) >> 1;
+        const int fx = bx0 + (((bx0 + 1) ^ qx) & 1), fy = by0 + (((by0 + 1) ^ qy) & 1);
+        const int nxa = (bx1 - fx + 1) >> 1, nya = (by1 - fy + 1) >> 1;
         for (int i = threadIdx.x; i < nxa * nya; i += kFBlock) {
             const int iy = i / nxa, ix = i - iy * nxa;
             const int rx = fx + 2 * ix, ry = fy + 2 * iy;
@@ -1231,12 +1245,8 @@ __global__ void __launch_bounds__(kFBlock, 2) k_sweep_fused(FusedArgs a)
 
     // the shift and rebuild (Alg. 4) of the interior: new cell c holds the
     // stayers of c, then the leavers of its neighbour in direction f
-    const bool along_x = f < 2;
-    const bool minus = (f == 0 || f == 2);   // +x / +y: t = v - d
     const float w = along_x ? g.wx : g.wy;
     const float swd = minus ? w : -w;
-    const int ddx = along_x ? (minus ? 1 : -1) : 0;
-    const int ddy = along_x ? 0 : (minus ? 1 : -1);
     bool over = false;
     for (int i = threadIdx.x; i < wI * hI; i += kFBlock) {
         const int iy = i / wI, ix = i - iy * wI;
@@ -1749,7 +1759,7 @@ hipError_t launch_fold_counters(const Tables &t, const Work &w, hipStream_t st)
     return hipGetLastError();
 }
 
-int fused_tile(bool acc, bool tag) { return tag ? 20 : (acc ? 24 : 36); }
+int fused_tile(bool acc, bool tag) { return tag ? 20 : (acc ? 24 : 38); }
 
 bool sweep_fused_supported(const Tables &t) { return t.cap == 4 && t.ftiles > 0; }
 
@@ -1785,7 +1795,7 @@ hipError_t launch_sweep_fused(const Tables &t, int par, const float2 *pos, const
         if (T && A) MPMC_FUSED(PROP, ONE, 20, true, true);                                     \
         else if (T) MPMC_FUSED(PROP, ONE, 20, false, true);                                    \
         else if (A) MPMC_FUSED(PROP, ONE, 24, true, false);                                    \
-        else MPMC_FUSED(PROP, ONE, 36, false, false);                                          \
+        else MPMC_FUSED(PROP, ONE, 38, false, false);                                          \
     } while (0)
 #define MPMC_FUSED_P(ONE)                                                                      \
     do {                                                                                       \
