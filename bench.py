@@ -704,9 +704,10 @@ def main():
         ks = args.steps
         k_avg_ms = gpu_ms / args.steps
         bytes_per_launch = 56.0 * N + 24.0 * C
-        # template arguments: capacity, proposal (0 = square), one system, tile side,
-        # accumulators, tags
-        kernel_name = "k_sweep_fused<%d, 0, true, 36, false, false>" % cap
+        # template arguments: capacity, proposal (0 = square), one system, largest
+        # tile side, accumulators, tags
+        tile, ftx, fty = S.fused_tile
+        kernel_name = "k_sweep_fused<%d, 0, true, %d, false, false>" % (cap, tile)
         timing = ("the timed region: %d sweeps, one launch each, HIP events on the system's "
                   "stream (graph gaps included)" % args.steps)
     else:
@@ -746,7 +747,8 @@ def main():
                    "sweeps_per_s": args.steps / secs,
                    "acceptance": (t1_acc - t0_acc) / max(trials, 1),
                    "trial_moves_per_sweep": trials / args.steps,
-                   "sweep_kernel": "fused (one tiled launch per sweep)" if fused
+                   "sweep_kernel": ("fused (one tiled launch per sweep, tiles of %dx%d cells)"
+                                    % S.fused_tile[1:]) if fused
                                    else "four sub-sweep launches and a rebuild",
                    "subsweep_lanes_per_cell": S.lanes,
                    "subsweep_block": S.block,

@@ -82,6 +82,18 @@ typedef int32_t mpmc_status;
  * All other random draws are unchanged.  Replicas may differ in them. */
 #define MPMC_FLAG_NO_PARTICLE_SHUFFLE 16u
 #define MPMC_FLAG_NO_SET_SHUFFLE 32u
+/* Diagnostics, the two cell-leaving pitfalls of Sec. 2.4 (they break
+ * detailed balance): LEAVE lets a move take its disk out of the cell, by
+ * at most e = (w - 1)/2 per axis (so that the 3x3 overlap test stays
+ * complete and the cells of one set independent); the disk stays in its
+ * cell's list until the sweep's shift re-homes it on both axes.
+ * LEAVE_ONCE is LEAVE with n_M = n for every cell update, each disk moved
+ * exactly once per sweep.  The shift then lists, in new cell c, its own
+ * stayers and then the arrivals from the eight neighbours in row-major
+ * order of the offset.  Replicas may differ in them.  Sweeps of a handle
+ * with either flag use the separate launches, one lane per cell. */
+#define MPMC_FLAG_LEAVE 64u
+#define MPMC_FLAG_LEAVE_ONCE 128u
 
 #define MPMC_HIST_BINS 200 /* contact histogram: 200 bins of 1e-4 sigma */
 
@@ -348,6 +360,13 @@ mpmc_status mpmc_set_launch(mpmc_handle h, int32_t lanes_per_cell, int32_t block
  * only. */
 mpmc_status mpmc_set_sweep_kernel(mpmc_handle h, int32_t fused);
 mpmc_status mpmc_get_sweep_kernel(mpmc_handle h, int32_t *fused);
+
+/* Utility (performance only): the fused sweep's tiling.  *tile is the
+ * largest tile interior side (in cells) the kernel is compiled for, which
+ * depends on the buffer flags; *tx x *ty is the interior of the tile shape
+ * chosen for this handle's grids and the device's compute-unit count.  All
+ * three are 0 when sweeps of this handle do not run fused.  Host only. */
+mpmc_status mpmc_get_fused_tile(mpmc_handle h, int32_t *tile, int32_t *tx, int32_t *ty);
 
 /* Utility (performance only): autotuner for the launch shape.  Only shape
  * knobs that leave results bit

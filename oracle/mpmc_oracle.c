@@ -284,6 +284,18 @@ typedef struct oracle_sys {
  * set shuffle is not needed for correct sampling.  Diagnostic only. */
 #define FLAG_NO_PARTICLE_SHUFFLE 16
 #define FLAG_NO_SET_SHUFFLE 32
+/* The two cell-leaving pitfalls of Sec. 2.4, diagnostic only.  LEAVE: a
+ * move may take the disk out of its cell; it stays in the cell's list with
+ * a local coordinate outside (0, w] until the sweep's shift re-homes it.
+ * LEAVE_ONCE: the same, with n_M = n for every cell update, so each disk
+ * is moved exactly once per sweep.  To keep the 3x3 overlap test complete
+ * and the cells of one set independent, a move is rejected if it takes
+ * the disk more than e = (w - 1)/2 outside its cell (per axis): two disks
+ * displaced towards each other are then still a full cell width apart
+ * minus 2e >= 1.  With w = 1 the bound is 0 and LEAVE is the plain chain. */
+#define FLAG_LEAVE 64
+#define FLAG_LEAVE_ONCE 128
+#define FLAG_LEAVE_ANY (FLAG_LEAVE | FLAG_LEAVE_ONCE)
 
 static void *xcalloc(size_t n, size_t sz)
 {
@@ -492,8 +504,16 @@ static void cell_update(oracle_sys *S, int cx, int cy, uint64_t *trials, uint64_
         swap_slots(S, base + i, base + j);
     }
 
-    /* n_M trial moves, particle list[s mod n] (Alg. 1). */
-    for (int s = 0; s < S->n_moves; ++s) {
+    /* n_M trial moves, particle list[s mod n] (Alg. 1); under the
+     * leave-once pitfall n of them, one per disk.  The window a trial
+     * position must stay in: the cell, or under the leaving pitfalls the
+     * cell grown by e = (w - 1)/2 per axis. */
+    int leave = (S->flags & FLAG_LEAVE_ANY) != 0;
+    int trials_here = (S->flags & FLAG_LEAVE_ONCE) ? n : S->n_moves;
+    float ex = leave ? (S->wx - 1.0f) * 0.5f : 0.0f;
+    float ey = leave ? (S->wy - 1.0f) * 0.5f : 0.0f;
+    float lox = -ex, hix = S->wx + ex, loy = -ey, hiy = S->wy + ey;
+    for (int s = 0; s < trials_here; ++s) {
         if ((s & 3) == 0) stream_block((uint32_t)c, S->sweep, TAG_TRIAL + (uint32_t)(s >> 2), S->key, words);
         int slot = base + visit_slot(s, n);
         float dx, dy;
@@ -503,7 +523,7 @@ static void cell_update(oracle_sys *S, int cx, int cy, uint64_t *trials, uint64_
             oracle_trial_displacement(words[s & 3], S->delta, &dx, &dy);
         float xm = S->disk_x[slot] + dx;
         float ym = S->disk_y[slot] + dy;
-        int in_cell = xm > 0.0f && xm <= S->wx && ym > 0.0f && ym <= S->wy;
+        int in_cell = xm > lox && xm <= hix && ym > loy && ym <= hiy;
         *trials += 1;
         if (in_cell && !overlaps(S, cx, cy, slot, xm, ym)) {
             S->disk_x[slot] = xm;
@@ -577,8 +597,66 @@ static float shifted(float v, int f, float d)
     return (f == 0 || f == 2) ? v - d : v + d;
 }
 
+/* The shift under the leaving pitfalls: disks may sit up to (w - 1)/2
+ * outside their cell on either axis.  Each disk's coordinates are the
+ * shifted one (one FP32 operation, as above) and the other one; per axis a
+ * value <= 0 sends the disk one cell down (coordinate + w), a value > w one
+ * cell up (coordinate - w), one rounding each.  New cell c lists the disks
+ * that land in it: first its own stayers, then the arrivals from the eight
+ * neighbours in row-major order of the offset (dy, then dx), each source in
+ * list order.  Without excursions only the neighbour in direction f has
+ * arrivals, and this is the order above. */
+static void land(float t, float w, int *off, float *u)
+{
+    if (t <= 0.0f) { *off = -1; *u = t + w; }
+    else if (t > w) { *off = 1; *u = t - w; }
+    else { *off = 0; *u = t; }
+}
+
+static void shift_cells_general(oracle_sys *S, int f, float d)
+{
+    int along_x = (f < 2);
+    for (int cy = 0; cy < S->my; ++cy) {
+        for (int cx = 0; cx < S->mx; ++cx) {
+            int c = cy * S->mx + cx;
+            int out = c * S->cap;
+            int n_new = 0;
+            for (int k = 0; k < 9; ++k) {
+                /* k = 0: the cell itself; then (dy, dx) row-major without (0, 0) */
+                int q = k == 0 ? 4 : (k <= 4 ? k - 1 : k);
+                int ox = q % 3 - 1, oy = q / 3 - 1;
+                int sx = wrap(cx + ox, S->mx), sy = wrap(cy + oy, S->my);
+                int sc = sy * S->mx + sx;
+                for (int i = 0; i < S->n[sc]; ++i) {
+                    int slot = sc * S->cap + i;
+                    float vx = S->disk_x[slot], vy = S->disk_y[slot];
+                    float tx = along_x ? shifted(vx, f, d) : vx;
+                    float ty = along_x ? vy : shifted(vy, f, d);
+                    int mxo, myo;
+                    float ux, uy;
+                    land(tx, S->wx, &mxo, &ux);
+                    land(ty, S->wy, &myo, &uy);
+                    if (mxo != -ox || myo != -oy) continue; /* lands elsewhere */
+                    if (n_new >= S->cap) { S->n_dbl[c] = -1; goto next_cell; }
+                    int o = out + n_new++;
+                    S->dbl_x[o] = ux;
+                    S->dbl_y[o] = uy;
+                    S->dacc_x[o] = S->acc_x[slot]; S->dacc_y[o] = S->acc_y[slot];
+                    S->dtag[o] = S->tag[slot];
+                }
+            }
+            S->n_dbl[c] = n_new;
+        next_cell:;
+        }
+    }
+}
+
 void oracle_shift_cells(oracle_sys *S, int f, float d)
 {
+    if (S->flags & FLAG_LEAVE_ANY) {
+        shift_cells_general(S, f, d);
+        goto swap;
+    }
     int along_x = (f < 2);
     int sgn = (f == 0 || f == 2) ? +1 : -1; /* direction of f along its axis */
     float w = along_x ? S->wx : S->wy;
@@ -625,6 +703,7 @@ void oracle_shift_cells(oracle_sys *S, int f, float d)
         next_cell:;
         }
     }
+swap:;
     /* swap the double buffers */
     float *tp;
     uint32_t *tu;

@@ -25,6 +25,8 @@ FLAG_ACCEPT_LOG = 4
 FLAG_DISK = 8        # in-circle trial moves (the paper's proposal)
 FLAG_NO_PARTICLE_SHUFFLE = 16  # diagnostic: breaks detailed balance (Table 1)
 FLAG_NO_SET_SHUFFLE = 32       # diagnostic: sets always a, b, c, d (Table 1)
+FLAG_LEAVE = 64                # diagnostic: moves may leave the cell (Sec. 2.4)
+FLAG_LEAVE_ONCE = 128          # diagnostic: leaving allowed, each disk moved once per sweep
 HIST_BINS = 200
 MLP_PARAMS = 1217
 
@@ -102,6 +104,8 @@ _SIGNATURES = {
     "mpmc_prepare_sweeps": (C.c_int32, [_H, C.c_int64]),
     "mpmc_set_sweep_kernel": (C.c_int32, [_H, C.c_int32]),
     "mpmc_get_sweep_kernel": (C.c_int32, [_H, C.POINTER(C.c_int32)]),
+    "mpmc_get_fused_tile": (C.c_int32, [_H, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_int32)]),
     "mpmc_set_acc": (C.c_int32, [_H, C.c_void_p]),
     "mpmc_replica_set_acc": (C.c_int32, [_H, C.c_int32, C.c_void_p]),
     "mpmc_subsweep": (C.c_int32, [_H, C.c_int32]),

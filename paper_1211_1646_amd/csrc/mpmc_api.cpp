@@ -141,8 +141,8 @@ mpmc_status derive_geometry(const mpmc_params *p, mpmc_geometry *g)
 }
 
 // Flags that change only the chain, not the buffers: may differ between replicas.
-constexpr uint32_t kChainFlags =
-    MPMC_FLAG_DISK | MPMC_FLAG_NO_PARTICLE_SHUFFLE | MPMC_FLAG_NO_SET_SHUFFLE;
+constexpr uint32_t kChainFlags = MPMC_FLAG_DISK | MPMC_FLAG_NO_PARTICLE_SHUFFLE |
+                                 MPMC_FLAG_NO_SET_SHUFFLE | MPMC_FLAG_LEAVE | MPMC_FLAG_LEAVE_ONCE;
 
 mpmc_status check_params(const mpmc_params *p, const mpmc_geometry &g)
 {
@@ -240,7 +240,9 @@ mpmc_status plan(const mpmc_params *p, int n, Layout *L)
         R.delta0 = p[r].delta;
         R.disk = (p[r].flags & MPMC_FLAG_DISK) ? 1 : 0;
         R.ablate = ((p[r].flags & MPMC_FLAG_NO_PARTICLE_SHUFFLE) ? mpmc::kAblateParticleShuffle : 0) |
-                   ((p[r].flags & MPMC_FLAG_NO_SET_SHUFFLE) ? mpmc::kAblateSetShuffle : 0);
+                   ((p[r].flags & MPMC_FLAG_NO_SET_SHUFFLE) ? mpmc::kAblateSetShuffle : 0) |
+                   ((p[r].flags & MPMC_FLAG_LEAVE) ? mpmc::kAblateLeave : 0) |
+                   ((p[r].flags & MPMC_FLAG_LEAVE_ONCE) ? mpmc::kAblateLeaveOnce : 0);
         // tiles of the fused sweep at the smallest shape (an upper bound for
         // the tile table; the shape is chosen when the handle is built)
         L->ftile = mpmc::fused_tile((p[0].flags & MPMC_FLAG_ACC) != 0, (p[0].flags & MPMC_FLAG_TAG) != 0);
@@ -727,12 +729,14 @@ mpmc_status create(const mpmc_params *p, int n, const mpmc_buffers *b, void *str
     h->t.R = n;
     h->t.cap = L.cap;
     {
-        int ndisk = 0, noshuf = 0;
+        int ndisk = 0, noshuf = 0, nleave = 0;
         for (const Rep &R : L.reps) {
             ndisk += R.disk;
             noshuf += (R.ablate & mpmc::kAblateParticleShuffle) ? 1 : 0;
+            nleave += (R.ablate & (mpmc::kAblateLeave | mpmc::kAblateLeaveOnce)) ? 1 : 0;
         }
-        h->t.prop = noshuf > 0 ? 2 : (ndisk == 0 ? 0 : (ndisk == n ? 1 : 2));
+        h->t.prop = (noshuf > 0 || nleave > 0) ? 2 : (ndisk == 0 ? 0 : (ndisk == n ? 1 : 2));
+        h->t.leave = nleave > 0 ? 1 : 0;
     }
     h->t.cells = L.cells;
     h->t.active = L.active;
@@ -1265,6 +1269,16 @@ mpmc_status mpmc_get_sweep_kernel(mpmc_handle h, int32_t *fused)
 {
     if (!h || !fused) return fail(MPMC_EINVAL, "null argument");
     *fused = use_fused(h) ? 1 : 0;
+    return MPMC_OK;
+}
+
+mpmc_status mpmc_get_fused_tile(mpmc_handle h, int32_t *tile, int32_t *tx, int32_t *ty)
+{
+    if (!h || !tile || !tx || !ty) return fail(MPMC_EINVAL, "null argument");
+    const bool f = use_fused(h);
+    *tile = f ? h->t.ftile : 0;
+    *tx = f ? h->t.ftx : 0;
+    *ty = f ? h->t.fty : 0;
     return MPMC_OK;
 }
 

@@ -26,6 +26,8 @@ constexpr int kMlpParams = 1217;          // 3 -> 32 -> 32 -> 1 network
 constexpr int kNbrLds = 16;               // reachable neighbours a lane keeps in LDS
 constexpr int kAblateParticleShuffle = 1; // Rep::ablate: visit cells in stored order
 constexpr int kAblateSetShuffle = 2;      // Rep::ablate: sets always a, b, c, d
+constexpr int kAblateLeave = 4;           // Rep::ablate: moves may leave the cell by (w - 1)/2
+constexpr int kAblateLeaveOnce = 8;       // Rep::ablate: as kAblateLeave, n_M = n
 
 // Per-replica control block: everything a captured sweep graph reads or
 // writes that changes between launches lives here, not in kernel arguments.
@@ -95,7 +97,8 @@ struct Tables {
     int R;
     int cap;                // largest capacity
     int prop;               // sub-sweep variant: 0 all square, 1 all in-circle, 2 per replica
-                            // (mixed proposals or the particle-shuffle ablation)
+                            // (mixed proposals, the particle-shuffle or leaving pitfalls)
+    int leave;              // some replica lets disks leave their cells (general rebuild)
     long long cells;        // padded cells, all replicas
     long long active;       // padded active slots, all replicas
     long long N;            // disks, all replicas

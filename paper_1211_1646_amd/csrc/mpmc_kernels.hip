@@ -254,6 +254,14 @@ k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restri
     // replica (PROP 2, which also carries the particle-shuffle ablation)
     const bool disk = PROP == 2 ? R.disk != 0 : PROP == 1;
     const bool shuffle = PROP == 2 ? (R.ablate & kAblateParticleShuffle) == 0 : true;
+    // the cell-leaving pitfalls (Sec. 2.4, diagnostic): the trial window is
+    // the cell grown by (w - 1)/2 per axis, no reach filter (neighbours may
+    // sit outside their cells), and under leave-once n_M = n
+    const bool leave = PROP == 2 && (R.ablate & (kAblateLeave | kAblateLeaveOnce)) != 0;
+    const bool leave_once = PROP == 2 && (R.ablate & kAblateLeaveOnce) != 0;
+    const float ex = leave ? (g.wx - 1.0f) * 0.5f : 0.0f;
+    const float ey = leave ? (g.wy - 1.0f) * 0.5f : 0.0f;
+    const float lox = -ex, hix = g.wx + ex, loy = -ey, hiy = g.wy + ey;
     const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
 
     int Q = set;
@@ -296,7 +304,7 @@ k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restri
         uint4 Wsh = make_uint4(0, 0, 0, 0);
         if (shuffle) Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle, k0, k1);
         uint4 W = make_uint4(0, 0, 0, 0);
-        if (n_moves > 0) W = philox((uint32_t)c, s_lo, s_hi, 0u, k0, k1);
+        if (n_moves > 0 || leave_once) W = philox((uint32_t)c, s_lo, s_hi, 0u, k0, k1);
         bool bad = false;
 #pragma unroll
         for (int q = 0; q < 9; ++q) bad |= rn[q] > (uint32_t)g.cap;
@@ -344,7 +352,7 @@ k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restri
                     bool reach;
                     const float2 v = frame_of(nv[q][i], q / 3, q % 3, g.wx, g.wy, reach);
                     nbr[K < kL ? K : kL] = v;
-                    K += (i < (int)rn[q] && reach) ? 1 : 0;
+                    K += (i < (int)rn[q] && (reach || leave)) ? 1 : 0;
                 }
             }
             // pad to a multiple of four with a disk that overlaps nothing
@@ -363,7 +371,7 @@ k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restri
                     for (int i = 0; i < CAP; ++i) {
                         bool reach;
                         const float2 v = frame_of(nv[q][i], q / 3, q % 3, g.wx, g.wy, reach);
-                        const bool take = i < (int)rn[q] && reach;
+                        const bool take = i < (int)rn[q] && (reach || leave);
                         if (take && k2 >= kL) ovf[k2 - kL] = v;
                         k2 += take ? 1 : 0;
                     }
@@ -419,7 +427,8 @@ k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restri
             float2 nr[kL];
 #pragma unroll
             for (int k = 0; k < kL; ++k) nr[k] = k < KLw ? nbr[k] : far;
-            for (int tr = 0; tr < n_moves; ++tr) {
+            const int nm = leave_once ? n : n_moves;   // trial moves of this cell update
+            for (int tr = 0; tr < nm; ++tr) {
                 if (tr > 0 && (tr & 3) == 0) W = philox((uint32_t)c, s_lo, s_hi, (uint32_t)(tr >> 2), k0, k1);
                 float dx, dy;
                 if (disk)
@@ -428,7 +437,7 @@ k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restri
                     displacement(word_of(W, tr & 3), delta, dx, dy);
                 const float xm = px[0] + dx;
                 const float ym = py[0] + dy;
-                bool ok = (xm > 0.0f) & (xm <= g.wx) & (ym > 0.0f) & (ym <= g.wy);
+                bool ok = (xm > lox) & (xm <= hix) & (ym > loy) & (ym <= hiy);
 #pragma unroll
                 for (int q = 1; q < CAP; ++q) {
                     const float ddx = xm - px[q];
@@ -463,9 +472,9 @@ k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restri
                 }
                 if (has_tag) rrot(tg, n);
             }
-            n_trials = (unsigned)n_moves;
+            n_trials = (unsigned)nm;
             // register entry q now holds list position (q + n_M) mod n
-            const int r0 = n_moves % n;
+            const int r0 = nm % n;
 #pragma unroll
             for (int q = 0; q < CAP; ++q) {
                 if (q < n) {
@@ -905,6 +914,99 @@ __global__ void __launch_bounds__(kRebinTile) k_rebin(RebinArgs a)
         }
     } else if (cl < R.cpad) {
         a.count_out[cell0 + threadIdx.x] = 0u;   // padding cells stay empty
+    }
+    if (cell0 == R.cb && threadIdx.x == 0) {
+        const unsigned long long s = ctl->sweep_at[a.par];
+        if (a.advance) {
+            store_draws(ctl, a.par ^ 1, s + 1ull, R);
+        } else {
+            ctl->sweep_at[a.par ^ 1] = s;
+            ctl->draw_at[a.par ^ 1] = ctl->draw_at[a.par];
+        }
+    }
+}
+
+// The shift under the cell-leaving pitfalls (diagnostic): disks may sit up
+// to (w - 1)/2 outside their cells on either axis.  One thread per new cell
+// c: every disk of the 3x3 old cells gets its shifted coordinate (one FP32
+// operation) and the other one; per axis a value <= 0 lands one cell down
+// (coordinate + w), a value > w one cell up (coordinate - w).  The disks
+// that land in c are listed: c's own first, then the eight neighbours' in
+// row-major order of the offset, each in list order -- without excursions
+// exactly k_rebin's order.
+__device__ __forceinline__ int land(float t, float w, float &u)
+{
+    if (t <= 0.0f) {
+        u = t + w;
+        return -1;
+    }
+    if (t > w) {
+        u = t - w;
+        return 1;
+    }
+    u = t;
+    return 0;
+}
+
+template <int CAP, bool ONE>
+__global__ void __launch_bounds__(kRebinTile) k_rebin_general(RebinArgs a)
+{
+    const int tile = xcd_tile(a.per);
+    if (tile >= a.ntile) return;
+    const long long cell0 = (long long)tile * kRebinTile;
+    const int r = ONE ? 0 : tile_replica(a.t, true, tile);
+    const Rep R = ONE ? a.t.rep0 : a.t.reps[r];
+    const Geom g = R.g;
+    Ctl *ctl = a.t.ctls + r;
+    int f = a.f;
+    float d = a.d;
+    if (f < 0) {
+        f = ctl->draw_at[a.par].f;
+        d = ctl->draw_at[a.par].d;
+    }
+    const bool along_x = f < 2;
+    const bool minus = (f == 0 || f == 2);   // +x / +y: t = v - d
+    const int cl = (int)(cell0 - R.cb) + (int)threadIdx.x;   // cell within the replica
+    if (cl < g.C) {
+        const int cy = cl / g.mx, cx = cl - cy * g.mx;
+        const bool has_acc = a.acc != nullptr, has_tag = a.tag != nullptr;
+        const size_t ob = (size_t)(R.cb + cl) * CAP;
+        int o = 0;
+        bool over = false;
+        for (int k = 0; k < 9; ++k) {
+            const int q = k == 0 ? 4 : (k <= 4 ? k - 1 : k);
+            const int ox = q % 3 - 1, oy = q / 3 - 1;
+            const int sx = ox < 0 ? (cx == 0 ? g.mx - 1 : cx - 1) : (ox > 0 ? (cx == g.mx - 1 ? 0 : cx + 1) : cx);
+            const int sy = oy < 0 ? (cy == 0 ? g.my - 1 : cy - 1) : (oy > 0 ? (cy == g.my - 1 ? 0 : cy + 1) : cy);
+            const long long sc = R.cb + (long long)sy * g.mx + sx;
+            int ns = (int)a.count[sc];
+            if (ns > g.cap) {
+                over = true;
+                ns = g.cap;
+            }
+            for (int i = 0; i < ns; ++i) {
+                const size_t si = (size_t)sc * CAP + (size_t)i;
+                const float2 v = a.pos[si];
+                const float tx = along_x ? shifted(v.x, minus, d) : v.x;
+                const float ty = along_x ? v.y : shifted(v.y, minus, d);
+                float ux, uy;
+                const int mxo = land(tx, g.wx, ux);
+                const int myo = land(ty, g.wy, uy);
+                if (mxo != -ox || myo != -oy) continue;   // lands elsewhere
+                if (o < g.cap) {
+                    a.pos_out[ob + (size_t)o] = make_float2(ux, uy);
+                    if (has_acc) a.acc_out[ob + (size_t)o] = a.acc[si];
+                    if (has_tag) a.tag_out[ob + (size_t)o] = a.tag[si];
+                } else {
+                    over = true;
+                }
+                ++o;
+            }
+        }
+        if (over) atomicOr(&ctl->errword, kErrCapacity);
+        a.count_out[R.cb + cl] = (uint32_t)(o > g.cap ? g.cap : o);
+    } else if (cl < R.cpad) {
+        a.count_out[R.cb + cl] = 0u;   // padding cells stay empty
     }
     if (cell0 == R.cb && threadIdx.x == 0) {
         const unsigned long long s = ctl->sweep_at[a.par];
@@ -1704,6 +1806,7 @@ hipError_t launch_subsweep(const Tables &t, int par, float2 *pos, const uint32_t
                            int block, int lanes, hipStream_t st)
 {
     if (lanes != 1 && lanes != 2 && lanes != 4) return hipErrorInvalidValue;
+    if (t.leave) lanes = 1;   // the cell-leaving pitfalls run on the one-lane kernel only
     block = subsweep_block(t.cap, block, lanes);
     if (block < 64 || block > 256 || block % 64 || (kActiveChunk * lanes) % block)
         return hipErrorInvalidValue;
@@ -1761,7 +1864,7 @@ hipError_t launch_fold_counters(const Tables &t, const Work &w, hipStream_t st)
 
 int fused_tile(bool acc, bool tag) { return tag ? 20 : (acc ? 24 : 38); }
 
-bool sweep_fused_supported(const Tables &t) { return t.cap == 4 && t.ftiles > 0; }
+bool sweep_fused_supported(const Tables &t) { return t.cap == 4 && t.ftiles > 0 && !t.leave; }
 
 hipError_t launch_sweep_fused(const Tables &t, int par, const float2 *pos, const uint32_t *count,
                               const float2 *acc, const uint32_t *tag, float2 *pos_out,
@@ -1829,8 +1932,14 @@ hipError_t launch_rebin(const Tables &t, int par, const float2 *pos, const uint3
     const dim3 grid(8 * a.per), blk(kRebinTile);
 #define MPMC_REBIN(CAP)                                                                        \
     do {                                                                                       \
-        if (t.R == 1) hipLaunchKernelGGL((k_rebin<CAP, true>), grid, blk, 0, st, a);           \
-        else hipLaunchKernelGGL((k_rebin<CAP, false>), grid, blk, 0, st, a);                   \
+        if (t.leave) {                                                                         \
+            if (t.R == 1) hipLaunchKernelGGL((k_rebin_general<CAP, true>), grid, blk, 0, st, a); \
+            else hipLaunchKernelGGL((k_rebin_general<CAP, false>), grid, blk, 0, st, a);       \
+        } else if (t.R == 1) {                                                                 \
+            hipLaunchKernelGGL((k_rebin<CAP, true>), grid, blk, 0, st, a);                     \
+        } else {                                                                               \
+            hipLaunchKernelGGL((k_rebin<CAP, false>), grid, blk, 0, st, a);                    \
+        }                                                                                      \
     } while (0)
     switch (t.cap) {
     case 4: MPMC_REBIN(4); break;

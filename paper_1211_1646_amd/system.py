@@ -145,6 +145,14 @@ class HardDiskSystem:
         L.check(self.lib.mpmc_get_sweep_kernel(self._h, C.byref(v)))
         return bool(v.value)
 
+    @property
+    def fused_tile(self):
+        """(compiled tile side, chosen interior tx, ty) of the fused sweep,
+        zeros when sweeps do not run fused."""
+        v = [C.c_int32() for _ in range(3)]
+        L.check(self.lib.mpmc_get_fused_tile(self._h, *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
     def prepare_sweeps(self, n: int):
         """Capture the graphs a following sweep(n) launches (runs nothing)."""
         L.check(self.lib.mpmc_prepare_sweeps(self._h, int(n)))

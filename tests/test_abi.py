@@ -179,7 +179,10 @@ def test_batch_argument_errors():
     ab = SystemConfig(lattice_nx=20, lattice_ny=20, phi=0.7, delta=0.1,
                       flags=pkg.FLAG_NO_PARTICLE_SHUFFLE | pkg.FLAG_NO_SET_SHUFFLE)
     assert _batch_sizes([a, d, ab])[0] == L.MPMC_OK
-    unknown = SystemConfig(lattice_nx=16, lattice_ny=16, phi=0.6, delta=0.1, flags=64)
+    lv = SystemConfig(lattice_nx=16, lattice_ny=16, phi=0.6, delta=0.1,
+                      flags=pkg.FLAG_LEAVE | pkg.FLAG_LEAVE_ONCE)
+    assert _batch_sizes([a, lv])[0] == L.MPMC_OK                     # chain flags may differ
+    unknown = SystemConfig(lattice_nx=16, lattice_ny=16, phi=0.6, delta=0.1, flags=256)
     assert _batch_sizes([unknown])[0] == L.MPMC_EINVAL
 
 
