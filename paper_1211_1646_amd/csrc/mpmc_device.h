@@ -87,6 +87,33 @@ __device__ __forceinline__ void rperm(T (&a)[N], uint32_t P)
     rperm_(a, P, std::make_integer_sequence<int, N>{});
 }
 
+// As rrot and rperm over the first M entries only, for n <= M: the entries
+// at or past M are the ones the full forms leave unchanged.
+template <int M, typename T, int N, int... I>
+__device__ __forceinline__ void rrot_m_(T (&a)[N], int n, std::integer_sequence<int, I...>)
+{
+    const T first = a[0];
+    ((a[I] = (I + 1 < n) ? a[(I + 1 < M) ? I + 1 : I] : ((I == n - 1) ? first : a[I])), ...);
+}
+template <int M, typename T, int N>
+__device__ __forceinline__ void rrot_m(T (&a)[N], int n)
+{
+    static_assert(M <= N, "prefix longer than the array");
+    rrot_m_<M>(a, n, std::make_integer_sequence<int, M>{});
+}
+template <int M, typename T, int N, int... I>
+__device__ __forceinline__ void rperm_m_(T (&a)[N], uint32_t P, std::integer_sequence<int, I...>)
+{
+    const T old[M] = {a[I]...};
+    ((a[I] = rsel(old, (int)((P >> (4 * I)) & 0xFu))), ...);
+}
+template <int M, typename T, int N>
+__device__ __forceinline__ void rperm_m(T (&a)[N], uint32_t P)
+{
+    static_assert(M <= N, "prefix longer than the array");
+    rperm_m_<M>(a, P, std::make_integer_sequence<int, M>{});
+}
+
 // Swap nibbles i and j of a packed permutation.
 __device__ __forceinline__ uint32_t nib_swap(uint32_t P, int i, int j)
 {

@@ -70,7 +70,15 @@ inline int subsweep_tiles(const Geom3 &g, int lanes)
 {
     return (int)(((long long)g.active * lanes + kSubBlock - 1) / kSubBlock);
 }
-inline int subsweep_groups(const Geom3 &g) { return subsweep_tiles(g, 4); }
+// Bricks of 4 x 4 x 4 active cells along an axis of m cells (m / 2 active),
+// for the one-lane form; the partials cover whichever launch has more groups.
+inline int brick_count(int m) { return (m / 2 + 3) / 4; }
+inline int subsweep_groups(const Geom3 &g)
+{
+    const int bricks = brick_count(g.m[0]) * brick_count(g.m[1]) * brick_count(g.m[2]);
+    const int tiles = subsweep_tiles(g, 4);
+    return bricks > tiles ? bricks : tiles;
+}
 inline int xcd_groups(int tiles) { return 8 * ((tiles + 7) / 8); }
 
 hipError_t launch_subsweep3(const Geom3 &g, Ctl3 *ctl, int par, float4 *pos,

@@ -516,6 +516,409 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     }
 }
 
+// ------------------------------------------------------- brick sub-sweep
+// The one-lane-per-cell form without accumulators.  A workgroup of 64
+// lanes serves a brick of kBk^3 active cells of set Q; lane (lx, ly, lz)
+// owns active cell (kBk bx + lx, ...).  The brick's region -- its cells and
+// all their neighbours, kRg^3 cells with periodic indices -- is staged into
+// LDS by coalesced loads that are all independent: per cell slots 0 and 1
+// (a far sphere where empty), in eight parity planes so that the lanes of a
+// wave, reading the same neighbour offset, read consecutive words.  Spheres
+// in slots 2..7, which only cells with more than two spheres have, go to a
+// list of the brick, and from there to per-lane lists of the lanes whose
+// neighbourhood holds them.  Each lane then holds the 52 staged slots of its
+// 26 neighbour cells and its listed spheres in registers, translated into
+// its frame (exactly -w, 0 or +w per axis), and runs its trials against all
+// of them: no reach filter, no per-lane compaction, and no memory round
+// trip that depends on another beyond the overflow slots.  A lane with more
+// listed spheres than it holds, or a brick whose list overflows, tests every
+// neighbour straight from memory instead (overlap_from_memory).  Every pair
+// is tested with the same FP32 operations as in the other forms, and a far
+// sphere never overlaps, so the decisions are the same.
+constexpr int kBk = 4;                     // active cells per brick side
+constexpr int kRg = 2 * kBk + 1;           // region side, cells
+constexpr int kRgC = kRg * kRg * kRg;      // region cells
+constexpr int kOvMax = 128;                // listed spheres per brick
+constexpr int kOvLane = 8;                 // listed spheres a lane holds
+
+// Parity plane of region coordinate r along one axis: class r & 1 holds
+// 5 - (r & 1) cells, index r >> 1.  Plane (px, py, pz) starts at
+// kPlaneBase[px + 2 py + 4 pz].
+constexpr int plane_size(int c) { return (5 - (c & 1)) * (5 - ((c >> 1) & 1)) * (5 - (c >> 2)); }
+constexpr int plane_base(int c) { return c == 0 ? 0 : plane_base(c - 1) + plane_size(c - 1); }
+__device__ __forceinline__ constexpr int plane_index(int rx, int ry, int rz)
+{
+    return plane_base((rx & 1) | ((ry & 1) << 1) | ((rz & 1) << 2)) + (rx >> 1) +
+           (5 - (rx & 1)) * ((ry >> 1) + (5 - (ry & 1)) * (rz >> 1));
+}
+
+template <bool TAG>
+__global__ void __launch_bounds__(64)
+k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
+             const uint32_t *__restrict__ count, uint32_t *__restrict__ tag,
+             unsigned long long *__restrict__ cnt, int set, int nbrick, int per, int nbx, int nby)
+{
+    // slot planes [coordinate][slot][parity-plane index]; after the registers
+    // are filled the same memory holds the per-lane lists [lane][k] (x, y, z)
+    __shared__ float planes[6][kRgC];
+    float(*sx)[kRgC] = planes, (*sy)[kRgC] = planes + 2, (*sz)[kRgC] = planes + 4;
+    __shared__ float ovx[kOvMax], ovy[kOvMax], ovz[kOvMax];
+    __shared__ int ovr[kOvMax];            // region coordinates rx | ry << 4 | rz << 8
+    __shared__ int row_base[kRg * kRg];    // global index of region row (ry, rz), x = 0
+    __shared__ int col_x[kRg];             // global x of region column rx
+    __shared__ uint32_t ov_lane[64];       // listed spheres per lane
+    __shared__ uint32_t n_ov, brick_bad;
+    static_assert(64 * kOvLane * 3 <= 6 * kRgC, "per-lane lists fit the slot planes");
+    const int brick = xcd_tile(per);
+    if (brick >= nbrick) return;           // a padding workgroup of the XCD-aligned grid
+    const int lane = threadIdx.x;
+    const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+    const int bz = brick / (nbx * nby), by = (brick / nbx) % nby, bx = brick % nbx;
+    const int hx = g.m[0] >> 1, hy = g.m[1] >> 1, hz = g.m[2] >> 1;
+    const int ix = kBk * bx + lx, iy = kBk * by + ly, iz = kBk * bz + lz;
+    const bool live = ix < hx && iy < hy && iz < hz;
+    const unsigned long long s = ctl->sweep_at[par];
+    const uint32_t k0 = ctl->key0, k1 = ctl->key1;
+    const float delta = ctl->delta;
+    const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
+    int Q = set;
+    if (Q < 0) Q = (int)((ctl->draw_at[par].order >> (4 * (-1 - set))) & 0xFu);
+    const int qx = Q & 1, qy = (Q >> 1) & 1, qz = Q >> 2;
+    // region origin (global cell coordinates of region cell (0, 0, 0)), may be -1
+    const int ox0 = 2 * kBk * bx + qx - 1, oy0 = 2 * kBk * by + qy - 1, oz0 = 2 * kBk * bz + qz - 1;
+    auto wrapc = [](int v, int m) {        // v in [-1, 3 m): the periodic image in [0, m)
+        v = v < 0 ? v + m : v;
+        v = v >= m ? v - m : v;
+        return v >= m ? v - m : v;
+    };
+    for (int k = lane; k < kRg * kRg; k += 64) {
+        const int ry = k % kRg, rz = k / kRg;
+        row_base[k] = (wrapc(oz0 + rz, g.m[2]) * g.m[1] + wrapc(oy0 + ry, g.m[1])) * g.m[0];
+    }
+    if (lane < kRg) col_x[lane] = wrapc(ox0 + lane, g.m[0]);
+    ov_lane[lane] = 0u;
+    if (lane == 0) {
+        n_ov = 0u;
+        brick_bad = 0u;
+    }
+    __syncthreads();
+
+    // 1. stage the region, plane by plane; every load of this pass is
+    // independent of the others
+    constexpr int kSt = 15;                // staging steps per lane (planes of 125..64 cells)
+    uint32_t cn[kSt];
+    int gc[kSt], pi[kSt], rc[kSt];
+    float4 v0[kSt], v1[kSt];
+    {
+        int t = 0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int px = c & 1, py = (c >> 1) & 1, pz = c >> 2;
+            const int nx = 5 - px, ny = 5 - py, nzc = 5 - pz;
+            const int size = nx * ny * nzc;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (u * 64 >= size) continue;
+                const int idx = u * 64 + lane;
+                const int id = idx < size ? idx : size - 1;
+                const int i = id % nx, j = (id / nx) % ny, k = id / (nx * ny);
+                const int rx = 2 * i + px, ry = 2 * j + py, rz = 2 * k + pz;
+                const int cell = row_base[ry + kRg * rz] + col_x[rx];
+                gc[t] = cell;
+                pi[t] = idx < size ? plane_base(c) + id : -1;
+                rc[t] = rx | (ry << 4) | (rz << 8);
+                cn[t] = count[cell];
+                v0[t] = pos[(size_t)cell * kPrim];
+                v1[t] = pos[(size_t)cell * kPrim + 1];
+                ++t;
+            }
+        }
+    }
+    bool bad = false;
+#pragma unroll
+    for (int t = 0; t < kSt; ++t) {
+        if (pi[t] >= 0) {
+            const uint32_t n = cn[t];
+            bad |= n > (uint32_t)kCap;
+            sx[0][pi[t]] = n > 0 ? v0[t].x : kFar;
+            sy[0][pi[t]] = n > 0 ? v0[t].y : kFar;
+            sz[0][pi[t]] = n > 0 ? v0[t].z : kFar;
+            sx[1][pi[t]] = n > 1 ? v1[t].x : kFar;
+            sy[1][pi[t]] = n > 1 ? v1[t].y : kFar;
+            sz[1][pi[t]] = n > 1 ? v1[t].z : kFar;
+        }
+    }
+    // slots 2..7 of the cells that have them go to the brick's list: slots 2
+    // and 3 of every staged cell in one batch (raw buffer loads: a slot past
+    // the cell's count reads zeros without a memory access), 4..7 cell by
+    // cell, only where some lane of the wave has such a cell
+    const __amdgpu_buffer_rsrc_t slots = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)pos, (short)0, (int)((unsigned)g.C * (unsigned)(kCap * sizeof(float4))), kBufferWord3);
+    uint32_t nst[kSt];
+#pragma unroll
+    for (int t = 0; t < kSt; ++t) nst[t] = pi[t] >= 0 ? min(cn[t], (uint32_t)kCap) : 0u;
+    if (__ballot(bad) == 0ull) {
+        bool any2 = false;
+#pragma unroll
+        for (int t = 0; t < kSt; ++t) any2 |= nst[t] > (uint32_t)kPrim;
+        if (__ballot(any2) != 0ull) {
+#pragma unroll
+            for (int t = 0; t < kSt; ++t) {
+                const int o2 = nst[t] > 2u ? (int)slot_of(g.C, gc[t], 2) * (int)sizeof(float4) : kPastEnd;
+                const int o3 = nst[t] > 3u ? (int)slot_of(g.C, gc[t], 3) * (int)sizeof(float4) : kPastEnd;
+                v0[t] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(slots, o2, 0, 0));
+                v1[t] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(slots, o3, 0, 0));
+            }
+#pragma unroll
+            for (int t = 0; t < kSt; ++t) {
+                if (nst[t] > 2u) {
+                    const uint32_t m = min(nst[t], 4u) - 2u;
+                    const uint32_t e0 = atomicAdd(&n_ov, m);
+                    if (e0 < (uint32_t)kOvMax) {
+                        ovx[e0] = v0[t].x;
+                        ovy[e0] = v0[t].y;
+                        ovz[e0] = v0[t].z;
+                        ovr[e0] = rc[t];
+                    }
+                    if (m > 1u && e0 + 1u < (uint32_t)kOvMax) {
+                        ovx[e0 + 1] = v1[t].x;
+                        ovy[e0 + 1] = v1[t].y;
+                        ovz[e0 + 1] = v1[t].z;
+                        ovr[e0 + 1] = rc[t];
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < kSt; ++t) {
+                if (__ballot(nst[t] > 4u) == 0ull) continue;
+                if (nst[t] > 4u) {
+                    const uint32_t m = nst[t] - 4u;
+                    const uint32_t e0 = atomicAdd(&n_ov, m);
+                    for (uint32_t q = 0; q < m; ++q) {
+                        const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
+                            slots, (int)slot_of(g.C, gc[t], 4 + (int)q) * (int)sizeof(float4), 0, 0));
+                        if (e0 + q < (uint32_t)kOvMax) {
+                            ovx[e0 + q] = v.x;
+                            ovy[e0 + q] = v.y;
+                            ovz[e0 + q] = v.z;
+                            ovr[e0 + q] = rc[t];
+                        }
+                    }
+                }
+            }
+        }
+    } else {
+        // a cell above capacity: report it and leave the brick unchanged
+        if (bad) atomicOr(&ctl->errword, kErrCapacity);
+        brick_bad = 1u;
+    }
+    __syncthreads();
+
+    // 2. the 26 neighbour cells' staged slots, in this cell's frame
+    const int cx = 2 * ix + qx, cy = 2 * iy + qy, cz = 2 * iz + qz;
+    const int c = live ? (cz * g.m[1] + cy) * g.m[0] + cx : 0;
+    const int rxo = 1 + 2 * lx, ryo = 1 + 2 * ly, rzo = 1 + 2 * lz;   // own region cell
+    float nx[52], ny[52], nz[52];
+#pragma unroll
+    for (int j = 0; j < 26; ++j) {
+        const int q = j < 13 ? j : j + 1;
+        const int ox = q % 3 - 1, oy = (q / 3) % 3 - 1, oz = q / 9 - 1;
+        const int rn = plane_index(rxo + ox, ryo + oy, rzo + oz);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            nx[2 * j + u] = frame(sx[u][rn], ox, g.w[0]);
+            ny[2 * j + u] = frame(sy[u][rn], oy, g.w[1]);
+            nz[2 * j + u] = frame(sz[u][rn], oz, g.w[2]);
+        }
+    }
+    const int ro = plane_index(rxo, ryo, rzo);
+    float px[kCap], py[kCap], pz[kCap];
+    uint32_t tg[kCap];
+#pragma unroll
+    for (int q = 0; q < kCap; ++q) {
+        px[q] = py[q] = pz[q] = kFar;
+        tg[q] = 0u;
+    }
+    px[0] = sx[0][ro];
+    py[0] = sy[0][ro];
+    pz[0] = sz[0][ro];
+    px[1] = sx[1][ro];
+    py[1] = sy[1][ro];
+    pz[1] = sz[1][ro];
+    const int nlist = (int)n_ov;
+    const bool brick_ok = brick_bad == 0u;
+    __syncthreads();   // the slot planes are read; their memory takes the per-lane lists
+
+    // 3. the brick's listed spheres to the lists of the lanes whose
+    // neighbourhood holds them (at most 8 lanes each, offsets -1, 0, +1)
+    float *lst = &planes[0][0];            // [lane][k][3]
+    const int lim = nlist < kOvMax ? nlist : kOvMax;
+    for (int e = lane; e < lim; e += 64) {
+        const int code = ovr[e];
+        const int r[3] = {code & 15, (code >> 4) & 15, code >> 8};
+        const float v[3] = {ovx[e], ovy[e], ovz[e]};
+        // per axis: an even region coordinate 2t neighbours lanes t - 1
+        // (offset +1) and t (offset -1), an odd one 2t + 1 only lane t (0)
+#pragma unroll
+        for (int cmb = 0; cmb < 8; ++cmb) {
+            int l[3], o[3];
+            bool ok = true;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int b = (cmb >> d) & 1;
+                if (r[d] & 1) {
+                    l[d] = r[d] >> 1;
+                    o[d] = 0;
+                    ok = ok && b == 0;
+                } else {
+                    l[d] = (r[d] >> 1) - 1 + b;
+                    o[d] = b ? -1 : 1;
+                }
+                ok = ok && l[d] >= 0 && l[d] < kBk;
+            }
+            ok = ok && (o[0] | o[1] | o[2]) != 0;   // the own cell's spheres are the lane's own
+            if (ok) {
+                const int tl = l[0] + kBk * (l[1] + kBk * l[2]);
+                const uint32_t k = atomicAdd(&ov_lane[tl], 1u);
+                if (k < (uint32_t)kOvLane) {
+                    float *dst = lst + (tl * kOvLane + (int)k) * 3;
+                    dst[0] = frame(v[0], o[0], g.w[0]);
+                    dst[1] = frame(v[1], o[1], g.w[1]);
+                    dst[2] = frame(v[2], o[2], g.w[2]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int kov = (int)ov_lane[lane];
+    bool spill = nlist > kOvMax || kov > kOvLane;
+    float ex[kOvLane], ey[kOvLane], ez[kOvLane];
+#pragma unroll
+    for (int k = 0; k < kOvLane; ++k) {
+        const float *src = lst + (lane * kOvLane + k) * 3;
+        ex[k] = k < kov ? src[0] : kFar;
+        ey[k] = k < kov ? src[1] : kFar;
+        ez[k] = k < kov ? src[2] : kFar;
+    }
+    int kw = kov < kOvLane ? kov : kOvLane;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) kw = max(kw, __shfl_xor(kw, o, 64));
+
+    // 4. the own cell: slots 2..7 and the tags from memory
+    const uint32_t n_raw = live ? count[c] : 0u;
+    const int n = (live && brick_ok) ? (int)min(n_raw, (uint32_t)kCap) : 0;
+    constexpr bool has_tag = TAG;          // a compile-time variant: no registers without tags
+    if (__ballot(n > kPrim) != 0ull) {
+#pragma unroll
+        for (int q = kPrim; q < kCap; ++q) {
+            const int off = n > q ? (int)slot_of(g.C, c, q) * (int)sizeof(float4) : kPastEnd;
+            const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(slots, off, 0, 0));
+            px[q] = v.x;
+            py[q] = v.y;
+            pz[q] = v.z;
+        }
+    }
+    if (has_tag) {
+#pragma unroll
+        for (int q = 0; q < kCap; ++q)
+            if (q < n) tg[q] = tag[slot_of(g.C, c, q)];
+    }
+    uint4 Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle, k0, k1);
+    uint4 W = make_uint4(0, 0, 0, 0);
+    if (g.n_moves > 0) W = philox((uint32_t)c, s_lo, s_hi, 0u, k0, k1);
+
+    // 5. shuffle and trials; own entries at or past M = the wave's largest
+    // count (2, 4 or 8) are far spheres or identities throughout, so the
+    // phase is compiled for each M and the wave runs the smallest that fits
+    int nw = n;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nw = max(nw, __shfl_xor(nw, o, 64));
+    unsigned n_trials = 0, n_acc = 0;
+    auto phase = [&](auto Mc) {
+        constexpr int M = decltype(Mc)::value;
+        if (n == 0) return;
+        // rng.shuffle(c.particles): Fisher-Yates on a packed permutation
+        // (nibble q = source slot of list position q), applied once
+        uint32_t P = 0x76543210u;
+        for (int k = 0; k < n - 1; ++k) {
+            if (k > 0 && (k & 3) == 0)
+                Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle + (uint32_t)(k >> 2), k0, k1);
+            const int i = n - 1 - k;
+            P = nib_swap(P, i, (int)bounded(word_of(Wsh, k & 3), (uint32_t)(i + 1)));
+        }
+        if (n > 1) {
+            rperm_m<M>(px, P);
+            rperm_m<M>(py, P);
+            rperm_m<M>(pz, P);
+            if (has_tag) rperm_m<M>(tg, P);
+        }
+#pragma unroll
+        for (int q = 1; q < M; ++q) {
+            px[q] = q < n ? px[q] : kFar;
+            py[q] = q < n ? py[q] : kFar;
+            pz[q] = q < n ? pz[q] : kFar;
+        }
+        for (int t = 0; t < g.n_moves; ++t) {
+            if (t > 0 && (t & 1) == 0) W = philox((uint32_t)c, s_lo, s_hi, (uint32_t)(t >> 1), k0, k1);
+            float dx, dy, dz;
+            displacement3((t & 1) ? W.z : W.x, (t & 1) ? W.w : W.y, delta, dx, dy, dz);
+            const float xm = px[0] + dx;
+            const float ym = py[0] + dy;
+            const float zm = pz[0] + dz;
+            bool ok = (xm > 0.0f) & (xm <= g.w[0]) & (ym > 0.0f) & (ym <= g.w[1]) &
+                      (zm > 0.0f) & (zm <= g.w[2]);
+#pragma unroll
+            for (int q = 1; q < M; ++q) {
+                const float ddx = xm - px[q];
+                const float ddy = ym - py[q];
+                const float ddz = zm - pz[q];
+                ok = ok & !((ddx * ddx + ddy * ddy) + ddz * ddz < 1.0f);
+            }
+#pragma unroll
+            for (int k = 0; k < 52; k += 4)
+                ok = ok & !(min_r2_4(xm, ym, zm, nx + k, ny + k, nz + k) < 1.0f);
+#pragma unroll
+            for (int k = 0; k < kOvLane; k += 4)
+                if (k < kw) ok = ok & !(min_r2_4(xm, ym, zm, ex + k, ey + k, ez + k) < 1.0f);
+            if (spill && ok) ok = !overlap_from_memory(g, pos, count, cx, cy, cz, xm, ym, zm);
+            px[0] = ok ? xm : px[0];
+            py[0] = ok ? ym : py[0];
+            pz[0] = ok ? zm : pz[0];
+            n_acc += ok ? 1u : 0u;
+            rrot_m<M>(px, n);   // the identity for n = 1
+            rrot_m<M>(py, n);
+            rrot_m<M>(pz, n);
+            if (has_tag) rrot_m<M>(tg, n);
+        }
+        n_trials = (unsigned)g.n_moves;
+        // register entry q now holds list position (q + n_M) mod n
+        const int r0 = g.n_moves % n;
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            if (q < n) {
+                int o = q + r0;
+                o = o >= n ? o - n : o;
+                const size_t so = slot_of(g.C, c, o);
+                pos[so] = make_float4(px[q], py[q], pz[q], 0.0f);
+                if (has_tag && n > 1) tag[so] = tg[q];
+            }
+        }
+    };
+    if (nw <= 2)
+        phase(std::integral_constant<int, 2>{});
+    else if (nw <= 4)
+        phase(std::integral_constant<int, 4>{});
+    else
+        phase(std::integral_constant<int, kCap>{});
+    // this workgroup's partials (one wave; the same entry in every launch)
+    const unsigned bt = wave_sum_u32(n_trials);
+    const unsigned ba = wave_sum_u32(n_acc);
+    if (lane == 0 && bt) {
+        cnt[2 * brick] += (unsigned long long)bt;
+        cnt[2 * brick + 1] += (unsigned long long)ba;
+    }
+}
+
 // Add the partials into the control block and clear them (one workgroup).
 __global__ void __launch_bounds__(256) k_fold3(Ctl3 *ctl, unsigned long long *cnt, int groups)
 {
@@ -976,7 +1379,19 @@ hipError_t launch_subsweep3(const Geom3 &g, Ctl3 *ctl, int par, float4 *pos,
     } else if (lanes == 2) {
         if (a) SPH_SUB(2, true); else SPH_SUB(2, false);
     } else {
-        if (a) SPH_SUB(1, true); else SPH_SUB(1, false);
+        // one lane per cell: the brick form, or with accumulators the
+        // per-lane form (the brick's registers have no room for them)
+        const int nbx = brick_count(g.m[0]), nby = brick_count(g.m[1]), nbz = brick_count(g.m[2]);
+        const int nbrick = nbx * nby * nbz;
+        const int bgrid = xcd_groups(nbrick);
+        if (a)
+            SPH_SUB(1, true);
+        else if (tag)
+            hipLaunchKernelGGL(k_subsweep3b<true>, dim3(bgrid), dim3(64), 0, st, g, ctl, par, pos,
+                               count, tag, cnt, set, nbrick, bgrid / 8, nbx, nby);
+        else
+            hipLaunchKernelGGL(k_subsweep3b<false>, dim3(bgrid), dim3(64), 0, st, g, ctl, par, pos,
+                               count, tag, cnt, set, nbrick, bgrid / 8, nbx, nby);
     }
 #undef SPH_SUB
     return hipGetLastError();
