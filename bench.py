@@ -202,9 +202,9 @@ def spheres_leg(args):
                    kernel_samples=64)
     src = os.path.join(ROOT, "paper_1211_1646_amd", "csrc", "sphere_kernels.hip")
     prof = "sphere_subsweep_1M_eta045_counters.md"
-    r["roofline"]["traffic"] = traffic_from_profile(src, "k_subsweep3", profile=prof)
-    r["roofline"]["valu_busy"] = traffic_from_profile(src, "k_subsweep3", "valu busy fraction",
-                                                      profile=prof)
+    k = r["roofline"]["kernel"]
+    r["roofline"]["traffic"] = traffic_from_profile(src, k, profile=prof)
+    r["roofline"]["valu_busy"] = traffic_from_profile(src, k, "valu busy fraction", profile=prof)
     return r
 
 

@@ -553,7 +553,7 @@ __device__ __forceinline__ constexpr int plane_index(int rx, int ry, int rz)
 }
 
 template <bool TAG>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
              const uint32_t *__restrict__ count, uint32_t *__restrict__ tag,
              unsigned long long *__restrict__ cnt, int set, int nbrick, int per, int nbx, int nby)
@@ -564,10 +564,8 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     float(*sx)[kRgC] = planes, (*sy)[kRgC] = planes + 2, (*sz)[kRgC] = planes + 4;
     __shared__ float ovx[kOvMax], ovy[kOvMax], ovz[kOvMax];
     __shared__ int ovr[kOvMax];            // region coordinates rx | ry << 4 | rz << 8
-    __shared__ int row_base[kRg * kRg];    // global index of region row (ry, rz), x = 0
-    __shared__ int col_x[kRg];             // global x of region column rx
     __shared__ uint32_t ov_lane[64];       // listed spheres per lane
-    __shared__ uint32_t n_ov, brick_bad;
+    __shared__ uint32_t n_ov;
     static_assert(64 * kOvLane * 3 <= 6 * kRgC, "per-lane lists fit the slot planes");
     const int brick = xcd_tile(per);
     if (brick >= nbrick) return;           // a padding workgroup of the XCD-aligned grid
@@ -591,20 +589,14 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
         v = v >= m ? v - m : v;
         return v >= m ? v - m : v;
     };
-    for (int k = lane; k < kRg * kRg; k += 64) {
-        const int ry = k % kRg, rz = k / kRg;
-        row_base[k] = (wrapc(oz0 + rz, g.m[2]) * g.m[1] + wrapc(oy0 + ry, g.m[1])) * g.m[0];
-    }
-    if (lane < kRg) col_x[lane] = wrapc(ox0 + lane, g.m[0]);
     ov_lane[lane] = 0u;
-    if (lane == 0) {
-        n_ov = 0u;
-        brick_bad = 0u;
-    }
-    __syncthreads();
+    if (lane == 0) n_ov = 0u;
+    const int cx = 2 * ix + qx, cy = 2 * iy + qy, cz = 2 * iz + qz;
+    const int c = live ? (cz * g.m[1] + cy) * g.m[0] + cx : 0;
+    constexpr bool has_tag = TAG;          // a compile-time variant: no registers without tags
 
-    // 1. stage the region, plane by plane; every load of this pass is
-    // independent of the others
+    // 1. stage the region, plane by plane, with the own count and tags; every
+    // load of this pass is independent of the others
     constexpr int kSt = 15;                // staging steps per lane (planes of 125..64 cells)
     uint32_t cn[kSt];
     int gc[kSt], pi[kSt], rc[kSt];
@@ -612,8 +604,8 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     {
         int t = 0;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int px = c & 1, py = (c >> 1) & 1, pz = c >> 2;
+        for (int cl = 0; cl < 8; ++cl) {
+            const int px = cl & 1, py = (cl >> 1) & 1, pz = cl >> 2;
             const int nx = 5 - px, ny = 5 - py, nzc = 5 - pz;
             const int size = nx * ny * nzc;
 #pragma unroll
@@ -623,9 +615,10 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
                 const int id = idx < size ? idx : size - 1;
                 const int i = id % nx, j = (id / nx) % ny, k = id / (nx * ny);
                 const int rx = 2 * i + px, ry = 2 * j + py, rz = 2 * k + pz;
-                const int cell = row_base[ry + kRg * rz] + col_x[rx];
+                const int cell = (wrapc(oz0 + rz, g.m[2]) * g.m[1] + wrapc(oy0 + ry, g.m[1])) * g.m[0] +
+                                 wrapc(ox0 + rx, g.m[0]);
                 gc[t] = cell;
-                pi[t] = idx < size ? plane_base(c) + id : -1;
+                pi[t] = idx < size ? plane_base(cl) + id : -1;
                 rc[t] = rx | (ry << 4) | (rz << 8);
                 cn[t] = count[cell];
                 v0[t] = pos[(size_t)cell * kPrim];
@@ -634,12 +627,15 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
             }
         }
     }
-    bool bad = false;
+    const uint32_t n_raw = live ? count[c] : 0u;
+    bool bad = n_raw > (uint32_t)kCap;
+    uint32_t ovm = 0u;                     // staging steps whose cell has more than kPrim spheres
 #pragma unroll
     for (int t = 0; t < kSt; ++t) {
         if (pi[t] >= 0) {
             const uint32_t n = cn[t];
             bad |= n > (uint32_t)kCap;
+            ovm |= n > (uint32_t)kPrim ? 1u << t : 0u;
             sx[0][pi[t]] = n > 0 ? v0[t].x : kFar;
             sy[0][pi[t]] = n > 0 ? v0[t].y : kFar;
             sz[0][pi[t]] = n > 0 ? v0[t].z : kFar;
@@ -648,75 +644,86 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
             sz[1][pi[t]] = n > 1 ? v1[t].z : kFar;
         }
     }
-    // slots 2..7 of the cells that have them go to the brick's list: slots 2
-    // and 3 of every staged cell in one batch (raw buffer loads: a slot past
-    // the cell's count reads zeros without a memory access), 4..7 cell by
-    // cell, only where some lane of the wave has such a cell
+    // 2. slots 2..7: of the staged cells that have them, to the brick's list,
+    // and of the own cell, to registers.  A lane's cells with such slots are
+    // taken three at a time (their loads in one batch), while any lane has
+    // some left; a slot past the cell's count is a raw buffer load past the
+    // buffer's end, which reads zeros without a memory access.
     const __amdgpu_buffer_rsrc_t slots = __builtin_amdgcn_make_buffer_rsrc(
         (void *)pos, (short)0, (int)((unsigned)g.C * (unsigned)(kCap * sizeof(float4))), kBufferWord3);
-    uint32_t nst[kSt];
+    float px[kCap], py[kCap], pz[kCap];
 #pragma unroll
-    for (int t = 0; t < kSt; ++t) nst[t] = pi[t] >= 0 ? min(cn[t], (uint32_t)kCap) : 0u;
-    if (__ballot(bad) == 0ull) {
-        bool any2 = false;
+    for (int q = 0; q < kCap; ++q) px[q] = py[q] = pz[q] = kFar;
+    const int n = (live && __ballot(bad) == 0ull) ? (int)min(n_raw, (uint32_t)kCap) : 0;
+    if (__ballot(n > kPrim) != 0ull) {
 #pragma unroll
-        for (int t = 0; t < kSt; ++t) any2 |= nst[t] > (uint32_t)kPrim;
-        if (__ballot(any2) != 0ull) {
+        for (int q = kPrim; q < kCap; ++q) {
+            const int off = n > q ? (int)slot_of(g.C, c, q) * (int)sizeof(float4) : kPastEnd;
+            const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(slots, off, 0, 0));
+            px[q] = v.x;
+            py[q] = v.y;
+            pz[q] = v.z;
+        }
+    }
+    if (__ballot(bad) != 0ull) {
+        // a cell above capacity: report it and leave the brick unchanged
+        if (bad) atomicOr(&ctl->errword, kErrCapacity);
+        ovm = 0u;
+    }
+    while (__ballot(ovm != 0u) != 0ull) {
+        constexpr int kB3 = 3;
+        int cel[kB3], cod[kB3];
+        uint32_t cnt3[kB3];
 #pragma unroll
-            for (int t = 0; t < kSt; ++t) {
-                const int o2 = nst[t] > 2u ? (int)slot_of(g.C, gc[t], 2) * (int)sizeof(float4) : kPastEnd;
-                const int o3 = nst[t] > 3u ? (int)slot_of(g.C, gc[t], 3) * (int)sizeof(float4) : kPastEnd;
-                v0[t] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(slots, o2, 0, 0));
-                v1[t] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(slots, o3, 0, 0));
+        for (int b = 0; b < kB3; ++b) {
+            const bool have = ovm != 0u;
+            const int t = have ? __builtin_ctz(ovm) : 0;
+            ovm &= have ? ovm - 1u : 0u;
+            int ce = gc[0], co = rc[0];
+            uint32_t nc = 0u;
+#pragma unroll
+            for (int u = 0; u < kSt; ++u) {
+                ce = t == u ? gc[u] : ce;
+                co = t == u ? rc[u] : co;
+                nc = t == u ? min(cn[u], (uint32_t)kCap) : nc;
             }
+            cel[b] = ce;
+            cod[b] = co;
+            cnt3[b] = have ? nc : 0u;   // more than kPrim whenever the step was listed
+        }
+        float4 w[kB3][kCap - kPrim];
 #pragma unroll
-            for (int t = 0; t < kSt; ++t) {
-                if (nst[t] > 2u) {
-                    const uint32_t m = min(nst[t], 4u) - 2u;
-                    const uint32_t e0 = atomicAdd(&n_ov, m);
-                    if (e0 < (uint32_t)kOvMax) {
-                        ovx[e0] = v0[t].x;
-                        ovy[e0] = v0[t].y;
-                        ovz[e0] = v0[t].z;
-                        ovr[e0] = rc[t];
-                    }
-                    if (m > 1u && e0 + 1u < (uint32_t)kOvMax) {
-                        ovx[e0 + 1] = v1[t].x;
-                        ovy[e0 + 1] = v1[t].y;
-                        ovz[e0 + 1] = v1[t].z;
-                        ovr[e0 + 1] = rc[t];
-                    }
+        for (int b = 0; b < kB3; ++b)
+#pragma unroll
+            for (int q = kPrim; q < kCap; ++q) {
+                if (q >= 4 && __ballot(cnt3[b] > (uint32_t)q) == 0ull) {
+                    w[b][q - kPrim] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    continue;
                 }
+                const int off = cnt3[b] > (uint32_t)q ? (int)slot_of(g.C, cel[b], q) * (int)sizeof(float4) : kPastEnd;
+                w[b][q - kPrim] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(slots, off, 0, 0));
             }
 #pragma unroll
-            for (int t = 0; t < kSt; ++t) {
-                if (__ballot(nst[t] > 4u) == 0ull) continue;
-                if (nst[t] > 4u) {
-                    const uint32_t m = nst[t] - 4u;
-                    const uint32_t e0 = atomicAdd(&n_ov, m);
-                    for (uint32_t q = 0; q < m; ++q) {
-                        const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
-                            slots, (int)slot_of(g.C, gc[t], 4 + (int)q) * (int)sizeof(float4), 0, 0));
-                        if (e0 + q < (uint32_t)kOvMax) {
-                            ovx[e0 + q] = v.x;
-                            ovy[e0 + q] = v.y;
-                            ovz[e0 + q] = v.z;
-                            ovr[e0 + q] = rc[t];
-                        }
+        for (int b = 0; b < kB3; ++b) {
+            if (cnt3[b] > (uint32_t)kPrim) {
+                const uint32_t m = cnt3[b] - (uint32_t)kPrim;
+                const uint32_t e0 = atomicAdd(&n_ov, m);
+#pragma unroll
+                for (int q = 0; q < kCap - kPrim; ++q) {
+                    const uint32_t e = e0 + (uint32_t)q;
+                    if ((uint32_t)q < m && e < (uint32_t)kOvMax) {
+                        ovx[e] = w[b][q].x;
+                        ovy[e] = w[b][q].y;
+                        ovz[e] = w[b][q].z;
+                        ovr[e] = cod[b];
                     }
                 }
             }
         }
-    } else {
-        // a cell above capacity: report it and leave the brick unchanged
-        if (bad) atomicOr(&ctl->errword, kErrCapacity);
-        brick_bad = 1u;
     }
     __syncthreads();
 
-    // 2. the 26 neighbour cells' staged slots, in this cell's frame
-    const int cx = 2 * ix + qx, cy = 2 * iy + qy, cz = 2 * iz + qz;
-    const int c = live ? (cz * g.m[1] + cy) * g.m[0] + cx : 0;
+    // 3. the 26 neighbour cells' staged slots, in this cell's frame
     const int rxo = 1 + 2 * lx, ryo = 1 + 2 * ly, rzo = 1 + 2 * lz;   // own region cell
     float nx[52], ny[52], nz[52];
 #pragma unroll
@@ -732,13 +739,6 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
         }
     }
     const int ro = plane_index(rxo, ryo, rzo);
-    float px[kCap], py[kCap], pz[kCap];
-    uint32_t tg[kCap];
-#pragma unroll
-    for (int q = 0; q < kCap; ++q) {
-        px[q] = py[q] = pz[q] = kFar;
-        tg[q] = 0u;
-    }
     px[0] = sx[0][ro];
     py[0] = sy[0][ro];
     pz[0] = sz[0][ro];
@@ -746,10 +746,9 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     py[1] = sy[1][ro];
     pz[1] = sz[1][ro];
     const int nlist = (int)n_ov;
-    const bool brick_ok = brick_bad == 0u;
     __syncthreads();   // the slot planes are read; their memory takes the per-lane lists
 
-    // 3. the brick's listed spheres to the lists of the lanes whose
+    // 4. the brick's listed spheres to the lists of the lanes whose
     // neighbourhood holds them (at most 8 lanes each, offsets -1, 0, +1)
     float *lst = &planes[0][0];            // [lane][k][3]
     const int lim = nlist < kOvMax ? nlist : kOvMax;
@@ -804,20 +803,9 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) kw = max(kw, __shfl_xor(kw, o, 64));
 
-    // 4. the own cell: slots 2..7 and the tags from memory
-    const uint32_t n_raw = live ? count[c] : 0u;
-    const int n = (live && brick_ok) ? (int)min(n_raw, (uint32_t)kCap) : 0;
-    constexpr bool has_tag = TAG;          // a compile-time variant: no registers without tags
-    if (__ballot(n > kPrim) != 0ull) {
+    uint32_t tg[kCap];
 #pragma unroll
-        for (int q = kPrim; q < kCap; ++q) {
-            const int off = n > q ? (int)slot_of(g.C, c, q) * (int)sizeof(float4) : kPastEnd;
-            const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(slots, off, 0, 0));
-            px[q] = v.x;
-            py[q] = v.y;
-            pz[q] = v.z;
-        }
-    }
+    for (int q = 0; q < kCap; ++q) tg[q] = 0u;
     if (has_tag) {
 #pragma unroll
         for (int q = 0; q < kCap; ++q)

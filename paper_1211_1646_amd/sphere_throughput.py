@@ -89,7 +89,9 @@ def measure(side: int = 100, eta: float = 0.45, n_moves: int = 4, delta: float =
             "trial_moves_per_sweep": trials / steps, "overlaps_after": overlaps,
             "lanes_per_cell": lanes or "library default",
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "kernel": "k_subsweep3",
+                         "frac": achieved / HBM_PEAK_GBS,
+                         "kernel": ("k_subsweep3b<false>" if lanes in (0, 1)
+                                    else "k_subsweep3<%d, false>" % lanes),
                          "kernel_avg_us": k_ms * 1e3,
                          "kernel_timing": "%d launches in one captured graph, HIP events around "
                                           "the replay on the system's stream" % ks,
