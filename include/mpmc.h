@@ -343,9 +343,13 @@ mpmc_status mpmc_tune(mpmc_handle h, int32_t window_sweeps, int32_t n_windows);
 /* Utility (performance only): launch shape of the sub-sweep: lanes
  * cooperating on one active cell (1, 2
  * or 4: the group splits the neighbour cells, their filtering and the
- * overlap tests, and combines its verdicts) and workgroup size in lanes (64,
- * 128, 192 or 256; reduced where the neighbour rows would exceed 64 KB of
- * LDS).  Results do not depend on either: every comparison is the same. */
+ * overlap tests, and combines its verdicts; 64: one wavefront per cell, one
+ * neighbourhood slot per lane, the verdicts combined by a wave ballot -- the
+ * slow mapping, kept for comparison) and workgroup size in lanes (64, 128,
+ * 192 or 256; reduced where the neighbour rows would exceed 64 KB of LDS).
+ * Results do not depend on either: every comparison is the same.  The
+ * launch shape applies to the separate sub-sweep launches, which the fused
+ * sweep replaces unless mpmc_set_sweep_kernel(h, 0). */
 mpmc_status mpmc_set_launch(mpmc_handle h, int32_t lanes_per_cell, int32_t block_size);
 
 /* Utility (performance only): how mpmc_sweep launches a sweep.  fused != 0

@@ -1246,8 +1246,8 @@ mpmc_status mpmc_tune(mpmc_handle h, int32_t window_sweeps, int32_t n_windows)
 mpmc_status mpmc_set_launch(mpmc_handle h, int32_t lanes_per_cell, int32_t block_size)
 {
     if (!h) return fail(MPMC_EINVAL, "null handle");
-    if (lanes_per_cell != 1 && lanes_per_cell != 2 && lanes_per_cell != 4)
-        return fail(MPMC_EINVAL, "lanes_per_cell must be 1, 2 or 4");
+    if (lanes_per_cell != 1 && lanes_per_cell != 2 && lanes_per_cell != 4 && lanes_per_cell != 64)
+        return fail(MPMC_EINVAL, "lanes_per_cell must be 1, 2, 4 or 64");
     if (block_size < 64 || block_size > 256 || block_size % 64)
         return fail(MPMC_EINVAL, "block size must be a multiple of 64 in [64, 256]");
     if (block_size != h->block || lanes_per_cell != h->lanes) drop_graphs(h);

@@ -500,6 +500,146 @@ k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restri
     }
 }
 
+// One wavefront per active cell (lanes_per_cell = 64): lane l < 9 CAP holds
+// slot l % CAP of neighbourhood cell l / CAP (q = 3 row + col; the own cell
+// is q = 4) in the cell's frame, and each trial is tested by every lane
+// against its own entry, the verdicts combined by a wave ballot.  The moved
+// disk's position is broadcast from the lane that holds it.  The chain is
+// k_subsweep's -- the same draws, the same visit order, the same FP32 pair
+// test and write-back order -- so the results are identical.  A wave does
+// the work of one lane of k_subsweep, so this is the slow form; it is kept
+// to measure that mapping against one lane per cell.  The cell-leaving
+// pitfalls use the one-lane kernel.
+template <int CAP, int PROP, bool ONE>
+__global__ void __launch_bounds__(256)
+k_subsweep_wave(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restrict__ count,
+                float2 *__restrict__ acc, uint32_t *__restrict__ tag, uint32_t *__restrict__ alog,
+                unsigned long long *__restrict__ cnt, int cnt_stride, int set, int ntile, int per)
+{
+    static_assert(9 * CAP <= 64, "one neighbourhood slot per lane");
+    const int tile = xcd_tile(per);
+    const int lane = (int)(threadIdx.x & 63u);
+    const long long slot = (long long)tile * (blockDim.x / 64) + (long long)(threadIdx.x / 64);
+    const int r = ONE ? 0 : chunk_replica(t, tile < ntile, slot / kActiveChunk);
+    const Rep R = ONE ? t.rep0 : t.reps[r];
+    const Geom g = R.g;
+    Ctl *ctl = t.ctls + r;
+    const unsigned long long s = ctl->sweep_at[par];
+    const uint32_t k0 = ctl->key0, k1 = ctl->key1;
+    const float delta = ctl->delta;
+    const int n_moves = R.n_moves;
+    const bool disk = PROP == 2 ? R.disk != 0 : PROP == 1;
+    const bool shuffle = PROP == 2 ? (R.ablate & kAblateParticleShuffle) == 0 : true;
+    const uint32_t s_lo = (uint32_t)s, s_hi = (uint32_t)(s >> 32);
+    int Q = set;
+    if (Q < 0) Q = (int)((ctl->draw_at[par].order >> (8 * (-1 - set))) & 0xFFu);
+    const int qx = Q & 1, qy = Q >> 1;
+    const int hx = g.mx >> 1, hy = g.my >> 1;
+    const int gid = (int)(slot - R.ab);               // the wave's cell within the replica
+    const uint32_t *const cn = count + R.cb;
+    const size_t sb = (size_t)R.cb * CAP;
+    unsigned n_trials = 0, n_acc = 0;
+    uint32_t abits = 0;
+    const bool valid = tile < ntile && gid < hx * hy;   // uniform across the wave
+    if (valid) {
+        const int iy = (int)((unsigned)gid / (unsigned)hx), ix = gid - iy * hx;
+        const int cx = 2 * ix + qx, cy = 2 * iy + qy;
+        const int c = cy * g.mx + cx;
+        const int xl = cx == 0 ? g.mx - 1 : cx - 1;
+        const int xr = cx == g.mx - 1 ? 0 : cx + 1;
+        const int yd = cy == 0 ? g.my - 1 : cy - 1;
+        const int yu = cy == g.my - 1 ? 0 : cy + 1;
+        const bool holds = lane < 9 * CAP;
+        const int q = holds ? lane / CAP : 4, i = holds ? lane % CAP : 0;
+        const int row = q / 3 == 0 ? yd : (q / 3 == 1 ? cy : yu);
+        const int col = q % 3 == 0 ? xl : (q % 3 == 1 ? cx : xr);
+        const int cc = row * g.mx + col;
+        const uint32_t rn = cn[cc];
+        const float2 v = pos[sb + (size_t)cc * CAP + (size_t)i];
+        const uint32_t n_raw = cn[c];
+        uint4 Wsh = make_uint4(0, 0, 0, 0);
+        if (shuffle) Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle, k0, k1);
+        uint4 W = make_uint4(0, 0, 0, 0);
+        if (n_moves > 0) W = philox((uint32_t)c, s_lo, s_hi, 0u, k0, k1);
+        int n = (int)n_raw;
+        if (__ballot(holds && rn > (uint32_t)g.cap) != 0ull) {
+            if (lane == 0) atomicOr((unsigned int *)&ctl->errword, kErrCapacity);
+            n = 0;
+        }
+        bool reach;
+        const float2 f = frame_of(v, q / 3, q % 3, g.wx, g.wy, reach);
+        const bool own = holds && q == 4 && i < n;        // a disk of the cell
+        const bool nbr = holds && q != 4 && i < (int)rn;  // a disk of a neighbour cell
+        if (n > 0) {
+            const size_t b0 = sb + (size_t)c * CAP;
+            const bool has_acc = acc != nullptr, has_tag = tag != nullptr;
+            float px = f.x, py = f.y, ax = 0.0f, ay = 0.0f;
+            uint32_t tg = 0u;
+            if (has_acc && own) {
+                const float2 a = acc[b0 + (size_t)i];
+                ax = a.x;
+                ay = a.y;
+            }
+            if (has_tag && own) tg = tag[b0 + (size_t)i];
+            // rng.shuffle(c.particles) as a packed permutation: list
+            // position p holds the disk of slot nibble p (the same on every lane)
+            uint32_t P = 0x76543210u;
+            const int nshuf = shuffle ? n - 1 : 0;
+            for (int k = 0; k < nshuf; ++k) {
+                if (k > 0 && (k & 3) == 0)
+                    Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle + (uint32_t)(k >> 2), k0, k1);
+                const int a = n - 1 - k;
+                const int b = (int)bounded(word_of(Wsh, k & 3), (uint32_t)(a + 1));
+                P = nib_swap(P, a, b);
+            }
+            for (int tr = 0; tr < n_moves; ++tr) {
+                if (tr > 0 && (tr & 3) == 0) W = philox((uint32_t)c, s_lo, s_hi, (uint32_t)(tr >> 2), k0, k1);
+                float dx, dy;
+                if (disk)
+                    disk_displacement(word_of(W, tr & 3), delta, dx, dy);
+                else
+                    displacement(word_of(W, tr & 3), delta, dx, dy);
+                const int p = tr % n;                                   // list position moved
+                const int L = 4 * CAP + (int)((P >> (4 * p)) & 0xFu);   // the lane holding it
+                const float xm = __shfl(px, L, 64) + dx;
+                const float ym = __shfl(py, L, 64) + dy;
+                const bool in_cell = (xm > 0.0f) & (xm <= g.wx) & (ym > 0.0f) & (ym <= g.wy);
+                const float ddx = xm - px, ddy = ym - py;
+                const float r2 = ddx * ddx + ddy * ddy;
+                const bool hit = (nbr || (own && lane != L)) && r2 < 1.0f;
+                const bool ok = in_cell && __ballot(hit) == 0ull;
+                if (tr < 32) abits |= (ok ? 1u : 0u) << tr;
+                if (ok && lane == L) {
+                    px = xm;
+                    py = ym;
+                    if (has_acc) {
+                        ax = ax + dx;
+                        ay = ay + dy;
+                    }
+                }
+                n_acc += ok ? 1u : 0u;
+            }
+            n_trials = (unsigned)n_moves;
+            // back to memory in list order: the disk of slot i goes to the
+            // list position whose nibble is i
+            if (own) {
+                int o = 0;
+#pragma unroll
+                for (int k = 0; k < CAP; ++k) o = ((P >> (4 * k)) & 0xFu) == (uint32_t)i ? k : o;
+                pos[b0 + (size_t)o] = make_float2(px, py);
+                if (has_acc) acc[b0 + (size_t)o] = make_float2(ax, ay);
+                if (has_tag && n > 1) tag[b0 + (size_t)o] = tg;
+            }
+        }
+        if (alog && lane == 0) alog[R.cb + c] = abits;
+    }
+    if (lane == 0 && valid && n_trials) {
+        const long long gr = slot / kGranule;
+        atomicAdd(&cnt[gr], (unsigned long long)n_trials);
+        atomicAdd(&cnt[cnt_stride + gr], (unsigned long long)n_acc);
+    }
+}
+
 // The sub-sweep with LPC = 2 or 4 lanes per active cell: the same chain as
 // k_subsweep, with the work that dominates a lane split across its group.
 // Each lane loads the own cell and 8 / LPC of the neighbour cells (one
@@ -1805,7 +1945,7 @@ hipError_t launch_subsweep(const Tables &t, int par, float2 *pos, const uint32_t
                            float2 *acc, uint32_t *tag, uint32_t *alog, const Work &w, int set,
                            int block, int lanes, hipStream_t st)
 {
-    if (lanes != 1 && lanes != 2 && lanes != 4) return hipErrorInvalidValue;
+    if (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 64) return hipErrorInvalidValue;
     if (t.leave) lanes = 1;   // the cell-leaving pitfalls run on the one-lane kernel only
     block = subsweep_block(t.cap, block, lanes);
     if (block < 64 || block > 256 || block % 64 || (kActiveChunk * lanes) % block)
@@ -1815,10 +1955,13 @@ hipError_t launch_subsweep(const Tables &t, int par, float2 *pos, const uint32_t
     const dim3 grid(8 * per), blk(block);
     const int e = 8 / lanes * t.cap;
     const int row = (e < kNbrLds ? e : kNbrLds) + 1;
-    const size_t lds = (size_t)row * block * sizeof(float2);
+    const size_t lds = lanes == 64 ? 0 : (size_t)row * block * sizeof(float2);
 #define MPMC_SUB1(CAP, PROP, ONE)                                                              \
     do {                                                                                       \
-        if (lanes == 1)                                                                        \
+        if (lanes == 64)                                                                       \
+            hipLaunchKernelGGL((k_subsweep_wave<CAP, PROP, ONE>), grid, blk, 0, st, t, par, pos, \
+                               count, acc, tag, alog, w.cnt, w.cnt_stride, set, ntile, per);   \
+        else if (lanes == 1)                                                                   \
             hipLaunchKernelGGL((k_subsweep<CAP, PROP, ONE>), grid, blk, lds, st, t, par, pos,    \
                                count, acc, tag, alog, w.cnt, w.cnt_stride, w.ovf, set, ntile,  \
                                per);                                                           \

@@ -160,10 +160,11 @@ def test_batch_subsweeps_and_explicit_shifts(gpu):
         assert_replica(B, r, O, "subsweeps + shifts")
 
 
-@pytest.mark.parametrize("lanes,block", [(1, 64), (1, 192), (2, 128), (4, 256)])
+@pytest.mark.parametrize("lanes,block", [(1, 64), (1, 192), (2, 128), (4, 256), (64, 256)])
 def test_batch_launch_shape_does_not_change_results(gpu, lanes, block):
     B = gpu.HardDiskBatch(configs(gpu, MIXED, seed=7))
     Os = oracles(MIXED, seed=7)
+    B.set_fused(False)
     B.set_launch(lanes, block)
     B.sweep(18)
     for r, O in enumerate(Os):

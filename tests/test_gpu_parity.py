@@ -162,17 +162,20 @@ def test_graph_path_matches_eager_path(gpu):
     assert_same(G1, O, "graph odd")
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 64])
 @pytest.mark.parametrize("block", [64, 128, 192, 256])
 def test_launch_shape_does_not_change_results(gpu, lanes, block):
+    """The separate sub-sweep launches (the fused sweep switched off) at every
+    launch shape, one wavefront per cell (64 lanes) included."""
     G, O = lattice_pair(gpu, 40, 40, 0.70, math.sqrt(2.0), delta=0.15, seed=9)
+    G.set_fused(False)
     G.set_launch(lanes, block)
     G.sweep(20)
     O.sweep(20)
     assert_same(G, O, "lanes %d block %d" % (lanes, block))
 
 
-@pytest.mark.parametrize("lanes", [2, 4])
+@pytest.mark.parametrize("lanes", [2, 4, 64])
 @pytest.mark.parametrize("nx,ny,phi,w_max", CONFIGS)
 def test_lane_groups_match_for_every_capacity(gpu, lanes, nx, ny, phi, w_max):
     """Lane groups on capacities 4-7 and n_M from 0 to 9: single sub-sweeps
@@ -187,13 +190,14 @@ def test_lane_groups_match_for_every_capacity(gpu, lanes, nx, ny, phi, w_max):
         assert_same(G, O, "lanes %d subsweep %d" % (lanes, Q))
     for n_moves in (0, 1, 6, 9):
         Gm, Om = lattice_pair(gpu, nx, ny, phi, w_max, delta=0.17, n_moves=n_moves, seed=n_moves + 2)
+        Gm.set_fused(False)
         Gm.set_launch(lanes, 64)
         Gm.sweep(17)
         Om.sweep(17)
         assert_same(Gm, Om, "lanes %d n_M %d" % (lanes, n_moves))
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 64])
 @pytest.mark.parametrize("nx,ny,phi,w_max", CONFIGS)
 def test_in_circle_moves_match(gpu, lanes, nx, ny, phi, w_max):
     """In-circle trial moves (the paper's proposal, MPMC_FLAG_DISK) on every
@@ -204,6 +208,7 @@ def test_in_circle_moves_match(gpu, lanes, nx, ny, phi, w_max):
     for n_moves, delta in ((4, 0.16), (7, 0.45)):
         G, O = lattice_pair(gpu, nx, ny, phi, w_max, delta=delta, n_moves=n_moves, seed=11,
                             flags=flags)
+        G.set_fused(False)
         G.set_launch(lanes, 128)
         G.sweep(19)
         O.sweep(19)
@@ -211,7 +216,7 @@ def test_in_circle_moves_match(gpu, lanes, nx, ny, phi, w_max):
         assert G.count_overlaps() == 0
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 64])
 @pytest.mark.parametrize("ablate", ["particle", "set", "both"])
 def test_shuffle_ablations_match(gpu, lanes, ablate):
     """The balance-test switches of Table 1 (no particle shuffle, no set
@@ -223,6 +228,7 @@ def test_shuffle_ablations_match(gpu, lanes, ablate):
         for nx, ny, phi, w_max in ((24, 24, 0.70, math.sqrt(2.0)), (20, 20, 0.72, 1.932)):
             G, O = lattice_pair(gpu, nx, ny, phi, w_max, delta=0.15, n_moves=5, seed=21,
                                 flags=FLAGS | bits | extra)
+            G.set_fused(False)
             G.set_launch(lanes, 128)
             G.sweep(17)
             O.sweep(17)
@@ -463,7 +469,7 @@ def test_paper_benchmark_largest_full_size(gpu):
     assert G.count_overlaps() == 0
 
 
-@pytest.mark.parametrize("lanes", [1, 2])
+@pytest.mark.parametrize("lanes", [1, 2, 64])
 @pytest.mark.parametrize("nx,ny,phi,w_max", [(64, 64, 0.60, 0.0), (20, 20, 0.72, 1.932)])
 def test_accept_log_matches_every_sweep(gpu, lanes, nx, ny, phi, w_max):
     """The accept/reject sequence of every cell, sweep after sweep, equals
@@ -471,6 +477,7 @@ def test_accept_log_matches_every_sweep(gpu, lanes, nx, ny, phi, w_max):
     for n_moves in (4, 9):
         G, O = lattice_pair(gpu, nx, ny, phi, w_max, delta=0.12, n_moves=n_moves, seed=5,
                             flags=FLAGS | 4)
+        G.set_fused(False)
         G.set_launch(lanes, 128)
         for k in range(12):
             G.sweep(1)
