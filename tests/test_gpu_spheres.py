@@ -29,12 +29,13 @@ def gpu():
     return pkg
 
 
-def lattice_pair(pkg, n, eta, delta=0.1, n_moves=4, seed=1, replica=0, w_max=0.0, lanes=4):
-    log("  sphere lattice pair n=%s eta=%.3f delta=%.3f n_moves=%d seed=%d lanes=%d"
-        % (n, eta, delta, n_moves, seed, lanes))
+def lattice_pair(pkg, n, eta, delta=0.1, n_moves=4, seed=1, replica=0, w_max=0.0, lanes=4,
+                 tags=True):
+    log("  sphere lattice pair n=%s eta=%.3f delta=%.3f n_moves=%d seed=%d lanes=%d tags=%d"
+        % (n, eta, delta, n_moves, seed, lanes, tags))
     cfg = pkg.SphereConfig(lattice_nx=n[0], lattice_ny=n[1], lattice_nz=n[2], eta=eta,
                            w_max=w_max, delta=delta, n_moves=n_moves, seed=seed,
-                           replica=replica, flags=pkg.FLAG_TAG)
+                           replica=replica, flags=pkg.FLAG_TAG if tags else 0)
     G = pkg.HardSphereSystem(cfg)
     G.set_launch(lanes)
     O = SphereOracle.lattice(*n, eta, w_max=w_max, delta=delta, n_moves=n_moves, seed=seed,
@@ -315,14 +316,46 @@ def test_pair_histogram_and_pressure(gpu):
     G.close()
 
 
-def test_full_size_one_million_spheres(gpu):
+def assert_same_untagged(G, O, what=""):
+    gx, gs, gsw = G.get_state()
+    ox, os_, _, osw = O.get_state()
+    assert gsw == osw, (what, gsw, osw)
+    assert np.array_equal(gs, os_), "cell lists differ " + what
+    bad = np.nonzero(gx.view(np.uint32) != ox.view(np.uint32))[0]
+    assert bad.size == 0, "positions differ %s at %s" % (what, bad[:5])
+    assert G.counters() == tuple(O.counters()), (what, G.counters(), O.counters())
+
+
+@pytest.mark.parametrize("lanes,tags", [(1, False), (1, True), (4, True)])
+def test_full_size_one_million_spheres(gpu, lanes, tags):
     """The benchmark configuration (100^3 spheres at eta = 0.45, n_M = 4),
     compared in full after three sweeps (the oracle takes about half a second
-    per sweep at this size)."""
-    G, O = lattice_pair(gpu, (100, 100, 100), 0.45, delta=0.1, n_moves=4, seed=1)
+    per sweep at this size): the brick form without and with tags (the
+    first sweeps from the lattice, whose cells of four and eight spheres
+    send lanes to the from-memory path), and the four-lane form."""
+    G, O = lattice_pair(gpu, (100, 100, 100), 0.45, delta=0.1, n_moves=4, seed=1, lanes=lanes,
+                        tags=tags)
     G.sweep(3)
     O.sweep(3)
-    assert_same(G, O, "1M spheres, 3 sweeps")
+    (assert_same if tags else assert_same_untagged)(G, O, "1M spheres, 3 sweeps")
+    G.close()
+
+
+@pytest.mark.parametrize("n,eta,delta,n_moves,sweeps", [
+    ((4, 4, 4), 0.4, 0.15, 4, 25),        # a 4^3-cell grid: one brick, its region wraps twice
+    ((4, 6, 20), 0.35, 0.12, 5, 19),      # one, one and three bricks per axis
+    ((12, 8, 16), 0.45, 0.12, 4, 37),     # ragged bricks; two captured graphs + 5 direct sweeps
+    ((50, 50, 50), 0.45, 0.1, 4, 4),      # the benchmark's spheres per cell, from the lattice
+    ((14, 14, 14), 0.5, 0.05, 9, 20)])
+def test_brick_form_without_tags(gpu, n, eta, delta, n_moves, sweeps):
+    """The default one-lane form as the benchmark runs it (no tags, no
+    accumulators: the kernel variant that carries neither), bit-exact."""
+    G, O = lattice_pair(gpu, n, eta, delta=delta, n_moves=n_moves, seed=6, lanes=1, tags=False)
+    log("  grid %s" % (G.m,))
+    G.sweep(sweeps)
+    O.sweep(sweeps)
+    assert_same_untagged(G, O, "brick, %d sweeps" % sweeps)
+    assert G.count_overlaps() == 0
     G.close()
 
 
