@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--block", type=int, default=0,
                     help="sub-sweep workgroup size; 0 = pick the shape with the autotuner")
     ap.add_argument("--lanes", type=int, default=1, help="lanes per cell when --block is given")
+    ap.add_argument("--separate", action="store_true",
+                    help="four sub-sweep launches and a rebuild per sweep instead of the fused sweep "
+                         "(the same chain; for profiling the separate kernels)")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="threads of the all-core oracle run (0 = every host core)")
     ap.add_argument("--kernel-samples", type=int, default=200,
@@ -648,6 +651,8 @@ def main():
         torch.cuda.synchronize()
         del a, b
     S = pkg.HardDiskSystem(cfg)
+    if args.separate:
+        S.set_fused(False)
     geo = S.geometry
     N, C = geo["n_particles"], geo["cells_x"] * geo["cells_y"]
 
