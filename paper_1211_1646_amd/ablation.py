@@ -45,12 +45,15 @@ def shuffle_ablation(phi: float, side: int = 256, per_case: int = 16,
                      equilibration: int = 400_000, production: int = 400_000,
                      sample_every: int = 100, blocks: int = 10, n_moves: int = 4,
                      delta: float = 0.16, in_circle: bool = True, seed: int = 1,
-                     progress=None) -> dict:
-    R = 4 * per_case
+                     cases=(0, 1, 2, 3), progress=None) -> dict:
+    """`cases` picks rows of CASES (the first is the reference of the z
+    scores; Table 1's reference is both shuffles on, case 0)."""
+    K = len(cases)
+    R = K * per_case
     disk = FLAG_DISK if in_circle else 0
     cfgs = [SystemConfig(lattice_nx=side, lattice_ny=side, phi=phi, w_min=1.0,
                          w_max=math.sqrt(2.0), delta=delta, n_moves=n_moves, seed=seed,
-                         replica=r, flags=CASES[r % 4][2] | disk) for r in range(R)]
+                         replica=r, flags=CASES[cases[r % K]][2] | disk) for r in range(R)]
     B = HardDiskBatch(cfgs)
     t0 = time.time()
     chunk = 50_000
@@ -82,13 +85,14 @@ def shuffle_ablation(phi: float, side: int = 256, per_case: int = 16,
            "equilibration_sweeps": equilibration, "production_sweeps": production,
            "proposal": "in-circle" if in_circle else "square", "delta": delta,
            "n_moves": n_moves, "seconds": time.time() - t0, "cases": []}
-    for i, (ps, cs, _) in enumerate(CASES):
-        v = per_replica[i::4]
+    for i, ci in enumerate(cases):
+        ps, cs, _ = CASES[ci]
+        v = per_replica[i::K]
         case = {"particle_shuffle": ps, "set_shuffle": cs, "P": float(v.mean()),
                 "P_se": float(v.std(ddof=1) / math.sqrt(len(v))),
-                "acceptance": float(ac[i::4].sum() / max(tr[i::4].sum(), 1))}
+                "acceptance": float(ac[i::K].sum() / max(tr[i::K].sum(), 1))}
         if key in PAPER_TABLE1:
-            case["paper_P"] = PAPER_TABLE1[key][i]
+            case["paper_P"] = PAPER_TABLE1[key][ci]
         out["cases"].append(case)
     ref = out["cases"][0]
     for c in out["cases"][1:]:
@@ -212,6 +216,9 @@ def main():
     ap.add_argument("--leave", action="store_true",
                     help="the cell-leaving pitfalls against the plain chain instead of the shuffles")
     ap.add_argument("--deltas", type=float, nargs="+", default=[0.08, 0.16])
+    ap.add_argument("--cases", type=int, nargs="+", default=[0, 1, 2, 3],
+                    help="rows of Table 1 to run (0: both shuffles, 1: no set shuffle, 2: no "
+                         "particle shuffle, 3: neither); the first is the z reference")
     a = ap.parse_args()
     if a.leave:
         for phi in a.phi:
@@ -223,6 +230,7 @@ def main():
     for phi in a.phi:
         r = shuffle_ablation(phi, a.side, a.per_case, a.equilibration, a.production,
                              a.sample_every, a.blocks, in_circle=not a.square, seed=a.seed,
+                             cases=tuple(a.cases),
                              progress=lambda m: print("[ablation] " + m, flush=True))
         print(json.dumps(r), flush=True)
 
