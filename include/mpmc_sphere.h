@@ -196,10 +196,12 @@ mpmc_status mpmc_sphere_pressure(mpmc_sphere_handle h, double *p_star, double *g
 mpmc_status mpmc_sphere_count_overlaps(mpmc_sphere_handle h, int64_t *pairs);
 
 /* Utility (performance only): launch shape of the sub-sweep: 1, 2 or 4
- * lanes per active cell (default 1).  The lanes of a group split the 26 neighbour cells and their overlap
- * tests and combine their verdicts; every comparison is the same, so the
- * results do not depend on it (sync: waits for the stream, drops the sweep
- * graphs). */
+ * lanes per active cell (default 1).  With one lane per cell a workgroup
+ * stages a brick of 4 x 4 x 4 active cells and their neighbours in LDS (the
+ * per-lane form when accumulators are on); with 2 or 4 the lanes of a group
+ * split the 26 neighbour cells and their overlap tests and combine their
+ * verdicts.  Every comparison is the same, so the results do not depend on
+ * it (sync: waits for the stream, drops the sweep graphs). */
 mpmc_status mpmc_sphere_set_launch(mpmc_sphere_handle h, int32_t lanes_per_cell);
 
 /* Utility, not in the paper (diffusion measure): displacement accumulators
