@@ -95,7 +95,9 @@ typedef struct mpmc_sphere_geometry {
  * needs the reported size.  On the device the spheres sit in fixed slots,
  * MPMC_SPHERE_CAPACITY per cell, as float4 (x, y, z, 0), with a uint32
  * count per cell: slots 0..1 of cell c in its 32-byte primary line, slots
- * 2..7 in an overflow region after all primary lines. */
+ * 2..7 in an overflow region after all primary lines.  The fourth word of
+ * slot 0 repeats the cell's count (its bits), so that the sub-sweep reads a
+ * cell's count and first two spheres from one line. */
 typedef struct mpmc_sphere_buffer_sizes {
     size_t pos;   /* float4 per slot (cells x 8)                 */
     size_t count; /* uint32 per cell                             */

@@ -46,6 +46,14 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kGraphSweeps = 16;   // sweeps per captured graph (even)
 constexpr int kDefaultLanes = 1;   // sub-sweep lanes per active cell
 
+// The bits of a uint32 as a float (slot 0's fourth word carries the count).
+float u32_as_float(uint32_t u)
+{
+    float f;
+    std::memcpy(&f, &u, sizeof f);
+    return f;
+}
+
 mpmc_status fail(mpmc_status st, const std::string &msg)
 {
     mpmc::set_last_error(msg.c_str());
@@ -266,7 +274,8 @@ mpmc_status upload(mpmc_sphere *h, const float *xyz, const uint32_t *start, uint
         cnt[(size_t)c] = n;
         for (uint32_t i = 0; i < n; ++i) {
             const size_t k = mpmc::sph::slot_of(g.C, c, (int)i), src = (size_t)(b + i);
-            slots[k] = make_float4(xyz[3 * src], xyz[3 * src + 1], xyz[3 * src + 2], 0.0f);
+            slots[k] = make_float4(xyz[3 * src], xyz[3 * src + 1], xyz[3 * src + 2],
+                                   i == 0 ? u32_as_float(n) : 0.0f);
             if (!tg.empty()) tg[k] = tags ? tags[src] : (uint32_t)src;
         }
     }

@@ -10,7 +10,9 @@
 //   pos[8 C]    float4 (x, y, z, 0) cell-local coordinates in (0, w], slots
 //               [0, count) used: slots 0..1 of cell c in its 32-byte primary
 //               line at 2 c, slots 2..7 in an overflow region at 2 C + 6 c
-//               (slot_of);
+//               (slot_of).  The fourth word of slot 0 holds the bits of the
+//               cell's count, also when the cell is empty, so that one
+//               32-byte line gives a cell's count and first two spheres;
 //   tag[8 C]    uint32 identity of each sphere (optional), same slots;
 //   acc[8 C]    float4 displacement accumulated by accepted moves (optional),
 //               same slots.
@@ -499,8 +501,8 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
                 if (q < n) {
                     int o = q + r0;
                     o = o >= n ? o - n : o;
-                    const size_t so = slot_of(g.C, c, o);
-                    pos[so] = make_float4(px[q], py[q], pz[q], 0.0f);
+                    const size_t so = slot_of(g.C, c, o);   // slot 0 carries the count
+                    pos[so] = make_float4(px[q], py[q], pz[q], o == 0 ? __uint_as_float((uint32_t)n) : 0.0f);
                     if (has_tag && n > 1) tag[so] = tg[q];
                     if (has_acc) acc[so] = make_float4(ax[q], ay[q], az[q], 0.0f);
                 }
@@ -521,17 +523,18 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
 // lanes serves a brick of kBk^3 active cells of set Q; lane (lx, ly, lz)
 // owns active cell (kBk bx + lx, ...).  The brick's region -- its cells and
 // all their neighbours, kRg^3 cells with periodic indices -- is staged into
-// LDS by coalesced loads that are all independent: per cell slots 0 and 1
-// (a far sphere where empty), in eight parity planes so that the lanes of a
-// wave, reading the same neighbour offset, read consecutive words.  Spheres
-// in slots 2..7, which only cells with more than two spheres have, go to a
-// list of the brick, and from there to per-lane lists of the lanes whose
-// neighbourhood holds them.  Each lane then holds the 52 staged slots of its
-// 26 neighbour cells and its listed spheres in registers, translated into
-// its frame (exactly -w, 0 or +w per axis), and runs its trials against all
-// of them: no reach filter, no per-lane compaction, and no memory round
-// trip that depends on another beyond the overflow slots.  A lane with more
-// listed spheres than it holds, or a brick whose list overflows, tests every
+// LDS by coalesced loads that are all independent: the primary line of
+// every cell (slots 0 and 1, the count in slot 0's fourth word), three
+// rows of the region per load, and written out as one word per coordinate
+// and slot (a far sphere where the slot is empty).  Spheres in slots 2..7,
+// which only cells with more than two spheres have, go to a list of the
+// brick, and from there to per-lane lists of the lanes whose neighbourhood
+// holds them.  Each lane then holds the 52 staged slots of its 26 neighbour
+// cells and its listed spheres in registers, translated into its frame
+// (exactly -w, 0 or +w per axis), and runs its trials against all of them:
+// no reach filter, no per-lane compaction, and no memory round trip that
+// depends on another beyond the overflow slots.  A lane with more listed
+// spheres than it holds, or a brick whose list overflows, tests every
 // neighbour straight from memory instead (overlap_from_memory).  Every pair
 // is tested with the same FP32 operations as in the other forms, and a far
 // sphere never overlaps, so the decisions are the same.
@@ -541,15 +544,15 @@ constexpr int kRgC = kRg * kRg * kRg;      // region cells
 constexpr int kOvMax = 128;                // listed spheres per brick
 constexpr int kOvLane = 8;                 // listed spheres a lane holds
 
-// Parity plane of region coordinate r along one axis: class r & 1 holds
-// 5 - (r & 1) cells, index r >> 1.  Plane (px, py, pz) starts at
-// kPlaneBase[px + 2 py + 4 pz].
-constexpr int plane_size(int c) { return (5 - (c & 1)) * (5 - ((c >> 1) & 1)) * (5 - (c >> 2)); }
-constexpr int plane_base(int c) { return c == 0 ? 0 : plane_base(c - 1) + plane_size(c - 1); }
-__device__ __forceinline__ constexpr int plane_index(int rx, int ry, int rz)
+// LDS index of region cell (rx, ry, rz): per axis the even coordinates
+// 0, 2, .., 8 come first (0..4), then the odd ones (5..8).  A lane's own
+// cell has odd coordinates 2 l + 1 and its neighbours at offset -1 / +1
+// have even ones 2 l / 2 l + 2, so the lanes of a wave, reading the same
+// neighbour offset, read runs of consecutive words.
+__device__ __forceinline__ constexpr int reg_axis(int r) { return (r >> 1) + 5 * (r & 1); }
+__device__ __forceinline__ constexpr int reg_index(int rx, int ry, int rz)
 {
-    return plane_base((rx & 1) | ((ry & 1) << 1) | ((rz & 1) << 2)) + (rx >> 1) +
-           (5 - (rx & 1)) * ((ry >> 1) + (5 - (ry & 1)) * (rz >> 1));
+    return reg_axis(rx) + kRg * (reg_axis(ry) + kRg * reg_axis(rz));
 }
 
 template <bool TAG>
@@ -595,53 +598,54 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     const int c = live ? (cz * g.m[1] + cy) * g.m[0] + cx : 0;
     constexpr bool has_tag = TAG;          // a compile-time variant: no registers without tags
 
-    // 1. stage the region, plane by plane, with the own count and tags; every
-    // load of this pass is independent of the others
-    constexpr int kSt = 15;                // staging steps per lane (planes of 125..64 cells)
+    // 1. stage the region, three rows of kRg cells (kRg x 2 slots) per
+    // step: lane l < 54 takes row j = l / 18 of the step's three and slot
+    // l & 1 of region cell (l % 18) / 2, so a wave's load reads three runs of
+    // consecutive 16-byte slots and each cache line once.  Lanes 54..63
+    // repeat the loads of lanes 36..45 and write nothing.  Step t covers
+    // rows ry = 3 (t % 3) + j, rz = t / 3.  Every load of this pass is
+    // independent of the others.
+    constexpr int kSt = kRg * kRg / 3;      // 27 steps
+    const bool stg = lane < 54;
+    const int ls = stg ? lane : lane - 18;
+    const int jr = ls / 18, hs = ls & 1, rxs = (ls % 18) >> 1;
+    const int gx = wrapc(ox0 + rxs, g.m[0]);
+    int gy3[3], li3[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        gy3[a] = wrapc(oy0 + 3 * a + jr, g.m[1]);
+        li3[a] = reg_axis(rxs) + kRg * reg_axis(3 * a + jr);
+    }
     uint32_t cn[kSt];
-    int gc[kSt], pi[kSt], rc[kSt];
-    float4 v0[kSt], v1[kSt];
-    {
-        int t = 0;
+    float4 v[kSt];
 #pragma unroll
-        for (int cl = 0; cl < 8; ++cl) {
-            const int px = cl & 1, py = (cl >> 1) & 1, pz = cl >> 2;
-            const int nx = 5 - px, ny = 5 - py, nzc = 5 - pz;
-            const int size = nx * ny * nzc;
+    for (int t = 0; t < kSt; ++t) {
+        const int gz = wrapc(oz0 + t / 3, g.m[2]);
+        const int cell = (gz * g.m[1] + gy3[t % 3]) * g.m[0] + gx;
+        v[t] = pos[(size_t)cell * kPrim + hs];
+    }
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                if (u * 64 >= size) continue;
-                const int idx = u * 64 + lane;
-                const int id = idx < size ? idx : size - 1;
-                const int i = id % nx, j = (id / nx) % ny, k = id / (nx * ny);
-                const int rx = 2 * i + px, ry = 2 * j + py, rz = 2 * k + pz;
-                const int cell = (wrapc(oz0 + rz, g.m[2]) * g.m[1] + wrapc(oy0 + ry, g.m[1])) * g.m[0] +
-                                 wrapc(ox0 + rx, g.m[0]);
-                gc[t] = cell;
-                pi[t] = idx < size ? plane_base(cl) + id : -1;
-                rc[t] = rx | (ry << 4) | (rz << 8);
-                cn[t] = count[cell];
-                v0[t] = pos[(size_t)cell * kPrim];
-                v1[t] = pos[(size_t)cell * kPrim + 1];
-                ++t;
-            }
-        }
+    for (int t = 0; t < kSt; ++t) {
+        // slot 0's fourth word is the cell's count; lane pairs (2 i, 2 i + 1)
+        // hold slots 0 and 1 of one cell
+        const uint32_t w0 = __float_as_uint(v[t].w);
+        const uint32_t w1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w0, 0xB1, 0xF, 0xF, false);
+        cn[t] = hs == 0 ? w0 : w1;
     }
     const uint32_t n_raw = live ? count[c] : 0u;
     bool bad = n_raw > (uint32_t)kCap;
     uint32_t ovm = 0u;                     // staging steps whose cell has more than kPrim spheres
+    if (stg) {
 #pragma unroll
-    for (int t = 0; t < kSt; ++t) {
-        if (pi[t] >= 0) {
+        for (int t = 0; t < kSt; ++t) {
             const uint32_t n = cn[t];
+            const int li = li3[t % 3] + kRg * kRg * reg_axis(t / 3);
             bad |= n > (uint32_t)kCap;
-            ovm |= n > (uint32_t)kPrim ? 1u << t : 0u;
-            sx[0][pi[t]] = n > 0 ? v0[t].x : kFar;
-            sy[0][pi[t]] = n > 0 ? v0[t].y : kFar;
-            sz[0][pi[t]] = n > 0 ? v0[t].z : kFar;
-            sx[1][pi[t]] = n > 1 ? v1[t].x : kFar;
-            sy[1][pi[t]] = n > 1 ? v1[t].y : kFar;
-            sz[1][pi[t]] = n > 1 ? v1[t].z : kFar;
+            ovm |= (hs == 0 && n > (uint32_t)kPrim) ? 1u << t : 0u;
+            const bool have = n > (uint32_t)hs;
+            sx[hs][li] = have ? v[t].x : kFar;
+            sy[hs][li] = have ? v[t].y : kFar;
+            sz[hs][li] = have ? v[t].z : kFar;
         }
     }
     // 2. slots 2..7: of the staged cells that have them, to the brick's list,
@@ -679,16 +683,12 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
             const bool have = ovm != 0u;
             const int t = have ? __builtin_ctz(ovm) : 0;
             ovm &= have ? ovm - 1u : 0u;
-            int ce = gc[0], co = rc[0];
             uint32_t nc = 0u;
 #pragma unroll
-            for (int u = 0; u < kSt; ++u) {
-                ce = t == u ? gc[u] : ce;
-                co = t == u ? rc[u] : co;
-                nc = t == u ? min(cn[u], (uint32_t)kCap) : nc;
-            }
-            cel[b] = ce;
-            cod[b] = co;
+            for (int u = 0; u < kSt; ++u) nc = t == u ? min(cn[u], (uint32_t)kCap) : nc;
+            const int rz = t / 3, ry = 3 * (t - 3 * rz) + jr;
+            cel[b] = (wrapc(oz0 + rz, g.m[2]) * g.m[1] + wrapc(oy0 + ry, g.m[1])) * g.m[0] + gx;
+            cod[b] = rxs | (ry << 4) | (rz << 8);
             cnt3[b] = have ? nc : 0u;   // more than kPrim whenever the step was listed
         }
         float4 w[kB3][kCap - kPrim];
@@ -730,7 +730,7 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     for (int j = 0; j < 26; ++j) {
         const int q = j < 13 ? j : j + 1;
         const int ox = q % 3 - 1, oy = (q / 3) % 3 - 1, oz = q / 9 - 1;
-        const int rn = plane_index(rxo + ox, ryo + oy, rzo + oz);
+        const int rn = reg_index(rxo + ox, ryo + oy, rzo + oz);
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             nx[2 * j + u] = frame(sx[u][rn], ox, g.w[0]);
@@ -738,7 +738,7 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
             nz[2 * j + u] = frame(sz[u][rn], oz, g.w[2]);
         }
     }
-    const int ro = plane_index(rxo, ryo, rzo);
+    const int ro = reg_index(rxo, ryo, rzo);
     px[0] = sx[0][ro];
     py[0] = sy[0][ro];
     pz[0] = sz[0][ro];
@@ -886,8 +886,8 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
             if (q < n) {
                 int o = q + r0;
                 o = o >= n ? o - n : o;
-                const size_t so = slot_of(g.C, c, o);
-                pos[so] = make_float4(px[q], py[q], pz[q], 0.0f);
+                const size_t so = slot_of(g.C, c, o);   // slot 0 carries the count
+                pos[so] = make_float4(px[q], py[q], pz[q], o == 0 ? __uint_as_float((uint32_t)n) : 0.0f);
                 if (has_tag && n > 1) tag[so] = tg[q];
             }
         }
@@ -938,8 +938,10 @@ __global__ void __launch_bounds__(256) k_fold3(Ctl3 *ctl, unsigned long long *cn
 // ----------------------------------------------------------------- rebin
 // Alg. 4 in d = 3 on the slot layout: new cell c holds the stayers of old c
 // followed by the spheres of the old neighbour in direction f that move in,
-// both in old slot order.  One thread per cell; the counts and all 8 slots
-// of both cells are loaded in one round trip.  The first workgroup writes
+// both in old slot order.  One thread per cell; the counts and the primary
+// lines of both cells are loaded in one round trip, the overflow slots only
+// where a count needs them.  Slot 0 of every new cell is written, with the
+// new count in its fourth word.  The first workgroup writes
 // the sweep slot of the half it writes: the next sweep and its draws when
 // the shift is the sweep's own, else a copy of the current slot.
 struct Rebin3Args {
@@ -1025,7 +1027,9 @@ __global__ void __launch_bounds__(kTile) k_rebin3(Rebin3Args a)
         }
         const unsigned k = (unsigned)(__popc(stay) + __popc(leave));
         if (k > (unsigned)kCap) atomicOr(&ctl->errword, kErrCapacity);
-        a.count_out[c] = k > (unsigned)kCap ? (unsigned)kCap : k;
+        const unsigned kc = k > (unsigned)kCap ? (unsigned)kCap : k;
+        a.count_out[c] = kc;
+        if (kc == 0u) a.pos_out[slot_of(g.C, c, 0)] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         const bool has_tag = a.tag != nullptr;
         int o = 0;   // next slot of the new list (never past the cell's 8)
 #pragma unroll
@@ -1035,7 +1039,7 @@ __global__ void __launch_bounds__(kTile) k_rebin3(Rebin3Args a)
                 if (ax == 0) v.x = to[i];
                 else if (ax == 1) v.y = to[i];
                 else v.z = to[i];
-                v.w = 0.0f;
+                v.w = o == 0 ? __uint_as_float(kc) : 0.0f;
                 a.pos_out[slot_of(g.C, c, o)] = v;
                 if (has_tag) a.tag_out[slot_of(g.C, c, o)] = a.tag[slot_of(g.C, c, i)];
                 if (a.acc) a.acc_out[slot_of(g.C, c, o)] = a.acc[slot_of(g.C, c, i)];
@@ -1050,7 +1054,7 @@ __global__ void __launch_bounds__(kTile) k_rebin3(Rebin3Args a)
                 if (ax == 0) v.x = t2;
                 else if (ax == 1) v.y = t2;
                 else v.z = t2;
-                v.w = 0.0f;
+                v.w = o == 0 ? __uint_as_float(kc) : 0.0f;
                 a.pos_out[slot_of(g.C, c, o)] = v;
                 if (has_tag) a.tag_out[slot_of(g.C, c, o)] = a.tag[slot_of(g.C, nc, i)];
                 if (a.acc) a.acc_out[slot_of(g.C, c, o)] = a.acc[slot_of(g.C, nc, i)];
