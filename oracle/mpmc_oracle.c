@@ -456,7 +456,9 @@ static void swap_slots(oracle_sys *S, int a, int b)
  * 3x3 neighbourhood other than slot `self` of the cell itself?  A neighbour
  * at offset (ox, oy) is seen at (x + ox*wx, y + oy*wy); the translation is
  * one of -w, 0, +w exactly (Sec. 3.1).  Overlap iff r^2 < sigma^2 = 1
- * (Alg. 2); touching disks are allowed. */
+ * (Alg. 2); touching disks are allowed.  The paper fixes no rounding for
+ * r^2; the chain takes ddx*ddx rounded, plus ddy*ddy by one fused
+ * multiply-add (fmaf rounds once). */
 static int overlaps(const oracle_sys *S, int cx, int cy, int self, float xm, float ym)
 {
     for (int oy = -1; oy <= 1; ++oy) {
@@ -474,7 +476,7 @@ static int overlaps(const oracle_sys *S, int cx, int cy, int self, float xm, flo
                 float py = S->disk_y[slot] + ty;
                 float ddx = xm - px;
                 float ddy = ym - py;
-                float r2 = ddx * ddx + ddy * ddy;
+                float r2 = fmaf(ddy, ddy, ddx * ddx);
                 if (r2 < 1.0f) return 1;
             }
         }

@@ -29,7 +29,9 @@
  *      +x, -x, +y, -y, +z, -z; d = u24 of the first word of block (...,
  *      0x80000002) times w_f / 2.  Sub-sweeps in order, then the shift.
  *   S7 trial: as in 2D with three coordinates; the overlap test is
- *      r2 = (ddx*ddx + ddy*ddy) + ddz*ddz < 1 over the 27 cells.
+ *      r2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx*ddx)) < 1 over the 27 cells
+ *      (ddx*ddx rounded, each further square added by one fused
+ *      multiply-add).
  *   S8 shift: as in 2D along the axis of f.
  *   S9 pair histogram: ordered pairs within reach, r^2 bins on FP32 edges
  *      (1 + b 1e-4)^2 computed in FP64.
@@ -249,7 +251,7 @@ static int overlaps(const sphere_sys *S, const int cc[3], int self, const float 
                     const float ddx = xm[0] - (p[0] + tr[0]);
                     const float ddy = xm[1] - (p[1] + tr[1]);
                     const float ddz = xm[2] - (p[2] + tr[2]);
-                    const float r2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
+                    const float r2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
                     if (r2 < 1.0f) return 1;
                 }
             }

@@ -1,7 +1,8 @@
 // Device helpers shared by the hard-disk (mpmc_kernels.hip) and hard-sphere
 // (sphere_kernels.hip) kernels: the counter-based random numbers, per-lane
 // register arrays indexed only at compile time, the XCD-aware workgroup
-// order, a wave reduction and the votes of a lane group.  Not part of the public ABI.
+// order, a wave reduction, the votes of a lane group and the pair distance of
+// the overlap test.  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,6 +39,15 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
 __device__ __forceinline__ uint32_t word_of(const uint4 &v, int i)
 {
     return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+
+// The chain's squared pair distance (the overlap test of Alg. 2 is
+// r^2 < 1): dx*dx rounded, each further square added by one fused
+// multiply-add, as the CPU oracle evaluates it.
+__device__ __forceinline__ float pair_r2(float dx, float dy) { return __builtin_fmaf(dy, dy, dx * dx); }
+__device__ __forceinline__ float pair_r2(float dx, float dy, float dz)
+{
+    return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
 }
 
 // Uniform integer in [0, k): high word of the 64-bit product v * k.

@@ -219,8 +219,7 @@ __device__ __forceinline__ float min_r2(float xm, float ym, const float2 *e)
     const float d1x = xm - e1.x, d1y = ym - e1.y;
     const float d2x = xm - e2.x, d2y = ym - e2.y;
     const float d3x = xm - e3.x, d3y = ym - e3.y;
-    return fminf(fminf(d0x * d0x + d0y * d0y, d1x * d1x + d1y * d1y),
-                 fminf(d2x * d2x + d2y * d2y, d3x * d3x + d3y * d3y));
+    return fminf(fminf(pair_r2(d0x, d0y), pair_r2(d1x, d1y)), fminf(pair_r2(d2x, d2y), pair_r2(d3x, d3y)));
 }
 
 template <int CAP, int PROP, bool ONE>
@@ -442,7 +441,7 @@ k_subsweep(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__restri
                 for (int q = 1; q < CAP; ++q) {
                     const float ddx = xm - px[q];
                     const float ddy = ym - py[q];
-                    const float r2 = ddx * ddx + ddy * ddy;
+                    const float r2 = pair_r2(ddx, ddy);
                     ok = ok & !(r2 < 1.0f);
                 }
                 // neighbours four at a time, up to the wave's group count
@@ -605,7 +604,7 @@ k_subsweep_wave(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__r
                 const float ym = __shfl(py, L, 64) + dy;
                 const bool in_cell = (xm > 0.0f) & (xm <= g.wx) & (ym > 0.0f) & (ym <= g.wy);
                 const float ddx = xm - px, ddy = ym - py;
-                const float r2 = ddx * ddx + ddy * ddy;
+                const float r2 = pair_r2(ddx, ddy);
                 const bool hit = (nbr || (own && lane != L)) && r2 < 1.0f;
                 const bool ok = in_cell && __ballot(hit) == 0ull;
                 if (tr < 32) abits |= (ok ? 1u : 0u) << tr;
@@ -842,7 +841,7 @@ k_subsweep_mc(Tables t, int par, float2 *__restrict__ pos, const uint32_t *__res
                         if (q < n) {
                             const float ddx = xm - px[q];
                             const float ddy = ym - py[q];
-                            const float r2 = ddx * ddx + ddy * ddy;
+                            const float r2 = pair_r2(ddx, ddy);
                             ok = ok && !(r2 < 1.0f);
                         }
                     }
@@ -1333,7 +1332,7 @@ __device__ __forceinline__ void fused_cell_update(const FRegion<CAP, TILE, ACC, 
         for (int q = 1; q < CAP; ++q) {
             const float ddx = xm - px[q];
             const float ddy = ym - py[q];
-            const float r2 = ddx * ddx + ddy * ddy;
+            const float r2 = pair_r2(ddx, ddy);
             ok = ok & !(r2 < 1.0f);
         }
 #pragma unroll
@@ -1342,8 +1341,8 @@ __device__ __forceinline__ void fused_cell_update(const FRegion<CAP, TILE, ACC, 
             const float d1x = xm - nx[e + 1], d1y = ym - ny[e + 1];
             const float d2x = xm - nx[e + 2], d2y = ym - ny[e + 2];
             const float d3x = xm - nx[e + 3], d3y = ym - ny[e + 3];
-            const float m = fminf(fminf(d0x * d0x + d0y * d0y, d1x * d1x + d1y * d1y),
-                                  fminf(d2x * d2x + d2y * d2y, d3x * d3x + d3y * d3y));
+            const float m = fminf(fminf(pair_r2(d0x, d0y), pair_r2(d1x, d1y)),
+                                  fminf(pair_r2(d2x, d2y), pair_r2(d3x, d3y)));
             ok = ok & !(m < 1.0f);
         }
         if (tr < 32) abits |= (ok ? 1u : 0u) << tr;

@@ -140,7 +140,7 @@ __device__ __forceinline__ float min_r2_4(float xm, float ym, float zm, const fl
         const float dx = xm - ex[e];
         const float dy = ym - ey[e];
         const float dz = zm - ez[e];
-        m = fminf(m, (dx * dx + dy * dy) + dz * dz);
+        m = fminf(m, pair_r2(dx, dy, dz));
     }
     return m;
 }
@@ -177,7 +177,7 @@ __device__ bool overlap_from_memory(const Geom3 &g, const float4 *__restrict__ p
             const float dx = xm - frame(v.x, ox, g.w[0]);
             const float dy = ym - frame(v.y, oy, g.w[1]);
             const float dz = zm - frame(v.z, oz, g.w[2]);
-            hit |= (dx * dx + dy * dy) + dz * dz < 1.0f;
+            hit |= pair_r2(dx, dy, dz) < 1.0f;
         }
     }
     return hit;
@@ -466,7 +466,7 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
                 const float ddx = xm - px[q];
                 const float ddy = ym - py[q];
                 const float ddz = zm - pz[q];
-                ok = ok & !((ddx * ddx + ddy * ddy) + ddz * ddz < 1.0f);
+                ok = ok & !(pair_r2(ddx, ddy, ddz) < 1.0f);
             }
 #pragma unroll
             for (int k = 0; k < kL; k += 4)
@@ -860,7 +860,7 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
                 const float ddx = xm - px[q];
                 const float ddy = ym - py[q];
                 const float ddz = zm - pz[q];
-                ok = ok & !((ddx * ddx + ddy * ddy) + ddz * ddz < 1.0f);
+                ok = ok & !(pair_r2(ddx, ddy, ddz) < 1.0f);
             }
 #pragma unroll
             for (int k = 0; k < 52; k += 4)
