@@ -526,23 +526,25 @@ k_subsweep3(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
 // LDS by coalesced loads that are all independent: the primary line of
 // every cell (slots 0 and 1, the count in slot 0's fourth word), three
 // rows of the region per load, and written out as one word per coordinate
-// and slot (a far sphere where the slot is empty).  Spheres in slots 2..7,
-// which only cells with more than two spheres have, go to a list of the
-// brick, and from there to per-lane lists of the lanes whose neighbourhood
-// holds them.  Each lane then holds the 52 staged slots of its 26 neighbour
-// cells and its listed spheres in registers, translated into its frame
-// (exactly -w, 0 or +w per axis), and runs its trials against all of them:
-// no reach filter, no per-lane compaction, and no memory round trip that
-// depends on another beyond the overflow slots.  A lane with more listed
-// spheres than it holds, or a brick whose list overflows, tests every
-// neighbour straight from memory instead (overlap_from_memory).  Every pair
-// is tested with the same FP32 operations as in the other forms, and a far
-// sphere never overlaps, so the decisions are the same.
+// and slot (a far sphere where the slot is empty).  The region's cells with
+// more than two spheres are compacted into a list of the brick, one entry
+// per cell; each lane loads the slots 2..7 of one entry in a single round
+// trip, issued before the lane fills its registers from LDS so that the
+// two overlap, and hands them to the lists of the lanes whose
+// neighbourhood holds that cell.  Each lane then holds the 52 staged slots
+// of its 26 neighbour cells and its listed spheres in registers, translated
+// into its frame (exactly -w, 0 or +w per axis), and runs its trials
+// against all of them: no reach filter and no per-lane compaction.  A lane
+// with more listed spheres than it holds, or a brick with more such cells
+// than its list holds, tests every neighbour straight from memory instead
+// (overlap_from_memory).  Every pair is tested with the same FP32
+// operations as in the other forms, and a far sphere never overlaps, so the
+// decisions are the same.
 constexpr int kBk = 4;                     // active cells per brick side
 constexpr int kRg = 2 * kBk + 1;           // region side, cells
 constexpr int kRgC = kRg * kRg * kRg;      // region cells
-constexpr int kOvMax = 128;                // listed spheres per brick
 constexpr int kOvLane = 8;                 // listed spheres a lane holds
+constexpr int kOvCell = 128;               // listed cells with more than two spheres per brick
 
 // LDS index of region cell (rx, ry, rz): per axis the even coordinates
 // 0, 2, .., 8 come first (0..4), then the odd ones (5..8).  A lane's own
@@ -555,6 +557,13 @@ __device__ __forceinline__ constexpr int reg_index(int rx, int ry, int rz)
     return reg_axis(rx) + kRg * (reg_axis(ry) + kRg * reg_axis(rz));
 }
 
+// x, y, z of the slot at byte offset off (a raw buffer load of 12 bytes).
+__device__ __forceinline__ float3 slot_xyz(__amdgpu_buffer_rsrc_t r, int off)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, 0);
+    return make_float3(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]));
+}
+
 template <bool TAG>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
@@ -565,10 +574,9 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     // are filled the same memory holds the per-lane lists [lane][k] (x, y, z)
     __shared__ float planes[6][kRgC];
     float(*sx)[kRgC] = planes, (*sy)[kRgC] = planes + 2, (*sz)[kRgC] = planes + 4;
-    __shared__ float ovx[kOvMax], ovy[kOvMax], ovz[kOvMax];
-    __shared__ int ovr[kOvMax];            // region coordinates rx | ry << 4 | rz << 8
     __shared__ uint32_t ov_lane[64];       // listed spheres per lane
-    __shared__ uint32_t n_ov;
+    __shared__ int oc_cell[kOvCell];       // the region's cells with more than kPrim spheres
+    __shared__ int oc_cn[kOvCell];         // their region code | count << 12
     static_assert(64 * kOvLane * 3 <= 6 * kRgC, "per-lane lists fit the slot planes");
     const int brick = xcd_tile(per);
     if (brick >= nbrick) return;           // a padding workgroup of the XCD-aligned grid
@@ -593,7 +601,6 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
         return v >= m ? v - m : v;
     };
     ov_lane[lane] = 0u;
-    if (lane == 0) n_ov = 0u;
     const int cx = 2 * ix + qx, cy = 2 * iy + qy, cz = 2 * iz + qz;
     const int c = live ? (cz * g.m[1] + cy) * g.m[0] + cx : 0;
     constexpr bool has_tag = TAG;          // a compile-time variant: no registers without tags
@@ -624,6 +631,10 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
         const int cell = (gz * g.m[1] + gy3[t % 3]) * g.m[0] + gx;
         v[t] = pos[(size_t)cell * kPrim + hs];
     }
+    // the cell's first random blocks, while the staging loads are in flight
+    uint4 Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle, k0, k1);
+    uint4 W = make_uint4(0, 0, 0, 0);
+    if (g.n_moves > 0) W = philox((uint32_t)c, s_lo, s_hi, 0u, k0, k1);
 #pragma unroll
     for (int t = 0; t < kSt; ++t) {
         // slot 0's fourth word is the cell's count; lane pairs (2 i, 2 i + 1)
@@ -634,96 +645,153 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     }
     const uint32_t n_raw = live ? count[c] : 0u;
     bool bad = n_raw > (uint32_t)kCap;
-    uint32_t ovm = 0u;                     // staging steps whose cell has more than kPrim spheres
+    // staging steps whose cell has more than kPrim spheres, the even steps
+    // on the lane of slot 0 and the odd ones on the lane of slot 1; the
+    // counts packed four bits each
+    uint32_t ovm = 0u;
+    uint32_t cpk[4] = {0u, 0u, 0u, 0u};
     if (stg) {
 #pragma unroll
         for (int t = 0; t < kSt; ++t) {
             const uint32_t n = cn[t];
             const int li = li3[t % 3] + kRg * kRg * reg_axis(t / 3);
             bad |= n > (uint32_t)kCap;
-            ovm |= (hs == 0 && n > (uint32_t)kPrim) ? 1u << t : 0u;
+            ovm |= ((t & 1) == hs && n > (uint32_t)kPrim) ? 1u << t : 0u;
+            cpk[t >> 3] |= min(n, 15u) << (4 * (t & 7));
             const bool have = n > (uint32_t)hs;
             sx[hs][li] = have ? v[t].x : kFar;
             sy[hs][li] = have ? v[t].y : kFar;
             sz[hs][li] = have ? v[t].z : kFar;
         }
     }
-    // 2. slots 2..7: of the staged cells that have them, to the brick's list,
-    // and of the own cell, to registers.  A lane's cells with such slots are
-    // taken three at a time (their loads in one batch), while any lane has
-    // some left; a slot past the cell's count is a raw buffer load past the
-    // buffer's end, which reads zeros without a memory access.
+    // 2. slots 2..7 of the staged cells that have them (more than kPrim
+    // spheres): the cells are compacted into a list of the brick, one entry
+    // per cell, and each lane then loads the slots of one entry per round, so
+    // that one round trip serves the whole region.  The own cell's slots
+    // 2..7 come in the same round trip.  A slot past the cell's count is a
+    // raw buffer load past the buffer's end, which reads zeros without a
+    // memory access.
     const __amdgpu_buffer_rsrc_t slots = __builtin_amdgcn_make_buffer_rsrc(
         (void *)pos, (short)0, (int)((unsigned)g.C * (unsigned)(kCap * sizeof(float4))), kBufferWord3);
     float px[kCap], py[kCap], pz[kCap];
 #pragma unroll
     for (int q = 0; q < kCap; ++q) px[q] = py[q] = pz[q] = kFar;
     const int n = (live && __ballot(bad) == 0ull) ? (int)min(n_raw, (uint32_t)kCap) : 0;
-    if (__ballot(n > kPrim) != 0ull) {
-#pragma unroll
-        for (int q = kPrim; q < kCap; ++q) {
-            const int off = n > q ? (int)slot_of(g.C, c, q) * (int)sizeof(float4) : kPastEnd;
-            const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(slots, off, 0, 0));
-            px[q] = v.x;
-            py[q] = v.y;
-            pz[q] = v.z;
-        }
-    }
     if (__ballot(bad) != 0ull) {
         // a cell above capacity: report it and leave the brick unchanged
         if (bad) atomicOr(&ctl->errword, kErrCapacity);
         ovm = 0u;
     }
+    int noc = 0;                           // overflow cells of the region (wave-uniform)
     while (__ballot(ovm != 0u) != 0ull) {
-        constexpr int kB3 = 3;
-        int cel[kB3], cod[kB3];
-        uint32_t cnt3[kB3];
-#pragma unroll
-        for (int b = 0; b < kB3; ++b) {
-            const bool have = ovm != 0u;
-            const int t = have ? __builtin_ctz(ovm) : 0;
-            ovm &= have ? ovm - 1u : 0u;
-            uint32_t nc = 0u;
-#pragma unroll
-            for (int u = 0; u < kSt; ++u) nc = t == u ? min(cn[u], (uint32_t)kCap) : nc;
+        const bool have = ovm != 0u;
+        const unsigned long long bal = __ballot(have);
+        const int t = have ? __builtin_ctz(ovm) : 0;
+        ovm &= have ? ovm - 1u : 0u;
+        const int e = noc + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        if (have && e < kOvCell) {
+            const int tw = t >> 3;
+            const uint32_t pk = tw == 0 ? cpk[0] : (tw == 1 ? cpk[1] : (tw == 2 ? cpk[2] : cpk[3]));
+            const uint32_t nc = min((pk >> (4 * (t & 7))) & 15u, (uint32_t)kCap);
             const int rz = t / 3, ry = 3 * (t - 3 * rz) + jr;
-            cel[b] = (wrapc(oz0 + rz, g.m[2]) * g.m[1] + wrapc(oy0 + ry, g.m[1])) * g.m[0] + gx;
-            cod[b] = rxs | (ry << 4) | (rz << 8);
-            cnt3[b] = have ? nc : 0u;   // more than kPrim whenever the step was listed
+            oc_cell[e] = (wrapc(oz0 + rz, g.m[2]) * g.m[1] + wrapc(oy0 + ry, g.m[1])) * g.m[0] + gx;
+            oc_cn[e] = (rxs | (ry << 4) | (rz << 8)) | (int)(nc << 12);
         }
-        float4 w[kB3][kCap - kPrim];
+        noc += __popcll(bal);
+    }
+    __syncthreads();
+    const int ncl = noc < kOvCell ? noc : kOvCell;
+    // the slots 2..7 of list entry e (zeros past its count), its region code
+    // (12-byte loads: a fourth, unused register would be reallocated while the
+    // load is in flight, and the compiler would wait for it)
+    auto load_entry = [&](int e, float3 (&w)[kCap - kPrim], int &code, uint32_t &cnt) {
+        const bool have = e < ncl;
+        const int ce = have ? oc_cell[e] : 0;
+        const int cc = have ? oc_cn[e] : 0;
+        code = cc & 0xFFF;
+        cnt = (uint32_t)cc >> 12;
 #pragma unroll
-        for (int b = 0; b < kB3; ++b)
-#pragma unroll
-            for (int q = kPrim; q < kCap; ++q) {
-                if (q >= 4 && __ballot(cnt3[b] > (uint32_t)q) == 0ull) {
-                    w[b][q - kPrim] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                    continue;
-                }
-                const int off = cnt3[b] > (uint32_t)q ? (int)slot_of(g.C, cel[b], q) * (int)sizeof(float4) : kPastEnd;
-                w[b][q - kPrim] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(slots, off, 0, 0));
+        for (int q = kPrim; q < kCap; ++q) {
+            if (q >= 4 && __ballot(cnt > (uint32_t)q) == 0ull) {
+                w[q - kPrim] = make_float3(0.0f, 0.0f, 0.0f);
+                continue;
             }
+            const int off = cnt > (uint32_t)q ? (int)slot_of(g.C, ce, q) * (int)sizeof(float4) : kPastEnd;
+            w[q - kPrim] = slot_xyz(slots, off);
+        }
+    };
+    // the slots of an entry to the lists of the lanes whose neighbourhood
+    // holds its cell (at most 8, the own lane excluded): per axis an even
+    // region coordinate 2t neighbours lanes t - 1 (offset +1) and t (offset
+    // -1), an odd one 2t + 1 only lane t (offset 0).  The lists take the slot
+    // planes' memory, so this runs after the planes are read.
+    float *lst = &planes[0][0];            // [lane][k][3]
+    auto deal_entry = [&](const float3 (&w)[kCap - kPrim], int code, uint32_t cnt) {
+        const int m = cnt > (uint32_t)kPrim ? (int)cnt - kPrim : 0;
+        int mw = m;
 #pragma unroll
-        for (int b = 0; b < kB3; ++b) {
-            if (cnt3[b] > (uint32_t)kPrim) {
-                const uint32_t m = cnt3[b] - (uint32_t)kPrim;
-                const uint32_t e0 = atomicAdd(&n_ov, m);
+        for (int o = 32; o > 0; o >>= 1) mw = max(mw, __shfl_xor(mw, o, 64));
+        if (mw == 0) return;
+        const int r[3] = {code & 15, (code >> 4) & 15, code >> 8};
+#pragma unroll
+        for (int cmb = 0; cmb < 8; ++cmb) {
+            int l[3], o[3];
+            bool ok = m > 0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int bit = (cmb >> d) & 1;
+                if (r[d] & 1) {
+                    l[d] = r[d] >> 1;
+                    o[d] = 0;
+                    ok = ok && bit == 0;
+                } else {
+                    l[d] = (r[d] >> 1) - 1 + bit;
+                    o[d] = bit ? -1 : 1;
+                }
+                ok = ok && l[d] >= 0 && l[d] < kBk;
+            }
+            ok = ok && (o[0] | o[1] | o[2]) != 0;   // the own cell's spheres are the lane's own
+            if (ok) {
+                const int tl = l[0] + kBk * (l[1] + kBk * l[2]);
+                const uint32_t k = atomicAdd(&ov_lane[tl], (uint32_t)m);
 #pragma unroll
                 for (int q = 0; q < kCap - kPrim; ++q) {
-                    const uint32_t e = e0 + (uint32_t)q;
-                    if ((uint32_t)q < m && e < (uint32_t)kOvMax) {
-                        ovx[e] = w[b][q].x;
-                        ovy[e] = w[b][q].y;
-                        ovz[e] = w[b][q].z;
-                        ovr[e] = cod[b];
+                    if (q < mw && q < m && k + (uint32_t)q < (uint32_t)kOvLane) {
+                        float *dst = lst + (tl * kOvLane + (int)k + q) * 3;
+                        dst[0] = frame(w[q].x, o[0], g.w[0]);
+                        dst[1] = frame(w[q].y, o[1], g.w[1]);
+                        dst[2] = frame(w[q].z, o[2], g.w[2]);
                     }
                 }
             }
         }
+    };
+    if (__ballot(n > kPrim) != 0ull) {
+#pragma unroll
+        for (int q = kPrim; q < kCap; ++q) {
+            const int off = n > q ? (int)slot_of(g.C, c, q) * (int)sizeof(float4) : kPastEnd;
+            const float3 v = slot_xyz(slots, off);
+            px[q] = v.x;
+            py[q] = v.y;
+            pz[q] = v.z;
+        }
     }
-    __syncthreads();
+    float3 w0[kCap - kPrim];
+    int code0;
+    uint32_t cnt0;
+    load_entry(lane, w0, code0, cnt0);
+    uint32_t tg[kCap];
+#pragma unroll
+    for (int q = 0; q < kCap; ++q) tg[q] = 0u;
+    if (has_tag) {
+#pragma unroll
+        for (int q = 0; q < kCap; ++q)
+            if (q < n) tg[q] = tag[slot_of(g.C, c, q)];
+    }
 
-    // 3. the 26 neighbour cells' staged slots, in this cell's frame
+    // 3. while those loads are in flight: the 26 neighbour cells' staged
+    // slots, in this cell's frame
     const int rxo = 1 + 2 * lx, ryo = 1 + 2 * ly, rzo = 1 + 2 * lz;   // own region cell
     float nx[52], ny[52], nz[52];
 #pragma unroll
@@ -745,52 +813,20 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     px[1] = sx[1][ro];
     py[1] = sy[1][ro];
     pz[1] = sz[1][ro];
-    const int nlist = (int)n_ov;
-    __syncthreads();   // the slot planes are read; their memory takes the per-lane lists
-
-    // 4. the brick's listed spheres to the lists of the lanes whose
-    // neighbourhood holds them (at most 8 lanes each, offsets -1, 0, +1)
-    float *lst = &planes[0][0];            // [lane][k][3]
-    const int lim = nlist < kOvMax ? nlist : kOvMax;
-    for (int e = lane; e < lim; e += 64) {
-        const int code = ovr[e];
-        const int r[3] = {code & 15, (code >> 4) & 15, code >> 8};
-        const float v[3] = {ovx[e], ovy[e], ovz[e]};
-        // per axis: an even region coordinate 2t neighbours lanes t - 1
-        // (offset +1) and t (offset -1), an odd one 2t + 1 only lane t (0)
-#pragma unroll
-        for (int cmb = 0; cmb < 8; ++cmb) {
-            int l[3], o[3];
-            bool ok = true;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const int b = (cmb >> d) & 1;
-                if (r[d] & 1) {
-                    l[d] = r[d] >> 1;
-                    o[d] = 0;
-                    ok = ok && b == 0;
-                } else {
-                    l[d] = (r[d] >> 1) - 1 + b;
-                    o[d] = b ? -1 : 1;
-                }
-                ok = ok && l[d] >= 0 && l[d] < kBk;
-            }
-            ok = ok && (o[0] | o[1] | o[2]) != 0;   // the own cell's spheres are the lane's own
-            if (ok) {
-                const int tl = l[0] + kBk * (l[1] + kBk * l[2]);
-                const uint32_t k = atomicAdd(&ov_lane[tl], 1u);
-                if (k < (uint32_t)kOvLane) {
-                    float *dst = lst + (tl * kOvLane + (int)k) * 3;
-                    dst[0] = frame(v[0], o[0], g.w[0]);
-                    dst[1] = frame(v[1], o[1], g.w[1]);
-                    dst[2] = frame(v[2], o[2], g.w[2]);
-                }
-            }
-        }
+    deal_entry(w0, code0, cnt0);
+    for (int r = 64; r < ncl; r += 64) {   // regions with more than 64 such cells
+        float3 w1[kCap - kPrim];
+        int code1;
+        uint32_t cnt1;
+        load_entry(r + lane, w1, code1, cnt1);
+        deal_entry(w1, code1, cnt1);
     }
     __syncthreads();
+
+    // 4. this lane's list; more than the list holds, or more listed cells than
+    // the brick's list of cells holds, and the lane tests from memory
     const int kov = (int)ov_lane[lane];
-    bool spill = nlist > kOvMax || kov > kOvLane;
+    bool spill = noc > kOvCell || kov > kOvLane;
     float ex[kOvLane], ey[kOvLane], ez[kOvLane];
 #pragma unroll
     for (int k = 0; k < kOvLane; ++k) {
@@ -802,18 +838,6 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
     int kw = kov < kOvLane ? kov : kOvLane;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) kw = max(kw, __shfl_xor(kw, o, 64));
-
-    uint32_t tg[kCap];
-#pragma unroll
-    for (int q = 0; q < kCap; ++q) tg[q] = 0u;
-    if (has_tag) {
-#pragma unroll
-        for (int q = 0; q < kCap; ++q)
-            if (q < n) tg[q] = tag[slot_of(g.C, c, q)];
-    }
-    uint4 Wsh = philox((uint32_t)c, s_lo, s_hi, kTagShuffle, k0, k1);
-    uint4 W = make_uint4(0, 0, 0, 0);
-    if (g.n_moves > 0) W = philox((uint32_t)c, s_lo, s_hi, 0u, k0, k1);
 
     // 5. shuffle and trials; own entries at or past M = the wave's largest
     // count (2, 4 or 8) are far spheres or identities throughout, so the
