@@ -44,16 +44,16 @@ def lattice_pair(pkg, n, eta, delta=0.1, n_moves=4, seed=1, replica=0, w_max=0.0
 
 
 def grid_pair(pkg, m, w, xyz, start, tags, sweep=0, delta=0.1, n_moves=4, seed=1, replica=0,
-              lanes=4):
+              lanes=4, tagged=True):
     log("  sphere grid pair m=%s N=%d delta=%.3f n_moves=%d lanes=%d"
         % (m, len(xyz), delta, n_moves, lanes))
     cfg = pkg.SphereConfig(cells_x=m[0], cells_y=m[1], cells_z=m[2], cell_w_x=float(w[0]),
                            cell_w_y=float(w[1]), cell_w_z=float(w[2]), n_particles=len(xyz),
                            delta=delta, n_moves=n_moves, seed=seed, replica=replica,
-                           flags=pkg.FLAG_TAG)
+                           flags=pkg.FLAG_TAG if tagged else 0)
     G = pkg.HardSphereSystem(cfg)
     G.set_launch(lanes)
-    G.set_state(xyz, start, sweep, tags)
+    G.set_state(xyz, start, sweep, tags if tagged else None)
     O = SphereOracle.grid(m, w, len(xyz), delta=delta, n_moves=n_moves, seed=seed,
                           replica=replica)
     O.set_state(xyz, start, tags, sweep)
@@ -227,6 +227,48 @@ def test_dense_crystal_exercises_the_spill_path(gpu, lanes):
     G.sweep(16)
     O.sweep(16)
     assert_same(G, O, "dense crystal, 19 sweeps")
+    G.close()
+
+
+def region_overflow_cells(m, start):
+    """Per brick region of the one-lane form (4^3 active cells of a set and
+    their neighbours, 9^3 cells with periodic indices), for every set, the
+    number of cells holding more than two spheres."""
+    M = m[0]
+    cnt = np.diff(start.astype(np.int64)).reshape(M, M, M)   # [z][y][x]
+    nb = (M // 2 + 3) // 4
+    out = []
+    for Q in range(8):
+        q = (Q & 1, (Q >> 1) & 1, Q >> 2)
+        for bz in range(nb):
+            for by in range(nb):
+                for bx in range(nb):
+                    ix = (np.arange(9) + 8 * bx + q[0] - 1) % M
+                    iy = (np.arange(9) + 8 * by + q[1] - 1) % M
+                    iz = (np.arange(9) + 8 * bz + q[2] - 1) % M
+                    out.append(int((cnt[np.ix_(iz, iy, ix)] > 2).sum()))
+    return np.array(out)
+
+
+def test_dense_crystal_on_the_untagged_brick_form(gpu):
+    """The dense crystal on the kernel variant the benchmark runs (one lane
+    per cell, no tags): brick regions with more than 64 cells of more than
+    two spheres load those cells' slots in several rounds, and regions with
+    more than the 128 cells the brick lists send every lane to the
+    from-memory path.  Bit-exact either way."""
+    m, w, xyz, start, tags = fcc_state(8, 0.70)
+    k = region_overflow_cells(m, start)
+    log("  cells past two spheres per region: max %d, regions above 64: %d, above 128: %d"
+        % (k.max(), (k > 64).sum(), (k > 128).sum()))
+    assert ((k > 64) & (k <= 128)).any() and (k > 128).any()
+    G, O = grid_pair(gpu, m, w, xyz, start, tags, 0, delta=0.05, n_moves=16, seed=9, lanes=1,
+                     tagged=False)
+    G.sweep(3)
+    O.sweep(3)
+    assert_same_untagged(G, O, "dense crystal, untagged, 3 sweeps")
+    G.sweep(16)
+    O.sweep(16)
+    assert_same_untagged(G, O, "dense crystal, untagged, 19 sweeps")
     G.close()
 
 
