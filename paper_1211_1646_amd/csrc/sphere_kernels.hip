@@ -570,8 +570,8 @@ k_subsweep3b(Geom3 g, Ctl3 *__restrict__ ctl, int par, float4 *__restrict__ pos,
              const uint32_t *__restrict__ count, uint32_t *__restrict__ tag,
              unsigned long long *__restrict__ cnt, int set, int nbrick, int per, int nbx, int nby)
 {
-    // slot planes [coordinate][slot][parity-plane index]; after the registers
-    // are filled the same memory holds the per-lane lists [lane][k] (x, y, z)
+    // slot planes [coordinate][slot][reg_index]; after the registers are
+    // filled the same memory holds the per-lane lists [lane][k] (x, y, z)
     __shared__ float planes[6][kRgC];
     float(*sx)[kRgC] = planes, (*sy)[kRgC] = planes + 2, (*sz)[kRgC] = planes + 4;
     __shared__ uint32_t ov_lane[64];       // listed spheres per lane
