@@ -7,8 +7,9 @@
  * A sweep (Alg. 1) shuffles the four checkerboard sets of cells (Eq. 1),
  * updates every cell of one set concurrently -- shuffle the cell's particles,
  * then n_M trial moves on particle list[s mod n], rejecting moves that leave
- * the cell or overlap a disk of the 3x3 neighbourhood (Alg. 2) -- and ends
- * with a random shift of the cell grid (Alg. 4).
+ * the cell or overlap a disk of the 3x3 neighbourhood (Alg. 2; in FP32,
+ * r^2 = fmaf(dy, dy, dx*dx) < 1) -- and ends with a random shift of the cell
+ * grid (Alg. 4).
  *
  * Conventions for every call:
  *  - Device memory is owned by the caller.  mpmc_required_bytes() reports the

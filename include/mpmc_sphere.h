@@ -15,7 +15,8 @@
  *  - 8 checkerboard sets, set Q = (cx & 1) + 2 (cy & 1) + 4 (cz & 1), cells
  *    numbered c = (cz m_y + cy) m_x + cx;
  *  - the 27-cell neighbourhood, with pair distance
- *    r^2 = (dx*dx + dy*dy) + dz*dz in FP32, overlap iff r^2 < 1;
+ *    r^2 = fmaf(dz, dz, fmaf(dy, dy, dx*dx)) in FP32 (one rounding per
+ *    added square), overlap iff r^2 < 1;
  *  - 6 shift directions f = +x, -x, +y, -y, +z, -z (0..5).
  *
  * Random numbers (Philox4x32-10, key (seed, replica), counter (cell or
