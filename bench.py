@@ -208,6 +208,7 @@ def spheres_leg(args):
     k = r["roofline"]["kernel"]
     r["roofline"]["traffic"] = traffic_from_profile(src, k, profile=prof)
     r["roofline"]["valu_busy"] = traffic_from_profile(src, k, "valu busy fraction", profile=prof)
+    r["roofline"]["alu"] = alu_roofline(src, k, prof, r["roofline"]["kernel_avg_us"] * 1e-3)
     return r
 
 
